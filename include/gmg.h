@@ -1,0 +1,158 @@
+/*
+ * gmg.h -- C ABI of the MI355X geometric-multigrid library (libgmg.so).
+ *
+ * The library solves the periodic Poisson problem -Laplace(u) = f on the unit
+ * cube (eq. 1.1 of Gholami, Malhotra, Sundar, Biros, "FFT, FMM, or Multigrid?")
+ * with continuous Galerkin Q_q elements on LGL nodes (Section 2.3.2), a
+ * multigrid hierarchy of nested meshes (Section 2.3.1), a Chebyshev-accelerated
+ * Jacobi smoother (Section 2.3.3), P(i,j) = phi_j^{k-1}(p_i) and R = P^T
+ * (Section 2.3.4, eqs. 2.1-2.2), the V-cycle of Algorithm 2.1 with a direct
+ * coarsest solve, and CG preconditioned by one V-cycle (Section 2.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns a gmg_status; nothing throws across the ABI.
+ *  - Pointers named *_dev are device pointers (HIP global memory) owned by the
+ *    caller; the library never frees them.  Pointers named *_host are host
+ *    memory.  The library owns the context and every buffer inside it.
+ *  - Vectors are DoF vectors of one level: length N^3 with N = q * n_level,
+ *    lexicographic with x fastest: index i + N (j + N k).  Lattice node i sits at
+ *    x = (e + xi_a) / n_level, e = i div q, a = i mod q, xi the LGL nodes on [0,1].
+ *  - A vector's element type is double for GMG_FP64 and float for GMG_FP32.
+ *  - Calls are ordered on the HIP stream given to gmg_setup.  gmg_apply,
+ *    gmg_smooth, gmg_restrict, gmg_prolong, gmg_coarse_solve, gmg_vcycle and
+ *    gmg_rhs enqueue work and return without synchronizing.  gmg_solve,
+ *    gmg_dot and the query calls synchronize the stream.
+ *  - Input and output device buffers of one call must not overlap unless the
+ *    call says so.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Errors: GMG_E_ARG for an invalid argument (null pointer, level out of
+ *    range, order not in {1,2,4}, n not a power of two, ...); GMG_E_HIP when a
+ *    HIP runtime call fails (the context should then be destroyed);
+ *    GMG_E_NOCONV when a solve stops at max_iters (info is filled);
+ *    GMG_E_BREAKDOWN for NaN/Inf or a non-positive p^T A p; GMG_E_OOM when a
+ *    device allocation fails.  gmg_last_error() returns a message for the last
+ *    failing call on a context.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmg_ctx gmg_ctx;
+
+typedef enum {
+  GMG_OK = 0,
+  GMG_E_ARG = 1,
+  GMG_E_MESH = 2,
+  GMG_E_OOM = 3,
+  GMG_E_HIP = 4,
+  GMG_E_NOCONV = 5,
+  GMG_E_BREAKDOWN = 6,
+  GMG_E_STATE = 7
+} gmg_status;
+
+typedef enum { GMG_FP64 = 0, GMG_FP32 = 1 } gmg_prec;
+
+/* Mesh description.  Uniform periodic meshes: n = elements per direction
+ * (a power of two, n >= 2, and q*n >= 4), order in {1, 2, 4}.  levels = number
+ * of multigrid levels (level 0 coarsest, levels-1 finest, n halves per level,
+ * Section 2.3.1); 0 selects the deepest hierarchy whose coarsest level has at
+ * most 512 DoFs and at least 2 elements per direction. */
+typedef struct {
+  int32_t order;
+  int32_t n;
+  int32_t levels;
+  int32_t reserved;
+} gmg_mesh;
+
+/* Solver options.  Zero-initialized fields take the defaults given here. */
+typedef struct {
+  int32_t cheb_degree;      /* Chebyshev polynomial degree (default 3)                    */
+  int32_t nu_pre, nu_post;  /* polynomial applications before/after correction (2, 2)      */
+  double cheb_lo, cheb_hi;  /* [alpha, beta] = [lo, hi] * lambda_hat (0.1, 1.1)            */
+  int32_t lanczos_steps;    /* Lanczos steps for lambda_hat of D^-1 A (10; Section 2.3.3)  */
+  int32_t smoother;         /* 0 Chebyshev-Jacobi, 1 damped Jacobi (omega below)           */
+  double jacobi_omega;      /* damping of the Jacobi smoother (2/3)                        */
+  uint64_t seed;            /* key of the SplitMix64 Lanczos start vectors (0)             */
+  int32_t vcycle_prec;      /* GMG_FP64: PCG on FP64 V-cycles; GMG_FP32: FP64 iterative
+                               refinement around flexible CG on FP32 V-cycles              */
+  int32_t krylov;           /* 0 PCG, 1 FCG(1) (forced to 1 with FP32 V-cycles)            */
+  double inner_rtol;        /* inner relative tolerance of the FP32 solve (1e-4)           */
+  int32_t max_iters;        /* cap on Krylov iterations, inner+outer (500)                 */
+  double lambda_override;   /* > 0: use this lambda_hat on every level instead of Lanczos  */
+} gmg_options;
+
+typedef struct {
+  int32_t outer_iters;      /* iterative-refinement steps (0 for plain FP64 PCG)           */
+  int32_t inner_iters;      /* total Krylov iterations                                     */
+  int32_t fallbacks;        /* reserved                                                    */
+  int32_t reserved;
+  double rel_residual_f64;  /* final ||b - A u||_2 / ||b||_2, recomputed in FP64           */
+  double t_setup;           /* seconds spent in gmg_setup (host clock)                     */
+  double t_solve;           /* seconds inside the solve (HIP events on the stream)         */
+} gmg_info;
+
+/* Build the hierarchy on the current HIP device: operator tables, diagonal
+ * (Section 2.3, Setup), Lanczos estimate of lambda_max(D^-1 A) per level
+ * (Section 2.3.3), coarsest-level pseudo-inverse (dense FP64), device buffers.
+ * hip_stream: a hipStream_t (NULL = the null stream).  *out receives the context. */
+gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_stream, gmg_ctx** out);
+gmg_status gmg_destroy(gmg_ctx* ctx);
+
+/* Queries (host).  gmg_dof_coords_1d writes the N coordinates of one axis; the
+ * DoF (i, j, k) sits at (x[i], x[j], x[k]). */
+gmg_status gmg_num_levels(const gmg_ctx* ctx, int32_t* levels);
+gmg_status gmg_num_dofs(const gmg_ctx* ctx, int32_t level, int64_t* n);
+gmg_status gmg_dof_coords_1d(const gmg_ctx* ctx, int32_t level, double* x_host);
+gmg_status gmg_lambda(const gmg_ctx* ctx, int32_t level, double* lambda_host);
+
+/* d_dev[i] = A_ii on a level (FP64), the Jacobi diagonal of Section 2.3 Setup. */
+gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev);
+
+/* y = A_level x: matrix-free, sum-factorized stiffness apply (Section 2.3.2). */
+gmg_status gmg_apply(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev);
+
+/* y = M_level x with the consistent mass matrix (used for the load vector). */
+gmg_status gmg_mass(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev);
+
+/* u <- S^nu (u; b): nu applications of the level smoother to A u = b, in place
+ * (Section 2.3.3).  u_dev holds the initial guess on entry. */
+gmg_status gmg_smooth(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, void* u_dev, int32_t nu);
+
+/* rc = R rf = P^T rf from level `level` (fine) to level-1 (Section 2.3.4). */
+gmg_status gmg_restrict(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* rf_dev, void* rc_dev);
+
+/* uf += P ec from level-1 to level `level` (eq. 2.2). */
+gmg_status gmg_prolong(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* ec_dev, void* uf_dev);
+
+/* x = A_0^+ (b - mean(b)) on the coarsest level, computed in FP64 whatever prec
+ * says (the direct coarsest solve of Algorithm 2.1). */
+gmg_status gmg_coarse_solve(gmg_ctx* ctx, gmg_prec prec, const void* b_dev, void* x_dev);
+
+/* z = V r: one V-cycle (Algorithm 2.1) on the finest level, zero initial guess. */
+gmg_status gmg_vcycle(gmg_ctx* ctx, gmg_prec prec, const void* r_dev, void* z_dev);
+
+/* b = M f - mean(M f): load vector of nodal source values f on the finest level. */
+gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev);
+
+/* Solve A u = b(f) to ||b - A u||_2 <= rtol ||b||_2 (true FP64 residual); u is
+ * returned with zero integral.  f_dev: nodal source values (FP64).  The
+ * variant gmg_solve_rhs takes an already projected load vector b_dev. */
+gmg_status gmg_solve(gmg_ctx* ctx, const double* f_dev, double* u_dev, double rtol, gmg_info* info);
+gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info);
+
+/* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
+gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
+
+const char* gmg_status_string(gmg_status s);
+const char* gmg_last_error(const gmg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMG_H */

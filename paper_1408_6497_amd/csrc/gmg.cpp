@@ -1,0 +1,702 @@
+// Host orchestration and C ABI of the multigrid library.
+//
+// Setup (Section 2.3, "Setup"): mesh hierarchy of nested uniform periodic
+// meshes (Section 2.3.1: every coarse element is the parent of 8 fine ones),
+// operator tables and Jacobi diagonal, Lanczos estimate of lambda_max(D^-1 A)
+// (Section 2.3.3), dense coarsest pseudo-inverse.  Solve: V-cycle of
+// Algorithm 2.1 with Chebyshev-Jacobi smoothing, CG preconditioned by one
+// V-cycle (Section 2.3), and FP64 iterative refinement around an FP32 flexible
+// CG.  Every vector operation runs in the HIP kernels declared in
+// gmg_kernels.h; the host only sequences launches and reads scalars back.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gmg.h"
+#include "gmg_kernels.h"
+#include "gmg_setup_math.h"
+
+using namespace gmg;
+
+namespace {
+
+constexpr int kNumScal = 32;
+// device scalar slots
+enum : int {
+  S_PW = 0,   // p . w
+  S_PR = 1,   // p . r
+  S_RZ0 = 2,  // r . z (two slots, ping-pong)
+  S_RZ1 = 3,
+  S_ZW = 4,   // z . w
+  S_SUM = 5,  // projection sum
+  S_RR = 6,   // r . r
+  S_TMP = 7,
+};
+
+struct Level {
+  int n = 0, N = 0;
+  int64_t size = 0;
+  LevelTables tab{};
+  double lam = 0, alpha = 0, beta = 0;
+  void* b[2] = {nullptr, nullptr};   // [0] FP64, [1] FP32
+  void* u[2] = {nullptr, nullptr};
+  void* xp[2] = {nullptr, nullptr};
+};
+
+}  // namespace
+
+struct gmg_ctx {
+  int q = 0, L = 0;
+  gmg_options opt{};
+  hipStream_t stream = nullptr;
+  std::vector<Level> lv;
+  AxisTab prol{}, rest{};
+  void* tA[2] = {nullptr, nullptr};
+  void* tB[2] = {nullptr, nullptr};
+  bool have_prec[2] = {false, false};
+  double* ainv = nullptr;
+  int n0 = 0;
+  double* scal = nullptr;
+  double* part = nullptr;
+  // finest-level Krylov vectors per precision: r, z, p, w, c
+  void* kr[2] = {nullptr, nullptr};
+  void* kz[2] = {nullptr, nullptr};
+  void* kp[2] = {nullptr, nullptr};
+  void* kw[2] = {nullptr, nullptr};
+  void* kc[2] = {nullptr, nullptr};
+  void* bint = nullptr;  // FP64 load vector inside gmg_solve
+  std::vector<void*> allocs;
+  std::string err;
+  double t_setup = 0.0;
+};
+
+namespace {
+
+inline int pidx(gmg_prec p) { return p == GMG_FP32 ? 1 : 0; }
+inline size_t esize(int pi) { return pi ? sizeof(float) : sizeof(double); }
+
+gmg_status fail(gmg_ctx* c, gmg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+  do {                                                                                        \
+    const hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((ctx), GMG_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define STCHK(expr)                     \
+  do {                                  \
+    const gmg_status s_ = (expr);       \
+    if (s_ != GMG_OK) return s_;        \
+  } while (0)
+
+gmg_status dalloc(gmg_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, GMG_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  c->allocs.push_back(*p);
+  return GMG_OK;
+}
+
+// Allocate every buffer of one precision (level vectors, transfer temporaries,
+// Krylov vectors) on first use.
+gmg_status ensure_prec(gmg_ctx* c, int pi) {
+  if (c->have_prec[pi]) return GMG_OK;
+  const size_t es = esize(pi);
+  for (auto& L : c->lv) {
+    STCHK(dalloc(c, &L.b[pi], L.size * es));
+    STCHK(dalloc(c, &L.u[pi], L.size * es));
+    STCHK(dalloc(c, &L.xp[pi], L.size * es));
+  }
+  const int64_t nf = c->lv.back().size;
+  STCHK(dalloc(c, &c->tA[pi], (nf / 2 + 1) * es));
+  STCHK(dalloc(c, &c->tB[pi], (nf / 4 + 1) * es));
+  STCHK(dalloc(c, &c->kr[pi], nf * es));
+  STCHK(dalloc(c, &c->kz[pi], nf * es));
+  STCHK(dalloc(c, &c->kp[pi], nf * es));
+  STCHK(dalloc(c, &c->kw[pi], nf * es));
+  STCHK(dalloc(c, &c->kc[pi], nf * es));
+  c->have_prec[pi] = true;
+  return GMG_OK;
+}
+
+gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out, const void* b, const void* xp,
+                    double c1, double c2, bool mass = false) {
+  const Level& L = c->lv[l];
+  // the kernel moves q consecutive values per vector access
+  const uintptr_t al = static_cast<uintptr_t>(c->q) * esize(pi);
+  for (const void* ptr : {x, static_cast<const void*>(out), b, xp})
+    if (ptr && (reinterpret_cast<uintptr_t>(ptr) % al) != 0)
+      return fail(c, GMG_E_ARG, "device buffer not aligned to q elements");
+  ApplyArgs a{};
+  a.N = L.N;
+  a.n = L.n;
+  a.x = x;
+  a.out = out;
+  a.b = b;
+  a.xp = xp;
+  a.c1 = c1;
+  a.c2 = c2;
+  a.epi = epi;
+  HIPCHK(c, launch_apply(mass ? L.tab.mass : L.tab.stiff, pi == 1, a, c->stream));
+  return GMG_OK;
+}
+
+gmg_status read_scalars(gmg_ctx* c, double* host, int count) {
+  HIPCHK(c, hipMemcpyAsync(host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GMG_OK;
+}
+
+// v <- v - mean(v)
+gmg_status project(gmg_ctx* c, int pi, int64_t n, void* v) {
+  HIPCHK(c, launch_sum(pi == 1, n, v, c->part, c->scal + S_SUM, c->stream));
+  HIPCHK(c, launch_shift(pi == 1, n, c->scal, S_SUM, 1.0 / static_cast<double>(n), v, c->stream));
+  return GMG_OK;
+}
+
+// u <- S^nu(u; b) on level l.  zero_init: u is taken as 0 on entry (not read).
+gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, bool zero_init) {
+  Level& L = c->lv[l];
+  const bool f32 = pi == 1;
+  if (nu <= 0) {
+    if (zero_init) HIPCHK(c, launch_fill_zero(f32, L.size, u, c->stream));
+    return GMG_OK;
+  }
+  void* bufs[2] = {u, L.xp[pi]};
+  int cur = 0;
+  bool prev_zero = false;
+  bool x_zero = zero_init;
+  if (c->opt.smoother == 1) {
+    const double w = c->opt.jacobi_omega;
+    for (int s = 0; s < nu; ++s) {
+      if (x_zero) {
+        HIPCHK(c, launch_class_scale(f32, c->q, L.N, L.tab.stiff.dinv, w, b, bufs[1 - cur], c->stream));
+        x_zero = false;
+      } else {
+        STCHK(apply_op(c, l, pi, Epi::Cheb, bufs[cur], bufs[1 - cur], b, nullptr, 0.0, w));
+      }
+      cur ^= 1;
+    }
+  } else {
+    const double theta = 0.5 * (L.beta + L.alpha);
+    const double delta = 0.5 * (L.beta - L.alpha);
+    const double sigma = theta / delta;
+    const int deg = c->opt.cheb_degree;
+    for (int app = 0; app < nu; ++app) {
+      double rho = 1.0 / sigma;
+      for (int j = 0; j < deg; ++j) {
+        double c1 = 0.0, c2 = 1.0 / theta;
+        if (j > 0) {
+          const double rho_new = 1.0 / (2.0 * sigma - rho);
+          c1 = rho_new * rho;
+          c2 = 2.0 * rho_new / delta;
+          rho = rho_new;
+        }
+        if (x_zero) {
+          // x_1 = x_0 + D^-1 (b - A x_0) / theta with x_0 = 0
+          HIPCHK(c, launch_class_scale(f32, c->q, L.N, L.tab.stiff.dinv, c2, b, bufs[1 - cur], c->stream));
+          x_zero = false;
+          prev_zero = true;
+        } else {
+          const void* xpp = (c1 != 0.0 && !prev_zero) ? bufs[1 - cur] : nullptr;
+          STCHK(apply_op(c, l, pi, Epi::Cheb, bufs[cur], bufs[1 - cur], b, xpp, c1, c2));
+          prev_zero = false;
+        }
+        cur ^= 1;
+      }
+    }
+  }
+  if (bufs[cur] != u) HIPCHK(c, launch_copy(f32, L.size, bufs[cur], u, c->stream));
+  return GMG_OK;
+}
+
+// rc = P^T rf, fine level l -> l-1
+gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
+  const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
+  const bool f32 = pi == 1;
+  HIPCHK(c, launch_axis(c->rest, f32, rf, c->tA[pi], Nc, Nf, Nf, 0, Nf, false, c->stream));
+  HIPCHK(c, launch_axis(c->rest, f32, c->tA[pi], c->tB[pi], Nc, Nc, Nf, 1, Nf, false, c->stream));
+  HIPCHK(c, launch_axis(c->rest, f32, c->tB[pi], rc, Nc, Nc, Nc, 2, Nf, false, c->stream));
+  return GMG_OK;
+}
+
+// uf += P ec, level l-1 -> l
+gmg_status prolong_level(gmg_ctx* c, int l, int pi, const void* ec, void* uf) {
+  const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
+  const bool f32 = pi == 1;
+  HIPCHK(c, launch_axis(c->prol, f32, ec, c->tB[pi], Nf, Nc, Nc, 0, Nc, false, c->stream));
+  HIPCHK(c, launch_axis(c->prol, f32, c->tB[pi], c->tA[pi], Nf, Nf, Nc, 1, Nc, false, c->stream));
+  HIPCHK(c, launch_axis(c->prol, f32, c->tA[pi], uf, Nf, Nf, Nf, 2, Nc, true, c->stream));
+  return GMG_OK;
+}
+
+gmg_status coarse_solve(gmg_ctx* c, int pi, const void* b, void* x) {
+  HIPCHK(c, launch_coarse(pi == 1, c->n0, c->ainv, b, x, c->stream));
+  return GMG_OK;
+}
+
+// Algorithm 2.1 on level l with zero initial guess: u = V_l b.
+gmg_status vcycle_level(gmg_ctx* c, int l, int pi, const void* b, void* u) {
+  if (l == 0) return coarse_solve(c, pi, b, u);
+  Level& L = c->lv[l];
+  Level& C = c->lv[l - 1];
+  STCHK(smooth(c, l, pi, b, u, c->opt.nu_pre, true));                            // pre-smooth
+  STCHK(apply_op(c, l, pi, Epi::Residual, u, L.xp[pi], b, nullptr, 0, 0));       // residual
+  STCHK(restrict_level(c, l, pi, L.xp[pi], C.b[pi]));                             // restrict
+  STCHK(vcycle_level(c, l - 1, pi, C.b[pi], C.u[pi]));                            // recurse
+  STCHK(prolong_level(c, l, pi, C.u[pi], u));                                     // correct
+  STCHK(smooth(c, l, pi, b, u, c->opt.nu_post, false));                           // post-smooth
+  return GMG_OK;
+}
+
+// Largest Ritz value of Lanczos on D^-1/2 A D^-1/2 (FP64, on the device).
+gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
+  Level& L = c->lv[l];
+  const int q = c->q;
+  const int64_t n = L.size;
+  void* v = L.b[0];
+  void* vprev = L.u[0];
+  void* w = L.xp[0];
+  void* t = c->kr[0];
+  const hipStream_t s = c->stream;
+  HIPCHK(c, launch_splitmix_start(c->opt.seed + static_cast<uint64_t>(l), n, static_cast<double*>(v), s));
+  // project out the null vector D^1/2 1 of the scaled operator
+  double w0w0 = 0.0;
+  const int64_t per_class = n / (q * q * q);
+  for (int i = 0; i < q * q * q; ++i) w0w0 += L.tab.diag[i] * static_cast<double>(per_class);
+  HIPCHK(c, launch_class_dot(false, q, L.N, L.tab.dsqrt, v, c->part, c->scal + S_TMP, s));
+  double hs[kNumScal];
+  STCHK(read_scalars(c, hs, kNumScal));
+  HIPCHK(c, launch_class_axpy(false, q, L.N, L.tab.dsqrt, -hs[S_TMP] / w0w0, v, s));
+  HIPCHK(c, launch_dot(false, n, v, v, c->part, c->scal + S_TMP, s));
+  STCHK(read_scalars(c, hs, kNumScal));
+  const double ones[kMaxQ * kMaxQ * kMaxQ] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                              1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                              1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+  HIPCHK(c, launch_class_scale(false, q, L.N, ones, 1.0 / std::sqrt(hs[S_TMP]), v, v, s));
+  HIPCHK(c, launch_fill_zero(false, n, vprev, s));
+  const int steps = static_cast<int>(std::min<int64_t>(c->opt.lanczos_steps, n - 1));
+  std::vector<double> alpha, beta;
+  double bprev = 0.0, amax = 0.0;
+  for (int j = 0; j < steps; ++j) {
+    HIPCHK(c, launch_class_scale(false, q, L.N, L.tab.dinv_sqrt, 1.0, v, t, s));
+    STCHK(apply_op(c, l, 0, Epi::Apply, t, w, nullptr, nullptr, 0, 0));
+    HIPCHK(c, launch_class_scale(false, q, L.N, L.tab.dinv_sqrt, 1.0, w, w, s));
+    if (bprev != 0.0) HIPCHK(c, launch_axpy(false, n, -bprev, vprev, w, s));
+    HIPCHK(c, launch_dot(false, n, w, v, c->part, c->scal + S_TMP, s));
+    STCHK(read_scalars(c, hs, kNumScal));
+    const double a = hs[S_TMP];
+    alpha.push_back(a);
+    amax = std::max(amax, std::fabs(a));
+    HIPCHK(c, launch_axpy(false, n, -a, v, w, s));
+    HIPCHK(c, launch_dot(false, n, w, w, c->part, c->scal + S_TMP, s));
+    STCHK(read_scalars(c, hs, kNumScal));
+    const double bnew = std::sqrt(hs[S_TMP]);
+    if (j == steps - 1 || bnew <= 1e-12 * amax) break;
+    beta.push_back(bnew);
+    // vprev <- v ; v <- w / bnew
+    std::swap(v, vprev);
+    HIPCHK(c, launch_class_scale(false, q, L.N, ones, 1.0 / bnew, w, v, s));
+    bprev = bnew;
+  }
+  *lam_out = tridiag_max_eig(alpha, beta);
+  return GMG_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Preconditioned Krylov solve of A c = r on the finest level in precision pi,
+// c = 0 initially.  r is overwritten with the recursive residual.  Stops when
+// ||r||_2 <= tol_abs.  With b_true, the stop is confirmed on the true residual
+// b_true - A c (and r is reset to it if that is above tolerance).
+gmg_status krylov(gmg_ctx* c, int pi, bool flexible, const void* b_true, void* u, void* r, double tol_abs,
+                  int maxit, int* iters, double* final_rr) {
+  const int l = c->L - 1;
+  const int64_t n = c->lv[l].size;
+  const bool f32 = pi == 1;
+  const hipStream_t s = c->stream;
+  void* z = c->kz[pi];
+  void* p = c->kp[pi];
+  void* w = c->kw[pi];
+  double hs[kNumScal];
+  int rz = S_RZ0;
+  HIPCHK(c, launch_fill_zero(f32, n, u, s));
+  STCHK(project(c, pi, n, r));
+  auto restart = [&]() -> gmg_status {
+    STCHK(vcycle_level(c, l, pi, r, z));
+    STCHK(project(c, pi, n, z));
+    if (!flexible) HIPCHK(c, launch_dot(f32, n, r, z, c->part, c->scal + rz, s));
+    HIPCHK(c, launch_copy(f32, n, z, p, s));
+    return GMG_OK;
+  };
+  STCHK(restart());
+  int it = 0;
+  bool first = true;
+  while (true) {
+    HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+    STCHK(read_scalars(c, hs, kNumScal));
+    if (!std::isfinite(hs[S_RR]) || (!first && !finite_pos(hs[S_PW]))) {
+      *iters = it;
+      *final_rr = hs[S_RR];
+      return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: non-finite residual or p^T A p <= 0");
+    }
+    first = false;
+    if (std::sqrt(hs[S_RR]) <= tol_abs) {
+      if (!b_true) break;
+      STCHK(apply_op(c, l, pi, Epi::Residual, u, r, b_true, nullptr, 0, 0));
+      STCHK(project(c, pi, n, r));
+      HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+      STCHK(read_scalars(c, hs, kNumScal));
+      if (std::sqrt(hs[S_RR]) <= tol_abs) break;
+      if (it >= maxit) break;
+      STCHK(restart());
+      continue;
+    }
+    if (it >= maxit) break;
+    STCHK(apply_op(c, l, pi, Epi::Apply, p, w, nullptr, nullptr, 0, 0));
+    HIPCHK(c, launch_dot(f32, n, p, w, c->part, c->scal + S_PW, s));
+    if (flexible) HIPCHK(c, launch_dot(f32, n, p, r, c->part, c->scal + S_PR, s));
+    HIPCHK(c, launch_axpy2(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, s));
+    STCHK(project(c, pi, n, r));
+    STCHK(vcycle_level(c, l, pi, r, z));
+    STCHK(project(c, pi, n, z));
+    if (flexible) {
+      HIPCHK(c, launch_dot(f32, n, z, w, c->part, c->scal + S_ZW, s));
+      HIPCHK(c, launch_xpby(f32, n, c->scal, S_ZW, S_PW, -1.0, z, p, s));
+    } else {
+      const int rzn = rz == S_RZ0 ? S_RZ1 : S_RZ0;
+      HIPCHK(c, launch_dot(f32, n, r, z, c->part, c->scal + rzn, s));
+      HIPCHK(c, launch_xpby(f32, n, c->scal, rzn, rz, 1.0, z, p, s));
+      rz = rzn;
+    }
+    ++it;
+  }
+  *iters = it;
+  *final_rr = hs[S_RR];
+  return GMG_OK;
+}
+
+gmg_status check_level(const gmg_ctx* c, int level) {
+  if (level < 0 || level >= c->L) return GMG_E_ARG;
+  return GMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gmg_status_string(gmg_status s) {
+  switch (s) {
+    case GMG_OK: return "ok";
+    case GMG_E_ARG: return "invalid argument";
+    case GMG_E_MESH: return "invalid mesh";
+    case GMG_E_OOM: return "out of device memory";
+    case GMG_E_HIP: return "HIP runtime error";
+    case GMG_E_NOCONV: return "not converged";
+    case GMG_E_BREAKDOWN: return "breakdown";
+    case GMG_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* gmg_last_error(const gmg_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_stream, gmg_ctx** out) {
+  if (!mesh || !out) return GMG_E_ARG;
+  *out = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int q = mesh->order;
+  const int n = mesh->n;
+  if (!(q == 1 || q == 2 || q == 4)) return GMG_E_ARG;
+  if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n / 1 > (512 * 1) || (q * n) / q > 512) return GMG_E_ARG;
+  int L = mesh->levels;
+  if (L <= 0) {
+    L = 1;
+    // deepest hierarchy with coarsest level >= 2 elements and <= 512 DoFs
+    while (true) {
+      const int nc = n >> (L - 1);
+      const int64_t dofs = static_cast<int64_t>(q * nc) * (q * nc) * (q * nc);
+      if (dofs <= 512 || nc / 2 < 2 || q * (nc / 2) < 4) break;
+      ++L;
+    }
+  }
+  if ((n >> (L - 1)) < 1 || (n >> (L - 1)) << (L - 1) != n) return GMG_E_ARG;
+  const int nc0 = n >> (L - 1);
+  if (q * nc0 < 4 || nc0 < 2) return GMG_E_ARG;
+  const int64_t n0 = static_cast<int64_t>(q * nc0) * (q * nc0) * (q * nc0);
+  if (n0 > 4096) return GMG_E_ARG;
+
+  gmg_ctx* c = new (std::nothrow) gmg_ctx();
+  if (!c) return GMG_E_OOM;
+  c->q = q;
+  c->L = L;
+  gmg_options o{};
+  if (opts) o = *opts;
+  if (o.cheb_degree <= 0) o.cheb_degree = 3;
+  if (o.nu_pre <= 0 && !(opts && opts->nu_pre < 0)) o.nu_pre = 2;
+  if (o.nu_post <= 0 && !(opts && opts->nu_post < 0)) o.nu_post = 2;
+  if (o.nu_pre < 0) o.nu_pre = 0;
+  if (o.nu_post < 0) o.nu_post = 0;
+  if (o.cheb_lo <= 0) o.cheb_lo = 0.1;
+  if (o.cheb_hi <= 0) o.cheb_hi = 1.1;
+  if (o.lanczos_steps <= 0) o.lanczos_steps = 10;
+  if (o.jacobi_omega <= 0) o.jacobi_omega = 2.0 / 3.0;
+  if (o.inner_rtol <= 0) o.inner_rtol = 1e-4;
+  if (o.max_iters <= 0) o.max_iters = 500;
+  if (o.vcycle_prec == GMG_FP32) o.krylov = 1;
+  c->opt = o;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->lv.resize(L);
+  for (int l = 0; l < L; ++l) {
+    Level& lev = c->lv[l];
+    lev.n = n >> (L - 1 - l);
+    lev.N = q * lev.n;
+    lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
+    lev.tab = make_level_tables(q, lev.n);
+  }
+  make_transfer_tables(q, &c->prol, &c->rest);
+  gmg_status st = GMG_OK;
+  auto bail = [&](gmg_status s) {
+    gmg_destroy(c);
+    return s;
+  };
+  if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
+  if ((st = dalloc(c, reinterpret_cast<void**>(&c->part), sizeof(double) * kRedBlocks)) != GMG_OK) return bail(st);
+  if (hipMemsetAsync(c->scal, 0, sizeof(double) * kNumScal, c->stream) != hipSuccess) return bail(GMG_E_HIP);
+  if ((st = ensure_prec(c, 0)) != GMG_OK) return bail(st);
+  // coarsest pseudo-inverse
+  c->n0 = static_cast<int>(n0);
+  std::vector<double> inv;
+  try {
+    inv = coarse_pseudo_inverse(q, nc0);
+  } catch (...) {
+    return bail(GMG_E_ARG);
+  }
+  if ((st = dalloc(c, reinterpret_cast<void**>(&c->ainv), sizeof(double) * inv.size())) != GMG_OK) return bail(st);
+  if (hipMemcpyAsync(c->ainv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(GMG_E_HIP);
+  // Chebyshev interval per level
+  for (int l = 0; l < L; ++l) {
+    Level& lev = c->lv[l];
+    double lam = o.lambda_override;
+    if (lam <= 0.0) {
+      if ((st = lanczos(c, l, &lam)) != GMG_OK) return bail(st);
+    }
+    lev.lam = lam;
+    lev.alpha = o.cheb_lo * lam;
+    lev.beta = o.cheb_hi * lam;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(GMG_E_HIP);
+  c->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = c;
+  return GMG_OK;
+}
+
+gmg_status gmg_destroy(gmg_ctx* ctx) {
+  if (!ctx) return GMG_OK;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+  return GMG_OK;
+}
+
+gmg_status gmg_num_levels(const gmg_ctx* ctx, int32_t* levels) {
+  if (!ctx || !levels) return GMG_E_ARG;
+  *levels = ctx->L;
+  return GMG_OK;
+}
+
+gmg_status gmg_num_dofs(const gmg_ctx* ctx, int32_t level, int64_t* n) {
+  if (!ctx || !n || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  *n = ctx->lv[level].size;
+  return GMG_OK;
+}
+
+gmg_status gmg_dof_coords_1d(const gmg_ctx* ctx, int32_t level, double* x_host) {
+  if (!ctx || !x_host || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const Level& L = ctx->lv[level];
+  const std::vector<double> xi = lgl_nodes01(ctx->q);
+  for (int i = 0; i < L.N; ++i) x_host[i] = (i / ctx->q + xi[i % ctx->q]) / L.n;
+  return GMG_OK;
+}
+
+gmg_status gmg_lambda(const gmg_ctx* ctx, int32_t level, double* lambda_host) {
+  if (!ctx || !lambda_host || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  *lambda_host = ctx->lv[level].lam;
+  return GMG_OK;
+}
+
+gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev) {
+  if (!ctx || !d_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const Level& L = ctx->lv[level];
+  HIPCHK(ctx, launch_class_scale(false, ctx->q, L.N, L.tab.diag, 1.0, nullptr, d_dev, ctx->stream));
+  return GMG_OK;
+}
+
+gmg_status gmg_apply(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {
+  if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "apply: x and y must not alias");
+  return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0);
+}
+
+gmg_status gmg_mass(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {
+  if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "mass: x and y must not alias");
+  return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0, true);
+}
+
+gmg_status gmg_smooth(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, void* u_dev, int32_t nu) {
+  if (!ctx || !b_dev || !u_dev || nu < 0 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const int pi = pidx(prec);
+  STCHK(ensure_prec(ctx, pi));
+  return smooth(ctx, level, pi, b_dev, u_dev, nu, false);
+}
+
+gmg_status gmg_restrict(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* rf_dev, void* rc_dev) {
+  if (!ctx || !rf_dev || !rc_dev || level < 1 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const int pi = pidx(prec);
+  STCHK(ensure_prec(ctx, pi));
+  return restrict_level(ctx, level, pi, rf_dev, rc_dev);
+}
+
+gmg_status gmg_prolong(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* ec_dev, void* uf_dev) {
+  if (!ctx || !ec_dev || !uf_dev || level < 1 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const int pi = pidx(prec);
+  STCHK(ensure_prec(ctx, pi));
+  return prolong_level(ctx, level, pi, ec_dev, uf_dev);
+}
+
+gmg_status gmg_coarse_solve(gmg_ctx* ctx, gmg_prec prec, const void* b_dev, void* x_dev) {
+  if (!ctx || !b_dev || !x_dev || b_dev == x_dev) return GMG_E_ARG;
+  return coarse_solve(ctx, pidx(prec), b_dev, x_dev);
+}
+
+gmg_status gmg_vcycle(gmg_ctx* ctx, gmg_prec prec, const void* r_dev, void* z_dev) {
+  if (!ctx || !r_dev || !z_dev || r_dev == z_dev) return GMG_E_ARG;
+  const int pi = pidx(prec);
+  STCHK(ensure_prec(ctx, pi));
+  return vcycle_level(ctx, ctx->L - 1, pi, r_dev, z_dev);
+}
+
+gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev) {
+  if (!ctx || !f_dev || !b_dev || static_cast<const void*>(f_dev) == static_cast<void*>(b_dev)) return GMG_E_ARG;
+  const int l = ctx->L - 1;
+  STCHK(apply_op(ctx, l, 0, Epi::Apply, f_dev, b_dev, nullptr, nullptr, 0, 0, true));
+  return project(ctx, 0, ctx->lv[l].size, b_dev);
+}
+
+gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host) {
+  if (!ctx || !x_dev || !y_dev || !out_host || n < 0) return GMG_E_ARG;
+  HIPCHK(ctx, launch_dot(prec == GMG_FP32, n, x_dev, y_dev, ctx->part, ctx->scal + S_TMP, ctx->stream));
+  double hs[kNumScal];
+  STCHK(read_scalars(ctx, hs, kNumScal));
+  *out_host = hs[S_TMP];
+  return GMG_OK;
+}
+
+gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info) {
+  if (!ctx || !b_dev || !u_dev || !(rtol > 0.0)) return GMG_E_ARG;
+  gmg_ctx* c = ctx;
+  const int l = c->L - 1;
+  const int64_t n = c->lv[l].size;
+  const hipStream_t s = c->stream;
+  gmg_info inf{};
+  inf.t_setup = c->t_setup;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, s));
+  double hs[kNumScal];
+  HIPCHK(c, launch_dot(false, n, b_dev, b_dev, c->part, c->scal + S_TMP, s));
+  STCHK(read_scalars(c, hs, kNumScal));
+  const double nb = std::sqrt(hs[S_TMP]);
+  gmg_status st = GMG_OK;
+  if (!std::isfinite(nb)) {
+    st = fail(c, GMG_E_BREAKDOWN, "load vector is not finite");
+  } else if (nb == 0.0) {
+    HIPCHK(c, launch_fill_zero(false, n, u_dev, s));
+  } else if (c->opt.vcycle_prec != GMG_FP32) {
+    // plain FP64: CG / FCG(1) preconditioned by one FP64 V-cycle
+    HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));
+    int it = 0;
+    double rr = 0.0;
+    st = krylov(c, 0, c->opt.krylov == 1, b_dev, u_dev, c->kr[0], rtol * nb, c->opt.max_iters, &it, &rr);
+    inf.inner_iters = it;
+    inf.rel_residual_f64 = std::sqrt(rr) / nb;
+    if (st == GMG_OK && !(inf.rel_residual_f64 <= rtol)) st = fail(c, GMG_E_NOCONV, "max_iters reached");
+  } else {
+    // FP64 iterative refinement around FP32 FCG(1) with FP32 V-cycles
+    STCHK(ensure_prec(c, 1));
+    HIPCHK(c, launch_fill_zero(false, n, u_dev, s));
+    int total = 0;
+    while (true) {
+      STCHK(apply_op(c, l, 0, Epi::Residual, u_dev, c->kr[0], b_dev, nullptr, 0, 0));
+      STCHK(project(c, 0, n, c->kr[0]));
+      HIPCHK(c, launch_dot(false, n, c->kr[0], c->kr[0], c->part, c->scal + S_TMP, s));
+      STCHK(read_scalars(c, hs, kNumScal));
+      const double rn = std::sqrt(hs[S_TMP]);
+      inf.rel_residual_f64 = rn / nb;
+      if (!std::isfinite(rn)) {
+        st = fail(c, GMG_E_BREAKDOWN, "non-finite residual in refinement");
+        break;
+      }
+      if (rn <= rtol * nb) break;
+      if (total >= c->opt.max_iters) {
+        st = fail(c, GMG_E_NOCONV, "max_iters reached");
+        break;
+      }
+      HIPCHK(c, launch_cast_d2f(n, static_cast<const double*>(c->kr[0]), static_cast<float*>(c->kr[1]), s));
+      int it = 0;
+      double rr = 0.0;
+      // inner tolerance relative to the current residual, never below what FP32 can resolve
+      const double inner = std::max(c->opt.inner_rtol, 1e-6);
+      st = krylov(c, 1, true, nullptr, c->kc[1], c->kr[1], inner * rn, c->opt.max_iters - total, &it, &rr);
+      total += it;
+      if (st != GMG_OK) break;
+      HIPCHK(c, launch_add_f2d(n, static_cast<const float*>(c->kc[1]), u_dev, s));
+      ++inf.outer_iters;
+    }
+    inf.inner_iters = total;
+  }
+  if (st == GMG_OK || st == GMG_E_NOCONV) {
+    // zero integral: u <- u - (int u_h) / |cube|
+    const Level& F = c->lv[l];
+    HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u_dev, c->part, c->scal + S_TMP, s));
+    HIPCHK(c, launch_shift(false, n, c->scal, S_TMP, 1.0, u_dev, s));
+  }
+  HIPCHK(c, hipEventRecord(e1, s));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  inf.t_solve = ms * 1e-3;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (info) *info = inf;
+  return st;
+}
+
+gmg_status gmg_solve(gmg_ctx* ctx, const double* f_dev, double* u_dev, double rtol, gmg_info* info) {
+  if (!ctx || !f_dev || !u_dev) return GMG_E_ARG;
+  if (!ctx->bint) STCHK(dalloc(ctx, &ctx->bint, sizeof(double) * ctx->lv.back().size));
+  STCHK(gmg_rhs(ctx, f_dev, static_cast<double*>(ctx->bint)));
+  return gmg_solve_rhs(ctx, static_cast<const double*>(ctx->bint), u_dev, rtol, info);
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Host-side interface of the gfx950 kernels of the multigrid hot path.
+//
+// Every launcher enqueues on the given stream and returns the launch status.
+// Level vectors are N^3 DoF vectors, x fastest (index i + N (j + N k)),
+// N = q * n with n (elements per direction) a power of two.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gmg {
+
+constexpr int kMaxQ = 4;
+constexpr int kMaxTaps = 4 * kMaxQ + 1;
+
+// Coefficients of the sum-factorized operator on one level (FP64 master copy;
+// the launchers convert to the kernel precision).
+//   A = Kx (x) My (x) Mz + Mx (x) Ky (x) Mz + Mx (x) My (x) Kz,
+// with the x and y passes done by rows of the assembled periodic 1D matrices
+// (krow, mrow: node class c = i mod q, offsets -q..q) and the z pass done
+// element by element (zk, zm: (q+1) x (q+1) element matrices).
+// The same kernel applies the mass M (x) M (x) M with krow = 0 and zk = mass.
+struct OpTab {
+  int q;
+  double krow[kMaxQ][2 * kMaxQ + 1];
+  double mrow[kMaxQ][2 * kMaxQ + 1];
+  double zk[kMaxQ + 1][kMaxQ + 1];
+  double zm[kMaxQ + 1][kMaxQ + 1];
+  double dinv[kMaxQ * kMaxQ * kMaxQ];  // 1 / A_ii by node class (cx + q (cy + q cz))
+};
+
+// One-axis transfer table (separable P = P1 (x) P1 (x) P1 on uniform meshes).
+// Output index o along the axis has class c = o mod period and base
+// b = (o div period) * base_mul; it reads input (b + off[c][t]) mod in_len with
+// weight w[c][t] for t < ntap[c].
+struct AxisTab {
+  int period;
+  int base_mul;
+  int ntap[2 * kMaxQ];
+  int off[2 * kMaxQ][kMaxTaps];
+  double w[2 * kMaxQ][kMaxTaps];
+};
+
+enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2 };
+
+// out = A x                          (Epi::Apply)
+// out = b - A x                      (Epi::Residual)
+// out = x + c1 (x - xp) + c2 D^-1 (b - A x)   (Epi::Cheb; xp unused when c1 == 0,
+//                                      read as zero when null; out may alias xp, never x)
+struct ApplyArgs {
+  int N;  // lattice nodes per direction
+  int n;  // elements per direction
+  const void* x;
+  void* out;
+  const void* b;
+  const void* xp;
+  double c1, c2;
+  Epi epi;
+};
+
+hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
+
+// out[idx] (+)= sum_t w in[...] along one axis; dims are the OUTPUT extents
+// (d0 = x, d1 = y, d2 = z); in_len is the input extent along `axis`.
+hipError_t launch_axis(const AxisTab& tab, bool fp32, const void* in, void* out, int d0, int d1, int d2,
+                       int axis, int in_len, bool accumulate, hipStream_t s);
+
+// out = c * tab[class(i)] * in  (class table of length q^3; in may be null -> 1)
+hipError_t launch_class_scale(bool fp32, int q, int N, const double* tab, double c, const void* in, void* out,
+                              hipStream_t s);
+
+// Reductions: partial sums per block in FP64 into `part` (length >= kRedBlocks),
+// then one block adds them in a fixed order into *dst (device).
+constexpr int kRedBlocks = 1024;
+hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double* part, double* dst,
+                      hipStream_t s);
+hipError_t launch_sum(bool fp32, int64_t n, const void* x, double* part, double* dst, hipStream_t s);
+// sum_i tab[class(i)] x_i (the integral of the FE function on a uniform level)
+hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const void* x, double* part,
+                            double* dst, hipStream_t s);
+
+// Vector updates whose coefficients live in device memory (no host sync).
+//  axpy2:   u += a p ; r -= a w        with a = sc[i_num] / sc[i_den]
+//  xpby:    p = z + b p                with b = sgn * sc[i_num] / sc[i_den]
+//  shift:   v -= sc[i] * scale         (projection: scale = 1/n)
+hipError_t launch_axpy2(bool fp32, int64_t n, const double* sc, int i_num, int i_den, void* u, const void* p,
+                        void* r, const void* w, hipStream_t s);
+hipError_t launch_xpby(bool fp32, int64_t n, const double* sc, int i_num, int i_den, double sgn, const void* z,
+                       void* p, hipStream_t s);
+hipError_t launch_shift(bool fp32, int64_t n, const double* sc, int i, double scale, void* v, hipStream_t s);
+
+// y += a x with a host scalar; v_i += c tab[class(i)].
+hipError_t launch_axpy(bool fp32, int64_t n, double a, const void* x, void* y, hipStream_t s);
+hipError_t launch_class_axpy(bool fp32, int q, int N, const double* tab, double c, void* v, hipStream_t s);
+// out_i = 2 U_i - 1 with U_i the i-th uniform double of the SplitMix64 stream `key`.
+hipError_t launch_splitmix_start(uint64_t key, int64_t n, double* out, hipStream_t s);
+
+// Precision conversions: f64 -> f32 copy, and u64 += c32.
+hipError_t launch_cast_d2f(int64_t n, const double* in, float* out, hipStream_t s);
+hipError_t launch_add_f2d(int64_t n, const float* c, double* u, hipStream_t s);
+hipError_t launch_fill_zero(bool fp32, int64_t n, void* v, hipStream_t s);
+hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStream_t s);
+
+// Coarsest solve: x = Ainv (b - mean(b)), Ainv dense symmetric N0 x N0 (FP64),
+// b and x of the kernel precision, arithmetic in FP64.
+hipError_t launch_coarse(bool fp32, int n0, const double* ainv, const void* b, void* x, hipStream_t s);
+
+}  // namespace gmg

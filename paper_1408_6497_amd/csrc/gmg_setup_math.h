@@ -1,0 +1,34 @@
+// Host-side setup arithmetic of the library (see gmg_setup_math.cpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "gmg_kernels.h"
+
+namespace gmg {
+
+// Per-level tables of a uniform periodic mesh with n elements of order q.
+struct LevelTables {
+  OpTab stiff;                             // stiffness apply (and D^-1 by class)
+  OpTab mass;                              // consistent mass apply
+  double diag[kMaxQ * kMaxQ * kMaxQ];      // A_ii by node class
+  double dinv_sqrt[kMaxQ * kMaxQ * kMaxQ]; // A_ii^-1/2
+  double dsqrt[kMaxQ * kMaxQ * kMaxQ];     // A_ii^1/2
+  double wint[kMaxQ * kMaxQ * kMaxQ];      // int phi_i dx (row sums of M) by class
+};
+
+std::vector<double> lgl_nodes01(int q);
+void gauss01(int m, std::vector<double>* pts, std::vector<double>* wts);
+double lagrange_at(const std::vector<double>& xi, int a, double t);
+double lagrange_deriv_at(const std::vector<double>& xi, int a, double t);
+void reference_matrices(int q, std::vector<double>* khat, std::vector<double>* mhat);
+LevelTables make_level_tables(int q, int n);
+void make_transfer_tables(int q, AxisTab* prolong, AxisTab* restrict_);
+// (A_0 + 1 1^T / N0)^-1 of the coarsest level, dense, symmetric, row-major.
+std::vector<double> coarse_pseudo_inverse(int q, int n);
+uint64_t splitmix64_at(uint64_t key, uint64_t i);
+void lanczos_start_vector(uint64_t seed, int level, int64_t count, double* out);
+double tridiag_max_eig(const std::vector<double>& alpha, const std::vector<double>& beta);
+
+}  // namespace gmg

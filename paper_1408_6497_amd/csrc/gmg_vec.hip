@@ -1,0 +1,418 @@
+// Intergrid transfers, reductions, vector updates and the coarsest solve.
+//
+// Transfers (Section 2.3.4, eqs. 2.1-2.2): on nested uniform meshes
+// P = P1 (x) P1 (x) P1 with P1(i, j) = phi_j^{coarse}(p_i); it is applied as
+// three one-axis passes, each output node gathering its few banded taps (no
+// scatter, so fine nodes shared by coarse elements are counted once and no
+// atomics are needed).  R = P^T uses the transposed taps.
+//
+// Reductions accumulate in FP64 whatever the vector type: 64-lane wavefront
+// shuffles, then LDS across the block, then a second single-block pass over the
+// per-block partials in a fixed order (deterministic results).
+#include "gmg_kernels.h"
+
+namespace gmg {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n, int per_thread = 4) {
+  int64_t g = (n + static_cast<int64_t>(kBlock) * per_thread - 1) / (static_cast<int64_t>(kBlock) * per_thread);
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  return static_cast<int>(g);
+}
+
+// ---------------------------------------------------------------- transfers
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axis(const T* __restrict__ in, T* __restrict__ out, const AxisTab tab,
+                                                  const int d0, const int d1, const int d2, const int axis,
+                                                  const int in_len, const int accumulate) {
+  const int64_t total = static_cast<int64_t>(d0) * d1 * d2;
+  const int inm = in_len - 1;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int c0 = static_cast<int>(idx % d0);
+    int64_t rest = idx / d0;
+    int c1 = static_cast<int>(rest % d1);
+    int c2 = static_cast<int>(rest / d1);
+    int o = axis == 0 ? c0 : (axis == 1 ? c1 : c2);
+    const int cls = o % tab.period;
+    const int base = (o / tab.period) * tab.base_mul;
+    // input strides with extent in_len along `axis`
+    const int e0 = axis == 0 ? in_len : d0;
+    const int e1 = axis == 1 ? in_len : d1;
+    double accv = 0.0;
+    const int nt = tab.ntap[cls];
+    for (int t = 0; t < nt; ++t) {
+      const int ic = (base + tab.off[cls][t] + in_len) & inm;
+      int i0 = c0, i1 = c1, i2 = c2;
+      if (axis == 0) i0 = ic;
+      else if (axis == 1) i1 = ic;
+      else i2 = ic;
+      const int64_t iidx = i0 + static_cast<int64_t>(e0) * (i1 + static_cast<int64_t>(e1) * i2);
+      accv += tab.w[cls][t] * static_cast<double>(in[iidx]);
+    }
+    if (accumulate) out[idx] = static_cast<T>(static_cast<double>(out[idx]) + accv);
+    else out[idx] = static_cast<T>(accv);
+  }
+}
+
+// ---------------------------------------------------------------- class tables
+struct ClassTab {
+  double v[kMaxQ * kMaxQ * kMaxQ];
+};
+
+__device__ __forceinline__ int node_class(int64_t idx, int N, int q) {
+  const int i = static_cast<int>(idx % N);
+  const int64_t r = idx / N;
+  const int j = static_cast<int>(r % N);
+  const int k = static_cast<int>(r / N);
+  return (i % q) + q * ((j % q) + q * (k % q));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_class_scale(const ClassTab tab, const int q, const int N, const double c,
+                                                         const T* in, T* out) {
+  const int64_t total = static_cast<int64_t>(N) * N * N;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double v = in ? static_cast<double>(in[idx]) : 1.0;
+    out[idx] = static_cast<T>(c * tab.v[node_class(idx, N, q)] * v);
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+  }
+  return s;  // valid in thread 0
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot(const int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                                                 double* part) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s = fma(static_cast<double>(x[i]), static_cast<double>(y ? y[i] : T(1)), s);
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_class_dot(const ClassTab tab, const int q, const int N,
+                                                       const T* __restrict__ x, double* part) {
+  const int64_t n = static_cast<int64_t>(N) * N * N;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s = fma(tab.v[node_class(i, N, q)], static_cast<double>(x[i]), s);
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish(const double* part, const int nparts, double* dst) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *dst = s;
+}
+
+inline int red_grid(int64_t n) {
+  int g = grid_for(n, 8);
+  return g > kRedBlocks ? kRedBlocks : g;
+}
+
+// ---------------------------------------------------------------- vector updates
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axpy2(const int64_t n, const double* sc, const int inum, const int iden,
+                                                   T* u, const T* __restrict__ p, T* r, const T* __restrict__ w) {
+  const T a = static_cast<T>(sc[inum] / sc[iden]);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    u[i] = fma(a, p[i], u[i]);
+    r[i] = fma(-a, w[i], r[i]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_xpby(const int64_t n, const double* sc, const int inum, const int iden,
+                                                  const double sgn, const T* __restrict__ z, T* p) {
+  const T b = static_cast<T>(sgn * sc[inum] / sc[iden]);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = fma(b, p[i], z[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_shift(const int64_t n, const double* sc, const int i0, const double scale,
+                                                   T* v) {
+  const T m = static_cast<T>(sc[i0] * scale);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    v[i] -= m;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axpy(const int64_t n, const double a, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
+  const T aa = static_cast<T>(a);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = fma(aa, x[i], y[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_class_axpy(const ClassTab tab, const int q, const int N, const double c,
+                                                        T* v) {
+  const int64_t total = static_cast<int64_t>(N) * N * N;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    v[idx] = static_cast<T>(static_cast<double>(v[idx]) + c * tab.v[node_class(idx, N, q)]);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output i of the stream with key k.
+__global__ void __launch_bounds__(kBlock) k_splitmix_start(const uint64_t key, const int64_t n, double* out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    uint64_t z = key + static_cast<uint64_t>(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    out[i] = 2.0 * static_cast<double>(z >> 11) * 0x1.0p-53 - 1.0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cast_d2f(const int64_t n, const double* __restrict__ in,
+                                                      float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<float>(in[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_add_f2d(const int64_t n, const float* __restrict__ c,
+                                                     double* __restrict__ u) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    u[i] += static_cast<double>(c[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill_zero(const int64_t n, T* v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    v[i] = T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy(const int64_t n, const T* __restrict__ in, T* __restrict__ out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[i] = in[i];
+}
+
+// ---------------------------------------------------------------- coarsest solve
+constexpr int kCoarseBlock = 512;
+constexpr int kCoarseMax = 4096;
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseBlock) k_coarse(const int n0, const double* __restrict__ ainv,
+                                                          const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ double bs[kCoarseMax];
+  __shared__ double red[kCoarseBlock / 64];
+  __shared__ double mean;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n0; i += kCoarseBlock) {
+    const double v = static_cast<double>(b[i]);
+    bs[i] = v;
+    s += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kCoarseBlock / 64; ++w) t += red[w];
+    mean = t / n0;
+  }
+  __syncthreads();
+  const double m = mean;
+  for (int i = threadIdx.x; i < n0; i += kCoarseBlock) {
+    double acc = 0.0;
+    for (int j = 0; j < n0; ++j) acc = fma(ainv[static_cast<int64_t>(j) * n0 + i], bs[j] - m, acc);
+    x[i] = static_cast<T>(acc);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_axis(const AxisTab& tab, bool fp32, const void* in, void* out, int d0, int d1, int d2, int axis,
+                       int in_len, bool accumulate, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(d0) * d1 * d2;
+  const int g = grid_for(total, 2);
+  if (fp32)
+    hipLaunchKernelGGL(k_axis<float>, dim3(g), dim3(kBlock), 0, s, static_cast<const float*>(in),
+                       static_cast<float*>(out), tab, d0, d1, d2, axis, in_len, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_axis<double>, dim3(g), dim3(kBlock), 0, s, static_cast<const double*>(in),
+                       static_cast<double*>(out), tab, d0, d1, d2, axis, in_len, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_scale(bool fp32, int q, int N, const double* tab, double c, const void* in, void* out,
+                              hipStream_t s) {
+  ClassTab ct{};
+  for (int i = 0; i < q * q * q; ++i) ct.v[i] = tab[i];
+  const int64_t total = static_cast<int64_t>(N) * N * N;
+  const int g = grid_for(total);
+  if (fp32)
+    hipLaunchKernelGGL(k_class_scale<float>, dim3(g), dim3(kBlock), 0, s, ct, q, N, c,
+                       static_cast<const float*>(in), static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(k_class_scale<double>, dim3(g), dim3(kBlock), 0, s, ct, q, N, c,
+                       static_cast<const double*>(in), static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double* part, double* dst, hipStream_t s) {
+  const int g = red_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_dot<float>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const float*>(x),
+                       static_cast<const float*>(y), part);
+  else
+    hipLaunchKernelGGL(k_dot<double>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const double*>(x),
+                       static_cast<const double*>(y), part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(bool fp32, int64_t n, const void* x, double* part, double* dst, hipStream_t s) {
+  return launch_dot(fp32, n, x, nullptr, part, dst, s);
+}
+
+hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const void* x, double* part, double* dst,
+                            hipStream_t s) {
+  ClassTab ct{};
+  for (int i = 0; i < q * q * q; ++i) ct.v[i] = tab[i];
+  const int64_t n = static_cast<int64_t>(N) * N * N;
+  const int g = red_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_class_dot<float>, dim3(g), dim3(kBlock), 0, s, ct, q, N, static_cast<const float*>(x),
+                       part);
+  else
+    hipLaunchKernelGGL(k_class_dot<double>, dim3(g), dim3(kBlock), 0, s, ct, q, N, static_cast<const double*>(x),
+                       part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy2(bool fp32, int64_t n, const double* sc, int inum, int iden, void* u, const void* p, void* r,
+                        const void* w, hipStream_t s) {
+  const int g = grid_for(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_axpy2<float>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, static_cast<float*>(u),
+                       static_cast<const float*>(p), static_cast<float*>(r), static_cast<const float*>(w));
+  else
+    hipLaunchKernelGGL(k_axpy2<double>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, static_cast<double*>(u),
+                       static_cast<const double*>(p), static_cast<double*>(r), static_cast<const double*>(w));
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby(bool fp32, int64_t n, const double* sc, int inum, int iden, double sgn, const void* z, void* p,
+                       hipStream_t s) {
+  const int g = grid_for(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_xpby<float>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, sgn,
+                       static_cast<const float*>(z), static_cast<float*>(p));
+  else
+    hipLaunchKernelGGL(k_xpby<double>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, sgn,
+                       static_cast<const double*>(z), static_cast<double*>(p));
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(bool fp32, int64_t n, const double* sc, int i, double scale, void* v, hipStream_t s) {
+  const int g = grid_for(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_shift<float>, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, static_cast<float*>(v));
+  else
+    hipLaunchKernelGGL(k_shift<double>, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, static_cast<double*>(v));
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(bool fp32, int64_t n, double a, const void* x, void* y, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_axpy<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, a, static_cast<const float*>(x),
+                       static_cast<float*>(y));
+  else
+    hipLaunchKernelGGL(k_axpy<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, a, static_cast<const double*>(x),
+                       static_cast<double*>(y));
+  return hipGetLastError();
+}
+
+hipError_t launch_class_axpy(bool fp32, int q, int N, const double* tab, double c, void* v, hipStream_t s) {
+  ClassTab ct{};
+  for (int i = 0; i < q * q * q; ++i) ct.v[i] = tab[i];
+  const int64_t total = static_cast<int64_t>(N) * N * N;
+  if (fp32)
+    hipLaunchKernelGGL(k_class_axpy<float>, dim3(grid_for(total)), dim3(kBlock), 0, s, ct, q, N, c,
+                       static_cast<float*>(v));
+  else
+    hipLaunchKernelGGL(k_class_axpy<double>, dim3(grid_for(total)), dim3(kBlock), 0, s, ct, q, N, c,
+                       static_cast<double*>(v));
+  return hipGetLastError();
+}
+
+hipError_t launch_splitmix_start(uint64_t key, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitmix_start, dim3(grid_for(n)), dim3(kBlock), 0, s, key, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_d2f(int64_t n, const double* in, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_d2f, dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f2d(int64_t n, const float* c, double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f2d, dim3(grid_for(n)), dim3(kBlock), 0, s, n, c, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(bool fp32, int64_t n, void* v, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_fill_zero<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, static_cast<float*>(v));
+  else
+    hipLaunchKernelGGL(k_fill_zero<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, static_cast<double*>(v));
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_copy<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, static_cast<const float*>(in),
+                       static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(k_copy<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, static_cast<const double*>(in),
+                       static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse(bool fp32, int n0, const double* ainv, const void* b, void* x, hipStream_t s) {
+  if (n0 < 1 || n0 > kCoarseMax) return hipErrorInvalidValue;
+  if (fp32)
+    hipLaunchKernelGGL(k_coarse<float>, dim3(1), dim3(kCoarseBlock), 0, s, n0, ainv, static_cast<const float*>(b),
+                       static_cast<float*>(x));
+  else
+    hipLaunchKernelGGL(k_coarse<double>, dim3(1), dim3(kCoarseBlock), 0, s, n0, ainv,
+                       static_cast<const double*>(b), static_cast<double*>(x));
+  return hipGetLastError();
+}
+
+}  // namespace gmg

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libgmg.so (include/gmg.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Device buffers are torch tensors on the GPU (passed by data_ptr());
+torch is used for device memory and the stream, nothing else.  If the library
+is not built, every call raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmg.so")
+
+GMG_FP64 = 0
+GMG_FP32 = 1
+
+_STATUS = {
+    0: "GMG_OK", 1: "GMG_E_ARG", 2: "GMG_E_MESH", 3: "GMG_E_OOM", 4: "GMG_E_HIP",
+    5: "GMG_E_NOCONV", 6: "GMG_E_BREAKDOWN", 7: "GMG_E_STATE",
+}
+
+EXPORTS = [
+    "gmg_setup", "gmg_destroy", "gmg_num_levels", "gmg_num_dofs", "gmg_dof_coords_1d", "gmg_lambda",
+    "gmg_diagonal", "gmg_apply", "gmg_mass", "gmg_smooth", "gmg_restrict", "gmg_prolong",
+    "gmg_coarse_solve", "gmg_vcycle", "gmg_rhs", "gmg_solve", "gmg_solve_rhs", "gmg_dot",
+    "gmg_status_string", "gmg_last_error",
+]
+
+
+class GmgMesh(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("n", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class GmgOptions(ctypes.Structure):
+    _fields_ = [
+        ("cheb_degree", ctypes.c_int32), ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+        ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+        ("lanczos_steps", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_omega", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("vcycle_prec", ctypes.c_int32), ("krylov", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("lambda_override", ctypes.c_double),
+    ]
+
+
+class GmgInfo(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("rel_residual_f64", ctypes.c_double), ("t_setup", ctypes.c_double),
+        ("t_solve", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class GmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libgmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "gmg_setup": [ctypes.POINTER(GmgMesh), ctypes.POINTER(GmgOptions), P, ctypes.POINTER(P)],
+        "gmg_destroy": [P],
+        "gmg_num_levels": [P, ctypes.POINTER(I32)],
+        "gmg_num_dofs": [P, I32, ctypes.POINTER(I64)],
+        "gmg_dof_coords_1d": [P, I32, P],
+        "gmg_lambda": [P, I32, ctypes.POINTER(D)],
+        "gmg_diagonal": [P, I32, P],
+        "gmg_apply": [P, I32, I32, P, P],
+        "gmg_mass": [P, I32, I32, P, P],
+        "gmg_smooth": [P, I32, I32, P, P, I32],
+        "gmg_restrict": [P, I32, I32, P, P],
+        "gmg_prolong": [P, I32, I32, P, P],
+        "gmg_coarse_solve": [P, I32, P, P],
+        "gmg_vcycle": [P, I32, P, P],
+        "gmg_rhs": [P, P, P],
+        "gmg_solve": [P, P, P, D, ctypes.POINTER(GmgInfo)],
+        "gmg_solve_rhs": [P, P, P, D, ctypes.POINTER(GmgInfo)],
+        "gmg_dot": [P, I32, I64, P, P, ctypes.POINTER(D)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.gmg_status_string.argtypes = [ctypes.c_int]
+    lib.gmg_status_string.restype = ctypes.c_char_p
+    lib.gmg_last_error.argtypes = [P]
+    lib.gmg_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns one gmg_ctx (a multigrid hierarchy on the current HIP device)."""
+
+    def __init__(self, order, n, levels=0, stream=None, **opts):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        mesh = GmgMesh(order=order, n=n, levels=levels, reserved=0)
+        o = GmgOptions()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, v)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream),
+                                ctypes.byref(h))
+        if st != 0:
+            raise GmgError(st, "gmg_setup failed")
+        self.h = h
+        self.order = order
+        self.n = n
+        nl = ctypes.c_int32()
+        self._check(self.lib.gmg_num_levels(self.h, ctypes.byref(nl)))
+        self.levels = nl.value
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.gmg_last_error(self.h) if getattr(self, "h", None) else b""
+            raise GmgError(st, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries
+    def num_dofs(self, level=-1):
+        level = self._lvl(level)
+        v = ctypes.c_int64()
+        self._check(self.lib.gmg_num_dofs(self.h, level, ctypes.byref(v)))
+        return v.value
+
+    def lattice(self, level=-1):
+        return round(self.num_dofs(level) ** (1.0 / 3.0))
+
+    def dof_coords_1d(self, level=-1):
+        import numpy as np
+        level = self._lvl(level)
+        x = np.zeros(self.lattice(level), dtype=np.float64)
+        self._check(self.lib.gmg_dof_coords_1d(self.h, level, x.ctypes.data_as(ctypes.c_void_p)))
+        return x
+
+    def lam(self, level=-1):
+        v = ctypes.c_double()
+        self._check(self.lib.gmg_lambda(self.h, self._lvl(level), ctypes.byref(v)))
+        return v.value
+
+    def _lvl(self, level):
+        return level + self.levels if level < 0 else level
+
+    def _vec(self, t, level, prec=None):
+        torch = self._torch
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("expected a contiguous GPU tensor")
+        if prec is not None:
+            want = torch.float32 if prec == GMG_FP32 else torch.float64
+            if t.dtype != want:
+                raise ValueError(f"expected dtype {want}, got {t.dtype}")
+        if level is not None and t.numel() != self.num_dofs(level):
+            raise ValueError(f"expected {self.num_dofs(level)} values, got {t.numel()}")
+        return _ptr(t)
+
+    @staticmethod
+    def prec_of(t):
+        import torch
+        return GMG_FP32 if t.dtype == torch.float32 else GMG_FP64
+
+    # -- operations (enqueued on the context stream)
+    def diagonal(self, level, d):
+        level = self._lvl(level)
+        self._check(self.lib.gmg_diagonal(self.h, level, self._vec(d, level, GMG_FP64)))
+
+    def apply(self, level, x, y):
+        level = self._lvl(level)
+        p = self.prec_of(x)
+        self._check(self.lib.gmg_apply(self.h, level, p, self._vec(x, level, p), self._vec(y, level, p)))
+
+    def mass(self, level, x, y):
+        level = self._lvl(level)
+        p = self.prec_of(x)
+        self._check(self.lib.gmg_mass(self.h, level, p, self._vec(x, level, p), self._vec(y, level, p)))
+
+    def smooth(self, level, b, u, nu):
+        level = self._lvl(level)
+        p = self.prec_of(b)
+        self._check(self.lib.gmg_smooth(self.h, level, p, self._vec(b, level, p), self._vec(u, level, p), nu))
+
+    def restrict(self, level, rf, rc):
+        level = self._lvl(level)
+        p = self.prec_of(rf)
+        self._check(self.lib.gmg_restrict(self.h, level, p, self._vec(rf, level, p), self._vec(rc, level - 1, p)))
+
+    def prolong(self, level, ec, uf):
+        level = self._lvl(level)
+        p = self.prec_of(ec)
+        self._check(self.lib.gmg_prolong(self.h, level, p, self._vec(ec, level - 1, p), self._vec(uf, level, p)))
+
+    def coarse_solve(self, b, x):
+        p = self.prec_of(b)
+        self._check(self.lib.gmg_coarse_solve(self.h, p, self._vec(b, 0, p), self._vec(x, 0, p)))
+
+    def vcycle(self, r, z):
+        p = self.prec_of(r)
+        lv = self.levels - 1
+        self._check(self.lib.gmg_vcycle(self.h, p, self._vec(r, lv, p), self._vec(z, lv, p)))
+
+    def rhs(self, f, b):
+        lv = self.levels - 1
+        self._check(self.lib.gmg_rhs(self.h, self._vec(f, lv, GMG_FP64), self._vec(b, lv, GMG_FP64)))
+
+    def dot(self, x, y):
+        v = ctypes.c_double()
+        p = self.prec_of(x)
+        self._check(self.lib.gmg_dot(self.h, p, x.numel(), self._vec(x, None, p), self._vec(y, None, p),
+                                     ctypes.byref(v)))
+        return v.value
+
+    def solve(self, f, u, rtol, raise_on_noconv=True):
+        lv = self.levels - 1
+        info = GmgInfo()
+        st = self.lib.gmg_solve(self.h, self._vec(f, lv, GMG_FP64), self._vec(u, lv, GMG_FP64), rtol,
+                                ctypes.byref(info))
+        if st != 0 and (raise_on_noconv or st != 5):
+            self._check(st)
+        return info
+
+    def solve_rhs(self, b, u, rtol, raise_on_noconv=True):
+        lv = self.levels - 1
+        info = GmgInfo()
+        st = self.lib.gmg_solve_rhs(self.h, self._vec(b, lv, GMG_FP64), self._vec(u, lv, GMG_FP64), rtol,
+                                    ctypes.byref(info))
+        if st != 0 and (raise_on_noconv or st != 5):
+            self._check(st)
+        return info

@@ -1,0 +1,229 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: FP64 apply 1e-12 relative (l2), FP32 apply 2e-5; composite steps
+(smoother, V-cycle) accumulate a few applies, so they use 1e-11 (FP64) and
+1e-4 (FP32); solves are judged by the oracle's own CSR residual of the GPU
+solution (<= tolerance) and the distance to the oracle's solution is reported.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import (FP32_TOL, FP64_TOL, mean_free_normal, oracle_hierarchy, rel_l2, to_dev, to_host,
+                              torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(1, 4), (1, 8), (1, 32), (2, 2), (2, 4), (2, 8), (2, 16), (4, 2), (4, 4), (4, 8)]
+
+
+def _ctx(q, n, levels=0, **kw):
+    torch_cuda()
+    from paper_1408_6497_amd import Context
+    return Context(q, n, levels, **kw)
+
+
+def _levels_for(ctx):
+    return ctx.levels
+
+
+@pytest.mark.parametrize("q,n", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_parity(q, n, prec):
+    torch = torch_cuda()
+    from oracle import operator as op
+    print(f"[apply] q={q} n={n} prec={prec}", flush=True)
+    ctx = _ctx(q, n, 1)
+    A = op.assemble(q, n)
+    x = mean_free_normal(A.shape[0], seed=100 + q * 10 + n)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    xd = to_dev(x, dt)
+    yd = torch.empty_like(xd)
+    ctx.apply(0, xd, yd)
+    torch.cuda.synchronize()
+    y_gpu = to_host(yd)
+    y_orc = A @ to_host(xd)   # the oracle sees the same (rounded) input
+    err = rel_l2(y_gpu, y_orc)
+    tol = FP64_TOL if prec == "fp64" else FP32_TOL
+    print(f"  rel_l2={err:.3e}", flush=True)
+    assert err <= tol
+    assert np.max(np.abs(y_gpu - y_orc)) <= 10 * tol * np.max(np.abs(y_orc))
+
+
+@pytest.mark.parametrize("q,n", [(1, 8), (2, 8), (4, 4)])
+def test_mass_diagonal_coords(q, n):
+    torch = torch_cuda()
+    from oracle import operator as op
+    ctx = _ctx(q, n, 1)
+    assert np.max(np.abs(ctx.dof_coords_1d(0) - op.dof_coords_1d(q, n))) < 1e-15
+    M = op.assemble(q, n, "mass")
+    x = mean_free_normal(M.shape[0], seed=7)
+    xd = to_dev(x, torch.float64)
+    yd = torch.empty_like(xd)
+    ctx.mass(0, xd, yd)
+    d = torch.empty_like(xd)
+    ctx.diagonal(0, d)
+    torch.cuda.synchronize()
+    assert rel_l2(to_host(yd), M @ x) <= FP64_TOL
+    assert rel_l2(to_host(d), op.assemble(q, n).diagonal()) <= 1e-14
+
+
+@pytest.mark.parametrize("q,n", [(1, 16), (2, 8), (4, 4)])
+def test_lanczos_lambda_parity(q, n):
+    torch_cuda()
+    ctx = _ctx(q, n, 0, seed=11)
+    H = oracle_hierarchy(q, n, ctx.levels, seed=11)
+    for l in range(ctx.levels):
+        assert abs(ctx.lam(l) - H.levels[l].lam) <= 1e-10 * H.levels[l].lam, (l, ctx.lam(l), H.levels[l].lam)
+
+
+@pytest.mark.parametrize("q,n", [(1, 16), (2, 8), (4, 4)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_smoother_parity(q, n, prec):
+    torch = torch_cuda()
+    ctx = _ctx(q, n, 0, seed=3)
+    H = oracle_hierarchy(q, n, ctx.levels, seed=3)
+    lev = H.finest
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    b = to_dev(mean_free_normal(lev.size, 21), dt)
+    u = to_dev(np.random.default_rng(22).standard_normal(lev.size), dt)
+    u0 = to_host(u)
+    ctx.smooth(ctx.levels - 1, b, u, 2)
+    torch.cuda.synchronize()
+    ref = H.smooth(lev, to_host(b), u0, 2)
+    err = rel_l2(to_host(u), ref)
+    print(f"[smooth] q={q} n={n} {prec} rel={err:.2e}", flush=True)
+    assert err <= (1e-11 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("q,n", [(1, 8), (2, 4), (2, 8), (4, 4)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_transfer_parity(q, n, prec):
+    torch = torch_cuda()
+    from oracle import transfer
+    ctx = _ctx(q, n, 2)
+    P = transfer.prolongation(q, n // 2)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    tol = 1e-14 if prec == "fp64" else 1e-6
+    rf = to_dev(np.random.default_rng(5).standard_normal(P.shape[0]), dt)
+    rc = torch.empty(P.shape[1], dtype=dt, device="cuda")
+    ctx.restrict(1, rf, rc)
+    ec = to_dev(np.random.default_rng(6).standard_normal(P.shape[1]), dt)
+    uf = to_dev(np.random.default_rng(7).standard_normal(P.shape[0]), dt)
+    uf0 = to_host(uf)
+    ctx.prolong(1, ec, uf)
+    torch.cuda.synchronize()
+    assert rel_l2(to_host(rc), P.T @ to_host(rf)) <= tol
+    assert rel_l2(to_host(uf), uf0 + P @ to_host(ec)) <= tol
+
+
+@pytest.mark.parametrize("q,n", [(1, 8), (2, 4), (4, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_coarse_solve_parity(q, n, prec):
+    torch = torch_cuda()
+    ctx = _ctx(q, n, 1)
+    H = oracle_hierarchy(q, n, 1)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    b = to_dev(np.random.default_rng(8).standard_normal(H.levels[0].size), dt)   # not mean-free on purpose
+    x = torch.empty_like(b)
+    ctx.coarse_solve(b, x)
+    torch.cuda.synchronize()
+    ref = H.coarse_solve(to_host(b))
+    assert rel_l2(to_host(x), ref) <= (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("q,n,levels", [(1, 16, 3), (1, 32, 4), (2, 8, 0), (2, 16, 0), (4, 4, 0), (4, 8, 0)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vcycle_parity(q, n, levels, prec):
+    torch = torch_cuda()
+    ctx = _ctx(q, n, levels, seed=5)
+    H = oracle_hierarchy(q, n, ctx.levels, seed=5)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    r = to_dev(mean_free_normal(H.finest.size, 31), dt)
+    z = torch.empty_like(r)
+    ctx.vcycle(r, z)
+    torch.cuda.synchronize()
+    ref = H.vcycle(to_host(r))
+    err = rel_l2(to_host(z), ref)
+    print(f"[vcycle] q={q} n={n} L={ctx.levels} {prec} rel={err:.2e}", flush=True)
+    assert err <= (1e-11 if prec == "fp64" else 1e-4)
+
+
+def _oracle_residual(q, n, u, b):
+    from oracle import operator as op
+    A = op.assemble(q, n)
+    r = b - A @ u
+    r -= r.mean()
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def test_solve_c1_closed_form():
+    """Q1, 32^3, 4 levels, f = 12 pi^2 sin sin sin, plain FP64 to 1e-10."""
+    torch = torch_cuda()
+    from workloads import sin_source, sin_exact
+    from oracle import multigrid as mg, krylov
+    q, n = 1, 32
+    ctx = _ctx(q, n, 4)
+    x1 = ctx.dof_coords_1d()
+    f = sin_source(x1).cuda()
+    u = torch.empty_like(f)
+    info = ctx.solve(f, u, 1e-10)
+    torch.cuda.synchronize()
+    ug = to_host(u)
+    b = mg.rhs(q, n, to_host(f))
+    res = _oracle_residual(q, n, ug, b)
+    th, h = 2 * math.pi / n, 1.0 / n
+    amp = 4 * math.pi ** 2 * (h * (4 + 2 * math.cos(th)) / 6) / ((2 - 2 * math.cos(th)) / h)
+    closed = amp * sin_exact(x1)
+    print(f"[c1] iters={info.inner_iters} gpu_rel={info.rel_residual_f64:.2e} oracle_res={res:.2e} "
+          f"err_vs_closed={np.max(np.abs(ug - closed)):.2e}", flush=True)
+    assert info.rel_residual_f64 <= 1e-10
+    assert res <= 1e-10 * (1 + 1e-3)
+    assert np.max(np.abs(ug - closed)) < 1e-9
+
+
+@pytest.mark.parametrize("q,n,prec", [(2, 16, "fp64"), (2, 16, "fp32"), (4, 8, "fp32"), (1, 32, "fp32")])
+def test_solve_gaussian_source(q, n, prec):
+    """Gaussian-sum source, FP64 PCG or FP32 V-cycle + FP64 refinement, to 1e-8."""
+    torch = torch_cuda()
+    from workloads import gaussian_params, gaussian_source
+    from oracle import multigrid as mg, krylov
+    from paper_1408_6497_amd import GMG_FP32, GMG_FP64
+    vp = GMG_FP32 if prec == "fp32" else GMG_FP64
+    ctx = _ctx(q, n, 0, seed=1, vcycle_prec=vp)
+    params = gaussian_params(0, 32, 0.02, 0.1)
+    f = gaussian_source(ctx.dof_coords_1d(), params).cuda()
+    u = torch.empty_like(f)
+    info = ctx.solve(f, u, 1e-8)
+    torch.cuda.synchronize()
+    ug = to_host(u)
+    b = mg.rhs(q, n, to_host(f))
+    res = _oracle_residual(q, n, ug, b)
+    H = oracle_hierarchy(q, n, ctx.levels, seed=1)
+    uo, oinfo = krylov.pcg(H.finest.A, b, H.vcycle, 1e-12)
+    uo = krylov.normalize_mean(uo, q, n)
+    diff = rel_l2(ug, uo)
+    print(f"[solve] q={q} n={n} {prec} outer={info.outer_iters} inner={info.inner_iters} "
+          f"gpu_rel={info.rel_residual_f64:.2e} oracle_res={res:.2e} |u-u_orc|/|u_orc|={diff:.2e}", flush=True)
+    assert info.rel_residual_f64 <= 1e-8
+    assert res <= 1e-8 * (1 + 1e-3)
+    assert diff <= 1e-5
+
+
+def test_error_paths_on_device():
+    torch = torch_cuda()
+    from paper_1408_6497_amd import GmgError
+    ctx = _ctx(2, 8, 0, max_iters=1)
+    f = torch.from_numpy(mean_free_normal(16 ** 3, 3)).cuda()
+    u = torch.empty_like(f)
+    with pytest.raises(GmgError) as e:
+        ctx.solve(f, u, 1e-12)
+    assert e.value.status == 5          # GMG_E_NOCONV
+    f[5] = float("nan")
+    ctx2 = _ctx(2, 8, 0)
+    with pytest.raises(GmgError) as e:
+        ctx2.solve(f, u, 1e-8)
+    assert e.value.status == 6          # GMG_E_BREAKDOWN
+    with pytest.raises(ValueError):
+        ctx2.apply(-1, f, f[:10])
