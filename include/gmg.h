@@ -59,10 +59,12 @@ typedef enum {
 typedef enum { GMG_FP64 = 0, GMG_FP32 = 1 } gmg_prec;
 
 /* Mesh description.  Uniform periodic meshes: n = elements per direction
- * (a power of two, n >= 2, and q*n >= 4), order in {1, 2, 4}.  levels = number
- * of multigrid levels (level 0 coarsest, levels-1 finest, n halves per level,
- * Section 2.3.1); 0 selects the deepest hierarchy whose coarsest level has at
- * most 512 DoFs and at least 2 elements per direction. */
+ * (a power of two, 2 <= n <= 512, and q*n >= 4), order in {1, 2, 4}.
+ * levels = number of multigrid levels (level 0 coarsest, levels-1 finest, n
+ * halves per level, Section 2.3.1); 0 selects the deepest hierarchy whose
+ * coarsest level has at most 512 DoFs and at least 2 elements per direction.
+ * The coarsest level is solved with a dense FP64 pseudo-inverse, so an explicit
+ * `levels` must leave at most 512 DoFs there (else GMG_E_ARG). */
 typedef struct {
   int32_t order;
   int32_t n;

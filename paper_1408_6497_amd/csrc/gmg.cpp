@@ -422,7 +422,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   const int q = mesh->order;
   const int n = mesh->n;
   if (!(q == 1 || q == 2 || q == 4)) return GMG_E_ARG;
-  if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n / 1 > (512 * 1) || (q * n) / q > 512) return GMG_E_ARG;
+  if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n > 512) return GMG_E_ARG;
   int L = mesh->levels;
   if (L <= 0) {
     L = 1;
@@ -438,7 +438,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   const int nc0 = n >> (L - 1);
   if (q * nc0 < 4 || nc0 < 2) return GMG_E_ARG;
   const int64_t n0 = static_cast<int64_t>(q * nc0) * (q * nc0) * (q * nc0);
-  if (n0 > 4096) return GMG_E_ARG;
+  if (n0 > 512) return GMG_E_ARG;  // dense FP64 coarsest solve: at most 512 DoFs
 
   gmg_ctx* c = new (std::nothrow) gmg_ctx();
   if (!c) return GMG_E_OOM;

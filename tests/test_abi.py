@@ -49,8 +49,9 @@ def test_invalid_arguments_rejected_before_device_work():
         st = lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h))
         assert st == 1, (order, n, st)
     assert lib.gmg_setup(None, None, None, ctypes.byref(h)) == 1
-    # too many levels for the mesh
-    mesh = gmg.GmgMesh(order=2, n=8, levels=5, reserved=0)
-    assert lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h)) == 1
+    # too many levels for the mesh; too few (coarsest level above 512 DoFs)
+    for levels in (5, 1):
+        mesh = gmg.GmgMesh(order=2, n=8, levels=levels, reserved=0)
+        assert lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h)) == 1
     assert lib.gmg_status_string(5) == b"not converged"
     assert lib.gmg_destroy(None) == 0

@@ -34,13 +34,13 @@ def test_apply_parity(q, n, prec):
     torch = torch_cuda()
     from oracle import operator as op
     print(f"[apply] q={q} n={n} prec={prec}", flush=True)
-    ctx = _ctx(q, n, 1)
+    ctx = _ctx(q, n, 0)
     A = op.assemble(q, n)
     x = mean_free_normal(A.shape[0], seed=100 + q * 10 + n)
     dt = torch.float64 if prec == "fp64" else torch.float32
     xd = to_dev(x, dt)
     yd = torch.empty_like(xd)
-    ctx.apply(0, xd, yd)
+    ctx.apply(ctx.levels - 1, xd, yd)
     torch.cuda.synchronize()
     y_gpu = to_host(yd)
     y_orc = A @ to_host(xd)   # the oracle sees the same (rounded) input
@@ -55,15 +55,16 @@ def test_apply_parity(q, n, prec):
 def test_mass_diagonal_coords(q, n):
     torch = torch_cuda()
     from oracle import operator as op
-    ctx = _ctx(q, n, 1)
-    assert np.max(np.abs(ctx.dof_coords_1d(0) - op.dof_coords_1d(q, n))) < 1e-15
+    ctx = _ctx(q, n, 0)
+    top = ctx.levels - 1
+    assert np.max(np.abs(ctx.dof_coords_1d(top) - op.dof_coords_1d(q, n))) < 1e-15
     M = op.assemble(q, n, "mass")
     x = mean_free_normal(M.shape[0], seed=7)
     xd = to_dev(x, torch.float64)
     yd = torch.empty_like(xd)
-    ctx.mass(0, xd, yd)
+    ctx.mass(top, xd, yd)
     d = torch.empty_like(xd)
-    ctx.diagonal(0, d)
+    ctx.diagonal(top, d)
     torch.cuda.synchronize()
     assert rel_l2(to_host(yd), M @ x) <= FP64_TOL
     assert rel_l2(to_host(d), op.assemble(q, n).diagonal()) <= 1e-14
