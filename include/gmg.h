@@ -19,7 +19,9 @@
  *    lexicographic with x fastest: index i + N (j + N k).  Lattice node i sits at
  *    x = (e + xi_a) / n_level, e = i div q, a = i mod q, xi the LGL nodes on [0,1].
  *  - A vector's element type is double for GMG_FP64 and float for GMG_FP32.
- *  - Calls are ordered on the HIP stream given to gmg_setup.  gmg_apply,
+ *  - Calls are ordered on the HIP stream given to gmg_setup: the library runs
+ *    its kernels on a stream of its own after the work already queued there,
+ *    and the caller's stream waits for them.  gmg_apply,
  *    gmg_smooth, gmg_restrict, gmg_prolong, gmg_coarse_solve, gmg_vcycle and
  *    gmg_rhs enqueue work and return without synchronizing.  gmg_solve,
  *    gmg_dot and the query calls synchronize the stream.
@@ -59,7 +61,7 @@ typedef enum {
 typedef enum { GMG_FP64 = 0, GMG_FP32 = 1 } gmg_prec;
 
 /* Mesh description.  Uniform periodic meshes: n = elements per direction
- * (a power of two, 2 <= n <= 512, and q*n >= 4), order in {1, 2, 4}.
+ * (a power of two, 2 <= n <= 512 (256 for q = 4), and q*n >= 4), order in {1, 2, 4}.
  * levels = number of multigrid levels (level 0 coarsest, levels-1 finest, n
  * halves per level, Section 2.3.1); 0 selects the deepest hierarchy whose
  * coarsest level has at most 512 DoFs and at least 2 elements per direction.
@@ -81,12 +83,21 @@ typedef struct {
   int32_t smoother;         /* 0 Chebyshev-Jacobi, 1 damped Jacobi (omega below)           */
   double jacobi_omega;      /* damping of the Jacobi smoother (2/3)                        */
   uint64_t seed;            /* key of the SplitMix64 Lanczos start vectors (0)             */
-  int32_t vcycle_prec;      /* GMG_FP64: PCG on FP64 V-cycles; GMG_FP32: FP64 iterative
-                               refinement around flexible CG on FP32 V-cycles              */
+  int32_t vcycle_prec;      /* GMG_FP64: CG on FP64 V-cycles.  GMG_FP32: FP32 V-cycles
+                               with FP64 refinement, as chosen by ir_mode               */
   int32_t krylov;           /* 0 PCG, 1 FCG(1) (forced to 1 with FP32 V-cycles)            */
-  double inner_rtol;        /* inner relative tolerance of the FP32 solve (1e-4)           */
+  double inner_rtol;        /* floor of the inner FP32 relative tolerance (2e-6)           */
   int32_t max_iters;        /* cap on Krylov iterations, inner+outer (500)                 */
   double lambda_override;   /* > 0: use this lambda_hat on every level instead of Lanczos  */
+  int32_t timing;           /* != 0: bracket every operator-apply launch with HIP events
+                               (read back with gmg_timing_get); disables graph replay      */
+  int32_t no_graphs;        /* != 0: launch the V-cycles of gmg_solve eagerly instead of
+                               replaying the HIP graph captured on first use               */
+  int32_t ir_mode;          /* FP32 V-cycles only.  0: FP64 flexible CG whose preconditioner
+                               is one FP32 V-cycle (FP64 residual, update, dots and
+                               projection at every iteration).  1: nested refinement,
+                               FP64 residual / update around FP32 flexible CG solves    */
+  int32_t reserved_opt;
 } gmg_options;
 
 typedef struct {
@@ -150,6 +161,23 @@ gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, doubl
 
 /* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
+
+/* Per-kernel timing, a tracing aid (Section 3 reports Setup/Eval/Comm phase
+ * times; this goes down to single launches).  With gmg_options.timing != 0,
+ * every launch of the operator-apply kernel is bracketed by HIP events on the
+ * context stream.  gmg_timing_get synchronizes the stream and returns, for one
+ * level, kind and precision, the number of launches and their summed duration
+ * in seconds since setup or the last gmg_timing_reset.  Kinds:
+ *   0 y = A x            (algorithmic traffic 2 values per DoF)
+ *   1 r = b - A x        (3 values per DoF)
+ *   2 smoother step without a previous iterate, x' = x + c D^-1 (b - A x)
+ *                        (3 values per DoF)
+ *   3 smoother step x' = x + c1 (x - x_prev) + c2 D^-1 (b - A x)
+ *                        (4 values per DoF)
+ *   4 y = M x            (2 values per DoF)                                        */
+gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
+                          double* seconds);
+gmg_status gmg_timing_reset(gmg_ctx* ctx);
 
 const char* gmg_status_string(gmg_status s);
 const char* gmg_last_error(const gmg_ctx* ctx);

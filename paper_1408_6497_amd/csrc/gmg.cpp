@@ -10,6 +10,7 @@
 // gmg_kernels.h; the host only sequences launches and reads scalars back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -54,9 +55,15 @@ struct Level {
 struct gmg_ctx {
   int q = 0, L = 0;
   gmg_options opt{};
-  hipStream_t stream = nullptr;
+  hipStream_t user = nullptr;    // the caller's stream (gmg_setup argument)
+  hipStream_t stream = nullptr;  // the library's own work stream, ordered with `user` by events
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // captured finest V-cycles: [0] FP64 on (kr0, kz0), [1] FP32 on (kr1, kz1),
+  // [2] FP64 r -> FP32 V-cycle -> FP64 z on (kr0, kz0)
+  hipGraphExec_t vgraph[3] = {nullptr, nullptr, nullptr};
+  bool graph_failed[3] = {false, false, false};
   std::vector<Level> lv;
-  AxisTab prol{}, rest{};
+  TransferTab xfer{};
   void* tA[2] = {nullptr, nullptr};
   void* tB[2] = {nullptr, nullptr};
   bool have_prec[2] = {false, false};
@@ -64,6 +71,7 @@ struct gmg_ctx {
   int n0 = 0;
   double* scal = nullptr;
   double* part = nullptr;
+  int64_t part_cap = 0;
   // finest-level Krylov vectors per precision: r, z, p, w, c
   void* kr[2] = {nullptr, nullptr};
   void* kz[2] = {nullptr, nullptr};
@@ -74,6 +82,16 @@ struct gmg_ctx {
   std::vector<void*> allocs;
   std::string err;
   double t_setup = 0.0;
+  // launch timing (gmg_options.timing)
+  struct Pending {
+    hipEvent_t a, b;
+    int level, kind, pi;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_all;
+  std::vector<Pending> pending;
+  std::vector<double> tsec;     // [level][kind][prec]
+  std::vector<int64_t> tcount;
 };
 
 namespace {
@@ -133,6 +151,38 @@ gmg_status ensure_prec(gmg_ctx* c, int pi) {
   return GMG_OK;
 }
 
+constexpr int kKinds = 5;
+inline int tslot(int level, int kind, int pi) { return (level * kKinds + kind) * 2 + pi; }
+
+hipEvent_t take_event(gmg_ctx* c) {
+  if (c->ev_pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_all.push_back(e);
+    return e;
+  }
+  hipEvent_t e = c->ev_pool.back();
+  c->ev_pool.pop_back();
+  return e;
+}
+
+// Fold every completed event pair into the per-(level, kind, prec) sums.
+gmg_status drain_timing(gmg_ctx* c) {
+  if (c->pending.empty()) return GMG_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (const auto& p : c->pending) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+    const int s = tslot(p.level, p.kind, p.pi);
+    c->tsec[s] += 1e-3 * ms;
+    c->tcount[s] += 1;
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return GMG_OK;
+}
+
 gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out, const void* b, const void* xp,
                     double c1, double c2, bool mass = false) {
   const Level& L = c->lv[l];
@@ -151,7 +201,23 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.c1 = c1;
   a.c2 = c2;
   a.epi = epi;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (c->opt.timing) {
+    ea = take_event(c);
+    eb = take_event(c);
+    if (!ea || !eb) return fail(c, GMG_E_HIP, "hipEventCreate failed");
+    HIPCHK(c, hipEventRecord(ea, c->stream));
+  }
   HIPCHK(c, launch_apply(mass ? L.tab.mass : L.tab.stiff, pi == 1, a, c->stream));
+  if (c->opt.timing) {
+    HIPCHK(c, hipEventRecord(eb, c->stream));
+    int kind = 0;
+    if (mass) kind = 4;
+    else if (epi == Epi::Residual) kind = 1;
+    else if (epi == Epi::Cheb) kind = (xp != nullptr && c1 != 0.0) ? 3 : 2;
+    c->pending.push_back({ea, eb, l, kind, pi});
+    if (c->pending.size() > 4096) STCHK(drain_timing(c));
+  }
   return GMG_OK;
 }
 
@@ -228,9 +294,8 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
 gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
   const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
   const bool f32 = pi == 1;
-  HIPCHK(c, launch_axis(c->rest, f32, rf, c->tA[pi], Nc, Nf, Nf, 0, Nf, false, c->stream));
-  HIPCHK(c, launch_axis(c->rest, f32, c->tA[pi], c->tB[pi], Nc, Nc, Nf, 1, Nf, false, c->stream));
-  HIPCHK(c, launch_axis(c->rest, f32, c->tB[pi], rc, Nc, Nc, Nc, 2, Nf, false, c->stream));
+  (void)Nf;
+  HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream));
   return GMG_OK;
 }
 
@@ -238,9 +303,8 @@ gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
 gmg_status prolong_level(gmg_ctx* c, int l, int pi, const void* ec, void* uf) {
   const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
   const bool f32 = pi == 1;
-  HIPCHK(c, launch_axis(c->prol, f32, ec, c->tB[pi], Nf, Nc, Nc, 0, Nc, false, c->stream));
-  HIPCHK(c, launch_axis(c->prol, f32, c->tB[pi], c->tA[pi], Nf, Nf, Nc, 1, Nc, false, c->stream));
-  HIPCHK(c, launch_axis(c->prol, f32, c->tA[pi], uf, Nf, Nf, Nf, 2, Nc, true, c->stream));
+  (void)Nf;
+  HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream));
   return GMG_OK;
 }
 
@@ -263,6 +327,58 @@ gmg_status vcycle_level(gmg_ctx* c, int l, int pi, const void* b, void* u) {
   return GMG_OK;
 }
 
+// Every API call that enqueues work runs it on the library stream, after the
+// work already queued on the caller's stream, and makes the caller's stream
+// wait for it before returning.
+template <class F>
+gmg_status scoped(gmg_ctx* c, F&& body) {
+  HIPCHK(c, hipEventRecord(c->ev_in, c->user));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  const gmg_status st = body();
+  HIPCHK(c, hipEventRecord(c->ev_out, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->user, c->ev_out, 0));
+  return st;
+}
+
+// z = V r on the finest level, in precision vpi, for Krylov vectors of
+// precision pi (vpi = FP32 with pi = FP64 casts r down and z back up).  Inside
+// the Krylov loops r and z are always the context's own vectors, so the
+// sequence (a few dozen launches with fixed arguments) is captured once into a
+// HIP graph and replayed.  With launch timing on, or if capture fails, it runs
+// eagerly.
+gmg_status vcycle_seq(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
+  const int l = c->L - 1;
+  if (pi == vpi) return vcycle_level(c, l, pi, r, z);
+  const int64_t n = c->lv[l].size;
+  HIPCHK(c, launch_cast_d2f(n, static_cast<const double*>(r), static_cast<float*>(c->kr[1]), c->stream));
+  STCHK(vcycle_level(c, l, 1, c->kr[1], c->kz[1]));
+  HIPCHK(c, launch_cast_f2d(n, static_cast<const float*>(c->kz[1]), static_cast<double*>(z), c->stream));
+  return GMG_OK;
+}
+
+gmg_status run_vcycle(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
+  const int key = (pi == vpi) ? pi : 2;
+  if (c->opt.timing || c->opt.no_graphs || c->graph_failed[key] || r != c->kr[pi] || z != c->kz[pi])
+    return vcycle_seq(c, pi, vpi, r, z);
+  if (!c->vgraph[key]) {
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const gmg_status st = vcycle_seq(c, pi, vpi, r, z);
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    hipGraphExec_t ex = nullptr;
+    if (st != GMG_OK || e != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      c->graph_failed[key] = true;
+      return vcycle_seq(c, pi, vpi, r, z);
+    }
+    (void)hipGraphDestroy(g);
+    c->vgraph[key] = ex;
+  }
+  HIPCHK(c, hipGraphLaunch(c->vgraph[key], c->stream));
+  return GMG_OK;
+}
+
 // Largest Ritz value of Lanczos on D^-1/2 A D^-1/2 (FP64, on the device).
 gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
   Level& L = c->lv[l];
@@ -278,7 +394,7 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
   double w0w0 = 0.0;
   const int64_t per_class = n / (q * q * q);
   for (int i = 0; i < q * q * q; ++i) w0w0 += L.tab.diag[i] * static_cast<double>(per_class);
-  HIPCHK(c, launch_class_dot(false, q, L.N, L.tab.dsqrt, v, c->part, c->scal + S_TMP, s));
+  HIPCHK(c, launch_class_dot(false, q, L.N, L.tab.dsqrt, v, c->part, c->part_cap, c->scal + S_TMP, s));
   double hs[kNumScal];
   STCHK(read_scalars(c, hs, kNumScal));
   HIPCHK(c, launch_class_axpy(false, q, L.N, L.tab.dsqrt, -hs[S_TMP] / w0w0, v, s));
@@ -322,8 +438,10 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // Preconditioned Krylov solve of A c = r on the finest level in precision pi,
 // c = 0 initially.  r is overwritten with the recursive residual.  Stops when
 // ||r||_2 <= tol_abs.  With b_true, the stop is confirmed on the true residual
-// b_true - A c (and r is reset to it if that is above tolerance).
-gmg_status krylov(gmg_ctx* c, int pi, bool flexible, const void* b_true, void* u, void* r, double tol_abs,
+// b_true - A c (and r is reset to it if that is above tolerance).  The
+// convergence test comes right after the residual update, so no V-cycle is
+// spent on a residual that already meets the tolerance.
+gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true, void* u, void* r, double tol_abs,
                   int maxit, int* iters, double* final_rr) {
   const int l = c->L - 1;
   const int64_t n = c->lv[l].size;
@@ -334,45 +452,59 @@ gmg_status krylov(gmg_ctx* c, int pi, bool flexible, const void* b_true, void* u
   void* w = c->kw[pi];
   double hs[kNumScal];
   int rz = S_RZ0;
+  *iters = 0;
   HIPCHK(c, launch_fill_zero(f32, n, u, s));
   STCHK(project(c, pi, n, r));
   auto restart = [&]() -> gmg_status {
-    STCHK(vcycle_level(c, l, pi, r, z));
+    STCHK(run_vcycle(c, pi, vpi, r, z));
     STCHK(project(c, pi, n, z));
     if (!flexible) HIPCHK(c, launch_dot(f32, n, r, z, c->part, c->scal + rz, s));
     HIPCHK(c, launch_copy(f32, n, z, p, s));
     return GMG_OK;
   };
-  STCHK(restart());
+  HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+  STCHK(read_scalars(c, hs, kNumScal));
+  double rr = hs[S_RR];
+  bool have_dir = false;
   int it = 0;
-  bool first = true;
   while (true) {
-    HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
-    STCHK(read_scalars(c, hs, kNumScal));
-    if (!std::isfinite(hs[S_RR]) || (!first && !finite_pos(hs[S_PW]))) {
+    if (!std::isfinite(rr)) {
       *iters = it;
-      *final_rr = hs[S_RR];
-      return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: non-finite residual or p^T A p <= 0");
+      *final_rr = rr;
+      return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: non-finite residual");
     }
-    first = false;
-    if (std::sqrt(hs[S_RR]) <= tol_abs) {
+    if (std::sqrt(rr) <= tol_abs) {
       if (!b_true) break;
       STCHK(apply_op(c, l, pi, Epi::Residual, u, r, b_true, nullptr, 0, 0));
       STCHK(project(c, pi, n, r));
       HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
       STCHK(read_scalars(c, hs, kNumScal));
-      if (std::sqrt(hs[S_RR]) <= tol_abs) break;
-      if (it >= maxit) break;
-      STCHK(restart());
+      rr = hs[S_RR];
+      if (std::sqrt(rr) <= tol_abs || it >= maxit) break;
+      have_dir = false;
       continue;
     }
     if (it >= maxit) break;
+    if (!have_dir) {
+      STCHK(restart());
+      have_dir = true;
+    }
     STCHK(apply_op(c, l, pi, Epi::Apply, p, w, nullptr, nullptr, 0, 0));
     HIPCHK(c, launch_dot(f32, n, p, w, c->part, c->scal + S_PW, s));
     if (flexible) HIPCHK(c, launch_dot(f32, n, p, r, c->part, c->scal + S_PR, s));
     HIPCHK(c, launch_axpy2(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, s));
     STCHK(project(c, pi, n, r));
-    STCHK(vcycle_level(c, l, pi, r, z));
+    HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+    STCHK(read_scalars(c, hs, kNumScal));
+    rr = hs[S_RR];
+    ++it;
+    if (!finite_pos(hs[S_PW])) {
+      *iters = it;
+      *final_rr = rr;
+      return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: p^T A p <= 0 or not finite");
+    }
+    if (std::sqrt(rr) <= tol_abs) continue;
+    STCHK(run_vcycle(c, pi, vpi, r, z));
     STCHK(project(c, pi, n, z));
     if (flexible) {
       HIPCHK(c, launch_dot(f32, n, z, w, c->part, c->scal + S_ZW, s));
@@ -383,10 +515,9 @@ gmg_status krylov(gmg_ctx* c, int pi, bool flexible, const void* b_true, void* u
       HIPCHK(c, launch_xpby(f32, n, c->scal, rzn, rz, 1.0, z, p, s));
       rz = rzn;
     }
-    ++it;
   }
   *iters = it;
-  *final_rr = hs[S_RR];
+  *final_rr = rr;
   return GMG_OK;
 }
 
@@ -422,7 +553,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   const int q = mesh->order;
   const int n = mesh->n;
   if (!(q == 1 || q == 2 || q == 4)) return GMG_E_ARG;
-  if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n > 512) return GMG_E_ARG;
+  if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n > (q == 4 ? 256 : 512)) return GMG_E_ARG;
   int L = mesh->levels;
   if (L <= 0) {
     L = 1;
@@ -455,12 +586,28 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   if (o.cheb_hi <= 0) o.cheb_hi = 1.1;
   if (o.lanczos_steps <= 0) o.lanczos_steps = 10;
   if (o.jacobi_omega <= 0) o.jacobi_omega = 2.0 / 3.0;
-  if (o.inner_rtol <= 0) o.inner_rtol = 1e-4;
+  if (o.inner_rtol <= 0) o.inner_rtol = 2e-6;
   if (o.max_iters <= 0) o.max_iters = 500;
   if (o.vcycle_prec == GMG_FP32) o.krylov = 1;
   c->opt = o;
-  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->user = static_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    c->stream = nullptr;
+    gmg_destroy(c);
+    return GMG_E_HIP;
+  }
+  if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+    gmg_destroy(c);
+    return GMG_E_HIP;
+  }
+  if (hipEventRecord(c->ev_in, c->user) != hipSuccess || hipStreamWaitEvent(c->stream, c->ev_in, 0) != hipSuccess) {
+    gmg_destroy(c);
+    return GMG_E_HIP;
+  }
   c->lv.resize(L);
+  c->tsec.assign(static_cast<size_t>(L) * kKinds * 2, 0.0);
+  c->tcount.assign(static_cast<size_t>(L) * kKinds * 2, 0);
   for (int l = 0; l < L; ++l) {
     Level& lev = c->lv[l];
     lev.n = n >> (L - 1 - l);
@@ -468,14 +615,15 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
     lev.tab = make_level_tables(q, lev.n);
   }
-  make_transfer_tables(q, &c->prol, &c->rest);
+  make_transfer_table(q, &c->xfer);
   gmg_status st = GMG_OK;
   auto bail = [&](gmg_status s) {
     gmg_destroy(c);
     return s;
   };
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
-  if ((st = dalloc(c, reinterpret_cast<void**>(&c->part), sizeof(double) * kRedBlocks)) != GMG_OK) return bail(st);
+  c->part_cap = std::max<int64_t>(kRedBlocks, static_cast<int64_t>(c->lv.back().N) * c->lv.back().N);
+  if ((st = dalloc(c, reinterpret_cast<void**>(&c->part), sizeof(double) * c->part_cap)) != GMG_OK) return bail(st);
   if (hipMemsetAsync(c->scal, 0, sizeof(double) * kNumScal, c->stream) != hipSuccess) return bail(GMG_E_HIP);
   if ((st = ensure_prec(c, 0)) != GMG_OK) return bail(st);
   // coarsest pseudo-inverse
@@ -512,7 +660,13 @@ gmg_status gmg_destroy(gmg_ctx* ctx) {
   if (!ctx) return GMG_OK;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
+  for (hipGraphExec_t g : ctx->vgraph)
+    if (g) (void)hipGraphExecDestroy(g);
   for (void* p : ctx->allocs) (void)hipFree(p);
+  for (hipEvent_t e : ctx->ev_all) (void)hipEventDestroy(e);
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return GMG_OK;
 }
@@ -546,73 +700,82 @@ gmg_status gmg_lambda(const gmg_ctx* ctx, int32_t level, double* lambda_host) {
 gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev) {
   if (!ctx || !d_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   const Level& L = ctx->lv[level];
-  HIPCHK(ctx, launch_class_scale(false, ctx->q, L.N, L.tab.diag, 1.0, nullptr, d_dev, ctx->stream));
-  return GMG_OK;
+  return scoped(ctx, [&] {
+    HIPCHK(ctx, launch_class_scale(false, ctx->q, L.N, L.tab.diag, 1.0, nullptr, d_dev, ctx->stream));
+    return GMG_OK;
+  });
 }
 
 gmg_status gmg_apply(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {
   if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "apply: x and y must not alias");
-  return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0);
+  return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0); });
 }
 
 gmg_status gmg_mass(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {
   if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "mass: x and y must not alias");
-  return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0, true);
+  return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0, true); });
 }
 
 gmg_status gmg_smooth(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, void* u_dev, int32_t nu) {
   if (!ctx || !b_dev || !u_dev || nu < 0 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   const int pi = pidx(prec);
   STCHK(ensure_prec(ctx, pi));
-  return smooth(ctx, level, pi, b_dev, u_dev, nu, false);
+  return scoped(ctx, [&] { return smooth(ctx, level, pi, b_dev, u_dev, nu, false); });
 }
 
 gmg_status gmg_restrict(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* rf_dev, void* rc_dev) {
   if (!ctx || !rf_dev || !rc_dev || level < 1 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   const int pi = pidx(prec);
   STCHK(ensure_prec(ctx, pi));
-  return restrict_level(ctx, level, pi, rf_dev, rc_dev);
+  return scoped(ctx, [&] { return restrict_level(ctx, level, pi, rf_dev, rc_dev); });
 }
 
 gmg_status gmg_prolong(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* ec_dev, void* uf_dev) {
   if (!ctx || !ec_dev || !uf_dev || level < 1 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   const int pi = pidx(prec);
   STCHK(ensure_prec(ctx, pi));
-  return prolong_level(ctx, level, pi, ec_dev, uf_dev);
+  return scoped(ctx, [&] { return prolong_level(ctx, level, pi, ec_dev, uf_dev); });
 }
 
 gmg_status gmg_coarse_solve(gmg_ctx* ctx, gmg_prec prec, const void* b_dev, void* x_dev) {
   if (!ctx || !b_dev || !x_dev || b_dev == x_dev) return GMG_E_ARG;
-  return coarse_solve(ctx, pidx(prec), b_dev, x_dev);
+  return scoped(ctx, [&] { return coarse_solve(ctx, pidx(prec), b_dev, x_dev); });
 }
 
 gmg_status gmg_vcycle(gmg_ctx* ctx, gmg_prec prec, const void* r_dev, void* z_dev) {
   if (!ctx || !r_dev || !z_dev || r_dev == z_dev) return GMG_E_ARG;
   const int pi = pidx(prec);
   STCHK(ensure_prec(ctx, pi));
-  return vcycle_level(ctx, ctx->L - 1, pi, r_dev, z_dev);
+  return scoped(ctx, [&] { return vcycle_level(ctx, ctx->L - 1, pi, r_dev, z_dev); });
 }
 
 gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev) {
   if (!ctx || !f_dev || !b_dev || static_cast<const void*>(f_dev) == static_cast<void*>(b_dev)) return GMG_E_ARG;
   const int l = ctx->L - 1;
-  STCHK(apply_op(ctx, l, 0, Epi::Apply, f_dev, b_dev, nullptr, nullptr, 0, 0, true));
-  return project(ctx, 0, ctx->lv[l].size, b_dev);
+  return scoped(ctx, [&] {
+    STCHK(apply_op(ctx, l, 0, Epi::Apply, f_dev, b_dev, nullptr, nullptr, 0, 0, true));
+    return project(ctx, 0, ctx->lv[l].size, b_dev);
+  });
 }
 
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host) {
   if (!ctx || !x_dev || !y_dev || !out_host || n < 0) return GMG_E_ARG;
-  HIPCHK(ctx, launch_dot(prec == GMG_FP32, n, x_dev, y_dev, ctx->part, ctx->scal + S_TMP, ctx->stream));
-  double hs[kNumScal];
-  STCHK(read_scalars(ctx, hs, kNumScal));
-  *out_host = hs[S_TMP];
-  return GMG_OK;
+  return scoped(ctx, [&] {
+    HIPCHK(ctx, launch_dot(prec == GMG_FP32, n, x_dev, y_dev, ctx->part, ctx->scal + S_TMP, ctx->stream));
+    double hs[kNumScal];
+    STCHK(read_scalars(ctx, hs, kNumScal));
+    *out_host = hs[S_TMP];
+    return GMG_OK;
+  });
 }
 
-gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info) {
-  if (!ctx || !b_dev || !u_dev || !(rtol > 0.0)) return GMG_E_ARG;
+}  // extern "C"
+
+namespace {
+
+gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info) {
   gmg_ctx* c = ctx;
   const int l = c->L - 1;
   const int64_t n = c->lv[l].size;
@@ -632,23 +795,44 @@ gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, doubl
     st = fail(c, GMG_E_BREAKDOWN, "load vector is not finite");
   } else if (nb == 0.0) {
     HIPCHK(c, launch_fill_zero(false, n, u_dev, s));
+  } else if (c->opt.vcycle_prec == GMG_FP32 && c->opt.ir_mode == 0) {
+    // FP64 FCG(1) preconditioned by one FP32 V-cycle: the residual update, dots
+    // and projection stay in FP64 at every iteration (refinement at each step),
+    // the V-cycle -- smoother, transfers, level operators -- runs in FP32.
+    STCHK(ensure_prec(c, 1));
+    HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));
+    int it = 0;
+    double rr = 0.0;
+    st = krylov(c, 0, 1, true, b_dev, u_dev, c->kr[0], rtol * nb, c->opt.max_iters, &it, &rr);
+    inf.inner_iters = it;
+    inf.outer_iters = it;
+    inf.rel_residual_f64 = std::sqrt(rr) / nb;
+    if (st == GMG_OK && !(inf.rel_residual_f64 <= rtol)) st = fail(c, GMG_E_NOCONV, "max_iters reached");
   } else if (c->opt.vcycle_prec != GMG_FP32) {
     // plain FP64: CG / FCG(1) preconditioned by one FP64 V-cycle
     HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));
     int it = 0;
     double rr = 0.0;
-    st = krylov(c, 0, c->opt.krylov == 1, b_dev, u_dev, c->kr[0], rtol * nb, c->opt.max_iters, &it, &rr);
+    st = krylov(c, 0, 0, c->opt.krylov == 1, b_dev, u_dev, c->kr[0], rtol * nb, c->opt.max_iters, &it, &rr);
     inf.inner_iters = it;
     inf.rel_residual_f64 = std::sqrt(rr) / nb;
     if (st == GMG_OK && !(inf.rel_residual_f64 <= rtol)) st = fail(c, GMG_E_NOCONV, "max_iters reached");
   } else {
-    // FP64 iterative refinement around FP32 FCG(1) with FP32 V-cycles
+    // FP64 iterative refinement around FP32 FCG(1) with FP32 V-cycles.  Each
+    // inner solve reduces its residual by tau = max(inner_rtol, rtol ||b|| / (2 ||r||)):
+    // no further than the outer tolerance needs, and not below what FP32
+    // arithmetic resolves.
     STCHK(ensure_prec(c, 1));
     HIPCHK(c, launch_fill_zero(false, n, u_dev, s));
+    HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));   // r = b - A 0
     int total = 0;
+    bool first = true;
     while (true) {
-      STCHK(apply_op(c, l, 0, Epi::Residual, u_dev, c->kr[0], b_dev, nullptr, 0, 0));
-      STCHK(project(c, 0, n, c->kr[0]));
+      if (!first) {
+        STCHK(apply_op(c, l, 0, Epi::Residual, u_dev, c->kr[0], b_dev, nullptr, 0, 0));
+        STCHK(project(c, 0, n, c->kr[0]));
+      }
+      first = false;
       HIPCHK(c, launch_dot(false, n, c->kr[0], c->kr[0], c->part, c->scal + S_TMP, s));
       STCHK(read_scalars(c, hs, kNumScal));
       const double rn = std::sqrt(hs[S_TMP]);
@@ -665,20 +849,24 @@ gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, doubl
       HIPCHK(c, launch_cast_d2f(n, static_cast<const double*>(c->kr[0]), static_cast<float*>(c->kr[1]), s));
       int it = 0;
       double rr = 0.0;
-      // inner tolerance relative to the current residual, never below what FP32 can resolve
-      const double inner = std::max(c->opt.inner_rtol, 1e-6);
-      st = krylov(c, 1, true, nullptr, c->kc[1], c->kr[1], inner * rn, c->opt.max_iters - total, &it, &rr);
+      const double tau = std::max(c->opt.inner_rtol, 0.5 * rtol * nb / rn);
+      const int cap = std::min(c->opt.max_iters - total, 40);
+      st = krylov(c, 1, 1, true, nullptr, c->kc[1], c->kr[1], tau * rn, cap, &it, &rr);
       total += it;
       if (st != GMG_OK) break;
       HIPCHK(c, launch_add_f2d(n, static_cast<const float*>(c->kc[1]), u_dev, s));
       ++inf.outer_iters;
+      if (it == 0) {
+        st = fail(c, GMG_E_NOCONV, "FP32 inner solve made no progress");
+        break;
+      }
     }
     inf.inner_iters = total;
   }
   if (st == GMG_OK || st == GMG_E_NOCONV) {
     // zero integral: u <- u - (int u_h) / |cube|
     const Level& F = c->lv[l];
-    HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u_dev, c->part, c->scal + S_TMP, s));
+    HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u_dev, c->part, c->part_cap, c->scal + S_TMP, s));
     HIPCHK(c, launch_shift(false, n, c->scal, S_TMP, 1.0, u_dev, s));
   }
   HIPCHK(c, hipEventRecord(e1, s));
@@ -690,6 +878,34 @@ gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, doubl
   (void)hipEventDestroy(e1);
   if (info) *info = inf;
   return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info) {
+  if (!ctx || !b_dev || !u_dev || !(rtol > 0.0)) return GMG_E_ARG;
+  return scoped(ctx, [&] { return solve_rhs_impl(ctx, b_dev, u_dev, rtol, info); });
+}
+
+gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
+                          double* seconds) {
+  if (!ctx || !launches || !seconds || check_level(ctx, level) != GMG_OK || kind < 0 || kind >= kKinds)
+    return GMG_E_ARG;
+  STCHK(drain_timing(ctx));
+  const int s = tslot(level, kind, pidx(prec));
+  *launches = ctx->tcount[s];
+  *seconds = ctx->tsec[s];
+  return GMG_OK;
+}
+
+gmg_status gmg_timing_reset(gmg_ctx* ctx) {
+  if (!ctx) return GMG_E_ARG;
+  STCHK(drain_timing(ctx));
+  std::fill(ctx->tsec.begin(), ctx->tsec.end(), 0.0);
+  std::fill(ctx->tcount.begin(), ctx->tcount.end(), 0);
+  return GMG_OK;
 }
 
 gmg_status gmg_solve(gmg_ctx* ctx, const double* f_dev, double* u_dev, double rtol, gmg_info* info) {

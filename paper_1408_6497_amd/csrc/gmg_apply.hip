@@ -1,29 +1,36 @@
 // Matrix-free, sum-factorized Q_q stiffness apply on uniform periodic meshes
-// (Section 2.3.2: tensorized LGL nodal basis, element MatVec in O(q^4) instead
-// of O(q^6); here the tensor structure is used globally, so each node is
-// touched once per 1D pass).
+// (Section 2.3.2: tensorized LGL nodal basis, so the element MatVec costs
+// O(q^4) instead of O(q^6); here the tensor structure is used globally and
+// every node is touched once per 1D pass).
 //
 // Operator:  A = Kx (x) My (x) Mz + Mx (x) Ky (x) Mz + Mx (x) My (x) Kz
 // split per z plane:  g = (Kx My + Mx Ky) x,  h = Mx My x,  A x = Mz g + Kz h.
 //
-// Work decomposition (gfx950, 64-wide wavefronts):
-//   * a workgroup owns a tile of TY = 4*G full x-rows and a chunk of TZ element
-//     layers in z; thread (tx, ty) owns one element column in x (q nodes,
-//     loaded/stored as one q-wide vector, so a wavefront streams 64*q
-//     consecutive values per row) and RY = 4 rows;
-//   * each input plane is staged once in LDS with a q-row halo in y (rows
-//     wrap periodically), the y pass writes (My x, Ky x) for the TY rows back
-//     to LDS, the x pass reads the neighbouring element columns from LDS
-//     (periodic wrap) and produces (g, h) in registers;
-//   * the z pass is done element layer by element layer with q+1 register
-//     accumulators per point (element form), so only one plane of halo
-//     (the vertex plane below the chunk) is recomputed per element layer;
-//   * the next plane's global loads are issued before the LDS passes of the
-//     current plane (one-plane register prefetch);
+// Two kernels:
+//
+// k_apply_col (levels with N >= 64): streams z planes.
+//   * a workgroup owns TY = 4 G full x-rows and a chunk of TZ element layers;
+//     thread (tx, ty) owns one element column in x (q nodes, moved as one
+//     q-wide vector, so a wavefront reads 64 q consecutive values per row) and
+//     RY = 4 rows of row group ty;
+//   * each thread loads its own column strip of RY + 2q rows (the y halo wraps
+//     periodically) straight into registers and does the y pass there
+//     (P = My x, S = Ky x); only P and S go through LDS, double-buffered, for
+//     the x pass across element columns -- one barrier per plane;
+//   * the x pass reads the neighbouring element columns (periodic wrap) and
+//     produces g, h; the z pass is done element layer by element layer with
+//     q+1 accumulators per point (element form), so only the element layer
+//     below the chunk is recomputed;
+//   * the next plane's loads are issued before the current plane is computed;
 //   * node classes (i mod q) are compile-time in y and z and per thread in x,
-//     so banded taps that are structurally zero are never issued;
-//   * blocks are remapped so that each XCD (blockIdx mod 8) sweeps a
-//     contiguous range of tiles and shares halos in its own L2.
+//     so structurally zero taps are never issued;
+//   * blocks are remapped so each XCD (blockIdx mod 8) sweeps a contiguous
+//     range of tiles and shares the y halos in its own L2.
+//
+// k_apply_pt (levels with N <= 32, latency-bound): one thread per element
+//   column of one row sums its (2q+1)^3 neighbourhood by sum factorization in
+//   registers; the whole level sits in cache and no thread waits on another.
+//
 // Epilogues fuse the residual (b - A x) and the Chebyshev-Jacobi step
 // x + c1 (x - x_prev) + c2 D^-1 (b - A x) into the same pass.
 #include "gmg_kernels.h"
@@ -42,6 +49,8 @@ struct KTab {
   T mr[Q][2 * Q + 1];
   T zk[Q + 1][Q + 1];
   T zm[Q + 1][Q + 1];
+  T zkr[Q][2 * Q + 1];
+  T zmr[Q][2 * Q + 1];
   T dinv[Q * Q * Q];
 };
 
@@ -50,14 +59,59 @@ __host__ __device__ constexpr bool tap(int Q, int c, int o) {
   return c == 0 ? true : (o >= -c && o <= Q - c);
 }
 
+// Fused epilogue on one q-wide output vector.
+template <typename T, int Q, int EPI>
+__device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, const int cy, const int cz,
+                                     const T (&ax)[Q], const T* __restrict__ x, T* out, const T* bvec,
+                                     const T* xp, const T c1, const T c2) {
+  using V = VecQ<T, Q>;
+  V res;
+  if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+#pragma unroll
+    for (int c = 0; c < Q; ++c) res.v[c] = ax[c];
+  } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
+    const V bv = *reinterpret_cast<const V*>(bvec + idx);
+#pragma unroll
+    for (int c = 0; c < Q; ++c) res.v[c] = bv.v[c] - ax[c];
+  } else {
+    const V bv = *reinterpret_cast<const V*>(bvec + idx);
+    const V xv = *reinterpret_cast<const V*>(x + idx);
+    V pv;
+    if (c1 != T(0)) {
+      if (xp != nullptr) {
+        pv = *reinterpret_cast<const V*>(xp + idx);
+      } else {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) pv.v[c] = T(0);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < Q; ++c) pv.v[c] = xv.v[c];
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      const T dinv = tb.dinv[c + Q * (cy + Q * cz)];
+      res.v[c] = xv.v[c] + c1 * (xv.v[c] - pv.v[c]) + c2 * dinv * (bv.v[c] - ax[c]);
+    }
+  }
+  *reinterpret_cast<V*>(out + idx) = res;
+}
+
+template <int Q>
+constexpr int col_bound() {
+  return Q == 4 ? 256 : 512;
+}
+
+// --------------------------------------------------------------------------
+// Streaming column kernel.
 template <typename T, int Q, int G, int EPI>
-__global__ void __launch_bounds__(512) k_apply(const T* __restrict__ x, const KTab<T, Q> tb, const int N,
-                                                 const int TZ, const int ntiles_y, T* out, const T* bvec,
-                                                 const T* xp, const T c1, const T c2) {
+__global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
+                                                              const int N, const int TZ, const int ntiles_y,
+                                                              T* out, const T* bvec, const T* xp, const T c1,
+                                                              const T c2) {
   constexpr int RY = 4;
   constexpr int TY = G * RY;
-  constexpr int NR = TY + 2 * Q;
-  constexpr int NL = (NR + G - 1) / G;
+  constexpr int NR = RY + 2 * Q;
   using V = VecQ<T, Q>;
 
   const int tx = threadIdx.x;
@@ -65,9 +119,8 @@ __global__ void __launch_bounds__(512) k_apply(const T* __restrict__ x, const KT
   const int NX = N / Q;
   const int Nm = N - 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);  // NR x N
-  T* ps = xs + NR * N;                     // TY x N
-  T* ss = ps + TY * N;                     // TY x N
+  T* lds = reinterpret_cast<T*>(smem_raw);  // [2 buffers][P,S][TY][N]
+  const int buf_stride = 2 * TY * N;
 
   const int nblocks = gridDim.x;
   int tile = blockIdx.x;
@@ -75,86 +128,78 @@ __global__ void __launch_bounds__(512) k_apply(const T* __restrict__ x, const KT
   const int Y0 = (tile % ntiles_y) * TY;
   const int E0 = (tile / ntiles_y) * TZ;
   const size_t NN = static_cast<size_t>(N) * N;
+  const int yrow0 = Y0 + ty * RY;  // first output row of this thread
 
-  V pre[NL];
+  // offsets (in elements) of the strip rows inside a plane, y wrapping periodically
+  int roff[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) roff[r] = ((yrow0 - Q + r) & Nm) * N + Q * tx;
+
+  V pre[NR];
   auto load_plane = [&](int p) {
     const T* base = x + static_cast<size_t>(p & Nm) * NN;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int r = ty + i * G;
-      if (r < NR) {
-        const int yy = (Y0 - Q + r) & Nm;
-        pre[i] = *reinterpret_cast<const V*>(base + static_cast<size_t>(yy) * N + Q * tx);
-      }
-    }
-  };
-  auto store_plane = [&]() {
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      const int r = ty + i * G;
-      if (r < NR) *reinterpret_cast<V*>(xs + r * N + Q * tx) = pre[i];
-    }
+    for (int r = 0; r < NR; ++r) pre[r] = *reinterpret_cast<const V*>(base + roff[r]);
   };
 
-  T g[RY][Q], h[RY][Q];
   const int txl = (tx - 1) & (NX - 1);
   const int txr = (tx + 1) & (NX - 1);
+  T g[RY][Q], h[RY][Q];
+  int parity = 0;
 
   auto compute_gh = [&](int p, bool prefetch) {
-    store_plane();
+    V xv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) xv[r] = pre[r];
     if (prefetch) load_plane(p + 1);
-    __syncthreads();
-    // ---- y pass: P = My x, S = Ky x on this thread's RY rows and q columns
-    {
-      V xv[RY + 2 * Q];
+    T* ps = lds + parity * buf_stride;
+    T* ss = ps + TY * N;
+    // y pass in registers
 #pragma unroll
-      for (int r = 0; r < RY + 2 * Q; ++r) xv[r] = *reinterpret_cast<const V*>(xs + (ty * RY + r) * N + Q * tx);
+    for (int i = 0; i < RY; ++i) {
+      const int ci = i % Q;
+      V pv, sv;
 #pragma unroll
-      for (int i = 0; i < RY; ++i) {
-        const int ci = i % Q;
-        V pv, sv;
+      for (int c = 0; c < Q; ++c) {
+        pv.v[c] = T(0);
+        sv.v[c] = T(0);
+      }
+#pragma unroll
+      for (int o = -Q; o <= Q; ++o) {
+        if (!tap(Q, ci, o)) continue;
+        const T m = tb.mr[ci][o + Q];
+        const T k = tb.kr[ci][o + Q];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
-          pv.v[c] = T(0);
-          sv.v[c] = T(0);
+          pv.v[c] = fma(m, xv[i + Q + o].v[c], pv.v[c]);
+          sv.v[c] = fma(k, xv[i + Q + o].v[c], sv.v[c]);
         }
-#pragma unroll
-        for (int o = -Q; o <= Q; ++o) {
-          if (!tap(Q, ci, o)) continue;
-          const T m = tb.mr[ci][o + Q];
-          const T k = tb.kr[ci][o + Q];
-#pragma unroll
-          for (int c = 0; c < Q; ++c) {
-            pv.v[c] = fma(m, xv[i + Q + o].v[c], pv.v[c]);
-            sv.v[c] = fma(k, xv[i + Q + o].v[c], sv.v[c]);
-          }
-        }
-        *reinterpret_cast<V*>(ps + (ty * RY + i) * N + Q * tx) = pv;
-        *reinterpret_cast<V*>(ss + (ty * RY + i) * N + Q * tx) = sv;
       }
+      *reinterpret_cast<V*>(ps + (ty * RY + i) * N + Q * tx) = pv;
+      *reinterpret_cast<V*>(ss + (ty * RY + i) * N + Q * tx) = sv;
     }
     __syncthreads();
-    // ---- x pass: g = Kx P + Mx S, h = Mx P
+    // x pass across element columns
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       const int row = (ty * RY + i) * N;
-      T pw[3 * Q], sw[3 * Q];
+      T pw[2 * Q + 1], sw[2 * Q + 1];
       {
         const V a = *reinterpret_cast<const V*>(ps + row + Q * txl);
         const V b = *reinterpret_cast<const V*>(ps + row + Q * tx);
-        const V c = *reinterpret_cast<const V*>(ps + row + Q * txr);
+        const T c = ps[row + Q * txr];
         const V d = *reinterpret_cast<const V*>(ss + row + Q * txl);
         const V e = *reinterpret_cast<const V*>(ss + row + Q * tx);
-        const V f = *reinterpret_cast<const V*>(ss + row + Q * txr);
+        const T f = ss[row + Q * txr];
 #pragma unroll
-        for (int c2i = 0; c2i < Q; ++c2i) {
-          pw[c2i] = a.v[c2i];
-          pw[Q + c2i] = b.v[c2i];
-          pw[2 * Q + c2i] = c.v[c2i];
-          sw[c2i] = d.v[c2i];
-          sw[Q + c2i] = e.v[c2i];
-          sw[2 * Q + c2i] = f.v[c2i];
+        for (int k = 0; k < Q; ++k) {
+          pw[k] = a.v[k];
+          pw[Q + k] = b.v[k];
+          sw[k] = d.v[k];
+          sw[Q + k] = e.v[k];
         }
+        pw[2 * Q] = c;
+        sw[2 * Q] = f;
       }
 #pragma unroll
       for (int c = 0; c < Q; ++c) {
@@ -172,10 +217,11 @@ __global__ void __launch_bounds__(512) k_apply(const T* __restrict__ x, const KT
         h[i][c] = hh;
       }
     }
+    parity ^= 1;
   };
 
   T acc[RY][Q][Q + 1];
-  const int zlast = (E0 + TZ) * Q;  // last plane of the chunk (vertex plane above it)
+  const int zlast = (E0 + TZ) * Q;
 
   load_plane((E0 - 1) * Q);
   compute_gh((E0 - 1) * Q, true);
@@ -205,39 +251,11 @@ __global__ void __launch_bounds__(512) k_apply(const T* __restrict__ x, const KT
         const size_t zoff = static_cast<size_t>(E * Q + a) * NN;
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-          const size_t idx = zoff + static_cast<size_t>(Y0 + ty * RY + i) * N + Q * tx;
-          V res;
-          if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+          T ax[Q];
 #pragma unroll
-            for (int c = 0; c < Q; ++c) res.v[c] = acc[i][c][a];
-          } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
-            const V bv = *reinterpret_cast<const V*>(bvec + idx);
-#pragma unroll
-            for (int c = 0; c < Q; ++c) res.v[c] = bv.v[c] - acc[i][c][a];
-          } else {
-            const V bv = *reinterpret_cast<const V*>(bvec + idx);
-            const V xv = *reinterpret_cast<const V*>(x + idx);
-            V pv;
-            if (c1 != T(0)) {
-              if (xp != nullptr) {
-                pv = *reinterpret_cast<const V*>(xp + idx);
-              } else {
-#pragma unroll
-                for (int c = 0; c < Q; ++c) pv.v[c] = T(0);
-              }
-            } else {
-#pragma unroll
-              for (int c = 0; c < Q; ++c) pv.v[c] = xv.v[c];
-            }
-            const int ci = i % Q;
-#pragma unroll
-            for (int c = 0; c < Q; ++c) {
-              const T dinv = tb.dinv[c + Q * (ci + Q * a)];
-              const T rr = bv.v[c] - acc[i][c][a];
-              res.v[c] = xv.v[c] + c1 * (xv.v[c] - pv.v[c]) + c2 * dinv * rr;
-            }
-          }
-          *reinterpret_cast<V*>(out + idx) = res;
+          for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
+          const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
+          emit<T, Q, EPI>(tb, idx, i % Q, a, ax, x, out, bvec, xp, c1, c2);
         }
       }
     }
@@ -254,21 +272,58 @@ __global__ void __launch_bounds__(512) k_apply(const T* __restrict__ x, const KT
   }
 }
 
-inline size_t apply_lds(int G, int Q, int N, size_t elem) {
-  return static_cast<size_t>(12 * G + 2 * Q) * N * elem;
-}
-
-inline size_t max_lds_per_block() {
-  static size_t cached = 0;
-  if (cached == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-      cached = static_cast<size_t>(v);
-    else
-      cached = 65536;
+// --------------------------------------------------------------------------
+// Point kernel for small levels: thread = one element column (q nodes) of one row.
+template <typename T, int Q, int EPI>
+__global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const KTab<T, Q> tb, const int N,
+                                                   T* out, const T* bvec, const T* xp, const T c1, const T c2) {
+  const int NX = N / Q;
+  const int64_t total = static_cast<int64_t>(NX) * N * N;
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t >= total) return;
+  const int Nm = N - 1;
+  const int tx = static_cast<int>(t % NX);
+  const int yy = static_cast<int>((t / NX) % N);
+  const int zz = static_cast<int>(t / (static_cast<int64_t>(NX) * N));
+  const int cy = yy % Q;
+  const int cz = zz % Q;
+  // sum over the (dz, dy) rows of the neighbourhood of
+  //   (Kx row . x) My Zm + (Mx row . x) (Ky Zm + My Zk)
+  // with (Zm, Zk) = (Mz, Kz) for the stiffness and (0, Mz) for the mass
+  T ax[Q];
+#pragma unroll
+  for (int c = 0; c < Q; ++c) ax[c] = T(0);
+  // fully unrolled so that all (2q+1)^2 row loads can be in flight at once;
+  // taps outside a row's band carry zero weights
+#pragma unroll
+  for (int dz = -Q; dz <= Q; ++dz) {
+    const T mz = tb.zmr[cz][dz + Q], kz = tb.zkr[cz][dz + Q];
+    const int zr = (zz + dz) & Nm;
+#pragma unroll
+    for (int dy = -Q; dy <= Q; ++dy) {
+      const T my = tb.mr[cy][dy + Q], ky = tb.kr[cy][dy + Q];
+      const int yr = (yy + dy) & Nm;
+      const T* row = x + (static_cast<size_t>(zr) * N + yr) * N;
+      const T wk = my * mz;            // weight of the Kx row product
+      const T wm = ky * mz + my * kz;  // weight of the Mx row product
+      T xr[2 * Q + 1];
+#pragma unroll
+      for (int k = 0; k <= 2 * Q; ++k) xr[k] = row[(Q * tx - Q + k + N) & Nm];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        T rk = T(0), rm = T(0);
+#pragma unroll
+        for (int o = -Q; o <= Q; ++o) {
+          if (!tap(Q, c, o)) continue;
+          rk = fma(tb.kr[c][o + Q], xr[Q + c + o], rk);
+          rm = fma(tb.mr[c][o + Q], xr[Q + c + o], rm);
+        }
+        ax[c] = fma(wk, rk, fma(wm, rm, ax[c]));
+      }
+    }
   }
-  return cached;
+  const size_t idx = (static_cast<size_t>(zz) * N + yy) * N + Q * tx;
+  emit<T, Q, EPI>(tb, idx, cy, cz, ax, x, out, bvec, xp, c1, c2);
 }
 
 template <typename T, int Q>
@@ -278,6 +333,8 @@ KTab<T, Q> make_ktab(const OpTab& t) {
     for (int o = 0; o < 2 * Q + 1; ++o) {
       k.kr[c][o] = static_cast<T>(t.krow[c][o]);
       k.mr[c][o] = static_cast<T>(t.mrow[c][o]);
+      k.zkr[c][o] = static_cast<T>(t.zkrow[c][o]);
+      k.zmr[c][o] = static_cast<T>(t.zmrow[c][o]);
     }
   for (int a = 0; a <= Q; ++a)
     for (int b = 0; b <= Q; ++b) {
@@ -288,71 +345,85 @@ KTab<T, Q> make_ktab(const OpTab& t) {
   return k;
 }
 
-template <typename T, int Q, int G, int EPI>
-hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
-  constexpr int TY = 4 * G;
-  const int N = a.N;
-  const int n = a.n;
-  const int ntiles_y = N / TY;
-  // element layers per block: enough blocks to fill 256 CUs several times while
-  // keeping the recomputed layer below the chunk small
+// Launch shape of the column kernel on one level.
+struct ColShape {
+  int G, TZ, ntiles_y, nblocks;
+  size_t lds;
+};
+
+inline ColShape col_shape(int N, int n, int Q, size_t elem) {
+  ColShape s{};
+  const int nx = N / Q;
+  int G = 1;
+  while (G < 4 && G * nx < 64 && 8 * G <= N) G *= 2;  // at least one full wavefront per block
+  s.G = G;
+  s.ntiles_y = N / (4 * G);
+  // enough blocks for several per CU, as few recomputed element layers as possible
   int TZ = n;
-  while (TZ > 2 && static_cast<int64_t>(ntiles_y) * (n / TZ) < 2048) TZ >>= 1;
-  const int nchunks = n / TZ;
-  const dim3 block(N / Q, G);
-  const dim3 grid(ntiles_y * nchunks);
-  const size_t lds = apply_lds(G, Q, N, sizeof(T));
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply<T, Q, G, EPI>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  while (TZ > 1 && static_cast<int64_t>(s.ntiles_y) * (n / TZ) < 1024) TZ >>= 1;
+  s.TZ = TZ;
+  s.nblocks = s.ntiles_y * (n / TZ);
+  s.lds = static_cast<size_t>(2 * 2 * 4 * G) * N * elem;
+  return s;
+}
+
+template <typename T, int Q, int G, int EPI>
+hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, const ColShape& sh, hipStream_t s) {
+  if (sh.lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
     if (e != hipSuccess) return e;
   }
-  const KTab<T, Q> kt = make_ktab<T, Q>(tab);
-  hipLaunchKernelGGL((k_apply<T, Q, G, EPI>), grid, block, lds, s, static_cast<const T*>(a.x), kt, N, TZ,
-                     ntiles_y, static_cast<T*>(a.out), static_cast<const T*>(a.b), static_cast<const T*>(a.xp),
-                     static_cast<T>(a.c1), static_cast<T>(a.c2));
+  hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
+                     static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
+                     static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
+                     static_cast<T>(a.c2));
   return hipGetLastError();
 }
 
-template <typename T, int Q, int G>
-hipError_t launch_tqg(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
+template <typename T, int Q, int EPI>
+hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
+  const KTab<T, Q> kt = make_ktab<T, Q>(tab);
+  if (a.N <= 32) {
+    const int64_t total = static_cast<int64_t>(a.N / Q) * a.N * a.N;
+    const int blk = 128;
+    hipLaunchKernelGGL((k_apply_pt<T, Q, EPI>), dim3(static_cast<unsigned>((total + blk - 1) / blk)), dim3(blk), 0,
+                       s, static_cast<const T*>(a.x), kt, a.N, static_cast<T*>(a.out), static_cast<const T*>(a.b),
+                       static_cast<const T*>(a.xp), static_cast<T>(a.c1), static_cast<T>(a.c2));
+    return hipGetLastError();
+  }
+  const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T));
+  if ((a.N / Q) * sh.G > col_bound<Q>()) return hipErrorInvalidConfiguration;
+  switch (sh.G) {
+    case 1: return launch_col<T, Q, 1, EPI>(kt, a, sh, s);
+    case 2: return launch_col<T, Q, 2, EPI>(kt, a, sh, s);
+    case 4: return launch_col<T, Q, 4, EPI>(kt, a, sh, s);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
+template <typename T, int Q>
+hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
   switch (a.epi) {
-    case Epi::Apply: return launch_tq<T, Q, G, 0>(tab, a, s);
-    case Epi::Residual: return launch_tq<T, Q, G, 1>(tab, a, s);
-    case Epi::Cheb: return launch_tq<T, Q, G, 2>(tab, a, s);
+    case Epi::Apply: return launch_te<T, Q, 0>(tab, a, s);
+    case Epi::Residual: return launch_te<T, Q, 1>(tab, a, s);
+    case Epi::Cheb: return launch_te<T, Q, 2>(tab, a, s);
   }
   return hipErrorInvalidValue;
 }
 
-// Row groups per block: as many as fit 512 threads and the LDS budget, with
-// TY = 4 G rows dividing N.  Returns 0 when even G = 1 does not fit.
-inline int pick_g(int N, int Q, size_t elem) {
-  const int nx = N / Q;
-  const size_t lim = max_lds_per_block();
-  for (int G = 4; G >= 1; G >>= 1)
-    if (G * nx <= 512 && 4 * G <= N && apply_lds(G, Q, N, elem) <= lim) return G;
-  return 0;
-}
-
-template <typename T, int Q>
-hipError_t launch_tqx(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
-  switch (pick_g(a.N, Q, sizeof(T))) {
-    case 4: return launch_tqg<T, Q, 4>(tab, a, s);
-    case 2: return launch_tqg<T, Q, 2>(tab, a, s);
-    case 1: return launch_tqg<T, Q, 1>(tab, a, s);
-    default: return hipErrorInvalidConfiguration;
-  }
-}
-
 }  // namespace
 
+int apply_max_elements_x(int q) { return q == 4 ? 256 : 512; }
+
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s) {
-  // shape checks: the grid above assumes these
-  if (a.N != tab.q * a.n || a.N < 4 || (a.N & (a.N - 1)) != 0 || a.N / tab.q > 512) return hipErrorInvalidValue;
+  // shape checks: the launch shapes above assume these
+  if (a.N != tab.q * a.n || a.N < 4 || (a.N & (a.N - 1)) != 0 || a.n > apply_max_elements_x(tab.q))
+    return hipErrorInvalidValue;
   switch (tab.q) {
-    case 1: return fp32 ? launch_tqx<float, 1>(tab, a, s) : launch_tqx<double, 1>(tab, a, s);
-    case 2: return fp32 ? launch_tqx<float, 2>(tab, a, s) : launch_tqx<double, 2>(tab, a, s);
-    case 4: return fp32 ? launch_tqx<float, 4>(tab, a, s) : launch_tqx<double, 4>(tab, a, s);
+    case 1: return fp32 ? launch_tq<float, 1>(tab, a, s) : launch_tq<double, 1>(tab, a, s);
+    case 2: return fp32 ? launch_tq<float, 2>(tab, a, s) : launch_tq<double, 2>(tab, a, s);
+    case 4: return fp32 ? launch_tq<float, 4>(tab, a, s) : launch_tq<double, 4>(tab, a, s);
     default: return hipErrorInvalidValue;
   }
 }

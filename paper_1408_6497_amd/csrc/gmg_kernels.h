@@ -19,26 +19,29 @@ constexpr int kMaxTaps = 4 * kMaxQ + 1;
 // with the x and y passes done by rows of the assembled periodic 1D matrices
 // (krow, mrow: node class c = i mod q, offsets -q..q) and the z pass done
 // element by element (zk, zm: (q+1) x (q+1) element matrices).
-// The same kernel applies the mass M (x) M (x) M with krow = 0 and zk = mass.
+// The same kernels apply the mass M (x) M (x) M with krow = 0, zk = zkrow = mass
+// and zm = zmrow = 0.
 struct OpTab {
   int q;
   double krow[kMaxQ][2 * kMaxQ + 1];
   double mrow[kMaxQ][2 * kMaxQ + 1];
   double zk[kMaxQ + 1][kMaxQ + 1];
   double zm[kMaxQ + 1][kMaxQ + 1];
+  // the same two z operators as assembled periodic rows (used by the point kernel)
+  double zkrow[kMaxQ][2 * kMaxQ + 1];
+  double zmrow[kMaxQ][2 * kMaxQ + 1];
   double dinv[kMaxQ * kMaxQ * kMaxQ];  // 1 / A_ii by node class (cx + q (cy + q cz))
 };
 
-// One-axis transfer table (separable P = P1 (x) P1 (x) P1 on uniform meshes).
-// Output index o along the axis has class c = o mod period and base
-// b = (o div period) * base_mul; it reads input (b + off[c][t]) mod in_len with
-// weight w[c][t] for t < ntap[c].
-struct AxisTab {
-  int period;
-  int base_mul;
-  int ntap[2 * kMaxQ];
-  int off[2 * kMaxQ][kMaxTaps];
-  double w[2 * kMaxQ][kMaxTaps];
+// One-axis transfer weights (P = P1 (x) P1 (x) P1 on uniform meshes).
+//   p[b][a]: fine node 2qE + b (b < 2q) from coarse node qE + a (a <= q) of
+//            coarse element E: phi_a at the child node;
+//   r[a][t]: coarse node qE + a (a < q) from fine node 2qE - 2q + t (t <= 4q);
+//            the row of P^T.
+struct TransferTab {
+  int q;
+  double p[2 * kMaxQ][kMaxQ + 1];
+  double r[kMaxQ][4 * kMaxQ + 1];
 };
 
 enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2 };
@@ -60,10 +63,12 @@ struct ApplyArgs {
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 
-// out[idx] (+)= sum_t w in[...] along one axis; dims are the OUTPUT extents
-// (d0 = x, d1 = y, d2 = z); in_len is the input extent along `axis`.
-hipError_t launch_axis(const AxisTab& tab, bool fp32, const void* in, void* out, int d0, int d1, int d2,
-                       int axis, int in_len, bool accumulate, hipStream_t s);
+// uf += P ec (coarse Nc^3 -> fine (2Nc)^3) and rc = P^T rf, as three one-axis
+// passes through the temporaries t1 (>= Nf^3/2 values) and t2 (>= Nf^3/4).
+hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
+                          hipStream_t s);
+hipError_t launch_restrict(const TransferTab& tab, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
+                           hipStream_t s);
 
 // out = c * tab[class(i)] * in  (class table of length q^3; in may be null -> 1)
 hipError_t launch_class_scale(bool fp32, int q, int N, const double* tab, double c, const void* in, void* out,
@@ -75,9 +80,10 @@ constexpr int kRedBlocks = 1024;
 hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double* part, double* dst,
                       hipStream_t s);
 hipError_t launch_sum(bool fp32, int64_t n, const void* x, double* part, double* dst, hipStream_t s);
-// sum_i tab[class(i)] x_i (the integral of the FE function on a uniform level)
+// sum_i tab[class(i)] x_i (the integral of the FE function on a uniform level);
+// needs N^2 partials in `part` (capacity part_cap).
 hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const void* x, double* part,
-                            double* dst, hipStream_t s);
+                            int64_t part_cap, double* dst, hipStream_t s);
 
 // Vector updates whose coefficients live in device memory (no host sync).
 //  axpy2:   u += a p ; r -= a w        with a = sc[i_num] / sc[i_den]
@@ -95,8 +101,9 @@ hipError_t launch_class_axpy(bool fp32, int q, int N, const double* tab, double 
 // out_i = 2 U_i - 1 with U_i the i-th uniform double of the SplitMix64 stream `key`.
 hipError_t launch_splitmix_start(uint64_t key, int64_t n, double* out, hipStream_t s);
 
-// Precision conversions: f64 -> f32 copy, and u64 += c32.
+// Precision conversions: f64 -> f32 and f32 -> f64 copies, and u64 += c32.
 hipError_t launch_cast_d2f(int64_t n, const double* in, float* out, hipStream_t s);
+hipError_t launch_cast_f2d(int64_t n, const float* in, double* out, hipStream_t s);
 hipError_t launch_add_f2d(int64_t n, const float* c, double* u, hipStream_t s);
 hipError_t launch_fill_zero(bool fp32, int64_t n, void* v, hipStream_t s);
 hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStream_t s);

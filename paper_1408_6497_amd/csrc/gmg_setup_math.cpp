@@ -135,6 +135,8 @@ LevelTables make_level_tables(int q, int n) {
   A.q = q;
   assembled_rows(q, khat, 1.0 / h, A.krow);
   assembled_rows(q, mhat, h, A.mrow);
+  assembled_rows(q, khat, 1.0 / h, A.zkrow);
+  assembled_rows(q, mhat, h, A.zmrow);
   for (int a = 0; a <= q; ++a)
     for (int b = 0; b <= q; ++b) {
       A.zk[a][b] = khat[a * (q + 1) + b] / h;
@@ -163,7 +165,11 @@ LevelTables make_level_tables(int q, int n) {
   OpTab& M = L.mass;
   M = A;
   for (int c = 0; c < q; ++c)
-    for (int o = 0; o < 2 * kMaxQ + 1; ++o) M.krow[c][o] = 0.0;
+    for (int o = 0; o < 2 * kMaxQ + 1; ++o) {
+      M.krow[c][o] = 0.0;
+      M.zkrow[c][o] = A.mrow[c][o];
+      M.zmrow[c][o] = 0.0;
+    }
   for (int a = 0; a <= q; ++a)
     for (int b = 0; b <= q; ++b) {
       M.zk[a][b] = A.zm[a][b];
@@ -179,53 +185,22 @@ static double child_coord(const std::vector<double>& xi, int q, int b) {
   return (e + xi[a]) / 2.0;
 }
 
-void make_transfer_tables(int q, AxisTab* prolong, AxisTab* restrict_) {
+void make_transfer_table(int q, TransferTab* tab) {
   const std::vector<double> xi = lgl_nodes01(q);
-  std::memset(prolong, 0, sizeof(AxisTab));
-  std::memset(restrict_, 0, sizeof(AxisTab));
-  // prolongation: fine node o = 2 q E + b (b < 2q) reads coarse q E + a, a = 0..q
-  prolong->period = 2 * q;
-  prolong->base_mul = q;
-  for (int b = 0; b < 2 * q; ++b) {
-    int nt = 0;
-    for (int a = 0; a <= q; ++a) {
-      const double w = lagrange_at(xi, a, child_coord(xi, q, b));
-      if (std::fabs(w) < 1e-15) continue;
-      prolong->off[b][nt] = a;
-      prolong->w[b][nt] = w;
-      ++nt;
+  std::memset(tab, 0, sizeof(TransferTab));
+  tab->q = q;
+  for (int b = 0; b < 2 * q; ++b)
+    for (int a = 0; a <= q; ++a) tab->p[b][a] = lagrange_at(xi, a, child_coord(xi, q, b));
+  // coarse node qE + a gathers fine 2qE + (t - 2q): for t >= 2q the children of
+  // element E (child node t - 2q, value phi_a there); for t < 2q the children of
+  // element E-1, reached only by the vertex a = 0 (coarse local node q of E-1).
+  for (int a = 0; a < q; ++a)
+    for (int t = 0; t <= 4 * q; ++t) {
+      double w = 0.0;
+      if (t >= 2 * q) w = lagrange_at(xi, a, child_coord(xi, q, t - 2 * q));
+      else if (a == 0) w = lagrange_at(xi, q, child_coord(xi, q, t));
+      tab->r[a][t] = (std::fabs(w) < 1e-15) ? 0.0 : w;
     }
-    prolong->ntap[b] = nt;
-  }
-  // restriction (R = P^T): coarse node o = q E + a gathers fine 2 q E + b over
-  // the children of element E (b = 0 .. 2q) and, for a vertex, of element E-1
-  // (b = -2q .. -1, child node b + 2q of E-1, coarse local node q).
-  restrict_->period = q;
-  restrict_->base_mul = 2 * q;
-  for (int a = 0; a < q; ++a) {
-    int nt = 0;
-    if (a == 0) {
-      for (int b = 0; b < 2 * q; ++b) {
-        const double w = lagrange_at(xi, q, child_coord(xi, q, b));
-        if (std::fabs(w) < 1e-15) continue;
-        restrict_->off[a][nt] = b - 2 * q;
-        restrict_->w[a][nt] = w;
-        ++nt;
-      }
-    }
-    for (int b = 0; b <= 2 * q; ++b) {
-      if (a == 0 && b == 2 * q) {
-        // fine node 2q(E+1) is the next coarse vertex: phi_0(1) = 0
-        continue;
-      }
-      const double w = lagrange_at(xi, a, child_coord(xi, q, b));
-      if (std::fabs(w) < 1e-15) continue;
-      restrict_->off[a][nt] = b;
-      restrict_->w[a][nt] = w;
-      ++nt;
-    }
-    restrict_->ntap[a] = nt;
-  }
 }
 
 // Dense periodic 1D matrices of order q on n elements (N = q n).

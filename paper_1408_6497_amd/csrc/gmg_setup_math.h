@@ -24,7 +24,7 @@ double lagrange_at(const std::vector<double>& xi, int a, double t);
 double lagrange_deriv_at(const std::vector<double>& xi, int a, double t);
 void reference_matrices(int q, std::vector<double>* khat, std::vector<double>* mhat);
 LevelTables make_level_tables(int q, int n);
-void make_transfer_tables(int q, AxisTab* prolong, AxisTab* restrict_);
+void make_transfer_table(int q, TransferTab* tab);
 // (A_0 + 1 1^T / N0)^-1 of the coarsest level, dense, symmetric, row-major.
 std::vector<double> coarse_pseudo_inverse(int q, int n);
 uint64_t splitmix64_at(uint64_t key, uint64_t i);

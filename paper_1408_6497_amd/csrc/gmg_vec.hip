@@ -1,10 +1,4 @@
-// Intergrid transfers, reductions, vector updates and the coarsest solve.
-//
-// Transfers (Section 2.3.4, eqs. 2.1-2.2): on nested uniform meshes
-// P = P1 (x) P1 (x) P1 with P1(i, j) = phi_j^{coarse}(p_i); it is applied as
-// three one-axis passes, each output node gathering its few banded taps (no
-// scatter, so fine nodes shared by coarse elements are counted once and no
-// atomics are needed).  R = P^T uses the transposed taps.
+// Reductions, vector updates, node-class scalings and the coarsest solve.
 //
 // Reductions accumulate in FP64 whatever the vector type: 64-lane wavefront
 // shuffles, then LDS across the block, then a second single-block pass over the
@@ -23,63 +17,38 @@ inline int grid_for(int64_t n, int per_thread = 4) {
   return static_cast<int>(g);
 }
 
-// ---------------------------------------------------------------- transfers
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_axis(const T* __restrict__ in, T* __restrict__ out, const AxisTab tab,
-                                                  const int d0, const int d1, const int d2, const int axis,
-                                                  const int in_len, const int accumulate) {
-  const int64_t total = static_cast<int64_t>(d0) * d1 * d2;
-  const int inm = in_len - 1;
-  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
-       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    int c0 = static_cast<int>(idx % d0);
-    int64_t rest = idx / d0;
-    int c1 = static_cast<int>(rest % d1);
-    int c2 = static_cast<int>(rest / d1);
-    int o = axis == 0 ? c0 : (axis == 1 ? c1 : c2);
-    const int cls = o % tab.period;
-    const int base = (o / tab.period) * tab.base_mul;
-    // input strides with extent in_len along `axis`
-    const int e0 = axis == 0 ? in_len : d0;
-    const int e1 = axis == 1 ? in_len : d1;
-    double accv = 0.0;
-    const int nt = tab.ntap[cls];
-    for (int t = 0; t < nt; ++t) {
-      const int ic = (base + tab.off[cls][t] + in_len) & inm;
-      int i0 = c0, i1 = c1, i2 = c2;
-      if (axis == 0) i0 = ic;
-      else if (axis == 1) i1 = ic;
-      else i2 = ic;
-      const int64_t iidx = i0 + static_cast<int64_t>(e0) * (i1 + static_cast<int64_t>(e1) * i2);
-      accv += tab.w[cls][t] * static_cast<double>(in[iidx]);
-    }
-    if (accumulate) out[idx] = static_cast<T>(static_cast<double>(out[idx]) + accv);
-    else out[idx] = static_cast<T>(accv);
-  }
-}
-
 // ---------------------------------------------------------------- class tables
 struct ClassTab {
   double v[kMaxQ * kMaxQ * kMaxQ];
 };
 
-__device__ __forceinline__ int node_class(int64_t idx, int N, int q) {
-  const int i = static_cast<int>(idx % N);
-  const int64_t r = idx / N;
-  const int j = static_cast<int>(r % N);
-  const int k = static_cast<int>(r / N);
-  return (i % q) + q * ((j % q) + q * (k % q));
+// Node-class kernels run on a (ceil(N/256), N, N) grid: x along the row, y and z
+// from the block index, so the class (i mod q, j mod q, k mod q) needs no 64-bit
+// division.
+struct Ijk {
+  int i, j, k;
+  size_t idx;
+};
+
+__device__ __forceinline__ bool ijk_of(int N, Ijk* p) {
+  p->i = blockIdx.x * blockDim.x + threadIdx.x;
+  p->j = blockIdx.y;
+  p->k = blockIdx.z;
+  p->idx = (static_cast<size_t>(p->k) * N + p->j) * N + p->i;
+  return p->i < N;
 }
+
+__device__ __forceinline__ int cls(const Ijk& p, int q) { return (p.i % q) + q * ((p.j % q) + q * (p.k % q)); }
+
+inline dim3 class_grid(int N) { return dim3((N + kBlock - 1) / kBlock, N, N); }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_class_scale(const ClassTab tab, const int q, const int N, const double c,
                                                          const T* in, T* out) {
-  const int64_t total = static_cast<int64_t>(N) * N * N;
-  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
-       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double v = in ? static_cast<double>(in[idx]) : 1.0;
-    out[idx] = static_cast<T>(c * tab.v[node_class(idx, N, q)] * v);
-  }
+  Ijk p;
+  if (!ijk_of(N, &p)) return;
+  const double v = in ? static_cast<double>(in[p.idx]) : 1.0;
+  out[p.idx] = static_cast<T>(c * tab.v[cls(p, q)] * v);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -108,16 +77,18 @@ __global__ void __launch_bounds__(kBlock) k_dot(const int64_t n, const T* __rest
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// sum_i tab[class(i)] x_i: each block sums a plane-row strip, blocks write
+// partials in a fixed order (grid (1, N, N) -> N^2 partials, folded by k_finish_many).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_class_dot(const ClassTab tab, const int q, const int N,
                                                        const T* __restrict__ x, double* part) {
-  const int64_t n = static_cast<int64_t>(N) * N * N;
+  const int j = blockIdx.y, k = blockIdx.z;
+  const T* row = x + (static_cast<size_t>(k) * N + j) * N;
   double s = 0.0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    s = fma(tab.v[node_class(i, N, q)], static_cast<double>(x[i]), s);
+  const int base = q * ((j % q) + q * (k % q));
+  for (int i = threadIdx.x; i < N; i += kBlock) s = fma(tab.v[base + i % q], static_cast<double>(row[i]), s);
   s = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[static_cast<size_t>(k) * N + j] = s;
 }
 
 __global__ void __launch_bounds__(kBlock) k_finish(const double* part, const int nparts, double* dst) {
@@ -174,10 +145,9 @@ __global__ void __launch_bounds__(kBlock) k_axpy(const int64_t n, const double a
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_class_axpy(const ClassTab tab, const int q, const int N, const double c,
                                                         T* v) {
-  const int64_t total = static_cast<int64_t>(N) * N * N;
-  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
-       idx += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    v[idx] = static_cast<T>(static_cast<double>(v[idx]) + c * tab.v[node_class(idx, N, q)]);
+  Ijk p;
+  if (!ijk_of(N, &p)) return;
+  v[p.idx] = static_cast<T>(static_cast<double>(v[p.idx]) + c * tab.v[cls(p, q)]);
 }
 
 // SplitMix64 (Steele, Lea, Flood 2014): output i of the stream with key k.
@@ -197,6 +167,13 @@ __global__ void __launch_bounds__(kBlock) k_cast_d2f(const int64_t n, const doub
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     out[i] = static_cast<float>(in[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cast_f2d(const int64_t n, const float* __restrict__ in,
+                                                      double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<double>(in[i]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_add_f2d(const int64_t n, const float* __restrict__ c,
@@ -221,64 +198,50 @@ __global__ void __launch_bounds__(kBlock) k_copy(const int64_t n, const T* __res
 }
 
 // ---------------------------------------------------------------- coarsest solve
-constexpr int kCoarseBlock = 512;
-constexpr int kCoarseMax = 4096;
+// x = Ainv (b - mean(b)) with Ainv symmetric (row i read contiguously): each
+// block has 4 wavefronts, one row each; every block recomputes the mean of b
+// (n0 <= 512 values) so no second launch is needed.
+constexpr int kCoarseMax = 512;
+constexpr int kCoarseRows = 4;
 
 template <typename T>
-__global__ void __launch_bounds__(kCoarseBlock) k_coarse(const int n0, const double* __restrict__ ainv,
-                                                          const T* __restrict__ b, T* __restrict__ x) {
+__global__ void __launch_bounds__(64 * kCoarseRows) k_coarse(const int n0, const double* __restrict__ ainv,
+                                                              const T* __restrict__ b, T* __restrict__ x) {
   __shared__ double bs[kCoarseMax];
-  __shared__ double red[kCoarseBlock / 64];
-  __shared__ double mean;
+  __shared__ double red[kCoarseRows];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n0; i += kCoarseBlock) {
+  for (int i = threadIdx.x; i < n0; i += 64 * kCoarseRows) {
     const double v = static_cast<double>(b[i]);
     bs[i] = v;
     s += v;
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  if (lane == 0) red[w] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < kCoarseBlock / 64; ++w) t += red[w];
-    mean = t / n0;
-  }
-  __syncthreads();
-  const double m = mean;
-  for (int i = threadIdx.x; i < n0; i += kCoarseBlock) {
-    double acc = 0.0;
-    for (int j = 0; j < n0; ++j) acc = fma(ainv[static_cast<int64_t>(j) * n0 + i], bs[j] - m, acc);
-    x[i] = static_cast<T>(acc);
-  }
+  double tot = 0.0;
+  for (int k = 0; k < kCoarseRows; ++k) tot += red[k];
+  const double m = tot / n0;
+  const int row = blockIdx.x * kCoarseRows + w;
+  if (row >= n0) return;
+  const double* arow = ainv + static_cast<size_t>(row) * n0;
+  double acc = 0.0;
+  for (int j = lane; j < n0; j += 64) acc = fma(arow[j], bs[j] - m, acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) x[row] = static_cast<T>(acc);
 }
 
 }  // namespace
-
-hipError_t launch_axis(const AxisTab& tab, bool fp32, const void* in, void* out, int d0, int d1, int d2, int axis,
-                       int in_len, bool accumulate, hipStream_t s) {
-  const int64_t total = static_cast<int64_t>(d0) * d1 * d2;
-  const int g = grid_for(total, 2);
-  if (fp32)
-    hipLaunchKernelGGL(k_axis<float>, dim3(g), dim3(kBlock), 0, s, static_cast<const float*>(in),
-                       static_cast<float*>(out), tab, d0, d1, d2, axis, in_len, accumulate ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_axis<double>, dim3(g), dim3(kBlock), 0, s, static_cast<const double*>(in),
-                       static_cast<double*>(out), tab, d0, d1, d2, axis, in_len, accumulate ? 1 : 0);
-  return hipGetLastError();
-}
 
 hipError_t launch_class_scale(bool fp32, int q, int N, const double* tab, double c, const void* in, void* out,
                               hipStream_t s) {
   ClassTab ct{};
   for (int i = 0; i < q * q * q; ++i) ct.v[i] = tab[i];
-  const int64_t total = static_cast<int64_t>(N) * N * N;
-  const int g = grid_for(total);
   if (fp32)
-    hipLaunchKernelGGL(k_class_scale<float>, dim3(g), dim3(kBlock), 0, s, ct, q, N, c,
+    hipLaunchKernelGGL(k_class_scale<float>, class_grid(N), dim3(kBlock), 0, s, ct, q, N, c,
                        static_cast<const float*>(in), static_cast<float*>(out));
   else
-    hipLaunchKernelGGL(k_class_scale<double>, dim3(g), dim3(kBlock), 0, s, ct, q, N, c,
+    hipLaunchKernelGGL(k_class_scale<double>, class_grid(N), dim3(kBlock), 0, s, ct, q, N, c,
                        static_cast<const double*>(in), static_cast<double*>(out));
   return hipGetLastError();
 }
@@ -299,19 +262,19 @@ hipError_t launch_sum(bool fp32, int64_t n, const void* x, double* part, double*
   return launch_dot(fp32, n, x, nullptr, part, dst, s);
 }
 
-hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const void* x, double* part, double* dst,
-                            hipStream_t s) {
+hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const void* x, double* part,
+                            int64_t part_cap, double* dst, hipStream_t s) {
+  // one partial per (j, k) row
+  if (static_cast<int64_t>(N) * N > part_cap) return hipErrorInvalidValue;
   ClassTab ct{};
   for (int i = 0; i < q * q * q; ++i) ct.v[i] = tab[i];
-  const int64_t n = static_cast<int64_t>(N) * N * N;
-  const int g = red_grid(n);
   if (fp32)
-    hipLaunchKernelGGL(k_class_dot<float>, dim3(g), dim3(kBlock), 0, s, ct, q, N, static_cast<const float*>(x),
+    hipLaunchKernelGGL(k_class_dot<float>, dim3(1, N, N), dim3(kBlock), 0, s, ct, q, N, static_cast<const float*>(x),
                        part);
   else
-    hipLaunchKernelGGL(k_class_dot<double>, dim3(g), dim3(kBlock), 0, s, ct, q, N, static_cast<const double*>(x),
-                       part);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
+    hipLaunchKernelGGL(k_class_dot<double>, dim3(1, N, N), dim3(kBlock), 0, s, ct, q, N,
+                       static_cast<const double*>(x), part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, N * N, dst);
   return hipGetLastError();
 }
 
@@ -361,12 +324,10 @@ hipError_t launch_axpy(bool fp32, int64_t n, double a, const void* x, void* y, h
 hipError_t launch_class_axpy(bool fp32, int q, int N, const double* tab, double c, void* v, hipStream_t s) {
   ClassTab ct{};
   for (int i = 0; i < q * q * q; ++i) ct.v[i] = tab[i];
-  const int64_t total = static_cast<int64_t>(N) * N * N;
   if (fp32)
-    hipLaunchKernelGGL(k_class_axpy<float>, dim3(grid_for(total)), dim3(kBlock), 0, s, ct, q, N, c,
-                       static_cast<float*>(v));
+    hipLaunchKernelGGL(k_class_axpy<float>, class_grid(N), dim3(kBlock), 0, s, ct, q, N, c, static_cast<float*>(v));
   else
-    hipLaunchKernelGGL(k_class_axpy<double>, dim3(grid_for(total)), dim3(kBlock), 0, s, ct, q, N, c,
+    hipLaunchKernelGGL(k_class_axpy<double>, class_grid(N), dim3(kBlock), 0, s, ct, q, N, c,
                        static_cast<double*>(v));
   return hipGetLastError();
 }
@@ -378,6 +339,11 @@ hipError_t launch_splitmix_start(uint64_t key, int64_t n, double* out, hipStream
 
 hipError_t launch_cast_d2f(int64_t n, const double* in, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_d2f, dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f2d(int64_t n, const float* in, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_f2d, dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out);
   return hipGetLastError();
 }
 
@@ -406,11 +372,12 @@ hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStrea
 
 hipError_t launch_coarse(bool fp32, int n0, const double* ainv, const void* b, void* x, hipStream_t s) {
   if (n0 < 1 || n0 > kCoarseMax) return hipErrorInvalidValue;
+  const dim3 grid((n0 + kCoarseRows - 1) / kCoarseRows);
   if (fp32)
-    hipLaunchKernelGGL(k_coarse<float>, dim3(1), dim3(kCoarseBlock), 0, s, n0, ainv, static_cast<const float*>(b),
+    hipLaunchKernelGGL(k_coarse<float>, grid, dim3(64 * kCoarseRows), 0, s, n0, ainv, static_cast<const float*>(b),
                        static_cast<float*>(x));
   else
-    hipLaunchKernelGGL(k_coarse<double>, dim3(1), dim3(kCoarseBlock), 0, s, n0, ainv,
+    hipLaunchKernelGGL(k_coarse<double>, grid, dim3(64 * kCoarseRows), 0, s, n0, ainv,
                        static_cast<const double*>(b), static_cast<double*>(x));
   return hipGetLastError();
 }

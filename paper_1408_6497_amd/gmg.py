@@ -23,7 +23,7 @@ EXPORTS = [
     "gmg_setup", "gmg_destroy", "gmg_num_levels", "gmg_num_dofs", "gmg_dof_coords_1d", "gmg_lambda",
     "gmg_diagonal", "gmg_apply", "gmg_mass", "gmg_smooth", "gmg_restrict", "gmg_prolong",
     "gmg_coarse_solve", "gmg_vcycle", "gmg_rhs", "gmg_solve", "gmg_solve_rhs", "gmg_dot",
-    "gmg_status_string", "gmg_last_error",
+    "gmg_timing_get", "gmg_timing_reset", "gmg_status_string", "gmg_last_error",
 ]
 
 
@@ -39,6 +39,8 @@ class GmgOptions(ctypes.Structure):
         ("lanczos_steps", ctypes.c_int32), ("smoother", ctypes.c_int32), ("jacobi_omega", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("vcycle_prec", ctypes.c_int32), ("krylov", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("lambda_override", ctypes.c_double),
+        ("timing", ctypes.c_int32), ("no_graphs", ctypes.c_int32),
+        ("ir_mode", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
     ]
 
 
@@ -90,6 +92,8 @@ def load():
         "gmg_solve": [P, P, P, D, ctypes.POINTER(GmgInfo)],
         "gmg_solve_rhs": [P, P, P, D, ctypes.POINTER(GmgInfo)],
         "gmg_dot": [P, I32, I64, P, P, ctypes.POINTER(D)],
+        "gmg_timing_get": [P, I32, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D)],
+        "gmg_timing_reset": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -242,6 +246,19 @@ class Context:
         self._check(self.lib.gmg_dot(self.h, p, x.numel(), self._vec(x, None, p), self._vec(y, None, p),
                                      ctypes.byref(v)))
         return v.value
+
+    # -- launch timing (needs timing=1 at construction)
+    KIND_APPLY, KIND_RESIDUAL, KIND_SMOOTH0, KIND_SMOOTH, KIND_MASS = range(5)
+
+    def timing(self, level, kind, prec):
+        """(launches, seconds) of one level / kind / precision since the last reset."""
+        cnt, sec = ctypes.c_int64(), ctypes.c_double()
+        self._check(self.lib.gmg_timing_get(self.h, self._lvl(level), kind, prec, ctypes.byref(cnt),
+                                            ctypes.byref(sec)))
+        return cnt.value, sec.value
+
+    def timing_reset(self):
+        self._check(self.lib.gmg_timing_reset(self.h))
 
     def solve(self, f, u, rtol, raise_on_noconv=True):
         lv = self.levels - 1

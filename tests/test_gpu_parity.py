@@ -228,3 +228,25 @@ def test_error_paths_on_device():
     assert e.value.status == 6          # GMG_E_BREAKDOWN
     with pytest.raises(ValueError):
         ctx2.apply(-1, f, f[:10])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_matches_eager(prec):
+    """The V-cycle replayed from a captured HIP graph gives the bits of the eager launches."""
+    torch = torch_cuda()
+    from workloads import gaussian_params, gaussian_source
+    from paper_1408_6497_amd import GMG_FP32, GMG_FP64
+    vp = GMG_FP32 if prec == "fp32" else GMG_FP64
+    q, n = 2, 16
+    eager = _ctx(q, n, 0, seed=2, vcycle_prec=vp, no_graphs=1)
+    graph = _ctx(q, n, 0, seed=2, vcycle_prec=vp)
+    f = gaussian_source(eager.dof_coords_1d(), gaussian_params(3, 32, 0.02, 0.1)).cuda()
+    ue, ug = torch.empty_like(f), torch.empty_like(f)
+    for rep in range(3):
+        ie = eager.solve(f, ue, 1e-8)
+        scratch = torch.randn_like(f) * 3.0          # eager work between replays
+        ig = graph.solve(f, ug, 1e-8)
+        torch.cuda.synchronize()
+        assert ie.inner_iters == ig.inner_iters and ie.outer_iters == ig.outer_iters
+        assert torch.equal(ue, ug), f"replay {rep} differs"
+        del scratch
