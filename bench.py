@@ -80,6 +80,26 @@ def smoother_roofline(ctx, order):
     return launches, sec, algo_bytes, per_level
 
 
+def traffic_record():
+    """HBM traffic per launch of the roofline kernel, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary; None if the kernel source changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_apply_col_f32_q2_256cubed_traffic.md")
+    src = os.path.join(ROOT, "paper_1408_6497_amd", "csrc", "gmg_apply.hip")
+    try:
+        rec = None
+        for line in open(path):
+            if line.startswith("traffic_record: "):
+                rec = json.loads(line[len("traffic_record: "):])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if rec and rec.get("source_sha256_16") == sha:
+            return rec
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(q=2, n_sample=64, n_full=128, seed=0):
     """The oracle (numpy/scipy, FP64, Kronecker form) solving the same workload at a
     smaller size; its solve time is scaled to the full size by the DoF ratio (the
@@ -118,6 +138,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-apply-bench", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for rocprofv3 --pmc runs: a 256 MiB device copy (counter calibration), then one eager "
+                         "mixed solve of the bench problem; prints nothing on stdout")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -129,6 +152,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     q, n, seed = 2, 128, 0
+    if args.traffic_probe:
+        a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)          # reads and writes 256 MiB each
+        torch.cuda.synchronize()
+        ctxp = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP32, no_graphs=1)
+        f = gaussian_source(ctxp.dof_coords_1d(), gaussian_params(seed, 32, 0.02, 0.1), device="cuda")
+        u = torch.empty_like(f)
+        ctxp.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        log("[bench] traffic probe done")
+        return
     log(f"[bench] setup Q{q} n={n}")
     ctx32 = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP32)
     ctx64 = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP64)
@@ -183,6 +219,7 @@ def main():
         big.close()
         log(f"[bench] apply {json.dumps(apply)}")
 
+    traffic = traffic_record()
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -220,7 +257,10 @@ def main():
             "kernel": "k_apply_col<float, 2, 1, Cheb>: FP32 smoother step on the 256^3 and 128^3 levels",
             "measured": "HIP events around every launch in an eager repeat of the timed solve",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (traffic["traffic_bytes_per_launch"] if traffic else None),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00, copy-calibrated)",
+            "algorithmic_bytes_per_launch": algo_bytes / max(launches, 1),
             "launches": launches, "avg_launch_us": avg_dur * 1e6, "per_level": per_level,
         },
         "cpu_baseline": cpu,
