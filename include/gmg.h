@@ -97,13 +97,15 @@ typedef struct {
                                is one FP32 V-cycle (FP64 residual, update, dots and
                                projection at every iteration).  1: nested refinement,
                                FP64 residual / update around FP32 flexible CG solves    */
-  int32_t reserved_opt;
+  int32_t use_learned;      /* != 0: learned smoother in every smoothing phase of levels with
+                               at least 16 lattice nodes per direction (forces FP32
+                               V-cycles and flexible CG); see gmg_set_learned            */
 } gmg_options;
 
 typedef struct {
   int32_t outer_iters;      /* iterative-refinement steps (0 for plain FP64 PCG)           */
   int32_t inner_iters;      /* total Krylov iterations                                     */
-  int32_t fallbacks;        /* reserved                                                    */
+  int32_t fallbacks;        /* learned cycles replaced by the plain cycle                  */
   int32_t reserved;
   double rel_residual_f64;  /* final ||b - A u||_2 / ||b||_2, recomputed in FP64           */
   double t_setup;           /* seconds spent in gmg_setup (host clock)                     */
@@ -161,6 +163,43 @@ gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, doubl
 
 /* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoother (not in the paper, whose smoother choice is heuristic, Section 1
+ * "Limitations" and Section 2.3.3).  One net per depth d (d = 0 finest level,
+ * d = levels-2 the level above the coarsest); a depth without weights uses the
+ * deepest depth that has them.  Net: Conv3d(1->16) - ReLU - Conv3d(16->16) - ReLU -
+ * Conv3d(16->1), 3x3x3, circular padding on the level's DoF lattice, no bias,
+ * BF16 weights and activations, FP32 accumulation.  Weights are 7776 values in
+ * the flat layout W1[co][t] (432), W2[co][ci][t] (6912), W3[ci][t] (432), tap
+ * t = (dz+1)*9 + (dy+1)*3 + (dx+1), out(v) = sum_t W[.., t] in(v + (dx, dy, dz)).
+ * In a learned cycle each smoothing phase is (nu - 1) Chebyshev applications then
+ * u <- u + s N(D^-1 (b - A u) / s), s = RMS(D^-1 (b - A u)).  Inside gmg_solve each
+ * learned cycle is kept only if ||r - A z|| / ||r|| is no larger than the plain
+ * cycle's last measured value (initialized by two plain cycles on a seeded
+ * vector); otherwise the plain FP32 cycle replaces it (info->fallbacks).
+ * The lattice must have at least 16 nodes per direction (GMG_E_ARG otherwise).
+ * ------------------------------------------------------------------------- */
+
+/* FP32 master weights of one depth (host, 7776 values); resets its Adam state. */
+gmg_status gmg_net_set_weights(gmg_ctx* ctx, int32_t depth, const float* w_host, int64_t n);
+/* BF16 weights (host, 7776 values, round-to-nearest-even bit patterns) of one depth. */
+gmg_status gmg_set_learned(gmg_ctx* ctx, int32_t depth, const uint16_t* w_bf16_host, int64_t n_w);
+gmg_status gmg_net_get_weights(gmg_ctx* ctx, int32_t depth, float* w_host, int64_t n);
+/* Bytes of the activation cache of gmg_net_forward / gmg_net_backward at one depth. */
+gmg_status gmg_net_cache_bytes(const gmg_ctx* ctx, int32_t depth, int64_t* bytes);
+/* y = N_depth(x) on the depth's lattice (x, y FP32 device vectors); cache_dev
+ * (caller-owned, gmg_net_cache_bytes) receives bf16(x) and both activations. */
+gmg_status gmg_net_forward(gmg_ctx* ctx, int32_t depth, const float* x_dev, float* y_dev, void* cache_dev);
+/* gw_dev (7776 FP32, device) += d(sum gy . y)/dw for the forward pass held in
+ * cache_dev; gin_dev (may be NULL) = d(sum gy . y)/d bf16(x). */
+gmg_status gmg_net_backward(gmg_ctx* ctx, int32_t depth, const float* gy_dev, const void* cache_dev, float* gw_dev,
+                            float* gin_dev);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the FP32
+ * master weights of one depth, then re-rounds the BF16 copies. */
+gmg_status gmg_adam_step(gmg_ctx* ctx, int32_t depth, const float* gw_dev, float lr, int64_t step);
+/* e = s N(D^-1 r / s) on one level (FP32 device vectors): the learned correction. */
+gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, float* e_dev);
 
 /* Per-kernel timing, a tracing aid (Section 3 reports Setup/Eval/Comm phase
  * times; this goes down to single launches).  With gmg_options.timing != 0,

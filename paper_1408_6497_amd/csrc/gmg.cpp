@@ -27,7 +27,7 @@ using namespace gmg;
 
 namespace {
 
-constexpr int kNumScal = 32;
+constexpr int kNumScal = 64;
 // device scalar slots
 enum : int {
   S_PW = 0,   // p . w
@@ -38,6 +38,9 @@ enum : int {
   S_SUM = 5,  // projection sum
   S_RR = 6,   // r . r
   S_TMP = 7,
+  S_LRES = 8,   // ||r - A z||^2 of a cycle under test
+  S_LRR = 9,    // ||r||^2 of that cycle's input
+  S_SSUM = 16,  // + level: sum of (D^-1 r)^2 of the learned correction on that level
 };
 
 struct Level {
@@ -60,8 +63,10 @@ struct gmg_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // captured finest V-cycles: [0] FP64 on (kr0, kz0), [1] FP32 on (kr1, kz1),
   // [2] FP64 r -> FP32 V-cycle -> FP64 z on (kr0, kz0)
-  hipGraphExec_t vgraph[3] = {nullptr, nullptr, nullptr};
-  bool graph_failed[3] = {false, false, false};
+  // [3..6] the learned / plain test sequences of the learned cycle (see precondition)
+  hipGraphExec_t vgraph[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool graph_failed[8] = {false, false, false, false, false, false, false, false};
+  bool suppress_learned = false;
   std::vector<Level> lv;
   TransferTab xfer{};
   void* tA[2] = {nullptr, nullptr};
@@ -87,6 +92,16 @@ struct gmg_ctx {
     hipEvent_t a, b;
     int level, kind, pi;
   };
+  // learned smoother: one net per depth (depth 0 = finest level)
+  std::vector<NetDev> nets;
+  std::vector<char> net_set;
+  std::vector<void*> lcache;      // per level: forward cache of the learned correction
+  void* g1g2 = nullptr;           // backward scratch (64 bytes per voxel of the largest trained level)
+  int64_t g1g2_bytes = 0;
+  float* npart = nullptr;         // weight-gradient partials
+  int64_t npart_floats = 0;
+  double rho_plain = -1.0;        // most recent contraction of a plain FP32 cycle
+  int64_t fallbacks = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_all;
   std::vector<Pending> pending;
@@ -313,17 +328,55 @@ gmg_status coarse_solve(gmg_ctx* c, int pi, const void* b, void* x) {
   return GMG_OK;
 }
 
+// Net used at depth d: its own if set, else the deepest (largest depth) net that is set.
+int net_for_depth(const gmg_ctx* c, int d) {
+  if (d >= 0 && d < static_cast<int>(c->net_set.size()) && c->net_set[d]) return d;
+  for (int k = static_cast<int>(c->net_set.size()) - 1; k >= 0; --k)
+    if (c->net_set[k]) return k;
+  return -1;
+}
+
+bool learned_on_level(const gmg_ctx* c, int l, int pi) {
+  return c->opt.use_learned && !c->suppress_learned && pi == 1 && l > 0 && c->lv[l].N >= 16 &&
+         net_for_depth(c, c->L - 1 - l) >= 0;
+}
+
+gmg_status ensure_lcache(gmg_ctx* c, int l) {
+  if (c->lcache[l]) return GMG_OK;
+  return dalloc(c, &c->lcache[l], static_cast<size_t>(net_cache_bytes(c->lv[l].N)));
+}
+
+// u <- u + s N_d(D^-1 (b - A u) / s) on level l (FP32), s = RMS(D^-1 (b - A u)).
+gmg_status learned_correction(gmg_ctx* c, int l, const void* b, void* u) {
+  Level& L = c->lv[l];
+  const int d = net_for_depth(c, c->L - 1 - l);
+  STCHK(ensure_lcache(c, l));
+  STCHK(apply_op(c, l, 1, Epi::Residual, u, L.xp[1], b, nullptr, 0, 0));
+  HIPCHK(c, launch_net_input(static_cast<const float*>(L.xp[1]), L.tab.stiff.dinv, c->q, c->scal + S_SSUM + l,
+                             c->part, L.N, c->lcache[l], c->stream));
+  HIPCHK(c, launch_net_forward(c->nets[d], L.N, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
+                               c->stream));
+  return GMG_OK;
+}
+
 // Algorithm 2.1 on level l with zero initial guess: u = V_l b.
 gmg_status vcycle_level(gmg_ctx* c, int l, int pi, const void* b, void* u) {
   if (l == 0) return coarse_solve(c, pi, b, u);
   Level& L = c->lv[l];
   Level& C = c->lv[l - 1];
-  STCHK(smooth(c, l, pi, b, u, c->opt.nu_pre, true));                            // pre-smooth
+  // learned cycle: in each smoothing phase the last polynomial application is
+  // replaced by one learned correction
+  const bool lrn = learned_on_level(c, l, pi);
+  const int nu_pre = lrn ? c->opt.nu_pre - 1 : c->opt.nu_pre;
+  const int nu_post = lrn ? c->opt.nu_post - 1 : c->opt.nu_post;
+  STCHK(smooth(c, l, pi, b, u, nu_pre, true));                                    // pre-smooth
+  if (lrn) STCHK(learned_correction(c, l, b, u));
   STCHK(apply_op(c, l, pi, Epi::Residual, u, L.xp[pi], b, nullptr, 0, 0));       // residual
   STCHK(restrict_level(c, l, pi, L.xp[pi], C.b[pi]));                             // restrict
   STCHK(vcycle_level(c, l - 1, pi, C.b[pi], C.u[pi]));                            // recurse
   STCHK(prolong_level(c, l, pi, C.u[pi], u));                                     // correct
-  STCHK(smooth(c, l, pi, b, u, c->opt.nu_post, false));                           // post-smooth
+  STCHK(smooth(c, l, pi, b, u, nu_post, false));                                  // post-smooth
+  if (lrn) STCHK(learned_correction(c, l, b, u));
   return GMG_OK;
 }
 
@@ -356,26 +409,111 @@ gmg_status vcycle_seq(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
   return GMG_OK;
 }
 
-gmg_status run_vcycle(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
-  const int key = (pi == vpi) ? pi : 2;
-  if (c->opt.timing || c->opt.no_graphs || c->graph_failed[key] || r != c->kr[pi] || z != c->kz[pi])
-    return vcycle_seq(c, pi, vpi, r, z);
+// Run a launch sequence with fixed arguments through a HIP graph captured on
+// first use (eagerly with launch timing on, with no_graphs, or if capture fails).
+template <class F>
+gmg_status graph_run(gmg_ctx* c, int key, F&& seq) {
+  if (c->opt.timing || c->opt.no_graphs || c->graph_failed[key]) return seq();
   if (!c->vgraph[key]) {
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    const gmg_status st = vcycle_seq(c, pi, vpi, r, z);
+    const gmg_status st = seq();
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     hipGraphExec_t ex = nullptr;
     if (st != GMG_OK || e != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       (void)hipGetLastError();
       c->graph_failed[key] = true;
-      return vcycle_seq(c, pi, vpi, r, z);
+      return seq();
     }
     (void)hipGraphDestroy(g);
     c->vgraph[key] = ex;
   }
   HIPCHK(c, hipGraphLaunch(c->vgraph[key], c->stream));
+  return GMG_OK;
+}
+
+gmg_status run_vcycle(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
+  const int key = (pi == vpi) ? pi : 2;
+  if (r != c->kr[pi] || z != c->kz[pi]) return vcycle_seq(c, pi, vpi, r, z);
+  return graph_run(c, key, [&] { return vcycle_seq(c, pi, vpi, r, z); });
+}
+
+// One FP32 cycle under test: z32 = V r32 (learned or plain), then
+// ||r32 - A z32||^2 -> S_LRES and ||r32||^2 -> S_LRR.  r is the Krylov residual
+// (FP64 when pi = 0: cast down first).
+gmg_status test_cycle(gmg_ctx* c, int pi, const void* r, bool plain) {
+  const int l = c->L - 1;
+  const int64_t n = c->lv[l].size;
+  void* r32 = c->kr[1];
+  if (pi == 0) HIPCHK(c, launch_cast_d2f(n, static_cast<const double*>(r), static_cast<float*>(r32), c->stream));
+  c->suppress_learned = plain;
+  const gmg_status st = vcycle_level(c, l, 1, r32, c->kz[1]);
+  c->suppress_learned = false;
+  STCHK(st);
+  void* t = c->lv[l].xp[1];
+  STCHK(apply_op(c, l, 1, Epi::Residual, c->kz[1], t, r32, nullptr, 0, 0));
+  HIPCHK(c, launch_dot(true, n, t, t, c->part, c->scal + S_LRES, c->stream));
+  HIPCHK(c, launch_dot(true, n, r32, r32, c->part, c->scal + S_LRR, c->stream));
+  return GMG_OK;
+}
+
+// Contraction of the plain FP32 cycle, initialized by two plain cycles on a
+// seeded mean-zero vector (SplitMix64 key seed + 7777).
+gmg_status init_rho_plain(gmg_ctx* c) {
+  const int l = c->L - 1;
+  const int64_t n = c->lv[l].size;
+  double hs[kNumScal];
+  HIPCHK(c, launch_splitmix_start(c->opt.seed + 7777, n, static_cast<double*>(c->kc[0]), c->stream));
+  STCHK(project(c, 0, n, c->kc[0]));
+  double rho = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    STCHK(test_cycle(c, 0, c->kc[0], true));
+    STCHK(read_scalars(c, hs, kNumScal));
+    rho = std::sqrt(hs[S_LRES] / hs[S_LRR]);
+    // next input: the residual of this cycle, widened to FP64
+    HIPCHK(c, launch_cast_f2d(n, static_cast<const float*>(c->lv[l].xp[1]), static_cast<double*>(c->kc[0]),
+                              c->stream));
+  }
+  c->rho_plain = rho;
+  return GMG_OK;
+}
+
+// Everything the learned cycles need before any graph capture: FP32 buffers,
+// the forward caches of the levels that use a net, and the reference
+// contraction of the plain cycle.
+gmg_status prepare_learned(gmg_ctx* c) {
+  if (!c->opt.use_learned || net_for_depth(c, 0) < 0) return GMG_OK;
+  STCHK(ensure_prec(c, 1));
+  for (int l = 1; l < c->L; ++l)
+    if (learned_on_level(c, l, 1)) STCHK(ensure_lcache(c, l));
+  if (c->rho_plain < 0.0) STCHK(init_rho_plain(c));
+  return GMG_OK;
+}
+
+// z = preconditioner(r).  With the learned smoother active, one learned cycle is
+// tried and kept if its contraction is no worse than the plain cycle's most
+// recent one; otherwise the plain FP32 cycle is used (a fallback) and its
+// contraction becomes the new reference.
+gmg_status precondition(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
+  const bool lrn = c->opt.use_learned && vpi == 1 && net_for_depth(c, 0) >= 0;
+  if (!lrn) return run_vcycle(c, pi, vpi, r, z);
+  const int l = c->L - 1;
+  const int64_t n = c->lv[l].size;
+  if (c->rho_plain < 0.0) return fail(c, GMG_E_STATE, "learned cycle used before prepare_learned");
+  double hs[kNumScal];
+  const int base = 3 + (pi == vpi ? 2 : 0);
+  STCHK(graph_run(c, base, [&] { return test_cycle(c, pi, r, false); }));
+  STCHK(read_scalars(c, hs, kNumScal));
+  const double rho_l = std::sqrt(hs[S_LRES] / hs[S_LRR]);
+  if (!(rho_l <= c->rho_plain)) {
+    ++c->fallbacks;
+    STCHK(graph_run(c, base + 1, [&] { return test_cycle(c, pi, r, true); }));
+    STCHK(read_scalars(c, hs, kNumScal));
+    c->rho_plain = std::sqrt(hs[S_LRES] / hs[S_LRR]);
+  }
+  if (pi == 0) HIPCHK(c, launch_cast_f2d(n, static_cast<const float*>(c->kz[1]), static_cast<double*>(z), c->stream));
+  else if (z != c->kz[1]) HIPCHK(c, launch_copy(true, n, c->kz[1], z, c->stream));
   return GMG_OK;
 }
 
@@ -456,7 +594,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   HIPCHK(c, launch_fill_zero(f32, n, u, s));
   STCHK(project(c, pi, n, r));
   auto restart = [&]() -> gmg_status {
-    STCHK(run_vcycle(c, pi, vpi, r, z));
+    STCHK(precondition(c, pi, vpi, r, z));
     STCHK(project(c, pi, n, z));
     if (!flexible) HIPCHK(c, launch_dot(f32, n, r, z, c->part, c->scal + rz, s));
     HIPCHK(c, launch_copy(f32, n, z, p, s));
@@ -504,7 +642,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: p^T A p <= 0 or not finite");
     }
     if (std::sqrt(rr) <= tol_abs) continue;
-    STCHK(run_vcycle(c, pi, vpi, r, z));
+    STCHK(precondition(c, pi, vpi, r, z));
     STCHK(project(c, pi, n, z));
     if (flexible) {
       HIPCHK(c, launch_dot(f32, n, z, w, c->part, c->scal + S_ZW, s));
@@ -588,6 +726,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   if (o.jacobi_omega <= 0) o.jacobi_omega = 2.0 / 3.0;
   if (o.inner_rtol <= 0) o.inner_rtol = 2e-6;
   if (o.max_iters <= 0) o.max_iters = 500;
+  if (o.use_learned) o.vcycle_prec = GMG_FP32;  // the learned cycle is an FP32 cycle
   if (o.vcycle_prec == GMG_FP32) o.krylov = 1;
   c->opt = o;
   c->user = static_cast<hipStream_t>(hip_stream);
@@ -606,6 +745,9 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     return GMG_E_HIP;
   }
   c->lv.resize(L);
+  c->nets.resize(L);
+  c->net_set.assign(L, 0);
+  c->lcache.assign(L, nullptr);
   c->tsec.assign(static_cast<size_t>(L) * kKinds * 2, 0.0);
   c->tcount.assign(static_cast<size_t>(L) * kKinds * 2, 0);
   for (int l = 0; l < L; ++l) {
@@ -782,6 +924,8 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   const hipStream_t s = c->stream;
   gmg_info inf{};
   inf.t_setup = c->t_setup;
+  STCHK(prepare_learned(c));
+  c->fallbacks = 0;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -876,6 +1020,7 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   inf.t_solve = ms * 1e-3;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  inf.fallbacks = static_cast<int32_t>(c->fallbacks);
   if (info) *info = inf;
   return st;
 }
@@ -906,6 +1051,139 @@ gmg_status gmg_timing_reset(gmg_ctx* ctx) {
   std::fill(ctx->tsec.begin(), ctx->tsec.end(), 0.0);
   std::fill(ctx->tcount.begin(), ctx->tcount.end(), 0);
   return GMG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+gmg_status ensure_net(gmg_ctx* c, int d) {
+  NetDev& n = c->nets[d];
+  if (n.w) return GMG_OK;
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w), sizeof(float) * kNetWeights));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.m), sizeof(float) * kNetWeights));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.v), sizeof(float) * kNetWeights));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w1q), sizeof(float) * 432));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w3q), sizeof(float) * 432));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w2f), sizeof(uint16_t) * 6912));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w2b), sizeof(uint16_t) * 6912));
+  return GMG_OK;
+}
+
+gmg_status check_depth(const gmg_ctx* c, int d) {
+  if (!c || d < 0 || d >= c->L - 1) return GMG_E_ARG;  // the coarsest level has no smoother
+  if (c->lv[c->L - 1 - d].N < 16) return GMG_E_ARG;
+  return GMG_OK;
+}
+
+gmg_status set_master(gmg_ctx* c, int d, const float* w_host) {
+  STCHK(ensure_net(c, d));
+  NetDev& n = c->nets[d];
+  HIPCHK(c, hipMemcpyAsync(n.w, w_host, sizeof(float) * kNetWeights, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_fill_zero(true, kNetWeights, n.m, c->stream));
+  HIPCHK(c, launch_fill_zero(true, kNetWeights, n.v, c->stream));
+  HIPCHK(c, launch_net_pack(n.w, n, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->net_set[d] = 1;
+  // captured cycles bake in which levels use a net
+  for (int k = 0; k < 8; ++k)
+    if (c->vgraph[k]) {
+      (void)hipGraphExecDestroy(c->vgraph[k]);
+      c->vgraph[k] = nullptr;
+    }
+  c->rho_plain = -1.0;
+  return GMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gmg_status gmg_net_cache_bytes(const gmg_ctx* ctx, int32_t depth, int64_t* bytes) {
+  if (!bytes || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  *bytes = net_cache_bytes(ctx->lv[ctx->L - 1 - depth].N);
+  return GMG_OK;
+}
+
+gmg_status gmg_net_set_weights(gmg_ctx* ctx, int32_t depth, const float* w_host, int64_t n) {
+  if (!w_host || n != kNetWeights || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  return scoped(ctx, [&] { return set_master(ctx, depth, w_host); });
+}
+
+gmg_status gmg_set_learned(gmg_ctx* ctx, int32_t depth, const uint16_t* w_bf16_host, int64_t n_w) {
+  if (!w_bf16_host || n_w != kNetWeights || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  std::vector<float> w(kNetWeights);
+  for (int i = 0; i < kNetWeights; ++i) {
+    const uint32_t u = static_cast<uint32_t>(w_bf16_host[i]) << 16;
+    std::memcpy(&w[i], &u, sizeof(float));
+  }
+  return scoped(ctx, [&] { return set_master(ctx, depth, w.data()); });
+}
+
+gmg_status gmg_net_get_weights(gmg_ctx* ctx, int32_t depth, float* w_host, int64_t n) {
+  if (!w_host || n != kNetWeights || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
+  return scoped(ctx, [&] {
+    HIPCHK(ctx, hipMemcpyAsync(w_host, ctx->nets[depth].w, sizeof(float) * kNetWeights, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_net_forward(gmg_ctx* ctx, int32_t depth, const float* x_dev, float* y_dev, void* cache_dev) {
+  if (!x_dev || !y_dev || !cache_dev || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
+  const int N = ctx->lv[ctx->L - 1 - depth].N;
+  return scoped(ctx, [&] {
+    HIPCHK(ctx, launch_net_input(x_dev, nullptr, ctx->q, nullptr, ctx->part, N, cache_dev, ctx->stream));
+    HIPCHK(ctx, launch_net_forward(ctx->nets[depth], N, cache_dev, 0, nullptr, y_dev, ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_net_backward(gmg_ctx* ctx, int32_t depth, const float* gy_dev, const void* cache_dev, float* gw_dev,
+                            float* gin_dev) {
+  if (!gy_dev || !cache_dev || !gw_dev || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
+    return GMG_E_ARG;
+  const int N = ctx->lv[ctx->L - 1 - depth].N;
+  const int64_t nv = static_cast<int64_t>(N) * N * N;
+  if (ctx->g1g2_bytes < nv * 64) {
+    STCHK(dalloc(ctx, &ctx->g1g2, static_cast<size_t>(nv * 64)));
+    ctx->g1g2_bytes = nv * 64;
+  }
+  if (ctx->npart_floats < net_partial_floats(N)) {
+    STCHK(dalloc(ctx, reinterpret_cast<void**>(&ctx->npart), sizeof(float) * net_partial_floats(N)));
+    ctx->npart_floats = net_partial_floats(N);
+  }
+  return scoped(ctx, [&] {
+    HIPCHK(ctx, launch_net_backward(ctx->nets[depth], N, cache_dev, gy_dev, ctx->g1g2, ctx->npart, gw_dev, gin_dev,
+                                    ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_adam_step(gmg_ctx* ctx, int32_t depth, const float* gw_dev, float lr, int64_t step) {
+  if (!gw_dev || step < 1 || !(lr > 0.0f) || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
+    return GMG_E_ARG;
+  return scoped(ctx, [&] {
+    HIPCHK(ctx, launch_adam(ctx->nets[depth], gw_dev, lr, step, ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, float* e_dev) {
+  if (!ctx || !r_dev || !e_dev || check_level(ctx, level) != GMG_OK || ctx->lv[level].N < 16) return GMG_E_ARG;
+  const int d = net_for_depth(ctx, ctx->L - 1 - level);
+  if (d < 0) return fail(ctx, GMG_E_STATE, "no learned weights set");
+  return scoped(ctx, [&] {
+    STCHK(ensure_lcache(ctx, level));
+    const Level& L = ctx->lv[level];
+    HIPCHK(ctx, launch_fill_zero(true, L.size, e_dev, ctx->stream));
+    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ctx->scal + S_SSUM + level, ctx->part, L.N,
+                                 ctx->lcache[level], ctx->stream));
+    HIPCHK(ctx, launch_net_forward(ctx->nets[d], L.N, ctx->lcache[level], 1, ctx->scal + S_SSUM + level, e_dev,
+                                   ctx->stream));
+    return GMG_OK;
+  });
 }
 
 gmg_status gmg_solve(gmg_ctx* ctx, const double* f_dev, double* u_dev, double rtol, gmg_info* info) {

@@ -108,6 +108,42 @@ hipError_t launch_add_f2d(int64_t n, const float* c, double* u, hipStream_t s);
 hipError_t launch_fill_zero(bool fp32, int64_t n, void* v, hipStream_t s);
 hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStream_t s);
 
+// *dst = sum of `count` FP64 partials, in a fixed order (one block).
+hipError_t launch_sum_partials(const double* part, int64_t count, double* dst, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Learned smoother (gmg_net.hip): device state of one net.  Master weights w
+// and Adam moments m, v are FP32 in the flat layout W1[co][t], W2[co][ci][t],
+// W3[ci][t] (7776 values); w1q, w3q hold the BF16-rounded layer-1/3 weights
+// tap-major as FP32; w2f / w2b are the BF16 A operands of the forward and
+// backward-data layer-2 MFMA passes.
+struct NetDev {
+  float* w = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  float* w1q = nullptr;
+  uint16_t* w2f = nullptr;
+  uint16_t* w2b = nullptr;
+  float* w3q = nullptr;
+};
+constexpr int kNetWeights = 7776;
+// bytes of the forward cache (BF16 input + two 16-channel BF16 activations)
+int64_t net_cache_bytes(int N);
+// FP32 scratch values needed by the weight-gradient reductions
+int64_t net_partial_floats(int N);
+hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s);
+// cache.x_in = bf16(D^-1 r / s), s = RMS(D^-1 r) written to *ssum as a sum of squares
+// (dinv == null: x_in = bf16(r), ssum unused); part needs N^2 doubles.
+hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part, int N,
+                            void* cache, hipStream_t s);
+// y = N(x_in) (mode 0) or y += s N(x_in) with s = sqrt(*ssum / N^3) (mode 1)
+hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, const double* ssum, float* y,
+                              hipStream_t s);
+// gw += d(sum gy . y)/dw; gin = d(sum gy . y)/dx_in when non-null.  g1g2: 64 bytes per voxel.
+hipError_t launch_net_backward(const NetDev& d, int N, const void* cache, const float* gy, void* g1g2, float* part,
+                               float* gw, float* gin, hipStream_t s);
+hipError_t launch_adam(NetDev& d, const float* gw, float lr, int64_t step, hipStream_t s);
+
 // Coarsest solve: x = Ainv (b - mean(b)), Ainv dense symmetric N0 x N0 (FP64),
 // b and x of the kernel precision, arithmetic in FP64.
 hipError_t launch_coarse(bool fp32, int n0, const double* ainv, const void* b, void* x, hipStream_t s);

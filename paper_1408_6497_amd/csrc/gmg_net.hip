@@ -1,0 +1,531 @@
+// Learned smoother kernels: a 3-layer 3x3x3 convolutional net on the DoF
+// lattice of one level (circular padding, no bias, 16 hidden channels), its
+// backward pass and an Adam step.
+//
+//   x_in = bf16(D^-1 r / s)                       s = RMS(D^-1 r)
+//   a1   = bf16(relu(W1 * x_in))                  1 -> 16 channels
+//   a2   = bf16(relu(W2 * a1))                    16 -> 16 (MFMA)
+//   y    = W3 * a2                                16 -> 1
+//   u   += s y                                    (learned correction)
+//
+// Weights and activations are BF16 (round to nearest even from FP32), every
+// accumulation is FP32.  Activations are channels-last: 16 BF16 values (32
+// bytes) per voxel, voxel index i + N (j + N k).  A tap t = (dz+1) 9 + (dy+1) 3
+// + (dx+1) reads the voxel at offset (dx, dy, dz), wrapped periodically.
+//
+// Layer 2 (6912 of the 7776 multiply-adds per voxel) runs on the matrix cores:
+// v_mfma_f32_16x16x16_bf16 with the 16x16 weight block of a tap as A (held in
+// registers for all 27 taps), 16 input channels x 16 voxels along x as B (read
+// from an LDS brick with a one-voxel halo), accumulating 16 output channels x
+// 16 voxels over the 27 taps.  The same kernel does the backward-data pass with
+// the flipped, transposed weights and the ReLU mask of the forward pass.
+#include "gmg_kernels.h"
+
+namespace gmg {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNC = 16;
+constexpr int kTaps = 27;
+constexpr int kBlk = 256;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__device__ __forceinline__ size_t vox(int i, int j, int k, int N) {
+  return (static_cast<size_t>(k) * N + j) * N + i;
+}
+
+// voxel index of (i, j, k) + offset of tap t (sign +1) or - offset (sign -1)
+__device__ __forceinline__ size_t nbr(int i, int j, int k, int t, int sign, int N) {
+  const int m = N - 1;
+  const int dx = (t % 3) - 1, dy = ((t / 3) % 3) - 1, dz = (t / 9) - 1;
+  return vox((i + sign * dx) & m, (j + sign * dy) & m, (k + sign * dz) & m, N);
+}
+
+struct ClassTab64 {
+  double v[64];
+};
+
+// ---------------------------------------------------------------------------- input
+// x_in = bf16(D^-1 r / s) with s = sqrt(ssum / N^3) (or x_in = bf16(x) when dinv is null)
+__global__ void __launch_bounds__(kBlk) k_net_in(const float* __restrict__ r, const ClassTab64 dinv, const int q,
+                                                 const int use_dinv, const double* __restrict__ ssum, const int N,
+                                                 uint16_t* __restrict__ xin) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= N) return;
+  const size_t v = vox(i, j, k, N);
+  float x = r[v];
+  if (use_dinv) {
+    const double nn = static_cast<double>(N) * N * N;
+    const float s = static_cast<float>(sqrt(*ssum / nn));
+    const float d = static_cast<float>(dinv.v[(i % q) + q * ((j % q) + q * (k % q))]);
+    x = (s > 0.0f) ? (d * x) / s : 0.0f;
+  }
+  xin[v] = f2bf(x);
+}
+
+// sum over voxels of (D^-1 r)^2, one partial per (j, k) row
+__global__ void __launch_bounds__(kBlk) k_net_sqsum(const float* __restrict__ r, const ClassTab64 dinv, const int q,
+                                                    const int N, double* part) {
+  __shared__ double red[kBlk / 64];
+  const int j = blockIdx.y, k = blockIdx.z;
+  double s = 0.0;
+  const float* row = r + (static_cast<size_t>(k) * N + j) * N;
+  const int base = q * ((j % q) + q * (k % q));
+  for (int i = threadIdx.x; i < N; i += kBlk) {
+    const float d = static_cast<float>(dinv.v[base + i % q]);
+    const double t = static_cast<double>(d * row[i]);
+    s = fma(t, t, s);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlk / 64; ++w) t += red[w];
+    part[static_cast<size_t>(k) * N + j] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------- layer 1 (1 -> 16)
+__global__ void __launch_bounds__(kBlk) k_net_l1(const uint16_t* __restrict__ xin, const float* __restrict__ w1q,
+                                                 const int N, uint16_t* __restrict__ a1) {
+  __shared__ float w[kTaps * kNC];  // [t][co]
+  for (int e = threadIdx.x; e < kTaps * kNC; e += kBlk) w[e] = w1q[e];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= N) return;
+  float z[kNC];
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) z[c] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) {
+    const float x = bf2f(xin[nbr(i, j, k, t, 1, N)]);
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) z[c] = fmaf(w[t * kNC + c], x, z[c]);
+  }
+  uint32_t p[kNC / 2];
+#pragma unroll
+  for (int c = 0; c < kNC / 2; ++c)
+    p[c] = static_cast<uint32_t>(f2bf(fmaxf(z[2 * c], 0.0f))) |
+           (static_cast<uint32_t>(f2bf(fmaxf(z[2 * c + 1], 0.0f))) << 16);
+  uint4* dst = reinterpret_cast<uint4*>(a1 + vox(i, j, k, N) * kNC);
+  dst[0] = make_uint4(p[0], p[1], p[2], p[3]);
+  dst[1] = make_uint4(p[4], p[5], p[6], p[7]);
+}
+
+// ---------------------------------------------------------------------------- layer 2 (16 -> 16, MFMA)
+constexpr int kBX = 16, kBY = 8, kBZ = 4;
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
+
+// out[v][m] = sum_t sum_k wA[t][m][k] in[v + off(t)][k];  forward: bf16(relu(.)),
+// backward-data (MASK): bf16(. * 1[mask[v][m] > 0]).  N >= 16.
+template <bool MASK>
+__global__ void __launch_bounds__(kBlk) k_net_l2(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wA,
+                                                 const uint16_t* __restrict__ mask, const int N,
+                                                 uint16_t* __restrict__ out) {
+  __shared__ uint2 tile[kHZ * kHY * kHX * 4];  // 4 x (4 bf16) per voxel
+  const int nbx = N / kBX, nby = N / kBY;
+  const int b = blockIdx.x;
+  const int x0 = (b % nbx) * kBX;
+  const int y0 = ((b / nbx) % nby) * kBY;
+  const int z0 = (b / (nbx * nby)) * kBZ;
+  const int m = N - 1;
+  const uint2* in2 = reinterpret_cast<const uint2*>(in);
+  for (int e = threadIdx.x; e < kHZ * kHY * kHX * 4; e += kBlk) {
+    const int c = e & 3;
+    const int vx = e >> 2;
+    const int hx = vx % kHX, hy = (vx / kHX) % kHY, hz = vx / (kHX * kHY);
+    const size_t g = vox((x0 - 1 + hx) & m, (y0 - 1 + hy) & m, (z0 - 1 + hz) & m, N);
+    tile[e] = in2[g * 4 + c];
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;   // A row (output channel) / B column (voxel)
+  const int kb = lane >> 4;    // k block: input channels 4 kb .. 4 kb + 3
+  bf16x4 wa[kTaps];
+  const uint2* wA2 = reinterpret_cast<const uint2*>(wA);
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) {
+    const uint2 u = wA2[(t * kNC + col) * 4 + kb];
+    wa[t] = *reinterpret_cast<const bf16x4*>(&u);
+  }
+  __syncthreads();
+  for (int tt = wave; tt < kBY * kBZ; tt += kBlk / 64) {
+    const int ty = tt % kBY, tz = tt / kBY;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const int dx = (t % 3) - 1, dy = ((t / 3) % 3) - 1, dz = (t / 9) - 1;
+      const int hidx = ((tz + 1 + dz) * kHY + (ty + 1 + dy)) * kHX + (col + 1 + dx);
+      const uint2 u = tile[hidx * 4 + kb];
+      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&u);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], bv, acc, 0, 0, 0);
+    }
+    // lane holds output channels 4 kb .. 4 kb + 3 of voxel (x0 + col, y0 + ty, z0 + tz)
+    const size_t v = vox(x0 + col, y0 + ty, z0 + tz, N);
+    float o[4];
+    if (MASK) {
+      const uint2 mk = reinterpret_cast<const uint2*>(mask)[v * 4 + kb];
+      const uint16_t mv[4] = {static_cast<uint16_t>(mk.x & 0xFFFF), static_cast<uint16_t>(mk.x >> 16),
+                              static_cast<uint16_t>(mk.y & 0xFFFF), static_cast<uint16_t>(mk.y >> 16)};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = bf2f(mv[r]) > 0.0f ? acc[r] : 0.0f;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = fmaxf(acc[r], 0.0f);
+    }
+    uint2 pk;
+    pk.x = static_cast<uint32_t>(f2bf(o[0])) | (static_cast<uint32_t>(f2bf(o[1])) << 16);
+    pk.y = static_cast<uint32_t>(f2bf(o[2])) | (static_cast<uint32_t>(f2bf(o[3])) << 16);
+    reinterpret_cast<uint2*>(out)[v * 4 + kb] = pk;
+  }
+}
+
+// ---------------------------------------------------------------------------- layer 3 (16 -> 1)
+// y = W3 * a2;  mode 0: y_out[v] = y;  mode 1: u[v] += s y with s = sqrt(ssum / N^3)
+__device__ __forceinline__ void load16(const uint16_t* p, float* f) {
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+  const uint4 a = q[0], b = q[1];
+  const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    f[2 * c] = __uint_as_float(w[c] << 16);
+    f[2 * c + 1] = __uint_as_float(w[c] & 0xFFFF0000u);
+  }
+}
+
+__global__ void __launch_bounds__(kBlk) k_net_l3(const uint16_t* __restrict__ a2, const float* __restrict__ w3q,
+                                                 const int N, const int mode, const double* __restrict__ ssum,
+                                                 float* __restrict__ y) {
+  __shared__ float w[kTaps * kNC];  // [t][ci]
+  for (int e = threadIdx.x; e < kTaps * kNC; e += kBlk) w[e] = w3q[e];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= N) return;
+  float acc = 0.0f;
+#pragma unroll 3
+  for (int t = 0; t < kTaps; ++t) {
+    float a[kNC];
+    load16(a2 + nbr(i, j, k, t, 1, N) * kNC, a);
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) acc = fmaf(w[t * kNC + c], a[c], acc);
+  }
+  const size_t v = vox(i, j, k, N);
+  if (mode == 0) {
+    y[v] = acc;
+  } else {
+    const double nn = static_cast<double>(N) * N * N;
+    const float s = static_cast<float>(sqrt(*ssum / nn));
+    y[v] += s * acc;
+  }
+}
+
+// ---------------------------------------------------------------------------- backward
+// g2[v][c] = bf16(1[a2[v][c] > 0] sum_t W3[c][t] gy[v - off(t)])
+__global__ void __launch_bounds__(kBlk) k_net_l3_bwd(const float* __restrict__ gy, const uint16_t* __restrict__ a2,
+                                                     const float* __restrict__ w3q, const int N,
+                                                     uint16_t* __restrict__ g2) {
+  __shared__ float w[kTaps * kNC];
+  for (int e = threadIdx.x; e < kTaps * kNC; e += kBlk) w[e] = w3q[e];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= N) return;
+  float g[kNC];
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) g[c] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) {
+    const float gv = gy[nbr(i, j, k, t, -1, N)];
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) g[c] = fmaf(w[t * kNC + c], gv, g[c]);
+  }
+  const size_t v = vox(i, j, k, N);
+  float a[kNC];
+  load16(a2 + v * kNC, a);
+  uint32_t p[kNC / 2];
+#pragma unroll
+  for (int c = 0; c < kNC / 2; ++c) {
+    const float lo = a[2 * c] > 0.0f ? g[2 * c] : 0.0f;
+    const float hi = a[2 * c + 1] > 0.0f ? g[2 * c + 1] : 0.0f;
+    p[c] = static_cast<uint32_t>(f2bf(lo)) | (static_cast<uint32_t>(f2bf(hi)) << 16);
+  }
+  uint4* dst = reinterpret_cast<uint4*>(g2 + v * kNC);
+  dst[0] = make_uint4(p[0], p[1], p[2], p[3]);
+  dst[1] = make_uint4(p[4], p[5], p[6], p[7]);
+}
+
+// gin[v] = sum_t sum_c W1[c][t] g1[v - off(t)][c]
+__global__ void __launch_bounds__(kBlk) k_net_gin(const uint16_t* __restrict__ g1, const float* __restrict__ w1q,
+                                                  const int N, float* __restrict__ gin) {
+  __shared__ float w[kTaps * kNC];
+  for (int e = threadIdx.x; e < kTaps * kNC; e += kBlk) w[e] = w1q[e];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y, k = blockIdx.z;
+  if (i >= N) return;
+  float acc = 0.0f;
+#pragma unroll 3
+  for (int t = 0; t < kTaps; ++t) {
+    float g[kNC];
+    load16(g1 + nbr(i, j, k, t, -1, N) * kNC, g);
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) acc = fmaf(w[t * kNC + c], g[c], acc);
+  }
+  gin[vox(i, j, k, N)] = acc;
+}
+
+// Weight gradients of layers 1 and 3 (16 values per tap), one partial per
+// (block, tap):  layer 3: sum_v gy[v] a2[v + off(t)][c];
+//                layer 1: sum_v g1[v][c] x_in[v + off(t)].
+constexpr int kWgChunk = 4096;  // voxels per block
+
+template <int LAYER>
+__global__ void __launch_bounds__(kBlk) k_net_wgrad13(const float* __restrict__ gy, const uint16_t* __restrict__ a2,
+                                                      const uint16_t* __restrict__ g1,
+                                                      const uint16_t* __restrict__ xin, const int N,
+                                                      float* __restrict__ part) {
+  __shared__ float red[kBlk][kNC + 1];
+  const int t = blockIdx.y;
+  const size_t nv = static_cast<size_t>(N) * N * N;
+  const size_t v0 = static_cast<size_t>(blockIdx.x) * kWgChunk;
+  float acc[kNC];
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) acc[c] = 0.0f;
+  for (size_t v = v0 + threadIdx.x; v < v0 + kWgChunk && v < nv; v += kBlk) {
+    const int i = static_cast<int>(v % N);
+    const int j = static_cast<int>((v / N) % N);
+    const int k = static_cast<int>(v / (static_cast<size_t>(N) * N));
+    const size_t u = nbr(i, j, k, t, 1, N);
+    float f[kNC];
+    if (LAYER == 3) {
+      const float g = gy[v];
+      load16(a2 + u * kNC, f);
+#pragma unroll
+      for (int c = 0; c < kNC; ++c) acc[c] = fmaf(g, f[c], acc[c]);
+    } else {
+      const float x = bf2f(xin[u]);
+      load16(g1 + v * kNC, f);
+#pragma unroll
+      for (int c = 0; c < kNC; ++c) acc[c] = fmaf(f[c], x, acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) red[threadIdx.x][c] = acc[c];
+  __syncthreads();
+  for (int s = kBlk / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int c = 0; c < kNC; ++c) red[threadIdx.x][c] += red[threadIdx.x + s][c];
+    __syncthreads();
+  }
+  if (threadIdx.x < kNC) part[(static_cast<size_t>(blockIdx.x) * kTaps + t) * kNC + threadIdx.x] = red[0][threadIdx.x];
+}
+
+// Layer-2 weight gradient on the matrix cores: for each tap,
+// D[o][i] += sum over 16-voxel groups of G^T (16 o x 16 voxels) X_t (16 voxels x 16 i),
+// G = g2, X_t = a1 shifted by the tap.  Each wavefront sums kW2Vox voxels and
+// writes one partial of 27 x 256 values.
+constexpr int kW2Vox = 2048;
+
+__global__ void __launch_bounds__(kBlk) k_net_wgrad2(const uint16_t* __restrict__ g2, const uint16_t* __restrict__ a1,
+                                                     const int N, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * (kBlk / 64) + (threadIdx.x >> 6);
+  const size_t nv = static_cast<size_t>(N) * N * N;
+  const size_t v0 = static_cast<size_t>(wv) * kW2Vox;
+  const int col = lane & 15, kb = lane >> 4;
+  floatx4 acc[kTaps];
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (size_t g = v0; g < v0 + kW2Vox && g < nv; g += 16) {
+    // group of 16 consecutive voxels along x (N is a multiple of 16)
+    const int i0 = static_cast<int>(g % N);
+    const int j = static_cast<int>((g / N) % N);
+    const int k = static_cast<int>(g / (static_cast<size_t>(N) * N));
+    // A[m = o = col][kk = voxel 4 kb + r] = g2[g + 4 kb + r][col]
+    short av[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) av[r] = static_cast<short>(g2[(g + 4 * kb + r) * kNC + col]);
+    const bf16x4 a = {av[0], av[1], av[2], av[3]};
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      // B[kk = voxel 4 kb + r][n = i = col] = a1[(voxel + off(t))][col]
+      short bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[r] = static_cast<short>(a1[nbr(i0 + 4 * kb + r, j, k, t, 1, N) * kNC + col]);
+      const bf16x4 b = {bv[0], bv[1], bv[2], bv[3]};
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // D[o = 4 kb + r][i = col]
+  float* dst = part + static_cast<size_t>(wv) * kTaps * kNC * kNC;
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[(t * kNC + 4 * kb + r) * kNC + col] = acc[t][r];
+}
+
+// gw[base + (o * nin + i) * 27 + t] += sum_p part[p][t][o][i]   (fixed order)
+__global__ void __launch_bounds__(kBlk) k_net_reduce(const float* __restrict__ part, const int np, const int nout,
+                                                     const int nin, float* __restrict__ gw, const int base) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = kTaps * nout * nin;
+  if (e >= per) return;
+  const int t = e / (nout * nin), oi = e % (nout * nin);
+  double s = 0.0;
+  for (int p = 0; p < np; ++p) s += part[static_cast<size_t>(p) * per + e];
+  gw[base + oi * kTaps + t] += static_cast<float>(s);
+}
+
+// ---------------------------------------------------------------------------- weights
+// Flat master layout: W1[co][t] (432), W2[co][ci][t] (6912), W3[ci][t] (432).
+// Kernel layouts: w1q[t][co], w3q[t][ci] (BF16-rounded values as FP32),
+// w2f[t][co][ci] (forward A operand), w2b[t'][ci][co] with t' the mirrored tap
+// (backward-data A operand).
+__global__ void __launch_bounds__(kBlk) k_net_pack(const float* __restrict__ w, float* __restrict__ w1q,
+                                                   uint16_t* __restrict__ w2f, uint16_t* __restrict__ w2b,
+                                                   float* __restrict__ w3q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < 432) {
+    const int co = e / kTaps, t = e % kTaps;
+    w1q[t * kNC + co] = bf2f(f2bf(w[e]));
+  } else if (e < 432 + 6912) {
+    const int f = e - 432;
+    const int co = f / (kNC * kTaps), ci = (f / kTaps) % kNC, t = f % kTaps;
+    const uint16_t h = f2bf(w[e]);
+    w2f[(t * kNC + co) * kNC + ci] = h;
+    w2b[((kTaps - 1 - t) * kNC + ci) * kNC + co] = h;
+  } else if (e < 7776) {
+    const int f = e - 432 - 6912;
+    const int ci = f / kTaps, t = f % kTaps;
+    w3q[t * kNC + ci] = bf2f(f2bf(w[e]));
+  }
+}
+
+// Adam (Kingma and Ba 2015) on the FP32 master weights.
+__global__ void __launch_bounds__(kBlk) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v2,
+                                               const float* __restrict__ g, const int n, const float lr,
+                                               const float b1, const float b2, const float eps, const float c1,
+                                               const float c2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const float gg = g[e];
+  const float mm = b1 * m[e] + (1.0f - b1) * gg;
+  const float vv = b2 * v2[e] + (1.0f - b2) * gg * gg;
+  m[e] = mm;
+  v2[e] = vv;
+  w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+inline dim3 vgrid(int N) { return dim3((N + kBlk - 1) / kBlk, N, N); }
+
+ClassTab64 ctab(const double* t, int q) {
+  ClassTab64 c{};
+  for (int i = 0; i < q * q * q; ++i) c.v[i] = t[i];
+  return c;
+}
+
+}  // namespace
+
+int64_t net_cache_bytes(int N) {
+  const int64_t nv = static_cast<int64_t>(N) * N * N;
+  const int64_t a = (nv * 2 + 255) / 256 * 256;
+  return a + 2 * nv * kNC * 2;
+}
+
+int64_t net_partial_floats(int N) {
+  const int64_t nv = static_cast<int64_t>(N) * N * N;
+  const int64_t waves = (nv + kW2Vox - 1) / kW2Vox;
+  const int64_t w2 = ((waves + 3) / 4) * 4 * kTaps * kNC * kNC;
+  const int64_t w13 = ((nv + kWgChunk - 1) / kWgChunk) * kTaps * kNC;
+  return w2 > w13 ? w2 : w13;
+}
+
+hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_net_pack, dim3((7776 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, w, d.w1q, d.w2f, d.w2b, d.w3q);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part, int N,
+                            void* cache, hipStream_t s) {
+  uint16_t* xin = static_cast<uint16_t*>(cache);
+  if (dinv) {
+    const ClassTab64 c = ctab(dinv, q);
+    hipLaunchKernelGGL(k_net_sqsum, dim3(1, N, N), dim3(kBlk), 0, s, r, c, q, N, part);
+    const hipError_t e = launch_sum_partials(part, static_cast<int64_t>(N) * N, const_cast<double*>(ssum), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_net_in, vgrid(N), dim3(kBlk), 0, s, r, c, q, 1, ssum, N, xin);
+  } else {
+    const ClassTab64 c{};
+    hipLaunchKernelGGL(k_net_in, vgrid(N), dim3(kBlk), 0, s, r, c, q, 0, ssum, N, xin);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, const double* ssum, float* y,
+                              hipStream_t s) {
+  if (N < 16 || (N & (N - 1)) != 0) return hipErrorInvalidValue;
+  const int64_t nv = static_cast<int64_t>(N) * N * N;
+  uint16_t* xin = static_cast<uint16_t*>(cache);
+  uint16_t* a1 = reinterpret_cast<uint16_t*>(static_cast<char*>(cache) + (nv * 2 + 255) / 256 * 256);
+  uint16_t* a2 = a1 + nv * kNC;
+  hipLaunchKernelGGL(k_net_l1, vgrid(N), dim3(kBlk), 0, s, xin, d.w1q, N, a1);
+  const int nb = (N / kBX) * (N / kBY) * (N / kBZ);
+  hipLaunchKernelGGL(k_net_l2<false>, dim3(nb), dim3(kBlk), 0, s, a1, d.w2f, nullptr, N, a2);
+  hipLaunchKernelGGL(k_net_l3, vgrid(N), dim3(kBlk), 0, s, a2, d.w3q, N, mode, ssum, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_backward(const NetDev& d, int N, const void* cache, const float* gy, void* g1g2, float* part,
+                               float* gw, float* gin, hipStream_t s) {
+  if (N < 16 || (N & (N - 1)) != 0) return hipErrorInvalidValue;
+  const int64_t nv = static_cast<int64_t>(N) * N * N;
+  const uint16_t* xin = static_cast<const uint16_t*>(cache);
+  const uint16_t* a1 = reinterpret_cast<const uint16_t*>(static_cast<const char*>(cache) + (nv * 2 + 255) / 256 * 256);
+  const uint16_t* a2 = a1 + nv * kNC;
+  uint16_t* g2 = static_cast<uint16_t*>(g1g2);
+  uint16_t* g1 = g2 + nv * kNC;
+  hipLaunchKernelGGL(k_net_l3_bwd, vgrid(N), dim3(kBlk), 0, s, gy, a2, d.w3q, N, g2);
+  const int nb = (N / kBX) * (N / kBY) * (N / kBZ);
+  hipLaunchKernelGGL(k_net_l2<true>, dim3(nb), dim3(kBlk), 0, s, g2, d.w2b, a1, N, g1);
+  // layer 3 weights
+  const int nch = static_cast<int>((nv + kWgChunk - 1) / kWgChunk);
+  hipLaunchKernelGGL(k_net_wgrad13<3>, dim3(nch, kTaps), dim3(kBlk), 0, s, gy, a2, nullptr, nullptr, N, part);
+  hipLaunchKernelGGL(k_net_reduce, dim3((kTaps * kNC + kBlk - 1) / kBlk), dim3(kBlk), 0, s, part, nch, 1, kNC, gw,
+                     432 + 6912);
+  // layer 2 weights (MFMA)
+  const int nw = static_cast<int>((nv + kW2Vox - 1) / kW2Vox);
+  const int nwb = (nw + 3) / 4;
+  hipLaunchKernelGGL(k_net_wgrad2, dim3(nwb), dim3(kBlk), 0, s, g2, a1, N, part);
+  hipLaunchKernelGGL(k_net_reduce, dim3((kTaps * kNC * kNC + kBlk - 1) / kBlk), dim3(kBlk), 0, s, part, nwb * 4,
+                     kNC, kNC, gw, 432);
+  // layer 1 weights
+  hipLaunchKernelGGL(k_net_wgrad13<1>, dim3(nch, kTaps), dim3(kBlk), 0, s, nullptr, nullptr, g1, xin, N, part);
+  hipLaunchKernelGGL(k_net_reduce, dim3((kTaps * kNC + kBlk - 1) / kBlk), dim3(kBlk), 0, s, part, nch, kNC, 1, gw,
+                     0);
+  if (gin) hipLaunchKernelGGL(k_net_gin, vgrid(N), dim3(kBlk), 0, s, g1, d.w1q, N, gin);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(NetDev& d, const float* gw, float lr, int64_t step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.0f - powf(b1, static_cast<float>(step));
+  const float c2 = 1.0f - powf(b2, static_cast<float>(step));
+  hipLaunchKernelGGL(k_adam, dim3((7776 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, d.w, d.m, d.v, gw, 7776, lr, b1, b2,
+                     eps, c1, c2);
+  return launch_net_pack(d.w, d, s);
+}
+
+}  // namespace gmg

@@ -278,6 +278,11 @@ hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const vo
   return hipGetLastError();
 }
 
+hipError_t launch_sum_partials(const double* part, int64_t count, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, static_cast<int>(count), dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_axpy2(bool fp32, int64_t n, const double* sc, int inum, int iden, void* u, const void* p, void* r,
                         const void* w, hipStream_t s) {
   const int g = grid_for(n);

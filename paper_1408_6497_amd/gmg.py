@@ -24,7 +24,11 @@ EXPORTS = [
     "gmg_diagonal", "gmg_apply", "gmg_mass", "gmg_smooth", "gmg_restrict", "gmg_prolong",
     "gmg_coarse_solve", "gmg_vcycle", "gmg_rhs", "gmg_solve", "gmg_solve_rhs", "gmg_dot",
     "gmg_timing_get", "gmg_timing_reset", "gmg_status_string", "gmg_last_error",
+    "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
+    "gmg_net_backward", "gmg_adam_step", "gmg_net_correction",
 ]
+
+NET_WEIGHTS = 7776
 
 
 class GmgMesh(ctypes.Structure):
@@ -40,7 +44,7 @@ class GmgOptions(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("vcycle_prec", ctypes.c_int32), ("krylov", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("lambda_override", ctypes.c_double),
         ("timing", ctypes.c_int32), ("no_graphs", ctypes.c_int32),
-        ("ir_mode", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
+        ("ir_mode", ctypes.c_int32), ("use_learned", ctypes.c_int32),
     ]
 
 
@@ -94,6 +98,14 @@ def load():
         "gmg_dot": [P, I32, I64, P, P, ctypes.POINTER(D)],
         "gmg_timing_get": [P, I32, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D)],
         "gmg_timing_reset": [P],
+        "gmg_net_set_weights": [P, I32, P, I64],
+        "gmg_set_learned": [P, I32, P, I64],
+        "gmg_net_get_weights": [P, I32, P, I64],
+        "gmg_net_cache_bytes": [P, I32, ctypes.POINTER(I64)],
+        "gmg_net_forward": [P, I32, P, P, P],
+        "gmg_net_backward": [P, I32, P, P, P, P],
+        "gmg_adam_step": [P, I32, P, ctypes.c_float, I64],
+        "gmg_net_correction": [P, I32, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -259,6 +271,54 @@ class Context:
 
     def timing_reset(self):
         self._check(self.lib.gmg_timing_reset(self.h))
+
+    # -- learned smoother (depth 0 = finest level)
+    def net_set_weights(self, depth, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != NET_WEIGHTS:
+            raise ValueError("expected 7776 weights")
+        self._check(self.lib.gmg_net_set_weights(self.h, depth, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+    def set_learned(self, depth, w_bf16):
+        import numpy as np
+        w = np.ascontiguousarray(w_bf16, dtype=np.uint16)
+        if w.size != NET_WEIGHTS:
+            raise ValueError("expected 7776 weights")
+        self._check(self.lib.gmg_set_learned(self.h, depth, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+    def net_get_weights(self, depth):
+        import numpy as np
+        w = np.zeros(NET_WEIGHTS, dtype=np.float32)
+        self._check(self.lib.gmg_net_get_weights(self.h, depth, w.ctypes.data_as(ctypes.c_void_p), w.size))
+        return w
+
+    def net_cache(self, depth):
+        """A device byte buffer large enough for one forward cache at this depth."""
+        v = ctypes.c_int64()
+        self._check(self.lib.gmg_net_cache_bytes(self.h, depth, ctypes.byref(v)))
+        return self._torch.empty(v.value, dtype=self._torch.uint8, device="cuda")
+
+    def net_forward(self, depth, x, y, cache):
+        lv = self.levels - 1 - depth
+        self._check(self.lib.gmg_net_forward(self.h, depth, self._vec(x, lv, GMG_FP32), self._vec(y, lv, GMG_FP32),
+                                             _ptr(cache)))
+
+    def net_backward(self, depth, gy, cache, gw, gin=None):
+        lv = self.levels - 1 - depth
+        if gw.numel() != NET_WEIGHTS or gw.dtype != self._torch.float32 or not gw.is_cuda:
+            raise ValueError("gw must be 7776 FP32 values on the GPU")
+        gin_p = self._vec(gin, lv, GMG_FP32) if gin is not None else None
+        self._check(self.lib.gmg_net_backward(self.h, depth, self._vec(gy, lv, GMG_FP32), _ptr(cache), _ptr(gw),
+                                              gin_p))
+
+    def adam_step(self, depth, gw, lr, step):
+        self._check(self.lib.gmg_adam_step(self.h, depth, _ptr(gw), ctypes.c_float(lr), step))
+
+    def net_correction(self, level, r, e):
+        level = self._lvl(level)
+        self._check(self.lib.gmg_net_correction(self.h, level, self._vec(r, level, GMG_FP32),
+                                                self._vec(e, level, GMG_FP32)))
 
     def solve(self, f, u, rtol, raise_on_noconv=True):
         lv = self.levels - 1

@@ -1,0 +1,131 @@
+"""Learned smoother on the GPU vs the FP64 oracle with BF16 emulation.
+
+Tolerances (reading of the learned-smoother definition): forward outputs 1e-2
+relative l2, gradients 1e-3 relative l2 -- the GPU accumulates in FP32 in a
+different order, and BF16 rounding of an activation or gradient can flip where
+the FP32 and FP64 sums straddle a rounding boundary.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import mean_free_normal, rel_l2, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(q, n, **kw):
+    torch_cuda()
+    from paper_1408_6497_amd import Context
+    return Context(q, n, 0, **kw)
+
+
+def _weights(seed, scale=0.25):
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(7776) * scale
+    return w.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("q,n", [(2, 8), (1, 16), (2, 16)])
+def test_net_forward_backward_parity(q, n):
+    torch = torch_cuda()
+    from oracle import learned
+    ctx = _ctx(q, n)
+    N = q * n
+    w = _weights(1)
+    ctx.net_set_weights(0, w)
+    x = np.random.default_rng(2).standard_normal(N ** 3)
+    xd = to_dev(x, torch.float32)
+    yd = torch.empty_like(xd)
+    cache = ctx.net_cache(0)
+    ctx.net_forward(0, xd, yd, cache)
+    y_ref, cache_ref = learned.forward(w, to_host(xd).reshape(N, N, N))
+    err_y = rel_l2(to_host(yd), y_ref.ravel())
+    gy = np.random.default_rng(3).standard_normal(N ** 3)
+    gyd = to_dev(gy, torch.float32)
+    gw = torch.zeros(7776, dtype=torch.float32, device="cuda")
+    gin = torch.empty_like(xd)
+    ctx.net_backward(0, gyd, cache, gw, gin)
+    torch.cuda.synchronize()
+    g_ref, gin_ref = learned.backward(cache_ref, to_host(gyd).reshape(N, N, N), want_gin=True)
+    err_w = rel_l2(to_host(gw), g_ref)
+    err_in = rel_l2(to_host(gin), gin_ref.ravel())
+    parts = [rel_l2(to_host(gw)[a:b], g_ref[a:b]) for a, b in ((0, 432), (432, 7344), (7344, 7776))]
+    print(f"[net] q={q} n={n} fwd={err_y:.2e} gw={err_w:.2e} parts={parts} gin={err_in:.2e}", flush=True)
+    assert err_y <= 1e-2
+    assert err_w <= 1e-3 and max(parts) <= 1e-3
+    assert err_in <= 1e-3
+
+
+def test_net_correction_parity_and_jacobi_special_case():
+    torch = torch_cuda()
+    from oracle import learned, operator as op
+    q, n = 2, 8
+    ctx = _ctx(q, n)
+    N = q * n
+    A = op.assemble(q, n)
+    dinv = (1.0 / A.diagonal()).reshape(N, N, N)
+    r = mean_free_normal(N ** 3, 4)
+    rd = to_dev(r, torch.float32)
+    e = torch.empty_like(rd)
+    # identity weights: the learned correction is damped Jacobi (up to BF16 input rounding)
+    omega = 0.625  # a BF16 value
+    ctx.net_set_weights(0, learned.jacobi_weights(omega))
+    ctx.net_correction(-1, rd, e)
+    torch.cuda.synchronize()
+    jac = omega * dinv.ravel() * to_host(rd)
+    assert np.max(np.abs(to_host(e) - jac)) <= 2 ** -8 * np.max(np.abs(jac))
+    ref, _ = learned.correction(learned.jacobi_weights(omega), to_host(rd).reshape(N, N, N), dinv)
+    assert rel_l2(to_host(e), ref.ravel()) <= 1e-5
+    # random weights
+    w = _weights(5)
+    ctx.net_set_weights(0, w)
+    ctx.net_correction(-1, rd, e)
+    torch.cuda.synchronize()
+    ref, _ = learned.correction(w, to_host(rd).reshape(N, N, N), dinv)
+    assert rel_l2(to_host(e), ref.ravel()) <= 1e-2
+
+
+def test_adam_step_matches_definition():
+    torch = torch_cuda()
+    ctx = _ctx(2, 8)
+    w0 = _weights(7).astype(np.float32)
+    ctx.net_set_weights(0, w0)
+    rng = np.random.default_rng(8)
+    m = np.zeros(7776, np.float32)
+    v = np.zeros(7776, np.float32)
+    w = w0.copy()
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for step in (1, 2, 3):
+        g = rng.standard_normal(7776).astype(np.float32)
+        ctx.adam_step(0, torch.from_numpy(g).cuda(), lr, step)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        w = w - lr * (m / (1 - b1 ** step)) / (np.sqrt(v / (1 - b2 ** step)) + eps)
+    got = ctx.net_get_weights(0)
+    assert np.max(np.abs(got - w)) <= 1e-6 * np.max(np.abs(w))
+
+
+def test_learned_solve_converges_and_fallback_fires():
+    """A learned solve reaches the tolerance; adversarial weights trigger the fallback every cycle."""
+    torch = torch_cuda()
+    from oracle import learned, multigrid as mg, operator as op
+    from workloads import gaussian_params, gaussian_source
+    q, n = 2, 16
+    f = None
+    for name, w in (("jacobi", learned.jacobi_weights(0.625)), ("adversarial", -50.0 * learned.jacobi_weights(1.0))):
+        ctx = _ctx(q, n, seed=4, use_learned=1)
+        ctx.net_set_weights(0, w)
+        if f is None:
+            f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(2, 32, 0.02, 0.1)).cuda()
+        u = torch.empty_like(f)
+        info = ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        b = mg.rhs(q, n, to_host(f))
+        A = op.assemble(q, n)
+        res = b - A @ to_host(u)
+        res -= res.mean()
+        rel = np.linalg.norm(res) / np.linalg.norm(b)
+        print(f"[learned-solve] {name}: iters={info.inner_iters} fallbacks={info.fallbacks} rel={rel:.2e}", flush=True)
+        assert rel <= 1e-8 * 1.001
+        if name == "adversarial":
+            assert info.fallbacks >= info.inner_iters - 1 and info.fallbacks >= 1
