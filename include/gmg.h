@@ -100,6 +100,9 @@ typedef struct {
   int32_t use_learned;      /* != 0: learned smoother in every smoothing phase of levels with
                                at least 16 lattice nodes per direction (forces FP32
                                V-cycles and flexible CG); see gmg_set_learned            */
+  int32_t learned_depths;   /* > 0: only depths 0 .. learned_depths-1 use a net; the other
+                               levels keep the Chebyshev smoother (0: every level)       */
+  int32_t reserved_opt;
 } gmg_options;
 
 typedef struct {
@@ -152,6 +155,9 @@ gmg_status gmg_coarse_solve(gmg_ctx* ctx, gmg_prec prec, const void* b_dev, void
 /* z = V r: one V-cycle (Algorithm 2.1) on the finest level, zero initial guess. */
 gmg_status gmg_vcycle(gmg_ctx* ctx, gmg_prec prec, const void* r_dev, void* z_dev);
 
+/* r = b - A_level u (vectors of type prec). */
+gmg_status gmg_residual(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, const void* u_dev, void* r_dev);
+
 /* b = M f - mean(M f): load vector of nodal source values f on the finest level. */
 gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev);
 
@@ -198,6 +204,15 @@ gmg_status gmg_net_backward(gmg_ctx* ctx, int32_t depth, const float* gy_dev, co
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the FP32
  * master weights of one depth, then re-rounds the BF16 copies. */
 gmg_status gmg_adam_step(gmg_ctx* ctx, int32_t depth, const float* gw_dev, float lr, int64_t step);
+/* Training loss of one pair on the depth's level (FP32 device vectors), with
+ * e~ = s N(D^-1 r / s), returned in *loss_host:
+ *   kind 0 (energy)    ||e - e~||_A^2 / ||e||_A^2 for e = A^+ r, evaluated as
+ *                      (e - e~)^T (r - A e~) / (e^T r);
+ *   kind 1 (residual)  ||r - A e~||_2^2 / ||r||_2^2 (e_dev unused, may be NULL).
+ * If gw_dev is not NULL, gw_dev += scale * d loss / dw (backward through A and the
+ * net).  The level's FP32 work vectors are overwritten. */
+gmg_status gmg_net_loss_grad(gmg_ctx* ctx, int32_t depth, int32_t kind, const float* r_dev, const float* e_dev,
+                             void* cache_dev, float* gw_dev, float scale, double* loss_host);
 /* e = s N(D^-1 r / s) on one level (FP32 device vectors): the learned correction. */
 gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, float* e_dev);
 
@@ -217,6 +232,19 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
 gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
                           double* seconds);
 gmg_status gmg_timing_reset(gmg_ctx* ctx);
+
+/* Convergence history of the last gmg_solve / gmg_solve_rhs (Section 3 reports
+ * iteration counts; this keeps every iterate).  Host call, no synchronization.
+ *   kind 0: the Krylov residual norm ||r_k||_2 at every iteration, starting with
+ *           the initial one, in the order the Krylov loops ran (with nested
+ *           refinement the inner FP32 solves follow each other).
+ *   kind 1: one triple per learned-cycle test: the learned cycle's contraction
+ *           rho_L = ||r - A z_L|| / ||r||, the reference contraction it was compared
+ *           with, and the plain cycle's contraction on the same r when the learned
+ *           cycle was rejected (NaN when it was kept).
+ * *count receives the number of values recorded; min(cap, *count) of them are
+ * copied to out (host memory owned by the caller; may be NULL when cap is 0). */
+gmg_status gmg_history(gmg_ctx* ctx, int32_t kind, double* out_host, int64_t cap, int64_t* count);
 
 const char* gmg_status_string(gmg_status s);
 const char* gmg_last_error(const gmg_ctx* ctx);

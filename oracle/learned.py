@@ -13,15 +13,18 @@ reading recorded for this build:
            accumulation is exact here (FP64), FP32 on the GPU;
   backward g2 = bf16(1[a2 > 0] (W3^T * gy)), g1 = bf16(1[a1 > 0] (W2^T * g2)),
            weight gradients accumulated over every voxel;
-  loss     ||e - e~||_A^2 / ||e||_A^2 with e = A^+ r.
+  loss     energy:   ||e - e~||_A^2 / ||e||_A^2 with e = A^+ r;
+           residual: ||r - A e~||_2^2 / ||r||_2^2, the squared contraction of
+           the residual in the norm the per-cycle fallback measures.
 
 Lattice arrays are (N, N, N) indexed [z, y, x]; hidden activations are
 (N, N, N, C) channels-last.  Tap t = (dz+1)*9 + (dy+1)*3 + (dx+1); a
 convolution is a cross-correlation: out(v) = sum_t W[.., t] in(v + off(t)).
 
 Pins (tests/test_oracle_learned.py): central finite differences of the FP64
-network; identity weights reduce the learned correction to damped Jacobi;
-zero weights give a zero correction.
+network and of both losses through the network; identity weights reduce the
+learned correction to damped Jacobi; zero weights give a zero correction; the
+losses vanish at the exact correction and equal 1 at the zero correction.
 """
 import numpy as np
 
@@ -122,6 +125,41 @@ def loss(A, e, e_tilde):
     """||e - e~||_A^2 / ||e||_A^2 (A a matrix acting on flat vectors)."""
     d = (e - e_tilde).ravel()
     return float(d @ (A @ d)) / float(e.ravel() @ (A @ e.ravel()))
+
+
+def residual_loss(A, r, e_tilde):
+    """||r - A e~||_2^2 / ||r||_2^2 (A a matrix acting on flat vectors)."""
+    d = r.ravel() - A @ e_tilde.ravel()
+    return float(d @ d) / float(r.ravel() @ r.ravel())
+
+
+def loss_and_gradient(w, A, dinv, r, e=None, kind="energy", emulate_bf16=True):
+    """Loss of one pair and its gradient with respect to the flat weights.
+
+    e~ = s y with y = N(D^-1 r / s); s depends on r alone, so dL/dy = s dL/de~ with
+      energy    dL/de~ = -2 A (e - e~) / ||e||_A^2
+      residual  dL/de~ = -2 A (r - A e~) / ||r||_2^2
+    and dL/dw is the network's backward pass applied to dL/dy.  r, e, dinv are
+    (N, N, N) lattices; A acts on flat vectors."""
+    t = dinv * r
+    s = np.sqrt(np.mean(t * t))
+    y, cache = forward(w, t / s, emulate_bf16)
+    et = (s * y).ravel()
+    if kind == "energy":
+        ev = e.ravel()
+        diff = ev - et
+        Ae = A @ ev
+        val = float(diff @ (A @ diff)) / float(ev @ Ae)
+        g_et = -2.0 * (A @ diff) / float(ev @ Ae)
+    elif kind == "residual":
+        d = r.ravel() - A @ et
+        rr = float(r.ravel() @ r.ravel())
+        val = float(d @ d) / rr
+        g_et = -2.0 * (A.T @ d) / rr
+    else:
+        raise ValueError(kind)
+    g, _ = backward(cache, (s * g_et).reshape(y.shape))
+    return val, g
 
 
 def jacobi_weights(omega):

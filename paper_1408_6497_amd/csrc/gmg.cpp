@@ -40,6 +40,9 @@ enum : int {
   S_TMP = 7,
   S_LRES = 8,   // ||r - A z||^2 of a cycle under test
   S_LRR = 9,    // ||r||^2 of that cycle's input
+  S_ER = 10,    // e^T r        (training loss)
+  S_ED = 11,    // e^T (r - A e~)
+  S_TD = 12,    // e~^T (r - A e~)
   S_SSUM = 16,  // + level: sum of (D^-1 r)^2 of the learned correction on that level
 };
 
@@ -102,6 +105,8 @@ struct gmg_ctx {
   int64_t npart_floats = 0;
   double rho_plain = -1.0;        // most recent contraction of a plain FP32 cycle
   int64_t fallbacks = 0;
+  std::vector<double> hist_res;   // last solve: Krylov residual norms, one per iteration
+  std::vector<double> hist_cyc;   // last solve: (rho_learned, rho_reference, rho_plain) per cycle
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_all;
   std::vector<Pending> pending;
@@ -337,8 +342,10 @@ int net_for_depth(const gmg_ctx* c, int d) {
 }
 
 bool learned_on_level(const gmg_ctx* c, int l, int pi) {
+  const int d = c->L - 1 - l;
+  if (c->opt.learned_depths > 0 && d >= c->opt.learned_depths) return false;
   return c->opt.use_learned && !c->suppress_learned && pi == 1 && l > 0 && c->lv[l].N >= 16 &&
-         net_for_depth(c, c->L - 1 - l) >= 0;
+         net_for_depth(c, d) >= 0;
 }
 
 gmg_status ensure_lcache(gmg_ctx* c, int l) {
@@ -506,12 +513,15 @@ gmg_status precondition(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
   STCHK(graph_run(c, base, [&] { return test_cycle(c, pi, r, false); }));
   STCHK(read_scalars(c, hs, kNumScal));
   const double rho_l = std::sqrt(hs[S_LRES] / hs[S_LRR]);
+  const double rho_ref = c->rho_plain;
+  double rho_p = std::nan("");
   if (!(rho_l <= c->rho_plain)) {
     ++c->fallbacks;
     STCHK(graph_run(c, base + 1, [&] { return test_cycle(c, pi, r, true); }));
     STCHK(read_scalars(c, hs, kNumScal));
-    c->rho_plain = std::sqrt(hs[S_LRES] / hs[S_LRR]);
+    c->rho_plain = rho_p = std::sqrt(hs[S_LRES] / hs[S_LRR]);
   }
+  c->hist_cyc.insert(c->hist_cyc.end(), {rho_l, rho_ref, rho_p});
   if (pi == 0) HIPCHK(c, launch_cast_f2d(n, static_cast<const float*>(c->kz[1]), static_cast<double*>(z), c->stream));
   else if (z != c->kz[1]) HIPCHK(c, launch_copy(true, n, c->kz[1], z, c->stream));
   return GMG_OK;
@@ -603,6 +613,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
   STCHK(read_scalars(c, hs, kNumScal));
   double rr = hs[S_RR];
+  c->hist_res.push_back(std::sqrt(rr));
   bool have_dir = false;
   int it = 0;
   while (true) {
@@ -635,6 +646,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
     STCHK(read_scalars(c, hs, kNumScal));
     rr = hs[S_RR];
+    c->hist_res.push_back(std::sqrt(rr));
     ++it;
     if (!finite_pos(hs[S_PW])) {
       *iters = it;
@@ -926,6 +938,8 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   inf.t_setup = c->t_setup;
   STCHK(prepare_learned(c));
   c->fallbacks = 0;
+  c->hist_res.clear();
+  c->hist_cyc.clear();
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -1042,6 +1056,14 @@ gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec pr
   const int s = tslot(level, kind, pidx(prec));
   *launches = ctx->tcount[s];
   *seconds = ctx->tsec[s];
+  return GMG_OK;
+}
+
+gmg_status gmg_history(gmg_ctx* ctx, int32_t kind, double* out, int64_t cap, int64_t* count) {
+  if (!ctx || !count || (kind != 0 && kind != 1) || cap < 0 || (cap > 0 && !out)) return GMG_E_ARG;
+  const std::vector<double>& h = kind == 0 ? ctx->hist_res : ctx->hist_cyc;
+  *count = static_cast<int64_t>(h.size());
+  std::copy(h.begin(), h.begin() + std::min<int64_t>(cap, *count), out);
   return GMG_OK;
 }
 
@@ -1182,6 +1204,69 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
                                  ctx->lcache[level], ctx->stream));
     HIPCHK(ctx, launch_net_forward(ctx->nets[d], L.N, ctx->lcache[level], 1, ctx->scal + S_SSUM + level, e_dev,
                                    ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_residual(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, const void* u_dev,
+                        void* r_dev) {
+  if (!ctx || !b_dev || !u_dev || !r_dev || u_dev == r_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Residual, u_dev, r_dev, b_dev, nullptr, 0, 0); });
+}
+
+gmg_status gmg_net_loss_grad(gmg_ctx* ctx, int32_t depth, int32_t kind, const float* r_dev, const float* e_dev,
+                             void* cache_dev, float* gw_dev, float scale, double* loss_host) {
+  if (!r_dev || !cache_dev || !loss_host || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
+    return GMG_E_ARG;
+  if (kind != 0 && kind != 1) return GMG_E_ARG;
+  if (kind == 0 && !e_dev) return GMG_E_ARG;
+  const int l = ctx->L - 1 - depth;
+  STCHK(ensure_prec(ctx, 1));
+  const int N = ctx->lv[l].N;
+  const int64_t nv = ctx->lv[l].size;
+  if (gw_dev) {
+    if (ctx->g1g2_bytes < nv * 64) {
+      STCHK(dalloc(ctx, &ctx->g1g2, static_cast<size_t>(nv * 64)));
+      ctx->g1g2_bytes = nv * 64;
+    }
+    if (ctx->npart_floats < net_partial_floats(N)) {
+      STCHK(dalloc(ctx, reinterpret_cast<void**>(&ctx->npart), sizeof(float) * net_partial_floats(N)));
+      ctx->npart_floats = net_partial_floats(N);
+    }
+  }
+  return scoped(ctx, [&] {
+    Level& L = ctx->lv[l];
+    const hipStream_t s = ctx->stream;
+    float* y = static_cast<float*>(L.u[1]);
+    float* et = static_cast<float*>(L.b[1]);
+    float* d = static_cast<float*>(L.xp[1]);
+    double* ssum = ctx->scal + S_SSUM + l;
+    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ssum, ctx->part, N, cache_dev, s));
+    HIPCHK(ctx, launch_net_forward(ctx->nets[depth], N, cache_dev, 0, nullptr, y, s));
+    HIPCHK(ctx, launch_net_scale(y, ssum, nv, et, s));
+    STCHK(apply_op(ctx, l, 1, Epi::Residual, et, d, r_dev, nullptr, 0, 0));  // d = r - A e~
+    const float* gsrc = d;
+    if (kind == 0) {
+      // A e = r: ||e - e~||_A^2 = (e - e~)^T d and ||e||_A^2 = e^T r; dL/de~ = -2 d / e^T r
+      HIPCHK(ctx, launch_dot(true, nv, e_dev, r_dev, ctx->part, ctx->scal + S_ER, s));
+      HIPCHK(ctx, launch_dot(true, nv, e_dev, d, ctx->part, ctx->scal + S_ED, s));
+      HIPCHK(ctx, launch_dot(true, nv, et, d, ctx->part, ctx->scal + S_TD, s));
+    } else {
+      // ||d||^2 / ||r||^2; dL/de~ = -2 A d / r^T r (A e~ no longer needed: reuse its buffer)
+      HIPCHK(ctx, launch_dot(true, nv, r_dev, r_dev, ctx->part, ctx->scal + S_ER, s));
+      HIPCHK(ctx, launch_dot(true, nv, d, d, ctx->part, ctx->scal + S_ED, s));
+      if (gw_dev) {
+        STCHK(apply_op(ctx, l, 1, Epi::Apply, d, et, nullptr, nullptr, 0, 0));
+        gsrc = et;
+      }
+    }
+    if (gw_dev) {
+      HIPCHK(ctx, launch_net_loss_gy(gsrc, ssum, ctx->scal + S_ER, static_cast<double>(scale), nv, y, s));
+      HIPCHK(ctx, launch_net_backward(ctx->nets[depth], N, cache_dev, y, ctx->g1g2, ctx->npart, gw_dev, nullptr, s));
+    }
+    double hs[kNumScal];
+    STCHK(read_scalars(ctx, hs, kNumScal));
+    *loss_host = kind == 0 ? (hs[S_ED] - hs[S_TD]) / hs[S_ER] : hs[S_ED] / hs[S_ER];
     return GMG_OK;
   });
 }

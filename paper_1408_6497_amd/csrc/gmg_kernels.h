@@ -143,6 +143,10 @@ hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, con
 hipError_t launch_net_backward(const NetDev& d, int N, const void* cache, const float* gy, void* g1g2, float* part,
                                float* gw, float* gin, hipStream_t s);
 hipError_t launch_adam(NetDev& d, const float* gw, float lr, int64_t step, hipStream_t s);
+// et = s y, s = sqrt(*ssum / n);   gy = -2 s scale d / (*er)
+hipError_t launch_net_scale(const float* y, const double* ssum, int64_t n, float* et, hipStream_t s);
+hipError_t launch_net_loss_gy(const float* d, const double* ssum, const double* er, double scale, int64_t n, float* gy,
+                              hipStream_t s);
 
 // Coarsest solve: x = Ainv (b - mean(b)), Ainv dense symmetric N0 x N0 (FP64),
 // b and x of the kernel precision, arithmetic in FP64.

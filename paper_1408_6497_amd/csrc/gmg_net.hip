@@ -19,6 +19,8 @@
 // from an LDS brick with a one-voxel halo), accumulating 16 output channels x
 // 16 voxels over the 27 taps.  The same kernel does the backward-data pass with
 // the flipped, transposed weights and the ReLU mask of the forward pass.
+#include <algorithm>
+
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -429,6 +431,27 @@ __global__ void __launch_bounds__(kBlk) k_adam(float* __restrict__ w, float* __r
   w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
+// et = s y with s = sqrt(ssum / N^3)
+__global__ void __launch_bounds__(kBlk) k_scale_s(const float* __restrict__ y, const double* __restrict__ ssum,
+                                                  const int64_t n, float* __restrict__ et) {
+  const float s = static_cast<float>(sqrt(*ssum / static_cast<double>(n)));
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    et[i] = s * y[i];
+}
+
+// gy = coef d with coef = -2 s scale / (e^T r): the gradient of
+// ||e - s y||_A^2 / ||e||_A^2 with respect to y, given d = r - A s y and A e = r.
+__global__ void __launch_bounds__(kBlk) k_loss_gy(const float* __restrict__ d, const double* __restrict__ ssum,
+                                                  const double* __restrict__ er, const double scale, const int64_t n,
+                                                  float* __restrict__ gy) {
+  const double s = sqrt(*ssum / static_cast<double>(n));
+  const float coef = static_cast<float>(-2.0 * s * scale / *er);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    gy[i] = coef * d[i];
+}
+
 inline dim3 vgrid(int N) { return dim3((N + kBlk - 1) / kBlk, N, N); }
 
 ClassTab64 ctab(const double* t, int q) {
@@ -516,6 +539,19 @@ hipError_t launch_net_backward(const NetDev& d, int N, const void* cache, const 
   hipLaunchKernelGGL(k_net_reduce, dim3((kTaps * kNC + kBlk - 1) / kBlk), dim3(kBlk), 0, s, part, nch, kNC, 1, gw,
                      0);
   if (gin) hipLaunchKernelGGL(k_net_gin, vgrid(N), dim3(kBlk), 0, s, g1, d.w1q, N, gin);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_scale(const float* y, const double* ssum, int64_t n, float* et, hipStream_t s) {
+  const int g = static_cast<int>(std::min<int64_t>((n + kBlk * 4 - 1) / (kBlk * 4), 65535));
+  hipLaunchKernelGGL(k_scale_s, dim3(g), dim3(kBlk), 0, s, y, ssum, n, et);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_loss_gy(const float* d, const double* ssum, const double* er, double scale, int64_t n, float* gy,
+                              hipStream_t s) {
+  const int g = static_cast<int>(std::min<int64_t>((n + kBlk * 4 - 1) / (kBlk * 4), 65535));
+  hipLaunchKernelGGL(k_loss_gy, dim3(g), dim3(kBlk), 0, s, d, ssum, er, scale, n, gy);
   return hipGetLastError();
 }
 

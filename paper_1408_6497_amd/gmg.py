@@ -23,12 +23,13 @@ EXPORTS = [
     "gmg_setup", "gmg_destroy", "gmg_num_levels", "gmg_num_dofs", "gmg_dof_coords_1d", "gmg_lambda",
     "gmg_diagonal", "gmg_apply", "gmg_mass", "gmg_smooth", "gmg_restrict", "gmg_prolong",
     "gmg_coarse_solve", "gmg_vcycle", "gmg_rhs", "gmg_solve", "gmg_solve_rhs", "gmg_dot",
-    "gmg_timing_get", "gmg_timing_reset", "gmg_status_string", "gmg_last_error",
+    "gmg_timing_get", "gmg_timing_reset", "gmg_history", "gmg_status_string", "gmg_last_error",
     "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
-    "gmg_net_backward", "gmg_adam_step", "gmg_net_correction",
+    "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
 ]
 
 NET_WEIGHTS = 7776
+LOSS_ENERGY, LOSS_RESIDUAL = 0, 1
 
 
 class GmgMesh(ctypes.Structure):
@@ -45,6 +46,7 @@ class GmgOptions(ctypes.Structure):
         ("inner_rtol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("lambda_override", ctypes.c_double),
         ("timing", ctypes.c_int32), ("no_graphs", ctypes.c_int32),
         ("ir_mode", ctypes.c_int32), ("use_learned", ctypes.c_int32),
+        ("learned_depths", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
     ]
 
 
@@ -98,6 +100,7 @@ def load():
         "gmg_dot": [P, I32, I64, P, P, ctypes.POINTER(D)],
         "gmg_timing_get": [P, I32, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D)],
         "gmg_timing_reset": [P],
+        "gmg_history": [P, I32, P, I64, ctypes.POINTER(I64)],
         "gmg_net_set_weights": [P, I32, P, I64],
         "gmg_set_learned": [P, I32, P, I64],
         "gmg_net_get_weights": [P, I32, P, I64],
@@ -106,6 +109,8 @@ def load():
         "gmg_net_backward": [P, I32, P, P, P, P],
         "gmg_adam_step": [P, I32, P, ctypes.c_float, I64],
         "gmg_net_correction": [P, I32, P, P],
+        "gmg_net_loss_grad": [P, I32, I32, P, P, P, P, ctypes.c_float, ctypes.POINTER(D)],
+        "gmg_residual": [P, I32, I32, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -272,6 +277,17 @@ class Context:
     def timing_reset(self):
         self._check(self.lib.gmg_timing_reset(self.h))
 
+    def history(self, kind=0):
+        """Last solve: kind 0 Krylov residual norms; kind 1 (rho_L, rho_ref, rho_plain) rows."""
+        import numpy as np
+        cnt = ctypes.c_int64()
+        self._check(self.lib.gmg_history(self.h, kind, None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.float64)
+        if cnt.value:
+            self._check(self.lib.gmg_history(self.h, kind, out.ctypes.data_as(ctypes.c_void_p), cnt.value,
+                                             ctypes.byref(cnt)))
+        return out.reshape(-1, 3) if kind == 1 else out
+
     # -- learned smoother (depth 0 = finest level)
     def net_set_weights(self, depth, w):
         import numpy as np
@@ -319,6 +335,22 @@ class Context:
         level = self._lvl(level)
         self._check(self.lib.gmg_net_correction(self.h, level, self._vec(r, level, GMG_FP32),
                                                 self._vec(e, level, GMG_FP32)))
+
+    def net_loss_grad(self, depth, r, e, cache, gw=None, scale=1.0, kind=LOSS_ENERGY):
+        """Loss of the pair (r, e) (e unused for LOSS_RESIDUAL); adds scale * dloss/dw into gw."""
+        lv = self.levels - 1 - depth
+        loss = ctypes.c_double()
+        ep = self._vec(e, lv, GMG_FP32) if e is not None else None
+        self._check(self.lib.gmg_net_loss_grad(self.h, depth, kind, self._vec(r, lv, GMG_FP32), ep,
+                                               _ptr(cache), _ptr(gw) if gw is not None else None,
+                                               ctypes.c_float(scale), ctypes.byref(loss)))
+        return loss.value
+
+    def residual(self, level, b, u, r):
+        level = self._lvl(level)
+        p = self.prec_of(b)
+        self._check(self.lib.gmg_residual(self.h, level, p, self._vec(b, level, p), self._vec(u, level, p),
+                                          self._vec(r, level, p)))
 
     def solve(self, f, u, rtol, raise_on_noconv=True):
         lv = self.levels - 1

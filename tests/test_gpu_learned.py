@@ -129,3 +129,45 @@ def test_learned_solve_converges_and_fallback_fires():
         assert rel <= 1e-8 * 1.001
         if name == "adversarial":
             assert info.fallbacks >= info.inner_iters - 1 and info.fallbacks >= 1
+        # the recorded tests follow the fallback rule: kept iff rho_L <= reference,
+        # and a rejection makes the plain cycle's contraction the next reference
+        hist = ctx.history(1)
+        rejected = np.isfinite(hist[:, 2])
+        assert len(hist) >= info.inner_iters - 1 and rejected.sum() == info.fallbacks
+        assert np.all((hist[:, 0] <= hist[:, 1]) == ~rejected)
+        for k in range(len(hist) - 1):
+            assert hist[k + 1, 1] == (hist[k, 2] if rejected[k] else hist[k, 1])
+        res = ctx.history(0)
+        assert len(res) >= info.inner_iters + 1 and res[-1] <= 1e-8 * res[0]
+
+
+@pytest.mark.parametrize("kind", ["energy", "residual"])
+def test_loss_gradient_parity(kind):
+    """gmg_net_loss_grad (forward, A e~, loss, backward through A and the net) vs the oracle."""
+    torch = torch_cuda()
+    from oracle import learned, operator as op
+    from paper_1408_6497_amd import LOSS_ENERGY, LOSS_RESIDUAL
+    q, n = 2, 8
+    ctx = _ctx(q, n)
+    N = q * n
+    A = op.assemble(q, n)
+    dinv = (1.0 / A.diagonal()).reshape(N, N, N)
+    w = _weights(9, scale=0.2)
+    ctx.net_set_weights(0, w)
+    r = mean_free_normal(N ** 3, 10)
+    rd = to_dev(r, torch.float32)
+    r = to_host(rd)
+    e = np.linalg.lstsq(A.toarray(), r, rcond=None)[0]
+    e -= e.mean()
+    ed = to_dev(e, torch.float32)
+    e = to_host(ed)
+    cache = ctx.net_cache(0)
+    gw = torch.zeros(7776, dtype=torch.float32, device="cuda")
+    k = LOSS_ENERGY if kind == "energy" else LOSS_RESIDUAL
+    loss = ctx.net_loss_grad(0, rd, ed if kind == "energy" else None, cache, gw, scale=0.5, kind=k)
+    torch.cuda.synchronize()
+    loss_ref, g_ref = learned.loss_and_gradient(w, A, dinv, r.reshape(N, N, N), e.reshape(N, N, N), kind)
+    err = rel_l2(to_host(gw), 0.5 * g_ref)
+    print(f"[loss-grad] {kind}: loss gpu={loss:.6f} oracle={loss_ref:.6f} grad rel={err:.2e}", flush=True)
+    assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
+    assert err <= 1e-3

@@ -71,3 +71,42 @@ def test_bf16_rounding_ties_to_even():
     assert learned.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
     assert learned.bf16(1.0 + 2.0 ** -7) == 1.0 + 2.0 ** -7
     assert learned.bf16(-3.0) == -3.0
+
+
+@pytest.mark.parametrize("kind", ["energy", "residual"])
+def test_loss_gradient_matches_central_differences(kind):
+    """The loss gradient through A and the net, by central differences of the loss itself."""
+    q, n = 2, 2
+    A = op.assemble(q, n).toarray()
+    N = q * n
+    dinv = (1.0 / np.diag(A)).reshape(N, N, N)
+    rng = np.random.default_rng(40)
+    r = rng.standard_normal(N ** 3)
+    r -= r.mean()
+    e = np.linalg.lstsq(A, r, rcond=None)[0]
+    r, e = r.reshape(N, N, N), e.reshape(N, N, N)
+    w = _rand_weights(41)
+    val, g = learned.loss_and_gradient(w, A, dinv, r, e, kind, emulate_bf16=False)
+
+    def f(ww):
+        et, _ = learned.correction(ww, r, dinv, emulate_bf16=False)
+        return learned.loss(A, e, et) if kind == "energy" else learned.residual_loss(A, r, et)
+
+    assert abs(val - f(w)) <= 1e-12 * abs(val)
+    h = 1e-6
+    for i in rng.choice(len(w), 30, replace=False):
+        ei = np.zeros_like(w)
+        ei[i] = h
+        fd = (f(w + ei) - f(w - ei)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_losses_at_exact_and_zero_corrections():
+    q, n = 1, 4
+    A = op.assemble(q, n)
+    r = np.random.default_rng(5).standard_normal(64)
+    r -= r.mean()
+    e = np.linalg.lstsq(A.toarray(), r, rcond=None)[0]
+    assert learned.residual_loss(A, r, np.zeros_like(r)) == 1.0
+    assert learned.residual_loss(A, r, e) < 1e-24
+    assert learned.loss(A, e, e) == 0.0

@@ -107,11 +107,10 @@ def grf(N, seed, alpha_lo=2.0, alpha_hi=4.0, device=None):
     import torch
     rng = np.random.default_rng(seed)
     alpha = rng.uniform(alpha_lo, alpha_hi)
-    gen = torch.Generator(device="cpu").manual_seed(int(seed))
-    re = torch.randn((N, N, N), generator=gen, dtype=torch.float64)
-    im = torch.randn((N, N, N), generator=gen, dtype=torch.float64)
     dev = torch.device("cpu") if device is None else torch.device(device)
-    re, im = re.to(dev), im.to(dev)
+    gen = torch.Generator(device=dev).manual_seed(int(seed))
+    re = torch.randn((N, N, N), generator=gen, dtype=torch.float64, device=dev)
+    im = torch.randn((N, N, N), generator=gen, dtype=torch.float64, device=dev)
     k = torch.fft.fftfreq(N, d=1.0 / N, dtype=torch.float64, device=dev)
     kk = (k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
     kk[0, 0, 0] = 1.0
