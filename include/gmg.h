@@ -15,9 +15,13 @@
  *  - Pointers named *_dev are device pointers (HIP global memory) owned by the
  *    caller; the library never frees them.  Pointers named *_host are host
  *    memory.  The library owns the context and every buffer inside it.
- *  - Vectors are DoF vectors of one level: length N^3 with N = q * n_level,
- *    lexicographic with x fastest: index i + N (j + N k).  Lattice node i sits at
- *    x = (e + xi_a) / n_level, e = i div q, a = i mod q, xi the LGL nodes on [0,1].
+ *  - Vectors are DoF vectors of one level.  Uniform meshes: length N^3 with
+ *    N = q * n_level, lexicographic with x fastest: index i + N (j + N k); lattice
+ *    node i sits at x = (e + xi_a) / n_level, e = i div q, a = i mod q, xi the LGL
+ *    nodes on [0,1].  Octree meshes: the independent nodes (hanging nodes are not
+ *    DoFs) in ascending order of x + T (y + T z), with (x, y, z) the node position
+ *    in units of 2^-11 and T = 2^11 (gmg_dof_coords returns the positions); for
+ *    an octree whose leaves all have one level this is the uniform order.
  *  - A vector's element type is double for GMG_FP64 and float for GMG_FP32.
  *  - Calls are ordered on the HIP stream given to gmg_setup: the library runs
  *    its kernels on a stream of its own after the work already queued there,
@@ -66,12 +70,26 @@ typedef enum { GMG_FP64 = 0, GMG_FP32 = 1 } gmg_prec;
  * halves per level, Section 2.3.1); 0 selects the deepest hierarchy whose
  * coarsest level has at most 512 DoFs and at least 2 elements per direction.
  * The coarsest level is solved with a dense FP64 pseudo-inverse, so an explicit
- * `levels` must leave at most 512 DoFs there (else GMG_E_ARG). */
+ * `levels` must leave at most 512 DoFs there (else GMG_E_ARG).
+ *
+ * Octree meshes (n = 0; order 1 or 2): a complete, 2:1-balanced linear octree
+ * of the periodic unit cube (Sections 2.2.1 and 2.3.1), given as n_leaves leaves
+ * sorted by Morton key: leaf_morton[i] interleaves the bits of the leaf's anchor
+ * (x, y, z) in units of 2^-10 (x in the lowest bit of each triple) and
+ * leaf_level[i] in [2, 10] is its level (width 2^-level).  Balance is across
+ * faces, edges and corners, wrapping periodically.  The hierarchy coarsens by
+ * merging every complete family of 8 sibling leaves and balancing again
+ * (Section 2.3.1) until the mesh is uniform at level 2; levels > 0 keeps the
+ * finest `levels` meshes of that sequence.  Host arrays, read during
+ * gmg_setup only.  An unsorted, incomplete or unbalanced octree gives GMG_E_MESH. */
 typedef struct {
   int32_t order;
-  int32_t n;
+  int32_t n;              /* elements per direction; 0 for an octree mesh       */
   int32_t levels;
   int32_t reserved;
+  int64_t n_leaves;       /* octree meshes only                                  */
+  const uint64_t* leaf_morton;
+  const uint8_t* leaf_level;
 } gmg_mesh;
 
 /* Solver options.  Zero-initialized fields take the defaults given here. */
@@ -122,8 +140,9 @@ typedef struct {
 gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_stream, gmg_ctx** out);
 gmg_status gmg_destroy(gmg_ctx* ctx);
 
-/* Queries (host).  gmg_dof_coords_1d writes the N coordinates of one axis; the
- * DoF (i, j, k) sits at (x[i], x[j], x[k]). */
+/* Queries (host).  gmg_dof_coords_1d writes the N coordinates of one axis of a
+ * uniform mesh (GMG_E_ARG on octree meshes); the DoF (i, j, k) sits at
+ * (x[i], x[j], x[k]). */
 gmg_status gmg_num_levels(const gmg_ctx* ctx, int32_t* levels);
 gmg_status gmg_num_dofs(const gmg_ctx* ctx, int32_t level, int64_t* n);
 gmg_status gmg_dof_coords_1d(const gmg_ctx* ctx, int32_t level, double* x_host);
@@ -232,6 +251,35 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
 gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
                           double* seconds);
 gmg_status gmg_timing_reset(gmg_ctx* ctx);
+
+/* Octree construction (host, integer work; Section 2.3.1, refinement on the
+ * gradient of f as in Section 3).  Outputs are leaves in the gmg_mesh format;
+ * cap is the capacity of the output arrays and *n_out receives the number of
+ * leaves (when it exceeds cap, nothing is written and GMG_E_ARG is returned).
+ *
+ * gmg_octree_refine_gaussians: start from the uniform mesh of base_level, split
+ * every leaf O with level < max_level and
+ *     h_O sum_i |a_i| g_i(d_i) > tol sum_i |a_i|,
+ * d_i = periodic distance from centre i to the box of O,
+ * g_i(d) = (d' / s_i^2) exp(-d'^2 / (2 s_i^2)), d' = max(d, s_i) (a bound on the
+ * gradient of a_i exp(-r^2 / (2 s_i^2)) over the box), until no leaf is split;
+ * then 2:1 balance.  centres: 3 * count doubles (x, y, z), sigma, amps: count.
+ * gmg_octree_balance: the coarsest 2:1-balanced refinement of a complete octree
+ * (GMG_E_MESH if the input is not complete).
+ * gmg_level_leaves: the leaves of one level of an octree context.
+ * gmg_num_elements: elements of one level (uniform: n_level^3). */
+gmg_status gmg_octree_refine_gaussians(int32_t base_level, int32_t max_level, int32_t count, const double* centres_host,
+                                       const double* sigma_host, const double* amps_host, double tol,
+                                       uint64_t* morton_out, uint8_t* level_out, int64_t cap, int64_t* n_out);
+gmg_status gmg_octree_balance(const uint64_t* morton_host, const uint8_t* level_host, int64_t n, uint64_t* morton_out,
+                              uint8_t* level_out, int64_t cap, int64_t* n_out);
+gmg_status gmg_level_leaves(const gmg_ctx* ctx, int32_t level, uint64_t* morton_out, uint8_t* level_out, int64_t cap,
+                            int64_t* n_out);
+gmg_status gmg_num_elements(const gmg_ctx* ctx, int32_t level, int64_t* n);
+
+/* Coordinates of every DoF of a level (uniform or octree): xyz_host[3 k + d] is
+ * coordinate d of DoF k, in [0, 1). */
+gmg_status gmg_dof_coords(const gmg_ctx* ctx, int32_t level, double* xyz_host);
 
 /* Convergence history of the last gmg_solve / gmg_solve_rhs (Section 3 reports
  * iteration counts; this keeps every iterate).  Host call, no synchronization.

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "gmg.h"
+#include "gmg_octree_host.h"
 #include "gmg_kernels.h"
 #include "gmg_setup_math.h"
 
@@ -47,9 +48,19 @@ enum : int {
 };
 
 struct Level {
-  int n = 0, N = 0;
+  int n = 0, N = 0;   // uniform: elements and lattice nodes per direction (0 on octree levels)
   int64_t size = 0;
   LevelTables tab{};
+  // octree levels: device arrays, and host copies of the leaves and DoF positions
+  bool oct = false;
+  OctLevelDev od{};
+  double* diag64 = nullptr;
+  double* dsqrt64 = nullptr;
+  double* dinv_sqrt64 = nullptr;
+  double* wint64 = nullptr;
+  double w0w0 = 0.0;  // sum of the diagonal: ||D^1/2 1||^2
+  std::vector<oct::Leaf> leaves;
+  std::vector<int64_t> points;
   double lam = 0, alpha = 0, beta = 0;
   void* b[2] = {nullptr, nullptr};   // [0] FP64, [1] FP32
   void* u[2] = {nullptr, nullptr};
@@ -87,6 +98,9 @@ struct gmg_ctx {
   void* kw[2] = {nullptr, nullptr};
   void* kc[2] = {nullptr, nullptr};
   void* bint = nullptr;  // FP64 load vector inside gmg_solve
+  bool octree = false;
+  void* oye[2] = {nullptr, nullptr};  // octree apply scratch: E m values of the largest level
+  int64_t oye_size = 0;
   std::vector<void*> allocs;
   std::string err;
   double t_setup = 0.0;
@@ -206,11 +220,12 @@ gmg_status drain_timing(gmg_ctx* c) {
 gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out, const void* b, const void* xp,
                     double c1, double c2, bool mass = false) {
   const Level& L = c->lv[l];
-  // the kernel moves q consecutive values per vector access
-  const uintptr_t al = static_cast<uintptr_t>(c->q) * esize(pi);
+  // the uniform kernel moves q consecutive values per vector access
+  const uintptr_t al = static_cast<uintptr_t>(L.oct ? 1 : c->q) * esize(pi);
   for (const void* ptr : {x, static_cast<const void*>(out), b, xp})
     if (ptr && (reinterpret_cast<uintptr_t>(ptr) % al) != 0)
       return fail(c, GMG_E_ARG, "device buffer not aligned to q elements");
+  if (L.oct && !c->oye[pi]) return fail(c, GMG_E_STATE, "octree scratch of this precision not allocated");
   ApplyArgs a{};
   a.N = L.N;
   a.n = L.n;
@@ -228,7 +243,12 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
     if (!ea || !eb) return fail(c, GMG_E_HIP, "hipEventCreate failed");
     HIPCHK(c, hipEventRecord(ea, c->stream));
   }
-  HIPCHK(c, launch_apply(mass ? L.tab.mass : L.tab.stiff, pi == 1, a, c->stream));
+  if (L.oct) {
+    const OctApply oa{x, out, b, xp, c1, c2, epi, c->oye[pi]};
+    HIPCHK(c, launch_oct_apply(L.od, pi == 1, mass, oa, c->stream));
+  } else {
+    HIPCHK(c, launch_apply(mass ? L.tab.mass : L.tab.stiff, pi == 1, a, c->stream));
+  }
   if (c->opt.timing) {
     HIPCHK(c, hipEventRecord(eb, c->stream));
     int kind = 0;
@@ -254,6 +274,12 @@ gmg_status project(gmg_ctx* c, int pi, int64_t n, void* v) {
   return GMG_OK;
 }
 
+// out = w D^-1 b on one level
+hipError_t dinv_scale(gmg_ctx* c, const Level& L, bool f32, double w, const void* b, void* out) {
+  if (L.oct) return launch_vec_scale(f32, L.size, L.od.dinv64, w, b, out, c->stream);
+  return launch_class_scale(f32, c->q, L.N, L.tab.stiff.dinv, w, b, out, c->stream);
+}
+
 // u <- S^nu(u; b) on level l.  zero_init: u is taken as 0 on entry (not read).
 gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, bool zero_init) {
   Level& L = c->lv[l];
@@ -270,7 +296,7 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
     const double w = c->opt.jacobi_omega;
     for (int s = 0; s < nu; ++s) {
       if (x_zero) {
-        HIPCHK(c, launch_class_scale(f32, c->q, L.N, L.tab.stiff.dinv, w, b, bufs[1 - cur], c->stream));
+        HIPCHK(c, dinv_scale(c, L, f32, w, b, bufs[1 - cur]));
         x_zero = false;
       } else {
         STCHK(apply_op(c, l, pi, Epi::Cheb, bufs[cur], bufs[1 - cur], b, nullptr, 0.0, w));
@@ -294,7 +320,7 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
         }
         if (x_zero) {
           // x_1 = x_0 + D^-1 (b - A x_0) / theta with x_0 = 0
-          HIPCHK(c, launch_class_scale(f32, c->q, L.N, L.tab.stiff.dinv, c2, b, bufs[1 - cur], c->stream));
+          HIPCHK(c, dinv_scale(c, L, f32, c2, b, bufs[1 - cur]));
           x_zero = false;
           prev_zero = true;
         } else {
@@ -314,6 +340,10 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
 gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
   const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
   const bool f32 = pi == 1;
+  if (c->lv[l].oct) {
+    HIPCHK(c, launch_oct_restrict(c->lv[l].od, c->lv[l - 1].size, f32, rf, rc, c->stream));
+    return GMG_OK;
+  }
   (void)Nf;
   HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream));
   return GMG_OK;
@@ -323,6 +353,10 @@ gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
 gmg_status prolong_level(gmg_ctx* c, int l, int pi, const void* ec, void* uf) {
   const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
   const bool f32 = pi == 1;
+  if (c->lv[l].oct) {
+    HIPCHK(c, launch_oct_prolong(c->lv[l].od, f32, ec, uf, c->stream));
+    return GMG_OK;
+  }
   (void)Nf;
   HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream));
   return GMG_OK;
@@ -344,6 +378,7 @@ int net_for_depth(const gmg_ctx* c, int d) {
 bool learned_on_level(const gmg_ctx* c, int l, int pi) {
   const int d = c->L - 1 - l;
   if (c->opt.learned_depths > 0 && d >= c->opt.learned_depths) return false;
+  if (c->lv[l].oct) return false;  // the lattice convolution needs a uniform level
   return c->opt.use_learned && !c->suppress_learned && pi == 1 && l > 0 && c->lv[l].N >= 16 &&
          net_for_depth(c, d) >= 0;
 }
@@ -537,29 +572,39 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
   void* w = L.xp[0];
   void* t = c->kr[0];
   const hipStream_t s = c->stream;
-  HIPCHK(c, launch_splitmix_start(c->opt.seed + static_cast<uint64_t>(l), n, static_cast<double*>(v), s));
-  // project out the null vector D^1/2 1 of the scaled operator
-  double w0w0 = 0.0;
-  const int64_t per_class = n / (q * q * q);
-  for (int i = 0; i < q * q * q; ++i) w0w0 += L.tab.diag[i] * static_cast<double>(per_class);
-  HIPCHK(c, launch_class_dot(false, q, L.N, L.tab.dsqrt, v, c->part, c->part_cap, c->scal + S_TMP, s));
-  double hs[kNumScal];
-  STCHK(read_scalars(c, hs, kNumScal));
-  HIPCHK(c, launch_class_axpy(false, q, L.N, L.tab.dsqrt, -hs[S_TMP] / w0w0, v, s));
-  HIPCHK(c, launch_dot(false, n, v, v, c->part, c->scal + S_TMP, s));
-  STCHK(read_scalars(c, hs, kNumScal));
   const double ones[kMaxQ * kMaxQ * kMaxQ] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
                                               1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
                                               1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
-  HIPCHK(c, launch_class_scale(false, q, L.N, ones, 1.0 / std::sqrt(hs[S_TMP]), v, v, s));
+  // the level's diagonal as a class table (uniform) or a vector (octree)
+  auto scale = [&](const double* tab, const double* vec, double a, const void* in, void* out) {
+    return L.oct ? launch_vec_scale(false, n, vec, a, in, out, s) : launch_class_scale(false, q, L.N, tab, a, in, out, s);
+  };
+  HIPCHK(c, launch_splitmix_start(c->opt.seed + static_cast<uint64_t>(l), n, static_cast<double*>(v), s));
+  // project out the null vector D^1/2 1 of the scaled operator
+  double w0w0 = 0.0;
+  if (L.oct) {
+    w0w0 = L.w0w0;
+    HIPCHK(c, launch_dot(false, n, L.dsqrt64, v, c->part, c->scal + S_TMP, s));
+  } else {
+    const int64_t per_class = n / (q * q * q);
+    for (int i = 0; i < q * q * q; ++i) w0w0 += L.tab.diag[i] * static_cast<double>(per_class);
+    HIPCHK(c, launch_class_dot(false, q, L.N, L.tab.dsqrt, v, c->part, c->part_cap, c->scal + S_TMP, s));
+  }
+  double hs[kNumScal];
+  STCHK(read_scalars(c, hs, kNumScal));
+  if (L.oct) HIPCHK(c, launch_axpy(false, n, -hs[S_TMP] / w0w0, L.dsqrt64, v, s));
+  else HIPCHK(c, launch_class_axpy(false, q, L.N, L.tab.dsqrt, -hs[S_TMP] / w0w0, v, s));
+  HIPCHK(c, launch_dot(false, n, v, v, c->part, c->scal + S_TMP, s));
+  STCHK(read_scalars(c, hs, kNumScal));
+  HIPCHK(c, scale(ones, nullptr, 1.0 / std::sqrt(hs[S_TMP]), v, v));
   HIPCHK(c, launch_fill_zero(false, n, vprev, s));
   const int steps = static_cast<int>(std::min<int64_t>(c->opt.lanczos_steps, n - 1));
   std::vector<double> alpha, beta;
   double bprev = 0.0, amax = 0.0;
   for (int j = 0; j < steps; ++j) {
-    HIPCHK(c, launch_class_scale(false, q, L.N, L.tab.dinv_sqrt, 1.0, v, t, s));
+    HIPCHK(c, scale(L.tab.dinv_sqrt, L.dinv_sqrt64, 1.0, v, t));
     STCHK(apply_op(c, l, 0, Epi::Apply, t, w, nullptr, nullptr, 0, 0));
-    HIPCHK(c, launch_class_scale(false, q, L.N, L.tab.dinv_sqrt, 1.0, w, w, s));
+    HIPCHK(c, scale(L.tab.dinv_sqrt, L.dinv_sqrt64, 1.0, w, w));
     if (bprev != 0.0) HIPCHK(c, launch_axpy(false, n, -bprev, vprev, w, s));
     HIPCHK(c, launch_dot(false, n, w, v, c->part, c->scal + S_TMP, s));
     STCHK(read_scalars(c, hs, kNumScal));
@@ -574,7 +619,7 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
     beta.push_back(bnew);
     // vprev <- v ; v <- w / bnew
     std::swap(v, vprev);
-    HIPCHK(c, launch_class_scale(false, q, L.N, ones, 1.0 / bnew, w, v, s));
+    HIPCHK(c, scale(ones, nullptr, 1.0 / bnew, w, v));
     bprev = bnew;
   }
   *lam_out = tridiag_max_eig(alpha, beta);
@@ -696,35 +741,204 @@ const char* gmg_status_string(gmg_status s) {
 
 const char* gmg_last_error(const gmg_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kOctCoarsest = 2;  // the octree hierarchy ends at the uniform mesh of this level
+
+// Host side of one octree level.
+struct OctHost {
+  oct::Space sp;
+  std::vector<double> diag, wint;
+  oct::Csr P;  // prolongation from the next coarser level (empty on level 0)
+};
+
+// Validate the caller's octree and build the hierarchy (finest last):
+// coarsening by sibling merge and 2:1 balance (Section 2.3.1) down to the
+// uniform mesh of level kOctCoarsest, or `levels` meshes when levels > 0.
+gmg_status octree_hierarchy(const gmg_mesh* mesh, int q, std::vector<OctHost>* lv, std::string* err) {
+  if (q != 1 && q != 2) {
+    *err = "octree meshes support orders 1 and 2";
+    return GMG_E_ARG;
+  }
+  if (mesh->n_leaves <= 0 || !mesh->leaf_morton || !mesh->leaf_level) return GMG_E_ARG;
+  std::vector<oct::Leaf> t(static_cast<size_t>(mesh->n_leaves));
+  for (int64_t i = 0; i < mesh->n_leaves; ++i) {
+    uint32_t x, y, z;
+    const uint64_t k = mesh->leaf_morton[i];
+    if (k >> (3 * oct::kMaxLevel)) {
+      *err = "Morton key beyond the finest level";
+      return GMG_E_MESH;
+    }
+    oct::morton_decode(k, &x, &y, &z);
+    t[i] = {static_cast<int32_t>(x), static_cast<int32_t>(y), static_cast<int32_t>(z), mesh->leaf_level[i]};
+    if (t[i].level < kOctCoarsest || t[i].level > oct::kMaxLevel) {
+      *err = "leaf level outside [2, 10]";
+      return GMG_E_MESH;
+    }
+  }
+  if (!oct::is_complete(t)) {
+    *err = "octree leaves are not sorted, aligned and complete";
+    return GMG_E_MESH;
+  }
+  if (!oct::is_balanced(t)) {
+    *err = "octree is not 2:1 balanced";
+    return GMG_E_MESH;
+  }
+  std::vector<std::vector<oct::Leaf>> trees{t};
+  auto uniform_coarsest = [](const std::vector<oct::Leaf>& tr) {
+    for (const auto& o : tr)
+      if (o.level != kOctCoarsest) return false;
+    return true;
+  };
+  while (!uniform_coarsest(trees.back())) trees.push_back(oct::coarsen(trees.back(), kOctCoarsest));
+  std::reverse(trees.begin(), trees.end());
+  if (mesh->levels > 0) {
+    if (mesh->levels > static_cast<int>(trees.size())) return GMG_E_ARG;
+    trees.erase(trees.begin(), trees.end() - mesh->levels);
+  }
+  std::vector<double> kref, mref;
+  oct::reference_element(q, &kref, &mref);
+  lv->resize(trees.size());
+  for (size_t l = 0; l < trees.size(); ++l) {
+    OctHost& h = (*lv)[l];
+    h.sp = oct::build_space(trees[l], q);
+    h.diag = oct::element_diag_sum(h.sp, kref);
+    h.wint = oct::basis_integrals(h.sp, mref);
+    if (l > 0) h.P = oct::prolongation((*lv)[l - 1].sp, h.sp);
+    if (h.sp.C.col.size() > static_cast<size_t>(INT32_MAX) || h.sp.C.rows > INT32_MAX) return GMG_E_ARG;
+  }
+  if ((*lv)[0].sp.ndof() > 512) {
+    *err = "coarsest octree level has more than 512 DoFs";
+    return GMG_E_ARG;
+  }
+  return GMG_OK;
+}
+
+template <typename T>
+gmg_status upload(gmg_ctx* c, const std::vector<T>& v, const T** dst) {
+  void* p = nullptr;
+  STCHK(dalloc(c, &p, sizeof(T) * std::max<size_t>(v.size(), 1)));
+  if (!v.empty()) HIPCHK(c, hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  *dst = static_cast<const T*>(p);
+  return GMG_OK;
+}
+
+std::vector<int> narrow(const std::vector<int64_t>& v) { return std::vector<int>(v.begin(), v.end()); }
+std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+gmg_status upload_csr(gmg_ctx* c, const oct::Csr& a, const int** ptr, const int** col, const double** v64,
+                      const float** v32) {
+  STCHK(upload(c, narrow(a.ptr), ptr));
+  STCHK(upload(c, a.col, col));
+  STCHK(upload(c, a.val, v64));
+  STCHK(upload(c, to_f32(a.val), v32));
+  return GMG_OK;
+}
+
+// Device arrays of octree level l from its host side.
+gmg_status upload_octree_level(gmg_ctx* c, Level& L, OctHost& h, const std::vector<double>& kref,
+                               const std::vector<double>& mref) {
+  L.oct = true;
+  L.n = L.N = 0;
+  L.size = h.sp.ndof();
+  L.leaves = h.sp.leaves;
+  L.points = h.sp.points;
+  OctLevelDev& d = L.od;
+  d.E = h.sp.elements();
+  d.n = L.size;
+  d.m = h.sp.m;
+  std::vector<uint8_t> lev(d.E);
+  for (int64_t e = 0; e < d.E; ++e) lev[e] = static_cast<uint8_t>(h.sp.leaves[e].level);
+  STCHK(upload(c, lev, &d.lev));
+  STCHK(upload_csr(c, h.sp.C, &d.cptr, &d.ccol, &d.cval64, &d.cval32));
+  STCHK(upload_csr(c, oct::transpose(h.sp.C), &d.tptr, &d.trow, &d.tval64, &d.tval32));
+  STCHK(upload(c, kref, &d.kref64));
+  STCHK(upload(c, to_f32(kref), &d.kref32));
+  STCHK(upload(c, mref, &d.mref64));
+  STCHK(upload(c, to_f32(mref), &d.mref32));
+  std::vector<double> dinv(L.size), dsq(L.size), dis(L.size);
+  L.w0w0 = 0.0;
+  for (int64_t k = 0; k < L.size; ++k) {
+    if (!(h.diag[k] > 0.0)) return fail(c, GMG_E_MESH, "non-positive diagonal entry on an octree level");
+    dinv[k] = 1.0 / h.diag[k];
+    dsq[k] = std::sqrt(h.diag[k]);
+    dis[k] = 1.0 / dsq[k];
+    L.w0w0 += h.diag[k];
+  }
+  STCHK(upload(c, dinv, &d.dinv64));
+  STCHK(upload(c, to_f32(dinv), &d.dinv32));
+  const double* p = nullptr;
+  STCHK(upload(c, h.diag, &p));
+  L.diag64 = const_cast<double*>(p);
+  STCHK(upload(c, dsq, &p));
+  L.dsqrt64 = const_cast<double*>(p);
+  STCHK(upload(c, dis, &p));
+  L.dinv_sqrt64 = const_cast<double*>(p);
+  STCHK(upload(c, h.wint, &p));
+  L.wint64 = const_cast<double*>(p);
+  if (h.P.rows > 0) {
+    STCHK(upload_csr(c, h.P, &d.pptr, &d.pcol, &d.pval64, &d.pval32));
+    STCHK(upload_csr(c, oct::transpose(h.P), &d.rptr, &d.rcol, &d.rval64, &d.rval32));
+  }
+  c->oye_size = std::max<int64_t>(c->oye_size, d.E * d.m);
+  return GMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_stream, gmg_ctx** out) {
   if (!mesh || !out) return GMG_E_ARG;
   *out = nullptr;
   const auto t0 = std::chrono::steady_clock::now();
   const int q = mesh->order;
   const int n = mesh->n;
+  const bool octree = n == 0;
   if (!(q == 1 || q == 2 || q == 4)) return GMG_E_ARG;
-  if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n > (q == 4 ? 256 : 512)) return GMG_E_ARG;
   int L = mesh->levels;
-  if (L <= 0) {
-    L = 1;
-    // deepest hierarchy with coarsest level >= 2 elements and <= 512 DoFs
-    while (true) {
-      const int nc = n >> (L - 1);
-      const int64_t dofs = static_cast<int64_t>(q * nc) * (q * nc) * (q * nc);
-      if (dofs <= 512 || nc / 2 < 2 || q * (nc / 2) < 4) break;
-      ++L;
+  int nc0 = 0;
+  int64_t n0 = 0;
+  std::vector<OctHost> oh;
+  std::string oerr;
+  if (octree) {
+    gmg_status st;
+    try {
+      st = octree_hierarchy(mesh, q, &oh, &oerr);
+    } catch (const std::bad_alloc&) {
+      return GMG_E_OOM;
+    } catch (...) {
+      return GMG_E_MESH;
     }
+    if (st != GMG_OK) return st;
+    L = static_cast<int>(oh.size());
+    n0 = oh[0].sp.ndof();
+  } else {
+    if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n > (q == 4 ? 256 : 512)) return GMG_E_ARG;
+    if (L <= 0) {
+      L = 1;
+      // deepest hierarchy with coarsest level >= 2 elements and <= 512 DoFs
+      while (true) {
+        const int nc = n >> (L - 1);
+        const int64_t dofs = static_cast<int64_t>(q * nc) * (q * nc) * (q * nc);
+        if (dofs <= 512 || nc / 2 < 2 || q * (nc / 2) < 4) break;
+        ++L;
+      }
+    }
+    if ((n >> (L - 1)) < 1 || (n >> (L - 1)) << (L - 1) != n) return GMG_E_ARG;
+    nc0 = n >> (L - 1);
+    if (q * nc0 < 4 || nc0 < 2) return GMG_E_ARG;
+    n0 = static_cast<int64_t>(q * nc0) * (q * nc0) * (q * nc0);
+    if (n0 > 512) return GMG_E_ARG;  // dense FP64 coarsest solve: at most 512 DoFs
   }
-  if ((n >> (L - 1)) < 1 || (n >> (L - 1)) << (L - 1) != n) return GMG_E_ARG;
-  const int nc0 = n >> (L - 1);
-  if (q * nc0 < 4 || nc0 < 2) return GMG_E_ARG;
-  const int64_t n0 = static_cast<int64_t>(q * nc0) * (q * nc0) * (q * nc0);
-  if (n0 > 512) return GMG_E_ARG;  // dense FP64 coarsest solve: at most 512 DoFs
 
   gmg_ctx* c = new (std::nothrow) gmg_ctx();
   if (!c) return GMG_E_OOM;
   c->q = q;
   c->L = L;
+  c->octree = octree;
   gmg_options o{};
   if (opts) o = *opts;
   if (o.cheb_degree <= 0) o.cheb_degree = 3;
@@ -762,19 +976,29 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   c->lcache.assign(L, nullptr);
   c->tsec.assign(static_cast<size_t>(L) * kKinds * 2, 0.0);
   c->tcount.assign(static_cast<size_t>(L) * kKinds * 2, 0);
-  for (int l = 0; l < L; ++l) {
-    Level& lev = c->lv[l];
-    lev.n = n >> (L - 1 - l);
-    lev.N = q * lev.n;
-    lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
-    lev.tab = make_level_tables(q, lev.n);
-  }
-  make_transfer_table(q, &c->xfer);
   gmg_status st = GMG_OK;
   auto bail = [&](gmg_status s) {
     gmg_destroy(c);
     return s;
   };
+  if (octree) {
+    std::vector<double> kref, mref;
+    oct::reference_element(q, &kref, &mref);
+    for (int l = 0; l < L; ++l)
+      if ((st = upload_octree_level(c, c->lv[l], oh[l], kref, mref)) != GMG_OK) return bail(st);
+    // apply scratch of both precisions (every entry point that applies an operator needs it)
+    for (int pi = 0; pi < 2; ++pi)
+      if ((st = dalloc(c, &c->oye[pi], c->oye_size * esize(pi))) != GMG_OK) return bail(st);
+  } else {
+    for (int l = 0; l < L; ++l) {
+      Level& lev = c->lv[l];
+      lev.n = n >> (L - 1 - l);
+      lev.N = q * lev.n;
+      lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
+      lev.tab = make_level_tables(q, lev.n);
+    }
+    make_transfer_table(q, &c->xfer);
+  }
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
   c->part_cap = std::max<int64_t>(kRedBlocks, static_cast<int64_t>(c->lv.back().N) * c->lv.back().N);
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->part), sizeof(double) * c->part_cap)) != GMG_OK) return bail(st);
@@ -784,7 +1008,14 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   c->n0 = static_cast<int>(n0);
   std::vector<double> inv;
   try {
-    inv = coarse_pseudo_inverse(q, nc0);
+    if (octree) {
+      std::vector<double> kref, mref;
+      oct::reference_element(q, &kref, &mref);
+      inv = dense_pseudo_inverse(oct::dense_operator(oh[0].sp, kref), static_cast<int>(n0));
+      oh.clear();
+    } else {
+      inv = coarse_pseudo_inverse(q, nc0);
+    }
   } catch (...) {
     return bail(GMG_E_ARG);
   }
@@ -838,7 +1069,7 @@ gmg_status gmg_num_dofs(const gmg_ctx* ctx, int32_t level, int64_t* n) {
 }
 
 gmg_status gmg_dof_coords_1d(const gmg_ctx* ctx, int32_t level, double* x_host) {
-  if (!ctx || !x_host || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  if (!ctx || !x_host || check_level(ctx, level) != GMG_OK || ctx->lv[level].oct) return GMG_E_ARG;
   const Level& L = ctx->lv[level];
   const std::vector<double> xi = lgl_nodes01(ctx->q);
   for (int i = 0; i < L.N; ++i) x_host[i] = (i / ctx->q + xi[i % ctx->q]) / L.n;
@@ -855,7 +1086,8 @@ gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev) {
   if (!ctx || !d_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   const Level& L = ctx->lv[level];
   return scoped(ctx, [&] {
-    HIPCHK(ctx, launch_class_scale(false, ctx->q, L.N, L.tab.diag, 1.0, nullptr, d_dev, ctx->stream));
+    if (L.oct) HIPCHK(ctx, launch_copy(false, L.size, L.diag64, d_dev, ctx->stream));
+    else HIPCHK(ctx, launch_class_scale(false, ctx->q, L.N, L.tab.diag, 1.0, nullptr, d_dev, ctx->stream));
     return GMG_OK;
   });
 }
@@ -1024,7 +1256,8 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   if (st == GMG_OK || st == GMG_E_NOCONV) {
     // zero integral: u <- u - (int u_h) / |cube|
     const Level& F = c->lv[l];
-    HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u_dev, c->part, c->part_cap, c->scal + S_TMP, s));
+    if (F.oct) HIPCHK(c, launch_dot(false, n, F.wint64, u_dev, c->part, c->scal + S_TMP, s));
+    else HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u_dev, c->part, c->part_cap, c->scal + S_TMP, s));
     HIPCHK(c, launch_shift(false, n, c->scal, S_TMP, 1.0, u_dev, s));
   }
   HIPCHK(c, hipEventRecord(e1, s));
@@ -1056,6 +1289,90 @@ gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec pr
   const int s = tslot(level, kind, pidx(prec));
   *launches = ctx->tcount[s];
   *seconds = ctx->tsec[s];
+  return GMG_OK;
+}
+
+namespace {
+gmg_status write_leaves(const std::vector<oct::Leaf>& t, uint64_t* morton_out, uint8_t* level_out, int64_t cap,
+                        int64_t* n_out) {
+  *n_out = static_cast<int64_t>(t.size());
+  if (*n_out > cap || !morton_out || !level_out) return GMG_E_ARG;
+  for (size_t i = 0; i < t.size(); ++i) {
+    morton_out[i] = oct::morton_key(t[i].x, t[i].y, t[i].z);
+    level_out[i] = static_cast<uint8_t>(t[i].level);
+  }
+  return GMG_OK;
+}
+}  // namespace
+
+gmg_status gmg_octree_refine_gaussians(int32_t base_level, int32_t max_level, int32_t count, const double* centres,
+                                       const double* sigma, const double* amps, double tol, uint64_t* morton_out,
+                                       uint8_t* level_out, int64_t cap, int64_t* n_out) {
+  if (!n_out || count < 0 || (count > 0 && (!centres || !sigma || !amps)) || base_level < 0 ||
+      max_level > oct::kMaxLevel || base_level > max_level || !(tol > 0.0))
+    return GMG_E_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!(sigma[i] > 0.0)) return GMG_E_ARG;
+  try {
+    return write_leaves(oct::refine_gaussians(base_level, max_level, count, centres, sigma, amps, tol), morton_out,
+                        level_out, cap, n_out);
+  } catch (...) {
+    return GMG_E_OOM;
+  }
+}
+
+gmg_status gmg_octree_balance(const uint64_t* morton, const uint8_t* level, int64_t n, uint64_t* morton_out,
+                              uint8_t* level_out, int64_t cap, int64_t* n_out) {
+  if (!morton || !level || n <= 0 || !n_out) return GMG_E_ARG;
+  std::vector<oct::Leaf> t(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) {
+    if (morton[i] >> (3 * oct::kMaxLevel) || level[i] > oct::kMaxLevel) return GMG_E_MESH;
+    uint32_t x, y, z;
+    oct::morton_decode(morton[i], &x, &y, &z);
+    t[i] = {static_cast<int32_t>(x), static_cast<int32_t>(y), static_cast<int32_t>(z), level[i]};
+  }
+  if (!oct::is_complete(t)) return GMG_E_MESH;
+  try {
+    return write_leaves(oct::balance(t), morton_out, level_out, cap, n_out);
+  } catch (...) {
+    return GMG_E_OOM;
+  }
+}
+
+gmg_status gmg_level_leaves(const gmg_ctx* ctx, int32_t level, uint64_t* morton_out, uint8_t* level_out, int64_t cap,
+                            int64_t* n_out) {
+  if (!ctx || !n_out || check_level(ctx, level) != GMG_OK || !ctx->lv[level].oct) return GMG_E_ARG;
+  return write_leaves(ctx->lv[level].leaves, morton_out, level_out, cap, n_out);
+}
+
+gmg_status gmg_num_elements(const gmg_ctx* ctx, int32_t level, int64_t* n) {
+  if (!ctx || !n || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const Level& L = ctx->lv[level];
+  *n = L.oct ? L.od.E : static_cast<int64_t>(L.n) * L.n * L.n;
+  return GMG_OK;
+}
+
+gmg_status gmg_dof_coords(const gmg_ctx* ctx, int32_t level, double* xyz) {
+  if (!ctx || !xyz || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const Level& L = ctx->lv[level];
+  if (L.oct) {
+    const double inv = 1.0 / static_cast<double>(oct::kTicks);
+    for (int64_t k = 0; k < L.size; ++k) {
+      const int64_t key = L.points[k];
+      xyz[3 * k] = static_cast<double>(key % oct::kTicks) * inv;
+      xyz[3 * k + 1] = static_cast<double>((key / oct::kTicks) % oct::kTicks) * inv;
+      xyz[3 * k + 2] = static_cast<double>(key / (oct::kTicks * oct::kTicks)) * inv;
+    }
+    return GMG_OK;
+  }
+  std::vector<double> x(L.N);
+  const std::vector<double> xi = lgl_nodes01(ctx->q);
+  for (int i = 0; i < L.N; ++i) x[i] = (i / ctx->q + xi[i % ctx->q]) / L.n;
+  for (int64_t k = 0; k < L.size; ++k) {
+    xyz[3 * k] = x[k % L.N];
+    xyz[3 * k + 1] = x[(k / L.N) % L.N];
+    xyz[3 * k + 2] = x[k / (static_cast<int64_t>(L.N) * L.N)];
+  }
   return GMG_OK;
 }
 

@@ -63,6 +63,59 @@ struct ApplyArgs {
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 
+// Device arrays of one octree level (owned by the library context).  The
+// stiffness is C^T blockdiag(h_e kref) C and the mass C^T blockdiag(h_e^3 mref) C,
+// with C the element-node constraint map (E m rows, CSR) and h_e = 2^-lev[e].
+struct OctLevelDev {
+  int64_t E = 0;  // leaves
+  int64_t n = 0;  // DoFs
+  int m = 0;      // nodes per element, (q+1)^3 (8 or 27)
+  const uint8_t* lev = nullptr;
+  const int* cptr = nullptr;
+  const int* ccol = nullptr;
+  const double* cval64 = nullptr;
+  const float* cval32 = nullptr;
+  const int* tptr = nullptr;  // C^T: n rows of (element node, weight)
+  const int* trow = nullptr;
+  const double* tval64 = nullptr;
+  const float* tval32 = nullptr;
+  const double* kref64 = nullptr;
+  const float* kref32 = nullptr;
+  const double* mref64 = nullptr;
+  const float* mref32 = nullptr;
+  const double* dinv64 = nullptr;
+  const float* dinv32 = nullptr;
+  // from the next coarser level: P (n rows) and P^T (coarse rows)
+  const int* pptr = nullptr;
+  const int* pcol = nullptr;
+  const double* pval64 = nullptr;
+  const float* pval32 = nullptr;
+  const int* rptr = nullptr;
+  const int* rcol = nullptr;
+  const double* rval64 = nullptr;
+  const float* rval32 = nullptr;
+};
+
+// Same epilogues as ApplyArgs; ye is scratch of E m values of the kernel precision.
+struct OctApply {
+  const void* x;
+  void* out;
+  const void* b;
+  const void* xp;
+  double c1, c2;
+  Epi epi;
+  void* ye;
+};
+
+hipError_t launch_oct_apply(const OctLevelDev& L, bool fp32, bool mass, const OctApply& a, hipStream_t s);
+// uf += P ec;  rc = P^T rf (nc coarse DoFs)
+hipError_t launch_oct_prolong(const OctLevelDev& fine, bool fp32, const void* ec, void* uf, hipStream_t s);
+hipError_t launch_oct_restrict(const OctLevelDev& fine, int64_t nc, bool fp32, const void* rf, void* rc,
+                               hipStream_t s);
+// out = c d .* in (in null: out = c d; d null: d = 1), d an FP64 vector; in may alias out
+hipError_t launch_vec_scale(bool fp32, int64_t n, const double* d, double c, const void* in, void* out,
+                            hipStream_t s);
+
 // uf += P ec (coarse Nc^3 -> fine (2Nc)^3) and rc = P^T rf, as three one-axis
 // passes through the temporaries t1 (>= Nf^3/2 values) and t2 (>= Nf^3/4).
 hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,

@@ -225,8 +225,8 @@ std::vector<double> coarse_pseudo_inverse(int q, int n) {
   const int n0 = N * N * N;
   std::vector<double> K, M;
   dense_1d(q, n, &K, &M);
-  // B = A_0 + 1 1^T / n0, A_0 = K (x) M (x) M + M (x) K (x) M + M (x) M (x) K
-  std::vector<double> B(static_cast<size_t>(n0) * n0);
+  // A_0 = K (x) M (x) M + M (x) K (x) M + M (x) M (x) K
+  std::vector<double> A(static_cast<size_t>(n0) * n0);
   for (int k = 0; k < N; ++k)
     for (int j = 0; j < N; ++j)
       for (int i = 0; i < N; ++i) {
@@ -235,12 +235,17 @@ std::vector<double> coarse_pseudo_inverse(int q, int n) {
           for (int jj = 0; jj < N; ++jj)
             for (int ii = 0; ii < N; ++ii) {
               const int c = ii + N * (jj + N * kk);
-              const double v = K[i * N + ii] * M[j * N + jj] * M[k * N + kk] +
-                               M[i * N + ii] * K[j * N + jj] * M[k * N + kk] +
-                               M[i * N + ii] * M[j * N + jj] * K[k * N + kk];
-              B[static_cast<size_t>(r) * n0 + c] = v + 1.0 / n0;
+              A[static_cast<size_t>(r) * n0 + c] = K[i * N + ii] * M[j * N + jj] * M[k * N + kk] +
+                                                   M[i * N + ii] * K[j * N + jj] * M[k * N + kk] +
+                                                   M[i * N + ii] * M[j * N + jj] * K[k * N + kk];
             }
       }
+  return dense_pseudo_inverse(std::move(A), n0);
+}
+
+std::vector<double> dense_pseudo_inverse(std::vector<double> B, int n0) {
+  // B = A_0 + 1 1^T / n0
+  for (auto& v : B) v += 1.0 / n0;
   // Cholesky B = L L^T (lower triangle in place)
   for (int j = 0; j < n0; ++j) {
     double d = B[static_cast<size_t>(j) * n0 + j];

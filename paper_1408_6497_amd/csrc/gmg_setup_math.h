@@ -27,6 +27,8 @@ LevelTables make_level_tables(int q, int n);
 void make_transfer_table(int q, TransferTab* tab);
 // (A_0 + 1 1^T / N0)^-1 of the coarsest level, dense, symmetric, row-major.
 std::vector<double> coarse_pseudo_inverse(int q, int n);
+// (A + 1 1^T / n0)^-1 of any dense symmetric n0 x n0 matrix A with null space 1 (row-major).
+std::vector<double> dense_pseudo_inverse(std::vector<double> A, int n0);
 uint64_t splitmix64_at(uint64_t key, uint64_t i);
 void lanczos_start_vector(uint64_t seed, int level, int64_t count, double* out);
 double tridiag_max_eig(const std::vector<double>& alpha, const std::vector<double>& beta);

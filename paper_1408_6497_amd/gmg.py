@@ -26,6 +26,7 @@ EXPORTS = [
     "gmg_timing_get", "gmg_timing_reset", "gmg_history", "gmg_status_string", "gmg_last_error",
     "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
+    "gmg_octree_refine_gaussians", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
 ]
 
 NET_WEIGHTS = 7776
@@ -34,7 +35,8 @@ LOSS_ENERGY, LOSS_RESIDUAL = 0, 1
 
 class GmgMesh(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("n", ctypes.c_int32), ("levels", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
+                ("leaf_morton", ctypes.POINTER(ctypes.c_uint64)), ("leaf_level", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class GmgOptions(ctypes.Structure):
@@ -101,6 +103,11 @@ def load():
         "gmg_timing_get": [P, I32, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D)],
         "gmg_timing_reset": [P],
         "gmg_history": [P, I32, P, I64, ctypes.POINTER(I64)],
+        "gmg_octree_refine_gaussians": [I32, I32, I32, P, P, P, D, P, P, I64, ctypes.POINTER(I64)],
+        "gmg_octree_balance": [P, P, I64, P, P, I64, ctypes.POINTER(I64)],
+        "gmg_level_leaves": [P, I32, P, P, I64, ctypes.POINTER(I64)],
+        "gmg_num_elements": [P, I32, ctypes.POINTER(I64)],
+        "gmg_dof_coords": [P, I32, P],
         "gmg_net_set_weights": [P, I32, P, I64],
         "gmg_set_learned": [P, I32, P, I64],
         "gmg_net_get_weights": [P, I32, P, I64],
@@ -131,11 +138,22 @@ def _ptr(t):
 class Context:
     """Owns one gmg_ctx (a multigrid hierarchy on the current HIP device)."""
 
-    def __init__(self, order, n, levels=0, stream=None, **opts):
+    def __init__(self, order, n, levels=0, stream=None, leaves=None, **opts):
+        """Uniform mesh of n^3 elements, or (n = 0) the octree leaves = (morton uint64, level uint8)."""
+        import numpy as np
         import torch
         self._torch = torch
         self.lib = load()
         mesh = GmgMesh(order=order, n=n, levels=levels, reserved=0)
+        if leaves is not None:
+            keys = np.ascontiguousarray(leaves[0], dtype=np.uint64)
+            lev = np.ascontiguousarray(leaves[1], dtype=np.uint8)
+            if n != 0 or keys.shape != lev.shape:
+                raise ValueError("octree meshes take n = 0 and equal-length key / level arrays")
+            self._leaf_arrays = (keys, lev)
+            mesh.n_leaves = keys.size
+            mesh.leaf_morton = keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+            mesh.leaf_level = lev.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         o = GmgOptions()
         for k, v in opts.items():
             if not hasattr(o, k):
@@ -178,6 +196,31 @@ class Context:
         v = ctypes.c_int64()
         self._check(self.lib.gmg_num_dofs(self.h, level, ctypes.byref(v)))
         return v.value
+
+    def num_elements(self, level=-1):
+        v = ctypes.c_int64()
+        self._check(self.lib.gmg_num_elements(self.h, self._lvl(level), ctypes.byref(v)))
+        return v.value
+
+    def dof_coords(self, level=-1):
+        """(n, 3) DoF coordinates (x, y, z) of a level."""
+        import numpy as np
+        level = self._lvl(level)
+        out = np.zeros((self.num_dofs(level), 3), dtype=np.float64)
+        self._check(self.lib.gmg_dof_coords(self.h, level, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def level_leaves(self, level=-1):
+        """(morton, level) arrays of an octree level."""
+        import numpy as np
+        level = self._lvl(level)
+        cnt = ctypes.c_int64()
+        self.lib.gmg_level_leaves(self.h, level, None, None, 0, ctypes.byref(cnt))
+        keys = np.zeros(cnt.value, dtype=np.uint64)
+        lev = np.zeros(cnt.value, dtype=np.uint8)
+        self._check(self.lib.gmg_level_leaves(self.h, level, keys.ctypes.data_as(ctypes.c_void_p),
+                                              lev.ctypes.data_as(ctypes.c_void_p), cnt.value, ctypes.byref(cnt)))
+        return keys, lev
 
     def lattice(self, level=-1):
         return round(self.num_dofs(level) ** (1.0 / 3.0))
@@ -369,3 +412,42 @@ class Context:
         if st != 0 and (raise_on_noconv or st != 5):
             self._check(st)
         return info
+
+
+def _leaves_call(fn, *args):
+    """Run an octree-construction call twice: once for the count, once to fill."""
+    import numpy as np
+    cnt = ctypes.c_int64()
+    st = fn(*args, None, None, 0, ctypes.byref(cnt))
+    if st not in (0, 1) or cnt.value <= 0:
+        raise GmgError(st, "octree construction failed")
+    keys = np.zeros(cnt.value, dtype=np.uint64)
+    lev = np.zeros(cnt.value, dtype=np.uint8)
+    st = fn(*args, keys.ctypes.data_as(ctypes.c_void_p), lev.ctypes.data_as(ctypes.c_void_p), cnt.value,
+            ctypes.byref(cnt))
+    if st != 0:
+        raise GmgError(st, "octree construction failed")
+    return keys, lev
+
+
+def octree_refine_gaussians(base_level, max_level, centres, sigma, amps, tol=1e-2):
+    """Leaves (morton, level) of the gradient-refined, 2:1-balanced octree of a Gaussian sum."""
+    import numpy as np
+    lib = load()
+    c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    a = np.ascontiguousarray(amps, dtype=np.float64)
+    if not (len(c) == len(s) == len(a)):
+        raise ValueError("centres, sigma and amps differ in length")
+    vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    return _leaves_call(lib.gmg_octree_refine_gaussians, base_level, max_level, len(a), vp(c), vp(s), vp(a), tol)
+
+
+def octree_balance(keys, levels):
+    """Leaves (morton, level) of the coarsest 2:1-balanced refinement of a complete octree."""
+    import numpy as np
+    lib = load()
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    l = np.ascontiguousarray(levels, dtype=np.uint8)
+    return _leaves_call(lib.gmg_octree_balance, k.ctypes.data_as(ctypes.c_void_p), l.ctypes.data_as(ctypes.c_void_p),
+                        k.size)

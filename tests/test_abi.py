@@ -55,3 +55,38 @@ def test_invalid_arguments_rejected_before_device_work():
         assert lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h)) == 1
     assert lib.gmg_status_string(5) == b"not converged"
     assert lib.gmg_destroy(None) == 0
+
+
+def test_invalid_octrees_rejected_before_device_work():
+    """Unsorted, incomplete or unbalanced octrees give GMG_E_MESH; q = 4 octrees and empty
+    leaf arrays give GMG_E_ARG -- all before any device call."""
+    import numpy as np
+    from oracle import octree as ot
+    from paper_1408_6497_amd import gmg
+    lib = _lib()
+    h = ctypes.c_void_p()
+    opts = gmg.GmgOptions()
+
+    def setup(order, leaves):
+        k = np.array([ot.morton(o[1], o[2], o[3]) for o in leaves], dtype=np.uint64)
+        l = np.array([o[0] for o in leaves], dtype=np.uint8)
+        mesh = gmg.GmgMesh(order=order, n=0, levels=0, reserved=0, n_leaves=k.size,
+                           leaf_morton=k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                           leaf_level=l.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        return lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h))
+
+    u = ot.uniform(2)
+    deep = set(u)
+    o = (2, 0, 0, 0)
+    for _ in range(3):
+        deep.remove(o)
+        kids = ot.children(o)
+        deep.update(kids)
+        o = kids[-1]
+    assert setup(2, ot.sort_leaves(deep)) == 2   # not 2:1 balanced
+    assert setup(2, u[:-1]) == 2                  # incomplete
+    assert setup(2, u[::-1]) == 2                 # not in Morton order
+    assert setup(2, ot.uniform(1)) == 2           # coarser than the coarsest multigrid level
+    assert setup(4, u) == 1                       # octrees take q = 1, 2
+    mesh = gmg.GmgMesh(order=2, n=0, levels=0, reserved=0, n_leaves=0)
+    assert lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h)) == 1

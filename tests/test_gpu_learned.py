@@ -171,3 +171,50 @@ def test_loss_gradient_parity(kind):
     print(f"[loss-grad] {kind}: loss gpu={loss:.6f} oracle={loss_ref:.6f} grad rel={err:.2e}", flush=True)
     assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
     assert err <= 1e-3
+
+
+def test_trained_net_gain_on_held_out_sources():
+    """What the shipped trained net (paper_1408_6497_amd/weights/q2_depth0.gmgw, made by
+    `python -m paper_1408_6497_amd.train --n 64 --sources 2500 --cycles 4 --loss residual`)
+    gains over the Chebyshev application it replaces, on sources it never saw.
+
+    Per application: the residual contraction ||r - A e~||^2 / ||r||^2 at the replaced
+    positions of plain cycles (lower is better).  Per solve: iterations and fallbacks of
+    the learned FP32 solve against the plain FP32 solve, both to 1e-8."""
+    torch = torch_cuda()
+    import os
+    from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64, LOSS_RESIDUAL
+    from paper_1408_6497_amd import train as T
+    from workloads import grf
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    w = T.load(os.path.join(here, "paper_1408_6497_amd", "weights", "q2_depth0.gmgw"))
+    assert (w["order"], w["depth"]) == (2, 0)
+    ctx = Context(2, 32, 0, seed=0, vcycle_prec=GMG_FP64)
+    cctx = Context(2, 16, 0, seed=0, vcycle_prec=GMG_FP64)
+    pm = T.PairMaker(ctx, cctx)
+    ctx.net_set_weights(0, w["w"])
+    cache = ctx.net_cache(0)
+    tmp = (torch.empty_like(pm.r32), torch.empty_like(pm.r32))
+    net, cheb = [], []
+    for seed in range(30000, 30004):
+        pm.source(seed)
+        for cyc in range(4):
+            if cyc:
+                pm.next_cycle()
+            for pos in ("pre", "post"):
+                r, _ = pm.pair(pos, need_e=False)
+                net.append(ctx.net_loss_grad(0, r, None, cache, kind=LOSS_RESIDUAL))
+                cheb.append(T.chebyshev_loss(ctx, r, None, tmp, LOSS_RESIDUAL))
+    net, cheb = float(np.mean(net)), float(np.mean(cheb))
+    out = {}
+    for name, kw in (("plain", dict(vcycle_prec=GMG_FP32)), ("learned", dict(use_learned=1))):
+        c = Context(2, 32, 0, seed=0, **kw)
+        if name == "learned":
+            c.net_set_weights(0, w["w"])
+        f, _ = grf(c.lattice(), 30000, device="cuda")
+        u = torch.empty_like(f)
+        info = c.solve(f, u, 1e-8)
+        out[name] = (info.inner_iters, info.fallbacks, info.rel_residual_f64)
+    print(f"[gain] held-out contraction: net {net:.4f} vs Chebyshev {cheb:.4f}; solves {out}", flush=True)
+    assert net < cheb
+    assert out["learned"][2] <= 1e-8 and out["learned"][0] <= out["plain"][0] + 1
