@@ -131,6 +131,83 @@ def cpu_baseline(q=2, n_sample=64, n_full=128, seed=0):
             "sample_seconds": t, "sample_iters": info.iters}
 
 
+def learned_workload(seeds=(30000, 30001, 30002, 30003, 30004), n=256):
+    """Q2 on 256^3 elements (512^3 DoFs), Gaussian-random-field sources of the held-out
+    evaluation seeds: plain FP64 CG, the FP32-cycle ablation and the learned FP32 cycle
+    (shipped depth-0 net, reused on every depth) to 1e-8; seconds per solve (graph replay)."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64
+    from paper_1408_6497_amd import train as T
+    from workloads import grf
+    w = T.load(os.path.join(ROOT, "paper_1408_6497_amd", "weights", "q2_depth0.gmgw"))["w"]
+    out = {"workload": f"Q2, {n}^3 elements ({(2 * n) ** 3} DoFs), GRF |k|^-alpha sources, seeds "
+                       f"{seeds[0]}..{seeds[-1]}, to 1e-8", "seeds": list(seeds)}
+    for name, kw in (("plain_fp64", dict(vcycle_prec=GMG_FP64)), ("fp32", dict(vcycle_prec=GMG_FP32)),
+                     ("learned_fp32", dict(use_learned=1))):
+        ctx = Context(2, n, 0, seed=0, **kw)
+        if name == "learned_fp32":
+            ctx.net_set_weights(0, w)
+        times, iters, fbs, rels = [], [], [], []
+        for i, sd in enumerate(seeds):
+            f, _ = grf(ctx.lattice(), sd, device="cuda")
+            u = torch.empty_like(f)
+            if i == 0:
+                ctx.solve(f, u, 1e-8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = ctx.solve(f, u, 1e-8)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            iters.append(info.inner_iters)
+            fbs.append(info.fallbacks)
+            rels.append(info.rel_residual_f64)
+            del f, u
+        out[name] = {"mean_s": sum(times) / len(times), "iters": iters, "fallbacks": fbs, "max_rel_residual": max(rels)}
+        log(f"[bench] learned workload {name}: {out[name]}")
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
+def octree_workload(steps=5):
+    """The adaptive workload: Q2 on the octree refined from level 3 to 9 around 4 Gaussians
+    (sigma 1e-3, seed 0); plain FP64 CG vs FP32 cycles in FP64 flexible CG, to 1e-8, plus the
+    octree apply launch time on the finest level."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64, octree_refine_gaussians
+    from workloads import gaussian_params, gaussian_source_points
+    p = gaussian_params(0, 4, 1e-3, 1e-3)
+    t0 = time.perf_counter()
+    leaves = octree_refine_gaussians(3, 9, p["centres"], p["sigma"], p["amps"])
+    t_tree = time.perf_counter() - t0
+    out = {"workload": "Q2 octree, leaf levels 3..9 refined on a gradient bound around 4 Gaussians "
+                       "(sigma 1e-3, seed 0), hanging nodes, to 1e-8", "leaves": int(leaves[0].size),
+           "tree_build_s": t_tree}
+    for name, kw in (("plain_fp64", dict(vcycle_prec=GMG_FP64)), ("fp32", dict(vcycle_prec=GMG_FP32))):
+        ctx = Context(2, 0, leaves=leaves, seed=0, **kw)
+        f = torch.from_numpy(gaussian_source_points(ctx.dof_coords(), p)).cuda()
+        u = torch.empty_like(f)
+        ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        out[name] = {"s": (time.perf_counter() - t0) / steps, "iters": info.inner_iters,
+                     "rel_residual_f64": info.rel_residual_f64, "setup_s": info.t_setup}
+        out["dofs"] = ctx.num_dofs()
+        out["levels"] = ctx.levels
+        ctx.close()
+    ctxt = Context(2, 0, leaves=leaves, seed=0, timing=1)
+    for prec in (GMG_FP32, GMG_FP64):
+        r = apply_rate(ctxt, prec)
+        out["apply_" + ("fp32" if prec == GMG_FP32 else "fp64")] = {"us": r["sec"] * 1e6, "gdofs": r["gdofs"]}
+    ctxt.close()
+    log(f"[bench] octree workload: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +215,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-apply-bench", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the learned-smoother (512^3 DoFs) and octree workloads")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a 256 MiB device copy (counter calibration), then one eager "
                          "mixed solve of the bench problem; prints nothing on stdout")
@@ -219,6 +298,11 @@ def main():
         big.close()
         log(f"[bench] apply {json.dumps(apply)}")
 
+    extra = {}
+    if not args.no_extra:
+        extra["learned"] = learned_workload()
+        extra["octree"] = octree_workload()
+
     traffic = traffic_record()
     cpu = None
     if not args.no_cpu_baseline:
@@ -264,6 +348,7 @@ def main():
             "launches": launches, "avg_launch_us": avg_dur * 1e6, "per_level": per_level,
         },
         "cpu_baseline": cpu,
+        "workloads": extra,
     }
     print(json.dumps(out), flush=True)
 
