@@ -44,6 +44,9 @@ enum : int {
   S_ER = 10,    // e^T r        (training loss)
   S_ED = 11,    // e^T (r - A e~)
   S_TD = 12,    // e~^T (r - A e~)
+  S_ZS = 13,    // sum z            (fused direction update)
+  S_YS = 14,    // sum w or sum r   (fused direction update)
+  S_ZWC = 15,   // (z - mean z) . w
   S_SSUM = 16,  // + level: sum of (D^-1 r)^2 of the learned correction on that level
 };
 
@@ -684,13 +687,15 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       have_dir = true;
     }
     STCHK(apply_op(c, l, pi, Epi::Apply, p, w, nullptr, nullptr, 0, 0));
-    HIPCHK(c, launch_dot(f32, n, p, w, c->part, c->scal + S_PW, s));
-    if (flexible) HIPCHK(c, launch_dot(f32, n, p, r, c->part, c->scal + S_PR, s));
-    HIPCHK(c, launch_axpy2(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, s));
-    STCHK(project(c, pi, n, r));
-    HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+    if (flexible) HIPCHK(c, launch_dot2(f32, n, p, w, r, c->part, c->scal, S_PW, S_PR, s));
+    else HIPCHK(c, launch_dot(f32, n, p, w, c->part, c->scal + S_PW, s));
+    // u += alpha p, r -= alpha w, with sum(r) and r.r of the new r in the same pass;
+    // the projection r <- r - mean(r) follows, and ||r - mean||^2 = r.r - (sum r)^2 / n
+    HIPCHK(c, launch_axpy2_sums(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, c->part, S_SUM, S_RR, s));
+    HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, 1.0 / static_cast<double>(n), r, s));
     STCHK(read_scalars(c, hs, kNumScal));
-    rr = hs[S_RR];
+    rr = std::max(0.0, hs[S_RR] - hs[S_SUM] * hs[S_SUM] / static_cast<double>(n));
+    if (!std::isfinite(hs[S_RR])) rr = hs[S_RR];
     c->hist_res.push_back(std::sqrt(rr));
     ++it;
     if (!finite_pos(hs[S_PW])) {
@@ -700,14 +705,18 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     }
     if (std::sqrt(rr) <= tol_abs) continue;
     STCHK(precondition(c, pi, vpi, r, z));
-    STCHK(project(c, pi, n, z));
+    // z is projected inside the direction update: p = (z - mean z) + beta p, with
+    // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
+    const double inv_n = 1.0 / static_cast<double>(n);
     if (flexible) {
-      HIPCHK(c, launch_dot(f32, n, z, w, c->part, c->scal + S_ZW, s));
-      HIPCHK(c, launch_xpby(f32, n, c->scal, S_ZW, S_PW, -1.0, z, p, s));
+      HIPCHK(c, launch_sums3(f32, n, z, w, c->part, c->scal, S_ZS, S_ZW, S_YS, s));
+      HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
+      HIPCHK(c, launch_xpby_shift(f32, n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z, p, s));
     } else {
       const int rzn = rz == S_RZ0 ? S_RZ1 : S_RZ0;
-      HIPCHK(c, launch_dot(f32, n, r, z, c->part, c->scal + rzn, s));
-      HIPCHK(c, launch_xpby(f32, n, c->scal, rzn, rz, 1.0, z, p, s));
+      HIPCHK(c, launch_sums3(f32, n, z, r, c->part, c->scal, S_ZS, rzn, S_YS, s));
+      HIPCHK(c, launch_combine(c->scal, rzn, rzn, S_ZS, S_YS, inv_n, s));
+      HIPCHK(c, launch_xpby_shift(f32, n, c->scal, rzn, rz, 1.0, S_ZS, inv_n, z, p, s));
       rz = rzn;
     }
   }
@@ -1000,7 +1009,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     make_transfer_table(q, &c->xfer);
   }
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
-  c->part_cap = std::max<int64_t>(kRedBlocks, static_cast<int64_t>(c->lv.back().N) * c->lv.back().N);
+  c->part_cap = std::max<int64_t>(3 * kRedBlocks, static_cast<int64_t>(c->lv.back().N) * c->lv.back().N);
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->part), sizeof(double) * c->part_cap)) != GMG_OK) return bail(st);
   if (hipMemsetAsync(c->scal, 0, sizeof(double) * kNumScal, c->stream) != hipSuccess) return bail(GMG_E_HIP);
   if ((st = ensure_prec(c, 0)) != GMG_OK) return bail(st);

@@ -133,6 +133,21 @@ constexpr int kRedBlocks = 1024;
 hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double* part, double* dst,
                       hipStream_t s);
 hipError_t launch_sum(bool fp32, int64_t n, const void* x, double* part, double* dst, hipStream_t s);
+// Fused Krylov reductions (part needs 3 * kRedBlocks doubles; results go to scalar slots of sc):
+//   dot2:        sc[dxy] = x.y, sc[dxz] = x.z
+//   axpy2_sums:  u += a p, r -= a w (a = sc[inum] / sc[iden]); sc[dsum] = sum r, sc[dsq] = r.r
+//   sums3:       sc[dz] = sum z, sc[dzy] = z.y, sc[dy] = sum y
+//   combine:     sc[dst] = sc[a] - sc[b] sc[c] scale (one thread)
+//   xpby_shift:  p = (z - sc[imean] scale) + (sgn sc[inum] / sc[iden]) p
+hipError_t launch_dot2(bool fp32, int64_t n, const void* x, const void* y, const void* z, double* part, double* sc,
+                       int dxy, int dxz, hipStream_t s);
+hipError_t launch_axpy2_sums(bool fp32, int64_t n, double* sc, int inum, int iden, void* u, const void* p, void* r,
+                             const void* w, double* part, int dsum, int dsq, hipStream_t s);
+hipError_t launch_sums3(bool fp32, int64_t n, const void* z, const void* y, double* part, double* sc, int dz,
+                        int dzy, int dy, hipStream_t s);
+hipError_t launch_combine(double* sc, int dst, int a, int b, int c, double scale, hipStream_t s);
+hipError_t launch_xpby_shift(bool fp32, int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
+                             double scale, const void* z, void* p, hipStream_t s);
 // sum_i tab[class(i)] x_i (the integral of the FE function on a uniform level);
 // needs N^2 partials in `part` (capacity part_cap).
 hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const void* x, double* part,

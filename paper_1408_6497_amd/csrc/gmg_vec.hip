@@ -98,6 +98,124 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double* part, const int
   if (threadIdx.x == 0) *dst = s;
 }
 
+// Three block sums at once (valid in thread 0): one LDS round, no reuse hazard.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red[3][kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+    c += __shfl_down(c, off, 64);
+  }
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wid] = a;
+    red[1][wid] = b;
+    red[2][wid] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = b = c = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+      c += red[2][w];
+    }
+  }
+}
+
+// Fused reductions of the Krylov loop.  Each block writes its partials to
+// part[k * nblocks + block] (k = 0, 1, 2); k_finish_multi folds them in a fixed order.
+// (x.y, x.z)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot2(const int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                                                 const T* __restrict__ z, double* part) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double xv = static_cast<double>(x[i]);
+    a = fma(xv, static_cast<double>(y[i]), a);
+    b = fma(xv, static_cast<double>(z[i]), b);
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// u += alpha p, r -= alpha w (alpha = sc[inum] / sc[iden]); partial sum(r) and r.r of the new r
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_axpy2_sums(const int64_t n, const double* sc, const int inum,
+                                                       const int iden, T* u, const T* __restrict__ p, T* r,
+                                                       const T* __restrict__ w, double* part) {
+  const T al = static_cast<T>(sc[inum] / sc[iden]);
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    u[i] = fma(al, p[i], u[i]);
+    const T rn = fma(-al, w[i], r[i]);
+    r[i] = rn;
+    const double rd = static_cast<double>(rn);
+    a += rd;
+    b = fma(rd, rd, b);
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// (sum z, z.y, sum y)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sums3(const int64_t n, const T* __restrict__ z, const T* __restrict__ y,
+                                                  double* part) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double zv = static_cast<double>(z[i]);
+    const double yv = static_cast<double>(y[i]);
+    a += zv;
+    b = fma(zv, yv, b);
+    c += yv;
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+    part[2 * gridDim.x + blockIdx.x] = c;
+  }
+}
+
+// dst[k] = sum of the k-th run of nparts partials, k < count (one block per k)
+__global__ void __launch_bounds__(kBlock) k_finish_multi(const double* part, const int nparts, double* sc,
+                                                         const int d0, const int d1, const int d2) {
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[static_cast<size_t>(k) * nparts + i];
+  double u = 0.0, v = 0.0;
+  block_sum3(s, u, v);
+  if (threadIdx.x == 0) sc[k == 0 ? d0 : (k == 1 ? d1 : d2)] = s;
+}
+
+// sc[dst] = sc[a] - sc[b] sc[c] scale   (one thread)
+__global__ void k_combine(double* sc, const int dst, const int a, const int b, const int c, const double scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[dst] = sc[a] - sc[b] * sc[c] * scale;
+}
+
+// p = (z - sc[imean] scale) + beta p,  beta = sgn sc[inum] / sc[iden]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_xpby_shift(const int64_t n, const double* sc, const int inum,
+                                                       const int iden, const double sgn, const int imean,
+                                                       const double scale, const T* __restrict__ z, T* p) {
+  const T be = static_cast<T>(sgn * sc[inum] / sc[iden]);
+  const T m = static_cast<T>(sc[imean] * scale);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = fma(be, p[i], z[i] - m);
+}
+
 inline int red_grid(int64_t n) {
   int g = grid_for(n, 8);
   return g > kRedBlocks ? kRedBlocks : g;
@@ -255,6 +373,63 @@ hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double
     hipLaunchKernelGGL(k_dot<double>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const double*>(x),
                        static_cast<const double*>(y), part);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2(bool fp32, int64_t n, const void* x, const void* y, const void* z, double* part, double* sc,
+                       int dxy, int dxz, hipStream_t s) {
+  const int g = red_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_dot2<float>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const float*>(x),
+                       static_cast<const float*>(y), static_cast<const float*>(z), part);
+  else
+    hipLaunchKernelGGL(k_dot2<double>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const double*>(x),
+                       static_cast<const double*>(y), static_cast<const double*>(z), part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, dxy, dxz, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy2_sums(bool fp32, int64_t n, double* sc, int inum, int iden, void* u, const void* p, void* r,
+                             const void* w, double* part, int dsum, int dsq, hipStream_t s) {
+  const int g = red_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_axpy2_sums<float>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, static_cast<float*>(u),
+                       static_cast<const float*>(p), static_cast<float*>(r), static_cast<const float*>(w), part);
+  else
+    hipLaunchKernelGGL(k_axpy2_sums<double>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden,
+                       static_cast<double*>(u), static_cast<const double*>(p), static_cast<double*>(r),
+                       static_cast<const double*>(w), part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, dsum, dsq, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_sums3(bool fp32, int64_t n, const void* z, const void* y, double* part, double* sc, int dz,
+                        int dzy, int dy, hipStream_t s) {
+  const int g = red_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_sums3<float>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const float*>(z),
+                       static_cast<const float*>(y), part);
+  else
+    hipLaunchKernelGGL(k_sums3<double>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const double*>(z),
+                       static_cast<const double*>(y), part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(3), dim3(kBlock), 0, s, part, g, sc, dz, dzy, dy);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(double* sc, int dst, int a, int b, int c, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, s, sc, dst, a, b, c, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby_shift(bool fp32, int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
+                             double scale, const void* z, void* p, hipStream_t s) {
+  const int g = grid_for(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_xpby_shift<float>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, sgn, imean, scale,
+                       static_cast<const float*>(z), static_cast<float*>(p));
+  else
+    hipLaunchKernelGGL(k_xpby_shift<double>, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, sgn, imean, scale,
+                       static_cast<const double*>(z), static_cast<double*>(p));
   return hipGetLastError();
 }
 
