@@ -170,6 +170,33 @@ def learned_workload(seeds=(30000, 30001, 30002, 30003, 30004), n=256):
     return out
 
 
+def q4_workload(steps=5):
+    """Q4 on 64^3 elements (256^3 DoFs), 8 Gaussians with sigma log-uniform in [1e-3, 1e-2]
+    (seed 0): plain FP64 CG vs FP32 cycles in FP64 flexible CG, to 1e-8."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64
+    from workloads import gaussian_params, gaussian_source
+    params = gaussian_params(0, 8, 1e-3, 1e-2, log_uniform=True)
+    out = {"workload": "Q4, 64^3 elements (256^3 DoFs), 8 Gaussians sigma log-uniform [1e-3, 1e-2], seed 0, to 1e-8"}
+    for name, kw in (("plain_fp64", dict(vcycle_prec=GMG_FP64)), ("fp32", dict(vcycle_prec=GMG_FP32))):
+        ctx = Context(4, 64, 0, seed=0, **kw)
+        f = gaussian_source(ctx.dof_coords_1d(), params, device="cuda")
+        u = torch.empty_like(f)
+        ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        out[name] = {"s": (time.perf_counter() - t0) / steps, "iters": info.inner_iters,
+                     "rel_residual_f64": info.rel_residual_f64}
+        ctx.close()
+        del f, u
+        torch.cuda.empty_cache()
+    log(f"[bench] q4 workload: {out}")
+    return out
+
+
 def octree_workload(steps=5):
     """The adaptive workload: Q2 on the octree refined from level 3 to 9 around 4 Gaussians
     (sigma 1e-3, seed 0); plain FP64 CG vs FP32 cycles in FP64 flexible CG, to 1e-8, plus the
@@ -301,6 +328,7 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["learned"] = learned_workload()
+        extra["q4_sharp"] = q4_workload()
         extra["octree"] = octree_workload()
 
     traffic = traffic_record()

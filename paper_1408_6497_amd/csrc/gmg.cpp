@@ -400,7 +400,7 @@ gmg_status learned_correction(gmg_ctx* c, int l, const void* b, void* u) {
   HIPCHK(c, launch_net_input(static_cast<const float*>(L.xp[1]), L.tab.stiff.dinv, c->q, c->scal + S_SSUM + l,
                              c->part, L.N, c->lcache[l], c->stream));
   HIPCHK(c, launch_net_forward(c->nets[d], L.N, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
-                               c->stream));
+                               c->stream, false));
   return GMG_OK;
 }
 
@@ -1529,7 +1529,7 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
     HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ctx->scal + S_SSUM + level, ctx->part, L.N,
                                  ctx->lcache[level], ctx->stream));
     HIPCHK(ctx, launch_net_forward(ctx->nets[d], L.N, ctx->lcache[level], 1, ctx->scal + S_SSUM + level, e_dev,
-                                   ctx->stream));
+                                   ctx->stream, false));
     return GMG_OK;
   });
 }

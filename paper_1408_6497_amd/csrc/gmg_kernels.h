@@ -204,9 +204,10 @@ hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s);
 // (dinv == null: x_in = bf16(r), ssum unused); part needs N^2 doubles.
 hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part, int N,
                             void* cache, hipStream_t s);
-// y = N(x_in) (mode 0) or y += s N(x_in) with s = sqrt(*ssum / N^3) (mode 1)
+// y = N(x_in) (mode 0) or y += s N(x_in) with s = sqrt(*ssum / N^3) (mode 1).
+// The cache receives a2 always and a1 only with keep_a1 (what the backward pass reads).
 hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, const double* ssum, float* y,
-                              hipStream_t s);
+                              hipStream_t s, bool keep_a1 = true);
 // gw += d(sum gy . y)/dw; gin = d(sum gy . y)/dx_in when non-null.  g1g2: 64 bytes per voxel.
 hipError_t launch_net_backward(const NetDev& d, int N, const void* cache, const float* gy, void* g1g2, float* part,
                                float* gw, float* gin, hipStream_t s);

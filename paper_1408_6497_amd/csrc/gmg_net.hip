@@ -13,12 +13,19 @@
 // bytes) per voxel, voxel index i + N (j + N k).  A tap t = (dz+1) 9 + (dy+1) 3
 // + (dx+1) reads the voxel at offset (dx, dy, dz), wrapped periodically.
 //
-// Layer 2 (6912 of the 7776 multiply-adds per voxel) runs on the matrix cores:
-// v_mfma_f32_16x16x16_bf16 with the 16x16 weight block of a tap as A (held in
-// registers for all 27 taps), 16 input channels x 16 voxels along x as B (read
-// from an LDS brick with a one-voxel halo), accumulating 16 output channels x
-// 16 voxels over the 27 taps.  The same kernel does the backward-data pass with
-// the flipped, transposed weights and the ReLU mask of the forward pass.
+// Forward pass, two kernels per application:
+//   k_net_l12  one 16x8x4 brick per block: bf16(x) with a two-voxel halo in LDS;
+//              layer 1 on the matrix cores over the brick plus a one-voxel halo
+//              (27 taps padded to K = 32); a1 stays in LDS; layer 2 (6912 of the
+//              7776 multiply-adds per voxel) on v_mfma_f32_16x16x16_bf16 with the
+//              16x16 weight block of a tap as A (registers, all 27 taps) and 16
+//              input channels x 16 voxels along x as B (from the LDS tile),
+//              accumulating 16 output channels x 16 voxels over the 27 taps; a2
+//              to HBM (32 B per voxel), a1 only when training keeps it.
+//   k_net_l3t  layer 3 over the same bricks from an LDS tile of a2, two voxels
+//              per thread, with the output update u += s y fused.
+// The backward-data pass of layer 2 is k_net_l2 with the flipped, transposed
+// weights and the ReLU mask of the forward pass.
 #include <algorithm>
 
 #include "gmg_kernels.h"
@@ -39,6 +46,14 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return static_cast<uint16_t>(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to packed BF16 (round to nearest even: v_cvt_pk_bf16_f32), a in the low half.
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  const bf16x2 v = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+  return __builtin_bit_cast(uint32_t, v);
+}
 
 __device__ __forceinline__ size_t vox(int i, int j, int k, int N) {
   return (static_cast<size_t>(k) * N + j) * N + i;
@@ -95,34 +110,6 @@ __global__ void __launch_bounds__(kBlk) k_net_sqsum(const float* __restrict__ r,
     for (int w = 0; w < kBlk / 64; ++w) t += red[w];
     part[static_cast<size_t>(k) * N + j] = t;
   }
-}
-
-// ---------------------------------------------------------------------------- layer 1 (1 -> 16)
-__global__ void __launch_bounds__(kBlk) k_net_l1(const uint16_t* __restrict__ xin, const float* __restrict__ w1q,
-                                                 const int N, uint16_t* __restrict__ a1) {
-  __shared__ float w[kTaps * kNC];  // [t][co]
-  for (int e = threadIdx.x; e < kTaps * kNC; e += kBlk) w[e] = w1q[e];
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i >= N) return;
-  float z[kNC];
-#pragma unroll
-  for (int c = 0; c < kNC; ++c) z[c] = 0.0f;
-#pragma unroll
-  for (int t = 0; t < kTaps; ++t) {
-    const float x = bf2f(xin[nbr(i, j, k, t, 1, N)]);
-#pragma unroll
-    for (int c = 0; c < kNC; ++c) z[c] = fmaf(w[t * kNC + c], x, z[c]);
-  }
-  uint32_t p[kNC / 2];
-#pragma unroll
-  for (int c = 0; c < kNC / 2; ++c)
-    p[c] = static_cast<uint32_t>(f2bf(fmaxf(z[2 * c], 0.0f))) |
-           (static_cast<uint32_t>(f2bf(fmaxf(z[2 * c + 1], 0.0f))) << 16);
-  uint4* dst = reinterpret_cast<uint4*>(a1 + vox(i, j, k, N) * kNC);
-  dst[0] = make_uint4(p[0], p[1], p[2], p[3]);
-  dst[1] = make_uint4(p[4], p[5], p[6], p[7]);
 }
 
 // ---------------------------------------------------------------------------- layer 2 (16 -> 16, MFMA)
@@ -193,8 +180,213 @@ __global__ void __launch_bounds__(kBlk) k_net_l2(const uint16_t* __restrict__ in
   }
 }
 
-// ---------------------------------------------------------------------------- layer 3 (16 -> 1)
-// y = W3 * a2;  mode 0: y_out[v] = y;  mode 1: u[v] += s y with s = sqrt(ssum / N^3)
+// ---------------------------------------------------------------------------- fused layers 1 + 2
+// One block per 16x8x4 output brick.  bf16(x) of the brick plus a two-voxel halo
+// goes to LDS; layer 1 runs on the matrix cores over the brick plus a one-voxel
+// halo (27 taps as K = 32: two v_mfma_f32_16x16x16_bf16 per 16 voxels, W1 as A,
+// the taps of 16 voxels as B), ReLU and BF16 rounding, into an LDS tile of the
+// same layout layer 2 reads; layer 2 then runs as in k_net_l2.  a1 never goes to
+// HBM unless the caller keeps it (training: the backward pass reads it).
+constexpr int kXX = kBX + 4, kXY = kBY + 4, kXZ = kBZ + 4;  // input tile with a two-voxel halo
+constexpr int kHalo = kHX * kHY * kHZ;                      // 1080 voxels of layer 1 output
+
+template <bool KEEP_A1>
+__global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ xin, const float* __restrict__ w1q,
+                                                  const uint16_t* __restrict__ wA, const int N,
+                                                  uint16_t* __restrict__ a1_out, uint16_t* __restrict__ a2_out) {
+  __shared__ uint16_t xt[kXZ * kXY * kXX];
+  __shared__ uint2 tile[kHalo * 4];
+  const int nbx = N / kBX, nby = N / kBY;
+  const int b = blockIdx.x;
+  const int x0 = (b % nbx) * kBX;
+  const int y0 = ((b / nbx) % nby) * kBY;
+  const int z0 = (b / (nbx * nby)) * kBZ;
+  const int m = N - 1;
+  for (int e = threadIdx.x; e < kXZ * kXY * kXX; e += kBlk) {
+    const int hx = e % kXX, hy = (e / kXX) % kXY, hz = e / (kXX * kXY);
+    xt[e] = xin[vox((x0 - 2 + hx) & m, (y0 - 2 + hy) & m, (z0 - 2 + hz) & m, N)];
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int kb = lane >> 4;
+  // W1 as the A operand: row = output channel col, k = taps 16 j + 4 kb + r
+  bf16x4 w1a[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    short h[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = 16 * j + 4 * kb + r;
+      h[r] = t < kTaps ? static_cast<short>(f2bf(w1q[t * kNC + col])) : static_cast<short>(0);
+    }
+    w1a[j] = bf16x4{h[0], h[1], h[2], h[3]};
+  }
+  bf16x4 wa[kTaps];
+  const uint2* wA2 = reinterpret_cast<const uint2*>(wA);
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) {
+    const uint2 u = wA2[(t * kNC + col) * 4 + kb];
+    wa[t] = *reinterpret_cast<const bf16x4*>(&u);
+  }
+  __syncthreads();
+  // per-lane tap offsets in the input tile: taps 16 j + 4 kb + r (taps >= 27 read zero)
+  int toff[8];
+  bool tuse[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int t = 16 * (i >> 2) + 4 * kb + (i & 3);
+    tuse[i] = t < kTaps;
+    const int dx = (t % 3) - 1, dy = ((t / 3) % 3) - 1, dz = (t / 9) - 1;
+    toff[i] = tuse[i] ? (dz * kXY + dy) * kXX + dx : 0;
+  }
+  // layer 1 over the 1080 voxels of the brick plus a one-voxel halo, 16 at a time
+  for (int g = wave; g < (kHalo + 15) / 16; g += kBlk / 64) {
+    const int e = 16 * g + col;
+    const bool live = e < kHalo;
+    const int ec = live ? e : kHalo - 1;
+    const int hz = ec / (kHX * kHY);
+    const int rem = ec - hz * (kHX * kHY);
+    const int hy = rem / kHX;
+    const int hx = rem - hy * kHX;
+    const int base = ((hz + 1) * kXY + (hy + 1)) * kXX + (hx + 1);
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      short h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[r] = tuse[4 * j + r] ? static_cast<short>(xt[base + toff[4 * j + r]]) : short(0);
+      const bf16x4 bv{h[0], h[1], h[2], h[3]};
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1a[j], bv, acc, 0, 0, 0);
+    }
+    // lane holds output channels 4 kb .. 4 kb + 3 of voxel e
+    uint2 pk;
+    pk.x = pack2(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f));
+    pk.y = pack2(fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
+    if (live) {
+      tile[e * 4 + kb] = pk;
+      if (KEEP_A1 && hx >= 1 && hx <= kBX && hy >= 1 && hy <= kBY && hz >= 1 && hz <= kBZ)
+        reinterpret_cast<uint2*>(a1_out)[vox(x0 + hx - 1, y0 + hy - 1, z0 + hz - 1, N) * 4 + kb] = pk;
+    }
+  }
+  __syncthreads();
+  // layer 2: wave tz owns the 8 output rows of plane tz (16 channels x 16 voxels
+  // each).  Every a1 row loaded from LDS feeds the up to three output rows it is
+  // a y-neighbour of, so the tile is read 90 times per wave instead of 216.
+  static_assert(kBlk / 64 == kBZ, "one wave per plane of the brick");
+  const int tz = wave;
+  floatx4 acc[kBY];
+#pragma unroll
+  for (int ty = 0; ty < kBY; ++ty) acc[ty] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx)
+#pragma unroll
+      for (int r = 0; r < kHY; ++r) {
+        const uint2 u = tile[(((tz + 1 + dz) * kHY + r) * kHX + (col + 1 + dx)) * 4 + kb];
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&u);
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int ty = r - 1 - dy;
+          if (ty < 0 || ty >= kBY) continue;
+          const int t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+          acc[ty] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], bv, acc[ty], 0, 0, 0);
+        }
+      }
+#pragma unroll
+  for (int ty = 0; ty < kBY; ++ty) {
+    const size_t v = vox(x0 + col, y0 + ty, z0 + tz, N);
+    uint2 pk;
+    pk.x = pack2(fmaxf(acc[ty][0], 0.0f), fmaxf(acc[ty][1], 0.0f));
+    pk.y = pack2(fmaxf(acc[ty][2], 0.0f), fmaxf(acc[ty][3], 0.0f));
+    reinterpret_cast<uint2*>(a2_out)[v * 4 + kb] = pk;
+  }
+}
+
+// ---------------------------------------------------------------------------- layer 3, LDS-tiled
+// y = W3 * a2 over one 16x8x4 brick: a2 of the brick plus a one-voxel halo in LDS,
+// each thread two neighbouring voxels along x (the 4 x-columns they need are read
+// once for both).  Channel pairs go through v_dot2c_f32_bf16 (two BF16 products
+// added to the FP32 accumulator) straight from the packed activations; the sum
+// runs over taps t = 0..26, then channel pairs.  Tile rows are padded by 16 bytes
+// so the 128-bit reads of neighbouring rows fall on different LDS banks.
+constexpr int kRowU2 = kHX * 4 + 2;  // uint2 per padded tile row
+
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
+}
+
+__global__ void __launch_bounds__(kBlk) k_net_l3t(const uint16_t* __restrict__ a2, const float* __restrict__ w3q,
+                                                  const int N, const int mode, const double* __restrict__ ssum,
+                                                  float* __restrict__ y) {
+  __shared__ __align__(16) uint2 tile[kHZ * kHY * kRowU2];
+  __shared__ uint32_t w[kTaps * kNC / 2];  // [t][channel pair], BF16 pairs
+  const int nbx = N / kBX, nby = N / kBY;
+  const int b = blockIdx.x;
+  const int x0 = (b % nbx) * kBX;
+  const int y0 = ((b / nbx) % nby) * kBY;
+  const int z0 = (b / (nbx * nby)) * kBZ;
+  const int m = N - 1;
+  const uint2* in2 = reinterpret_cast<const uint2*>(a2);
+  for (int e = threadIdx.x; e < kHalo * 4; e += kBlk) {
+    const int c = e & 3;
+    const int vx = e >> 2;
+    const int hx = vx % kHX, hy = (vx / kHX) % kHY, hz = vx / (kHX * kHY);
+    tile[(hz * kHY + hy) * kRowU2 + hx * 4 + c] =
+        in2[vox((x0 - 1 + hx) & m, (y0 - 1 + hy) & m, (z0 - 1 + hz) & m, N) * 4 + c];
+  }
+  for (int e = threadIdx.x; e < kTaps * kNC / 2; e += kBlk)
+    w[e] = static_cast<uint32_t>(f2bf(w3q[2 * e])) | (static_cast<uint32_t>(f2bf(w3q[2 * e + 1])) << 16);
+  __syncthreads();
+  const int xp = threadIdx.x & 7;          // voxel pair along x
+  const int ty = (threadIdx.x >> 3) & 7;
+  const int tz = threadIdx.x >> 6;
+  const int hx0 = 2 * xp;                   // halo column of x - 1 for the first voxel
+  float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int rowb = ((tz + 1 + dz) * kHY + (ty + 1 + dy)) * kRowU2;
+      uint32_t a[4][kNC / 2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint4* q = reinterpret_cast<const uint4*>(tile + rowb + (hx0 + k) * 4);
+        const uint4 u0 = q[0], u1 = q[1];
+        a[k][0] = u0.x;
+        a[k][1] = u0.y;
+        a[k][2] = u0.z;
+        a[k][3] = u0.w;
+        a[k][4] = u1.x;
+        a[k][5] = u1.y;
+        a[k][6] = u1.z;
+        a[k][7] = u1.w;
+      }
+      const int tb = (dz + 1) * 9 + (dy + 1) * 3;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const uint32_t* wt = w + (tb + dx) * (kNC / 2);
+#pragma unroll
+        for (int c = 0; c < kNC / 2; ++c) {
+          acc0 = dot2(a[dx][c], wt[c], acc0);
+          acc1 = dot2(a[dx + 1][c], wt[c], acc1);
+        }
+      }
+    }
+  const size_t v = vox(x0 + 2 * xp, y0 + ty, z0 + tz, N);
+  if (mode == 0) {
+    y[v] = acc0;
+    y[v + 1] = acc1;
+  } else {
+    const double nn = static_cast<double>(N) * N * N;
+    const float sc = static_cast<float>(sqrt(*ssum / nn));
+    y[v] += sc * acc0;
+    y[v + 1] += sc * acc1;
+  }
+}
+
+// 16 BF16 channels of one voxel (32 bytes) to FP32
 __device__ __forceinline__ void load16(const uint16_t* p, float* f) {
   const uint4* q = reinterpret_cast<const uint4*>(p);
   const uint4 a = q[0], b = q[1];
@@ -203,33 +395,6 @@ __device__ __forceinline__ void load16(const uint16_t* p, float* f) {
   for (int c = 0; c < 8; ++c) {
     f[2 * c] = __uint_as_float(w[c] << 16);
     f[2 * c + 1] = __uint_as_float(w[c] & 0xFFFF0000u);
-  }
-}
-
-__global__ void __launch_bounds__(kBlk) k_net_l3(const uint16_t* __restrict__ a2, const float* __restrict__ w3q,
-                                                 const int N, const int mode, const double* __restrict__ ssum,
-                                                 float* __restrict__ y) {
-  __shared__ float w[kTaps * kNC];  // [t][ci]
-  for (int e = threadIdx.x; e < kTaps * kNC; e += kBlk) w[e] = w3q[e];
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y, k = blockIdx.z;
-  if (i >= N) return;
-  float acc = 0.0f;
-#pragma unroll 3
-  for (int t = 0; t < kTaps; ++t) {
-    float a[kNC];
-    load16(a2 + nbr(i, j, k, t, 1, N) * kNC, a);
-#pragma unroll
-    for (int c = 0; c < kNC; ++c) acc = fmaf(w[t * kNC + c], a[c], acc);
-  }
-  const size_t v = vox(i, j, k, N);
-  if (mode == 0) {
-    y[v] = acc;
-  } else {
-    const double nn = static_cast<double>(N) * N * N;
-    const float s = static_cast<float>(sqrt(*ssum / nn));
-    y[v] += s * acc;
   }
 }
 
@@ -498,16 +663,18 @@ hipError_t launch_net_input(const float* r, const double* dinv, int q, const dou
 }
 
 hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, const double* ssum, float* y,
-                              hipStream_t s) {
+                              hipStream_t s, bool keep_a1) {
   if (N < 16 || (N & (N - 1)) != 0) return hipErrorInvalidValue;
   const int64_t nv = static_cast<int64_t>(N) * N * N;
   uint16_t* xin = static_cast<uint16_t*>(cache);
   uint16_t* a1 = reinterpret_cast<uint16_t*>(static_cast<char*>(cache) + (nv * 2 + 255) / 256 * 256);
   uint16_t* a2 = a1 + nv * kNC;
-  hipLaunchKernelGGL(k_net_l1, vgrid(N), dim3(kBlk), 0, s, xin, d.w1q, N, a1);
   const int nb = (N / kBX) * (N / kBY) * (N / kBZ);
-  hipLaunchKernelGGL(k_net_l2<false>, dim3(nb), dim3(kBlk), 0, s, a1, d.w2f, nullptr, N, a2);
-  hipLaunchKernelGGL(k_net_l3, vgrid(N), dim3(kBlk), 0, s, a2, d.w3q, N, mode, ssum, y);
+  if (keep_a1)
+    hipLaunchKernelGGL(k_net_l12<true>, dim3(nb), dim3(kBlk), 0, s, xin, d.w1q, d.w2f, N, a1, a2);
+  else
+    hipLaunchKernelGGL(k_net_l12<false>, dim3(nb), dim3(kBlk), 0, s, xin, d.w1q, d.w2f, N, nullptr, a2);
+  hipLaunchKernelGGL(k_net_l3t, dim3(nb), dim3(kBlk), 0, s, a2, d.w3q, N, mode, ssum, y);
   return hipGetLastError();
 }
 
