@@ -243,7 +243,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-apply-bench", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the learned-smoother (512^3 DoFs) and octree workloads")
+                    help="skip the learned-smoother (512^3 DoFs), Q4 and octree workloads")
+    ap.add_argument("--profile-workload", choices=("learned", "q4", "octree"), default=None,
+                    help="for profilers: run only this workload and print its JSON (no timed bench step)")
+    ap.add_argument("--profile-n", type=int, default=256,
+                    help="elements per direction of the learned workload under --profile-workload")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a 256 MiB device copy (counter calibration), then one eager "
                          "mixed solve of the bench problem; prints nothing on stdout")
@@ -257,6 +261,15 @@ def main():
     from workloads import gaussian_params, gaussian_source
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.profile_workload:
+        if args.profile_workload == "learned":
+            res = learned_workload(seeds=(30000, 30001), n=args.profile_n)
+        elif args.profile_workload == "q4":
+            res = q4_workload()
+        else:
+            res = octree_workload()
+        print(json.dumps(res), flush=True)
+        return
     q, n, seed = 2, 128, 0
     if args.traffic_probe:
         a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
