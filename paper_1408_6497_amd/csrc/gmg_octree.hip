@@ -55,40 +55,55 @@ __global__ void __launch_bounds__(kB) k_oct_elem(const int64_t E, const uint8_t*
   }
 }
 
-template <typename T, int EPI>
+// Sum over one CSR row with LPR lanes per row: lane i takes entries i, i + LPR, ...,
+// then a fixed butterfly of shuffles adds the lanes (the same order on every run).
+// Every lane of the wave takes part in the shuffles; rows past the end add zeros.
+template <typename T, int LPR, typename F>
+__device__ __forceinline__ T row_sum(const int* __restrict__ ptr, int64_t row, bool live, int sub, F term) {
+  T s = T(0);
+  if (live)
+    for (int j = ptr[row] + sub; j < ptr[row + 1]; j += LPR) s += term(j);
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+template <typename T, int EPI, int LPR>
 __global__ void __launch_bounds__(kB) k_oct_dof(const int64_t n, const int* __restrict__ tptr,
                                                 const int* __restrict__ trow, const T* __restrict__ tval,
                                                 const T* __restrict__ ye, const T* __restrict__ x,
                                                 const T* __restrict__ b, const T* xp, const T* __restrict__ dinv,
                                                 const T c1, const T c2, T* out) {
-  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
-       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    T ax = T(0);
-    for (int j = tptr[k]; j < tptr[k + 1]; ++j) ax = fma(tval[j], ye[trow[j]], ax);
-    if constexpr (EPI == static_cast<int>(Epi::Apply)) {
-      out[k] = ax;
-    } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
-      out[k] = b[k] - ax;
-    } else {
-      const T xv = x[k];
-      const T pv = (c1 != T(0)) ? (xp ? xp[k] : T(0)) : xv;
-      out[k] = xv + c1 * (xv - pv) + c2 * dinv[k] * (b[k] - ax);
-    }
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t k = t / LPR;
+  const int sub = static_cast<int>(t % LPR);
+  const bool live = k < n;
+  const T ax = row_sum<T, LPR>(tptr, k, live, sub, [&](int j) { return tval[j] * ye[trow[j]]; });
+  if (!live || sub != 0) return;
+  if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+    out[k] = ax;
+  } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
+    out[k] = b[k] - ax;
+  } else {
+    const T xv = x[k];
+    const T pv = (c1 != T(0)) ? (xp ? xp[k] : T(0)) : xv;
+    out[k] = xv + c1 * (xv - pv) + c2 * dinv[k] * (b[k] - ax);
   }
 }
 
-// y (+)= A x for a CSR matrix (one thread per row)
-template <typename T, bool ACC>
+// y (+)= A x for a CSR matrix, LPR lanes per row
+template <typename T, bool ACC, int LPR>
 __global__ void __launch_bounds__(kB) k_csr(const int64_t rows, const int* __restrict__ ptr,
                                             const int* __restrict__ col, const T* __restrict__ val,
                                             const T* __restrict__ x, T* __restrict__ y) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < rows;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    T s = T(0);
-    for (int j = ptr[i]; j < ptr[i + 1]; ++j) s = fma(val[j], x[col[j]], s);
-    if (ACC) y[i] += s;
-    else y[i] = s;
-  }
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t i = t / LPR;
+  const int sub = static_cast<int>(t % LPR);
+  const bool live = i < rows;
+  const T s = row_sum<T, LPR>(ptr, i, live, sub, [&](int j) { return val[j] * x[col[j]]; });
+  if (!live || sub != 0) return;
+  if (ACC) y[i] += s;
+  else y[i] = s;
 }
 
 // out = c d (.* in)   (in may be null: out = c d; d may be null: d = 1)
@@ -102,7 +117,13 @@ __global__ void __launch_bounds__(kB) k_vscale(const int64_t n, const double* d,
   }
 }
 
+// blocks for one thread per item (lanes = 1) or `lanes` threads per row; no grid-stride loop
+inline int grid_rows(int64_t rows, int lanes) { return static_cast<int>((rows * lanes + kB - 1) / kB); }
 inline int grid(int64_t n) { return static_cast<int>(std::min<int64_t>((n + kB - 1) / kB, 8192)); }
+
+constexpr int kDofLanes = 4;       // rows of C^T: the element nodes of one DoF (8 to ~30)
+constexpr int kProlongLanes = 4;   // rows of P: up to (q+1)^3 coarse DoFs
+constexpr int kRestrictLanes = 16; // rows of P^T: up to (2q+1)^3 fine DoFs
 
 template <typename T, int M>
 hipError_t elem(const OctLevelDev& L, bool mass, const T* x, const T* cval, const T* kmat, T* ye, hipStream_t s) {
@@ -129,17 +150,18 @@ hipError_t apply_t(const OctLevelDev& L, bool mass, const OctApply& a, hipStream
   const T* xp = static_cast<const T*>(a.xp);
   T* out = static_cast<T*>(a.out);
   const T c1 = static_cast<T>(a.c1), c2 = static_cast<T>(a.c2);
+  const dim3 g(grid_rows(L.n, kDofLanes));
   switch (a.epi) {
     case Epi::Apply:
-      hipLaunchKernelGGL((k_oct_dof<T, 0>), dim3(grid(L.n)), dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
+      hipLaunchKernelGGL((k_oct_dof<T, 0, kDofLanes>), g, dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
                          dinv, c1, c2, out);
       break;
     case Epi::Residual:
-      hipLaunchKernelGGL((k_oct_dof<T, 1>), dim3(grid(L.n)), dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
+      hipLaunchKernelGGL((k_oct_dof<T, 1, kDofLanes>), g, dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
                          dinv, c1, c2, out);
       break;
     case Epi::Cheb:
-      hipLaunchKernelGGL((k_oct_dof<T, 2>), dim3(grid(L.n)), dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
+      hipLaunchKernelGGL((k_oct_dof<T, 2, kDofLanes>), g, dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
                          dinv, c1, c2, out);
       break;
   }
@@ -153,21 +175,23 @@ hipError_t launch_oct_apply(const OctLevelDev& L, bool fp32, bool mass, const Oc
 }
 
 hipError_t launch_oct_prolong(const OctLevelDev& F, bool fp32, const void* ec, void* uf, hipStream_t s) {
+  const dim3 g(grid_rows(F.n, kProlongLanes));
   if (fp32)
-    hipLaunchKernelGGL((k_csr<float, true>), dim3(grid(F.n)), dim3(kB), 0, s, F.n, F.pptr, F.pcol, F.pval32,
+    hipLaunchKernelGGL((k_csr<float, true, kProlongLanes>), g, dim3(kB), 0, s, F.n, F.pptr, F.pcol, F.pval32,
                        static_cast<const float*>(ec), static_cast<float*>(uf));
   else
-    hipLaunchKernelGGL((k_csr<double, true>), dim3(grid(F.n)), dim3(kB), 0, s, F.n, F.pptr, F.pcol, F.pval64,
+    hipLaunchKernelGGL((k_csr<double, true, kProlongLanes>), g, dim3(kB), 0, s, F.n, F.pptr, F.pcol, F.pval64,
                        static_cast<const double*>(ec), static_cast<double*>(uf));
   return hipGetLastError();
 }
 
 hipError_t launch_oct_restrict(const OctLevelDev& F, int64_t nc, bool fp32, const void* rf, void* rc, hipStream_t s) {
+  const dim3 g(grid_rows(nc, kRestrictLanes));
   if (fp32)
-    hipLaunchKernelGGL((k_csr<float, false>), dim3(grid(nc)), dim3(kB), 0, s, nc, F.rptr, F.rcol, F.rval32,
+    hipLaunchKernelGGL((k_csr<float, false, kRestrictLanes>), g, dim3(kB), 0, s, nc, F.rptr, F.rcol, F.rval32,
                        static_cast<const float*>(rf), static_cast<float*>(rc));
   else
-    hipLaunchKernelGGL((k_csr<double, false>), dim3(grid(nc)), dim3(kB), 0, s, nc, F.rptr, F.rcol, F.rval64,
+    hipLaunchKernelGGL((k_csr<double, false, kRestrictLanes>), g, dim3(kB), 0, s, nc, F.rptr, F.rcol, F.rval64,
                        static_cast<const double*>(rf), static_cast<double*>(rc));
   return hipGetLastError();
 }
