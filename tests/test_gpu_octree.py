@@ -227,3 +227,23 @@ def test_adaptive_workload_full_size():
         print(f"[c5] leaves {len(tree)} DoFs {S.ndof} levels {ctx.levels} prec {prec}: iters {info.inner_iters} "
               f"rel {rel:.2e} t_solve {info.t_solve * 1e3:.2f} ms", flush=True)
         assert rel <= 1e-8 * 1.001
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_octree_graph_replay_matches_eager(prec):
+    """Octree V-cycles replayed from a captured HIP graph give the bits of the eager launches,
+    replay after replay, with unrelated eager work in between."""
+    torch = torch_cuda()
+    from workloads import gaussian_params, gaussian_source_points
+    eager = _ctx(2, "gauss", seed=2, vcycle_prec=prec, no_graphs=1)
+    graph = _ctx(2, "gauss", seed=2, vcycle_prec=prec)
+    f = torch.from_numpy(gaussian_source_points(eager.dof_coords(), gaussian_params(3, 4, 0.01, 0.05))).cuda()
+    ue, ug = torch.empty_like(f), torch.empty_like(f)
+    for rep in range(3):
+        ie = eager.solve(f, ue, 1e-8)
+        scratch = torch.randn_like(f) * 3.0
+        ig = graph.solve(f, ug, 1e-8)
+        torch.cuda.synchronize()
+        assert ie.inner_iters == ig.inner_iters
+        assert torch.equal(ue, ug), f"replay {rep} differs"
+        del scratch
