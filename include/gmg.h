@@ -131,6 +131,12 @@ typedef struct {
   double rel_residual_f64;  /* final ||b - A u||_2 / ||b||_2, recomputed in FP64           */
   double t_setup;           /* seconds spent in gmg_setup (host clock)                     */
   double t_solve;           /* seconds inside the solve (HIP events on the stream)         */
+  /* per-phase seconds of the solve (Section 3's Setup / Eval / Comm split, taken down to
+   * the V-cycle phases); filled only with gmg_options.timing != 0, else 0:            */
+  double t_smooth;          /* smoother steps, every level and precision                  */
+  double t_transfer;        /* restriction and prolongation                               */
+  double t_coarse;          /* coarsest solve                                             */
+  double t_learned;         /* learned corrections (residual, input scaling, net)         */
 } gmg_info;
 
 /* Build the hierarchy on the current HIP device: operator tables, diagonal
@@ -216,6 +222,13 @@ gmg_status gmg_net_cache_bytes(const gmg_ctx* ctx, int32_t depth, int64_t* bytes
 /* y = N_depth(x) on the depth's lattice (x, y FP32 device vectors); cache_dev
  * (caller-owned, gmg_net_cache_bytes) receives bf16(x) and both activations. */
 gmg_status gmg_net_forward(gmg_ctx* ctx, int32_t depth, const float* x_dev, float* y_dev, void* cache_dev);
+/* Training state of one depth for checkpoints (host FP32 arrays of 7776 values each):
+ * the master weights and Adam's first and second moment estimates.  gmg_net_set_state
+ * installs all three (and re-rounds the BF16 copies); gmg_adam_step then continues
+ * from them with the caller's step count. */
+gmg_status gmg_net_get_state(gmg_ctx* ctx, int32_t depth, float* w_host, float* m_host, float* v_host);
+gmg_status gmg_net_set_state(gmg_ctx* ctx, int32_t depth, const float* w_host, const float* m_host,
+                             const float* v_host);
 /* gw_dev (7776 FP32, device) += d(sum gy . y)/dw for the forward pass held in
  * cache_dev; gin_dev (may be NULL) = d(sum gy . y)/d bf16(x). */
 gmg_status gmg_net_backward(gmg_ctx* ctx, int32_t depth, const float* gy_dev, const void* cache_dev, float* gw_dev,
@@ -247,7 +260,11 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
  *                        (3 values per DoF)
  *   3 smoother step x' = x + c1 (x - x_prev) + c2 D^-1 (b - A x)
  *                        (4 values per DoF)
- *   4 y = M x            (2 values per DoF)                                        */
+ *   4 y = M x            (2 values per DoF)
+ * and, bracketing a whole step (all its launches):
+ *   5 restriction to this level's coarser neighbour   6 prolongation from it
+ *   7 coarsest solve (level 0)                        8 learned correction
+ *   9 first smoother step from a zero guess, x = c D^-1 b (2 values per DoF)          */
 gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
                           double* seconds);
 gmg_status gmg_timing_reset(gmg_ctx* ctx);

@@ -188,7 +188,20 @@ gmg_status ensure_prec(gmg_ctx* c, int pi) {
   return GMG_OK;
 }
 
-constexpr int kKinds = 5;
+// launch-timing kinds (gmg_timing_get)
+enum : int {
+  K_APPLY = 0,
+  K_RESIDUAL = 1,
+  K_SMOOTH0 = 2,
+  K_SMOOTH = 3,
+  K_MASS = 4,
+  K_RESTRICT = 5,
+  K_PROLONG = 6,
+  K_COARSE = 7,
+  K_LEARNED = 8,
+  K_SCALE = 9,  // first smoother step from a zero guess: x = c D^-1 b (no operator apply)
+};
+constexpr int kKinds = 10;
 inline int tslot(int level, int kind, int pi) { return (level * kKinds + kind) * 2 + pi; }
 
 hipEvent_t take_event(gmg_ctx* c) {
@@ -218,6 +231,35 @@ gmg_status drain_timing(gmg_ctx* c) {
   }
   c->pending.clear();
   return GMG_OK;
+}
+
+// With launch timing on, bracket the work `body` enqueues with HIP events, filed under
+// (level, kind, precision); otherwise just run it.
+template <class F>
+gmg_status timed(gmg_ctx* c, int l, int kind, int pi, F&& body) {
+  if (!c->opt.timing) return body();
+  hipEvent_t ea = take_event(c), eb = take_event(c);
+  if (!ea || !eb) return fail(c, GMG_E_HIP, "hipEventCreate failed");
+  HIPCHK(c, hipEventRecord(ea, c->stream));
+  const gmg_status st = body();
+  HIPCHK(c, hipEventRecord(eb, c->stream));
+  c->pending.push_back({ea, eb, l, kind, pi});
+  if (c->pending.size() > 4096) STCHK(drain_timing(c));
+  return st;
+}
+
+// Seconds per phase over every level and precision since the last reset:
+// smoother steps, transfers, coarsest solve, learned corrections.
+void phase_totals(const gmg_ctx* c, double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int l = 0; l < c->L; ++l)
+    for (int pi = 0; pi < 2; ++pi) {
+      auto t = [&](int k) { return c->tsec[tslot(l, k, pi)]; };
+      out[0] += t(K_SMOOTH0) + t(K_SMOOTH) + t(K_SCALE);
+      out[1] += t(K_RESTRICT) + t(K_PROLONG);
+      out[2] += t(K_COARSE);
+      out[3] += t(K_LEARNED);
+    }
 }
 
 gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out, const void* b, const void* xp,
@@ -254,10 +296,10 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   }
   if (c->opt.timing) {
     HIPCHK(c, hipEventRecord(eb, c->stream));
-    int kind = 0;
-    if (mass) kind = 4;
-    else if (epi == Epi::Residual) kind = 1;
-    else if (epi == Epi::Cheb) kind = (xp != nullptr && c1 != 0.0) ? 3 : 2;
+    int kind = K_APPLY;
+    if (mass) kind = K_MASS;
+    else if (epi == Epi::Residual) kind = K_RESIDUAL;
+    else if (epi == Epi::Cheb) kind = (xp != nullptr && c1 != 0.0) ? K_SMOOTH : K_SMOOTH0;
     c->pending.push_back({ea, eb, l, kind, pi});
     if (c->pending.size() > 4096) STCHK(drain_timing(c));
   }
@@ -299,7 +341,10 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
     const double w = c->opt.jacobi_omega;
     for (int s = 0; s < nu; ++s) {
       if (x_zero) {
-        HIPCHK(c, dinv_scale(c, L, f32, w, b, bufs[1 - cur]));
+        STCHK(timed(c, l, K_SCALE, pi, [&]() -> gmg_status {
+          HIPCHK(c, dinv_scale(c, L, f32, w, b, bufs[1 - cur]));
+          return GMG_OK;
+        }));
         x_zero = false;
       } else {
         STCHK(apply_op(c, l, pi, Epi::Cheb, bufs[cur], bufs[1 - cur], b, nullptr, 0.0, w));
@@ -323,7 +368,10 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
         }
         if (x_zero) {
           // x_1 = x_0 + D^-1 (b - A x_0) / theta with x_0 = 0
-          HIPCHK(c, dinv_scale(c, L, f32, c2, b, bufs[1 - cur]));
+          STCHK(timed(c, l, K_SCALE, pi, [&]() -> gmg_status {
+            HIPCHK(c, dinv_scale(c, L, f32, c2, b, bufs[1 - cur]));
+            return GMG_OK;
+          }));
           x_zero = false;
           prev_zero = true;
         } else {
@@ -341,33 +389,31 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
 
 // rc = P^T rf, fine level l -> l-1
 gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
-  const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
+  const int Nc = c->lv[l - 1].N;
   const bool f32 = pi == 1;
-  if (c->lv[l].oct) {
-    HIPCHK(c, launch_oct_restrict(c->lv[l].od, c->lv[l - 1].size, f32, rf, rc, c->stream));
+  return timed(c, l, K_RESTRICT, pi, [&]() -> gmg_status {
+    if (c->lv[l].oct) HIPCHK(c, launch_oct_restrict(c->lv[l].od, c->lv[l - 1].size, f32, rf, rc, c->stream));
+    else HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream));
     return GMG_OK;
-  }
-  (void)Nf;
-  HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream));
-  return GMG_OK;
+  });
 }
 
 // uf += P ec, level l-1 -> l
 gmg_status prolong_level(gmg_ctx* c, int l, int pi, const void* ec, void* uf) {
-  const int Nf = c->lv[l].N, Nc = c->lv[l - 1].N;
+  const int Nc = c->lv[l - 1].N;
   const bool f32 = pi == 1;
-  if (c->lv[l].oct) {
-    HIPCHK(c, launch_oct_prolong(c->lv[l].od, f32, ec, uf, c->stream));
+  return timed(c, l, K_PROLONG, pi, [&]() -> gmg_status {
+    if (c->lv[l].oct) HIPCHK(c, launch_oct_prolong(c->lv[l].od, f32, ec, uf, c->stream));
+    else HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream));
     return GMG_OK;
-  }
-  (void)Nf;
-  HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream));
-  return GMG_OK;
+  });
 }
 
 gmg_status coarse_solve(gmg_ctx* c, int pi, const void* b, void* x) {
-  HIPCHK(c, launch_coarse(pi == 1, c->n0, c->ainv, b, x, c->stream));
-  return GMG_OK;
+  return timed(c, 0, K_COARSE, pi, [&]() -> gmg_status {
+    HIPCHK(c, launch_coarse(pi == 1, c->n0, c->ainv, b, x, c->stream));
+    return GMG_OK;
+  });
 }
 
 // Net used at depth d: its own if set, else the deepest (largest depth) net that is set.
@@ -396,12 +442,14 @@ gmg_status learned_correction(gmg_ctx* c, int l, const void* b, void* u) {
   Level& L = c->lv[l];
   const int d = net_for_depth(c, c->L - 1 - l);
   STCHK(ensure_lcache(c, l));
-  STCHK(apply_op(c, l, 1, Epi::Residual, u, L.xp[1], b, nullptr, 0, 0));
-  HIPCHK(c, launch_net_input(static_cast<const float*>(L.xp[1]), L.tab.stiff.dinv, c->q, c->scal + S_SSUM + l,
-                             c->part, L.N, c->lcache[l], c->stream));
-  HIPCHK(c, launch_net_forward(c->nets[d], L.N, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
-                               c->stream, false));
-  return GMG_OK;
+  return timed(c, l, K_LEARNED, 1, [&]() -> gmg_status {
+    STCHK(apply_op(c, l, 1, Epi::Residual, u, L.xp[1], b, nullptr, 0, 0));
+    HIPCHK(c, launch_net_input(static_cast<const float*>(L.xp[1]), L.tab.stiff.dinv, c->q, c->scal + S_SSUM + l,
+                               c->part, L.N, c->lcache[l], c->stream));
+    HIPCHK(c, launch_net_forward(c->nets[d], L.N, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
+                                 c->stream, false));
+    return GMG_OK;
+  });
 }
 
 // Algorithm 2.1 on level l with zero initial guess: u = V_l b.
@@ -1181,6 +1229,11 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   c->fallbacks = 0;
   c->hist_res.clear();
   c->hist_cyc.clear();
+  double ph0[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c->opt.timing) {
+    STCHK(drain_timing(c));
+    phase_totals(c, ph0);
+  }
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -1277,6 +1330,15 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   inf.fallbacks = static_cast<int32_t>(c->fallbacks);
+  if (c->opt.timing) {
+    STCHK(drain_timing(c));
+    double ph1[4];
+    phase_totals(c, ph1);
+    inf.t_smooth = ph1[0] - ph0[0];
+    inf.t_transfer = ph1[1] - ph0[1];
+    inf.t_coarse = ph1[2] - ph0[2];
+    inf.t_learned = ph1[3] - ph0[3];
+  }
   if (info) *info = inf;
   return st;
 }
@@ -1473,6 +1535,33 @@ gmg_status gmg_net_get_weights(gmg_ctx* ctx, int32_t depth, float* w_host, int64
   return scoped(ctx, [&] {
     HIPCHK(ctx, hipMemcpyAsync(w_host, ctx->nets[depth].w, sizeof(float) * kNetWeights, hipMemcpyDeviceToHost,
                                ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_net_get_state(gmg_ctx* ctx, int32_t depth, float* w_host, float* m_host, float* v_host) {
+  if (!w_host || !m_host || !v_host || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
+  return scoped(ctx, [&] {
+    const NetDev& n = ctx->nets[depth];
+    const size_t bytes = sizeof(float) * kNetWeights;
+    HIPCHK(ctx, hipMemcpyAsync(w_host, n.w, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(m_host, n.m, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(v_host, n.v, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_net_set_state(gmg_ctx* ctx, int32_t depth, const float* w_host, const float* m_host,
+                             const float* v_host) {
+  if (!w_host || !m_host || !v_host || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  return scoped(ctx, [&] {
+    STCHK(set_master(ctx, depth, w_host));
+    const NetDev& n = ctx->nets[depth];
+    const size_t bytes = sizeof(float) * kNetWeights;
+    HIPCHK(ctx, hipMemcpyAsync(n.m, m_host, bytes, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(n.v, v_host, bytes, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return GMG_OK;
   });

@@ -27,6 +27,7 @@ EXPORTS = [
     "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
     "gmg_octree_refine_gaussians", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
+    "gmg_net_get_state", "gmg_net_set_state",
 ]
 
 NET_WEIGHTS = 7776
@@ -56,7 +57,8 @@ class GmgInfo(ctypes.Structure):
     _fields_ = [
         ("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("rel_residual_f64", ctypes.c_double), ("t_setup", ctypes.c_double),
-        ("t_solve", ctypes.c_double),
+        ("t_solve", ctypes.c_double), ("t_smooth", ctypes.c_double), ("t_transfer", ctypes.c_double),
+        ("t_coarse", ctypes.c_double), ("t_learned", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -108,6 +110,8 @@ def load():
         "gmg_level_leaves": [P, I32, P, P, I64, ctypes.POINTER(I64)],
         "gmg_num_elements": [P, I32, ctypes.POINTER(I64)],
         "gmg_dof_coords": [P, I32, P],
+        "gmg_net_get_state": [P, I32, P, P, P],
+        "gmg_net_set_state": [P, I32, P, P, P],
         "gmg_net_set_weights": [P, I32, P, I64],
         "gmg_set_learned": [P, I32, P, I64],
         "gmg_net_get_weights": [P, I32, P, I64],
@@ -308,7 +312,8 @@ class Context:
         return v.value
 
     # -- launch timing (needs timing=1 at construction)
-    KIND_APPLY, KIND_RESIDUAL, KIND_SMOOTH0, KIND_SMOOTH, KIND_MASS = range(5)
+    (KIND_APPLY, KIND_RESIDUAL, KIND_SMOOTH0, KIND_SMOOTH, KIND_MASS, KIND_RESTRICT, KIND_PROLONG, KIND_COARSE,
+     KIND_LEARNED, KIND_SCALE) = range(10)
 
     def timing(self, level, kind, prec):
         """(launches, seconds) of one level / kind / precision since the last reset."""
@@ -351,6 +356,20 @@ class Context:
         w = np.zeros(NET_WEIGHTS, dtype=np.float32)
         self._check(self.lib.gmg_net_get_weights(self.h, depth, w.ctypes.data_as(ctypes.c_void_p), w.size))
         return w
+
+    def net_get_state(self, depth):
+        """(w, m, v): FP32 master weights and Adam moments of one depth."""
+        import numpy as np
+        w, m, v = (np.zeros(NET_WEIGHTS, dtype=np.float32) for _ in range(3))
+        self._check(self.lib.gmg_net_get_state(self.h, depth, *(a.ctypes.data_as(ctypes.c_void_p) for a in (w, m, v))))
+        return w, m, v
+
+    def net_set_state(self, depth, w, m, v):
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (w, m, v)]
+        if any(a.size != NET_WEIGHTS for a in arrs):
+            raise ValueError("expected 7776 values each")
+        self._check(self.lib.gmg_net_set_state(self.h, depth, *(a.ctypes.data_as(ctypes.c_void_p) for a in arrs)))
 
     def net_cache(self, depth):
         """A device byte buffer large enough for one forward cache at this depth."""

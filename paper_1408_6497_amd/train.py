@@ -18,12 +18,18 @@ backward, loss gradient, Adam -- runs in libgmg's kernels; torch only holds the
 buffers and the random-field generator.
 
 Checkpoint file (little endian):
-  magic b"GMGW", uint32 version (1), int32 depth, int32 order, int32 n,
-  int64 step, int64 count (7776), float32 master[count], uint16 bf16[count].
+  magic b"GMGW", uint32 version, int32 depth, int32 order, int32 n,
+  int64 step, int64 count (7776), float32 master[count], uint16 bf16[count];
+  version 2 adds float32 adam_m[count], float32 adam_v[count], then uint32 length
+  and that many bytes of UTF-8 JSON: the training configuration and the position
+  in the pair stream (source, cycle, position), so a run can stop and resume and
+  end on the same bits as an uninterrupted one.
 
   python -m paper_1408_6497_amd.train --n 64 --sources 10000 --out weights.gmgw
+  python -m paper_1408_6497_amd.train --resume weights.gmgw --out weights.gmgw
 """
 import argparse
+import json
 import os
 import struct
 import sys
@@ -32,7 +38,7 @@ import time
 import numpy as np
 
 MAGIC = b"GMGW"
-VERSION = 1
+VERSION = 2
 NW = 7776
 
 
@@ -52,12 +58,19 @@ def bf16_bits(w):
     return u.astype(np.uint16)
 
 
-def save(path, w, depth, order, n, step):
+def save(path, w, depth, order, n, step, m=None, v=None, extra=None):
+    """Write a checkpoint: version 2 when the Adam moments are given, else version 1."""
     w = np.ascontiguousarray(w, dtype=np.float32)
+    version = 2 if m is not None else 1
     with open(path + ".tmp", "wb") as fh:
-        fh.write(MAGIC + struct.pack("<Iiiiqq", VERSION, depth, order, n, step, NW))
+        fh.write(MAGIC + struct.pack("<Iiiiqq", version, depth, order, n, step, NW))
         fh.write(w.tobytes())
         fh.write(bf16_bits(w).tobytes())
+        if version == 2:
+            fh.write(np.ascontiguousarray(m, dtype=np.float32).tobytes())
+            fh.write(np.ascontiguousarray(v, dtype=np.float32).tobytes())
+            blob = json.dumps(extra or {}).encode()
+            fh.write(struct.pack("<I", len(blob)) + blob)
     os.replace(path + ".tmp", path)
 
 
@@ -67,11 +80,18 @@ def load(path):
         if head[:4] != MAGIC:
             raise ValueError(f"{path}: not a weights file")
         version, depth, order, n, step, count = struct.unpack("<Iiiiqq", head[4:])
-        if version != VERSION or count != NW:
+        if version not in (1, 2) or count != NW:
             raise ValueError(f"{path}: unsupported version {version} / count {count}")
         w = np.frombuffer(fh.read(4 * NW), dtype=np.float32).copy()
         wb = np.frombuffer(fh.read(2 * NW), dtype=np.uint16).copy()
-    return {"w": w, "bf16": wb, "depth": depth, "order": order, "n": n, "step": step}
+        out = {"w": w, "bf16": wb, "depth": depth, "order": order, "n": n, "step": step, "version": version,
+               "m": None, "v": None, "extra": None}
+        if version == 2:
+            out["m"] = np.frombuffer(fh.read(4 * NW), dtype=np.float32).copy()
+            out["v"] = np.frombuffer(fh.read(4 * NW), dtype=np.float32).copy()
+            (ln,) = struct.unpack("<I", fh.read(4))
+            out["extra"] = json.loads(fh.read(ln).decode())
+    return out
 
 
 class PairMaker:
@@ -173,21 +193,44 @@ def validate(ctx, pm, cache, seeds, kind, with_cheb=False, cycles=1, positions=(
 
 
 def train(n=64, sources=10000, batch=8, lr=1e-3, val=100, init_seed=12345, out=None, log=print,
-          train_seed0=0, val_seed0=20000, cycles=2, positions=("pre", "post"), loss="residual"):
+          train_seed0=0, val_seed0=20000, cycles=2, positions=("pre", "post"), loss="residual",
+          stop_after=None, resume=None):
+    """Adam on the net of depth 0; stop_after ends the run early (a checkpoint to resume from),
+    resume continues a version-2 checkpoint with its own configuration."""
     import torch
     from paper_1408_6497_amd import Context, GMG_FP64, LOSS_ENERGY, LOSS_RESIDUAL
+    ck = None
+    if resume:
+        ck = load(resume)
+        if ck["version"] < 2:
+            raise ValueError(f"{resume}: version 1 checkpoints hold no optimizer state")
+        cfg = ck["extra"]["config"]
+        n, sources, batch, lr, val = cfg["n"], cfg["sources"], cfg["batch"], cfg["lr"], cfg["val"]
+        init_seed, train_seed0, val_seed0 = cfg["init_seed"], cfg["train_seed0"], cfg["val_seed0"]
+        cycles, positions, loss = cfg["cycles"], tuple(cfg["positions"]), cfg["loss"]
+    config = {"n": n, "sources": sources, "batch": batch, "lr": lr, "val": val, "init_seed": init_seed,
+              "train_seed0": train_seed0, "val_seed0": val_seed0, "cycles": cycles, "positions": list(positions),
+              "loss": loss}
     kind = {"energy": LOSS_ENERGY, "residual": LOSS_RESIDUAL}[loss]
     ctx = Context(2, n, 0, seed=0, vcycle_prec=GMG_FP64)
     cctx = Context(2, n // 2, 0, seed=0, vcycle_prec=GMG_FP64) if "post" in positions else None
     pm = PairMaker(ctx, cctx)
-    ctx.net_set_weights(0, he_init(init_seed))
+    if ck:
+        ctx.net_set_state(0, ck["w"], ck["m"], ck["v"])
+    else:
+        ctx.net_set_weights(0, he_init(init_seed))
     cache = ctx.net_cache(0)
     gw = torch.zeros(NW, dtype=torch.float32, device="cuda")
     vseeds = range(val_seed0, val_seed0 + val)
     v0, vcheb = validate(ctx, pm, cache, vseeds, kind, with_cheb=True, cycles=cycles, positions=positions)
     log(f"[train] validation before: loss {v0:.4f}  (Chebyshev application it replaces: {vcheb:.4f})")
     # each source contributes cycles x positions consecutive pairs
-    state = {"src": 0, "cyc": 0, "pos": 0}
+    state = dict(ck["extra"]["stream"]) if ck else {"src": 0, "cyc": 0, "pos": 0}
+    if state["cyc"] > 0 or state["pos"] > 0:
+        # rebuild the right side the next pair starts from
+        pm.source(train_seed0 + state["src"])
+        for _ in range(state["cyc"] - (1 if state["pos"] == 0 else 0)):
+            pm.next_cycle()
 
     def next_pair():
         if state["pos"] == 0:
@@ -204,9 +247,11 @@ def train(n=64, sources=10000, batch=8, lr=1e-3, val=100, init_seed=12345, out=N
         return r, e
 
     steps = sources * cycles * len(positions) // batch
+    step0 = ck["step"] if ck else 0
+    last = steps if stop_after is None else min(steps, step0 + stop_after)
     t0 = time.perf_counter()
     hist = []
-    for step in range(1, steps + 1):
+    for step in range(step0 + 1, last + 1):
         gw.zero_()
         tot = 0.0
         for k in range(batch):
@@ -216,13 +261,13 @@ def train(n=64, sources=10000, batch=8, lr=1e-3, val=100, init_seed=12345, out=N
         hist.append(tot / batch)
         if step % max(1, steps // 20) == 0 or step == steps:
             log(f"[train] step {step}/{steps} loss {np.mean(hist[-50:]):.4f} ({time.perf_counter() - t0:.1f} s)")
+    w, m, v = ctx.net_get_state(0)
+    if out:
+        save(out, w, 0, 2, n, last, m, v, {"config": config, "stream": state})
     v1, _ = validate(ctx, pm, cache, vseeds, kind, cycles=cycles, positions=positions)
     log(f"[train] validation after: loss {v1:.4f}")
-    w = ctx.net_get_weights(0)
-    if out:
-        save(out, w, 0, 2, n, steps)
-    return {"w": w, "val_before": v0, "val_after": v1, "val_chebyshev": vcheb, "steps": steps,
-            "seconds": time.perf_counter() - t0, "loss_history": hist}
+    return {"w": w, "val_before": v0, "val_after": v1, "val_chebyshev": vcheb, "steps": last - step0,
+            "step": last, "seconds": time.perf_counter() - t0, "loss_history": hist}
 
 
 def main():
@@ -236,9 +281,12 @@ def main():
     ap.add_argument("--positions", default="pre,post", help="pair positions in the cycle: pre, post or both")
     ap.add_argument("--loss", default="residual", choices=("residual", "energy"))
     ap.add_argument("--out", default=None)
+    ap.add_argument("--stop-after", type=int, default=None, help="stop after this many Adam steps (checkpoint)")
+    ap.add_argument("--resume", default=None, help="continue a version-2 checkpoint")
     a = ap.parse_args()
     res = train(a.n, a.sources, a.batch, a.lr, a.val, out=a.out, log=lambda *m: print(*m, flush=True),
-                cycles=a.cycles, positions=tuple(a.positions.split(",")), loss=a.loss)
+                cycles=a.cycles, positions=tuple(a.positions.split(",")), loss=a.loss,
+                stop_after=a.stop_after, resume=a.resume)
     print(f"[train] done: {res['steps']} steps in {res['seconds']:.1f} s; validation {res['val_before']:.4f} -> "
           f"{res['val_after']:.4f} (Chebyshev {res['val_chebyshev']:.4f})", flush=True)
 

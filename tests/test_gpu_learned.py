@@ -218,3 +218,25 @@ def test_trained_net_gain_on_held_out_sources():
     print(f"[gain] held-out contraction: net {net:.4f} vs Chebyshev {cheb:.4f}; solves {out}", flush=True)
     assert net < cheb
     assert out["learned"][2] <= 1e-8 and out["learned"][0] <= out["plain"][0] + 1
+
+
+def test_training_stops_and_resumes_on_the_same_bits(tmp_path):
+    """A run stopped twice (mid-source) and resumed from its version-2 checkpoints ends on the
+    same weights, bit for bit, as the uninterrupted run: optimizer moments, step count and the
+    position in the pair stream all travel in the file, and every training kernel is
+    deterministic (fixed-order reductions)."""
+    torch_cuda()
+    from paper_1408_6497_amd import train as T
+    kw = dict(n=16, sources=3, batch=3, val=2, cycles=2, positions=("pre", "post"), loss="residual",
+              log=lambda *a: None)
+    straight = T.train(**kw)
+    assert straight["step"] == 4
+    ck1, ck2 = str(tmp_path / "a.gmgw"), str(tmp_path / "b.gmgw")
+    T.train(**kw, stop_after=1, out=ck1)
+    c1 = T.load(ck1)
+    assert c1["version"] == 2 and c1["step"] == 1 and c1["extra"]["stream"] == {"src": 0, "cyc": 1, "pos": 1}
+    T.train(resume=ck1, stop_after=1, out=ck2, log=lambda *a: None)
+    assert T.load(ck2)["extra"]["stream"] == {"src": 1, "cyc": 1, "pos": 0}
+    resumed = T.train(resume=ck2, log=lambda *a: None)
+    assert resumed["step"] == 4
+    assert np.array_equal(resumed["w"], straight["w"])

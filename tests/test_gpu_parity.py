@@ -250,3 +250,24 @@ def test_graph_replay_matches_eager(prec):
         assert ie.inner_iters == ig.inner_iters and ie.outer_iters == ig.outer_iters
         assert torch.equal(ue, ug), f"replay {rep} differs"
         del scratch
+
+
+def test_phase_timing_fills_info():
+    """With launch timing on, the solve reports its smoother, transfer and coarsest-solve
+    seconds, each positive and together below the solve's own time."""
+    torch = torch_cuda()
+    from workloads import gaussian_params, gaussian_source
+    from paper_1408_6497_amd import Context
+    ctx = _ctx(2, 16, 0, seed=1, timing=1)
+    f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1)).cuda()
+    u = torch.empty_like(f)
+    info = ctx.solve(f, u, 1e-8)
+    parts = (info.t_smooth, info.t_transfer, info.t_coarse)
+    print(f"[phases] solve {info.t_solve * 1e3:.3f} ms: smooth {parts[0] * 1e3:.3f} transfer {parts[1] * 1e3:.3f} "
+          f"coarse {parts[2] * 1e3:.3f} ms", flush=True)
+    assert all(p > 0 for p in parts) and info.t_learned == 0.0
+    assert sum(parts) < info.t_solve
+    c, s = ctx.timing(0, Context.KIND_COARSE, 0)
+    assert c == info.inner_iters + 1 or c >= info.inner_iters
+    plain = _ctx(2, 16, 0, seed=1)
+    assert plain.solve(f, u, 1e-8).t_smooth == 0.0
