@@ -332,10 +332,14 @@ def main():
         ctxt.close()
         del ctx64
         torch.cuda.empty_cache()
-        big = Context(2, 256, 0, seed=seed, timing=1)
-        apply["q2_512cubed_fp32"] = apply_rate(big, GMG_FP32)
-        apply["q2_512cubed_fp64"] = apply_rate(big, GMG_FP64)
-        big.close()
+        # 512^3 DoFs for every order (Q1 on 512^3, Q2 on 256^3, Q4 on 128^3 elements)
+        for qq, nn in ((2, 256), (1, 512), (4, 128)):
+            big = Context(qq, nn, 0, seed=seed, timing=1, lambda_override=1.0)
+            apply[f"q{qq}_512cubed_fp32"] = apply_rate(big, GMG_FP32)
+            apply[f"q{qq}_512cubed_fp64"] = apply_rate(big, GMG_FP64)
+            big.close()
+            del big
+            torch.cuda.empty_cache()
         log(f"[bench] apply {json.dumps(apply)}")
 
     extra = {}

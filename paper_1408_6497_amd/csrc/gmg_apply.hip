@@ -9,10 +9,14 @@
 // Two kernels:
 //
 // k_apply_col (levels with N >= 64): streams z planes.
-//   * a workgroup owns TY = 4 G full x-rows and a chunk of TZ element layers;
-//     thread (tx, ty) owns one element column in x (q nodes, moved as one
-//     q-wide vector, so a wavefront reads 64 q consecutive values per row) and
-//     RY = 4 rows of row group ty;
+//   * a tile is 4 G full x-rows by a chunk of TZ element layers; thread (tx, ty)
+//     owns one element column in x (q nodes, moved as one q-wide vector, so a
+//     wavefront reads 64 q consecutive values per row) and RY rows of the 4
+//     rows 4 ty .. 4 ty + 3 of the tile.  RY = 4 (one workgroup per tile),
+//     except FP64 q = 4, whose accumulators do not fit the register file
+//     four rows deep: there RY = 2 and two workgroups share a tile, one
+//     taking row classes 0, 1 and the other 2, 3 (the class is uniform over
+//     the workgroup, so it stays compile-time);
 //   * each thread loads its own column strip of RY + 2q rows (the y halo wraps
 //     periodically) straight into registers and does the y pass there
 //     (P = My x, S = Ky x); only P and S go through LDS, double-buffered, for
@@ -102,16 +106,22 @@ constexpr int col_bound() {
   return Q == 4 ? 256 : 512;
 }
 
+// rows per thread of the column kernel
+template <typename T, int Q>
+constexpr int col_rows() {
+  return (Q == 4 && sizeof(T) == 8) ? 2 : 4;
+}
+
 // --------------------------------------------------------------------------
 // Streaming column kernel.
-template <typename T, int Q, int G, int EPI>
-__global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
-                                                              const int N, const int TZ, const int ntiles_y,
-                                                              T* out, const T* bvec, const T* xp, const T c1,
-                                                              const T c2) {
-  constexpr int RY = 4;
+// Body of the column kernel for workgroups whose threads start at row class CY0.
+template <typename T, int Q, int G, int EPI, int RY, int CY0>
+__device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, Q>& tb, const int N, const int TZ,
+                                         const int Y0, const int E0, T* out, const T* bvec, const T* xp,
+                                         const T c1, const T c2) {
   constexpr int TY = G * RY;
   constexpr int NR = RY + 2 * Q;
+  constexpr bool kLatePrefetch = Q == 4;
   using V = VecQ<T, Q>;
 
   const int tx = threadIdx.x;
@@ -121,14 +131,8 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);  // [2 buffers][P,S][TY][N]
   const int buf_stride = 2 * TY * N;
-
-  const int nblocks = gridDim.x;
-  int tile = blockIdx.x;
-  if ((nblocks & 7) == 0) tile = (blockIdx.x & 7) * (nblocks >> 3) + (blockIdx.x >> 3);
-  const int Y0 = (tile % ntiles_y) * TY;
-  const int E0 = (tile / ntiles_y) * TZ;
   const size_t NN = static_cast<size_t>(N) * N;
-  const int yrow0 = Y0 + ty * RY;  // first output row of this thread
+  const int yrow0 = Y0 + 4 * ty + CY0;  // first output row of this thread
 
   // offsets (in elements) of the strip rows inside a plane, y wrapping periodically
   int roff[NR];
@@ -147,17 +151,11 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
   T g[RY][Q], h[RY][Q];
   int parity = 0;
 
-  auto compute_gh = [&](int p, bool prefetch) {
-    V xv[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) xv[r] = pre[r];
-    if (prefetch) load_plane(p + 1);
-    T* ps = lds + parity * buf_stride;
-    T* ss = ps + TY * N;
-    // y pass in registers
+  // y pass in registers: P = My x and S = Ky x of the RY output rows into LDS
+  auto ypass = [&](const V (&xv)[NR], T* ps, T* ss) {
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-      const int ci = i % Q;
+      const int ci = (CY0 + i) % Q;
       V pv, sv;
 #pragma unroll
       for (int c = 0; c < Q; ++c) {
@@ -177,6 +175,24 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
       }
       *reinterpret_cast<V*>(ps + (ty * RY + i) * N + Q * tx) = pv;
       *reinterpret_cast<V*>(ss + (ty * RY + i) * N + Q * tx) = sv;
+    }
+  };
+
+  auto compute_gh = [&](int p, bool prefetch) {
+    T* ps = lds + parity * buf_stride;
+    T* ss = ps + TY * N;
+    if constexpr (kLatePrefetch) {
+      // the next plane's loads go out once the y pass has consumed this one: one strip
+      // of registers instead of two (q = 4 would spill), the loads still overlap the
+      // x and z passes
+      ypass(pre, ps, ss);
+      if (prefetch) load_plane(p + 1);
+    } else {
+      V xv[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) xv[r] = pre[r];
+      if (prefetch) load_plane(p + 1);
+      ypass(xv, ps, ss);
     }
     __syncthreads();
     // x pass across element columns
@@ -255,7 +271,7 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
 #pragma unroll
           for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
           const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
-          emit<T, Q, EPI>(tb, idx, i % Q, a, ax, x, out, bvec, xp, c1, c2);
+          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2);
         }
       }
     }
@@ -269,6 +285,27 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
 #pragma unroll
         for (int a = 1; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
       }
+  }
+}
+
+template <typename T, int Q, int G, int EPI>
+__global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
+                                                              const int N, const int TZ, const int ntiles_y,
+                                                              T* out, const T* bvec, const T* xp, const T c1,
+                                                              const T c2) {
+  constexpr int RY = col_rows<T, Q>();
+  constexpr int SPLIT = 4 / RY;  // workgroups per tile
+  const int nblocks = gridDim.x;
+  int b = blockIdx.x;
+  if ((nblocks & 7) == 0) b = (blockIdx.x & 7) * (nblocks >> 3) + (blockIdx.x >> 3);
+  const int tile = b / SPLIT;
+  const int Y0 = (tile % ntiles_y) * 4 * G;
+  const int E0 = (tile / ntiles_y) * TZ;
+  if constexpr (SPLIT == 1) {
+    col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2);
+  } else {
+    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2);
+    else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2);
   }
 }
 
@@ -293,9 +330,11 @@ __global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const
   T ax[Q];
 #pragma unroll
   for (int c = 0; c < Q; ++c) ax[c] = T(0);
-  // fully unrolled so that all (2q+1)^2 row loads can be in flight at once;
+  // unrolled so that the (2q+1)^2 row loads can be in flight at once (for q = 4 one
+  // z row of the neighbourhood at a time, or the loads would not fit in registers);
   // taps outside a row's band carry zero weights
-#pragma unroll
+  constexpr int kUnrollZ = Q == 4 ? 1 : 2 * Q + 1;
+#pragma unroll kUnrollZ
   for (int dz = -Q; dz <= Q; ++dz) {
     const T mz = tb.zmr[cz][dz + Q], kz = tb.zkr[cz][dz + Q];
     const int zr = (zz + dz) & Nm;
@@ -351,19 +390,20 @@ struct ColShape {
   size_t lds;
 };
 
-inline ColShape col_shape(int N, int n, int Q, size_t elem) {
+inline ColShape col_shape(int N, int n, int Q, size_t elem, int RY) {
   ColShape s{};
   const int nx = N / Q;
+  const int split = 4 / RY;
   int G = 1;
   while (G < 4 && G * nx < 64 && 8 * G <= N) G *= 2;  // at least one full wavefront per block
   s.G = G;
   s.ntiles_y = N / (4 * G);
   // enough blocks for several per CU, as few recomputed element layers as possible
   int TZ = n;
-  while (TZ > 1 && static_cast<int64_t>(s.ntiles_y) * (n / TZ) < 1024) TZ >>= 1;
+  while (TZ > 1 && static_cast<int64_t>(s.ntiles_y) * split * (n / TZ) < 1024) TZ >>= 1;
   s.TZ = TZ;
-  s.nblocks = s.ntiles_y * (n / TZ);
-  s.lds = static_cast<size_t>(2 * 2 * 4 * G) * N * elem;
+  s.nblocks = s.ntiles_y * split * (n / TZ);
+  s.lds = static_cast<size_t>(2 * 2 * RY * G) * N * elem;
   return s;
 }
 
@@ -392,7 +432,7 @@ hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
                        static_cast<const T*>(a.xp), static_cast<T>(a.c1), static_cast<T>(a.c2));
     return hipGetLastError();
   }
-  const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T));
+  const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T), col_rows<T, Q>());
   if ((a.N / Q) * sh.G > col_bound<Q>()) return hipErrorInvalidConfiguration;
   switch (sh.G) {
     case 1: return launch_col<T, Q, 1, EPI>(kt, a, sh, s);
