@@ -264,7 +264,11 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
  * and, bracketing a whole step (all its launches):
  *   5 restriction to this level's coarser neighbour   6 prolongation from it
  *   7 coarsest solve (level 0)                        8 learned correction
- *   9 first smoother step from a zero guess, x = c D^-1 b (2 values per DoF)          */
+ *   9 first smoother step from a zero guess, x = c D^-1 b (2 values per DoF; octree
+ *     levels and degree-1 smoothers)
+ *  10 first two Chebyshev steps from a zero guess in one pass on uniform levels:
+ *     x_1 = D^-1 b / theta formed from b as it is loaded, x_2 = x_1 + c1 x_1 +
+ *     c2 D^-1 (b - A x_1); x_1 and x_2 are stored (3 values per DoF)            */
 gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
                           double* seconds);
 gmg_status gmg_timing_reset(gmg_ctx* ctx);

@@ -199,9 +199,10 @@ enum : int {
   K_PROLONG = 6,
   K_COARSE = 7,
   K_LEARNED = 8,
-  K_SCALE = 9,  // first smoother step from a zero guess: x = c D^-1 b (no operator apply)
+  K_SCALE = 9,    // first smoother step from a zero guess: x = c D^-1 b (no operator apply)
+  K_SMOOTHZ = 10,  // first two Chebyshev steps from a zero guess in one pass
 };
-constexpr int kKinds = 10;
+constexpr int kKinds = 11;
 inline int tslot(int level, int kind, int pi) { return (level * kKinds + kind) * 2 + pi; }
 
 hipEvent_t take_event(gmg_ctx* c) {
@@ -255,7 +256,7 @@ void phase_totals(const gmg_ctx* c, double out[4]) {
   for (int l = 0; l < c->L; ++l)
     for (int pi = 0; pi < 2; ++pi) {
       auto t = [&](int k) { return c->tsec[tslot(l, k, pi)]; };
-      out[0] += t(K_SMOOTH0) + t(K_SMOOTH) + t(K_SCALE);
+      out[0] += t(K_SMOOTH0) + t(K_SMOOTH) + t(K_SCALE) + t(K_SMOOTHZ);
       out[1] += t(K_RESTRICT) + t(K_PROLONG);
       out[2] += t(K_COARSE);
       out[3] += t(K_LEARNED);
@@ -263,11 +264,11 @@ void phase_totals(const gmg_ctx* c, double out[4]) {
 }
 
 gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out, const void* b, const void* xp,
-                    double c1, double c2, bool mass = false) {
+                    double c1, double c2, bool mass = false, void* x1 = nullptr, double s0 = 0.0) {
   const Level& L = c->lv[l];
   // the uniform kernel moves q consecutive values per vector access
   const uintptr_t al = static_cast<uintptr_t>(L.oct ? 1 : c->q) * esize(pi);
-  for (const void* ptr : {x, static_cast<const void*>(out), b, xp})
+  for (const void* ptr : {x, static_cast<const void*>(out), b, xp, static_cast<const void*>(x1)})
     if (ptr && (reinterpret_cast<uintptr_t>(ptr) % al) != 0)
       return fail(c, GMG_E_ARG, "device buffer not aligned to q elements");
   if (L.oct && !c->oye[pi]) return fail(c, GMG_E_STATE, "octree scratch of this precision not allocated");
@@ -281,6 +282,8 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.c1 = c1;
   a.c2 = c2;
   a.epi = epi;
+  a.x1 = x1;
+  a.s0 = s0;
   hipEvent_t ea = nullptr, eb = nullptr;
   if (c->opt.timing) {
     ea = take_event(c);
@@ -300,6 +303,7 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
     if (mass) kind = K_MASS;
     else if (epi == Epi::Residual) kind = K_RESIDUAL;
     else if (epi == Epi::Cheb) kind = (xp != nullptr && c1 != 0.0) ? K_SMOOTH : K_SMOOTH0;
+    else if (epi == Epi::ChebZero) kind = K_SMOOTHZ;
     c->pending.push_back({ea, eb, l, kind, pi});
     if (c->pending.size() > 4096) STCHK(drain_timing(c));
   }
@@ -356,6 +360,10 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
     const double delta = 0.5 * (L.beta - L.alpha);
     const double sigma = theta / delta;
     const int deg = c->opt.cheb_degree;
+    // from a zero guess on a uniform level the scaling x_1 = D^-1 b / theta is not a
+    // pass of its own: the next step forms x_1 from b as it loads it (Epi::ChebZero)
+    const bool fuse_zero = !L.oct && deg >= 2;
+    double s0 = 0.0;
     for (int app = 0; app < nu; ++app) {
       double rho = 1.0 / sigma;
       for (int j = 0; j < deg; ++j) {
@@ -366,7 +374,16 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
           c2 = 2.0 * rho_new / delta;
           rho = rho_new;
         }
-        if (x_zero) {
+        if (x_zero && fuse_zero) {
+          s0 = c2;  // x_1 = s0 D^-1 b, formed by the next launch into bufs[1 - cur]
+          x_zero = false;
+          prev_zero = true;
+        } else if (prev_zero && s0 != 0.0) {
+          // x_2 = x_1 + c1 x_1 + c2 D^-1 (b - A x_1), storing x_1 where the scaling would have
+          STCHK(apply_op(c, l, pi, Epi::ChebZero, b, bufs[1 - cur], b, nullptr, c1, c2, false, bufs[cur], s0));
+          s0 = 0.0;
+          prev_zero = false;
+        } else if (x_zero) {
           // x_1 = x_0 + D^-1 (b - A x_0) / theta with x_0 = 0
           STCHK(timed(c, l, K_SCALE, pi, [&]() -> gmg_status {
             HIPCHK(c, dinv_scale(c, L, f32, c2, b, bufs[1 - cur]));
@@ -445,7 +462,7 @@ gmg_status learned_correction(gmg_ctx* c, int l, const void* b, void* u) {
   return timed(c, l, K_LEARNED, 1, [&]() -> gmg_status {
     STCHK(apply_op(c, l, 1, Epi::Residual, u, L.xp[1], b, nullptr, 0, 0));
     HIPCHK(c, launch_net_input(static_cast<const float*>(L.xp[1]), L.tab.stiff.dinv, c->q, c->scal + S_SSUM + l,
-                               c->part, L.N, c->lcache[l], c->stream));
+                               c->part, c->part_cap, L.N, c->lcache[l], c->stream));
     HIPCHK(c, launch_net_forward(c->nets[d], L.N, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
                                  c->stream, false));
     return GMG_OK;
@@ -588,9 +605,13 @@ gmg_status prepare_learned(gmg_ctx* c) {
 // tried and kept if its contraction is no worse than the plain cycle's most
 // recent one; otherwise the plain FP32 cycle is used (a fallback) and its
 // contraction becomes the new reference.
+// Is the finest-level cycle of precision vpi a learned one (with its per-cycle test)?
+bool learned_precond(const gmg_ctx* c, int vpi) {
+  return c->opt.use_learned && vpi == 1 && net_for_depth(c, 0) >= 0;
+}
+
 gmg_status precondition(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
-  const bool lrn = c->opt.use_learned && vpi == 1 && net_for_depth(c, 0) >= 0;
-  if (!lrn) return run_vcycle(c, pi, vpi, r, z);
+  if (!learned_precond(c, vpi)) return run_vcycle(c, pi, vpi, r, z);
   const int l = c->L - 1;
   const int64_t n = c->lv[l].size;
   if (c->rho_plain < 0.0) return fail(c, GMG_E_STATE, "learned cycle used before prepare_learned");
@@ -696,6 +717,13 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   void* w = c->kw[pi];
   double hs[kNumScal];
   int rz = S_RZ0;
+  // FCG in FP64 around plain FP32 cycles: the projection of the new residual is
+  // fused with its cast to FP32, and the direction update reads the cycle's FP32
+  // output directly (no FP64 copy of z); the arithmetic is that of the separate
+  // passes, so the iterates are the same bits
+  const bool mixed = pi == 0 && vpi == 1 && flexible && r == c->kr[0] && !learned_precond(c, vpi);
+  float* r32 = static_cast<float*>(c->kr[1]);
+  const float* z32 = static_cast<const float*>(c->kz[1]);
   *iters = 0;
   HIPCHK(c, launch_fill_zero(f32, n, u, s));
   STCHK(project(c, pi, n, r));
@@ -740,7 +768,10 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     // u += alpha p, r -= alpha w, with sum(r) and r.r of the new r in the same pass;
     // the projection r <- r - mean(r) follows, and ||r - mean||^2 = r.r - (sum r)^2 / n
     HIPCHK(c, launch_axpy2_sums(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, c->part, S_SUM, S_RR, s));
-    HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, 1.0 / static_cast<double>(n), r, s));
+    if (mixed)
+      HIPCHK(c, launch_shift_cast(n, c->scal, S_SUM, 1.0 / static_cast<double>(n), static_cast<double*>(r), r32, s));
+    else
+      HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, 1.0 / static_cast<double>(n), r, s));
     STCHK(read_scalars(c, hs, kNumScal));
     rr = std::max(0.0, hs[S_RR] - hs[S_SUM] * hs[S_SUM] / static_cast<double>(n));
     if (!std::isfinite(hs[S_RR])) rr = hs[S_RR];
@@ -752,10 +783,17 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: p^T A p <= 0 or not finite");
     }
     if (std::sqrt(rr) <= tol_abs) continue;
-    STCHK(precondition(c, pi, vpi, r, z));
     // z is projected inside the direction update: p = (z - mean z) + beta p, with
     // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
     const double inv_n = 1.0 / static_cast<double>(n);
+    if (mixed) {
+      STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+      HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
+      HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
+      HIPCHK(c, launch_xpby_shift_mixed(n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z32, static_cast<double*>(p), s));
+      continue;
+    }
+    STCHK(precondition(c, pi, vpi, r, z));
     if (flexible) {
       HIPCHK(c, launch_sums3(f32, n, z, w, c->part, c->scal, S_ZS, S_ZW, S_YS, s));
       HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
@@ -1057,7 +1095,11 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     make_transfer_table(q, &c->xfer);
   }
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
-  c->part_cap = std::max<int64_t>(3 * kRedBlocks, static_cast<int64_t>(c->lv.back().N) * c->lv.back().N);
+  {
+    // N^2 row partials of the finest level, plus room for their first folding pass
+    const int64_t rows = static_cast<int64_t>(c->lv.back().N) * c->lv.back().N;
+    c->part_cap = std::max<int64_t>(3 * kRedBlocks, rows + rows / 64 + 64);
+  }
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->part), sizeof(double) * c->part_cap)) != GMG_OK) return bail(st);
   if (hipMemsetAsync(c->scal, 0, sizeof(double) * kNumScal, c->stream) != hipSuccess) return bail(GMG_E_HIP);
   if ((st = ensure_prec(c, 0)) != GMG_OK) return bail(st);
@@ -1571,7 +1613,7 @@ gmg_status gmg_net_forward(gmg_ctx* ctx, int32_t depth, const float* x_dev, floa
   if (!x_dev || !y_dev || !cache_dev || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
   const int N = ctx->lv[ctx->L - 1 - depth].N;
   return scoped(ctx, [&] {
-    HIPCHK(ctx, launch_net_input(x_dev, nullptr, ctx->q, nullptr, ctx->part, N, cache_dev, ctx->stream));
+    HIPCHK(ctx, launch_net_input(x_dev, nullptr, ctx->q, nullptr, ctx->part, ctx->part_cap, N, cache_dev, ctx->stream));
     HIPCHK(ctx, launch_net_forward(ctx->nets[depth], N, cache_dev, 0, nullptr, y_dev, ctx->stream));
     return GMG_OK;
   });
@@ -1615,7 +1657,7 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
     STCHK(ensure_lcache(ctx, level));
     const Level& L = ctx->lv[level];
     HIPCHK(ctx, launch_fill_zero(true, L.size, e_dev, ctx->stream));
-    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ctx->scal + S_SSUM + level, ctx->part, L.N,
+    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ctx->scal + S_SSUM + level, ctx->part, ctx->part_cap, L.N,
                                  ctx->lcache[level], ctx->stream));
     HIPCHK(ctx, launch_net_forward(ctx->nets[d], L.N, ctx->lcache[level], 1, ctx->scal + S_SSUM + level, e_dev,
                                    ctx->stream, false));
@@ -1656,7 +1698,7 @@ gmg_status gmg_net_loss_grad(gmg_ctx* ctx, int32_t depth, int32_t kind, const fl
     float* et = static_cast<float*>(L.b[1]);
     float* d = static_cast<float*>(L.xp[1]);
     double* ssum = ctx->scal + S_SSUM + l;
-    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ssum, ctx->part, N, cache_dev, s));
+    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ssum, ctx->part, ctx->part_cap, N, cache_dev, s));
     HIPCHK(ctx, launch_net_forward(ctx->nets[depth], N, cache_dev, 0, nullptr, y, s));
     HIPCHK(ctx, launch_net_scale(y, ssum, nv, et, s));
     STCHK(apply_op(ctx, l, 1, Epi::Residual, et, d, r_dev, nullptr, 0, 0));  // d = r - A e~

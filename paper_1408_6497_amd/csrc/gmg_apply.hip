@@ -36,7 +36,10 @@
 //   registers; the whole level sits in cache and no thread waits on another.
 //
 // Epilogues fuse the residual (b - A x) and the Chebyshev-Jacobi step
-// x + c1 (x - x_prev) + c2 D^-1 (b - A x) into the same pass.
+// x + c1 (x - x_prev) + c2 D^-1 (b - A x) into the same pass.  From a zero
+// guess the first two steps are one pass: the input values are b scaled by
+// s0 D^-1 as they are loaded (x_1, formed in FP64 and rounded once, as a
+// separate scaling pass would), and the epilogue stores x_1 beside x_2.
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -56,7 +59,16 @@ struct KTab {
   T zkr[Q][2 * Q + 1];
   T zmr[Q][2 * Q + 1];
   T dinv[Q * Q * Q];
+  double fz[Q * Q * Q];  // s0 D^-1 by node class (first steps from a zero guess)
 };
+
+constexpr int kEpiZero = static_cast<int>(Epi::ChebZero);
+
+// x_1 = s0 D^-1 b at one node of class cls
+template <typename T, int Q>
+__device__ __forceinline__ T x1_of(const KTab<T, Q>& tb, int cls, T b) {
+  return static_cast<T>(tb.fz[cls] * static_cast<double>(b));
+}
 
 // Is offset o (in -Q..Q) a structural nonzero of the assembled 1D row of class c?
 __host__ __device__ constexpr bool tap(int Q, int c, int o) {
@@ -67,10 +79,20 @@ __host__ __device__ constexpr bool tap(int Q, int c, int o) {
 template <typename T, int Q, int EPI>
 __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, const int cy, const int cz,
                                      const T (&ax)[Q], const T* __restrict__ x, T* out, const T* bvec,
-                                     const T* xp, const T c1, const T c2) {
+                                     const T* xp, const T c1, const T c2, T* x1o) {
   using V = VecQ<T, Q>;
   V res;
-  if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+  if constexpr (EPI == kEpiZero) {
+    const V bv = *reinterpret_cast<const V*>(bvec + idx);
+    V x1;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      const int cls = c + Q * (cy + Q * cz);
+      x1.v[c] = x1_of(tb, cls, bv.v[c]);
+      res.v[c] = x1.v[c] + c1 * (x1.v[c] - T(0)) + c2 * tb.dinv[cls] * (bv.v[c] - ax[c]);
+    }
+    *reinterpret_cast<V*>(x1o + idx) = x1;
+  } else if constexpr (EPI == static_cast<int>(Epi::Apply)) {
 #pragma unroll
     for (int c = 0; c < Q; ++c) res.v[c] = ax[c];
   } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
@@ -118,7 +140,7 @@ constexpr int col_rows() {
 template <typename T, int Q, int G, int EPI, int RY, int CY0>
 __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, Q>& tb, const int N, const int TZ,
                                          const int Y0, const int E0, T* out, const T* bvec, const T* xp,
-                                         const T c1, const T c2) {
+                                         const T c1, const T c2, T* x1o) {
   constexpr int TY = G * RY;
   constexpr int NR = RY + 2 * Q;
   constexpr bool kLatePrefetch = Q == 4;
@@ -144,6 +166,14 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     const T* base = x + static_cast<size_t>(p & Nm) * NN;
 #pragma unroll
     for (int r = 0; r < NR; ++r) pre[r] = *reinterpret_cast<const V*>(base + roff[r]);
+    if constexpr (EPI == kEpiZero) {
+      // strip row r has y class (CY0 + r) mod q, the plane z class p mod q
+      const int cz = p & (Q - 1);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < Q; ++c) pre[r].v[c] = x1_of(tb, c + Q * ((CY0 + r) % Q + Q * cz), pre[r].v[c]);
+    }
   };
 
   const int txl = (tx - 1) & (NX - 1);
@@ -271,7 +301,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
 #pragma unroll
           for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
           const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
-          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2);
+          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o);
         }
       }
     }
@@ -292,7 +322,7 @@ template <typename T, int Q, int G, int EPI>
 __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
                                                               const int N, const int TZ, const int ntiles_y,
                                                               T* out, const T* bvec, const T* xp, const T c1,
-                                                              const T c2) {
+                                                              const T c2, T* x1o) {
   constexpr int RY = col_rows<T, Q>();
   constexpr int SPLIT = 4 / RY;  // workgroups per tile
   const int nblocks = gridDim.x;
@@ -302,10 +332,10 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
   const int Y0 = (tile % ntiles_y) * 4 * G;
   const int E0 = (tile / ntiles_y) * TZ;
   if constexpr (SPLIT == 1) {
-    col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2);
+    col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o);
   } else {
-    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2);
-    else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2);
+    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o);
+    else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o);
   }
 }
 
@@ -313,7 +343,8 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
 // Point kernel for small levels: thread = one element column (q nodes) of one row.
 template <typename T, int Q, int EPI>
 __global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const KTab<T, Q> tb, const int N,
-                                                   T* out, const T* bvec, const T* xp, const T c1, const T c2) {
+                                                   T* out, const T* bvec, const T* xp, const T c1, const T c2,
+                                                   T* x1o) {
   const int NX = N / Q;
   const int64_t total = static_cast<int64_t>(NX) * N * N;
   const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -348,6 +379,12 @@ __global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const
       T xr[2 * Q + 1];
 #pragma unroll
       for (int k = 0; k <= 2 * Q; ++k) xr[k] = row[(Q * tx - Q + k + N) & Nm];
+      if constexpr (EPI == kEpiZero) {
+        // node (Q tx - Q + k) has x class k mod q
+        const int base = Q * ((yr & (Q - 1)) + Q * (zr & (Q - 1)));
+#pragma unroll
+        for (int k = 0; k <= 2 * Q; ++k) xr[k] = x1_of(tb, base + k % Q, xr[k]);
+      }
 #pragma unroll
       for (int c = 0; c < Q; ++c) {
         T rk = T(0), rm = T(0);
@@ -362,11 +399,11 @@ __global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const
     }
   }
   const size_t idx = (static_cast<size_t>(zz) * N + yy) * N + Q * tx;
-  emit<T, Q, EPI>(tb, idx, cy, cz, ax, x, out, bvec, xp, c1, c2);
+  emit<T, Q, EPI>(tb, idx, cy, cz, ax, x, out, bvec, xp, c1, c2, x1o);
 }
 
 template <typename T, int Q>
-KTab<T, Q> make_ktab(const OpTab& t) {
+KTab<T, Q> make_ktab(const OpTab& t, double s0) {
   KTab<T, Q> k{};
   for (int c = 0; c < Q; ++c)
     for (int o = 0; o < 2 * Q + 1; ++o) {
@@ -380,7 +417,10 @@ KTab<T, Q> make_ktab(const OpTab& t) {
       k.zk[a][b] = static_cast<T>(t.zk[a][b]);
       k.zm[a][b] = static_cast<T>(t.zm[a][b]);
     }
-  for (int i = 0; i < Q * Q * Q; ++i) k.dinv[i] = static_cast<T>(t.dinv[i]);
+  for (int i = 0; i < Q * Q * Q; ++i) {
+    k.dinv[i] = static_cast<T>(t.dinv[i]);
+    k.fz[i] = s0 * t.dinv[i];
+  }
   return k;
 }
 
@@ -417,19 +457,20 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, const ColShape& 
   hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
                      static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
                      static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
-                     static_cast<T>(a.c2));
+                     static_cast<T>(a.c2), static_cast<T*>(a.x1));
   return hipGetLastError();
 }
 
 template <typename T, int Q, int EPI>
 hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
-  const KTab<T, Q> kt = make_ktab<T, Q>(tab);
+  const KTab<T, Q> kt = make_ktab<T, Q>(tab, a.s0);
   if (a.N <= 32) {
     const int64_t total = static_cast<int64_t>(a.N / Q) * a.N * a.N;
     const int blk = 128;
     hipLaunchKernelGGL((k_apply_pt<T, Q, EPI>), dim3(static_cast<unsigned>((total + blk - 1) / blk)), dim3(blk), 0,
                        s, static_cast<const T*>(a.x), kt, a.N, static_cast<T*>(a.out), static_cast<const T*>(a.b),
-                       static_cast<const T*>(a.xp), static_cast<T>(a.c1), static_cast<T>(a.c2));
+                       static_cast<const T*>(a.xp), static_cast<T>(a.c1), static_cast<T>(a.c2),
+                       static_cast<T*>(a.x1));
     return hipGetLastError();
   }
   const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T), col_rows<T, Q>());
@@ -448,6 +489,9 @@ hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
     case Epi::Apply: return launch_te<T, Q, 0>(tab, a, s);
     case Epi::Residual: return launch_te<T, Q, 1>(tab, a, s);
     case Epi::Cheb: return launch_te<T, Q, 2>(tab, a, s);
+    case Epi::ChebZero:
+      if (a.x1 == nullptr || a.x != a.b) return hipErrorInvalidValue;
+      return launch_te<T, Q, kEpiZero>(tab, a, s);
   }
   return hipErrorInvalidValue;
 }

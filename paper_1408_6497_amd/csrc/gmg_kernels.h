@@ -44,12 +44,15 @@ struct TransferTab {
   double r[kMaxQ][4 * kMaxQ + 1];
 };
 
-enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2 };
+enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3 };
 
 // out = A x                          (Epi::Apply)
 // out = b - A x                      (Epi::Residual)
 // out = x + c1 (x - xp) + c2 D^-1 (b - A x)   (Epi::Cheb; xp unused when c1 == 0,
 //                                      read as zero when null; out may alias xp, never x)
+// the first two Chebyshev steps from x_0 = 0 in one pass (Epi::ChebZero, uniform
+// levels): x_1 = s0 D^-1 b is formed from b as it is loaded (x must be b), then
+// out = x_1 + c1 x_1 + c2 D^-1 (b - A x_1) and x1 = x_1 is stored as well
 struct ApplyArgs {
   int N;  // lattice nodes per direction
   int n;  // elements per direction
@@ -59,6 +62,8 @@ struct ApplyArgs {
   const void* xp;
   double c1, c2;
   Epi epi;
+  void* x1;   // Epi::ChebZero: where x_1 goes
+  double s0;  // Epi::ChebZero: x_1 = s0 D^-1 b
 };
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
@@ -162,6 +167,14 @@ hipError_t launch_axpy2(bool fp32, int64_t n, const double* sc, int i_num, int i
 hipError_t launch_xpby(bool fp32, int64_t n, const double* sc, int i_num, int i_den, double sgn, const void* z,
                        void* p, hipStream_t s);
 hipError_t launch_shift(bool fp32, int64_t n, const double* sc, int i, double scale, void* v, hipStream_t s);
+// FP64 Krylov vectors around FP32 cycles: r -= sc[i] scale and r32 = float(r) in one pass;
+// the (sum z, z.y, sum y) reductions and the p = (z - mean) + beta p update reading the
+// FP32 cycle output z directly
+hipError_t launch_shift_cast(int64_t n, const double* sc, int i, double scale, double* r, float* r32, hipStream_t s);
+hipError_t launch_sums3_mixed(int64_t n, const float* z, const double* y, double* part, double* sc, int dz, int dzy,
+                              int dy, hipStream_t s);
+hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
+                                   double scale, const float* z, double* p, hipStream_t s);
 
 // y += a x with a host scalar; v_i += c tab[class(i)].
 hipError_t launch_axpy(bool fp32, int64_t n, double a, const void* x, void* y, hipStream_t s);
@@ -176,8 +189,9 @@ hipError_t launch_add_f2d(int64_t n, const float* c, double* u, hipStream_t s);
 hipError_t launch_fill_zero(bool fp32, int64_t n, void* v, hipStream_t s);
 hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStream_t s);
 
-// *dst = sum of `count` FP64 partials, in a fixed order (one block).
-hipError_t launch_sum_partials(const double* part, int64_t count, double* dst, hipStream_t s);
+// *dst = sum of `count` FP64 partials, in a fixed order: one block, or for long runs
+// a first pass over chunks of 64 into part[count ..] when part_cap has room for it.
+hipError_t launch_sum_partials(const double* part, int64_t count, int64_t part_cap, double* dst, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Learned smoother (gmg_net.hip): device state of one net.  Master weights w
@@ -201,9 +215,10 @@ int64_t net_cache_bytes(int N);
 int64_t net_partial_floats(int N);
 hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s);
 // cache.x_in = bf16(D^-1 r / s), s = RMS(D^-1 r) written to *ssum as a sum of squares
-// (dinv == null: x_in = bf16(r), ssum unused); part needs N^2 doubles.
-hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part, int N,
-                            void* cache, hipStream_t s);
+// (dinv == null: x_in = bf16(r), ssum unused); part needs N^2 doubles (part_cap of them
+// are allocated; with N^2 + N^2/64 the partials are folded in two passes).
+hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part,
+                            int64_t part_cap, int N, void* cache, hipStream_t s);
 // y = N(x_in) (mode 0) or y += s N(x_in) with s = sqrt(*ssum / N^3) (mode 1).
 // The cache receives a2 always and a1 only with keep_a1 (what the backward pass reads).
 hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, const double* ssum, float* y,

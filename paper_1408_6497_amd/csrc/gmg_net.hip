@@ -646,13 +646,13 @@ hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part, int N,
-                            void* cache, hipStream_t s) {
+hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part,
+                            int64_t part_cap, int N, void* cache, hipStream_t s) {
   uint16_t* xin = static_cast<uint16_t*>(cache);
   if (dinv) {
     const ClassTab64 c = ctab(dinv, q);
     hipLaunchKernelGGL(k_net_sqsum, dim3(1, N, N), dim3(kBlk), 0, s, r, c, q, N, part);
-    const hipError_t e = launch_sum_partials(part, static_cast<int64_t>(N) * N, const_cast<double*>(ssum), s);
+    const hipError_t e = launch_sum_partials(part, static_cast<int64_t>(N) * N, part_cap, const_cast<double*>(ssum), s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_net_in, vgrid(N), dim3(kBlk), 0, s, r, c, q, 1, ssum, N, xin);
   } else {

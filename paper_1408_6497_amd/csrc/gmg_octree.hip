@@ -136,6 +136,7 @@ hipError_t elem(const OctLevelDev& L, bool mass, const T* x, const T* cval, cons
 
 template <typename T>
 hipError_t apply_t(const OctLevelDev& L, bool mass, const OctApply& a, hipStream_t s) {
+  if (a.epi == Epi::ChebZero) return hipErrorInvalidValue;
   const T* x = static_cast<const T*>(a.x);
   T* ye = static_cast<T*>(a.ye);
   const bool f32 = sizeof(T) == 4;
@@ -164,6 +165,8 @@ hipError_t apply_t(const OctLevelDev& L, bool mass, const OctApply& a, hipStream
       hipLaunchKernelGGL((k_oct_dof<T, 2, kDofLanes>), g, dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
                          dinv, c1, c2, out);
       break;
+    case Epi::ChebZero:
+      return hipErrorInvalidValue;  // uniform levels only
   }
   return hipGetLastError();
 }

@@ -188,6 +188,26 @@ __global__ void __launch_bounds__(kBlock) k_sums3(const int64_t n, const T* __re
   }
 }
 
+// (sum z, z.y, sum y) with z the FP32 output of a cycle and y an FP64 Krylov vector
+__global__ void __launch_bounds__(kBlock) k_sums3_mixed(const int64_t n, const float* __restrict__ z,
+                                                        const double* __restrict__ y, double* part) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double zv = static_cast<double>(z[i]);
+    const double yv = y[i];
+    a += zv;
+    b = fma(zv, yv, b);
+    c += yv;
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+    part[2 * gridDim.x + blockIdx.x] = c;
+  }
+}
+
 // dst[k] = sum of the k-th run of nparts partials, k < count (one block per k)
 __global__ void __launch_bounds__(kBlock) k_finish_multi(const double* part, const int nparts, double* sc,
                                                          const int d0, const int d1, const int d2) {
@@ -214,6 +234,43 @@ __global__ void __launch_bounds__(kBlock) k_xpby_shift(const int64_t n, const do
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     p[i] = fma(be, p[i], z[i] - m);
+}
+
+// p = (z - sc[imean] scale) + beta p with z the FP32 output of a cycle, p FP64
+__global__ void __launch_bounds__(kBlock) k_xpby_shift_mixed(const int64_t n, const double* sc, const int inum,
+                                                             const int iden, const double sgn, const int imean,
+                                                             const double scale, const float* __restrict__ z,
+                                                             double* p) {
+  const double be = sgn * sc[inum] / sc[iden];
+  const double m = sc[imean] * scale;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = fma(be, p[i], static_cast<double>(z[i]) - m);
+}
+
+// r -= sc[i0] scale in place (FP64) and r32 = float(r): the projection of the
+// Krylov residual fused with its cast to the precision of the cycle
+__global__ void __launch_bounds__(kBlock) k_shift_cast(const int64_t n, const double* sc, const int i0,
+                                                       const double scale, double* r, float* __restrict__ r32) {
+  const double m = sc[i0] * scale;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double v = r[i] - m;
+    r[i] = v;
+    r32[i] = static_cast<float>(v);
+  }
+}
+
+// Sum of a long run of partials in two fixed-order passes: `blocks` blocks fold
+// contiguous chunks into part2, one block folds those.
+__global__ void __launch_bounds__(kBlock) k_fold(const double* part, const int64_t nparts, const int64_t chunk,
+                                                 double* part2) {
+  const int64_t b0 = blockIdx.x * chunk;
+  const int64_t b1 = b0 + chunk < nparts ? b0 + chunk : nparts;
+  double s = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part2[blockIdx.x] = s;
 }
 
 inline int red_grid(int64_t n) {
@@ -416,6 +473,26 @@ hipError_t launch_sums3(bool fp32, int64_t n, const void* z, const void* y, doub
   return hipGetLastError();
 }
 
+hipError_t launch_sums3_mixed(int64_t n, const float* z, const double* y, double* part, double* sc, int dz, int dzy,
+                              int dy, hipStream_t s) {
+  const int g = red_grid(n);
+  hipLaunchKernelGGL(k_sums3_mixed, dim3(g), dim3(kBlock), 0, s, n, z, y, part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(3), dim3(kBlock), 0, s, part, g, sc, dz, dzy, dy);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
+                                   double scale, const float* z, double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_xpby_shift_mixed, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, inum, iden, sgn, imean, scale,
+                     z, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_cast(int64_t n, const double* sc, int i, double scale, double* r, float* r32, hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_cast, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, i, scale, r, r32);
+  return hipGetLastError();
+}
+
 hipError_t launch_combine(double* sc, int dst, int a, int b, int c, double scale, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(1), dim3(64), 0, s, sc, dst, a, b, c, scale);
   return hipGetLastError();
@@ -449,12 +526,21 @@ hipError_t launch_class_dot(bool fp32, int q, int N, const double* tab, const vo
   else
     hipLaunchKernelGGL(k_class_dot<double>, dim3(1, N, N), dim3(kBlock), 0, s, ct, q, N,
                        static_cast<const double*>(x), part);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, N * N, dst);
-  return hipGetLastError();
+  return launch_sum_partials(part, static_cast<int64_t>(N) * N, part_cap, dst, s);
 }
 
-hipError_t launch_sum_partials(const double* part, int64_t count, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, static_cast<int>(count), dst);
+hipError_t launch_sum_partials(const double* part, int64_t count, int64_t part_cap, double* dst, hipStream_t s) {
+  // short runs: one block; long runs (N^2 row partials): fold chunks of 64 first,
+  // into the tail of the partial buffer when it has room
+  const int64_t chunk = 64;
+  const int64_t blocks = (count + chunk - 1) / chunk;
+  if (count <= 4 * kRedBlocks || count + blocks > part_cap || blocks > 65535) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, static_cast<int>(count), dst);
+    return hipGetLastError();
+  }
+  double* part2 = const_cast<double*>(part) + count;
+  hipLaunchKernelGGL(k_fold, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, part, count, chunk, part2);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part2, static_cast<int>(blocks), dst);
   return hipGetLastError();
 }
 

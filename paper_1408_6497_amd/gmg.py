@@ -313,7 +313,7 @@ class Context:
 
     # -- launch timing (needs timing=1 at construction)
     (KIND_APPLY, KIND_RESIDUAL, KIND_SMOOTH0, KIND_SMOOTH, KIND_MASS, KIND_RESTRICT, KIND_PROLONG, KIND_COARSE,
-     KIND_LEARNED, KIND_SCALE) = range(10)
+     KIND_LEARNED, KIND_SCALE, KIND_SMOOTHZ) = range(11)
 
     def timing(self, level, kind, prec):
         """(launches, seconds) of one level / kind / precision since the last reset."""

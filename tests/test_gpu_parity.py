@@ -134,12 +134,15 @@ def test_coarse_solve_parity(q, n, prec):
     assert rel_l2(to_host(x), ref) <= (1e-12 if prec == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("q,n,levels", [(1, 16, 3), (1, 32, 4), (2, 8, 0), (2, 16, 0), (4, 4, 0), (4, 8, 0)])
+# (1, 64), (2, 32), (4, 16): the finest level (64 nodes a side) runs the streaming column
+# kernel, including the fused first two smoother steps from the zero guess
+@pytest.mark.parametrize("q,n,levels", [(1, 16, 3), (1, 32, 4), (2, 8, 0), (2, 16, 0), (4, 4, 0), (4, 8, 0),
+                                        (1, 64, 0), (2, 32, 0), (4, 16, 0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_vcycle_parity(q, n, levels, prec):
     torch = torch_cuda()
     ctx = _ctx(q, n, levels, seed=5)
-    H = oracle_hierarchy(q, n, ctx.levels, seed=5)
+    H = oracle_hierarchy(q, n, ctx.levels, seed=5, form="kron" if q * n >= 64 else "csr")
     dt = torch.float64 if prec == "fp64" else torch.float32
     r = to_dev(mean_free_normal(H.finest.size, 31), dt)
     z = torch.empty_like(r)
