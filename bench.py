@@ -57,7 +57,9 @@ def smoother_roofline(ctx, order):
     """Achieved bandwidth of the FP32 smoother-step kernel instance
     k_apply_col<float, q, 1, Cheb> -- the one launched on every level with at
     least 64 element columns in x -- over all its launches since the last timing
-    reset, from per-launch HIP events."""
+    reset: algorithmic bytes of those launches over their duration, measured with
+    HIP events on the library stream around each run of consecutive smoother
+    steps (4 or 6 launches of this kernel per smoothing phase)."""
     from paper_1408_6497_amd import Context, GMG_FP32
     launches, sec, algo_bytes = 0, 0.0, 0.0
     per_level = []
@@ -384,7 +386,8 @@ def main():
         "apply": apply,
         "roofline": {
             "kernel": "k_apply_col<float, 2, 1, Cheb>: FP32 smoother step on the 256^3 and 128^3 levels",
-            "measured": "HIP events around every launch in an eager repeat of the timed solve",
+            "measured": ("HIP events on the library stream around each run of consecutive launches of this "
+                         "kernel (one smoothing phase) in an eager repeat of the timed solve"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic["traffic_bytes_per_launch"] if traffic else None),

@@ -251,9 +251,13 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
 /* Per-kernel timing, a tracing aid (Section 3 reports Setup/Eval/Comm phase
  * times; this goes down to single launches).  With gmg_options.timing != 0,
  * every launch of the operator-apply kernel is bracketed by HIP events on the
- * context stream.  gmg_timing_get synchronizes the stream and returns, for one
- * level, kind and precision, the number of launches and their summed duration
- * in seconds since setup or the last gmg_timing_reset.  Kinds:
+ * context stream; inside a smoothing phase the consecutive steps of kinds 2 and
+ * 3 on one level are bracketed as one run, whose time is split between the two
+ * kinds in proportion to their traffic (3 : 4 per launch), so that the events'
+ * own dispatch time is not added to each step.  gmg_timing_get synchronizes
+ * the stream and returns, for one level, kind and precision, the number of
+ * launches and their summed duration in seconds since setup or the last
+ * gmg_timing_reset.  Kinds:
  *   0 y = A x            (algorithmic traffic 2 values per DoF)
  *   1 r = b - A x        (3 values per DoF)
  *   2 smoother step without a previous iterate, x' = x + c D^-1 (b - A x)

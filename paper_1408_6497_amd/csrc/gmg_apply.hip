@@ -13,10 +13,11 @@
 //     owns one element column in x (q nodes, moved as one q-wide vector, so a
 //     wavefront reads 64 q consecutive values per row) and RY rows of the 4
 //     rows 4 ty .. 4 ty + 3 of the tile.  RY = 4 (one workgroup per tile),
-//     except FP64 q = 4, whose accumulators do not fit the register file
-//     four rows deep: there RY = 2 and two workgroups share a tile, one
-//     taking row classes 0, 1 and the other 2, 3 (the class is uniform over
-//     the workgroup, so it stays compile-time);
+//     except FP64 q = 4 and the FP64 q = 2 smoother steps, whose accumulators
+//     do not fit the register file four rows deep: there RY = 2 and two
+//     workgroups share a tile, one taking rows 0, 1 and the other rows 2, 3 of
+//     each group of four (the row class is uniform over the workgroup, so it
+//     stays compile-time);
 //   * each thread loads its own column strip of RY + 2q rows (the y halo wraps
 //     periodically) straight into registers and does the y pass there
 //     (P = My x, S = Ky x); only P and S go through LDS, double-buffered, for
@@ -75,6 +76,24 @@ __host__ __device__ constexpr bool tap(int Q, int c, int o) {
   return c == 0 ? true : (o >= -c && o <= Q - c);
 }
 
+// Non-temporal q-wide store: the output of a plain apply is not read again by
+// the kernel, and keeping it out of the L2 leaves room for the input halos
+// (measured: 512^3 DoF applies about 6% faster, except FP64 q = 4, which is
+// slower with it; the smoother steps, whose output is the next step's input,
+// are slower with it and do not use it).
+template <typename T, int Q>
+__device__ __forceinline__ void store_nt(T* p, const VecQ<T, Q>& v) {
+  if constexpr (Q == 1) {
+    __builtin_nontemporal_store(v.v[0], p);
+  } else {
+    typedef T vt __attribute__((ext_vector_type(Q)));
+    vt w;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) w[c] = v.v[c];
+    __builtin_nontemporal_store(w, reinterpret_cast<vt*>(p));
+  }
+}
+
 // Fused epilogue on one q-wide output vector.
 template <typename T, int Q, int EPI>
 __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, const int cy, const int cz,
@@ -95,6 +114,10 @@ __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, con
   } else if constexpr (EPI == static_cast<int>(Epi::Apply)) {
 #pragma unroll
     for (int c = 0; c < Q; ++c) res.v[c] = ax[c];
+    if constexpr (Q < 4 || sizeof(T) == 4) {
+      store_nt<T, Q>(out + idx, res);
+      return;
+    }
   } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
     const V bv = *reinterpret_cast<const V*>(bvec + idx);
 #pragma unroll
@@ -128,10 +151,16 @@ constexpr int col_bound() {
   return Q == 4 ? 256 : 512;
 }
 
-// rows per thread of the column kernel
-template <typename T, int Q>
+// Rows per thread of the column kernel: FP64 q = 4 and the FP64 q = 2 smoother
+// steps (whose epilogue holds three more vectors) take two, or their element-layer
+// accumulators would spill; the rest take four (measured: FP64 q = 2 smoother step
+// on 256^3 DoFs 140 -> 117 us with two rows, the plain FP64 apply slower with two).
+template <typename T, int Q, int EPI>
 constexpr int col_rows() {
-  return (Q == 4 && sizeof(T) == 8) ? 2 : 4;
+  if (sizeof(T) != 8) return 4;
+  if (Q == 4) return 2;
+  if (Q == 2 && (EPI == static_cast<int>(Epi::Cheb) || EPI == static_cast<int>(Epi::ChebZero))) return 2;
+  return 4;
 }
 
 // --------------------------------------------------------------------------
@@ -323,7 +352,7 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
                                                               const int N, const int TZ, const int ntiles_y,
                                                               T* out, const T* bvec, const T* xp, const T c1,
                                                               const T c2, T* x1o) {
-  constexpr int RY = col_rows<T, Q>();
+  constexpr int RY = col_rows<T, Q, EPI>();
   constexpr int SPLIT = 4 / RY;  // workgroups per tile
   const int nblocks = gridDim.x;
   int b = blockIdx.x;
@@ -473,7 +502,7 @@ hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
                        static_cast<T*>(a.x1));
     return hipGetLastError();
   }
-  const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T), col_rows<T, Q>());
+  const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T), col_rows<T, Q, EPI>());
   if ((a.N / Q) * sh.G > col_bound<Q>()) return hipErrorInvalidConfiguration;
   switch (sh.G) {
     case 1: return launch_col<T, Q, 1, EPI>(kt, a, sh, s);
