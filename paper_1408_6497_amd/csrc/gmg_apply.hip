@@ -34,7 +34,8 @@
 //
 // k_apply_pt (levels with N <= 32, latency-bound): one thread per element
 //   column of one row sums its (2q+1)^3 neighbourhood by sum factorization in
-//   registers; the whole level sits in cache and no thread waits on another.
+//   registers; the whole level sits in cache.  For q = 4 the 9 z rows of the
+//   neighbourhood go to 9 wavefronts and their partial sums meet in LDS.
 //
 // Epilogues fuse the residual (b - A x) and the Chebyshev-Jacobi step
 // x + c1 (x - x_prev) + c2 D^-1 (b - A x) into the same pass.  From a zero
@@ -369,19 +370,30 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
 }
 
 // --------------------------------------------------------------------------
-// Point kernel for small levels: thread = one element column (q nodes) of one row.
-template <typename T, int Q, int EPI>
-__global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const KTab<T, Q> tb, const int N,
-                                                   T* out, const T* bvec, const T* xp, const T c1, const T c2,
-                                                   T* x1o) {
+// Point kernel for small levels: thread = one element column (q nodes) of one
+// row.  With KZ > 1 (q = 4) the 2q+1 z rows of the neighbourhood are split over
+// the KZ = 2q+1 wavefronts of a block (one z row each, so the row loads of a
+// thread are one round of latency instead of 2q+1), and the partial sums are
+// added in LDS in a fixed order.
+template <int KZ>
+constexpr int pt_threads() {
+  return KZ == 1 ? 128 : 64 * KZ;
+}
+
+template <typename T, int Q, int EPI, int KZ>
+__global__ void __launch_bounds__(pt_threads<KZ>()) k_apply_pt(const T* __restrict__ x, const KTab<T, Q> tb,
+                                                               const int N, T* out, const T* bvec, const T* xp,
+                                                               const T c1, const T c2, T* x1o) {
+  constexpr int kCols = KZ == 1 ? 128 : 64;  // element columns per block (blockDim.x)
   const int NX = N / Q;
   const int64_t total = static_cast<int64_t>(NX) * N * N;
-  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (t >= total) return;
+  const int64_t t = blockIdx.x * static_cast<int64_t>(kCols) + threadIdx.x;
+  const bool live = t < total;
+  const int64_t tt = live ? t : 0;
   const int Nm = N - 1;
-  const int tx = static_cast<int>(t % NX);
-  const int yy = static_cast<int>((t / NX) % N);
-  const int zz = static_cast<int>(t / (static_cast<int64_t>(NX) * N));
+  const int tx = static_cast<int>(tt % NX);
+  const int yy = static_cast<int>((tt / NX) % N);
+  const int zz = static_cast<int>(tt / (static_cast<int64_t>(NX) * N));
   const int cy = yy % Q;
   const int cz = zz % Q;
   // sum over the (dz, dy) rows of the neighbourhood of
@@ -390,12 +402,7 @@ __global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const
   T ax[Q];
 #pragma unroll
   for (int c = 0; c < Q; ++c) ax[c] = T(0);
-  // unrolled so that the (2q+1)^2 row loads can be in flight at once (for q = 4 one
-  // z row of the neighbourhood at a time, or the loads would not fit in registers);
-  // taps outside a row's band carry zero weights
-  constexpr int kUnrollZ = Q == 4 ? 1 : 2 * Q + 1;
-#pragma unroll kUnrollZ
-  for (int dz = -Q; dz <= Q; ++dz) {
+  auto zrow = [&](const int dz) {
     const T mz = tb.zmr[cz][dz + Q], kz = tb.zkr[cz][dz + Q];
     const int zr = (zz + dz) & Nm;
 #pragma unroll
@@ -425,6 +432,28 @@ __global__ void __launch_bounds__(128) k_apply_pt(const T* __restrict__ x, const
         }
         ax[c] = fma(wk, rk, fma(wm, rm, ax[c]));
       }
+    }
+  };
+  if constexpr (KZ == 1) {
+    if (!live) return;
+    // unrolled so that all (2q+1)^2 row loads can be in flight at once;
+    // taps outside a row's band carry zero weights
+#pragma unroll
+    for (int dz = -Q; dz <= Q; ++dz) zrow(dz);
+  } else {
+    static_assert(KZ == 2 * Q + 1, "one z row per wavefront");
+    __shared__ T part[KZ][kCols][Q];
+    if (live) zrow(static_cast<int>(threadIdx.y) - Q);
+#pragma unroll
+    for (int c = 0; c < Q; ++c) part[threadIdx.y][threadIdx.x][c] = ax[c];
+    __syncthreads();
+    if (!live || threadIdx.y != 0) return;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      T s = part[0][threadIdx.x][c];
+#pragma unroll
+      for (int g = 1; g < KZ; ++g) s += part[g][threadIdx.x][c];
+      ax[c] = s;
     }
   }
   const size_t idx = (static_cast<size_t>(zz) * N + yy) * N + Q * tx;
@@ -494,12 +523,13 @@ template <typename T, int Q, int EPI>
 hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
   const KTab<T, Q> kt = make_ktab<T, Q>(tab, a.s0);
   if (a.N <= 32) {
+    constexpr int KZ = Q == 4 ? 2 * Q + 1 : 1;
+    constexpr int cols = KZ == 1 ? 128 : 64;
     const int64_t total = static_cast<int64_t>(a.N / Q) * a.N * a.N;
-    const int blk = 128;
-    hipLaunchKernelGGL((k_apply_pt<T, Q, EPI>), dim3(static_cast<unsigned>((total + blk - 1) / blk)), dim3(blk), 0,
-                       s, static_cast<const T*>(a.x), kt, a.N, static_cast<T*>(a.out), static_cast<const T*>(a.b),
-                       static_cast<const T*>(a.xp), static_cast<T>(a.c1), static_cast<T>(a.c2),
-                       static_cast<T*>(a.x1));
+    hipLaunchKernelGGL((k_apply_pt<T, Q, EPI, KZ>), dim3(static_cast<unsigned>((total + cols - 1) / cols)),
+                       dim3(cols, KZ), 0, s, static_cast<const T*>(a.x), kt, a.N, static_cast<T*>(a.out),
+                       static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
+                       static_cast<T>(a.c2), static_cast<T*>(a.x1));
     return hipGetLastError();
   }
   const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T), col_rows<T, Q, EPI>());
