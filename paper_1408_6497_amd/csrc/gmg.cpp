@@ -92,6 +92,7 @@ struct gmg_ctx {
   double* ainv = nullptr;
   int n0 = 0;
   double* scal = nullptr;
+  double* scal_host = nullptr;  // pinned host copy of scal (read back at each convergence test)
   double* part = nullptr;
   int64_t part_cap = 0;
   // finest-level Krylov vectors per precision: r, z, p, w, c
@@ -353,9 +354,11 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   return GMG_OK;
 }
 
+// The scalars go through a pinned buffer: a copy into pageable memory would be staged.
 gmg_status read_scalars(gmg_ctx* c, double* host, int count) {
-  HIPCHK(c, hipMemcpyAsync(host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(host, c->scal_host, sizeof(double) * count);
   return GMG_OK;
 }
 
@@ -767,24 +770,44 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   void* w = c->kw[pi];
   double hs[kNumScal];
   int rz = S_RZ0;
-  // FCG in FP64 around plain FP32 cycles: the projection of the new residual is
-  // fused with its cast to FP32, and the direction update reads the cycle's FP32
-  // output directly (no FP64 copy of z); the arithmetic is that of the separate
-  // passes, so the iterates are the same bits
+  // FCG in FP64 around plain FP32 cycles: the projection of each residual is
+  // fused with its cast to FP32 (and, where the norm is not known yet, with it),
+  // and the direction updates read the cycle's FP32 output directly (no FP64 copy
+  // of z); the arithmetic is that of the separate passes, so the iterates are the
+  // same bits
   const bool mixed = pi == 0 && vpi == 1 && flexible && r == c->kr[0] && !learned_precond(c, vpi);
   float* r32 = static_cast<float*>(c->kr[1]);
   const float* z32 = static_cast<const float*>(c->kz[1]);
   *iters = 0;
-  HIPCHK(c, launch_fill_zero(f32, n, u, s));
-  STCHK(project(c, pi, n, r));
+  const double inv_n = 1.0 / static_cast<double>(n);
+  // r <- r - mean(r) and ||r||^2 -> S_RR (mixed: r32 = float(r) in the same pass)
+  auto project_norm = [&]() -> gmg_status {
+    if (mixed) {
+      HIPCHK(c, launch_sum(false, n, r, c->part, c->scal + S_SUM, s));
+      HIPCHK(c, launch_shift_cast_sq(n, c->scal, S_SUM, inv_n, static_cast<double*>(r), r32, c->part,
+                                     c->scal + S_RR, s));
+      return GMG_OK;
+    }
+    STCHK(project(c, pi, n, r));
+    HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+    return GMG_OK;
+  };
+  // first direction p = z - mean(z), z = V r
   auto restart = [&]() -> gmg_status {
+    if (mixed) {
+      STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+      HIPCHK(c, launch_sum(true, n, z32, c->part, c->scal + S_ZS, s));
+      HIPCHK(c, launch_shift_f2d(n, c->scal, S_ZS, inv_n, z32, static_cast<double*>(p), s));
+      return GMG_OK;
+    }
     STCHK(precondition(c, pi, vpi, r, z));
     STCHK(project(c, pi, n, z));
     if (!flexible) HIPCHK(c, launch_dot(f32, n, r, z, c->part, c->scal + rz, s));
     HIPCHK(c, launch_copy(f32, n, z, p, s));
     return GMG_OK;
   };
-  HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+  HIPCHK(c, launch_fill_zero(f32, n, u, s));
+  STCHK(project_norm());
   STCHK(read_scalars(c, hs, kNumScal));
   double rr = hs[S_RR];
   c->hist_res.push_back(std::sqrt(rr));
@@ -799,8 +822,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     if (std::sqrt(rr) <= tol_abs) {
       if (!b_true) break;
       STCHK(apply_op(c, l, pi, Epi::Residual, u, r, b_true, nullptr, 0, 0));
-      STCHK(project(c, pi, n, r));
-      HIPCHK(c, launch_dot(f32, n, r, r, c->part, c->scal + S_RR, s));
+      STCHK(project_norm());
       STCHK(read_scalars(c, hs, kNumScal));
       rr = hs[S_RR];
       if (std::sqrt(rr) <= tol_abs || it >= maxit) break;
@@ -835,7 +857,6 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     if (std::sqrt(rr) <= tol_abs) continue;
     // z is projected inside the direction update: p = (z - mean z) + beta p, with
     // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
-    const double inv_n = 1.0 / static_cast<double>(n);
     if (mixed) {
       STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
       HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
@@ -1145,6 +1166,11 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     make_transfer_table(q, &c->xfer);
   }
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->scal_host), sizeof(double) * kNumScal, hipHostMallocDefault) !=
+      hipSuccess) {
+    c->scal_host = nullptr;
+    return bail(fail(c, GMG_E_OOM, "hipHostMalloc of the scalar read-back buffer failed"));
+  }
   {
     // N^2 row partials of the finest level, plus room for their first folding pass
     const int64_t rows = static_cast<int64_t>(c->lv.back().N) * c->lv.back().N;
@@ -1197,6 +1223,7 @@ gmg_status gmg_destroy(gmg_ctx* ctx) {
   for (hipGraphExec_t g : ctx->vgraph)
     if (g) (void)hipGraphExecDestroy(g);
   for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
   for (hipEvent_t e : ctx->ev_all) (void)hipEventDestroy(e);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);

@@ -40,8 +40,8 @@
 // Epilogues fuse the residual (b - A x) and the Chebyshev-Jacobi step
 // x + c1 (x - x_prev) + c2 D^-1 (b - A x) into the same pass.  From a zero
 // guess the first two steps are one pass: the input values are b scaled by
-// s0 D^-1 as they are loaded (x_1, formed in FP64 and rounded once, as a
-// separate scaling pass would), and the epilogue stores x_1 beside x_2.
+// s0 D^-1 as they are loaded (x_1, one multiply in the kernel's precision),
+// and the epilogue stores x_1 beside x_2.
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -61,7 +61,7 @@ struct KTab {
   T zkr[Q][2 * Q + 1];
   T zmr[Q][2 * Q + 1];
   T dinv[Q * Q * Q];
-  double fz[Q * Q * Q];  // s0 D^-1 by node class (first steps from a zero guess)
+  T fz[Q * Q * Q];  // s0 D^-1 by node class (first steps from a zero guess)
 };
 
 constexpr int kEpiZero = static_cast<int>(Epi::ChebZero);
@@ -69,7 +69,7 @@ constexpr int kEpiZero = static_cast<int>(Epi::ChebZero);
 // x_1 = s0 D^-1 b at one node of class cls
 template <typename T, int Q>
 __device__ __forceinline__ T x1_of(const KTab<T, Q>& tb, int cls, T b) {
-  return static_cast<T>(tb.fz[cls] * static_cast<double>(b));
+  return tb.fz[cls] * b;
 }
 
 // Is offset o (in -Q..Q) a structural nonzero of the assembled 1D row of class c?
@@ -477,7 +477,7 @@ KTab<T, Q> make_ktab(const OpTab& t, double s0) {
     }
   for (int i = 0; i < Q * Q * Q; ++i) {
     k.dinv[i] = static_cast<T>(t.dinv[i]);
-    k.fz[i] = s0 * t.dinv[i];
+    k.fz[i] = static_cast<T>(s0 * t.dinv[i]);
   }
   return k;
 }

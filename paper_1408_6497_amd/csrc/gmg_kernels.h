@@ -175,6 +175,12 @@ hipError_t launch_sums3_mixed(int64_t n, const float* z, const double* y, double
                               int dy, hipStream_t s);
 hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
                                    double scale, const float* z, double* p, hipStream_t s);
+// the same shift and cast with *dst = ||r - mean||^2 (bits of a dot(r, r) after the shift)
+hipError_t launch_shift_cast_sq(int64_t n, const double* sc, int i, double scale, double* r, float* r32,
+                                double* part, double* dst, hipStream_t s);
+// p = double(z) - sc[i] scale (first direction from an FP32 cycle output)
+hipError_t launch_shift_f2d(int64_t n, const double* sc, int i, double scale, const float* z, double* p,
+                            hipStream_t s);
 
 // y += a x with a host scalar; v_i += c tab[class(i)].
 hipError_t launch_axpy(bool fp32, int64_t n, double a, const void* x, void* y, hipStream_t s);

@@ -261,6 +261,34 @@ __global__ void __launch_bounds__(kBlock) k_shift_cast(const int64_t n, const do
   }
 }
 
+// r -= sc[i0] scale, r32 = float(r), and the partial sums of squares of the new r
+// (the same values, grid and order as a separate dot(r, r) after the shift)
+__global__ void __launch_bounds__(kBlock) k_shift_cast_sq(const int64_t n, const double* sc, const int i0,
+                                                          const double scale, double* r, float* __restrict__ r32,
+                                                          double* part) {
+  const double m = sc[i0] * scale;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double v = r[i] - m;
+    r[i] = v;
+    r32[i] = static_cast<float>(v);
+    s = fma(v, v, s);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = double(z) - sc[i0] scale: the first direction from an FP32 cycle output
+__global__ void __launch_bounds__(kBlock) k_shift_f2d(const int64_t n, const double* sc, const int i0,
+                                                      const double scale, const float* __restrict__ z,
+                                                      double* __restrict__ p) {
+  const double m = sc[i0] * scale;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = static_cast<double>(z[i]) - m;
+}
+
 // Sum of a long run of partials in two fixed-order passes: `blocks` blocks fold
 // contiguous chunks into part2, one block folds those.
 __global__ void __launch_bounds__(kBlock) k_fold(const double* part, const int64_t nparts, const int64_t chunk,
@@ -490,6 +518,20 @@ hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int id
 
 hipError_t launch_shift_cast(int64_t n, const double* sc, int i, double scale, double* r, float* r32, hipStream_t s) {
   hipLaunchKernelGGL(k_shift_cast, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, i, scale, r, r32);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_cast_sq(int64_t n, const double* sc, int i, double scale, double* r, float* r32,
+                                double* part, double* dst, hipStream_t s) {
+  const int g = red_grid(n);
+  hipLaunchKernelGGL(k_shift_cast_sq, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, r, r32, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_f2d(int64_t n, const double* sc, int i, double scale, const float* z, double* p,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_f2d, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, i, scale, z, p);
   return hipGetLastError();
 }
 
