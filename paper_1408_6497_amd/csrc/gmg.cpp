@@ -1162,6 +1162,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
       lev.N = q * lev.n;
       lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
       lev.tab = make_level_tables(q, lev.n);
+      prime_apply_shapes(q, lev.N);
     }
     make_transfer_table(q, &c->xfer);
   }

@@ -42,6 +42,10 @@
 // guess the first two steps are one pass: the input values are b scaled by
 // s0 D^-1 as they are loaded (x_1, one multiply in the kernel's precision),
 // and the epilogue stores x_1 beside x_2.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -484,29 +488,72 @@ KTab<T, Q> make_ktab(const OpTab& t, double s0) {
 
 // Launch shape of the column kernel on one level.
 struct ColShape {
-  int G, TZ, ntiles_y, nblocks;
+  int G, TZ, ntiles_y, nblocks, split;
   size_t lds;
 };
 
-inline ColShape col_shape(int N, int n, int Q, size_t elem, int RY) {
+// Rows per block and LDS of the column kernel on one level (the z chunk TZ is
+// chosen at launch, from the kernel's occupancy).
+inline ColShape col_shape(int N, int Q, size_t elem, int RY) {
   ColShape s{};
   const int nx = N / Q;
-  const int split = 4 / RY;
+  s.split = 4 / RY;
   int G = 1;
   while (G < 4 && G * nx < 64 && 8 * G <= N) G *= 2;  // at least one full wavefront per block
   s.G = G;
   s.ntiles_y = N / (4 * G);
-  // enough blocks for several per CU, as few recomputed element layers as possible
-  int TZ = n;
-  while (TZ > 1 && static_cast<int64_t>(s.ntiles_y) * split * (n / TZ) < 1024) TZ >>= 1;
-  s.TZ = TZ;
-  s.nblocks = s.ntiles_y * split * (n / TZ);
   s.lds = static_cast<size_t>(2 * 2 * RY * G) * N * elem;
   return s;
 }
 
+// Blocks of one column-kernel instance that the device holds at once: blocks per
+// CU from the occupancy API (registers, LDS, block size) times the CU count.
+// Cached per device and LDS size; the context primes it at setup, so no query
+// runs while a launch sequence is being captured into a graph.
 template <typename T, int Q, int G, int EPI>
-hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, const ColShape& sh, hipStream_t s) {
+int resident_blocks(int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<int, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(dev, lds);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  const void* fn = reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>);
+  if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  (void)hipGetLastError();
+  return cache[key] = per_cu * cus;
+}
+
+// z chunk (element layers per block): each block streams its TZ layers plus one
+// recomputed layer, and blocks run in rounds of `resident`; minimise
+// rounds x (TZ + 1), preferring the larger chunk on ties.
+inline int pick_tz(int n, int64_t tiles, int64_t resident) {
+  int best = n;
+  int64_t best_cost = -1;
+  for (int TZ = n; TZ >= 1; TZ >>= 1) {
+    const int64_t blocks = tiles * (n / TZ);
+    const int64_t cost = (blocks + resident - 1) / resident * (TZ + 1);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = TZ;
+    }
+  }
+  return best;
+}
+
+template <typename T, int Q, int G, int EPI>
+hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hipStream_t s) {
+  const int threads = (a.N / Q) * G;
+  const int64_t tiles = static_cast<int64_t>(sh.ntiles_y) * sh.split;
+  sh.TZ = pick_tz(a.n, tiles, resident_blocks<T, Q, G, EPI>(threads, sh.lds));
+  sh.nblocks = static_cast<int>(tiles * (a.n / sh.TZ));
   if (sh.lds > 65536) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
@@ -532,7 +579,7 @@ hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
                        static_cast<T>(a.c2), static_cast<T*>(a.x1));
     return hipGetLastError();
   }
-  const ColShape sh = col_shape(a.N, a.n, Q, sizeof(T), col_rows<T, Q, EPI>());
+  const ColShape sh = col_shape(a.N, Q, sizeof(T), col_rows<T, Q, EPI>());
   if ((a.N / Q) * sh.G > col_bound<Q>()) return hipErrorInvalidConfiguration;
   switch (sh.G) {
     case 1: return launch_col<T, Q, 1, EPI>(kt, a, sh, s);
@@ -540,6 +587,26 @@ hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
     case 4: return launch_col<T, Q, 4, EPI>(kt, a, sh, s);
   }
   return hipErrorInvalidConfiguration;
+}
+
+template <typename T, int Q, int EPI>
+void prime_te(int N) {
+  if (N <= 32) return;
+  const ColShape sh = col_shape(N, Q, sizeof(T), col_rows<T, Q, EPI>());
+  const int threads = (N / Q) * sh.G;
+  switch (sh.G) {
+    case 1: resident_blocks<T, Q, 1, EPI>(threads, sh.lds); break;
+    case 2: resident_blocks<T, Q, 2, EPI>(threads, sh.lds); break;
+    case 4: resident_blocks<T, Q, 4, EPI>(threads, sh.lds); break;
+  }
+}
+
+template <typename T, int Q>
+void prime_tq(int N) {
+  prime_te<T, Q, 0>(N);
+  prime_te<T, Q, 1>(N);
+  prime_te<T, Q, 2>(N);
+  prime_te<T, Q, kEpiZero>(N);
 }
 
 template <typename T, int Q>
@@ -558,6 +625,14 @@ hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
 }  // namespace
 
 int apply_max_elements_x(int q) { return q == 4 ? 256 : 512; }
+
+void prime_apply_shapes(int q, int N) {
+  switch (q) {
+    case 1: prime_tq<float, 1>(N); prime_tq<double, 1>(N); break;
+    case 2: prime_tq<float, 2>(N); prime_tq<double, 2>(N); break;
+    case 4: prime_tq<float, 4>(N); prime_tq<double, 4>(N); break;
+  }
+}
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s) {
   // shape checks: the launch shapes above assume these

@@ -67,6 +67,10 @@ struct ApplyArgs {
 };
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
+// Query (once per device) the occupancy that the launch shape of every apply
+// kernel instance for a level of N nodes a side depends on; call before any
+// launch sequence is captured into a graph.
+void prime_apply_shapes(int q, int N);
 
 // Device arrays of one octree level (owned by the library context).  The
 // stiffness is C^T blockdiag(h_e kref) C and the mass C^T blockdiag(h_e^3 mref) C,
