@@ -120,7 +120,9 @@ typedef struct {
                                V-cycles and flexible CG); see gmg_set_learned            */
   int32_t learned_depths;   /* > 0: only depths 0 .. learned_depths-1 use a net; the other
                                levels keep the Chebyshev smoother (0: every level)       */
-  int32_t reserved_opt;
+  int32_t no_fused_tail;    /* != 0: run the level of 16^3 nodes next to the coarsest with
+                               the separate kernels of every other level instead of the
+                               one-workgroup kernels that keep it in LDS (testing aid)  */
 } gmg_options;
 
 typedef struct {
@@ -272,7 +274,10 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
  *     levels and degree-1 smoothers)
  *  10 first two Chebyshev steps from a zero guess in one pass on uniform levels:
  *     x_1 = D^-1 b / theta formed from b as it is loaded, x_2 = x_1 + c1 x_1 +
- *     c2 D^-1 (b - A x_1); x_1 and x_2 are stored (3 values per DoF)            */
+ *     c2 D^-1 (b - A x_1); x_1 and x_2 are stored (3 values per DoF)
+ *  11 the cycle of the uniform 16^3-node level next to the coarsest, run by one
+ *     workgroup from LDS (pre-smoothing, residual and restriction; prolongation
+ *     and post-smoothing: two launches per cycle)                               */
 gmg_status gmg_timing_get(gmg_ctx* ctx, int32_t level, int32_t kind, gmg_prec prec, int64_t* launches,
                           double* seconds);
 gmg_status gmg_timing_reset(gmg_ctx* ctx);

@@ -206,8 +206,9 @@ enum : int {
   K_LEARNED = 8,
   K_SCALE = 9,    // first smoother step from a zero guess: x = c D^-1 b (no operator apply)
   K_SMOOTHZ = 10,  // first two Chebyshev steps from a zero guess in one pass
+  K_TAIL = 11,     // one-workgroup cycle on the 16^3-node level (smoothing, residual, transfers)
 };
-constexpr int kKinds = 11;
+constexpr int kKinds = 12;
 inline int tslot(int level, int kind, int pi) { return (level * kKinds + kind) * 2 + pi; }
 
 hipEvent_t take_event(gmg_ctx* c) {
@@ -283,7 +284,7 @@ void phase_totals(const gmg_ctx* c, double out[4]) {
   for (int l = 0; l < c->L; ++l)
     for (int pi = 0; pi < 2; ++pi) {
       auto t = [&](int k) { return c->tsec[tslot(l, k, pi)]; };
-      out[0] += t(K_SMOOTH0) + t(K_SMOOTH) + t(K_SCALE) + t(K_SMOOTHZ);
+      out[0] += t(K_SMOOTH0) + t(K_SMOOTH) + t(K_SCALE) + t(K_SMOOTHZ) + t(K_TAIL);
       out[1] += t(K_RESTRICT) + t(K_PROLONG);
       out[2] += t(K_COARSE);
       out[3] += t(K_LEARNED);
@@ -522,11 +523,71 @@ gmg_status learned_correction(gmg_ctx* c, int l, const void* b, void* u) {
   });
 }
 
+// Smoother coefficients of one smoothing phase on level l (the recurrence of
+// smooth(): Chebyshev steps j = 0 .. degree-1 per application, or Jacobi steps).
+void phase_steps(const gmg_ctx* c, const Level& L, int nu, int* count, double* c1, double* c2) {
+  int k = *count;
+  if (c->opt.smoother == 1) {
+    for (int s = 0; s < nu; ++s, ++k) {
+      c1[k] = 0.0;
+      c2[k] = c->opt.jacobi_omega;
+    }
+  } else {
+    const double theta = 0.5 * (L.beta + L.alpha);
+    const double delta = 0.5 * (L.beta - L.alpha);
+    const double sigma = theta / delta;
+    for (int app = 0; app < nu; ++app) {
+      double rho = 1.0 / sigma;
+      for (int j = 0; j < c->opt.cheb_degree; ++j, ++k) {
+        c1[k] = 0.0;
+        c2[k] = 1.0 / theta;
+        if (j > 0) {
+          const double rho_new = 1.0 / (2.0 * sigma - rho);
+          c1[k] = rho_new * rho;
+          c2[k] = 2.0 * rho_new / delta;
+          rho = rho_new;
+        }
+      }
+    }
+  }
+  *count = k;
+}
+
+// The level of 16^3 nodes next to the coarsest runs its whole cycle in two
+// one-workgroup launches around the coarsest solve (uniform levels, plain smoother).
+bool fused_tail(const gmg_ctx* c, int l, int pi, TailSteps* st) {
+  if (l != 1 || c->opt.no_fused_tail || c->lv[l].oct || learned_on_level(c, l, pi)) return false;
+  const int deg = c->opt.smoother == 1 ? 1 : c->opt.cheb_degree;
+  if (c->opt.nu_pre < 0 || c->opt.nu_post < 0 || deg < 1 ||
+      static_cast<int64_t>(c->opt.nu_pre + c->opt.nu_post) * deg > kTailMaxSteps)
+    return false;
+  int k = 0;
+  phase_steps(c, c->lv[l], c->opt.nu_pre, &k, st->c1, st->c2);
+  st->npre = k;
+  phase_steps(c, c->lv[l], c->opt.nu_post, &k, st->c1, st->c2);
+  st->npost = k - st->npre;
+  return tail_supported(c->q, pi == 1, c->lv[l].N, c->lv[0].N, *st);
+}
+
 // Algorithm 2.1 on level l with zero initial guess: u = V_l b.
 gmg_status vcycle_level(gmg_ctx* c, int l, int pi, const void* b, void* u) {
   if (l == 0) return coarse_solve(c, pi, b, u);
   Level& L = c->lv[l];
   Level& C = c->lv[l - 1];
+  TailSteps st{};
+  if (fused_tail(c, l, pi, &st)) {
+    const bool f32 = pi == 1;
+    STCHK(timed(c, l, K_TAIL, pi, [&]() -> gmg_status {
+      HIPCHK(c, launch_tail_down(L.tab.stiff, c->xfer, st, f32, b, u, C.b[pi], c->stream));
+      return GMG_OK;
+    }));
+    STCHK(coarse_solve(c, pi, C.b[pi], C.u[pi]));
+    STCHK(timed(c, l, K_TAIL, pi, [&]() -> gmg_status {
+      HIPCHK(c, launch_tail_up(L.tab.stiff, c->xfer, st, f32, b, u, C.u[pi], c->stream));
+      return GMG_OK;
+    }));
+    return GMG_OK;
+  }
   // learned cycle: in each smoothing phase the last polynomial application is
   // replaced by one learned correction
   const bool lrn = learned_on_level(c, l, pi);

@@ -246,4 +246,21 @@ hipError_t launch_net_loss_gy(const float* d, const double* ssum, const double* 
 // b and x of the kernel precision, arithmetic in FP64.
 hipError_t launch_coarse(bool fp32, int n0, const double* ainv, const void* b, void* x, hipStream_t s);
 
+// One-workgroup cycle on the uniform level of 16^3 nodes whose coarser
+// neighbour is the coarsest level (8^3 nodes): the smoother steps are
+// x' = x + c1[s] (x - x_prev) + c2[s] D^-1 (b - A x), npre of them from u = 0
+// before the coarse-grid correction and npost after it.
+constexpr int kTailMaxSteps = 24;
+struct TailSteps {
+  int npre, npost;
+  double c1[kTailMaxSteps], c2[kTailMaxSteps];
+};
+bool tail_supported(int q, bool fp32, int N, int Nc, const TailSteps& st);
+// u = pre-smoothed iterate from 0, bc = P^T (b - A u)   (u: 16^3, bc: 8^3)
+hipError_t launch_tail_down(const OpTab& op, const TransferTab& xf, const TailSteps& st, bool fp32, const void* b,
+                            void* u, void* bc, hipStream_t s);
+// u += P ec, then the post-smoothing steps
+hipError_t launch_tail_up(const OpTab& op, const TransferTab& xf, const TailSteps& st, bool fp32, const void* b,
+                          void* u, const void* ec, hipStream_t s);
+
 }  // namespace gmg

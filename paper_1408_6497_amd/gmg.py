@@ -49,7 +49,7 @@ class GmgOptions(ctypes.Structure):
         ("inner_rtol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("lambda_override", ctypes.c_double),
         ("timing", ctypes.c_int32), ("no_graphs", ctypes.c_int32),
         ("ir_mode", ctypes.c_int32), ("use_learned", ctypes.c_int32),
-        ("learned_depths", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
+        ("learned_depths", ctypes.c_int32), ("no_fused_tail", ctypes.c_int32),
     ]
 
 
@@ -313,7 +313,7 @@ class Context:
 
     # -- launch timing (needs timing=1 at construction)
     (KIND_APPLY, KIND_RESIDUAL, KIND_SMOOTH0, KIND_SMOOTH, KIND_MASS, KIND_RESTRICT, KIND_PROLONG, KIND_COARSE,
-     KIND_LEARNED, KIND_SCALE, KIND_SMOOTHZ) = range(11)
+     KIND_LEARNED, KIND_SCALE, KIND_SMOOTHZ, KIND_TAIL) = range(12)
 
     def timing(self, level, kind, prec):
         """(launches, seconds) of one level / kind / precision since the last reset."""

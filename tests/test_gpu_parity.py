@@ -154,6 +154,37 @@ def test_vcycle_parity(q, n, levels, prec):
     assert err <= (1e-11 if prec == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("q,n", [(1, 16), (2, 8), (2, 16), (4, 4)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fused_tail_level_parity(q, n, prec):
+    """The 16^3-node level next to the coarsest runs its cycle in two one-workgroup
+    launches (LDS-resident smoothing, residual and transfers); with the fusion on and
+    off the V-cycle matches the oracle, and the two agree to rounding."""
+    torch = torch_cuda()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    fused = _ctx(q, n, 0, seed=5)
+    plain = _ctx(q, n, 0, seed=5, no_fused_tail=1, timing=1)
+    H = oracle_hierarchy(q, n, fused.levels, seed=5)
+    r = to_dev(mean_free_normal(H.finest.size, 41), dt)
+    zf, zp = torch.empty_like(r), torch.empty_like(r)
+    fused.vcycle(r, zf)
+    plain.vcycle(r, zp)
+    torch.cuda.synchronize()
+    ref = H.vcycle(to_host(r))
+    tol = 1e-11 if prec == "fp64" else 1e-4
+    ef, ep, efp = rel_l2(to_host(zf), ref), rel_l2(to_host(zp), ref), rel_l2(to_host(zf), to_host(zp))
+    print(f"[tail] q={q} n={n} {prec}: fused {ef:.2e} separate {ep:.2e} between {efp:.2e}", flush=True)
+    assert ef <= tol and ep <= tol and efp <= tol
+    # the separate path really ran separate kernels on that level
+    from paper_1408_6497_amd import Context
+    assert plain.timing(1, Context.KIND_TAIL, 0 if prec == "fp64" else 1)[0] == 0
+    fused_t = _ctx(q, n, 0, seed=5, timing=1)
+    fused_t.vcycle(r, zf)
+    fused_used = fused_t.timing(1, Context.KIND_TAIL, 0 if prec == "fp64" else 1)[0] > 0
+    assert fused_used == (fused.levels >= 2 and q * n // (1 << (fused.levels - 2)) == 16
+                          and not (q == 4 and prec == "fp64"))
+
+
 def _oracle_residual(q, n, u, b):
     from oracle import operator as op
     A = op.assemble(q, n)
