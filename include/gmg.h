@@ -123,6 +123,8 @@ typedef struct {
   int32_t no_fused_tail;    /* != 0: run the level of 16^3 nodes next to the coarsest with
                                the separate kernels of every other level instead of the
                                one-workgroup kernels that keep it in LDS (testing aid)  */
+  int32_t learned_min_depth; /* > 0: depths below this keep the Chebyshev smoother (the
+                               finest levels, where a net application costs the most)   */
 } gmg_options;
 
 typedef struct {

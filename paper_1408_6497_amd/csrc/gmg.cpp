@@ -498,6 +498,7 @@ int net_for_depth(const gmg_ctx* c, int d) {
 bool learned_on_level(const gmg_ctx* c, int l, int pi) {
   const int d = c->L - 1 - l;
   if (c->opt.learned_depths > 0 && d >= c->opt.learned_depths) return false;
+  if (d < c->opt.learned_min_depth) return false;
   if (c->lv[l].oct) return false;  // the lattice convolution needs a uniform level
   return c->opt.use_learned && !c->suppress_learned && pi == 1 && l > 0 && c->lv[l].N >= 16 &&
          net_for_depth(c, d) >= 0;

@@ -141,6 +141,32 @@ def test_learned_solve_converges_and_fallback_fires():
         assert len(res) >= info.inner_iters + 1 and res[-1] <= 1e-8 * res[0]
 
 
+def test_learned_min_depth_keeps_the_finest_levels_plain():
+    """learned_min_depth = 2: the two finest levels keep the Chebyshev smoother (no net
+    launches there), the coarser levels with at least 16 nodes a side use the net, and the
+    solve still reaches the tolerance on the oracle's operator."""
+    torch = torch_cuda()
+    from oracle import learned, multigrid as mg, operator as op
+    from paper_1408_6497_amd import Context, GMG_FP32
+    from workloads import gaussian_params, gaussian_source
+    q, n = 2, 32   # levels of 64, 32, 16 and 8 nodes a side
+    ctx = _ctx(q, n, seed=4, use_learned=1, learned_min_depth=2, timing=1)
+    ctx.net_set_weights(0, learned.jacobi_weights(0.625))
+    f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(2, 32, 0.02, 0.1)).cuda()
+    u = torch.empty_like(f)
+    info = ctx.solve(f, u, 1e-8)
+    torch.cuda.synchronize()
+    L = ctx.levels
+    used = [ctx.timing(l, Context.KIND_LEARNED, GMG_FP32)[0] for l in range(L)]
+    print(f"[learned-min-depth] levels {L}: learned launches per level {used}, iters {info.inner_iters}", flush=True)
+    assert used[L - 1] == 0 and used[L - 2] == 0      # depths 0 and 1
+    assert used[L - 3] > 0                            # depth 2: 16 nodes a side
+    b = mg.rhs(q, n, to_host(f))
+    res = b - op.assemble(q, n) @ to_host(u)
+    res -= res.mean()
+    assert np.linalg.norm(res) / np.linalg.norm(b) <= 1e-8 * 1.001
+
+
 @pytest.mark.parametrize("kind", ["energy", "residual"])
 def test_loss_gradient_parity(kind):
     """gmg_net_loss_grad (forward, A e~, loss, backward through A and the net) vs the oracle."""
