@@ -16,6 +16,13 @@
 namespace gmg {
 namespace {
 
+// K consecutive values moved as one aligned vector access (x passes: the nodes
+// of one element column are contiguous and aligned to their count).
+template <typename T, int K>
+struct alignas(sizeof(T) * K) VecK {
+  T v[K];
+};
+
 template <typename T, int Q, int AXIS, bool ACC>
 __global__ void __launch_bounds__(256) k_prolong_axis(const T* __restrict__ in, T* __restrict__ out,
                                                        const TransferTab tab, const int X, const int Y,
@@ -49,30 +56,51 @@ __global__ void __launch_bounds__(256) k_prolong_axis(const T* __restrict__ in, 
   const int ix = AXIS == 0 ? Nc : X;
   const int iy = AXIS == 1 ? Nc : Y;
   T c[Q + 1];
+  if constexpr (AXIS == 0) {
+    // coarse nodes QE .. QE+Q-1 as one vector, the shared vertex QE+Q on its own
+    const T* row = in + (static_cast<size_t>(k) * iy + j) * ix;
+    const VecK<T, Q> cv = *reinterpret_cast<const VecK<T, Q>*>(row + Q * E);
 #pragma unroll
-  for (int a = 0; a <= Q; ++a) {
-    const int ca = (Q * E + a) & ncm;
-    int ii = i, jj = j, kk = k;
-    if (AXIS == 0) ii = ca;
-    else if (AXIS == 1) jj = ca;
-    else kk = ca;
-    c[a] = in[(static_cast<size_t>(kk) * iy + jj) * ix + ii];
+    for (int a = 0; a < Q; ++a) c[a] = cv.v[a];
+    c[Q] = row[(Q * E + Q) & ncm];
+  } else {
+#pragma unroll
+    for (int a = 0; a <= Q; ++a) {
+      const int ca = (Q * E + a) & ncm;
+      int ii = i, jj = j, kk = k;
+      if (AXIS == 1) jj = ca;
+      else kk = ca;
+      c[a] = in[(static_cast<size_t>(kk) * iy + jj) * ix + ii];
+    }
   }
+  if constexpr (AXIS == 0) {
+    // the element's 2q fine nodes as one vector
+    T* orow = out + (static_cast<size_t>(k) * Y + j) * (2 * Nc);
+    VecK<T, 2 * Q> fv;
+    if (ACC) fv = *reinterpret_cast<const VecK<T, 2 * Q>*>(orow + 2 * Q * E);
 #pragma unroll
-  for (int b = 0; b < 2 * Q; ++b) {
-    double s = 0.0;
+    for (int b = 0; b < 2 * Q; ++b) {
+      double s = 0.0;
 #pragma unroll
-    for (int a = 0; a <= Q; ++a) s = fma(tab.p[b][a], static_cast<double>(c[a]), s);
-    const int f = 2 * Q * E + b;
-    int ii = i, jj = j, kk = k;
-    if (AXIS == 0) ii = f;
-    else if (AXIS == 1) jj = f;
-    else kk = f;
-    const int ox = AXIS == 0 ? 2 * Nc : X;
-    const int oy = AXIS == 1 ? 2 * Nc : Y;
-    const size_t o = (static_cast<size_t>(kk) * oy + jj) * ox + ii;
-    if (ACC) out[o] = static_cast<T>(static_cast<double>(out[o]) + s);
-    else out[o] = static_cast<T>(s);
+      for (int a = 0; a <= Q; ++a) s = fma(tab.p[b][a], static_cast<double>(c[a]), s);
+      fv.v[b] = ACC ? static_cast<T>(static_cast<double>(fv.v[b]) + s) : static_cast<T>(s);
+    }
+    *reinterpret_cast<VecK<T, 2 * Q>*>(orow + 2 * Q * E) = fv;
+  } else {
+#pragma unroll
+    for (int b = 0; b < 2 * Q; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a <= Q; ++a) s = fma(tab.p[b][a], static_cast<double>(c[a]), s);
+      const int f = 2 * Q * E + b;
+      int ii = i, jj = j, kk = k;
+      if (AXIS == 1) jj = f;
+      else kk = f;
+      const int oy = AXIS == 1 ? 2 * Nc : Y;
+      const size_t o = (static_cast<size_t>(kk) * oy + jj) * X + ii;
+      if (ACC) out[o] = static_cast<T>(static_cast<double>(out[o]) + s);
+      else out[o] = static_cast<T>(s);
+    }
   }
 }
 
@@ -108,17 +136,30 @@ __global__ void __launch_bounds__(256) k_restrict_axis(const T* __restrict__ in,
   const int ix = AXIS == 0 ? Nf : X;
   const int iy = AXIS == 1 ? Nf : Y;
   T f[4 * Q + 1];
+  if constexpr (AXIS == 0) {
+    // fine nodes 2qE-2q .. 2qE+2q: two aligned vectors of 2q and the far vertex
+    const T* row = in + (static_cast<size_t>(k) * iy + j) * ix;
+    const VecK<T, 2 * Q> lv = *reinterpret_cast<const VecK<T, 2 * Q>*>(row + ((2 * Q * E - 2 * Q + Nf) & nfm));
+    const VecK<T, 2 * Q> rv = *reinterpret_cast<const VecK<T, 2 * Q>*>(row + 2 * Q * E);
 #pragma unroll
-  for (int t = 0; t <= 4 * Q; ++t) {
-    const int fa = (2 * Q * E - 2 * Q + t + Nf) & nfm;
-    int ii = i, jj = j, kk = k;
-    if (AXIS == 0) ii = fa;
-    else if (AXIS == 1) jj = fa;
-    else kk = fa;
-    f[t] = in[(static_cast<size_t>(kk) * iy + jj) * ix + ii];
+    for (int t = 0; t < 2 * Q; ++t) {
+      f[t] = lv.v[t];
+      f[2 * Q + t] = rv.v[t];
+    }
+    f[4 * Q] = row[(2 * Q * E + 2 * Q) & nfm];
+  } else {
+#pragma unroll
+    for (int t = 0; t <= 4 * Q; ++t) {
+      const int fa = (2 * Q * E - 2 * Q + t + Nf) & nfm;
+      int ii = i, jj = j, kk = k;
+      if (AXIS == 1) jj = fa;
+      else kk = fa;
+      f[t] = in[(static_cast<size_t>(kk) * iy + jj) * ix + ii];
+    }
   }
   const int ox = AXIS == 0 ? Nc : X;
   const int oy = AXIS == 1 ? Nc : Y;
+  VecK<T, Q> cv;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     double s = 0.0;
@@ -127,13 +168,17 @@ __global__ void __launch_bounds__(256) k_restrict_axis(const T* __restrict__ in,
       if (a > 0 && t < 2 * Q) continue;  // only the vertex reaches into the left element
       s = fma(tab.r[a][t], static_cast<double>(f[t]), s);
     }
-    const int cidx = Q * E + a;
-    int ii = i, jj = j, kk = k;
-    if (AXIS == 0) ii = cidx;
-    else if (AXIS == 1) jj = cidx;
-    else kk = cidx;
-    out[(static_cast<size_t>(kk) * oy + jj) * ox + ii] = static_cast<T>(s);
+    cv.v[a] = static_cast<T>(s);
+    if constexpr (AXIS != 0) {
+      const int cidx = Q * E + a;
+      int ii = i, jj = j, kk = k;
+      if (AXIS == 1) jj = cidx;
+      else kk = cidx;
+      out[(static_cast<size_t>(kk) * oy + jj) * ox + ii] = cv.v[a];
+    }
   }
+  if constexpr (AXIS == 0)  // the element's q coarse nodes as one vector
+    *reinterpret_cast<VecK<T, Q>*>(out + (static_cast<size_t>(k) * oy + j) * ox + Q * E) = cv;
 }
 
 constexpr int kTB = 128;
