@@ -185,6 +185,45 @@ def test_fused_tail_level_parity(q, n, prec):
                           and not (q == 4 and prec == "fp64"))
 
 
+@pytest.mark.parametrize("q,n", [(1, 16), (1, 64), (2, 8), (2, 32)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_paper_jacobi_v21_vcycle_parity(q, n, prec):
+    """The paper's own cycle (Section 3 runs): damped Jacobi, omega = 2/3, two pre- and one
+    post-smoothing sweep, on the column-kernel levels, the fused 16^3 level and the point kernel."""
+    torch = torch_cuda()
+    from oracle import multigrid as mg
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = _ctx(q, n, 0, seed=5, smoother=1, jacobi_omega=2.0 / 3.0, nu_pre=2, nu_post=1)
+    opts = mg.Options(seed=5, smoother="jacobi", jacobi_omega=2.0 / 3.0, nu_pre=2, nu_post=1)
+    H = mg.Hierarchy(q, n, ctx.levels, opts, form="kron" if q * n >= 64 else "csr")
+    r = to_dev(mean_free_normal(H.finest.size, 51), dt)
+    z = torch.empty_like(r)
+    ctx.vcycle(r, z)
+    torch.cuda.synchronize()
+    err = rel_l2(to_host(z), H.vcycle(to_host(r)))
+    print(f"[jacobi-v21] q={q} n={n} {prec} rel={err:.2e}", flush=True)
+    assert err <= (1e-11 if prec == "fp64" else 1e-4)
+
+
+def test_paper_jacobi_v21_solve():
+    """PCG with the Jacobi V(2,1) cycle reaches 1e-10 on the oracle's operator (C1 sizes)."""
+    torch = torch_cuda()
+    from oracle import multigrid as mg, operator as op
+    from workloads import gaussian_params, gaussian_source
+    q, n = 1, 32
+    ctx = _ctx(q, n, 4, seed=1, smoother=1, jacobi_omega=2.0 / 3.0, nu_pre=2, nu_post=1)
+    f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1)).cuda()
+    u = torch.empty_like(f)
+    info = ctx.solve(f, u, 1e-10)
+    torch.cuda.synchronize()
+    b = mg.rhs(q, n, to_host(f))
+    res = b - op.assemble(q, n) @ to_host(u)
+    res -= res.mean()
+    rel = np.linalg.norm(res) / np.linalg.norm(b)
+    print(f"[jacobi-v21-solve] iters={info.inner_iters} rel={rel:.2e}", flush=True)
+    assert rel <= 1e-10 * 1.001
+
+
 def _oracle_residual(q, n, u, b):
     from oracle import operator as op
     A = op.assemble(q, n)
