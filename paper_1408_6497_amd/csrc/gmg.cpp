@@ -93,6 +93,7 @@ struct gmg_ctx {
   int n0 = 0;
   double* scal = nullptr;
   double* scal_host = nullptr;  // pinned host copy of scal (read back at each convergence test)
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // bracket each solve (gmg_info.t_solve)
   double* part = nullptr;
   int64_t part_cap = 0;
   // finest-level Krylov vectors per precision: r, z, p, w, c
@@ -821,8 +822,11 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // b_true - A c (and r is reset to it if that is above tolerance).  The
 // convergence test comes right after the residual update, so no V-cycle is
 // spent on a residual that already meets the tolerance.
+//
+// norm_slot >= 0: tol_abs is relative to sqrt(scal[norm_slot]) (a norm the caller
+// enqueued, read back together with the first residual norm), which goes to *norm.
 gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true, void* u, void* r, double tol_abs,
-                  int maxit, int* iters, double* final_rr) {
+                  int maxit, int* iters, double* final_rr, int norm_slot = -1, double* norm = nullptr) {
   const int l = c->L - 1;
   const int64_t n = c->lv[l].size;
   const bool f32 = pi == 1;
@@ -871,6 +875,16 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   HIPCHK(c, launch_fill_zero(f32, n, u, s));
   STCHK(project_norm());
   STCHK(read_scalars(c, hs, kNumScal));
+  if (norm_slot >= 0) {
+    const double nb = std::sqrt(hs[norm_slot]);
+    if (norm) *norm = nb;
+    if (!std::isfinite(nb)) return fail(c, GMG_E_BREAKDOWN, "load vector is not finite");
+    tol_abs *= nb;
+    if (nb == 0.0) {  // u = 0 solves it
+      *final_rr = 0.0;
+      return GMG_OK;
+    }
+  }
   double rr = hs[S_RR];
   c->hist_res.push_back(std::sqrt(rr));
   bool have_dir = false;
@@ -1190,7 +1204,8 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     return GMG_E_HIP;
   }
   if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&c->ev_t0) != hipSuccess || hipEventCreate(&c->ev_t1) != hipSuccess) {
     gmg_destroy(c);
     return GMG_E_HIP;
   }
@@ -1289,6 +1304,8 @@ gmg_status gmg_destroy(gmg_ctx* ctx) {
   if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
   for (hipEvent_t e : ctx->ev_all) (void)hipEventDestroy(e);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_t0) (void)hipEventDestroy(ctx->ev_t0);
+  if (ctx->ev_t1) (void)hipEventDestroy(ctx->ev_t1);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -1416,14 +1433,17 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
     STCHK(drain_timing(c));
     phase_totals(c, ph0);
   }
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
+  hipEvent_t e0 = c->ev_t0, e1 = c->ev_t1;
   HIPCHK(c, hipEventRecord(e0, s));
   double hs[kNumScal];
   HIPCHK(c, launch_dot(false, n, b_dev, b_dev, c->part, c->scal + S_TMP, s));
-  STCHK(read_scalars(c, hs, kNumScal));
-  const double nb = std::sqrt(hs[S_TMP]);
+  // the Krylov paths read ||b|| back together with their first residual norm
+  const bool krylov_path = c->opt.vcycle_prec != GMG_FP32 || c->opt.ir_mode == 0;
+  double nb = 1.0;
+  if (!krylov_path) {
+    STCHK(read_scalars(c, hs, kNumScal));
+    nb = std::sqrt(hs[S_TMP]);
+  }
   gmg_status st = GMG_OK;
   if (!std::isfinite(nb)) {
     st = fail(c, GMG_E_BREAKDOWN, "load vector is not finite");
@@ -1437,19 +1457,20 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
     HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));
     int it = 0;
     double rr = 0.0;
-    st = krylov(c, 0, 1, true, b_dev, u_dev, c->kr[0], rtol * nb, c->opt.max_iters, &it, &rr);
+    st = krylov(c, 0, 1, true, b_dev, u_dev, c->kr[0], rtol, c->opt.max_iters, &it, &rr, S_TMP, &nb);
     inf.inner_iters = it;
     inf.outer_iters = it;
-    inf.rel_residual_f64 = std::sqrt(rr) / nb;
+    inf.rel_residual_f64 = nb > 0.0 ? std::sqrt(rr) / nb : 0.0;
     if (st == GMG_OK && !(inf.rel_residual_f64 <= rtol)) st = fail(c, GMG_E_NOCONV, "max_iters reached");
   } else if (c->opt.vcycle_prec != GMG_FP32) {
     // plain FP64: CG / FCG(1) preconditioned by one FP64 V-cycle
     HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));
     int it = 0;
     double rr = 0.0;
-    st = krylov(c, 0, 0, c->opt.krylov == 1, b_dev, u_dev, c->kr[0], rtol * nb, c->opt.max_iters, &it, &rr);
+    st = krylov(c, 0, 0, c->opt.krylov == 1, b_dev, u_dev, c->kr[0], rtol, c->opt.max_iters, &it, &rr, S_TMP,
+                &nb);
     inf.inner_iters = it;
-    inf.rel_residual_f64 = std::sqrt(rr) / nb;
+    inf.rel_residual_f64 = nb > 0.0 ? std::sqrt(rr) / nb : 0.0;
     if (st == GMG_OK && !(inf.rel_residual_f64 <= rtol)) st = fail(c, GMG_E_NOCONV, "max_iters reached");
   } else {
     // FP64 iterative refinement around FP32 FCG(1) with FP32 V-cycles.  Each
@@ -1509,8 +1530,6 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   float ms = 0.0f;
   HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
   inf.t_solve = ms * 1e-3;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   inf.fallbacks = static_cast<int32_t>(c->fallbacks);
   if (c->opt.timing) {
     STCHK(drain_timing(c));
