@@ -296,6 +296,12 @@ gmg_status gmg_timing_reset(gmg_ctx* ctx);
  * g_i(d) = (d' / s_i^2) exp(-d'^2 / (2 s_i^2)), d' = max(d, s_i) (a bound on the
  * gradient of a_i exp(-r^2 / (2 s_i^2)) over the box), until no leaf is split;
  * then 2:1 balance.  centres: 3 * count doubles (x, y, z), sigma, amps: count.
+ * gmg_octree_refine_sharp_layer: the same for f = -Laplace(u) of the sharp-layer
+ * solution u = exp(-(r/R)^alpha) of the paper's second time-to-solution test
+ * (Section 3), r the periodic distance to centre (3 doubles in [0, 1)): split
+ * while h_O max|f'| > tol max|f|, the maxima from a radial table with spacing
+ * R / (16 alpha) over the entries that cover O's distance range from the centre.
+ * R > 0, 2 < alpha <= 1e4.
  * gmg_octree_balance: the coarsest 2:1-balanced refinement of a complete octree
  * (GMG_E_MESH if the input is not complete).
  * gmg_level_leaves: the leaves of one level of an octree context.
@@ -303,6 +309,9 @@ gmg_status gmg_timing_reset(gmg_ctx* ctx);
 gmg_status gmg_octree_refine_gaussians(int32_t base_level, int32_t max_level, int32_t count, const double* centres_host,
                                        const double* sigma_host, const double* amps_host, double tol,
                                        uint64_t* morton_out, uint8_t* level_out, int64_t cap, int64_t* n_out);
+gmg_status gmg_octree_refine_sharp_layer(int32_t base_level, int32_t max_level, const double* centre_host,
+                                         double radius, double alpha, double tol, uint64_t* morton_out,
+                                         uint8_t* level_out, int64_t cap, int64_t* n_out);
 gmg_status gmg_octree_balance(const uint64_t* morton_host, const uint8_t* level_host, int64_t n, uint64_t* morton_out,
                               uint8_t* level_out, int64_t cap, int64_t* n_out);
 gmg_status gmg_level_leaves(const gmg_ctx* ctx, int32_t level, uint64_t* morton_out, uint8_t* level_out, int64_t cap,

@@ -20,6 +20,15 @@ Readings (the paper is silent on them):
     g(d) = (d'/s_i^2) exp(-d'^2 / (2 s_i^2)) with d' = max(d, s_i): an upper
     bound of |grad| of the Gaussian a_i exp(-r^2 / (2 s_i^2)) over the box.
 
+  * Refinement for the sharp-layer solution u = exp(-(r/R)^alpha) of the time-to-
+    solution test case (Section 3; f = -Laplace(u) in closed form): split leaf O
+    while its level is below the maximum and  h_O max|f'| > tol max|f|, the maxima
+    taken over a radial table of |f'(r)| and |f(r)| at r_j = j dr,
+    dr = R / (16 alpha), with the box's periodic distance range [d_min, d_max]
+    from the centre covered by the table entries floor(d_min/dr) .. ceil(d_max/dr).
+    The table spacing is a sixteenth of the layer width R / alpha, so the peak of
+    |f'| near r = R is not missed between entries.
+
 Representation: a leaf is (level, x, y, z) with its anchor in units of
 2^-DMAX; its Morton key interleaves the anchor bits with x in the lowest bit.
 A linear octree is a list of leaves sorted by Morton key.
@@ -164,6 +173,87 @@ def gradient_indicator(o, centres, sigma, amps):
         d = max(periodic_box_distance(c, lo, h), s)
         tot += abs(a) * (d / (s * s)) * math.exp(-d * d / (2.0 * s * s))
     return h * tot
+
+
+def periodic_box_distance_range(c, lo, h):
+    """(d_min, d_max): least and greatest periodic (nearest-image) distance from point c
+    to the points of the box [lo, lo + h]^3 on the unit torus."""
+    d2min = 0.0
+    d2max = 0.0
+    for k in range(3):
+        best = math.inf
+        for m in (-1.0, 0.0, 1.0):
+            ck = c[k] + m
+            best = min(best, max(0.0, lo[k] - ck, ck - (lo[k] + h)))
+        # the nearest-image distance along one axis is a tent in x with its top at the
+        # point opposite c; over [lo, lo + h] it is largest at an end or at that top
+        def tent(x):
+            d = abs(x - c[k]) % 1.0
+            return min(d, 1.0 - d)
+        far = max(tent(lo[k]), tent(lo[k] + h))
+        opp = (c[k] + 0.5) % 1.0
+        if lo[k] <= opp <= lo[k] + h or lo[k] <= opp + 1.0 <= lo[k] + h:
+            far = 0.5
+        d2min += best * best
+        d2max += far * far
+    return math.sqrt(d2min), math.sqrt(d2max)
+
+
+def sharp_layer_profile(r, R, alpha):
+    """(f(r), f'(r)) of f = -Laplace(u), u = exp(-s), s = (r/R)^alpha, written from
+    u' = -e^-s s', s' = alpha s / r:  f = e^-s (alpha s / r^2) (alpha + 1 - alpha s)."""
+    if r <= 0.0:
+        return 0.0, 0.0
+    s = math.exp(alpha * math.log(r / R))
+    e = math.exp(-s)
+    g = s / (r * r)
+    w = alpha + 1.0 - alpha * s
+    f = e * alpha * g * w
+    # d/dr of e^-s alpha g w, with s' = alpha s / r, g' = (alpha - 2) g / r, w' = -alpha s'
+    fp = alpha * e * (g / r) * (-alpha * s * w - alpha * alpha * s + w * (alpha - 2.0))
+    return f, fp
+
+
+def sharp_layer_table(R, alpha):
+    """(dr, |f'(r_j)|, max |f|) on r_j = j dr up to the largest periodic distance."""
+    dr = R / (16.0 * alpha)
+    count = int(math.ceil(math.sqrt(3.0) / 2.0 / dr)) + 2
+    fpabs = []
+    fmax = 0.0
+    for j in range(count):
+        f, fp = sharp_layer_profile(j * dr, R, alpha)
+        fpabs.append(abs(fp))
+        fmax = max(fmax, abs(f))
+    return dr, fpabs, fmax
+
+
+def sharp_layer_indicator(o, centre, table):
+    """h_O max |f'| over the table entries covering O's distance range from the centre."""
+    dr, fpabs, _ = table
+    l, x, y, z = o
+    h = 1.0 / (1 << l)
+    dmin, dmax = periodic_box_distance_range(centre, (x / UNITS, y / UNITS, z / UNITS), h)
+    j0 = int(math.floor(dmin / dr))
+    j1 = min(int(math.ceil(dmax / dr)), len(fpabs) - 1)
+    return h * max(fpabs[j0:j1 + 1])
+
+
+def refine_sharp_layer(base_level, max_level, centre, R, alpha, tol=1e-2):
+    """Uniform base, split every leaf whose indicator exceeds tol max|f| (below max_level),
+    until none does; then 2:1 balance."""
+    table = sharp_layer_table(R, alpha)
+    thresh = tol * table[2]
+    todo = uniform(base_level)
+    done = []
+    while todo:
+        nxt = []
+        for o in todo:
+            if o[0] < max_level and sharp_layer_indicator(o, centre, table) > thresh:
+                nxt.extend(children(o))
+            else:
+                done.append(o)
+        todo = nxt
+    return balance(sort_leaves(done))
 
 
 def refine_gaussians(base_level, max_level, centres, sigma, amps, tol=1e-2):

@@ -1593,6 +1593,22 @@ gmg_status gmg_octree_refine_gaussians(int32_t base_level, int32_t max_level, in
   }
 }
 
+gmg_status gmg_octree_refine_sharp_layer(int32_t base_level, int32_t max_level, const double* centre, double radius,
+                                         double alpha, double tol, uint64_t* morton_out, uint8_t* level_out,
+                                         int64_t cap, int64_t* n_out) {
+  if (!n_out || !centre || base_level < 0 || max_level > oct::kMaxLevel || base_level > max_level ||
+      !(tol > 0.0) || !(radius > 0.0) || !(alpha > 2.0) || !(alpha <= 1e4))
+    return GMG_E_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!(centre[k] >= 0.0 && centre[k] < 1.0)) return GMG_E_ARG;
+  try {
+    return write_leaves(oct::refine_sharp_layer(base_level, max_level, centre, radius, alpha, tol), morton_out,
+                        level_out, cap, n_out);
+  } catch (...) {
+    return GMG_E_OOM;
+  }
+}
+
 gmg_status gmg_octree_balance(const uint64_t* morton, const uint8_t* level, int64_t n, uint64_t* morton_out,
                               uint8_t* level_out, int64_t cap, int64_t* n_out) {
   if (!morton || !level || n <= 0 || !n_out) return GMG_E_ARG;

@@ -200,6 +200,96 @@ std::vector<Leaf> refine_gaussians(int base_level, int max_level, int count, con
   return balance(t);
 }
 
+namespace {
+
+// Least and greatest nearest-image distance from c to the box [lo, lo + h]^3.
+void box_distance_range(const double* c, const double lo[3], double h, double* dmin, double* dmax) {
+  double d2min = 0.0, d2max = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double best = INFINITY;
+    for (int m = -1; m <= 1; ++m) {
+      const double ck = c[k] + m;
+      best = std::min(best, std::max({0.0, lo[k] - ck, ck - (lo[k] + h)}));
+    }
+    // the one-axis nearest-image distance is a tent with its top opposite c: over
+    // [lo, lo + h] it is largest at an end or at that top
+    auto tent = [&](double x) {
+      const double d = std::fmod(std::fabs(x - c[k]), 1.0);
+      return std::min(d, 1.0 - d);
+    };
+    double far = std::max(tent(lo[k]), tent(lo[k] + h));
+    const double opp = std::fmod(c[k] + 0.5, 1.0);
+    if ((lo[k] <= opp && opp <= lo[k] + h) || (lo[k] <= opp + 1.0 && opp + 1.0 <= lo[k] + h)) far = 0.5;
+    d2min += best * best;
+    d2max += far * far;
+  }
+  *dmin = std::sqrt(d2min);
+  *dmax = std::sqrt(d2max);
+}
+
+// f = -Laplace(u) of u = exp(-s), s = (r/R)^alpha, and f' (radial):
+// f = e^-s (alpha s / r^2) (alpha + 1 - alpha s).
+void sharp_layer_profile(double r, double R, double alpha, double* f, double* fp) {
+  if (r <= 0.0) {
+    *f = 0.0;
+    *fp = 0.0;
+    return;
+  }
+  const double s = std::exp(alpha * std::log(r / R));
+  const double e = std::exp(-s);
+  const double g = s / (r * r);
+  const double w = alpha + 1.0 - alpha * s;
+  *f = e * alpha * g * w;
+  // with s' = alpha s / r, g' = (alpha - 2) g / r, w' = -alpha s'
+  *fp = alpha * e * (g / r) * (-alpha * s * w - alpha * alpha * s + w * (alpha - 2.0));
+}
+
+}  // namespace
+
+std::vector<Leaf> refine_sharp_layer(int base_level, int max_level, const double* centre, double R, double alpha,
+                                     double tol) {
+  // |f'| on r_j = j dr, dr = R / (16 alpha) (a sixteenth of the layer width), and max |f|
+  const double dr = R / (16.0 * alpha);
+  const int count = static_cast<int>(std::ceil(std::sqrt(3.0) / 2.0 / dr)) + 2;
+  std::vector<double> fpabs(count);
+  double fmax = 0.0;
+  for (int j = 0; j < count; ++j) {
+    double f, fp;
+    sharp_layer_profile(j * dr, R, alpha, &f, &fp);
+    fpabs[j] = std::fabs(fp);
+    fmax = std::max(fmax, std::fabs(f));
+  }
+  const double thresh = tol * fmax;
+  auto indicator = [&](const Leaf& o) {
+    const double h = 1.0 / static_cast<double>(1 << o.level);
+    const double lo[3] = {o.x / static_cast<double>(kUnits), o.y / static_cast<double>(kUnits),
+                          o.z / static_cast<double>(kUnits)};
+    double dmin, dmax;
+    box_distance_range(centre, lo, h, &dmin, &dmax);
+    const int j0 = static_cast<int>(std::floor(dmin / dr));
+    const int j1 = std::min(static_cast<int>(std::ceil(dmax / dr)), count - 1);
+    double m = 0.0;
+    for (int j = j0; j <= j1; ++j) m = std::max(m, fpabs[j]);
+    return h * m;
+  };
+  std::vector<Leaf> t = uniform(base_level);
+  while (true) {
+    std::vector<Leaf> next;
+    bool changed = false;
+    for (const Leaf& o : t) {
+      if (o.level < max_level && indicator(o) > thresh) {
+        push_children(o, &next);
+        changed = true;
+      } else {
+        next.push_back(o);
+      }
+    }
+    t.swap(next);
+    if (!changed) break;
+  }
+  return balance(t);
+}
+
 std::vector<Leaf> coarsen(const std::vector<Leaf>& t, int min_level) {
   std::vector<Leaf> out;
   out.reserve(t.size());

@@ -34,6 +34,12 @@ std::vector<Leaf> balance(const std::vector<Leaf>& t);
 // h sum_i |a_i| g(d_i) exceeds tol sum_i |a_i| is split, until none is; then balance.
 std::vector<Leaf> refine_gaussians(int base_level, int max_level, int count, const double* centres,
                                    const double* sigma, const double* amps, double tol);
+// Uniform base level, then every leaf below max_level with h max|f'| > tol max|f| is split,
+// until none is; then balance.  f = -Laplace(u) for u = exp(-(r/R)^alpha), r the periodic
+// distance to centre; the maxima come from a radial table with spacing R / (16 alpha),
+// over the table entries covering the leaf's distance range.
+std::vector<Leaf> refine_sharp_layer(int base_level, int max_level, const double* centre, double R, double alpha,
+                                     double tol);
 // Merge every complete family of 8 sibling leaves with parent level >= min_level, then balance.
 std::vector<Leaf> coarsen(const std::vector<Leaf>& t, int min_level);
 

@@ -26,7 +26,7 @@ EXPORTS = [
     "gmg_timing_get", "gmg_timing_reset", "gmg_history", "gmg_status_string", "gmg_last_error",
     "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
-    "gmg_octree_refine_gaussians", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
+    "gmg_octree_refine_gaussians", "gmg_octree_refine_sharp_layer", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
     "gmg_net_get_state", "gmg_net_set_state",
 ]
 
@@ -107,6 +107,7 @@ def load():
         "gmg_timing_reset": [P],
         "gmg_history": [P, I32, P, I64, ctypes.POINTER(I64)],
         "gmg_octree_refine_gaussians": [I32, I32, I32, P, P, P, D, P, P, I64, ctypes.POINTER(I64)],
+        "gmg_octree_refine_sharp_layer": [I32, I32, P, D, D, D, P, P, I64, ctypes.POINTER(I64)],
         "gmg_octree_balance": [P, P, I64, P, P, I64, ctypes.POINTER(I64)],
         "gmg_level_leaves": [P, I32, P, P, I64, ctypes.POINTER(I64)],
         "gmg_num_elements": [P, I32, ctypes.POINTER(I64)],
@@ -461,6 +462,16 @@ def octree_refine_gaussians(base_level, max_level, centres, sigma, amps, tol=1e-
         raise ValueError("centres, sigma and amps differ in length")
     vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
     return _leaves_call(lib.gmg_octree_refine_gaussians, base_level, max_level, len(a), vp(c), vp(s), vp(a), tol)
+
+
+def octree_refine_sharp_layer(base_level, max_level, centre, radius, alpha, tol=1e-2):
+    """Leaves (morton, level) of the gradient-refined, 2:1-balanced octree of the source of
+    the sharp-layer solution exp(-(r/radius)^alpha) around centre."""
+    import numpy as np
+    lib = load()
+    c = np.ascontiguousarray(centre, dtype=np.float64).reshape(3)
+    return _leaves_call(lib.gmg_octree_refine_sharp_layer, base_level, max_level,
+                        c.ctypes.data_as(ctypes.c_void_p), float(radius), float(alpha), tol)
 
 
 def octree_balance(keys, levels):

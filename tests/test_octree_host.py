@@ -42,6 +42,30 @@ def test_refine_gaussians_matches_oracle(seed, count, sigma, base, top):
     assert _as_leaves(keys, lev) == ref
 
 
+@pytest.mark.parametrize("base,top,centre,radius,alpha,tol", [
+    (2, 4, (0.5, 0.5, 0.5), 0.25, 10.0, 1e-2),
+    (3, 5, (0.3, 0.6, 0.9), 0.2, 20.0, 1e-2),
+    (2, 5, (0.01, 0.99, 0.5), 0.3, 40.0, 3e-2),   # the layer wraps across three faces
+])
+def test_refine_sharp_layer_matches_oracle(base, top, centre, radius, alpha, tol):
+    gmg, _ = _lib()
+    keys, lev = gmg.octree_refine_sharp_layer(base, top, centre, radius, alpha, tol)
+    assert _as_leaves(keys, lev) == ot.refine_sharp_layer(base, top, centre, radius, alpha, tol)
+
+
+def test_refine_sharp_layer_rejects_bad_arguments():
+    gmg, lib = _lib()
+    cnt = ctypes.c_int64()
+    c = np.array([0.5, 0.5, 0.5])
+    vp = c.ctypes.data_as(ctypes.c_void_p)
+    for args in ((3, 2, vp, 0.25, 10.0, 1e-2), (2, 4, vp, 0.0, 10.0, 1e-2), (2, 4, vp, 0.25, 2.0, 1e-2),
+                 (2, 4, None, 0.25, 10.0, 1e-2), (2, 11, vp, 0.25, 10.0, 1e-2)):
+        assert lib.gmg_octree_refine_sharp_layer(*args, None, None, 0, ctypes.byref(cnt)) == 1  # GMG_E_ARG
+    bad = np.array([0.5, 1.0, 0.5])
+    assert lib.gmg_octree_refine_sharp_layer(2, 4, bad.ctypes.data_as(ctypes.c_void_p), 0.25, 10.0, 1e-2,
+                                             None, None, 0, ctypes.byref(cnt)) == 1
+
+
 def test_balance_matches_oracle_and_rejects_incomplete():
     gmg, lib = _lib()
     leaves = set(ot.uniform(2))

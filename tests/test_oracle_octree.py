@@ -1,5 +1,6 @@
 """Pins of the oracle's periodic octree and its continuous Q_q space with hanging nodes."""
 import json
+import math
 import os
 
 import numpy as np
@@ -306,3 +307,81 @@ def test_octree_vcycle_is_symmetric_and_pcg_converges():
     u, info = krylov.pcg(S.A, b, MG.vcycle, 1e-10, 50)
     assert info.converged and info.iters <= 12
     assert np.linalg.norm(b - S.A @ u) <= 1e-10 * np.linalg.norm(b) * 1.001
+
+
+# ---------------------------------------------------------------- sharp layer (test case 2)
+
+def test_sharp_layer_profile_is_minus_the_radial_laplacian():
+    """f = -(u'' + 2 u'/r) for u = exp(-(r/R)^alpha), and f' is the derivative of f:
+    both against central differences of the plain definitions, across the layer."""
+    R, alpha = 0.25, 10.0
+    u = lambda r: math.exp(-((r / R) ** alpha))
+    h = 1e-5
+    for r in np.linspace(0.05, 0.45, 41):
+        f, fp = ot.sharp_layer_profile(r, R, alpha)
+        upp = (u(r + h) - 2.0 * u(r) + u(r - h)) / (h * h)
+        up = (u(r + h) - u(r - h)) / (2.0 * h)
+        assert abs(f + upp + 2.0 * up / r) <= 1e-4 * 400.0
+        fdf = (ot.sharp_layer_profile(r + h, R, alpha)[0] - ot.sharp_layer_profile(r - h, R, alpha)[0]) / (2 * h)
+        assert abs(fp - fdf) <= 1e-5 * max(1.0, abs(fp))
+    assert ot.sharp_layer_profile(0.0, R, alpha) == (0.0, 0.0)
+
+
+def test_periodic_box_distance_range_brackets_every_point():
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        c = rng.random(3)
+        l = int(rng.integers(1, 5))
+        h = 1.0 / (1 << l)
+        lo = rng.integers(0, 1 << l, 3) * h
+        dmin, dmax = ot.periodic_box_distance_range(c, lo, h)
+        pts = lo + h * rng.random((400, 3))
+        d = np.abs(pts - c) % 1.0
+        d = np.minimum(d, 1.0 - d)
+        r = np.sqrt((d * d).sum(1))
+        assert r.min() >= dmin - 1e-12 and r.max() <= dmax + 1e-12
+        # the corners and the box's nearest point attain the range up to the sampling
+        assert dmin == pytest.approx(ot.periodic_box_distance(c, lo, h), abs=1e-15)
+        assert r.max() >= dmax - 2 * h
+
+
+def test_sharp_layer_refinement_concentrates_on_the_sphere():
+    """Leaves cut by the sphere r = R reach the finest level, every finest leaf lies in a band
+    around the sphere, and the tree is complete and 2:1 balanced."""
+    centre, R, alpha, top = (0.5, 0.5, 0.5), 0.25, 10.0, 5
+    tree = ot.refine_sharp_layer(2, top, centre, R, alpha, 1e-2)
+    assert ot.is_linear_complete(tree) and not ot.violators(tree)
+    finest = 0
+    for l, x, y, z in tree:
+        h = 1.0 / (1 << l)
+        dmin, dmax = ot.periodic_box_distance_range(centre, (x / ot.UNITS, y / ot.UNITS, z / ot.UNITS), h)
+        if dmin <= R <= dmax:
+            assert l == top
+        if l == top:
+            finest += 1
+        if dmin > 0.4:  # exp(-(0.4/R)**alpha) < 1e-50: the source and its slope vanish there
+            assert l < top
+    assert finest > len(tree) // 2
+
+
+def _assert_refines(coarse, fine):
+    """Every leaf of `fine` lies inside some leaf of `coarse` (fine refines coarse)."""
+    cells = {(l, x, y, z) for l, x, y, z in coarse}
+    for l, x, y, z in fine:
+        hit = False
+        for lc in range(l, -1, -1):
+            m = ot.UNITS >> lc
+            if (lc, x - x % m, y - y % m, z - z % m) in cells:
+                hit = True
+                break
+        assert hit
+
+
+def test_sharp_layer_smaller_tolerance_refines_the_tree():
+    """The criterion h * max|f'| > tol * max|f| only switches on more cells as tol falls, so the
+    tree for a smaller tolerance refines the tree for a larger one."""
+    centre, R, alpha = (0.5, 0.5, 0.5), 0.25, 10.0
+    loose = ot.refine_sharp_layer(2, 5, centre, R, alpha, 1e-1)
+    tight = ot.refine_sharp_layer(2, 5, centre, R, alpha, 1e-2)
+    assert len(tight) > len(loose)
+    _assert_refines(loose, tight)

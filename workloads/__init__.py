@@ -14,6 +14,10 @@ Sources (shapes of the paper's workloads, Section 3):
                       and amplitudes, minus their exact mean (smooth but
                       localized sources, and the sharp-layer regime at small
                       widths).
+  * sharp_layer       u = exp(-(r/R)^alpha), r the periodic distance to a centre,
+                      and f = -Laplace(u) in closed form (the paper's second
+                      time-to-solution test, a sharp internal layer on the sphere
+                      r = R).
   * grf               Gaussian random fields with power spectrum |k|^-alpha.
   * normal_vector     seeded N(0, 1) vectors for operator-level parity.
 """
@@ -79,6 +83,23 @@ def gaussian_source_points(points, params):
             g *= _periodic_gauss_1d(pts[:, d], c[d], s)
         f += a * (g - (2.0 * math.pi * s * s) ** 1.5)
     return f
+
+
+def sharp_layer(points, centre=(0.5, 0.5, 0.5), radius=0.25, alpha=10.0):
+    """(u, f) at points (P, 3): u = exp(-s), s = (r/R)^alpha with r the nearest-image
+    distance to centre on the unit torus, and f = -Laplace(u) = e^-s (alpha s / r^2)
+    (alpha + 1 - alpha s) (radial Laplacian u'' + 2 u' / r; f -> 0 as r -> 0 for
+    alpha > 2).  u and f are not periodic, but for radius <= 0.3 and alpha >= 10 they
+    and their derivatives vanish to below 1e-14 at the faces."""
+    pts = np.asarray(points, dtype=np.float64)
+    d = np.abs(pts - np.asarray(centre, dtype=np.float64)[None, :]) % 1.0
+    d = np.minimum(d, 1.0 - d)
+    r = np.sqrt(np.sum(d * d, axis=1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = np.where(r > 0.0, np.exp(alpha * np.log(np.where(r > 0.0, r, 1.0) / radius)), 0.0)
+        rr = np.where(r > 0.0, r * r, 1.0)
+        f = np.where(r > 0.0, np.exp(-s) * (alpha * s / rr) * (alpha + 1.0 - alpha * s), 0.0)
+    return np.exp(-s), f
 
 
 def sin_source(x1d, device=None):
