@@ -241,6 +241,46 @@ def octree_workload(steps=5):
     return out
 
 
+def sharp_layer_workload(alpha=40.0, radius=0.25, tops=(6, 7, 8), steps=3, tol=1e-10):
+    """Time to accuracy for the sharp-layer solution u = exp(-(r/R)^alpha) (R 0.25, centre of
+    the unit torus), f = -Laplace(u) in closed form: octrees refined on the gradient of f from
+    level 2 to each maximum level, Q1 and Q2, FP32 cycles in FP64 flexible CG to the residual
+    tol; reports DoFs, the nodal max-norm error modulo a constant and the solve time."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32, octree_refine_sharp_layer
+    from workloads import sharp_layer
+    out = {"workload": f"sharp layer exp(-(r/R)^alpha), alpha {alpha:g}, R {radius:g}, octree levels 2..L "
+                       f"refined on h max|f'| > 1e-2 max|f|, FP32 cycles in FP64 flexible CG to {tol:g}",
+           "runs": []}
+    for top in tops:
+        t0 = time.perf_counter()
+        leaves = octree_refine_sharp_layer(2, top, (0.5, 0.5, 0.5), radius, alpha, 1e-2)
+        t_tree = time.perf_counter() - t0
+        for q in (1, 2):
+            ctx = Context(q, 0, leaves=leaves, seed=0, vcycle_prec=GMG_FP32)
+            ue, f = sharp_layer(ctx.dof_coords(), radius=radius, alpha=alpha)
+            fd = torch.from_numpy(f).cuda()
+            u = torch.empty_like(fd)
+            ctx.solve(fd, u, tol, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = ctx.solve(fd, u, tol, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t_solve = (time.perf_counter() - t0) / steps
+            e = u.cpu().numpy() - ue
+            run = {"q": q, "L": top, "leaves": int(leaves[0].size), "dofs": ctx.num_dofs(),
+                   "linf_err": float(0.5 * (e.max() - e.min())), "solve_s": t_solve,
+                   "iters": info.inner_iters, "rel_residual_f64": info.rel_residual_f64,
+                   "setup_s": info.t_setup, "tree_build_s": t_tree}
+            log(f"[bench] sharp layer {run}")
+            out["runs"].append(run)
+            ctx.close()
+            del fd, u
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +393,7 @@ def main():
         extra["learned"] = learned_workload()
         extra["q4_sharp"] = q4_workload()
         extra["octree"] = octree_workload()
+        extra["sharp_layer"] = sharp_layer_workload()
 
     traffic = traffic_record()
     cpu = None
