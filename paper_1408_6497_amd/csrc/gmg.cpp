@@ -48,7 +48,11 @@ enum : int {
   S_YS = 14,    // sum w or sum r   (fused direction update)
   S_ZWC = 15,   // (z - mean z) . w
   S_SSUM = 16,  // + level: sum of (D^-1 r)^2 of the learned correction on that level
+  S_RS = 48,    // sum of the stored Krylov residual (FCG around FP32 cycles)
+  S_WS = 49,    // sum of w = A p                      (the same)
 };
+// a hierarchy has at most 11 levels (n <= 512 uniform, leaf level <= 10 octree)
+static_assert(S_SSUM + 32 <= S_RS && S_WS < kNumScal, "scalar slots overlap");
 
 struct Level {
   int n = 0, N = 0;   // uniform: elements and lattice nodes per direction (0 on octree levels)
@@ -836,11 +840,11 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   void* w = c->kw[pi];
   double hs[kNumScal];
   int rz = S_RZ0;
-  // FCG in FP64 around plain FP32 cycles: the projection of each residual is
-  // fused with its cast to FP32 (and, where the norm is not known yet, with it),
-  // and the direction updates read the cycle's FP32 output directly (no FP64 copy
-  // of z); the arithmetic is that of the separate passes, so the iterates are the
-  // same bits
+  // FCG in FP64 around plain FP32 cycles: the residual update, its projection
+  // and its cast to FP32 are one pass (the mean it removes is predicted from
+  // sum(r) and sum(w), reduced with the step's products; the stored residual's
+  // exact sum keeps the norm and the next prediction exact), and the direction
+  // updates read the cycle's FP32 output directly (no FP64 copy of z)
   const bool mixed = pi == 0 && vpi == 1 && flexible && r == c->kr[0] && !learned_precond(c, vpi);
   float* r32 = static_cast<float*>(c->kr[1]);
   const float* z32 = static_cast<const float*>(c->kz[1]);
@@ -850,8 +854,8 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   auto project_norm = [&]() -> gmg_status {
     if (mixed) {
       HIPCHK(c, launch_sum(false, n, r, c->part, c->scal + S_SUM, s));
-      HIPCHK(c, launch_shift_cast_sq(n, c->scal, S_SUM, inv_n, static_cast<double*>(r), r32, c->part,
-                                     c->scal + S_RR, s));
+      HIPCHK(c, launch_shift_cast_sq(n, c->scal, S_SUM, inv_n, static_cast<double*>(r), r32, c->part, S_RR, S_RS,
+                                     s));
       return GMG_OK;
     }
     STCHK(project(c, pi, n, r));
@@ -911,17 +915,25 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       have_dir = true;
     }
     STCHK(apply_op(c, l, pi, Epi::Apply, p, w, nullptr, nullptr, 0, 0));
-    if (flexible) HIPCHK(c, launch_dot2(f32, n, p, w, r, c->part, c->scal, S_PW, S_PR, s));
-    else HIPCHK(c, launch_dot(f32, n, p, w, c->part, c->scal + S_PW, s));
     // u += alpha p, r -= alpha w, with sum(r) and r.r of the new r in the same pass;
-    // the projection r <- r - mean(r) follows, and ||r - mean||^2 = r.r - (sum r)^2 / n
-    HIPCHK(c, launch_axpy2_sums(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, c->part, S_SUM, S_RR, s));
-    if (mixed)
-      HIPCHK(c, launch_shift_cast(n, c->scal, S_SUM, 1.0 / static_cast<double>(n), static_cast<double*>(r), r32, s));
-    else
-      HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, 1.0 / static_cast<double>(n), r, s));
+    // the projection r <- r - mean(r) follows (mixed: is folded in), and
+    // ||r - mean||^2 = r.r - (sum r)^2 / n
+    int sum_slot = S_SUM;
+    if (mixed) {
+      HIPCHK(c, launch_dot2_sumy(n, static_cast<const double*>(p), static_cast<const double*>(w),
+                                 static_cast<const double*>(r), c->part, c->scal, S_PW, S_PR, S_WS, s));
+      HIPCHK(c, launch_axpy2_cast(n, c->scal, S_PR, S_PW, S_RS, S_WS, inv_n, static_cast<double*>(u),
+                                  static_cast<const double*>(p), static_cast<double*>(r),
+                                  static_cast<const double*>(w), r32, c->part, S_RR, s));
+      sum_slot = S_RS;
+    } else {
+      if (flexible) HIPCHK(c, launch_dot2(f32, n, p, w, r, c->part, c->scal, S_PW, S_PR, s));
+      else HIPCHK(c, launch_dot(f32, n, p, w, c->part, c->scal + S_PW, s));
+      HIPCHK(c, launch_axpy2_sums(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, c->part, S_SUM, S_RR, s));
+      HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, inv_n, r, s));
+    }
     STCHK(read_scalars(c, hs, kNumScal));
-    rr = std::max(0.0, hs[S_RR] - hs[S_SUM] * hs[S_SUM] / static_cast<double>(n));
+    rr = std::max(0.0, hs[S_RR] - hs[sum_slot] * hs[sum_slot] / static_cast<double>(n));
     if (!std::isfinite(hs[S_RR])) rr = hs[S_RR];
     c->hist_res.push_back(std::sqrt(rr));
     ++it;

@@ -171,17 +171,24 @@ hipError_t launch_axpy2(bool fp32, int64_t n, const double* sc, int i_num, int i
 hipError_t launch_xpby(bool fp32, int64_t n, const double* sc, int i_num, int i_den, double sgn, const void* z,
                        void* p, hipStream_t s);
 hipError_t launch_shift(bool fp32, int64_t n, const double* sc, int i, double scale, void* v, hipStream_t s);
-// FP64 Krylov vectors around FP32 cycles: r -= sc[i] scale and r32 = float(r) in one pass;
-// the (sum z, z.y, sum y) reductions and the p = (z - mean) + beta p update reading the
-// FP32 cycle output z directly
-hipError_t launch_shift_cast(int64_t n, const double* sc, int i, double scale, double* r, float* r32, hipStream_t s);
+// FP64 Krylov vectors around FP32 cycles: the (sum z, z.y, sum y) reductions and the
+// p = (z - mean) + beta p update reading the FP32 cycle output z directly
 hipError_t launch_sums3_mixed(int64_t n, const float* z, const double* y, double* part, double* sc, int dz, int dzy,
                               int dy, hipStream_t s);
 hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
                                    double scale, const float* z, double* p, hipStream_t s);
-// the same shift and cast with *dst = ||r - mean||^2 (bits of a dot(r, r) after the shift)
-hipError_t launch_shift_cast_sq(int64_t n, const double* sc, int i, double scale, double* r, float* r32,
-                                double* part, double* dst, hipStream_t s);
+// r -= sc[i] scale and r32 = float(r) in one pass, with sc[dsq] = ||r - mean||^2 (bits of a
+// dot(r, r) after the shift) and sc[dsum] = sum of the shifted r
+hipError_t launch_shift_cast_sq(int64_t n, double* sc, int i, double scale, double* r, float* r32, double* part,
+                                int dsq, int dsum, hipStream_t s);
+// (x.y, x.z, sum y) -> sc[dxy], sc[dxz], sc[dy]
+hipError_t launch_dot2_sumy(int64_t n, const double* x, const double* y, const double* z, double* part, double* sc,
+                            int dxy, int dxz, int dy, hipStream_t s);
+// alpha = sc[inum] / sc[iden]; u += alpha p; r <- r - alpha w - m with the predicted mean
+// m = (sc[irs] - alpha sc[iws]) scale; r32 = float(r); then sc[irs] = sum r, sc[dsq] = r.r
+hipError_t launch_axpy2_cast(int64_t n, double* sc, int inum, int iden, int irs, int iws, double scale, double* u,
+                             const double* p, double* r, const double* w, float* r32, double* part, int dsq,
+                             hipStream_t s);
 // p = double(z) - sc[i] scale (first direction from an FP32 cycle output)
 hipError_t launch_shift_f2d(int64_t n, const double* sc, int i, double scale, const float* z, double* p,
                             hipStream_t s);

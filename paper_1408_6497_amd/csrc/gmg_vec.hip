@@ -144,6 +144,58 @@ __global__ void __launch_bounds__(kBlock) k_dot2(const int64_t n, const T* __res
   }
 }
 
+// (x.y, x.z, sum y): the FCG step's two products and the sum of w = A p, whose
+// mean predicts the mean of the updated residual
+__global__ void __launch_bounds__(kBlock) k_dot2_sumy(const int64_t n, const double* __restrict__ x,
+                                                      const double* __restrict__ y, const double* __restrict__ z,
+                                                      double* part) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double xv = x[i];
+    const double yv = y[i];
+    a = fma(xv, yv, a);
+    b = fma(xv, z[i], b);
+    c += yv;
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+    part[2 * gridDim.x + blockIdx.x] = c;
+  }
+}
+
+// FCG update with the projection and the cast to the cycle's precision in the same
+// pass: alpha = sc[inum] / sc[iden], u += alpha p, r <- r - alpha w - m, r32 = float(r),
+// partial sum(r) and r.r of the stored r.  m = (sc[irs] - alpha sc[iws]) scale is the
+// mean of r - alpha w predicted from sum(r) (sc[irs]) and sum(w) (sc[iws]), so the
+// stored residual stays mean-free to rounding without a pass of its own; its exact
+// sum goes back to sc[irs] for the norm and the next prediction.
+__global__ void __launch_bounds__(kBlock) k_axpy2_cast(const int64_t n, const double* sc, const int inum,
+                                                       const int iden, const int irs, const int iws,
+                                                       const double scale, double* u, const double* __restrict__ p,
+                                                       double* r, const double* __restrict__ w,
+                                                       float* __restrict__ r32, double* part) {
+  const double al = sc[inum] / sc[iden];
+  const double m = (sc[irs] - al * sc[iws]) * scale;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    u[i] = fma(al, p[i], u[i]);
+    const double v = fma(-al, w[i], r[i]) - m;
+    r[i] = v;
+    r32[i] = static_cast<float>(v);
+    a += v;
+    b = fma(v, v, b);
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+  }
+}
+
 // u += alpha p, r -= alpha w (alpha = sc[inum] / sc[iden]); partial sum(r) and r.r of the new r
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_axpy2_sums(const int64_t n, const double* sc, const int inum,
@@ -248,35 +300,27 @@ __global__ void __launch_bounds__(kBlock) k_xpby_shift_mixed(const int64_t n, co
     p[i] = fma(be, p[i], static_cast<double>(z[i]) - m);
 }
 
-// r -= sc[i0] scale in place (FP64) and r32 = float(r): the projection of the
-// Krylov residual fused with its cast to the precision of the cycle
-__global__ void __launch_bounds__(kBlock) k_shift_cast(const int64_t n, const double* sc, const int i0,
-                                                       const double scale, double* r, float* __restrict__ r32) {
-  const double m = sc[i0] * scale;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double v = r[i] - m;
-    r[i] = v;
-    r32[i] = static_cast<float>(v);
-  }
-}
-
-// r -= sc[i0] scale, r32 = float(r), and the partial sums of squares of the new r
-// (the same values, grid and order as a separate dot(r, r) after the shift)
+// r -= sc[i0] scale, r32 = float(r), and the partial sums of squares and of the
+// values of the new r (the squares in the same grid and order as a separate
+// dot(r, r) after the shift)
 __global__ void __launch_bounds__(kBlock) k_shift_cast_sq(const int64_t n, const double* sc, const int i0,
                                                           const double scale, double* r, float* __restrict__ r32,
                                                           double* part) {
   const double m = sc[i0] * scale;
-  double s = 0.0;
+  double s = 0.0, t = 0.0, u = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const double v = r[i] - m;
     r[i] = v;
     r32[i] = static_cast<float>(v);
     s = fma(v, v, s);
+    t += v;
   }
-  s = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  block_sum3(s, t, u);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    part[gridDim.x + blockIdx.x] = t;
+  }
 }
 
 // p = double(z) - sc[i0] scale: the first direction from an FP32 cycle output
@@ -516,16 +560,29 @@ hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int id
   return hipGetLastError();
 }
 
-hipError_t launch_shift_cast(int64_t n, const double* sc, int i, double scale, double* r, float* r32, hipStream_t s) {
-  hipLaunchKernelGGL(k_shift_cast, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, i, scale, r, r32);
+hipError_t launch_shift_cast_sq(int64_t n, double* sc, int i, double scale, double* r, float* r32, double* part,
+                                int dsq, int dsum, hipStream_t s) {
+  const int g = red_grid(n);
+  hipLaunchKernelGGL(k_shift_cast_sq, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, r, r32, part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, dsq, dsum, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_shift_cast_sq(int64_t n, const double* sc, int i, double scale, double* r, float* r32,
-                                double* part, double* dst, hipStream_t s) {
+hipError_t launch_dot2_sumy(int64_t n, const double* x, const double* y, const double* z, double* part, double* sc,
+                            int dxy, int dxz, int dy, hipStream_t s) {
   const int g = red_grid(n);
-  hipLaunchKernelGGL(k_shift_cast_sq, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, r, r32, part);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
+  hipLaunchKernelGGL(k_dot2_sumy, dim3(g), dim3(kBlock), 0, s, n, x, y, z, part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(3), dim3(kBlock), 0, s, part, g, sc, dxy, dxz, dy);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy2_cast(int64_t n, double* sc, int inum, int iden, int irs, int iws, double scale, double* u,
+                             const double* p, double* r, const double* w, float* r32, double* part, int dsq,
+                             hipStream_t s) {
+  const int g = red_grid(n);
+  hipLaunchKernelGGL(k_axpy2_cast, dim3(g), dim3(kBlock), 0, s, n, sc, inum, iden, irs, iws, scale, u, p, r, w, r32,
+                     part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, irs, dsq, 0);
   return hipGetLastError();
 }
 
