@@ -50,6 +50,7 @@ enum : int {
   S_SSUM = 16,  // + level: sum of (D^-1 r)^2 of the learned correction on that level
   S_RS = 48,    // sum of the stored Krylov residual (FCG around FP32 cycles)
   S_WS = 49,    // sum of w = A p                      (the same)
+  S_ZR = 50,    // z . r                                (the same)
 };
 // a hierarchy has at most 11 levels (n <= 512 uniform, leaf level <= 10 octree)
 static_assert(S_SSUM + 32 <= S_RS && S_WS < kNumScal, "scalar slots overlap");
@@ -297,7 +298,8 @@ void phase_totals(const gmg_ctx* c, double out[4]) {
 }
 
 gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out, const void* b, const void* xp,
-                    double c1, double c2, bool mass = false, void* x1 = nullptr, double s0 = 0.0) {
+                    double c1, double c2, bool mass = false, void* x1 = nullptr, double s0 = 0.0, int d0 = -1,
+                    int d1 = -1) {
   const Level& L = c->lv[l];
   // the uniform kernel moves q consecutive values per vector access
   const uintptr_t al = static_cast<uintptr_t>(L.oct ? 1 : c->q) * esize(pi);
@@ -317,6 +319,14 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.epi = epi;
   a.x1 = x1;
   a.s0 = s0;
+  if (epi == Epi::ApplyDot) {
+    if (L.oct || pi != 0 || mass || d0 < 0 || d1 < 0) return fail(c, GMG_E_ARG, "fused apply and dot unsupported here");
+    a.part = c->part;
+    a.part_cap = c->part_cap;
+    a.sc = c->scal;
+    a.d0 = d0;
+    a.d1 = d1;
+  }
   hipEvent_t ea = nullptr, eb = nullptr;
   // Inside a smoothing phase, consecutive plain smoother steps on one level are
   // timed as one run (one event pair around all of them), so that the events'
@@ -846,6 +856,10 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   // exact sum keeps the norm and the next prediction exact), and the direction
   // updates read the cycle's FP32 output directly (no FP64 copy of z)
   const bool mixed = pi == 0 && vpi == 1 && flexible && r == c->kr[0] && !learned_precond(c, vpi);
+  // on levels the column kernel runs, p.w and sum(w) come out of the apply itself, and
+  // p.r is taken as (z - mean z).r: p_old.r = 0 by the choice of alpha, so the two agree
+  // in exact arithmetic, and z.r joins the direction update's reduction
+  const bool fused_pw = mixed && !c->lv[l].oct && c->lv[l].N > 32;
   float* r32 = static_cast<float*>(c->kr[1]);
   const float* z32 = static_cast<const float*>(c->kz[1]);
   *iters = 0;
@@ -866,7 +880,12 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   auto restart = [&]() -> gmg_status {
     if (mixed) {
       STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
-      HIPCHK(c, launch_sum(true, n, z32, c->part, c->scal + S_ZS, s));
+      if (fused_pw) {
+        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(r), c->part, c->scal, S_ZS, S_ZR, S_TMP, s));
+        HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
+      } else {
+        HIPCHK(c, launch_sum(true, n, z32, c->part, c->scal + S_ZS, s));
+      }
       HIPCHK(c, launch_shift_f2d(n, c->scal, S_ZS, inv_n, z32, static_cast<double*>(p), s));
       return GMG_OK;
     }
@@ -914,14 +933,16 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       STCHK(restart());
       have_dir = true;
     }
-    STCHK(apply_op(c, l, pi, Epi::Apply, p, w, nullptr, nullptr, 0, 0));
+    if (fused_pw) STCHK(apply_op(c, l, pi, Epi::ApplyDot, p, w, nullptr, nullptr, 0, 0, false, nullptr, 0.0, S_PW, S_WS));
+    else STCHK(apply_op(c, l, pi, Epi::Apply, p, w, nullptr, nullptr, 0, 0));
     // u += alpha p, r -= alpha w, with sum(r) and r.r of the new r in the same pass;
     // the projection r <- r - mean(r) follows (mixed: is folded in), and
     // ||r - mean||^2 = r.r - (sum r)^2 / n
     int sum_slot = S_SUM;
     if (mixed) {
-      HIPCHK(c, launch_dot2_sumy(n, static_cast<const double*>(p), static_cast<const double*>(w),
-                                 static_cast<const double*>(r), c->part, c->scal, S_PW, S_PR, S_WS, s));
+      if (!fused_pw)
+        HIPCHK(c, launch_dot2_sumy(n, static_cast<const double*>(p), static_cast<const double*>(w),
+                                   static_cast<const double*>(r), c->part, c->scal, S_PW, S_PR, S_WS, s));
       HIPCHK(c, launch_axpy2_cast(n, c->scal, S_PR, S_PW, S_RS, S_WS, inv_n, static_cast<double*>(u),
                                   static_cast<const double*>(p), static_cast<double*>(r),
                                   static_cast<const double*>(w), r32, c->part, S_RR, s));
@@ -947,7 +968,13 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
     if (mixed) {
       STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
-      HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
+      if (fused_pw) {
+        HIPCHK(c, launch_sums4_mixed(n, z32, static_cast<const double*>(w), static_cast<const double*>(r), c->part,
+                                     c->scal, S_ZS, S_ZW, S_YS, S_ZR, s));
+        HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
+      } else {
+        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
+      }
       HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
       HIPCHK(c, launch_xpby_shift_mixed(n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z32, static_cast<double*>(p), s));
       continue;

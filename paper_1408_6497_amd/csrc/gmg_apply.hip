@@ -69,6 +69,7 @@ struct KTab {
 };
 
 constexpr int kEpiZero = static_cast<int>(Epi::ChebZero);
+constexpr int kEpiDot = static_cast<int>(Epi::ApplyDot);
 
 // x_1 = s0 D^-1 b at one node of class cls
 template <typename T, int Q>
@@ -103,10 +104,24 @@ __device__ __forceinline__ void store_nt(T* p, const VecQ<T, Q>& v) {
 template <typename T, int Q, int EPI>
 __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, const int cy, const int cz,
                                      const T (&ax)[Q], const T* __restrict__ x, T* out, const T* bvec,
-                                     const T* xp, const T c1, const T c2, T* x1o) {
+                                     const T* xp, const T c1, const T c2, T* x1o, double (&dacc)[2]) {
   using V = VecQ<T, Q>;
   V res;
-  if constexpr (EPI == kEpiZero) {
+  if constexpr (EPI == kEpiDot) {
+    // x . A x and sum(A x) of this thread's outputs; x was loaded a few planes ago
+    // and is read again from the cache
+    const V xv = *reinterpret_cast<const V*>(x + idx);
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      res.v[c] = ax[c];
+      dacc[0] = fma(static_cast<double>(xv.v[c]), static_cast<double>(ax[c]), dacc[0]);
+      dacc[1] += static_cast<double>(ax[c]);
+    }
+    if constexpr (Q < 4 || sizeof(T) == 4) {
+      store_nt<T, Q>(out + idx, res);
+      return;
+    }
+  } else if constexpr (EPI == kEpiZero) {
     const V bv = *reinterpret_cast<const V*>(bvec + idx);
     V x1;
 #pragma unroll
@@ -174,7 +189,7 @@ constexpr int col_rows() {
 template <typename T, int Q, int G, int EPI, int RY, int CY0>
 __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, Q>& tb, const int N, const int TZ,
                                          const int Y0, const int E0, T* out, const T* bvec, const T* xp,
-                                         const T c1, const T c2, T* x1o) {
+                                         const T c1, const T c2, T* x1o, double (&dacc)[2]) {
   constexpr int TY = G * RY;
   constexpr int NR = RY + 2 * Q;
   constexpr bool kLatePrefetch = Q == 4;
@@ -335,7 +350,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
 #pragma unroll
           for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
           const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
-          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o);
+          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc);
         }
       }
     }
@@ -356,7 +371,7 @@ template <typename T, int Q, int G, int EPI>
 __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
                                                               const int N, const int TZ, const int ntiles_y,
                                                               T* out, const T* bvec, const T* xp, const T c1,
-                                                              const T c2, T* x1o) {
+                                                              const T c2, T* x1o, double* part) {
   constexpr int RY = col_rows<T, Q, EPI>();
   constexpr int SPLIT = 4 / RY;  // workgroups per tile
   const int nblocks = gridDim.x;
@@ -365,11 +380,35 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
   const int tile = b / SPLIT;
   const int Y0 = (tile % ntiles_y) * 4 * G;
   const int E0 = (tile / ntiles_y) * TZ;
+  double dacc[2] = {0.0, 0.0};
   if constexpr (SPLIT == 1) {
-    col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o);
+    col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
   } else {
-    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o);
-    else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o);
+    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+  }
+  if constexpr (EPI == kEpiDot) {
+    // block partials in a fixed order: wavefront shuffles, then the wavefronts in turn
+    __shared__ double red[2][col_bound<Q>() / 64];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      for (int off = 32; off > 0; off >>= 1) dacc[k] += __shfl_down(dacc[k], off, 64);
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nw = (blockDim.x * blockDim.y) >> 6;
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = dacc[0];
+      red[1][tid >> 6] = dacc[1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int w = 0; w < nw; ++w) {
+        s0 += red[0][w];
+        s1 += red[1][w];
+      }
+      part[blockIdx.x] = s0;
+      part[nblocks + blockIdx.x] = s1;
+    }
   }
 }
 
@@ -461,7 +500,8 @@ __global__ void __launch_bounds__(pt_threads<KZ>()) k_apply_pt(const T* __restri
     }
   }
   const size_t idx = (static_cast<size_t>(zz) * N + yy) * N + Q * tx;
-  emit<T, Q, EPI>(tb, idx, cy, cz, ax, x, out, bvec, xp, c1, c2, x1o);
+  double dacc[2] = {0.0, 0.0};
+  emit<T, Q, EPI>(tb, idx, cy, cz, ax, x, out, bvec, xp, c1, c2, x1o, dacc);
 }
 
 template <typename T, int Q>
@@ -554,6 +594,10 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
   const int64_t tiles = static_cast<int64_t>(sh.ntiles_y) * sh.split;
   sh.TZ = pick_tz(a.n, tiles, resident_blocks<T, Q, G, EPI>(threads, sh.lds));
   sh.nblocks = static_cast<int>(tiles * (a.n / sh.TZ));
+  if constexpr (EPI == kEpiDot) {
+    if (a.part == nullptr || a.sc == nullptr || 2 * static_cast<int64_t>(sh.nblocks) > a.part_cap)
+      return hipErrorInvalidValue;
+  }
   if (sh.lds > 65536) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
@@ -562,14 +606,25 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
   hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
                      static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
                      static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
-                     static_cast<T>(a.c2), static_cast<T*>(a.x1));
+                     static_cast<T>(a.c2), static_cast<T*>(a.x1), a.part);
+  if constexpr (EPI == kEpiDot) {
+    // the second run first: folding the first run writes into the second's place
+    const int64_t nb = sh.nblocks;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_sum_partials(a.part + nb, nb, a.part_cap - nb, a.sc + a.d1, s);
+    if (e != hipSuccess) return e;
+    return launch_sum_partials(a.part, nb, a.part_cap, a.sc + a.d0, s);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int Q, int EPI>
 hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
   const KTab<T, Q> kt = make_ktab<T, Q>(tab, a.s0);
-  if (a.N <= 32) {
+  if constexpr (EPI == kEpiDot) {
+    if (a.N <= 32) return hipErrorInvalidValue;  // column kernel only
+  } else if (a.N <= 32) {
     constexpr int KZ = Q == 4 ? 2 * Q + 1 : 1;
     constexpr int cols = KZ == 1 ? 128 : 64;
     const int64_t total = static_cast<int64_t>(a.N / Q) * a.N * a.N;
@@ -607,6 +662,7 @@ void prime_tq(int N) {
   prime_te<T, Q, 1>(N);
   prime_te<T, Q, 2>(N);
   prime_te<T, Q, kEpiZero>(N);
+  if constexpr (sizeof(T) == 8) prime_te<T, Q, kEpiDot>(N);
 }
 
 template <typename T, int Q>
@@ -618,6 +674,9 @@ hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
     case Epi::ChebZero:
       if (a.x1 == nullptr || a.x != a.b) return hipErrorInvalidValue;
       return launch_te<T, Q, kEpiZero>(tab, a, s);
+    case Epi::ApplyDot:
+      if constexpr (sizeof(T) == 8) return launch_te<T, Q, kEpiDot>(tab, a, s);
+      return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }

@@ -44,9 +44,12 @@ struct TransferTab {
   double r[kMaxQ][4 * kMaxQ + 1];
 };
 
-enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3 };
+enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3, ApplyDot = 4 };
 
 // out = A x                          (Epi::Apply)
+// out = A x, sc[d0] = x . A x and sc[d1] = sum(A x)   (Epi::ApplyDot: FP64, uniform levels
+//                                      of N >= 64 nodes; per-block partials go to part, which
+//                                      must hold twice the block count and their folding)
 // out = b - A x                      (Epi::Residual)
 // out = x + c1 (x - xp) + c2 D^-1 (b - A x)   (Epi::Cheb; xp unused when c1 == 0,
 //                                      read as zero when null; out may alias xp, never x)
@@ -64,6 +67,11 @@ struct ApplyArgs {
   Epi epi;
   void* x1;   // Epi::ChebZero: where x_1 goes
   double s0;  // Epi::ChebZero: x_1 = s0 D^-1 b
+  // Epi::ApplyDot: partials buffer (part_cap doubles) and the destination scalar slots
+  double* part;
+  int64_t part_cap;
+  double* sc;
+  int d0, d1;
 };
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
@@ -175,6 +183,9 @@ hipError_t launch_shift(bool fp32, int64_t n, const double* sc, int i, double sc
 // p = (z - mean) + beta p update reading the FP32 cycle output z directly
 hipError_t launch_sums3_mixed(int64_t n, const float* z, const double* y, double* part, double* sc, int dz, int dzy,
                               int dy, hipStream_t s);
+// (sum z, z.w, sum w, z.r) -> sc[dz], sc[dzw], sc[dw], sc[dzr]
+hipError_t launch_sums4_mixed(int64_t n, const float* z, const double* w, const double* r, double* part, double* sc,
+                              int dz, int dzw, int dw, int dzr, hipStream_t s);
 hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
                                    double scale, const float* z, double* p, hipStream_t s);
 // r -= sc[i] scale and r32 = float(r) in one pass, with sc[dsq] = ||r - mean||^2 (bits of a

@@ -260,15 +260,41 @@ __global__ void __launch_bounds__(kBlock) k_sums3_mixed(const int64_t n, const f
   }
 }
 
-// dst[k] = sum of the k-th run of nparts partials, k < count (one block per k)
+// (sum z, z.w, sum w, z.r) with z the FP32 output of a cycle, w and r FP64 Krylov vectors
+__global__ void __launch_bounds__(kBlock) k_sums4_mixed(const int64_t n, const float* __restrict__ z,
+                                                        const double* __restrict__ w, const double* __restrict__ r,
+                                                        double* part) {
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double zv = static_cast<double>(z[i]);
+    const double wv = w[i];
+    a += zv;
+    b = fma(zv, wv, b);
+    c += wv;
+    d = fma(zv, r[i], d);
+  }
+  double e = 0.0, f = 0.0;
+  block_sum3(a, b, c);
+  __syncthreads();  // block_sum3's LDS is reused below
+  block_sum3(d, e, f);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+    part[2 * gridDim.x + blockIdx.x] = c;
+    part[3 * gridDim.x + blockIdx.x] = d;
+  }
+}
+
+// sc[d_k] = sum of the k-th run of nparts partials (one block per k, k < 4)
 __global__ void __launch_bounds__(kBlock) k_finish_multi(const double* part, const int nparts, double* sc,
-                                                         const int d0, const int d1, const int d2) {
+                                                         const int d0, const int d1, const int d2, const int d3 = 0) {
   const int k = blockIdx.x;
   double s = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[static_cast<size_t>(k) * nparts + i];
   double u = 0.0, v = 0.0;
   block_sum3(s, u, v);
-  if (threadIdx.x == 0) sc[k == 0 ? d0 : (k == 1 ? d1 : d2)] = s;
+  if (threadIdx.x == 0) sc[k == 0 ? d0 : (k == 1 ? d1 : (k == 2 ? d2 : d3))] = s;
 }
 
 // sc[dst] = sc[a] - sc[b] sc[c] scale   (one thread)
@@ -550,6 +576,14 @@ hipError_t launch_sums3_mixed(int64_t n, const float* z, const double* y, double
   const int g = red_grid(n);
   hipLaunchKernelGGL(k_sums3_mixed, dim3(g), dim3(kBlock), 0, s, n, z, y, part);
   hipLaunchKernelGGL(k_finish_multi, dim3(3), dim3(kBlock), 0, s, part, g, sc, dz, dzy, dy);
+  return hipGetLastError();
+}
+
+hipError_t launch_sums4_mixed(int64_t n, const float* z, const double* w, const double* r, double* part, double* sc,
+                              int dz, int dzw, int dw, int dzr, hipStream_t s) {
+  const int g = red_grid(n);
+  hipLaunchKernelGGL(k_sums4_mixed, dim3(g), dim3(kBlock), 0, s, n, z, w, r, part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(4), dim3(kBlock), 0, s, part, g, sc, dz, dzw, dw, dzr);
   return hipGetLastError();
 }
 
