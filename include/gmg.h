@@ -125,6 +125,10 @@ typedef struct {
                                one-workgroup kernels that keep it in LDS (testing aid)  */
   int32_t learned_min_depth; /* > 0: depths below this keep the Chebyshev smoother (the
                                finest levels, where a net application costs the most)   */
+  int32_t no_speculation;   /* != 0: FP64 flexible CG around FP32 V-cycles waits for each
+                               residual norm before it enqueues the next V-cycle, instead
+                               of enqueueing it while the norm is read back whenever the
+                               last norm was far above the tolerance (testing aid)      */
 } gmg_options;
 
 typedef struct {

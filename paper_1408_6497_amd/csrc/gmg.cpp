@@ -98,6 +98,7 @@ struct gmg_ctx {
   int n0 = 0;
   double* scal = nullptr;
   double* scal_host = nullptr;  // pinned host copy of scal (read back at each convergence test)
+  hipEvent_t ev_copy = nullptr;  // marks the end of a read-back that later work overlaps
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // bracket each solve (gmg_info.t_solve)
   double* part = nullptr;
   int64_t part_cap = 0;
@@ -374,6 +375,23 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
 gmg_status read_scalars(gmg_ctx* c, double* host, int count) {
   HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(host, c->scal_host, sizeof(double) * count);
+  return GMG_OK;
+}
+
+// The same read-back in two halves: scalars_async enqueues the copy of the scalars
+// as they stand at this point of the work stream and an event after it, so that
+// work enqueued next follows the copy at once while the host waits in
+// scalars_wait (one stream: no cross-queue synchronisation, and the work after the
+// copy may overwrite the slots it copied).
+gmg_status scalars_async(gmg_ctx* c, int count) {
+  HIPCHK(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_copy, c->stream));
+  return GMG_OK;
+}
+
+gmg_status scalars_wait(gmg_ctx* c, double* host, int count) {
+  HIPCHK(c, hipEventSynchronize(c->ev_copy));
   std::memcpy(host, c->scal_host, sizeof(double) * count);
   return GMG_OK;
 }
@@ -881,7 +899,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     if (mixed) {
       STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
       if (fused_pw) {
-        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(r), c->part, c->scal, S_ZS, S_ZR, S_TMP, s));
+        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(r), c->part, c->scal, S_ZS, S_ZR, S_YS, s));
         HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
       } else {
         HIPCHK(c, launch_sum(true, n, z32, c->part, c->scal + S_ZS, s));
@@ -895,9 +913,39 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     HIPCHK(c, launch_copy(f32, n, z, p, s));
     return GMG_OK;
   };
+  // the mixed solve's next cycle and direction update (z = V r, p = (z - mean z) + beta p)
+  auto mixed_direction = [&]() -> gmg_status {
+    STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+    if (fused_pw) {
+      HIPCHK(c, launch_sums4_mixed(n, z32, static_cast<const double*>(w), static_cast<const double*>(r), c->part,
+                                   c->scal, S_ZS, S_ZW, S_YS, S_ZR, s));
+      HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
+    } else {
+      HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
+    }
+    HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
+    HIPCHK(c, launch_xpby_shift_mixed(n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z32, static_cast<double*>(p), s));
+    return GMG_OK;
+  };
+  // Mixed solves enqueue the cycle that follows a residual update before the host
+  // has read the residual's norm, whenever the last norm was more than kSpecMargin
+  // times the tolerance (no cycle contracts that much): the host's round trip then
+  // overlaps the cycle instead of leaving the device idle.  The speculative work
+  // writes only z, p and direction scalars, so on a converged residual it is
+  // simply dropped.
+  constexpr double kSpecMargin = 1e3;
+  bool have_dir = false;
   HIPCHK(c, launch_fill_zero(f32, n, u, s));
   STCHK(project_norm());
-  STCHK(read_scalars(c, hs, kNumScal));
+  const bool speculate = mixed && !c->opt.no_speculation;
+  if (speculate) {
+    STCHK(scalars_async(c, kNumScal));
+    STCHK(restart());
+    have_dir = true;
+    STCHK(scalars_wait(c, hs, kNumScal));
+  } else {
+    STCHK(read_scalars(c, hs, kNumScal));
+  }
   if (norm_slot >= 0) {
     const double nb = std::sqrt(hs[norm_slot]);
     if (norm) *norm = nb;
@@ -910,7 +958,6 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   }
   double rr = hs[S_RR];
   c->hist_res.push_back(std::sqrt(rr));
-  bool have_dir = false;
   int it = 0;
   while (true) {
     if (!std::isfinite(rr)) {
@@ -953,7 +1000,14 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       HIPCHK(c, launch_axpy2_sums(f32, n, c->scal, flexible ? S_PR : rz, S_PW, u, p, r, w, c->part, S_SUM, S_RR, s));
       HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, inv_n, r, s));
     }
-    STCHK(read_scalars(c, hs, kNumScal));
+    const bool spec = speculate && std::isfinite(rr) && std::sqrt(rr) > kSpecMargin * tol_abs;
+    if (spec) {
+      STCHK(scalars_async(c, kNumScal));
+      STCHK(mixed_direction());
+      STCHK(scalars_wait(c, hs, kNumScal));
+    } else {
+      STCHK(read_scalars(c, hs, kNumScal));
+    }
     rr = std::max(0.0, hs[S_RR] - hs[sum_slot] * hs[sum_slot] / static_cast<double>(n));
     if (!std::isfinite(hs[S_RR])) rr = hs[S_RR];
     c->hist_res.push_back(std::sqrt(rr));
@@ -967,16 +1021,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     // z is projected inside the direction update: p = (z - mean z) + beta p, with
     // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
     if (mixed) {
-      STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
-      if (fused_pw) {
-        HIPCHK(c, launch_sums4_mixed(n, z32, static_cast<const double*>(w), static_cast<const double*>(r), c->part,
-                                     c->scal, S_ZS, S_ZW, S_YS, S_ZR, s));
-        HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
-      } else {
-        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
-      }
-      HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
-      HIPCHK(c, launch_xpby_shift_mixed(n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z32, static_cast<double*>(p), s));
+      if (!spec) STCHK(mixed_direction());
       continue;
     }
     STCHK(precondition(c, pi, vpi, r, z));
@@ -1244,6 +1289,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   }
   if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming) != hipSuccess ||
       hipEventCreate(&c->ev_t0) != hipSuccess || hipEventCreate(&c->ev_t1) != hipSuccess) {
     gmg_destroy(c);
     return GMG_E_HIP;
@@ -1346,6 +1392,7 @@ gmg_status gmg_destroy(gmg_ctx* ctx) {
   if (ctx->ev_t0) (void)hipEventDestroy(ctx->ev_t0);
   if (ctx->ev_t1) (void)hipEventDestroy(ctx->ev_t1);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  if (ctx->ev_copy) (void)hipEventDestroy(ctx->ev_copy);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return GMG_OK;

@@ -344,3 +344,25 @@ def test_phase_timing_fills_info():
     assert c == info.inner_iters + 1 or c >= info.inner_iters
     plain = _ctx(2, 16, 0, seed=1)
     assert plain.solve(f, u, 1e-8).t_smooth == 0.0
+
+
+def test_speculative_cycles_give_the_same_bits():
+    """FP32 cycles in FP64 flexible CG enqueue the next cycle while the residual norm is read
+    back; the kernels and their order on the stream are those of the waiting solve, so the
+    solution and the iteration count are the same bits either way, over repeated solves."""
+    torch = torch_cuda()
+    from workloads import gaussian_params, gaussian_source
+    from paper_1408_6497_amd import GMG_FP32
+    for q, n in ((2, 32), (1, 64)):
+        spec = _ctx(q, n, 0, seed=3, vcycle_prec=GMG_FP32)
+        wait = _ctx(q, n, 0, seed=3, vcycle_prec=GMG_FP32, no_speculation=1)
+        f = gaussian_source(spec.dof_coords_1d(), gaussian_params(4, 32, 0.02, 0.1)).cuda()
+        us, uw = torch.empty_like(f), torch.empty_like(f)
+        for rep in range(2):
+            i_s = spec.solve(f, us, 1e-9)
+            i_w = wait.solve(f, uw, 1e-9)
+            torch.cuda.synchronize()
+            print(f"[spec] q={q} n={n} rep {rep}: iters {i_s.inner_iters} / {i_w.inner_iters} "
+                  f"rel {i_s.rel_residual_f64:.2e}", flush=True)
+            assert i_s.inner_iters == i_w.inner_iters and i_s.rel_residual_f64 == i_w.rel_residual_f64
+            assert torch.equal(us, uw)
