@@ -320,7 +320,7 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.epi = epi;
   a.x1 = x1;
   a.s0 = s0;
-  if (epi == Epi::ApplyDot) {
+  if (epi == Epi::ApplyDot || epi == Epi::ResidualSums) {
     if (L.oct || pi != 0 || mass || d0 < 0 || d1 < 0) return fail(c, GMG_E_ARG, "fused apply and dot unsupported here");
     a.part = c->part;
     a.part_cap = c->part_cap;
@@ -858,7 +858,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // norm_slot >= 0: tol_abs is relative to sqrt(scal[norm_slot]) (a norm the caller
 // enqueued, read back together with the first residual norm), which goes to *norm.
 gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true, void* u, void* r, double tol_abs,
-                  int maxit, int* iters, double* final_rr, int norm_slot = -1, double* norm = nullptr) {
+                  int maxit, int* iters, double* final_rr, int norm_slot = -1, double* norm = nullptr,
+                  bool start_from_b = false) {
   const int l = c->L - 1;
   const int64_t n = c->lv[l].size;
   const bool f32 = pi == 1;
@@ -886,8 +887,8 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   auto project_norm = [&]() -> gmg_status {
     if (mixed) {
       HIPCHK(c, launch_sum(false, n, r, c->part, c->scal + S_SUM, s));
-      HIPCHK(c, launch_shift_cast_sq(n, c->scal, S_SUM, inv_n, static_cast<double*>(r), r32, c->part, S_RR, S_RS,
-                                     s));
+      HIPCHK(c, launch_shift_cast_sq(n, c->scal, S_SUM, inv_n, static_cast<const double*>(r), static_cast<double*>(r),
+                                     r32, c->part, S_RR, S_RS, s));
       return GMG_OK;
     }
     STCHK(project(c, pi, n, r));
@@ -935,8 +936,21 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   // simply dropped.
   constexpr double kSpecMargin = 1e3;
   bool have_dir = false;
-  HIPCHK(c, launch_fill_zero(f32, n, u, s));
-  STCHK(project_norm());
+  if (start_from_b && mixed && norm_slot >= 0) {
+    // u = 0 with sum(b) and b.b (the caller's norm) in one pass; r = b - mean(b),
+    // its FP32 cast and its sums in the next
+    HIPCHK(c, launch_zero_sums(n, static_cast<const double*>(b_true), static_cast<double*>(u), c->part, c->scal,
+                               S_SUM, norm_slot, s));
+    HIPCHK(c, launch_shift_cast_sq(n, c->scal, S_SUM, inv_n, static_cast<const double*>(b_true),
+                                   static_cast<double*>(r), r32, c->part, S_RR, S_RS, s));
+  } else {
+    if (start_from_b) {
+      if (norm_slot >= 0) HIPCHK(c, launch_dot(f32, n, b_true, b_true, c->part, c->scal + norm_slot, s));
+      HIPCHK(c, launch_copy(f32, n, b_true, r, s));
+    }
+    HIPCHK(c, launch_fill_zero(f32, n, u, s));
+    STCHK(project_norm());
+  }
   const bool speculate = mixed && !c->opt.no_speculation;
   if (speculate) {
     STCHK(scalars_async(c, kNumScal));
@@ -967,6 +981,20 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     }
     if (std::sqrt(rr) <= tol_abs) {
       if (!b_true) break;
+      if (fused_pw) {
+        // the true residual with its sums from the apply; the projection and cast
+        // follow only if it is not below the tolerance
+        STCHK(apply_op(c, l, pi, Epi::ResidualSums, u, r, b_true, nullptr, 0, 0, false, nullptr, 0.0, S_RR, S_RS));
+        STCHK(read_scalars(c, hs, kNumScal));
+        rr = std::max(0.0, hs[S_RR] - hs[S_RS] * hs[S_RS] / static_cast<double>(n));
+        if (!std::isfinite(hs[S_RR])) rr = hs[S_RR];
+        if ((std::sqrt(rr) <= tol_abs && std::isfinite(rr)) || it >= maxit) break;
+        STCHK(project_norm());
+        STCHK(read_scalars(c, hs, kNumScal));
+        rr = hs[S_RR];
+        have_dir = false;
+        continue;
+      }
       STCHK(apply_op(c, l, pi, Epi::Residual, u, r, b_true, nullptr, 0, 0));
       STCHK(project_norm());
       STCHK(read_scalars(c, hs, kNumScal));
@@ -1522,9 +1550,11 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
   hipEvent_t e0 = c->ev_t0, e1 = c->ev_t1;
   HIPCHK(c, hipEventRecord(e0, s));
   double hs[kNumScal];
-  HIPCHK(c, launch_dot(false, n, b_dev, b_dev, c->part, c->scal + S_TMP, s));
-  // the Krylov paths read ||b|| back together with their first residual norm
+  // the Krylov paths read ||b|| back together with their first residual norm; the
+  // FP64 flexible CG around FP32 cycles also computes it in its first pass
   const bool krylov_path = c->opt.vcycle_prec != GMG_FP32 || c->opt.ir_mode == 0;
+  const bool mixed_fcg = c->opt.vcycle_prec == GMG_FP32 && c->opt.ir_mode == 0;
+  if (!mixed_fcg) HIPCHK(c, launch_dot(false, n, b_dev, b_dev, c->part, c->scal + S_TMP, s));
   double nb = 1.0;
   if (!krylov_path) {
     STCHK(read_scalars(c, hs, kNumScal));
@@ -1540,10 +1570,9 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
     // and projection stay in FP64 at every iteration (refinement at each step),
     // the V-cycle -- smoother, transfers, level operators -- runs in FP32.
     STCHK(ensure_prec(c, 1));
-    HIPCHK(c, launch_copy(false, n, b_dev, c->kr[0], s));
     int it = 0;
     double rr = 0.0;
-    st = krylov(c, 0, 1, true, b_dev, u_dev, c->kr[0], rtol, c->opt.max_iters, &it, &rr, S_TMP, &nb);
+    st = krylov(c, 0, 1, true, b_dev, u_dev, c->kr[0], rtol, c->opt.max_iters, &it, &rr, S_TMP, &nb, true);
     inf.inner_iters = it;
     inf.outer_iters = it;
     inf.rel_residual_f64 = nb > 0.0 ? std::sqrt(rr) / nb : 0.0;

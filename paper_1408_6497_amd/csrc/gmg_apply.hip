@@ -70,6 +70,9 @@ struct KTab {
 
 constexpr int kEpiZero = static_cast<int>(Epi::ChebZero);
 constexpr int kEpiDot = static_cast<int>(Epi::ApplyDot);
+constexpr int kEpiResSums = static_cast<int>(Epi::ResidualSums);
+// epilogues that reduce two sums per block into a partials buffer
+constexpr bool reduces(int epi) { return epi == kEpiDot || epi == kEpiResSums; }
 
 // x_1 = s0 D^-1 b at one node of class cls
 template <typename T, int Q>
@@ -137,6 +140,14 @@ __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, con
     if constexpr (Q < 4 || sizeof(T) == 4) {
       store_nt<T, Q>(out + idx, res);
       return;
+    }
+  } else if constexpr (EPI == kEpiResSums) {
+    const V bv = *reinterpret_cast<const V*>(bvec + idx);
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      res.v[c] = bv.v[c] - ax[c];
+      dacc[0] = fma(static_cast<double>(res.v[c]), static_cast<double>(res.v[c]), dacc[0]);
+      dacc[1] += static_cast<double>(res.v[c]);
     }
   } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
     const V bv = *reinterpret_cast<const V*>(bvec + idx);
@@ -387,7 +398,7 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
     if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
     else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
   }
-  if constexpr (EPI == kEpiDot) {
+  if constexpr (reduces(EPI)) {
     // block partials in a fixed order: wavefront shuffles, then the wavefronts in turn
     __shared__ double red[2][col_bound<Q>() / 64];
 #pragma unroll
@@ -594,7 +605,7 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
   const int64_t tiles = static_cast<int64_t>(sh.ntiles_y) * sh.split;
   sh.TZ = pick_tz(a.n, tiles, resident_blocks<T, Q, G, EPI>(threads, sh.lds));
   sh.nblocks = static_cast<int>(tiles * (a.n / sh.TZ));
-  if constexpr (EPI == kEpiDot) {
+  if constexpr (reduces(EPI)) {
     if (a.part == nullptr || a.sc == nullptr || 2 * static_cast<int64_t>(sh.nblocks) > a.part_cap)
       return hipErrorInvalidValue;
   }
@@ -607,7 +618,7 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
                      static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
                      static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
                      static_cast<T>(a.c2), static_cast<T*>(a.x1), a.part);
-  if constexpr (EPI == kEpiDot) {
+  if constexpr (reduces(EPI)) {
     // the second run first: folding the first run writes into the second's place
     const int64_t nb = sh.nblocks;
     hipError_t e = hipGetLastError();
@@ -622,7 +633,7 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
 template <typename T, int Q, int EPI>
 hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
   const KTab<T, Q> kt = make_ktab<T, Q>(tab, a.s0);
-  if constexpr (EPI == kEpiDot) {
+  if constexpr (reduces(EPI)) {
     if (a.N <= 32) return hipErrorInvalidValue;  // column kernel only
   } else if (a.N <= 32) {
     constexpr int KZ = Q == 4 ? 2 * Q + 1 : 1;
@@ -662,7 +673,10 @@ void prime_tq(int N) {
   prime_te<T, Q, 1>(N);
   prime_te<T, Q, 2>(N);
   prime_te<T, Q, kEpiZero>(N);
-  if constexpr (sizeof(T) == 8) prime_te<T, Q, kEpiDot>(N);
+  if constexpr (sizeof(T) == 8) {
+    prime_te<T, Q, kEpiDot>(N);
+    prime_te<T, Q, kEpiResSums>(N);
+  }
 }
 
 template <typename T, int Q>
@@ -676,6 +690,9 @@ hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
       return launch_te<T, Q, kEpiZero>(tab, a, s);
     case Epi::ApplyDot:
       if constexpr (sizeof(T) == 8) return launch_te<T, Q, kEpiDot>(tab, a, s);
+      return hipErrorInvalidValue;
+    case Epi::ResidualSums:
+      if constexpr (sizeof(T) == 8) return launch_te<T, Q, kEpiResSums>(tab, a, s);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;

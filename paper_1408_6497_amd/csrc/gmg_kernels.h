@@ -44,12 +44,14 @@ struct TransferTab {
   double r[kMaxQ][4 * kMaxQ + 1];
 };
 
-enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3, ApplyDot = 4 };
+enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3, ApplyDot = 4, ResidualSums = 5 };
 
 // out = A x                          (Epi::Apply)
 // out = A x, sc[d0] = x . A x and sc[d1] = sum(A x)   (Epi::ApplyDot: FP64, uniform levels
 //                                      of N >= 64 nodes; per-block partials go to part, which
 //                                      must hold twice the block count and their folding)
+// out = b - A x, sc[d0] = out . out and sc[d1] = sum(out)   (Epi::ResidualSums: the same
+//                                      conditions as Epi::ApplyDot)
 // out = b - A x                      (Epi::Residual)
 // out = x + c1 (x - xp) + c2 D^-1 (b - A x)   (Epi::Cheb; xp unused when c1 == 0,
 //                                      read as zero when null; out may alias xp, never x)
@@ -188,10 +190,13 @@ hipError_t launch_sums4_mixed(int64_t n, const float* z, const double* w, const 
                               int dz, int dzw, int dw, int dzr, hipStream_t s);
 hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int iden, double sgn, int imean,
                                    double scale, const float* z, double* p, hipStream_t s);
-// r -= sc[i] scale and r32 = float(r) in one pass, with sc[dsq] = ||r - mean||^2 (bits of a
-// dot(r, r) after the shift) and sc[dsum] = sum of the shifted r
-hipError_t launch_shift_cast_sq(int64_t n, double* sc, int i, double scale, double* r, float* r32, double* part,
-                                int dsq, int dsum, hipStream_t s);
+// r = src - sc[i] scale and r32 = float(r) in one pass (src may be r), with sc[dsq] =
+// ||r||^2 (bits of a dot(r, r) after the shift) and sc[dsum] = sum of the shifted r
+hipError_t launch_shift_cast_sq(int64_t n, double* sc, int i, double scale, const double* src, double* r, float* r32,
+                                double* part, int dsq, int dsum, hipStream_t s);
+// u = 0 and, of b, sc[dsum] = sum b and sc[dsq] = b . b in one pass
+hipError_t launch_zero_sums(int64_t n, const double* b, double* u, double* part, double* sc, int dsum, int dsq,
+                            hipStream_t s);
 // (x.y, x.z, sum y) -> sc[dxy], sc[dxz], sc[dy]
 hipError_t launch_dot2_sumy(int64_t n, const double* x, const double* y, const double* z, double* part, double* sc,
                             int dxy, int dxz, int dy, hipStream_t s);

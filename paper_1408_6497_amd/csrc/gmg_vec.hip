@@ -330,13 +330,13 @@ __global__ void __launch_bounds__(kBlock) k_xpby_shift_mixed(const int64_t n, co
 // values of the new r (the squares in the same grid and order as a separate
 // dot(r, r) after the shift)
 __global__ void __launch_bounds__(kBlock) k_shift_cast_sq(const int64_t n, const double* sc, const int i0,
-                                                          const double scale, double* r, float* __restrict__ r32,
-                                                          double* part) {
+                                                          const double scale, const double* src, double* r,
+                                                          float* __restrict__ r32, double* part) {
   const double m = sc[i0] * scale;
   double s = 0.0, t = 0.0, u = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double v = r[i] - m;
+    const double v = src[i] - m;
     r[i] = v;
     r32[i] = static_cast<float>(v);
     s = fma(v, v, s);
@@ -346,6 +346,24 @@ __global__ void __launch_bounds__(kBlock) k_shift_cast_sq(const int64_t n, const
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s;
     part[gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// u = 0 and the partial sums of b and of b^2 (the start of a solve from a zero guess)
+__global__ void __launch_bounds__(kBlock) k_zero_sums(const int64_t n, const double* __restrict__ b,
+                                                      double* __restrict__ u, double* part) {
+  double s = 0.0, q = 0.0, t = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double v = b[i];
+    u[i] = 0.0;
+    s += v;
+    q = fma(v, v, q);
+  }
+  block_sum3(s, q, t);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s;
+    part[gridDim.x + blockIdx.x] = q;
   }
 }
 
@@ -594,11 +612,19 @@ hipError_t launch_xpby_shift_mixed(int64_t n, const double* sc, int inum, int id
   return hipGetLastError();
 }
 
-hipError_t launch_shift_cast_sq(int64_t n, double* sc, int i, double scale, double* r, float* r32, double* part,
-                                int dsq, int dsum, hipStream_t s) {
+hipError_t launch_shift_cast_sq(int64_t n, double* sc, int i, double scale, const double* src, double* r, float* r32,
+                                double* part, int dsq, int dsum, hipStream_t s) {
   const int g = red_grid(n);
-  hipLaunchKernelGGL(k_shift_cast_sq, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, r, r32, part);
+  hipLaunchKernelGGL(k_shift_cast_sq, dim3(g), dim3(kBlock), 0, s, n, sc, i, scale, src, r, r32, part);
   hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, dsq, dsum, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_sums(int64_t n, const double* b, double* u, double* part, double* sc, int dsum, int dsq,
+                            hipStream_t s) {
+  const int g = red_grid(n);
+  hipLaunchKernelGGL(k_zero_sums, dim3(g), dim3(kBlock), 0, s, n, b, u, part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, dsum, dsq, 0);
   return hipGetLastError();
 }
 
