@@ -497,7 +497,8 @@ gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
   const bool f32 = pi == 1;
   return timed(c, l, K_RESTRICT, pi, [&]() -> gmg_status {
     if (c->lv[l].oct) HIPCHK(c, launch_oct_restrict(c->lv[l].od, c->lv[l - 1].size, f32, rf, rc, c->stream));
-    else HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream));
+    else
+      HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream, !c->opt.no_fused_transfer));
     return GMG_OK;
   });
 }
@@ -1353,6 +1354,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
       lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
       lev.tab = make_level_tables(q, lev.n);
       prime_apply_shapes(q, lev.N);
+      if (l + 1 < L) prime_transfer_shapes(q, lev.N);  // restriction onto this level
     }
     make_transfer_table(q, &c->xfer);
   }

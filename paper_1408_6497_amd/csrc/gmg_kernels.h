@@ -140,7 +140,11 @@ hipError_t launch_vec_scale(bool fp32, int64_t n, const double* d, double c, con
 hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
                           hipStream_t s);
 hipError_t launch_restrict(const TransferTab& tab, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
-                           hipStream_t s);
+                           hipStream_t s, bool fused = true);
+// fused: one kernel for the three axes (bit-identical to the axis passes) on coarse
+// levels of 64 <= Nc <= 256 nodes a side; prime_transfer_shapes queries its
+// occupancy once per level size, before any graph capture
+void prime_transfer_shapes(int q, int Nc);
 
 // out = c * tab[class(i)] * in  (class table of length q^3; in may be null -> 1)
 hipError_t launch_class_scale(bool fp32, int q, int N, const double* tab, double c, const void* in, void* out,

@@ -11,6 +11,10 @@
 //     (and, for the vertex, of the element on its left): 4q+1 fine values.
 // The fastest thread index always runs along x, so every access is coalesced
 // whatever the pass axis.  All indices are 32-bit (N <= 2048).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -181,6 +185,167 @@ __global__ void __launch_bounds__(256) k_restrict_axis(const T* __restrict__ in,
     *reinterpret_cast<VecK<T, Q>*>(out + (static_cast<size_t>(k) * oy + j) * ox + Q * E) = cv;
 }
 
+// Restriction in one pass over the fine grid (the three axis passes above, fused):
+// rc = Rz Ry Rx rf with the same arithmetic -- the x and y results rounded to T as
+// the axis passes store them, the z sums taken in FP64 in the same tap order -- so
+// the coarse values are the bits of the three-pass restriction.
+//   * a block takes full coarse x-rows, blockDim.y coarse rows Y0 .. (one per
+//     thread row; a multiple of q) and TZE coarse elements in z; thread (tx, ty)
+//     owns coarse element tx in x (q nodes) of coarse row Y0 + ty;
+//   * it streams the fine planes of its z window in order: per plane, the x pass
+//     of the 2 TY + 2q + 1 fine rows its coarse rows reach goes to LDS, then each
+//     thread's y pass gives its q values of that plane;
+//   * fine plane 2q E + t' (0 <= t' < 2q) feeds coarse element E at tap 2q + t',
+//     the vertex of element E + 1 at tap t', and for t' = 0 element E - 1 at its
+//     last tap 4q, which completes that element: three rolling accumulators;
+//   * blocks are remapped so that each XCD sweeps a contiguous range of tiles
+//     (neighbouring tiles share their halo rows and planes in its L2).
+template <typename T, int Q>
+__global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ rf, T* __restrict__ rc,
+                                                    const TransferTab tab, const int Nc, const int TZE,
+                                                    const int ntiles_y) {
+  using V = VecK<T, Q>;
+  using V2 = VecK<T, 2 * Q>;
+  // fine rows per thread and plane: ceil((2 TY + 2q + 1) / TY) <= 5 for TY >= q
+  constexpr int kMaxR = 5;
+  const int Nf = 2 * Nc;
+  const int nfm = Nf - 1;
+  const int ncm = Nc - 1;
+  const int TY = blockDim.y;
+  const int NFR = 2 * TY + 2 * Q + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* xr = reinterpret_cast<T*>(smem_raw);  // [NFR][Nc]: x-restricted rows of one fine plane
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if ((nb & 7) == 0) b = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int Y0 = (b % ntiles_y) * TY;
+  const int Z0 = (b / ntiles_y) * TZE;
+  const int tx = threadIdx.x;
+  const int ty = threadIdx.y;
+  const int fy0 = 2 * Y0 - 2 * Q;  // fine row of xr row 0 (wrapped when read)
+  const int ay = (Y0 + ty) % Q;    // node class of this thread's coarse row
+  const int ey = ty / Q;           // its element within the tile (Y0 is a multiple of q)
+  // offsets inside a fine plane of this thread's rows: left vector, right vector, far vertex
+  int off_l[kMaxR], off_r[kMaxR], off_f[kMaxR];
+#pragma unroll
+  for (int k = 0; k < kMaxR; ++k) {
+    const int r = ty + k * TY;
+    const size_t row = static_cast<size_t>((fy0 + (r < NFR ? r : 0) + Nf) & nfm) * Nf;
+    off_l[k] = static_cast<int>(row) + ((2 * Q * tx - 2 * Q + Nf) & nfm);
+    off_r[k] = static_cast<int>(row) + 2 * Q * tx;
+    off_f[k] = static_cast<int>(row) + ((2 * Q * tx + 2 * Q) & nfm);
+  }
+  V2 pl[kMaxR], pr[kMaxR];
+  T pf[kMaxR];
+  const int f0 = 2 * Q * (Z0 - 1);      // first fine plane of the window
+  const int total = 2 * Q * (TZE + 1) + 1;
+  auto load_plane = [&](int p) {
+    const T* plane = rf + static_cast<size_t>((f0 + p + Nf) & nfm) * Nf * Nf;
+#pragma unroll
+    for (int k = 0; k < kMaxR; ++k) {
+      if (ty + k * TY < NFR) {
+        pl[k] = *reinterpret_cast<const V2*>(plane + off_l[k]);
+        pr[k] = *reinterpret_cast<const V2*>(plane + off_r[k]);
+        pf[k] = plane[off_f[k]];
+      }
+    }
+  };
+  double P[Q][Q], C[Q][Q], N0[Q];
+#pragma unroll
+  for (int c = 0; c < Q; ++c) {
+    N0[c] = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) P[c][a] = C[c][a] = 0.0;
+  }
+  load_plane(0);
+  for (int p = 0; p < total; ++p) {
+    const int tp = p & (2 * Q - 1);
+    const int Ef = Z0 - 1 + p / (2 * Q);
+    V2 cl[kMaxR], cr[kMaxR];
+    T cf[kMaxR];
+#pragma unroll
+    for (int k = 0; k < kMaxR; ++k) {
+      cl[k] = pl[k];
+      cr[k] = pr[k];
+      cf[k] = pf[k];
+    }
+    if (p + 1 < total) load_plane(p + 1);  // in flight while this plane is reduced
+    // x pass: fine nodes 2qE-2q .. 2qE+2q of coarse element E = tx in each of the rows
+#pragma unroll
+    for (int k = 0; k < kMaxR; ++k) {
+      const int r = ty + k * TY;
+      if (r >= NFR) continue;
+      T f[4 * Q + 1];
+#pragma unroll
+      for (int t = 0; t < 2 * Q; ++t) {
+        f[t] = cl[k].v[t];
+        f[2 * Q + t] = cr[k].v[t];
+      }
+      f[4 * Q] = cf[k];
+      V cv;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        double sx = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 4 * Q; ++t) {
+          if (a > 0 && t < 2 * Q) continue;
+          sx = fma(tab.r[a][t], static_cast<double>(f[t]), sx);
+        }
+        cv.v[a] = static_cast<T>(sx);
+      }
+      *reinterpret_cast<V*>(xr + r * Nc + Q * tx) = cv;
+    }
+    __syncthreads();
+    // y pass of this thread's coarse row, then the z taps of this plane
+    double sy[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) sy[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t <= 4 * Q; ++t) {
+      if (ay > 0 && t < 2 * Q) continue;
+      const V xv = *reinterpret_cast<const V*>(xr + (2 * Q * ey + t) * Nc + Q * tx);
+      const double w = tab.r[ay][t];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) sy[c] = fma(w, static_cast<double>(xv.v[c]), sy[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      const double v = static_cast<double>(static_cast<T>(sy[c]));
+      if (tp == 0) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) P[c][a] = fma(tab.r[a][4 * Q], v, P[c][a]);
+      }
+#pragma unroll
+      for (int a = 0; a < Q; ++a) C[c][a] = fma(tab.r[a][2 * Q + tp], v, C[c][a]);
+      N0[c] = fma(tab.r[0][tp], v, N0[c]);
+    }
+    if (tp == 0 && Ef - 1 >= Z0) {
+      // element Ef - 1 is complete: its q coarse planes
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        V out;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) out.v[c] = static_cast<T>(P[c][a]);
+        const int kz = (Q * (Ef - 1) + a) & ncm;
+        *reinterpret_cast<V*>(rc + (static_cast<size_t>(kz) * Nc + Y0 + ty) * Nc + Q * tx) = out;
+      }
+    }
+    __syncthreads();  // xr is refilled by the next plane
+    if (tp == 2 * Q - 1) {
+      // element Ef becomes the one completed next, element Ef + 1 the one being filled
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) P[c][a] = C[c][a];
+        C[c][0] = N0[c];
+#pragma unroll
+        for (int a = 1; a < Q; ++a) C[c][a] = 0.0;
+        N0[c] = 0.0;
+      }
+    }
+  }
+}
+
 constexpr int kTB = 128;
 
 template <typename T, int Q>
@@ -215,6 +380,82 @@ hipError_t restrict3(const TransferTab& tab, const T* rf, T* t1, T* t2, T* rc, i
   return hipGetLastError();
 }
 
+// Launch shape of the fused restriction onto Nc coarse nodes a side: coarse rows per
+// block (one per thread row, about 256 threads a block), and the z chunk TZE that
+// minimises rounds x fine planes per block, 2q (TZE + 1) + 1, given the blocks the
+// device holds at once (occupancy, cached; primed at setup so that no query runs
+// during graph capture).
+struct R3Shape {
+  int TY, TZE, ntiles_y, nblocks;
+  size_t lds;
+};
+
+template <typename T, int Q>
+R3Shape r3_shape(int Nc) {
+  R3Shape sh{};
+  const int nxc = Nc / Q;
+  int TY = 256 / nxc;
+  if (TY < Q) TY = Q;
+  if (TY > Nc) TY = Nc;
+  sh.TY = TY;
+  sh.ntiles_y = Nc / TY;
+  sh.lds = static_cast<size_t>(2 * TY + 2 * Q + 1) * Nc * sizeof(T);
+  static std::mutex mu;
+  static std::map<std::tuple<int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  int resident = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(dev, Nc);
+    const auto it = cache.find(key);
+    if (it != cache.end()) {
+      resident = it->second;
+    } else {
+      int per_cu = 0, cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_restrict3<T, Q>),
+                                                       nxc * TY, sh.lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+      (void)hipGetLastError();
+      resident = cache[key] = per_cu * cus;
+    }
+  }
+  const int ne = Nc / Q;
+  int best = 1;
+  int64_t best_cost = -1;
+  for (int tz = 1; tz <= ne; tz <<= 1) {
+    const int64_t blocks = static_cast<int64_t>(sh.ntiles_y) * (ne / tz);
+    const int64_t cost = (blocks + resident - 1) / resident * (2 * Q * (tz + 1) + 1);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = tz;
+    }
+  }
+  sh.TZE = best;
+  sh.nblocks = sh.ntiles_y * (ne / best);
+  return sh;
+}
+
+template <typename T, int Q>
+hipError_t restrict3_fused(const TransferTab& tab, const T* rf, T* rc, int Nc, hipStream_t s) {
+  const R3Shape sh = r3_shape<T, Q>(Nc);
+  if (Nc % sh.TY != 0 || sh.TY % Q != 0 || (Nc / Q) * sh.TY > 256) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_restrict3<T, Q>), dim3(sh.nblocks), dim3(Nc / Q, sh.TY), sh.lds, s, rf, rc, tab, Nc, sh.TZE,
+                     sh.ntiles_y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t restrict_fused_q(int q, const TransferTab& tab, const T* rf, T* rc, int Nc, hipStream_t s) {
+  switch (q) {
+    case 1: return restrict3_fused<T, 1>(tab, rf, rc, Nc, s);
+    case 2: return restrict3_fused<T, 2>(tab, rf, rc, Nc, s);
+    case 4: return restrict3_fused<T, 4>(tab, rf, rc, Nc, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t prolong_q(int q, const TransferTab& tab, const T* ec, T* t1, T* t2, T* uf, int Nc, hipStream_t s) {
   switch (q) {
@@ -247,9 +488,29 @@ hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, voi
                            static_cast<double*>(t2), static_cast<double*>(uf), Nc, s);
 }
 
+// One thread per coarse element of a row, q coarse rows at least: 256 threads hold
+// Nc <= 256.  Below 64 coarse nodes a side the chain of 2q (TZE + 1) + 1 fine planes
+// a block streams is longer than the three short axis launches (measured: 14-15 us
+// against 11.5 us onto 16^3 and 32^3 nodes, q = 2), so those keep the axis passes.
+bool restrict_fusable(int q, int Nc) { return Nc >= 64 && Nc >= 2 * q && Nc <= 256; }
+
+void prime_transfer_shapes(int q, int Nc) {
+  if (!restrict_fusable(q, Nc)) return;
+  switch (q) {
+    case 1: r3_shape<float, 1>(Nc); r3_shape<double, 1>(Nc); break;
+    case 2: r3_shape<float, 2>(Nc); r3_shape<double, 2>(Nc); break;
+    case 4: r3_shape<float, 4>(Nc); r3_shape<double, 4>(Nc); break;
+  }
+}
+
 hipError_t launch_restrict(const TransferTab& tab, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
-                           hipStream_t s) {
+                           hipStream_t s, bool fused) {
   if (Nc < tab.q || (Nc & (Nc - 1)) != 0 || Nc > 1024) return hipErrorInvalidValue;
+  if (fused && restrict_fusable(tab.q, Nc)) {
+    if (fp32)
+      return restrict_fused_q<float>(tab.q, tab, static_cast<const float*>(rf), static_cast<float*>(rc), Nc, s);
+    return restrict_fused_q<double>(tab.q, tab, static_cast<const double*>(rf), static_cast<double*>(rc), Nc, s);
+  }
   if (fp32)
     return restrict_q<float>(tab.q, tab, static_cast<const float*>(rf), static_cast<float*>(t1),
                              static_cast<float*>(t2), static_cast<float*>(rc), Nc, s);

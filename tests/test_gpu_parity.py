@@ -98,22 +98,23 @@ def test_smoother_parity(q, n, prec):
     assert err <= (1e-11 if prec == "fp64" else 1e-4)
 
 
-@pytest.mark.parametrize("q,n", [(1, 8), (2, 4), (2, 8), (4, 4)])
+@pytest.mark.parametrize("q,n", [(1, 8), (2, 4), (2, 8), (4, 4), (1, 64), (2, 32), (4, 8), (1, 128)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_transfer_parity(q, n, prec):
     torch = torch_cuda()
     from oracle import transfer
-    ctx = _ctx(q, n, 2)
+    ctx = _ctx(q, n, 2) if q * n // 2 <= 8 else _ctx(q, n, 0)  # the finest transfer of the hierarchy
+    lv = ctx.levels - 1
     P = transfer.prolongation(q, n // 2)
     dt = torch.float64 if prec == "fp64" else torch.float32
     tol = 1e-14 if prec == "fp64" else 1e-6
     rf = to_dev(np.random.default_rng(5).standard_normal(P.shape[0]), dt)
     rc = torch.empty(P.shape[1], dtype=dt, device="cuda")
-    ctx.restrict(1, rf, rc)
+    ctx.restrict(lv, rf, rc)
     ec = to_dev(np.random.default_rng(6).standard_normal(P.shape[1]), dt)
     uf = to_dev(np.random.default_rng(7).standard_normal(P.shape[0]), dt)
     uf0 = to_host(uf)
-    ctx.prolong(1, ec, uf)
+    ctx.prolong(lv, ec, uf)
     torch.cuda.synchronize()
     assert rel_l2(to_host(rc), P.T @ to_host(rf)) <= tol
     assert rel_l2(to_host(uf), uf0 + P @ to_host(ec)) <= tol
@@ -366,3 +367,33 @@ def test_speculative_cycles_give_the_same_bits():
                   f"rel {i_s.rel_residual_f64:.2e}", flush=True)
             assert i_s.inner_iters == i_w.inner_iters and i_s.rel_residual_f64 == i_w.rel_residual_f64
             assert torch.equal(us, uw)
+
+
+@pytest.mark.parametrize("q,n,precs", [(1, 128, ("fp64", "fp32")), (2, 64, ("fp64", "fp32")), (4, 32, ("fp64", "fp32")),
+                                       (2, 128, ("fp64", "fp32")), (4, 64, ("fp32",)), (1, 512, ("fp32",)),
+                                       (2, 256, ("fp32",))])
+def test_fused_restriction_is_the_axis_passes(q, n, precs):
+    """The one-pass restriction gives the bits of the three one-axis passes on every level
+    of the hierarchy (it runs onto coarse grids of 64 to 256 nodes a side: several tiles
+    and z chunks), in both precisions."""
+    torch = torch_cuda()
+    fused = _ctx(q, n, 0)
+    axis = _ctx(q, n, 0, no_fused_transfer=1)
+    for prec in precs:
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        for lv in range(1, fused.levels):
+            size_f = fused.num_dofs(lv)
+            size_c = fused.num_dofs(lv - 1)
+            g = torch.Generator(device="cuda").manual_seed(100 + lv)
+            rf = torch.randn(size_f, dtype=dt, device="cuda", generator=g)
+            rc1 = torch.full((size_c,), float("nan"), dtype=dt, device="cuda")
+            rc2 = torch.full((size_c,), float("nan"), dtype=dt, device="cuda")
+            fused.restrict(lv, rf, rc1)
+            axis.restrict(lv, rf, rc2)
+            torch.cuda.synchronize()
+            print(f"[restrict3] q={q} n={n} {prec} level {lv}: {size_f} -> {size_c}", flush=True)
+            assert torch.equal(rc1, rc2), f"level {lv} differs"
+            del rf, rc1, rc2
+    fused.close()
+    axis.close()
+    torch.cuda.empty_cache()
