@@ -129,8 +129,9 @@ typedef struct {
                                residual norm before it enqueues the next V-cycle, instead
                                of enqueueing it while the norm is read back whenever the
                                last norm was far above the tolerance (testing aid)      */
-  int32_t no_fused_transfer; /* != 0: restrict on uniform levels with three one-axis passes
-                               instead of the one-pass kernel (the same bits; testing aid) */
+  int32_t no_fused_transfer; /* != 0: restrict and prolong on uniform levels with three
+                               one-axis passes instead of the one-pass kernels (the same
+                               bits; testing aid)                                        */
 } gmg_options;
 
 typedef struct {

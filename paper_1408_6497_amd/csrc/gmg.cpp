@@ -509,7 +509,8 @@ gmg_status prolong_level(gmg_ctx* c, int l, int pi, const void* ec, void* uf) {
   const bool f32 = pi == 1;
   return timed(c, l, K_PROLONG, pi, [&]() -> gmg_status {
     if (c->lv[l].oct) HIPCHK(c, launch_oct_prolong(c->lv[l].od, f32, ec, uf, c->stream));
-    else HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream));
+    else
+      HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream, !c->opt.no_fused_transfer));
     return GMG_OK;
   });
 }

@@ -138,12 +138,13 @@ hipError_t launch_vec_scale(bool fp32, int64_t n, const double* d, double c, con
 // uf += P ec (coarse Nc^3 -> fine (2Nc)^3) and rc = P^T rf, as three one-axis
 // passes through the temporaries t1 (>= Nf^3/2 values) and t2 (>= Nf^3/4).
 hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
-                          hipStream_t s);
+                          hipStream_t s, bool fused = true);
 hipError_t launch_restrict(const TransferTab& tab, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
                            hipStream_t s, bool fused = true);
-// fused: one kernel for the three axes (bit-identical to the axis passes) on coarse
-// levels of 64 <= Nc <= 256 nodes a side; prime_transfer_shapes queries its
-// occupancy once per level size, before any graph capture
+// fused: one kernel for the three axes (bit-identical to the axis passes): the
+// prolongation from coarse levels of 2q <= Nc <= 256 nodes a side, the restriction
+// onto those of 64 <= Nc <= 256; prime_transfer_shapes queries their occupancy once
+// per level size, before any graph capture
 void prime_transfer_shapes(int q, int Nc);
 
 // out = c * tab[class(i)] * in  (class table of length q^3; in may be null -> 1)

@@ -346,6 +346,100 @@ __global__ void __launch_bounds__(256) k_restrict3(const T* __restrict__ rf, T* 
   }
 }
 
+// Prolongation in one pass: uf += Pz Py Px ec with the arithmetic of the three axis
+// passes (x and y results rounded to T, the z sum in FP64 added to uf in FP64 and
+// rounded), so uf gets the bits of the three-pass prolongation.
+//   * a block takes full fine x-rows, 2 blockDim.y fine rows (whole coarse elements
+//     in y: blockDim.y is a multiple of q) and TZE coarse elements in z; thread
+//     (tx, ty) owns the 2q fine x nodes of coarse element tx in fine rows 2 ty and
+//     2 ty + 1 of the tile;
+//   * per coarse element E in z: the x pass of its q+1 coarse planes over the
+//     tile's coarse rows goes to LDS; each thread then forms its rows' y values on
+//     those q+1 planes and the 2q fine planes of E from them, added into uf.
+template <typename T, int Q>
+__global__ void __launch_bounds__(256) k_prolong3(const T* __restrict__ ec, T* __restrict__ uf,
+                                                   const TransferTab tab, const int Nc, const int TZE,
+                                                   const int ntiles_y) {
+  using V = VecK<T, Q>;
+  using V2 = VecK<T, 2 * Q>;
+  constexpr int kRows = 2;  // fine rows per thread
+  const int Nf = 2 * Nc;
+  const int ncm = Nc - 1;
+  const int TY = blockDim.y;
+  const int TYF = kRows * TY;        // fine rows of the tile
+  const int NCR = TYF / 2 + 1;       // coarse rows they reach: whole elements plus the closing vertex
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* xp = reinterpret_cast<T*>(smem_raw);  // [q+1 planes][NCR][Nf]: x-prolonged coarse rows
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if ((nb & 7) == 0) b = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+  const int Y0 = (b % ntiles_y) * TYF;  // first fine row (a multiple of 2q)
+  const int Z0 = (b / ntiles_y) * TZE;
+  const int tx = threadIdx.x;
+  const int ty = threadIdx.y;
+  const int cy0 = Y0 / 2;               // first coarse row
+  for (int E = Z0; E < Z0 + TZE; ++E) {
+    // x pass: coarse nodes qE' .. qE'+q of element E' = tx on plane qE + a, coarse row cy0 + r
+    for (int it = ty; it < (Q + 1) * NCR; it += TY) {
+      const int a = it / NCR;
+      const int r = it - a * NCR;
+      const T* row = ec + (static_cast<size_t>((Q * E + a) & ncm) * Nc + ((cy0 + r) & ncm)) * Nc;
+      T c[Q + 1];
+      const V cv = *reinterpret_cast<const V*>(row + Q * tx);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) c[k] = cv.v[k];
+      c[Q] = row[(Q * tx + Q) & ncm];
+      V2 fv;
+#pragma unroll
+      for (int bb = 0; bb < 2 * Q; ++bb) {
+        double sx = 0.0;
+#pragma unroll
+        for (int k = 0; k <= Q; ++k) sx = fma(tab.p[bb][k], static_cast<double>(c[k]), sx);
+        fv.v[bb] = static_cast<T>(sx);
+      }
+      *reinterpret_cast<V2*>(xp + (a * NCR + r) * Nf + 2 * Q * tx) = fv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const int fr = kRows * ty + i;        // fine row within the tile
+      const int ey = fr / (2 * Q);          // its coarse element in y, within the tile
+      const int by = fr - 2 * Q * ey;       // and its child index there
+      // y values of this row on the q+1 coarse planes, rounded as the y pass stores them
+      T xy[Q + 1][2 * Q];
+#pragma unroll
+      for (int a = 0; a <= Q; ++a) {
+        double sy[2 * Q];
+#pragma unroll
+        for (int t = 0; t < 2 * Q; ++t) sy[t] = 0.0;
+#pragma unroll
+        for (int k = 0; k <= Q; ++k) {
+          const V2 v = *reinterpret_cast<const V2*>(xp + (a * NCR + Q * ey + k) * Nf + 2 * Q * tx);
+          const double w = tab.p[by][k];
+#pragma unroll
+          for (int t = 0; t < 2 * Q; ++t) sy[t] = fma(w, static_cast<double>(v.v[t]), sy[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * Q; ++t) xy[a][t] = static_cast<T>(sy[t]);
+      }
+#pragma unroll
+      for (int bz = 0; bz < 2 * Q; ++bz) {
+        T* o = uf + (static_cast<size_t>(2 * Q * E + bz) * Nf + (Y0 + fr)) * Nf + 2 * Q * tx;
+        V2 u = *reinterpret_cast<const V2*>(o);
+#pragma unroll
+        for (int t = 0; t < 2 * Q; ++t) {
+          double sz = 0.0;
+#pragma unroll
+          for (int a = 0; a <= Q; ++a) sz = fma(tab.p[bz][a], static_cast<double>(xy[a][t]), sz);
+          u.v[t] = static_cast<T>(static_cast<double>(u.v[t]) + sz);
+        }
+        *reinterpret_cast<V2*>(o) = u;
+      }
+    }
+    __syncthreads();  // xp is refilled for the next element
+  }
+}
+
 constexpr int kTB = 128;
 
 template <typename T, int Q>
@@ -456,6 +550,83 @@ hipError_t restrict_fused_q(int q, const TransferTab& tab, const T* rf, T* rc, i
   return hipErrorInvalidValue;
 }
 
+// Launch shape of the fused prolongation from Nc coarse nodes a side: about 256
+// threads, 2 fine rows per thread row, and the z chunk that minimises rounds x
+// elements per block (occupancy cached and primed at setup like the restriction's).
+template <typename T, int Q>
+R3Shape p3_shape(int Nc) {
+  R3Shape sh{};
+  const int nxc = Nc / Q;
+  int TY = 256 / nxc;
+  if (TY < Q) TY = Q;
+  if (TY > Nc) TY = Nc;  // 2 TY fine rows <= 2 Nc
+  sh.TY = TY;
+  sh.ntiles_y = (2 * Nc) / (2 * TY);
+  sh.lds = static_cast<size_t>(Q + 1) * (TY + 1) * (2 * Nc) * sizeof(T);
+  static std::mutex mu;
+  static std::map<std::tuple<int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  int resident = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(dev, Nc);
+    const auto it = cache.find(key);
+    if (it != cache.end()) {
+      resident = it->second;
+    } else {
+      int per_cu = 0, cus = 0;
+      const void* fn = reinterpret_cast<const void*>(&k_prolong3<T, Q>);
+      if (sh.lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    static_cast<int>(sh.lds));
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nxc * TY, sh.lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+      (void)hipGetLastError();
+      resident = cache[key] = per_cu * cus;
+    }
+  }
+  const int ne = Nc / Q;
+  int best = 1;
+  int64_t best_cost = -1;
+  for (int tz = 1; tz <= ne; tz <<= 1) {
+    const int64_t blocks = static_cast<int64_t>(sh.ntiles_y) * (ne / tz);
+    const int64_t cost = (blocks + resident - 1) / resident * tz;
+    if (best_cost < 0 || cost <= best_cost) {  // ties: the longer chunk
+      best_cost = cost;
+      best = tz;
+    }
+  }
+  sh.TZE = best;
+  sh.nblocks = sh.ntiles_y * (ne / best);
+  return sh;
+}
+
+template <typename T, int Q>
+hipError_t prolong3_fused(const TransferTab& tab, const T* ec, T* uf, int Nc, hipStream_t s) {
+  const R3Shape sh = p3_shape<T, Q>(Nc);
+  if ((2 * sh.TY) % (2 * Q) != 0 || (2 * Nc) % (2 * sh.TY) != 0 || (Nc / Q) * sh.TY > 256)
+    return hipErrorInvalidConfiguration;
+  if (sh.lds > 65536) {  // q = 4 in FP64: up to 102 KB of the 160 KB a CU has
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_prolong3<T, Q>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_prolong3<T, Q>), dim3(sh.nblocks), dim3(Nc / Q, sh.TY), sh.lds, s, ec, uf, tab, Nc, sh.TZE,
+                     sh.ntiles_y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t prolong_fused_q(int q, const TransferTab& tab, const T* ec, T* uf, int Nc, hipStream_t s) {
+  switch (q) {
+    case 1: return prolong3_fused<T, 1>(tab, ec, uf, Nc, s);
+    case 2: return prolong3_fused<T, 2>(tab, ec, uf, Nc, s);
+    case 4: return prolong3_fused<T, 4>(tab, ec, uf, Nc, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t prolong_q(int q, const TransferTab& tab, const T* ec, T* t1, T* t2, T* uf, int Nc, hipStream_t s) {
   switch (q) {
@@ -478,9 +649,18 @@ hipError_t restrict_q(int q, const TransferTab& tab, const T* rf, T* t1, T* t2, 
 
 }  // namespace
 
+// one thread per coarse element of a row, q coarse rows at least: 256 threads hold Nc <= 256
+bool prolong_fusable(int q, int Nc) { return Nc >= 2 * q && Nc <= 256; }
+
 hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
-                          hipStream_t s) {
+                          hipStream_t s, bool fused) {
   if (Nc < tab.q || (Nc & (Nc - 1)) != 0 || Nc > 1024) return hipErrorInvalidValue;
+  // FP64 q = 4 keeps the axis passes: its fused kernel holds (q+1) 2q FP64 y values
+  // per row and spills
+  if (fused && prolong_fusable(tab.q, Nc) && (fp32 || tab.q < 4)) {
+    if (fp32) return prolong_fused_q<float>(tab.q, tab, static_cast<const float*>(ec), static_cast<float*>(uf), Nc, s);
+    return prolong_fused_q<double>(tab.q, tab, static_cast<const double*>(ec), static_cast<double*>(uf), Nc, s);
+  }
   if (fp32)
     return prolong_q<float>(tab.q, tab, static_cast<const float*>(ec), static_cast<float*>(t1),
                             static_cast<float*>(t2), static_cast<float*>(uf), Nc, s);
@@ -495,6 +675,13 @@ hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, voi
 bool restrict_fusable(int q, int Nc) { return Nc >= 64 && Nc >= 2 * q && Nc <= 256; }
 
 void prime_transfer_shapes(int q, int Nc) {
+  if (prolong_fusable(q, Nc)) {
+    switch (q) {
+      case 1: p3_shape<float, 1>(Nc); p3_shape<double, 1>(Nc); break;
+      case 2: p3_shape<float, 2>(Nc); p3_shape<double, 2>(Nc); break;
+      case 4: p3_shape<float, 4>(Nc); p3_shape<double, 4>(Nc); break;
+    }
+  }
   if (!restrict_fusable(q, Nc)) return;
   switch (q) {
     case 1: r3_shape<float, 1>(Nc); r3_shape<double, 1>(Nc); break;

@@ -397,3 +397,31 @@ def test_fused_restriction_is_the_axis_passes(q, n, precs):
     fused.close()
     axis.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("q,n,precs", [(1, 16, ("fp64", "fp32")), (2, 8, ("fp64", "fp32")), (4, 4, ("fp64", "fp32")),
+                                       (2, 128, ("fp64", "fp32")), (4, 64, ("fp64", "fp32")), (1, 512, ("fp32",)),
+                                       (2, 256, ("fp32",))])
+def test_fused_prolongation_is_the_axis_passes(q, n, precs):
+    """The one-pass prolongation adds the bits of the three one-axis passes into the fine
+    vector on every level of the hierarchy (from coarse grids of 2q up to 256 nodes a
+    side), in both precisions."""
+    torch = torch_cuda()
+    fused = _ctx(q, n, 0)
+    axis = _ctx(q, n, 0, no_fused_transfer=1)
+    for prec in precs:
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        for lv in range(1, fused.levels):
+            g = torch.Generator(device="cuda").manual_seed(200 + lv)
+            ec = torch.randn(fused.num_dofs(lv - 1), dtype=dt, device="cuda", generator=g)
+            uf1 = torch.randn(fused.num_dofs(lv), dtype=dt, device="cuda", generator=g)
+            uf2 = uf1.clone()
+            fused.prolong(lv, ec, uf1)
+            axis.prolong(lv, ec, uf2)
+            torch.cuda.synchronize()
+            print(f"[prolong3] q={q} n={n} {prec} level {lv}: {ec.numel()} -> {uf1.numel()}", flush=True)
+            assert torch.equal(uf1, uf2), f"level {lv} differs"
+            del ec, uf1, uf2
+    fused.close()
+    axis.close()
+    torch.cuda.empty_cache()
