@@ -197,7 +197,7 @@ constexpr int col_rows() {
 // --------------------------------------------------------------------------
 // Streaming column kernel.
 // Body of the column kernel for workgroups whose threads start at row class CY0.
-template <typename T, int Q, int G, int EPI, int RY, int CY0>
+template <typename T, int Q, int G, int EPI, int RY, int CY0, bool PRE>
 __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, Q>& tb, const int N, const int TZ,
                                          const int Y0, const int E0, T* out, const T* bvec, const T* xp,
                                          const T c1, const T c2, T* x1o, double (&dacc)[2]) {
@@ -222,19 +222,20 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
   for (int r = 0; r < NR; ++r) roff[r] = ((yrow0 - Q + r) & Nm) * N + Q * tx;
 
   V pre[NR];
-  auto load_plane = [&](int p) {
+  auto load_to = [&](V(&dst)[NR], int p) {
     const T* base = x + static_cast<size_t>(p & Nm) * NN;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) pre[r] = *reinterpret_cast<const V*>(base + roff[r]);
+    for (int r = 0; r < NR; ++r) dst[r] = *reinterpret_cast<const V*>(base + roff[r]);
     if constexpr (EPI == kEpiZero) {
       // strip row r has y class (CY0 + r) mod q, the plane z class p mod q
       const int cz = p & (Q - 1);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int c = 0; c < Q; ++c) pre[r].v[c] = x1_of(tb, c + Q * ((CY0 + r) % Q + Q * cz), pre[r].v[c]);
+        for (int c = 0; c < Q; ++c) dst[r].v[c] = x1_of(tb, c + Q * ((CY0 + r) % Q + Q * cz), dst[r].v[c]);
     }
   };
+  auto load_plane = [&](int p) { load_to(pre, p); };
 
   const int txl = (tx - 1) & (NX - 1);
   const int txr = (tx + 1) & (NX - 1);
@@ -268,24 +269,10 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     }
   };
 
-  auto compute_gh = [&](int p, bool prefetch) {
+  // x pass across element columns, after the y pass of this plane went to LDS
+  auto xpass = [&]() {
     T* ps = lds + parity * buf_stride;
     T* ss = ps + TY * N;
-    if constexpr (kLatePrefetch) {
-      // the next plane's loads go out once the y pass has consumed this one: one strip
-      // of registers instead of two (q = 4 would spill), the loads still overlap the
-      // x and z passes
-      ypass(pre, ps, ss);
-      if (prefetch) load_plane(p + 1);
-    } else {
-      V xv[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) xv[r] = pre[r];
-      if (prefetch) load_plane(p + 1);
-      ypass(xv, ps, ss);
-    }
-    __syncthreads();
-    // x pass across element columns
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       const int row = (ty * RY + i) * N;
@@ -326,7 +313,87 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     parity ^= 1;
   };
 
+  auto compute_gh = [&](int p, bool prefetch) {
+    T* ps = lds + parity * buf_stride;
+    T* ss = ps + TY * N;
+    if constexpr (kLatePrefetch) {
+      // the next plane's loads go out once the y pass has consumed this one: one strip
+      // of registers instead of two (q = 4 would spill), the loads still overlap the
+      // x and z passes
+      ypass(pre, ps, ss);
+      if (prefetch) load_plane(p + 1);
+    } else {
+      V xv[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) xv[r] = pre[r];
+      if (prefetch) load_plane(p + 1);
+      ypass(xv, ps, ss);
+    }
+    __syncthreads();
+    xpass();
+  };
+
   T acc[RY][Q][Q + 1];
+  if constexpr (PRE) {
+    // a one-layer chunk (TZ = 1): the 2q+1 planes (E0-1) q .. (E0+1) q are loaded at
+    // once, so the block waits for memory once instead of once per plane
+    V allp[2 * Q + 1][NR];
+#pragma unroll
+    for (int k = 0; k <= 2 * Q; ++k) load_to(allp[k], (E0 - 1) * Q + k);
+    auto gh_of = [&](int k) {
+      T* ps = lds + parity * buf_stride;
+      ypass(allp[k], ps, ps + TY * N);
+      __syncthreads();
+      xpass();
+    };
+    gh_of(0);
+#pragma unroll
+    for (int i = 0; i < RY; ++i)
+#pragma unroll
+      for (int c = 0; c < Q; ++c)
+#pragma unroll
+        for (int a = 0; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+#pragma unroll
+      for (int b = 1; b <= Q; ++b) {
+        gh_of(e * Q + b);
+#pragma unroll
+        for (int i = 0; i < RY; ++i)
+#pragma unroll
+          for (int c = 0; c < Q; ++c)
+#pragma unroll
+            for (int a = 0; a <= Q; ++a)
+              acc[i][c][a] = fma(tb.zm[a][b], g[i][c], fma(tb.zk[a][b], h[i][c], acc[i][c][a]));
+      }
+      if (e == 1) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+          const size_t zoff = static_cast<size_t>(E0 * Q + a) * NN;
+#pragma unroll
+          for (int i = 0; i < RY; ++i) {
+            T ax[Q];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
+            const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
+            emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc);
+          }
+        }
+      } else {
+        // carry the shared vertex plane into element layer E0
+#pragma unroll
+        for (int i = 0; i < RY; ++i)
+#pragma unroll
+          for (int c = 0; c < Q; ++c) {
+            const T top = acc[i][c][Q];
+            acc[i][c][0] = top + tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c];
+#pragma unroll
+            for (int a = 1; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
+          }
+      }
+    }
+    return;
+  }
   const int zlast = (E0 + TZ) * Q;
 
   load_plane((E0 - 1) * Q);
@@ -378,7 +445,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
   }
 }
 
-template <typename T, int Q, int G, int EPI>
+template <typename T, int Q, int G, int EPI, bool PRE = false>
 __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
                                                               const int N, const int TZ, const int ntiles_y,
                                                               T* out, const T* bvec, const T* xp, const T c1,
@@ -393,10 +460,10 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
   const int E0 = (tile / ntiles_y) * TZ;
   double dacc[2] = {0.0, 0.0};
   if constexpr (SPLIT == 1) {
-    col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    col_body<T, Q, G, EPI, RY, 0, PRE>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
   } else {
-    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
-    else col_body<T, Q, G, EPI, RY, 2>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0, PRE>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    else col_body<T, Q, G, EPI, RY, 2, PRE>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
   }
   if constexpr (reduces(EPI)) {
     // block partials in a fixed order: wavefront shuffles, then the wavefronts in turn
@@ -599,6 +666,12 @@ inline int pick_tz(int n, int64_t tiles, int64_t resident) {
   return best;
 }
 
+// the preloading variant: FP32 q <= 2 (2q+1 strips of registers), the plain epilogues
+template <typename T, int Q, int EPI>
+constexpr bool pre_ok() {
+  return sizeof(T) == 4 && Q <= 2 && !reduces(EPI);
+}
+
 template <typename T, int Q, int G, int EPI>
 hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hipStream_t s) {
   const int threads = (a.N / Q) * G;
@@ -613,6 +686,15 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
     if (e != hipSuccess) return e;
+  }
+  if constexpr (pre_ok<T, Q, EPI>()) {
+    if (sh.TZ == 1) {  // one element layer per block: all its planes loaded at once
+      hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI, true>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
+                         static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
+                         static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
+                         static_cast<T>(a.c2), static_cast<T*>(a.x1), a.part);
+      return hipGetLastError();
+    }
   }
   hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
                      static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
