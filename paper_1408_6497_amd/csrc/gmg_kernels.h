@@ -141,10 +141,10 @@ hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, voi
                           hipStream_t s, bool fused = true);
 hipError_t launch_restrict(const TransferTab& tab, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
                            hipStream_t s, bool fused = true);
-// fused: one kernel for the three axes (bit-identical to the axis passes): the
-// prolongation from coarse levels of 2q <= Nc <= 256 nodes a side, the restriction
-// onto those of 64 <= Nc <= 256; prime_transfer_shapes queries their occupancy once
-// per level size, before any graph capture
+// fused: one kernel for the three axes (bit-identical to the axis passes), q <= 2:
+// the prolongation from coarse levels of 2q <= Nc <= 256 nodes a side, the
+// restriction onto those of 64 <= Nc <= 256; prime_transfer_shapes queries their
+// occupancy once per level size, before any graph capture
 void prime_transfer_shapes(int q, int Nc);
 
 // out = c * tab[class(i)] * in  (class table of length q^3; in may be null -> 1)

@@ -649,15 +649,15 @@ hipError_t restrict_q(int q, const TransferTab& tab, const T* rf, T* t1, T* t2, 
 
 }  // namespace
 
-// one thread per coarse element of a row, q coarse rows at least: 256 threads hold Nc <= 256
-bool prolong_fusable(int q, int Nc) { return Nc >= 2 * q && Nc <= 256; }
+// one thread per coarse element of a row, q coarse rows at least: 256 threads hold
+// Nc <= 256; q = 4 keeps the axis passes (measured slower fused on every level but
+// the finest, 18.6 against 13.9 us from 16^3 coarse nodes)
+bool prolong_fusable(int q, int Nc) { return q <= 2 && Nc >= 2 * q && Nc <= 256; }
 
 hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
                           hipStream_t s, bool fused) {
   if (Nc < tab.q || (Nc & (Nc - 1)) != 0 || Nc > 1024) return hipErrorInvalidValue;
-  // FP64 q = 4 keeps the axis passes: its fused kernel holds (q+1) 2q FP64 y values
-  // per row and spills
-  if (fused && prolong_fusable(tab.q, Nc) && (fp32 || tab.q < 4)) {
+  if (fused && prolong_fusable(tab.q, Nc)) {
     if (fp32) return prolong_fused_q<float>(tab.q, tab, static_cast<const float*>(ec), static_cast<float*>(uf), Nc, s);
     return prolong_fused_q<double>(tab.q, tab, static_cast<const double*>(ec), static_cast<double*>(uf), Nc, s);
   }
@@ -672,7 +672,10 @@ hipError_t launch_prolong(const TransferTab& tab, bool fp32, const void* ec, voi
 // Nc <= 256.  Below 64 coarse nodes a side the chain of 2q (TZE + 1) + 1 fine planes
 // a block streams is longer than the three short axis launches (measured: 14-15 us
 // against 11.5 us onto 16^3 and 32^3 nodes, q = 2), so those keep the axis passes.
-bool restrict_fusable(int q, int Nc) { return Nc >= 64 && Nc >= 2 * q && Nc <= 256; }
+// q = 4 keeps the axis passes: its 4q+1-tap windows make the halo rows and planes
+// cost more than the passes they replace (measured onto 128^3 nodes: 85 against
+// 54 us, the Q4 solve 10.65 against 10.44 ms).
+bool restrict_fusable(int q, int Nc) { return q <= 2 && Nc >= 64 && Nc >= 2 * q && Nc <= 256; }
 
 void prime_transfer_shapes(int q, int Nc) {
   if (prolong_fusable(q, Nc)) {
