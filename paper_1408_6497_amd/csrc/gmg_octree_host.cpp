@@ -17,8 +17,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <map>
 #include <stdexcept>
+#include <thread>
 #include <unordered_map>
 
 #include "gmg_setup_math.h"
@@ -49,6 +51,28 @@ std::vector<uint64_t> keys_of(const std::vector<Leaf>& t) {
   std::vector<uint64_t> k(t.size());
   for (size_t i = 0; i < t.size(); ++i) k[i] = key_of(t[i]);
   return k;
+}
+
+// f(i) for i in [0, n) on up to 16 host threads, in contiguous chunks (the calls
+// must be independent); serial below min_n items.
+template <typename F>
+void parallel_for(int64_t n, const F& f, int64_t min_n = int64_t{1} << 16) {
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  if (n < min_n) nt = 1;
+  if (nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+    if (b < e) th.emplace_back([&f, b, e] {
+      for (int64_t i = b; i < e; ++i) f(i);
+    });
+  }
+  for (auto& x : th) x.join();
 }
 
 void push_children(const Leaf& o, std::vector<Leaf>* out) {
@@ -153,19 +177,40 @@ bool is_complete(const std::vector<Leaf>& t) {
   return pos == static_cast<uint64_t>(kUnits) * kUnits * kUnits;
 }
 
-bool is_balanced(const std::vector<Leaf>& t) {
+namespace {
+
+// Leaves that some leaf touches from two or more levels finer; the marks of each
+// thread's range of leaves go to a vector of its own and are OR-ed together.
+std::vector<char> coarse_neighbour_marks(const std::vector<Leaf>& t) {
   const std::vector<uint64_t> keys = keys_of(t);
-  std::vector<char> split(t.size(), 0);
-  for (size_t i = 0; i < t.size(); ++i) mark_coarse_neighbours(t, keys, i, &split);
+  const int64_t n = static_cast<int64_t>(t.size());
+  unsigned nt = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
+  if (n < (int64_t{1} << 16)) nt = 1;
+  std::vector<std::vector<char>> marks(nt, std::vector<char>(t.size(), 0));
+  const int64_t chunk = (n + nt - 1) / nt;
+  parallel_for(
+      nt,
+      [&](int64_t k) {
+        const int64_t b = k * chunk, e = std::min<int64_t>(n, b + chunk);
+        for (int64_t i = b; i < e; ++i) mark_coarse_neighbours(t, keys, static_cast<size_t>(i), &marks[k]);
+      },
+      2);
+  for (unsigned k = 1; k < nt; ++k)
+    for (int64_t i = 0; i < n; ++i) marks[0][i] |= marks[k][i];
+  return std::move(marks[0]);
+}
+
+}  // namespace
+
+bool is_balanced(const std::vector<Leaf>& t) {
+  const std::vector<char> split = coarse_neighbour_marks(t);
   return std::find(split.begin(), split.end(), 1) == split.end();
 }
 
 std::vector<Leaf> balance(const std::vector<Leaf>& t0) {
   std::vector<Leaf> t = t0;
   while (true) {
-    const std::vector<uint64_t> keys = keys_of(t);
-    std::vector<char> split(t.size(), 0);
-    for (size_t i = 0; i < t.size(); ++i) mark_coarse_neighbours(t, keys, i, &split);
+    const std::vector<char> split = coarse_neighbour_marks(t);
     if (std::find(split.begin(), split.end(), 1) == split.end()) return t;
     std::vector<Leaf> next;
     next.reserve(t.size() + 7 * std::count(split.begin(), split.end(), 1));
@@ -352,13 +397,18 @@ void reference_element(int q, std::vector<double>* kref, std::vector<double>* mr
 
 namespace {
 
+// Node positions are identified by their rank in the sorted list of distinct element-node
+// positions; each is either a DoF or hangs on a source leaf.
 struct Builder {
   const Space& s;
-  int p;                                       // nodes per direction (q + 1)
-  std::vector<int64_t> elem_pos;               // (E m) tick keys
-  std::unordered_map<int64_t, int> hang_src;   // hanging position -> source leaf
-  std::unordered_map<int64_t, int64_t> dof;    // independent position -> DoF
-  std::unordered_map<int64_t, std::map<int64_t, double>> memo;
+  int p;                                      // nodes per direction (q + 1)
+  std::vector<int64_t> elem_pos;              // (E m) tick keys
+  std::vector<int64_t> uniq;                  // distinct positions, ascending
+  std::vector<int32_t> rank_of;               // elem_pos index -> rank in uniq
+  std::vector<int64_t> dof_of;                // rank -> DoF, or -1 where the position hangs
+  std::vector<int32_t> src_of;                // rank -> leaf whose interpolant a hanging position takes
+  std::vector<std::vector<std::pair<int64_t, double>>> memo;  // rank -> resolved weights (hanging)
+  std::vector<char> done;
 
   static int64_t tkey(int64_t x, int64_t y, int64_t z) { return x + kTicks * (y + kTicks * z); }
 
@@ -405,26 +455,31 @@ struct Builder {
     return best;
   }
 
-  const std::map<int64_t, double>& expand(int64_t key) {
-    auto it = memo.find(key);
-    if (it != memo.end()) return it->second;
+  // weights of the hanging position of rank u on the DoFs, in ascending DoF order: the
+  // source leaf's interpolant, node by node (a ascending), each node resolved in turn
+  const std::vector<std::pair<int64_t, double>>& expand(int32_t u) {
+    if (done[u]) return memo[u];
+    const int e = src_of[u];
+    std::vector<double> phi;
+    basis_at(s.leaves[e], uniq[u], &phi);
+    const int m = p * p * p;
     std::map<int64_t, double> out;
-    const auto d = dof.find(key);
-    if (d != dof.end()) {
-      out[d->second] = 1.0;
-    } else {
-      const int e = hang_src.at(key);
-      std::vector<double> phi;
-      basis_at(s.leaves[e], key, &phi);
-      const int m = p * p * p;
-      for (int a = 0; a < m; ++a) {
-        if (phi[a] == 0.0) continue;
-        const std::map<int64_t, double> sub = expand(elem_pos[static_cast<size_t>(e) * m + a]);
+    for (int a = 0; a < m; ++a) {
+      if (phi[a] == 0.0) continue;
+      const int32_t v = rank_of[static_cast<size_t>(e) * m + a];
+      if (dof_of[v] >= 0) {
+        out[dof_of[v]] += phi[a] * 1.0;
+      } else {
+        const auto& sub = expand(v);
         for (const auto& kv : sub) out[kv.first] += phi[a] * kv.second;
       }
-      for (auto i = out.begin(); i != out.end();) i = (i->second == 0.0) ? out.erase(i) : std::next(i);
     }
-    return memo.emplace(key, std::move(out)).first->second;
+    std::vector<std::pair<int64_t, double>> w;
+    for (const auto& kv : out)
+      if (kv.second != 0.0) w.push_back(kv);
+    memo[u] = std::move(w);
+    done[u] = 1;
+    return memo[u];
   }
 };
 
@@ -438,43 +493,73 @@ Space build_space(const std::vector<Leaf>& t, int q) {
   s.m = p * p * p;
   s.leaves = t;
   s.keys = keys_of(t);
-  Builder B{s, p, {}, {}, {}, {}};
+  Builder B{s, p, {}, {}, {}, {}, {}, {}, {}};
   const int64_t E = s.elements();
-  B.elem_pos.resize(static_cast<size_t>(E) * s.m);
-  for (int64_t e = 0; e < E; ++e) {
+  const int m = s.m;
+  B.elem_pos.resize(static_cast<size_t>(E) * m);
+  parallel_for(E, [&](int64_t e) {
     const Leaf& o = t[e];
     const int64_t step = 2 * static_cast<int64_t>(leaf_size(o.level)) / q;
     for (int c = 0; c < p; ++c)
       for (int b = 0; b < p; ++b)
         for (int a = 0; a < p; ++a)
-          B.elem_pos[e * s.m + a + p * (b + p * c)] =
+          B.elem_pos[e * m + a + p * (b + p * c)] =
               Builder::tkey(wrap(2 * static_cast<int64_t>(o.x) + a * step, kTicks),
                             wrap(2 * static_cast<int64_t>(o.y) + b * step, kTicks),
                             wrap(2 * static_cast<int64_t>(o.z) + c * step, kTicks));
-  }
-  std::vector<int64_t> uniq = B.elem_pos;
-  std::sort(uniq.begin(), uniq.end());
-  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-  for (int64_t key : uniq) {
-    const int e = B.coarsest_containing(key);
-    if (B.is_node(t[e], key)) {
-      B.dof.emplace(key, static_cast<int64_t>(s.points.size()));
-      s.points.push_back(key);  // ascending: uniq is sorted
-    } else {
-      B.hang_src.emplace(key, e);
+  });
+  B.uniq = B.elem_pos;
+  std::sort(B.uniq.begin(), B.uniq.end());
+  B.uniq.erase(std::unique(B.uniq.begin(), B.uniq.end()), B.uniq.end());
+  const int64_t U = static_cast<int64_t>(B.uniq.size());
+  if (U > INT32_MAX) throw std::length_error("too many node positions");
+  // DoF or hanging, per position (independent); DoFs numbered in ascending position order
+  std::vector<char> is_dof(U);
+  B.src_of.assign(U, -1);
+  parallel_for(U, [&](int64_t u) {
+    const int e = B.coarsest_containing(B.uniq[u]);
+    is_dof[u] = B.is_node(t[e], B.uniq[u]);
+    if (!is_dof[u]) B.src_of[u] = e;
+  });
+  B.dof_of.assign(U, -1);
+  for (int64_t u = 0; u < U; ++u)
+    if (is_dof[u]) {
+      B.dof_of[u] = static_cast<int64_t>(s.points.size());
+      s.points.push_back(B.uniq[u]);
     }
-  }
-  s.C.rows = E * s.m;
+  B.rank_of.resize(B.elem_pos.size());
+  parallel_for(static_cast<int64_t>(B.elem_pos.size()), [&](int64_t r) {
+    B.rank_of[r] = static_cast<int32_t>(std::lower_bound(B.uniq.begin(), B.uniq.end(), B.elem_pos[r]) - B.uniq.begin());
+  });
+  // resolve every hanging position once (recursively, memoised)
+  B.memo.resize(U);
+  B.done.assign(U, 0);
+  for (int64_t u = 0; u < U; ++u)
+    if (!is_dof[u]) B.expand(static_cast<int32_t>(u));
+  // C: one row per element node, its position's weights
+  s.C.rows = E * m;
   s.C.cols = s.ndof();
   s.C.ptr.assign(s.C.rows + 1, 0);
   for (int64_t r = 0; r < s.C.rows; ++r) {
-    const std::map<int64_t, double>& w = B.expand(B.elem_pos[r]);
-    for (const auto& kv : w) {
-      s.C.col.push_back(static_cast<int32_t>(kv.first));
-      s.C.val.push_back(kv.second);
-    }
-    s.C.ptr[r + 1] = static_cast<int64_t>(s.C.col.size());
+    const int32_t u = B.rank_of[r];
+    s.C.ptr[r + 1] = s.C.ptr[r] + (is_dof[u] ? 1 : static_cast<int64_t>(B.memo[u].size()));
   }
+  s.C.col.resize(s.C.ptr[s.C.rows]);
+  s.C.val.resize(s.C.ptr[s.C.rows]);
+  parallel_for(s.C.rows, [&](int64_t r) {
+    const int32_t u = B.rank_of[r];
+    int64_t k = s.C.ptr[r];
+    if (is_dof[u]) {
+      s.C.col[k] = static_cast<int32_t>(B.dof_of[u]);
+      s.C.val[k] = 1.0;
+      return;
+    }
+    for (const auto& kv : B.memo[u]) {
+      s.C.col[k] = static_cast<int32_t>(kv.first);
+      s.C.val[k] = kv.second;
+      ++k;
+    }
+  });
   return s;
 }
 
