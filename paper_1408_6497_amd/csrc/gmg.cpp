@@ -86,8 +86,11 @@ struct gmg_ctx {
   // captured finest V-cycles: [0] FP64 on (kr0, kz0), [1] FP32 on (kr1, kz1),
   // [2] FP64 r -> FP32 V-cycle -> FP64 z on (kr0, kz0)
   // [3..6] the learned / plain test sequences of the learned cycle (see precondition)
-  hipGraphExec_t vgraph[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  bool graph_failed[8] = {false, false, false, false, false, false, false, false};
+  // captured launch sequences: 0-2 V-cycles, 3-6 learned cycles under test, 7-8 the
+  // cycle plus direction update of FP64 flexible CG around FP32 cycles
+  static constexpr int kGraphKeys = 9;
+  hipGraphExec_t vgraph[kGraphKeys] = {};
+  bool graph_failed[kGraphKeys] = {};
   bool suppress_learned = false;
   std::vector<Level> lv;
   TransferTab xfer{};
@@ -898,17 +901,21 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     return GMG_OK;
   };
   // first direction p = z - mean(z), z = V r
+  // (mixed: the cycle and the vector work after it are one captured sequence; every
+  // argument is fixed for the context)
   auto restart = [&]() -> gmg_status {
     if (mixed) {
-      STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
-      if (fused_pw) {
-        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(r), c->part, c->scal, S_ZS, S_ZR, S_YS, s));
-        HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
-      } else {
-        HIPCHK(c, launch_sum(true, n, z32, c->part, c->scal + S_ZS, s));
-      }
-      HIPCHK(c, launch_shift_f2d(n, c->scal, S_ZS, inv_n, z32, static_cast<double*>(p), s));
-      return GMG_OK;
+      return graph_run(c, 7, [&]() -> gmg_status {
+        STCHK(vcycle_seq(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+        if (fused_pw) {
+          HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(r), c->part, c->scal, S_ZS, S_ZR, S_YS, s));
+          HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
+        } else {
+          HIPCHK(c, launch_sum(true, n, z32, c->part, c->scal + S_ZS, s));
+        }
+        HIPCHK(c, launch_shift_f2d(n, c->scal, S_ZS, inv_n, z32, static_cast<double*>(p), s));
+        return GMG_OK;
+      });
     }
     STCHK(precondition(c, pi, vpi, r, z));
     STCHK(project(c, pi, n, z));
@@ -918,17 +925,19 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   };
   // the mixed solve's next cycle and direction update (z = V r, p = (z - mean z) + beta p)
   auto mixed_direction = [&]() -> gmg_status {
-    STCHK(run_vcycle(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
-    if (fused_pw) {
-      HIPCHK(c, launch_sums4_mixed(n, z32, static_cast<const double*>(w), static_cast<const double*>(r), c->part,
-                                   c->scal, S_ZS, S_ZW, S_YS, S_ZR, s));
-      HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
-    } else {
-      HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
-    }
-    HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
-    HIPCHK(c, launch_xpby_shift_mixed(n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z32, static_cast<double*>(p), s));
-    return GMG_OK;
+    return graph_run(c, 8, [&]() -> gmg_status {
+      STCHK(vcycle_seq(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+      if (fused_pw) {
+        HIPCHK(c, launch_sums4_mixed(n, z32, static_cast<const double*>(w), static_cast<const double*>(r), c->part,
+                                     c->scal, S_ZS, S_ZW, S_YS, S_ZR, s));
+        HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
+      } else {
+        HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(w), c->part, c->scal, S_ZS, S_ZW, S_YS, s));
+      }
+      HIPCHK(c, launch_combine(c->scal, S_ZWC, S_ZW, S_ZS, S_YS, inv_n, s));
+      HIPCHK(c, launch_xpby_shift_mixed(n, c->scal, S_ZWC, S_PW, -1.0, S_ZS, inv_n, z32, static_cast<double*>(p), s));
+      return GMG_OK;
+    });
   };
   // Mixed solves enqueue the cycle that follows a residual update before the host
   // has read the residual's norm, whenever the last norm was more than kSpecMargin
@@ -1831,7 +1840,7 @@ gmg_status set_master(gmg_ctx* c, int d, const float* w_host) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->net_set[d] = 1;
   // captured cycles bake in which levels use a net
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < gmg_ctx::kGraphKeys; ++k)
     if (c->vgraph[k]) {
       (void)hipGraphExecDestroy(c->vgraph[k]);
       c->vgraph[k] = nullptr;
