@@ -51,6 +51,8 @@ enum : int {
   S_RS = 48,    // sum of the stored Krylov residual (FCG around FP32 cycles)
   S_WS = 49,    // sum of w = A p                      (the same)
   S_ZR = 50,    // z . r                                (the same)
+  S_TR = 51,    // true residual's r . r and sum r      (the same, its final check)
+  S_TS = 52,
 };
 // a hierarchy has at most 11 levels (n <= 512 uniform, leaf level <= 10 octree)
 static_assert(S_SSUM + 32 <= S_RS && S_WS < kNumScal, "scalar slots overlap");
@@ -853,6 +855,16 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// zero integral: u <- u - (int u_h) / |cube| on level l (FP64)
+gmg_status zero_integral(gmg_ctx* c, int l, void* u) {
+  const Level& F = c->lv[l];
+  const int64_t n = F.size;
+  if (F.oct) HIPCHK(c, launch_dot(false, n, F.wint64, u, c->part, c->scal + S_TMP, c->stream));
+  else HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u, c->part, c->part_cap, c->scal + S_TMP, c->stream));
+  HIPCHK(c, launch_shift(false, n, c->scal, S_TMP, 1.0, u, c->stream));
+  return GMG_OK;
+}
+
 // Preconditioned Krylov solve of A c = r on the finest level in precision pi,
 // c = 0 initially.  r is overwritten with the recursive residual.  Stops when
 // ||r||_2 <= tol_abs.  With b_true, the stop is confirmed on the true residual
@@ -947,6 +959,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   // simply dropped.
   constexpr double kSpecMargin = 1e3;
   bool have_dir = false;
+  bool end_pending = false;  // the final check is already enqueued
   if (start_from_b && mixed && norm_slot >= 0) {
     // u = 0 with sum(b) and b.b (the caller's norm) in one pass; r = b - mean(b),
     // its FP32 cast and its sums in the next
@@ -993,13 +1006,18 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     if (std::sqrt(rr) <= tol_abs) {
       if (!b_true) break;
       if (fused_pw) {
-        // the true residual with its sums from the apply; the projection and cast
-        // follow only if it is not below the tolerance
-        STCHK(apply_op(c, l, pi, Epi::ResidualSums, u, r, b_true, nullptr, 0, 0, false, nullptr, 0.0, S_RR, S_RS));
+        // the true residual (into the unused FP64 z buffer) with its sums from the
+        // apply, unless it was enqueued behind the last read-back already; the
+        // projection and cast follow only if it is not below the tolerance
+        if (!end_pending)
+          STCHK(apply_op(c, l, pi, Epi::ResidualSums, u, c->kz[0], b_true, nullptr, 0, 0, false, nullptr, 0.0, S_TR,
+                         S_TS));
+        end_pending = false;
         STCHK(read_scalars(c, hs, kNumScal));
-        rr = std::max(0.0, hs[S_RR] - hs[S_RS] * hs[S_RS] / static_cast<double>(n));
-        if (!std::isfinite(hs[S_RR])) rr = hs[S_RR];
+        rr = std::max(0.0, hs[S_TR] - hs[S_TS] * hs[S_TS] / static_cast<double>(n));
+        if (!std::isfinite(hs[S_TR])) rr = hs[S_TR];
         if ((std::sqrt(rr) <= tol_abs && std::isfinite(rr)) || it >= maxit) break;
+        HIPCHK(c, launch_copy(false, n, c->kz[0], r, s));
         STCHK(project_norm());
         STCHK(read_scalars(c, hs, kNumScal));
         rr = hs[S_RR];
@@ -1044,6 +1062,14 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       STCHK(scalars_async(c, kNumScal));
       STCHK(mixed_direction());
       STCHK(scalars_wait(c, hs, kNumScal));
+    } else if (speculate && fused_pw && b_true) {
+      // near the tolerance: the true-residual check goes behind the read-back instead
+      // (it writes only the scratch vector and its two sums; if the iteration goes
+      // on, they are dropped)
+      STCHK(scalars_async(c, kNumScal));
+      STCHK(apply_op(c, l, pi, Epi::ResidualSums, u, c->kz[0], b_true, nullptr, 0, 0, false, nullptr, 0.0, S_TR, S_TS));
+      end_pending = true;
+      STCHK(scalars_wait(c, hs, kNumScal));
     } else {
       STCHK(read_scalars(c, hs, kNumScal));
     }
@@ -1057,6 +1083,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: p^T A p <= 0 or not finite");
     }
     if (std::sqrt(rr) <= tol_abs) continue;
+    end_pending = false;
     // z is projected inside the direction update: p = (z - mean z) + beta p, with
     // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
     if (mixed) {
@@ -1645,13 +1672,7 @@ gmg_status solve_rhs_impl(gmg_ctx* ctx, const double* b_dev, double* u_dev, doub
     }
     inf.inner_iters = total;
   }
-  if (st == GMG_OK || st == GMG_E_NOCONV) {
-    // zero integral: u <- u - (int u_h) / |cube|
-    const Level& F = c->lv[l];
-    if (F.oct) HIPCHK(c, launch_dot(false, n, F.wint64, u_dev, c->part, c->scal + S_TMP, s));
-    else HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u_dev, c->part, c->part_cap, c->scal + S_TMP, s));
-    HIPCHK(c, launch_shift(false, n, c->scal, S_TMP, 1.0, u_dev, s));
-  }
+  if (st == GMG_OK || st == GMG_E_NOCONV) STCHK(zero_integral(c, l, u_dev));
   HIPCHK(c, hipEventRecord(e1, s));
   HIPCHK(c, hipEventSynchronize(e1));
   float ms = 0.0f;
