@@ -183,14 +183,17 @@ constexpr int col_bound() {
 }
 
 // Rows per thread of the column kernel: FP64 q = 4 and the FP64 q = 2 smoother
-// steps (whose epilogue holds three more vectors) take two, or their element-layer
-// accumulators would spill; the rest take four (measured: FP64 q = 2 smoother step
-// on 256^3 DoFs 140 -> 117 us with two rows, the plain FP64 apply slower with two).
+// steps (whose epilogue holds three more vectors) and reducing epilogues take two,
+// or their element-layer accumulators would spill; the rest take four (measured on
+// 256^3 DoFs: FP64 q = 2 smoother step 140 -> 117 us with two rows, the apply with
+// its two sums 70 -> 49 us, the plain FP64 apply slower with two).
 template <typename T, int Q, int EPI>
 constexpr int col_rows() {
   if (sizeof(T) != 8) return 4;
   if (Q == 4) return 2;
-  if (Q == 2 && (EPI == static_cast<int>(Epi::Cheb) || EPI == static_cast<int>(Epi::ChebZero))) return 2;
+  if (Q == 2 && (EPI == static_cast<int>(Epi::Cheb) || EPI == static_cast<int>(Epi::ChebZero) ||
+                 EPI == static_cast<int>(Epi::ApplyDot) || EPI == static_cast<int>(Epi::ResidualSums)))
+    return 2;
   return 4;
 }
 
