@@ -203,6 +203,19 @@ gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev);
 gmg_status gmg_solve(gmg_ctx* ctx, const double* f_dev, double* u_dev, double rtol, gmg_info* info);
 gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info);
 
+/* Exact solve of the same finite-element system by the 3D FFT (the FFT Poisson method of
+ * Section 2, Table 7's uniform-grid baseline), for uniform Q1 meshes: on a periodic mesh
+ * the Q1 matrix is diagonal in the Fourier basis, with eigenvalue
+ *   kap(kx) mu(ky) mu(kz) + mu(kx) kap(ky) mu(kz) + mu(kx) mu(ky) kap(kz),
+ *   kap(k) = (2 - 2 cos(2 pi k/N)) / h,  mu(k) = h (4 + 2 cos(2 pi k/N)) / 6,
+ * so u = F^-1 [F(b) / eigenvalue] with the constant mode set to zero (the zero-integral
+ * solution).  b_dev: the load vector (as for gmg_solve_rhs, mean zero), u_dev: the
+ * solution, both FP64 device arrays of gmg_num_dofs values in lattice order, not
+ * aliased; b_dev is not modified.  FP64 transforms (hipFFT).  The first call allocates
+ * the transform plans and a spectrum buffer of N^2 (N/2+1) complex values, kept until
+ * gmg_destroy.  GMG_E_ARG on octree or q != 1 contexts and on aliasing. */
+gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev);
+
 /* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
 

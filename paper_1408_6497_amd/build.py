@@ -53,7 +53,7 @@ def build(verbose=False, jobs=8):
     if failed:
         raise RuntimeError("hipcc failed on: " + ", ".join(failed))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "gmg.h"
@@ -104,6 +105,7 @@ struct gmg_ctx {
   double* scal = nullptr;
   double* scal_host = nullptr;  // pinned host copy of scal (read back at each convergence test)
   hipEvent_t ev_copy = nullptr;  // marks the end of a read-back that later work overlaps
+  std::unique_ptr<FftQ1> fft;    // plans and spectrum of gmg_fft_solve (made on first use)
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // bracket each solve (gmg_info.t_solve)
   double* part = nullptr;
   int64_t part_cap = 0;
@@ -1505,6 +1507,20 @@ gmg_status gmg_apply(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_d
   if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "apply: x and y must not alias");
   return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0); });
+}
+
+gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev) {
+  if (!ctx || !b_dev || !u_dev) return GMG_E_ARG;
+  if (static_cast<const void*>(b_dev) == static_cast<const void*>(u_dev))
+    return fail(ctx, GMG_E_ARG, "FFT solve: b and u must not alias");
+  const Level& F = ctx->lv.back();
+  if (F.oct || ctx->q != 1) return fail(ctx, GMG_E_ARG, "FFT solve: uniform Q1 meshes only");
+  if (!ctx->fft) ctx->fft.reset(new FftQ1());
+  return scoped(ctx, [&]() -> gmg_status {
+    HIPCHK(ctx, fft_q1_prepare(ctx->fft.get(), F.N));
+    HIPCHK(ctx, fft_q1_solve(ctx->fft.get(), b_dev, u_dev, ctx->stream));
+    return GMG_OK;
+  });
 }
 
 gmg_status gmg_mass(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {

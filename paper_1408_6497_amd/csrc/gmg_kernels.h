@@ -76,6 +76,19 @@ struct ApplyArgs {
   int d0, d1;
 };
 
+// Exact FFT solve of the uniform periodic Q1 system on N^3 nodes (FP64): plans and the
+// spectrum buffer are made by fft_q1_prepare and kept until the object is destroyed.
+struct FftQ1 {
+  int N = 0;
+  void* fwd = nullptr;  // hipfftHandle (an opaque pointer)
+  void* inv = nullptr;
+  bool fwd_ok = false, inv_ok = false;
+  void* spec = nullptr;
+  ~FftQ1();
+};
+hipError_t fft_q1_prepare(FftQ1* f, int N);
+hipError_t fft_q1_solve(FftQ1* f, const double* b, double* u, hipStream_t s);
+
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 // Query (once per device) the occupancy that the launch shape of every apply
 // kernel instance for a level of N nodes a side depends on; call before any

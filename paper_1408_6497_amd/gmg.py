@@ -22,7 +22,7 @@ _STATUS = {
 EXPORTS = [
     "gmg_setup", "gmg_destroy", "gmg_num_levels", "gmg_num_dofs", "gmg_dof_coords_1d", "gmg_lambda",
     "gmg_diagonal", "gmg_apply", "gmg_mass", "gmg_smooth", "gmg_restrict", "gmg_prolong",
-    "gmg_coarse_solve", "gmg_vcycle", "gmg_rhs", "gmg_solve", "gmg_solve_rhs", "gmg_dot",
+    "gmg_coarse_solve", "gmg_vcycle", "gmg_rhs", "gmg_solve", "gmg_solve_rhs", "gmg_fft_solve", "gmg_dot",
     "gmg_timing_get", "gmg_timing_reset", "gmg_history", "gmg_status_string", "gmg_last_error",
     "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
@@ -103,6 +103,7 @@ def load():
         "gmg_rhs": [P, P, P],
         "gmg_solve": [P, P, P, D, ctypes.POINTER(GmgInfo)],
         "gmg_solve_rhs": [P, P, P, D, ctypes.POINTER(GmgInfo)],
+        "gmg_fft_solve": [P, P, P],
         "gmg_dot": [P, I32, I64, P, P, ctypes.POINTER(D)],
         "gmg_timing_get": [P, I32, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(D)],
         "gmg_timing_reset": [P],
@@ -425,6 +426,11 @@ class Context:
         if st != 0 and (raise_on_noconv or st != 5):
             self._check(st)
         return info
+
+    def fft_solve(self, b, u):
+        """Exact FFT solve of the uniform Q1 system A u = b (FP64)."""
+        lv = self.levels - 1
+        self._check(self.lib.gmg_fft_solve(self.h, self._vec(b, lv, GMG_FP64), self._vec(u, lv, GMG_FP64)))
 
     def solve_rhs(self, b, u, rtol, raise_on_noconv=True):
         lv = self.levels - 1

@@ -1,0 +1,93 @@
+"""FFT solve of the uniform Q1 system (gmg_fft_solve) against the oracle.
+
+The oracle's assembled Kronecker operator checks the residual of the FFT solution (an
+exact solve: within rounding, 1e-12 relative); the C1 source has the closed-form discrete
+solution amp * sin sin sin (the oracle's pin); the multigrid solve of the same load vector
+agrees to its own tolerance; errors are reported for other orders.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(q, n, levels=0, **kw):
+    torch_cuda()
+    from paper_1408_6497_amd import Context
+    return Context(q, n, levels, **kw)
+
+
+@pytest.mark.parametrize("n", [8, 32])
+def test_fft_solve_residual_on_the_oracle_operator(n):
+    torch = torch_cuda()
+    from oracle import operator as op
+    ctx = _ctx(1, n, 2 if n == 8 else 0)
+    b = np.random.default_rng(11).standard_normal(n ** 3)
+    b -= b.mean()
+    bd = to_dev(b, torch.float64)
+    b0 = bd.clone()
+    u = torch.empty_like(bd)
+    ctx.fft_solve(bd, u)
+    torch.cuda.synchronize()
+    uh = to_host(u)
+    A = op.assemble(1, n)
+    rel = np.linalg.norm(b - A @ uh) / np.linalg.norm(b)
+    print(f"[fft] n={n}: residual {rel:.2e}, mean {uh.mean():.1e}", flush=True)
+    assert rel <= 1e-12
+    assert abs(uh.mean()) <= 1e-12 * np.abs(uh).max()
+    assert torch.equal(bd, b0)  # the load vector is left as it was
+
+
+def test_fft_solve_c1_closed_form():
+    """f = 12 pi^2 sin sin sin on 64^3 Q1 nodes: the discrete solution is the closed form."""
+    torch = torch_cuda()
+    from workloads import sin_source, sin_exact
+    from oracle import multigrid as mg
+    q, n = 1, 64
+    ctx = _ctx(q, n)
+    x1 = ctx.dof_coords_1d()
+    b = to_dev(mg.rhs(q, n, to_host(sin_source(x1))), torch.float64)
+    u = torch.empty_like(b)
+    ctx.fft_solve(b, u)
+    torch.cuda.synchronize()
+    th, h = 2 * math.pi / n, 1.0 / n
+    amp = 4 * math.pi ** 2 * (h * (4 + 2 * math.cos(th)) / 6) / ((2 - 2 * math.cos(th)) / h)
+    err = np.max(np.abs(to_host(u) - amp * sin_exact(x1)))
+    print(f"[fft-c1] max error against the closed form {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_fft_solve_matches_multigrid():
+    """The FFT solution and the multigrid solution of one load vector agree (128^3 Q1 nodes)."""
+    torch = torch_cuda()
+    from workloads import gaussian_params, gaussian_source
+    ctx = _ctx(1, 128)
+    f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1), device="cuda")
+    b = torch.empty_like(f)
+    ctx.rhs(f, b)
+    uf, ug = torch.empty_like(b), torch.empty_like(b)
+    ctx.fft_solve(b, uf)
+    info = ctx.solve_rhs(b, ug, 1e-11)
+    torch.cuda.synchronize()
+    d = (uf - ug).norm().item() / ug.norm().item()
+    print(f"[fft-mg] relative difference {d:.2e} (multigrid to {info.rel_residual_f64:.1e})", flush=True)
+    assert d <= 1e-7
+
+
+def test_fft_solve_rejects_other_orders():
+    torch = torch_cuda()
+    from paper_1408_6497_amd import GmgError
+    ctx = _ctx(2, 8, 2)
+    b = torch.zeros(ctx.num_dofs(), dtype=torch.float64, device="cuda")
+    u = torch.empty_like(b)
+    with pytest.raises(GmgError) as e:
+        ctx.fft_solve(b, u)
+    assert e.value.status == 1  # GMG_E_ARG
+    c1 = _ctx(1, 8, 2)
+    b1 = torch.zeros(c1.num_dofs(), dtype=torch.float64, device="cuda")
+    with pytest.raises(GmgError):
+        c1.fft_solve(b1, b1)
