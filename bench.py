@@ -281,19 +281,19 @@ def sharp_layer_workload(alpha=40.0, radius=0.25, tops=(6, 7, 8), steps=3, tol=1
     return out
 
 
-def fft_workload(n=256, steps=5):
-    """Uniform Q1 on n^3 elements (n^3 DoFs), 32-Gaussian source (seed 0): the exact FFT solve
-    of the finite-element system against FP32 cycles in FP64 flexible CG to 1e-8, same load
-    vector (the paper's Table 7 comparison of FFT and GMG on a smooth, uniform problem)."""
+def fft_workload(n=256, steps=5, q=1):
+    """Uniform Q_q on n^3 elements ((q n)^3 DoFs), 32-Gaussian source (seed 0): the exact FFT
+    solve of the finite-element system against FP32 cycles in FP64 flexible CG to 1e-8, same
+    load vector (the paper's Table 7 comparison of FFT and GMG on a smooth, uniform problem)."""
     import torch
     from paper_1408_6497_amd import Context, GMG_FP32
     from workloads import gaussian_params, gaussian_source
-    ctx = Context(1, n, 0, seed=0, vcycle_prec=GMG_FP32)
+    ctx = Context(q, n, 0, seed=0, vcycle_prec=GMG_FP32)
     f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1), device="cuda")
     b = torch.empty_like(f)
     ctx.rhs(f, b)
     uf, ug = torch.empty_like(b), torch.empty_like(b)
-    out = {"workload": f"Q1, {n}^3 elements ({n}^3 DoFs), 32 Gaussians seed 0: FFT exact solve vs multigrid to 1e-8"}
+    out = {"workload": f"Q{q}, {n}^3 elements ({q * n}^3 DoFs), 32 Gaussians seed 0: FFT exact solve vs multigrid to 1e-8"}
     for name, call in (("fft", lambda: ctx.fft_solve(b, uf)), ("gmg_fp32_cycles", lambda: ctx.solve_rhs(b, ug, 1e-8))):
         call()
         torch.cuda.synchronize()
@@ -422,6 +422,7 @@ def main():
         extra["octree"] = octree_workload()
         extra["sharp_layer"] = sharp_layer_workload()
         extra["fft_q1"] = fft_workload()
+        extra["fft_q2"] = fft_workload(n=128, q=2)
 
     traffic = traffic_record()
     cpu = None

@@ -88,6 +88,20 @@ struct FftQ1 {
 };
 hipError_t fft_q1_prepare(FftQ1* f, int N);
 hipError_t fft_q1_solve(FftQ1* f, const double* b, double* u, hipStream_t s);
+// The same for uniform periodic Q2 on n^3 elements: 8 node classes, batched FFTs over the
+// elements and a 2x2-per-axis eigenbasis of the block symbol (tables on the device).
+struct FftQ2 {
+  int n = 0;
+  void* fwd = nullptr;
+  void* inv = nullptr;
+  bool fwd_ok = false, inv_ok = false;
+  void* spec = nullptr;  // 8 class spectra
+  void* cls = nullptr;   // 8 class arrays of n^3 values
+  void* axis = nullptr;  // per-wavenumber eigenbasis of one axis
+  ~FftQ2();
+};
+hipError_t fft_q2_prepare(FftQ2* f, int n);
+hipError_t fft_q2_solve(FftQ2* f, const double* b, double* u, hipStream_t s);
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 // Query (once per device) the occupancy that the launch shape of every apply

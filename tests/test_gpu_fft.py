@@ -1,4 +1,4 @@
-"""FFT solve of the uniform Q1 system (gmg_fft_solve) against the oracle.
+"""FFT solve of the uniform Q1 and Q2 systems (gmg_fft_solve) against the oracle.
 
 The oracle's assembled Kronecker operator checks the residual of the FFT solution (an
 exact solve: within rounding, 1e-12 relative); the C1 source has the closed-form discrete
@@ -21,12 +21,12 @@ def _ctx(q, n, levels=0, **kw):
     return Context(q, n, levels, **kw)
 
 
-@pytest.mark.parametrize("n", [8, 32])
-def test_fft_solve_residual_on_the_oracle_operator(n):
+@pytest.mark.parametrize("q,n", [(1, 8), (1, 32), (2, 4), (2, 16)])
+def test_fft_solve_residual_on_the_oracle_operator(q, n):
     torch = torch_cuda()
     from oracle import operator as op
-    ctx = _ctx(1, n, 2 if n == 8 else 0)
-    b = np.random.default_rng(11).standard_normal(n ** 3)
+    ctx = _ctx(q, n, 2 if q * n <= 8 else 0)
+    b = np.random.default_rng(11).standard_normal((q * n) ** 3)
     b -= b.mean()
     bd = to_dev(b, torch.float64)
     b0 = bd.clone()
@@ -34,11 +34,12 @@ def test_fft_solve_residual_on_the_oracle_operator(n):
     ctx.fft_solve(bd, u)
     torch.cuda.synchronize()
     uh = to_host(u)
-    A = op.assemble(1, n)
+    A = op.assemble(q, n)
     rel = np.linalg.norm(b - A @ uh) / np.linalg.norm(b)
-    print(f"[fft] n={n}: residual {rel:.2e}, mean {uh.mean():.1e}", flush=True)
+    print(f"[fft] q={q} n={n}: residual {rel:.2e}, mean {uh.mean():.1e}", flush=True)
     assert rel <= 1e-12
-    assert abs(uh.mean()) <= 1e-12 * np.abs(uh).max()
+    if q == 1:
+        assert abs(uh.mean()) <= 1e-12 * np.abs(uh).max()
     assert torch.equal(bd, b0)  # the load vector is left as it was
 
 
@@ -61,11 +62,13 @@ def test_fft_solve_c1_closed_form():
     assert err < 1e-12
 
 
-def test_fft_solve_matches_multigrid():
-    """The FFT solution and the multigrid solution of one load vector agree (128^3 Q1 nodes)."""
+@pytest.mark.parametrize("q,n", [(1, 128), (2, 64)])
+def test_fft_solve_matches_multigrid(q, n):
+    """The FFT solution and the multigrid solution of one load vector agree (128^3 nodes): both
+    take the zero-integral solution."""
     torch = torch_cuda()
     from workloads import gaussian_params, gaussian_source
-    ctx = _ctx(1, 128)
+    ctx = _ctx(q, n)
     f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1), device="cuda")
     b = torch.empty_like(f)
     ctx.rhs(f, b)
@@ -81,7 +84,7 @@ def test_fft_solve_matches_multigrid():
 def test_fft_solve_rejects_other_orders():
     torch = torch_cuda()
     from paper_1408_6497_amd import GmgError
-    ctx = _ctx(2, 8, 2)
+    ctx = _ctx(4, 4, 2)
     b = torch.zeros(ctx.num_dofs(), dtype=torch.float64, device="cuda")
     u = torch.empty_like(b)
     with pytest.raises(GmgError) as e:
