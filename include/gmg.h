@@ -204,20 +204,20 @@ gmg_status gmg_solve(gmg_ctx* ctx, const double* f_dev, double* u_dev, double rt
 gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, double rtol, gmg_info* info);
 
 /* Exact solve of the same finite-element system by the 3D FFT (the FFT Poisson method of
- * Section 2, Table 7's uniform-grid baseline), for uniform Q1 and Q2 meshes.  Q1: on a
+ * Section 2, Table 7's uniform-grid baseline), for uniform meshes of every order.  Q1: on a
  * periodic mesh the Q1 matrix is diagonal in the Fourier basis, with eigenvalue
  *   kap(kx) mu(ky) mu(kz) + mu(kx) kap(ky) mu(kz) + mu(kx) mu(ky) kap(kz),
  *   kap(k) = (2 - 2 cos(2 pi k/N)) / h,  mu(k) = h (4 + 2 cos(2 pi k/N)) / 6,
  * so u = F^-1 [F(b) / eigenvalue] with the constant mode set to zero (the zero-integral
- * solution).  Q2: the 8 node classes make the matrix block-circulant over the elements;
- * per wavenumber the 8x8 symbol is the Kronecker sum of the 1D 2x2 symbols, inverted in
- * the eigenbasis of each axis's 2x2 pencil (K, M), with the constant mode (the integral)
- * set to zero.  b_dev: the load vector (as for gmg_solve_rhs, mean zero), u_dev: the
+ * solution).  Q2, Q4: the q^3 node classes make the matrix block-circulant over the
+ * elements; per wavenumber the q^3 x q^3 symbol is the Kronecker sum of the 1D q x q
+ * symbols, inverted in the eigenbasis of each axis's q x q pencil (K, M), with the
+ * constant mode (the integral) set to zero.  b_dev: the load vector (as for gmg_solve_rhs, mean zero), u_dev: the
  * solution, both FP64 device arrays of gmg_num_dofs values in lattice order, not
  * aliased; b_dev is not modified.  FP64 transforms (hipFFT).  The first call allocates
  * the transform plans and a spectrum buffer of N^2 (N/2+1) complex values, kept until
- * gmg_destroy (Q2: 8 class spectra and 8 class arrays).  GMG_E_ARG on octree or q = 4
- * contexts and on aliasing. */
+ * gmg_destroy (Q2, Q4: q^3 class spectra and class arrays).  GMG_E_ARG on octree contexts
+ * and on aliasing. */
 gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev);
 
 /* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */

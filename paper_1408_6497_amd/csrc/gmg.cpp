@@ -107,6 +107,7 @@ struct gmg_ctx {
   hipEvent_t ev_copy = nullptr;  // marks the end of a read-back that later work overlaps
   std::unique_ptr<FftQ1> fft;    // plans and spectra of gmg_fft_solve (made on first use)
   std::unique_ptr<FftQ2> fft2;
+  std::unique_ptr<FftQ4> fft4;
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // bracket each solve (gmg_info.t_solve)
   double* part = nullptr;
   int64_t part_cap = 0;
@@ -1515,7 +1516,7 @@ gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev) {
   if (static_cast<const void*>(b_dev) == static_cast<const void*>(u_dev))
     return fail(ctx, GMG_E_ARG, "FFT solve: b and u must not alias");
   const Level& F = ctx->lv.back();
-  if (F.oct || (ctx->q != 1 && ctx->q != 2)) return fail(ctx, GMG_E_ARG, "FFT solve: uniform Q1 and Q2 meshes only");
+  if (F.oct) return fail(ctx, GMG_E_ARG, "FFT solve: uniform meshes only");
   if (ctx->q == 1) {
     if (!ctx->fft) ctx->fft.reset(new FftQ1());
     return scoped(ctx, [&]() -> gmg_status {
@@ -1524,10 +1525,18 @@ gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev) {
       return GMG_OK;
     });
   }
-  if (!ctx->fft2) ctx->fft2.reset(new FftQ2());
+  if (ctx->q == 2) {
+    if (!ctx->fft2) ctx->fft2.reset(new FftQ2());
+    return scoped(ctx, [&]() -> gmg_status {
+      HIPCHK(ctx, fft_q2_prepare(ctx->fft2.get(), F.n));
+      HIPCHK(ctx, fft_q2_solve(ctx->fft2.get(), b_dev, u_dev, ctx->stream));
+      return GMG_OK;
+    });
+  }
+  if (!ctx->fft4) ctx->fft4.reset(new FftQ4());
   return scoped(ctx, [&]() -> gmg_status {
-    HIPCHK(ctx, fft_q2_prepare(ctx->fft2.get(), F.n));
-    HIPCHK(ctx, fft_q2_solve(ctx->fft2.get(), b_dev, u_dev, ctx->stream));
+    HIPCHK(ctx, fft_q4_prepare(ctx->fft4.get(), F.n));
+    HIPCHK(ctx, fft_q4_solve(ctx->fft4.get(), b_dev, u_dev, ctx->stream));
     return GMG_OK;
   });
 }

@@ -15,9 +15,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "gmg_kernels.h"
+#include "gmg_setup_math.h"
 
 namespace gmg {
 namespace {
@@ -332,6 +334,319 @@ hipError_t fft_q2_solve(FftQ2* f, const double* b, double* u, hipStream_t s) {
     return hipErrorUnknown;
   hipLaunchKernelGGL(k_merge_classes, dim3(static_cast<unsigned>(g)), dim3(kFftBlock), 0, s,
                      static_cast<const double*>(f->cls), u, n);
+  return hipGetLastError();
+}
+
+}  // namespace gmg
+
+// ---------------------------------------------------------------------------------------
+// Q4: the same construction with 4 node classes per axis (64 per element cell) and 4x4
+// pencils, whose M-orthonormal eigenbases come from a Cholesky factor of M and a Jacobi
+// eigen-decomposition of L^-1 K L^-H (through its real symmetric 2q x 2q embedding).
+namespace gmg {
+namespace {
+
+template <int Q>
+struct AxisQ {
+  double vr[Q][Q], vi[Q][Q];  // V (rows: class, columns: mode)
+  double lam[Q];
+};
+
+template <int Q>
+__global__ void __launch_bounds__(kFftBlock) k_split_q(const double* __restrict__ b, double* __restrict__ bc, const int n,
+                                                       const int merge) {
+  constexpr int NC = Q * Q * Q;
+  const int N = Q * n;
+  const int64_t n3 = static_cast<int64_t>(n) * n * n;
+  const double norm = 1.0 / static_cast<double>(n3);
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < NC * n3;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int c = static_cast<int>(t / n3);
+    const int64_t e = t - c * n3;
+    const int ex = static_cast<int>(e % n), ey = static_cast<int>((e / n) % n), ez = static_cast<int>(e / (int64_t(n) * n));
+    const int i = Q * ex + c % Q, j = Q * ey + (c / Q) % Q, k = Q * ez + c / (Q * Q);
+    const int64_t idx = (static_cast<int64_t>(k) * N + j) * N + i;
+    if (merge) const_cast<double*>(b)[idx] = bc[t] * norm;
+    else bc[t] = b[idx];
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void axis_apply_q(const AxisQ<Q>& a, bool herm, int stride, double (&xr)[Q * Q * Q],
+                                             double (&xi)[Q * Q * Q]) {
+  constexpr int NC = Q * Q * Q;
+#pragma unroll
+  for (int base = 0; base < NC; ++base) {
+    if ((base / stride) % Q != 0) continue;
+    double yr[Q], yi[Q];
+#pragma unroll
+    for (int o = 0; o < Q; ++o) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        const double ar = herm ? a.vr[m][o] : a.vr[o][m];
+        const double ai = herm ? -a.vi[m][o] : a.vi[o][m];
+        const double xrr = xr[base + m * stride], xii = xi[base + m * stride];
+        sr += ar * xrr - ai * xii;
+        si += ar * xii + ai * xrr;
+      }
+      yr[o] = sr;
+      yi[o] = si;
+    }
+#pragma unroll
+    for (int o = 0; o < Q; ++o) {
+      xr[base + o * stride] = yr[o];
+      xi[base + o * stride] = yi[o];
+    }
+  }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(kFftBlock) k_fft_solve_q(hipfftDoubleComplex* spec, const AxisQ<Q>* __restrict__ ax,
+                                                           const int n) {
+  constexpr int NC = Q * Q * Q;
+  const int NX = n / 2 + 1;
+  const int64_t m = static_cast<int64_t>(n) * n * NX;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < m;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int kx = static_cast<int>(t % NX);
+    const int ky = static_cast<int>((t / NX) % n);
+    const int kz = static_cast<int>(t / (static_cast<int64_t>(NX) * n));
+    double xr[NC], xi[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      xr[c] = spec[c * m + t].x;
+      xi[c] = spec[c * m + t].y;
+    }
+    axis_apply_q<Q>(ax[kx], true, 1, xr, xi);
+    axis_apply_q<Q>(ax[ky], true, Q, xr, xi);
+    axis_apply_q<Q>(ax[kz], true, Q * Q, xr, xi);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double lam = ax[kx].lam[c % Q] + ax[ky].lam[(c / Q) % Q] + ax[kz].lam[c / (Q * Q)];
+      const double s = lam > 0.0 ? 1.0 / lam : 0.0;  // the constant mode: 0
+      xr[c] *= s;
+      xi[c] *= s;
+    }
+    axis_apply_q<Q>(ax[kz], false, Q * Q, xr, xi);
+    axis_apply_q<Q>(ax[ky], false, Q, xr, xi);
+    axis_apply_q<Q>(ax[kx], false, 1, xr, xi);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      spec[c * m + t].x = xr[c];
+      spec[c * m + t].y = xi[c];
+    }
+  }
+}
+
+// Eigen-decomposition of a real symmetric matrix (cyclic Jacobi), ascending eigenvalues,
+// eigenvectors as the columns of v (row-major, dimension d).
+void jacobi_eigen(int d, std::vector<double> a, std::vector<double>* w, std::vector<double>* v) {
+  v->assign(static_cast<size_t>(d) * d, 0.0);
+  for (int i = 0; i < d; ++i) (*v)[i * d + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        tot += a[i * d + j] * a[i * d + j];
+        if (i != j) off += a[i * d + j] * a[i * d + j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < d; ++p)
+      for (int r = p + 1; r < d; ++r) {
+        const double apr = a[p * d + r];
+        if (std::fabs(apr) < 1e-300) continue;
+        const double theta = (a[r * d + r] - a[p * d + p]) / (2.0 * apr);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < d; ++k) {  // columns p, r
+          const double akp = a[k * d + p], akr = a[k * d + r];
+          a[k * d + p] = c * akp - s * akr;
+          a[k * d + r] = s * akp + c * akr;
+        }
+        for (int k = 0; k < d; ++k) {  // rows p, r
+          const double apk = a[p * d + k], ark = a[r * d + k];
+          a[p * d + k] = c * apk - s * ark;
+          a[r * d + k] = s * apk + c * ark;
+        }
+        for (int k = 0; k < d; ++k) {
+          const double vkp = (*v)[k * d + p], vkr = (*v)[k * d + r];
+          (*v)[k * d + p] = c * vkp - s * vkr;
+          (*v)[k * d + r] = s * vkp + c * vkr;
+        }
+      }
+  }
+  std::vector<int> ord(d);
+  for (int i = 0; i < d; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return a[x * d + x] < a[y * d + y]; });
+  std::vector<double> vs(static_cast<size_t>(d) * d);
+  w->resize(d);
+  for (int j = 0; j < d; ++j) {
+    (*w)[j] = a[ord[j] * d + ord[j]];
+    for (int k = 0; k < d; ++k) vs[k * d + j] = (*v)[k * d + ord[j]];
+  }
+  *v = vs;
+}
+
+template <int Q>
+void axis_tables_q(int n, std::vector<AxisQ<Q>>* out) {
+  using C = std::complex<double>;
+  std::vector<double> khat, mhat;
+  reference_matrices(Q, &khat, &mhat);
+  const int p = Q + 1;
+  const double h = 1.0 / n;
+  out->resize(n);
+  for (int k = 0; k < n; ++k) {
+    const C ph = std::polar(1.0, 2.0 * M_PI * k / n);
+    // S = P^H E P, P: class a -> local node a (a < q), and local node q = e^{it} class 0
+    auto sym = [&](const std::vector<double>& E, double sc, C (&S)[Q][Q]) {
+      for (int a = 0; a < Q; ++a)
+        for (int b = 0; b < Q; ++b) {
+          C s = E[a * p + b];
+          if (a == 0) s += std::conj(ph) * E[Q * p + b];
+          if (b == 0) s += E[a * p + Q] * ph;
+          if (a == 0 && b == 0) s += E[Q * p + Q];
+          S[a][b] = sc * s;
+        }
+    };
+    C K[Q][Q], M[Q][Q], L[Q][Q] = {}, Li[Q][Q] = {};
+    sym(khat, 1.0 / h, K);
+    sym(mhat, h, M);
+    for (int j = 0; j < Q; ++j) {  // Cholesky M = L L^H
+      C s = M[j][j];
+      for (int t = 0; t < j; ++t) s -= L[j][t] * std::conj(L[j][t]);
+      L[j][j] = std::sqrt(s.real());
+      for (int i = j + 1; i < Q; ++i) {
+        C u = M[i][j];
+        for (int t = 0; t < j; ++t) u -= L[i][t] * std::conj(L[j][t]);
+        L[i][j] = u / L[j][j];
+      }
+    }
+    for (int j = 0; j < Q; ++j) {  // L^-1 by forward substitution
+      Li[j][j] = 1.0 / L[j][j];
+      for (int i = j + 1; i < Q; ++i) {
+        C s = 0.0;
+        for (int t = j; t < i; ++t) s += L[i][t] * Li[t][j];
+        Li[i][j] = -s / L[i][i];
+      }
+    }
+    C Cm[Q][Q];  // L^-1 K L^-H
+    for (int i = 0; i < Q; ++i)
+      for (int j = 0; j < Q; ++j) {
+        C s = 0.0;
+        for (int a = 0; a < Q; ++a)
+          for (int b = 0; b < Q; ++b) s += Li[i][a] * K[a][b] * std::conj(Li[j][b]);
+        Cm[i][j] = s;
+      }
+    // real symmetric embedding [[Re, -Im], [Im, Re]]: every eigenvalue twice
+    const int d = 2 * Q;
+    std::vector<double> R(static_cast<size_t>(d) * d), w, v;
+    for (int i = 0; i < Q; ++i)
+      for (int j = 0; j < Q; ++j) {
+        R[i * d + j] = Cm[i][j].real();
+        R[i * d + Q + j] = -Cm[i][j].imag();
+        R[(Q + i) * d + j] = Cm[i][j].imag();
+        R[(Q + i) * d + Q + j] = Cm[i][j].real();
+      }
+    jacobi_eigen(d, R, &w, &v);
+    // complex eigenvectors z = y_re + i y_im from the real ones, kept when independent of
+    // those already taken (Gram-Schmidt), in ascending eigenvalue order
+    std::vector<std::vector<C>> Z;
+    std::vector<double> lam;
+    for (int j = 0; j < d && static_cast<int>(Z.size()) < Q; ++j) {
+      std::vector<C> z(Q);
+      for (int i = 0; i < Q; ++i) z[i] = C(v[i * d + j], v[(Q + i) * d + j]);
+      for (const auto& y : Z) {
+        C dot = 0.0;
+        for (int i = 0; i < Q; ++i) dot += std::conj(y[i]) * z[i];
+        for (int i = 0; i < Q; ++i) z[i] -= dot * y[i];
+      }
+      double nn = 0.0;
+      for (int i = 0; i < Q; ++i) nn += std::norm(z[i]);
+      if (nn < 1e-12) continue;
+      for (int i = 0; i < Q; ++i) z[i] /= std::sqrt(nn);
+      Z.push_back(z);
+      lam.push_back(w[j]);
+    }
+    AxisQ<Q>& A = (*out)[k];
+    for (int o = 0; o < Q; ++o) {
+      A.lam[o] = o < static_cast<int>(lam.size()) ? lam[o] : 0.0;
+      for (int r = 0; r < Q; ++r) {  // V = L^-H Z: (L^-H)[r][i] = conj(Li[i][r])
+        C s = 0.0;
+        if (o < static_cast<int>(Z.size()))
+          for (int i = 0; i < Q; ++i) s += std::conj(Li[i][r]) * Z[o][i];
+        A.vr[r][o] = s.real();
+        A.vi[r][o] = s.imag();
+      }
+    }
+    if (k == 0) A.lam[0] = 0.0;  // the constant is exactly in the kernel of K at t = 0
+  }
+}
+
+}  // namespace
+
+FftQ4::~FftQ4() {
+  if (fwd_ok) (void)hipfftDestroy(fft_handle(fwd));
+  if (inv_ok) (void)hipfftDestroy(fft_handle(inv));
+  if (spec) (void)hipFree(spec);
+  if (cls) (void)hipFree(cls);
+  if (axis) (void)hipFree(axis);
+}
+
+hipError_t fft_q4_prepare(FftQ4* f, int n) {
+  if (f->n == n && f->fwd_ok && f->inv_ok && f->spec) return hipSuccess;
+  if (n < 2) return hipErrorInvalidValue;
+  constexpr int NC = 64;
+  const size_t n3 = static_cast<size_t>(n) * n * n;
+  const size_t m = static_cast<size_t>(n) * n * (n / 2 + 1);
+  if (hipMalloc(&f->spec, sizeof(hipfftDoubleComplex) * NC * m) != hipSuccess) return hipErrorOutOfMemory;
+  if (hipMalloc(&f->cls, sizeof(double) * NC * n3) != hipSuccess) return hipErrorOutOfMemory;
+  std::vector<AxisQ<4>> tab;
+  axis_tables_q<4>(n, &tab);
+  if (hipMalloc(&f->axis, sizeof(AxisQ<4>) * n) != hipSuccess) return hipErrorOutOfMemory;
+  if (hipMemcpy(f->axis, tab.data(), sizeof(AxisQ<4>) * n, hipMemcpyHostToDevice) != hipSuccess) return hipErrorUnknown;
+  int dims[3] = {n, n, n};
+  hipfftHandle h = nullptr;
+  if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(n3), nullptr, 1, static_cast<int>(m), HIPFFT_D2Z, NC) !=
+      HIPFFT_SUCCESS)
+    return hipErrorUnknown;
+  f->fwd = h;
+  f->fwd_ok = true;
+  if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(m), nullptr, 1, static_cast<int>(n3), HIPFFT_Z2D, NC) !=
+      HIPFFT_SUCCESS)
+    return hipErrorUnknown;
+  f->inv = h;
+  f->inv_ok = true;
+  f->n = n;
+  return hipSuccess;
+}
+
+hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s) {
+  const int n = f->n;
+  const int64_t total = 64 * static_cast<int64_t>(n) * n * n;
+  int64_t g = (total + kFftBlock - 1) / kFftBlock;
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_split_q<4>, dim3(static_cast<unsigned>(g)), dim3(kFftBlock), 0, s, b,
+                     static_cast<double*>(f->cls), n, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (hipfftSetStream(fft_handle(f->fwd), s) != HIPFFT_SUCCESS || hipfftSetStream(fft_handle(f->inv), s) != HIPFFT_SUCCESS)
+    return hipErrorUnknown;
+  if (hipfftExecD2Z(fft_handle(f->fwd), static_cast<double*>(f->cls), static_cast<hipfftDoubleComplex*>(f->spec)) !=
+      HIPFFT_SUCCESS)
+    return hipErrorUnknown;
+  const int64_t m = static_cast<int64_t>(n) * n * (n / 2 + 1);
+  int64_t g2 = (m + kFftBlock - 1) / kFftBlock;
+  if (g2 > 65535) g2 = 65535;
+  hipLaunchKernelGGL(k_fft_solve_q<4>, dim3(static_cast<unsigned>(g2)), dim3(kFftBlock), 0, s,
+                     static_cast<hipfftDoubleComplex*>(f->spec), static_cast<const AxisQ<4>*>(f->axis), n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (hipfftExecZ2D(fft_handle(f->inv), static_cast<hipfftDoubleComplex*>(f->spec), static_cast<double*>(f->cls)) !=
+      HIPFFT_SUCCESS)
+    return hipErrorUnknown;
+  hipLaunchKernelGGL(k_split_q<4>, dim3(static_cast<unsigned>(g)), dim3(kFftBlock), 0, s, u,
+                     static_cast<double*>(f->cls), n, 1);
   return hipGetLastError();
 }
 

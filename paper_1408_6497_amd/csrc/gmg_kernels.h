@@ -102,6 +102,19 @@ struct FftQ2 {
 };
 hipError_t fft_q2_prepare(FftQ2* f, int n);
 hipError_t fft_q2_solve(FftQ2* f, const double* b, double* u, hipStream_t s);
+// Q4: 64 node classes, 4x4 pencils per axis (same members as FftQ2)
+struct FftQ4 {
+  int n = 0;
+  void* fwd = nullptr;
+  void* inv = nullptr;
+  bool fwd_ok = false, inv_ok = false;
+  void* spec = nullptr;
+  void* cls = nullptr;
+  void* axis = nullptr;
+  ~FftQ4();
+};
+hipError_t fft_q4_prepare(FftQ4* f, int n);
+hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s);
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 // Query (once per device) the occupancy that the launch shape of every apply

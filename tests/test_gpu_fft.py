@@ -1,4 +1,4 @@
-"""FFT solve of the uniform Q1 and Q2 systems (gmg_fft_solve) against the oracle.
+"""FFT solve of the uniform Q1, Q2 and Q4 systems (gmg_fft_solve) against the oracle.
 
 The oracle's assembled Kronecker operator checks the residual of the FFT solution (an
 exact solve: within rounding, 1e-12 relative); the C1 source has the closed-form discrete
@@ -21,7 +21,7 @@ def _ctx(q, n, levels=0, **kw):
     return Context(q, n, levels, **kw)
 
 
-@pytest.mark.parametrize("q,n", [(1, 8), (1, 32), (2, 4), (2, 16)])
+@pytest.mark.parametrize("q,n", [(1, 8), (1, 32), (2, 4), (2, 16), (4, 4)])
 def test_fft_solve_residual_on_the_oracle_operator(q, n):
     torch = torch_cuda()
     from oracle import operator as op
@@ -62,7 +62,7 @@ def test_fft_solve_c1_closed_form():
     assert err < 1e-12
 
 
-@pytest.mark.parametrize("q,n", [(1, 128), (2, 64)])
+@pytest.mark.parametrize("q,n", [(1, 128), (2, 64), (4, 32)])
 def test_fft_solve_matches_multigrid(q, n):
     """The FFT solution and the multigrid solution of one load vector agree (128^3 nodes): both
     take the zero-integral solution."""
@@ -81,10 +81,14 @@ def test_fft_solve_matches_multigrid(q, n):
     assert d <= 1e-7
 
 
-def test_fft_solve_rejects_other_orders():
+def test_fft_solve_rejects_octrees_and_aliasing():
     torch = torch_cuda()
-    from paper_1408_6497_amd import GmgError
-    ctx = _ctx(4, 4, 2)
+    from oracle import octree as ot
+    from paper_1408_6497_amd import Context, GmgError
+    tree = ot.uniform(2)
+    keys = np.array([ot.morton(o[1], o[2], o[3]) for o in tree], dtype=np.uint64)
+    lev = np.array([o[0] for o in tree], dtype=np.uint8)
+    ctx = Context(2, 0, leaves=(keys, lev))
     b = torch.zeros(ctx.num_dofs(), dtype=torch.float64, device="cuda")
     u = torch.empty_like(b)
     with pytest.raises(GmgError) as e:
