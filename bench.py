@@ -423,6 +423,7 @@ def main():
         extra["sharp_layer"] = sharp_layer_workload()
         extra["fft_q1"] = fft_workload()
         extra["fft_q2"] = fft_workload(n=128, q=2)
+        extra["fft_q4"] = fft_workload(n=64, q=4)
 
     traffic = traffic_record()
     cpu = None
