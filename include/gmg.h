@@ -194,6 +194,25 @@ gmg_status gmg_vcycle(gmg_ctx* ctx, gmg_prec prec, const void* r_dev, void* z_de
 /* r = b - A_level u (vectors of type prec). */
 gmg_status gmg_residual(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, const void* u_dev, void* r_dev);
 
+/* u = S^nu (0; b): nu applications of the level smoother from a zero initial guess,
+ * the pre-smoothing of Algorithm 2.1 (Section 2.3.3).  u_dev need not be initialized
+ * and must not alias b_dev.  On uniform levels with a Chebyshev smoother the first
+ * two steps run as one pass that forms x_1 = D^-1 b / theta as it loads b. */
+gmg_status gmg_smooth_zero(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, void* u_dev, int32_t nu);
+
+/* Launch shape of one operation on a level (a tracing aid: which kernel instance the
+ * calls above launch there).  op: 0 y = A x, 1 r = b - A x, 2 smoother step, 3 the
+ * fused first two smoother steps from a zero guess, 4 restriction onto level-1,
+ * 5 prolongation from level-1.  shape_host[0..3] (host, 4 values):
+ *   [0] kernel: 0 point kernel (one thread per element column, levels of N <= 32
+ *       nodes), 1 streaming column kernel, 2 column kernel that loads all planes of its
+ *       one-layer z chunk at once, 3 one-pass (fused) transfer, 4 three one-axis
+ *       transfer passes, 5 octree kernels;
+ *   [1] G (a tile is 4G lattice rows), [2] TZ (element layers per block; 0 for the
+ *   point kernel), [3] blocks per launch (0 for transfers and octree levels).
+ * GMG_E_ARG for an invalid level or op (restriction and prolongation need level >= 1). */
+gmg_status gmg_launch_shape(const gmg_ctx* ctx, int32_t level, gmg_prec prec, int32_t op, int32_t* shape_host);
+
 /* b = M f - mean(M f): load vector of nodal source values f on the finest level. */
 gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev);
 

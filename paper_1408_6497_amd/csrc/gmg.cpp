@@ -2028,6 +2028,40 @@ gmg_status gmg_residual(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* 
   return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Residual, u_dev, r_dev, b_dev, nullptr, 0, 0); });
 }
 
+gmg_status gmg_smooth_zero(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, void* u_dev, int32_t nu) {
+  if (!ctx || !b_dev || !u_dev || b_dev == u_dev || nu < 0 || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  const int pi = pidx(prec);
+  STCHK(ensure_prec(ctx, pi));
+  return scoped(ctx, [&] { return smooth(ctx, level, pi, b_dev, u_dev, nu, true); });
+}
+
+gmg_status gmg_launch_shape(const gmg_ctx* ctx, int32_t level, gmg_prec prec, int32_t op, int32_t* shape_host) {
+  if (!ctx || !shape_host || check_level(ctx, level) != GMG_OK || op < 0 || op > 5) return GMG_E_ARG;
+  const Level& L = ctx->lv[level];
+  const bool f32 = prec == GMG_FP32;
+  for (int i = 0; i < 4; ++i) shape_host[i] = 0;
+  if (L.oct) {
+    shape_host[0] = 5;
+    return GMG_OK;
+  }
+  if (op >= 4) {
+    if (level < 1) return GMG_E_ARG;
+    const int Nc = ctx->lv[level - 1].N;
+    const bool fused = !ctx->opt.no_fused_transfer &&
+                       (op == 4 ? restrict_fusable(ctx->q, Nc) : prolong_fusable(ctx->q, Nc));
+    shape_host[0] = fused ? 3 : 4;
+    return GMG_OK;
+  }
+  static const Epi epis[4] = {Epi::Apply, Epi::Residual, Epi::Cheb, Epi::ChebZero};
+  const ApplyShape sh = apply_shape(ctx->q, f32, epis[op], L.N, L.n);
+  if (sh.kernel < 0) return GMG_E_ARG;
+  shape_host[0] = sh.kernel;
+  shape_host[1] = sh.G;
+  shape_host[2] = sh.TZ;
+  shape_host[3] = sh.nblocks;
+  return GMG_OK;
+}
+
 gmg_status gmg_net_loss_grad(gmg_ctx* ctx, int32_t depth, int32_t kind, const float* r_dev, const float* e_dev,
                              void* cache_dev, float* gw_dev, float scale, double* loss_host) {
   if (!r_dev || !cache_dev || !loss_host || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])

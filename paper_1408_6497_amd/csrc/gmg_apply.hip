@@ -753,6 +753,52 @@ void prime_te(int N) {
   }
 }
 
+// The shape launch_te takes for one instance (a query for tests and tracing).
+template <typename T, int Q, int EPI>
+ApplyShape shape_te(int N, int n) {
+  ApplyShape out{};
+  if (N <= 32) {
+    out.kernel = 0;
+    constexpr int KZ = Q >= 2 ? 2 * Q + 1 : 1;
+    constexpr int cols = KZ == 1 ? 128 : 64;
+    out.G = 1;
+    out.TZ = 0;
+    out.nblocks = static_cast<int>((static_cast<int64_t>(N / Q) * N * N + cols - 1) / cols);
+    return out;
+  }
+  ColShape sh = col_shape(N, Q, sizeof(T), col_rows<T, Q, EPI>());
+  const int threads = (N / Q) * sh.G;
+  int resident = 1;
+  switch (sh.G) {
+    case 1: resident = resident_blocks<T, Q, 1, EPI>(threads, sh.lds); break;
+    case 2: resident = resident_blocks<T, Q, 2, EPI>(threads, sh.lds); break;
+    case 4: resident = resident_blocks<T, Q, 4, EPI>(threads, sh.lds); break;
+  }
+  const int64_t tiles = static_cast<int64_t>(sh.ntiles_y) * sh.split;
+  out.TZ = pick_tz(n, tiles, resident);
+  out.G = sh.G;
+  out.nblocks = static_cast<int>(tiles * (n / out.TZ));
+  out.kernel = (pre_ok<T, Q, EPI>() && out.TZ == 1) ? 2 : 1;
+  return out;
+}
+
+template <typename T, int Q>
+ApplyShape shape_tq(Epi epi, int N, int n) {
+  switch (epi) {
+    case Epi::Apply: return shape_te<T, Q, 0>(N, n);
+    case Epi::Residual: return shape_te<T, Q, 1>(N, n);
+    case Epi::Cheb: return shape_te<T, Q, 2>(N, n);
+    case Epi::ChebZero: return shape_te<T, Q, kEpiZero>(N, n);
+    case Epi::ApplyDot:
+      if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiDot>(N, n);
+      break;
+    case Epi::ResidualSums:
+      if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiResSums>(N, n);
+      break;
+  }
+  return ApplyShape{-1, 0, 0, 0};
+}
+
 template <typename T, int Q>
 void prime_tq(int N) {
   prime_te<T, Q, 0>(N);
@@ -794,6 +840,16 @@ void prime_apply_shapes(int q, int N) {
     case 2: prime_tq<float, 2>(N); prime_tq<double, 2>(N); break;
     case 4: prime_tq<float, 4>(N); prime_tq<double, 4>(N); break;
   }
+}
+
+ApplyShape apply_shape(int q, bool fp32, Epi epi, int N, int n) {
+  if (N != q * n || N < 4 || (N & (N - 1)) != 0 || n > apply_max_elements_x(q)) return ApplyShape{-1, 0, 0, 0};
+  switch (q) {
+    case 1: return fp32 ? shape_tq<float, 1>(epi, N, n) : shape_tq<double, 1>(epi, N, n);
+    case 2: return fp32 ? shape_tq<float, 2>(epi, N, n) : shape_tq<double, 2>(epi, N, n);
+    case 4: return fp32 ? shape_tq<float, 4>(epi, N, n) : shape_tq<double, 4>(epi, N, n);
+  }
+  return ApplyShape{-1, 0, 0, 0};
 }
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s) {

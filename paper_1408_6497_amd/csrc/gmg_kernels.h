@@ -117,6 +117,15 @@ hipError_t fft_q4_prepare(FftQ4* f, int n);
 hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s);
 
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
+// The launch shape launch_apply takes on a uniform level: kernel 0 = the point kernel
+// (N <= 32), 1 = the streaming column kernel, 2 = the column kernel that loads all the
+// planes of its one-layer z chunk at once; G (4G rows per tile), TZ (element layers per
+// block, 0 for the point kernel) and the block count.  kernel = -1 for an unsupported
+// combination.
+struct ApplyShape {
+  int kernel, G, TZ, nblocks;
+};
+ApplyShape apply_shape(int q, bool fp32, Epi epi, int N, int n);
 // Query (once per device) the occupancy that the launch shape of every apply
 // kernel instance for a level of N nodes a side depends on; call before any
 // launch sequence is captured into a graph.
@@ -186,6 +195,8 @@ hipError_t launch_restrict(const TransferTab& tab, bool fp32, const void* rf, vo
 // restriction onto those of 64 <= Nc <= 256; prime_transfer_shapes queries their
 // occupancy once per level size, before any graph capture
 void prime_transfer_shapes(int q, int Nc);
+bool prolong_fusable(int q, int Nc);
+bool restrict_fusable(int q, int Nc);
 
 // out = c * tab[class(i)] * in  (class table of length q^3; in may be null -> 1)
 hipError_t launch_class_scale(bool fp32, int q, int N, const double* tab, double c, const void* in, void* out,

@@ -27,7 +27,7 @@ EXPORTS = [
     "gmg_net_set_weights", "gmg_set_learned", "gmg_net_get_weights", "gmg_net_cache_bytes", "gmg_net_forward",
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
     "gmg_octree_refine_gaussians", "gmg_octree_refine_sharp_layer", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
-    "gmg_net_get_state", "gmg_net_set_state",
+    "gmg_net_get_state", "gmg_net_set_state", "gmg_smooth_zero", "gmg_launch_shape",
 ]
 
 NET_WEIGHTS = 7776
@@ -126,6 +126,8 @@ def load():
         "gmg_net_correction": [P, I32, P, P],
         "gmg_net_loss_grad": [P, I32, I32, P, P, P, P, ctypes.c_float, ctypes.POINTER(D)],
         "gmg_residual": [P, I32, I32, P, P, P],
+        "gmg_smooth_zero": [P, I32, I32, P, P, I32],
+        "gmg_launch_shape": [P, I32, I32, I32, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -284,6 +286,23 @@ class Context:
         level = self._lvl(level)
         p = self.prec_of(b)
         self._check(self.lib.gmg_smooth(self.h, level, p, self._vec(b, level, p), self._vec(u, level, p), nu))
+
+    def smooth_zero(self, level, b, u, nu):
+        """u = S^nu(0; b): the smoother from a zero initial guess (u is not read)."""
+        level = self._lvl(level)
+        p = self.prec_of(b)
+        self._check(self.lib.gmg_smooth_zero(self.h, level, p, self._vec(b, level, p), self._vec(u, level, p), nu))
+
+    SHAPE_OPS = {"apply": 0, "residual": 1, "smooth": 2, "smooth_zero": 3, "restrict": 4, "prolong": 5}
+    SHAPE_KERNELS = {0: "point", 1: "column", 2: "column_preload", 3: "transfer_fused", 4: "transfer_axis",
+                     5: "octree"}
+
+    def launch_shape(self, level, prec, op):
+        """(kernel name, G, TZ, blocks) of the launch an operation takes on a level."""
+        level = self._lvl(level)
+        out = (ctypes.c_int32 * 4)()
+        self._check(self.lib.gmg_launch_shape(self.h, level, prec, self.SHAPE_OPS[op], out))
+        return self.SHAPE_KERNELS[out[0]], out[1], out[2], out[3]
 
     def restrict(self, level, rf, rc):
         level = self._lvl(level)

@@ -75,3 +75,29 @@ def test_learned_solve_full_size():
     print(f"[full] learned 512^3: iters {info.inner_iters} fallbacks {info.fallbacks} "
           f"gpu {info.rel_residual_f64:.2e} oracle {rel:.2e}", flush=True)
     assert rel <= 1e-8 * 1.001
+
+
+def test_nested_refinement_solve_full_size():
+    """ir_mode = 1 (FP64 residual and update around FP32 flexible CG solves) on the Q2 128^3-element
+    Gaussian workload, to 1e-8 on the oracle's operator, with its outer and inner counts."""
+    torch = torch_cuda()
+    from paper_1408_6497_amd import Context, GMG_FP32
+    from workloads import gaussian_params, gaussian_source
+    q, n = 2, 128
+    ctx = Context(q, n, 0, seed=0, vcycle_prec=GMG_FP32, ir_mode=1)
+    f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1), device="cuda")
+    u = torch.empty_like(f)
+    info = ctx.solve(f, u, 1e-8)
+    torch.cuda.synchronize()
+    rel = _oracle_rel_residual(q, n, to_host(f), to_host(u))
+    print(f"[full] nested refinement: outer {info.outer_iters} inner {info.inner_iters} "
+          f"gpu {info.rel_residual_f64:.2e} oracle {rel:.2e}", flush=True)
+    assert rel <= 1e-8 * 1.001
+    assert info.outer_iters >= 2 and info.inner_iters > info.outer_iters
+    # the distance to the default flexible-CG form's solution
+    ctx0 = Context(q, n, 0, seed=0, vcycle_prec=GMG_FP32)
+    u0 = torch.empty_like(f)
+    ctx0.solve(f, u0, 1e-8)
+    torch.cuda.synchronize()
+    d = float((u - u0).norm() / u0.norm())
+    print(f"  distance to the ir_mode 0 solution {d:.2e} (reported; bounded by kappa x tol)", flush=True)
