@@ -24,6 +24,7 @@ rng        SplitMix64 counter generator (the one random draw of the setup).
 learned    3-layer convolutional smoother: forward, backward, loss.
 octree     2:1-balanced periodic octree, hanging-node constraints, CSR assembly
            (Section 2.3.1).
+spectral   The FFT Poisson method of Section 2.1 on a uniform grid (numpy FFT).
 
 Parity status of each function is stated in its module docstring.
 """
