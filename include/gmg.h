@@ -242,6 +242,24 @@ gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev);
 /* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gmg_dot without any allocation and
+ * without synchronizing.  *out_dev (one double of device memory owned by the caller) =
+ * sum_i x_i y_i accumulated in FP64, the same kernels and summation order as gmg_dot (so
+ * the same bits); x_dev, y_dev: n values of type prec.  Enqueued in the stream order of
+ * the other enqueue-only calls; read *out_dev after synchronizing the caller's stream.
+ * The partials of the first pass go to a static device array of 1024 FP64 values
+ * (8 KiB per device, held until the process ends, its address looked up once per device
+ * in gmg_setup); the first pass uses at most 1024 blocks whatever n is, so every n >= 0
+ * fits (GMG_E_ARG if the block count ever exceeded the array).  Every call on one device
+ * shares that array and leaves its partials there: calls that overlap on one device (on
+ * different streams or contexts) race.  Calls no hipMalloc, hipFree or allocating
+ * library routine.  n = 0 writes 0 (x_dev and y_dev may then be null).  GMG_E_ARG for
+ * null pointers, n < 0 or a current device other than the context's; GMG_E_STATE if the
+ * array's address was not set up on this device. */
+gmg_status gmg_dot_noalloc(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev,
+                           double* out_dev);
+
 /* ---------------------------------------------------------------------------
  * Learned smoother (not in the paper, whose smoother choice is heuristic, Section 1
  * "Limitations" and Section 2.3.3).  One net per depth d (d = 0 finest level,

@@ -82,6 +82,7 @@ struct Level {
 
 struct gmg_ctx {
   int q = 0, L = 0;
+  int device = 0;                // the HIP device current at gmg_setup
   gmg_options opt{};
   hipStream_t user = nullptr;    // the caller's stream (gmg_setup argument)
   hipStream_t stream = nullptr;  // the library's own work stream, ordered with `user` by events
@@ -1352,6 +1353,15 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   if (o.vcycle_prec == GMG_FP32) o.krylov = 1;
   c->opt = o;
   c->user = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    gmg_destroy(c);
+    return GMG_E_HIP;
+  }
+  // the device address of gmg_dot_noalloc's static scratch, once per device
+  if (noalloc_scratch_init(c->device) != hipSuccess) {
+    gmg_destroy(c);
+    return GMG_E_HIP;
+  }
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
     c->stream = nullptr;
     gmg_destroy(c);
@@ -1596,6 +1606,22 @@ gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, co
     double hs[kNumScal];
     STCHK(read_scalars(ctx, hs, kNumScal));
     *out_host = hs[S_TMP];
+    return GMG_OK;
+  });
+}
+
+gmg_status gmg_dot_noalloc(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev,
+                           double* out_dev) {
+  // n = 0 reads nothing (x_dev, y_dev may then be null) and writes 0
+  if (!ctx || !out_dev || n < 0 || (n > 0 && (!x_dev || !y_dev))) return GMG_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+    return fail(ctx, GMG_E_ARG, "gmg_dot_noalloc: call with the context's device current");
+  return scoped(ctx, [&] {
+    const hipError_t e = launch_dot_noalloc(ctx->device, prec == GMG_FP32, n, x_dev, y_dev, out_dev, ctx->stream);
+    if (e == hipErrorNotInitialized) return fail(ctx, GMG_E_STATE, "gmg_dot_noalloc: scratch not set up on this device");
+    if (e == hipErrorInvalidValue) return fail(ctx, GMG_E_ARG, "gmg_dot_noalloc: more partials than the scratch holds");
+    HIPCHK(ctx, e);
     return GMG_OK;
   });
 }

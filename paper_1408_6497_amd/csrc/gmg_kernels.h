@@ -208,6 +208,16 @@ constexpr int kRedBlocks = 1024;
 hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double* part, double* dst,
                       hipStream_t s);
 hipError_t launch_sum(bool fp32, int64_t n, const void* x, double* part, double* dst, hipStream_t s);
+// The dot of launch_dot with its partials in a static device array instead of `part`:
+// kNoallocPartials FP64 values (8 KiB) per device.  noalloc_scratch_init(device), with that
+// device current, looks the array's device address up once (at context setup);
+// launch_dot_noalloc then allocates nothing.  Concurrent calls on one device share the
+// array and race.
+constexpr int kNoallocPartials = kRedBlocks;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch_init(int device);
+hipError_t launch_dot_noalloc(int device, bool fp32, int64_t n, const void* x, const void* y, double* dst,
+                              hipStream_t s);
 // Fused Krylov reductions (part needs 3 * kRedBlocks doubles; results go to scalar slots of sc):
 //   dot2:        sc[dxy] = x.y, sc[dxz] = x.z
 //   axpy2_sums:  u += a p, r -= a w (a = sc[inum] / sc[iden]); sc[dsum] = sum r, sc[dsq] = r.r

@@ -3,6 +3,8 @@
 // Reductions accumulate in FP64 whatever the vector type: 64-lane wavefront
 // shuffles, then LDS across the block, then a second single-block pass over the
 // per-block partials in a fixed order (deterministic results).
+#include <mutex>
+
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -547,6 +549,49 @@ hipError_t launch_dot(bool fp32, int64_t n, const void* x, const void* y, double
                        static_cast<const double*>(y), part);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, part, g, dst);
   return hipGetLastError();
+}
+
+}  // namespace gmg
+
+// ------------------------------------------------------------ the no-allocation dot
+// Partials of the first pass of gmg_dot_noalloc live in this file-scope device array
+// (one copy per device, held until the process ends), not in memory the library
+// allocates.  In host code `scratch` names a host-side stand-in, so its device address
+// is taken once per device with hipGetSymbolAddress at setup and only that address is
+// passed to kernels.
+static __device__ __align__(256) double scratch[gmg::kNoallocPartials];
+
+namespace gmg {
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (p == nullptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+hipError_t launch_dot_noalloc(int device, bool fp32, int64_t n, const void* x, const void* y, double* dst,
+                              hipStream_t s) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch_ptr[device];
+  }
+  if (p == nullptr) return hipErrorNotInitialized;
+  // the first pass writes one partial per block, every block, so nothing in the scratch
+  // needs clearing between calls; its block count must fit the scratch
+  if (red_grid(n) > kNoallocPartials) return hipErrorInvalidValue;
+  return launch_dot(fp32, n, x, y, static_cast<double*>(p), dst, s);
 }
 
 hipError_t launch_dot2(bool fp32, int64_t n, const void* x, const void* y, const void* z, double* part, double* sc,

@@ -28,6 +28,7 @@ EXPORTS = [
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
     "gmg_octree_refine_gaussians", "gmg_octree_refine_sharp_layer", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
     "gmg_net_get_state", "gmg_net_set_state", "gmg_smooth_zero", "gmg_launch_shape",
+    "gmg_dot_noalloc",
 ]
 
 NET_WEIGHTS = 7776
@@ -128,6 +129,7 @@ def load():
         "gmg_residual": [P, I32, I32, P, P, P],
         "gmg_smooth_zero": [P, I32, I32, P, P, I32],
         "gmg_launch_shape": [P, I32, I32, I32, P],
+        "gmg_dot_noalloc": [P, I32, I64, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -333,6 +335,14 @@ class Context:
         self._check(self.lib.gmg_dot(self.h, p, x.numel(), self._vec(x, None, p), self._vec(y, None, p),
                                      ctypes.byref(v)))
         return v.value
+
+    def dot_noalloc(self, x, y, out):
+        """out[0] = x . y in FP64 (out: one float64 GPU element), enqueued without allocating."""
+        p = self.prec_of(x)
+        if out.dtype != self._torch.float64 or out.numel() < 1 or not out.is_cuda:
+            raise ValueError("out must be a float64 GPU tensor with at least one element")
+        self._check(self.lib.gmg_dot_noalloc(self.h, p, x.numel(), self._vec(x, None, p), self._vec(y, None, p),
+                                             _ptr(out)))
 
     # -- launch timing (needs timing=1 at construction)
     (KIND_APPLY, KIND_RESIDUAL, KIND_SMOOTH0, KIND_SMOOTH, KIND_MASS, KIND_RESTRICT, KIND_PROLONG, KIND_COARSE,
