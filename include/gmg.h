@@ -239,6 +239,23 @@ gmg_status gmg_solve_rhs(gmg_ctx* ctx, const double* b_dev, double* u_dev, doubl
  * and on aliasing. */
 gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev);
 
+/* The paper's FFT Poisson method (Section 2.1, last paragraph): the spectral solution of
+ * -Laplace(u) = f on the uniform grid x = (i, j, k) / N of the periodic unit cube: the 3D
+ * discrete Fourier transform of f, each coefficient divided by 4 pi^2 |m|^2 (m the integer
+ * wavevector, components in {-N/2 .. N/2-1}; the m = 0 coefficient, the mean, set to 0),
+ * the inverse transform.  u is the zero-mean solution; the mean of f is ignored.
+ * gmg_spectral_create: N a power of two, 16 <= N <= 1024 (else GMG_E_ARG); allocates a
+ * complex FP64 work buffer of N^3 values (16 N^3 bytes) and a table of N roots of unity,
+ * kept until gmg_spectral_destroy; hip_stream: a hipStream_t (NULL = the null stream) on
+ * which gmg_spectral_solve enqueues its five kernels (hand-written transforms, no FFT
+ * library) and returns without synchronizing.  f_dev, u_dev: N^3 FP64 device values, x
+ * fastest (index i + N (j + N k)), caller-owned; they may alias.  A solver object is not
+ * thread-safe and must not run two solves at once. */
+typedef struct gmg_spectral gmg_spectral;
+gmg_status gmg_spectral_create(int32_t N, void* hip_stream, gmg_spectral** out);
+gmg_status gmg_spectral_solve(gmg_spectral* sp, const double* f_dev, double* u_dev);
+gmg_status gmg_spectral_destroy(gmg_spectral* sp);
+
 /* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
 

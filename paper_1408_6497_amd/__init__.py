@@ -4,4 +4,4 @@ The solver lives in libgmg.so (hand-written HIP for gfx950, C ABI in include/gmg
 ``gmg`` is its ctypes binding.
 """
 from .gmg import (Context, GmgError, GMG_FP32, GMG_FP64, LOSS_ENERGY, LOSS_RESIDUAL, load,  # noqa: F401
-                  octree_balance, octree_refine_gaussians, octree_refine_sharp_layer)
+                  octree_balance, octree_refine_gaussians, octree_refine_sharp_layer, SpectralSolver)

@@ -1610,6 +1610,41 @@ gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, co
   });
 }
 
+}  // extern "C"
+
+struct gmg_spectral {
+  FftSpectral f;
+  hipStream_t stream = nullptr;
+};
+
+extern "C" {
+
+gmg_status gmg_spectral_create(int32_t N, void* hip_stream, gmg_spectral** out) {
+  if (!out) return GMG_E_ARG;
+  *out = nullptr;
+  if (!spectral_size_ok(N)) return GMG_E_ARG;
+  gmg_spectral* s = new (std::nothrow) gmg_spectral();
+  if (!s) return GMG_E_OOM;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  const hipError_t e = spectral_prepare(&s->f, N);
+  if (e != hipSuccess) {
+    delete s;
+    return e == hipErrorOutOfMemory ? GMG_E_OOM : GMG_E_HIP;
+  }
+  *out = s;
+  return GMG_OK;
+}
+
+gmg_status gmg_spectral_solve(gmg_spectral* sp, const double* f_dev, double* u_dev) {
+  if (!sp || !f_dev || !u_dev) return GMG_E_ARG;
+  return spectral_solve(sp->f, f_dev, u_dev, sp->stream) == hipSuccess ? GMG_OK : GMG_E_HIP;
+}
+
+gmg_status gmg_spectral_destroy(gmg_spectral* sp) {
+  delete sp;
+  return GMG_OK;
+}
+
 gmg_status gmg_dot_noalloc(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev,
                            double* out_dev) {
   // n = 0 reads nothing (x_dev, y_dev may then be null) and writes 0

@@ -50,15 +50,25 @@ __global__ void __launch_bounds__(kFftBlock) k_fft_q1_divide(hipfftDoubleComplex
 
 static inline hipfftHandle fft_handle(void* p) { return static_cast<hipfftHandle>(p); }
 
-FftQ1::~FftQ1() {
-  if (fwd_ok) (void)hipfftDestroy(fft_handle(fwd));
-  if (inv_ok) (void)hipfftDestroy(fft_handle(inv));
-  if (spec) (void)hipFree(spec);
+// Plans and buffers of one FFT object are released together, so that a prepare that
+// fails half way (or one for another size) leaves nothing behind and starts afresh.
+template <typename F>
+void fft_release(F* f) {
+  if (f->fwd_ok) (void)hipfftDestroy(fft_handle(f->fwd));
+  if (f->inv_ok) (void)hipfftDestroy(fft_handle(f->inv));
+  f->fwd_ok = f->inv_ok = false;
+  f->fwd = f->inv = nullptr;
+  if (f->spec) (void)hipFree(f->spec);
+  f->spec = nullptr;
 }
+
+FftQ1::~FftQ1() { fft_release(this); }
 
 hipError_t fft_q1_prepare(FftQ1* f, int N) {
   if (f->N == N && f->fwd_ok && f->inv_ok && f->spec) return hipSuccess;
   if (N < 2) return hipErrorInvalidValue;
+  fft_release(f);
+  f->N = 0;
   const size_t bytes = sizeof(hipfftDoubleComplex) * static_cast<size_t>(N) * N * (N / 2 + 1);
   hipError_t e = hipMalloc(&f->spec, bytes);
   if (e != hipSuccess) {
@@ -66,10 +76,16 @@ hipError_t fft_q1_prepare(FftQ1* f, int N) {
     return e;
   }
   hipfftHandle h = nullptr;
-  if (hipfftPlan3d(&h, N, N, N, HIPFFT_D2Z) != HIPFFT_SUCCESS) return hipErrorUnknown;
+  if (hipfftPlan3d(&h, N, N, N, HIPFFT_D2Z) != HIPFFT_SUCCESS) {
+    fft_release(f);
+    return hipErrorUnknown;
+  }
   f->fwd = h;
   f->fwd_ok = true;
-  if (hipfftPlan3d(&h, N, N, N, HIPFFT_Z2D) != HIPFFT_SUCCESS) return hipErrorUnknown;
+  if (hipfftPlan3d(&h, N, N, N, HIPFFT_Z2D) != HIPFFT_SUCCESS) {
+    fft_release(f);
+    return hipErrorUnknown;
+  }
   f->inv = h;
   f->inv_ok = true;
   f->N = N;
@@ -209,13 +225,17 @@ __global__ void __launch_bounds__(kFftBlock) k_fft_q2_solve(hipfftDoubleComplex*
 
 }  // namespace
 
-FftQ2::~FftQ2() {
-  if (fwd_ok) (void)hipfftDestroy(fft_handle(fwd));
-  if (inv_ok) (void)hipfftDestroy(fft_handle(inv));
-  if (spec) (void)hipFree(spec);
-  if (cls) (void)hipFree(cls);
-  if (axis) (void)hipFree(axis);
+// the class-split objects (Q2, Q4) also hold the class arrays and the axis tables
+template <typename F>
+void fft_release_classes(F* f) {
+  fft_release(f);
+  if (f->cls) (void)hipFree(f->cls);
+  if (f->axis) (void)hipFree(f->axis);
+  f->cls = f->axis = nullptr;
+  f->n = 0;
 }
+
+FftQ2::~FftQ2() { fft_release_classes(this); }
 
 // 1D symbols of the Q2 element matrices (LGL nodes 0, 1/2, 1 on an element of width h) and
 // the M-orthonormal eigenvectors of each 2x2 pencil, for the n wavenumbers t = 2 pi k / n:
@@ -238,12 +258,18 @@ static void q2_axis_tables(int n, std::vector<Axis2>* out) {
     double ka, kbr, kbi, kd, ma, mbr, mbi, md;
     sym(k3, 1.0 / h, &ka, &kbr, &kbi, &kd);
     sym(m3, h, &ma, &mbr, &mbi, &md);
+    // det(K - lam M) = qa lam^2 + qb lam + qc.  det K = ka kd - |kb|^2 vanishes like t^2,
+    // so it is taken in closed form: with the Q2 rows above, ka kd - |kb|^2 =
+    // (32/3)(1 - cos t) / h^2 = (64/3) sin^2(t/2) / h^2, and the small root as
+    // 2 qc / (-qb + disc) (qa > 0, qb < 0), so neither loses digits to cancellation
+    // as t -> 0.
     const double qa = ma * md - (mbr * mbr + mbi * mbi);
     const double qb = -(ka * md + kd * ma) + 2.0 * (kbr * mbr + kbi * mbi);
-    const double qc = ka * kd - (kbr * kbr + kbi * kbi);
+    const double sh = std::sin(0.5 * t);
+    const double qc = (64.0 / 3.0) * sh * sh / (h * h);
     const double disc = std::sqrt(std::max(0.0, qb * qb - 4.0 * qa * qc));
     Axis2& A = (*out)[k];
-    A.lam[0] = (-qb - disc) / (2.0 * qa);
+    A.lam[0] = 2.0 * qc / (-qb + disc);
     A.lam[1] = (-qb + disc) / (2.0 * qa);
     if (k == 0) A.lam[0] = 0.0;  // the constant is exactly in the kernel of K at t = 0
     for (int o = 0; o < 2; ++o) {
@@ -281,31 +307,55 @@ static void q2_axis_tables(int n, std::vector<Axis2>* out) {
   }
 }
 
+// Buffers, axis tables and batched plans of a class-split solve with NC classes; on any
+// failure everything made so far is released and f->n stays 0.
+template <typename F, typename Tab>
+hipError_t fft_prepare_classes(F* f, int n, int NC, const std::vector<Tab>& tab) {
+  fft_release_classes(f);
+  const size_t n3 = static_cast<size_t>(n) * n * n;
+  const size_t m = static_cast<size_t>(n) * n * (n / 2 + 1);
+  hipError_t e = hipSuccess;
+  if (hipMalloc(&f->spec, sizeof(hipfftDoubleComplex) * NC * m) != hipSuccess ||
+      hipMalloc(&f->cls, sizeof(double) * NC * n3) != hipSuccess ||
+      hipMalloc(&f->axis, sizeof(Tab) * n) != hipSuccess)
+    e = hipErrorOutOfMemory;
+  if (e == hipSuccess && hipMemcpy(f->axis, tab.data(), sizeof(Tab) * n, hipMemcpyHostToDevice) != hipSuccess)
+    e = hipErrorUnknown;
+  int dims[3] = {n, n, n};
+  hipfftHandle h = nullptr;
+  if (e == hipSuccess) {
+    if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(n3), nullptr, 1, static_cast<int>(m), HIPFFT_D2Z,
+                       NC) == HIPFFT_SUCCESS) {
+      f->fwd = h;
+      f->fwd_ok = true;
+    } else {
+      e = hipErrorUnknown;
+    }
+  }
+  if (e == hipSuccess) {
+    if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(m), nullptr, 1, static_cast<int>(n3), HIPFFT_Z2D,
+                       NC) == HIPFFT_SUCCESS) {
+      f->inv = h;
+      f->inv_ok = true;
+    } else {
+      e = hipErrorUnknown;
+    }
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fft_release_classes(f);
+    return e;
+  }
+  f->n = n;
+  return hipSuccess;
+}
+
 hipError_t fft_q2_prepare(FftQ2* f, int n) {
   if (f->n == n && f->fwd_ok && f->inv_ok && f->spec) return hipSuccess;
   if (n < 2 || (n & 1)) return hipErrorInvalidValue;
-  const size_t n3 = static_cast<size_t>(n) * n * n;
-  const size_t m = static_cast<size_t>(n) * n * (n / 2 + 1);
-  if (hipMalloc(&f->spec, sizeof(hipfftDoubleComplex) * 8 * m) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMalloc(&f->cls, sizeof(double) * 8 * n3) != hipSuccess) return hipErrorOutOfMemory;
   std::vector<Axis2> tab;
   q2_axis_tables(n, &tab);
-  if (hipMalloc(&f->axis, sizeof(Axis2) * n) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMemcpy(f->axis, tab.data(), sizeof(Axis2) * n, hipMemcpyHostToDevice) != hipSuccess) return hipErrorUnknown;
-  int dims[3] = {n, n, n};
-  hipfftHandle h = nullptr;
-  if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(n3), nullptr, 1, static_cast<int>(m), HIPFFT_D2Z, 8) !=
-      HIPFFT_SUCCESS)
-    return hipErrorUnknown;
-  f->fwd = h;
-  f->fwd_ok = true;
-  if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(m), nullptr, 1, static_cast<int>(n3), HIPFFT_Z2D, 8) !=
-      HIPFFT_SUCCESS)
-    return hipErrorUnknown;
-  f->inv = h;
-  f->inv_ok = true;
-  f->n = n;
-  return hipSuccess;
+  return fft_prepare_classes(f, n, 8, tab);
 }
 
 hipError_t fft_q2_solve(FftQ2* f, const double* b, double* u, hipStream_t s) {
@@ -441,11 +491,14 @@ __global__ void __launch_bounds__(kFftBlock) k_fft_solve_q(hipfftDoubleComplex* 
 
 // Eigen-decomposition of a real symmetric matrix (cyclic Jacobi), ascending eigenvalues,
 // eigenvectors as the columns of v (row-major, dimension d).
-void jacobi_eigen(int d, std::vector<double> a, std::vector<double>* w, std::vector<double>* v) {
+template <typename R>
+void jacobi_eigen(int d, std::vector<R> a, std::vector<R>* w, std::vector<R>* v) {
+  using std::fabs;
+  using std::sqrt;
   v->assign(static_cast<size_t>(d) * d, 0.0);
   for (int i = 0; i < d; ++i) (*v)[i * d + i] = 1.0;
   for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
+    R off = 0, tot = 0;
     for (int i = 0; i < d; ++i)
       for (int j = 0; j < d; ++j) {
         tot += a[i * d + j] * a[i * d + j];
@@ -454,23 +507,23 @@ void jacobi_eigen(int d, std::vector<double> a, std::vector<double>* w, std::vec
     if (off <= 1e-30 * tot) break;
     for (int p = 0; p < d; ++p)
       for (int r = p + 1; r < d; ++r) {
-        const double apr = a[p * d + r];
-        if (std::fabs(apr) < 1e-300) continue;
-        const double theta = (a[r * d + r] - a[p * d + p]) / (2.0 * apr);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        const R apr = a[p * d + r];
+        if (fabs(apr) < R(1e-300)) continue;
+        const R theta = (a[r * d + r] - a[p * d + p]) / (2 * apr);
+        const R t = (theta >= 0 ? R(1) : R(-1)) / (fabs(theta) + sqrt(theta * theta + 1));
+        const R c = 1 / sqrt(t * t + 1), s = t * c;
         for (int k = 0; k < d; ++k) {  // columns p, r
-          const double akp = a[k * d + p], akr = a[k * d + r];
+          const R akp = a[k * d + p], akr = a[k * d + r];
           a[k * d + p] = c * akp - s * akr;
           a[k * d + r] = s * akp + c * akr;
         }
         for (int k = 0; k < d; ++k) {  // rows p, r
-          const double apk = a[p * d + k], ark = a[r * d + k];
+          const R apk = a[p * d + k], ark = a[r * d + k];
           a[p * d + k] = c * apk - s * ark;
           a[r * d + k] = s * apk + c * ark;
         }
         for (int k = 0; k < d; ++k) {
-          const double vkp = (*v)[k * d + p], vkr = (*v)[k * d + r];
+          const R vkp = (*v)[k * d + p], vkr = (*v)[k * d + r];
           (*v)[k * d + p] = c * vkp - s * vkr;
           (*v)[k * d + r] = s * vkp + c * vkr;
         }
@@ -479,7 +532,7 @@ void jacobi_eigen(int d, std::vector<double> a, std::vector<double>* w, std::vec
   std::vector<int> ord(d);
   for (int i = 0; i < d; ++i) ord[i] = i;
   std::sort(ord.begin(), ord.end(), [&](int x, int y) { return a[x * d + x] < a[y * d + y]; });
-  std::vector<double> vs(static_cast<size_t>(d) * d);
+  std::vector<R> vs(static_cast<size_t>(d) * d);
   w->resize(d);
   for (int j = 0; j < d; ++j) {
     (*w)[j] = a[ord[j] * d + ord[j]];
@@ -488,29 +541,48 @@ void jacobi_eigen(int d, std::vector<double> a, std::vector<double>* w, std::vec
   *v = vs;
 }
 
+// The tables are computed in x87 extended precision (64-bit significand) and rounded to
+// FP64 at the end: the smallest eigenvalue of a pencil vanishes like t^2 at small
+// wavenumbers t while the symbol's entries stay O(1/h), so an FP64 computation would
+// lose about log10(1/t^2) digits of it (3 at n = 256); 11 more bits keep it at FP64
+// accuracy up to the largest supported n.
 template <int Q>
 void axis_tables_q(int n, std::vector<AxisQ<Q>>* out) {
-  using C = std::complex<double>;
-  std::vector<double> khat, mhat;
-  reference_matrices(Q, &khat, &mhat);
+  using R = long double;
+  using C = std::complex<R>;
+  std::vector<double> khat64, mhat;
+  reference_matrices(Q, &khat64, &mhat);
   const int p = Q + 1;
-  const double h = 1.0 / n;
+  // The stiffness rows sum to zero (the derivative of a constant vanishes); the FP64 table
+  // does so only to rounding, which would put an O(eps / h) eigenvalue error at every small
+  // wavenumber.  The diagonal is set to minus the row's off-diagonal sum in extended
+  // precision, so the constant is exactly in the kernel at t = 0 and the small branch
+  // vanishes like t^2 without an eps floor.
+  std::vector<R> khat(khat64.begin(), khat64.end());
+  for (int a = 0; a <= Q; ++a) {
+    R off = 0;
+    for (int b = 0; b <= Q; ++b)
+      if (b != a) off += khat[a * p + b];
+    khat[a * p + a] = -off;
+  }
+  const R h = R(1) / n;
+  const R pi = std::acos(R(-1));
   out->resize(n);
   for (int k = 0; k < n; ++k) {
-    const C ph = std::polar(1.0, 2.0 * M_PI * k / n);
+    const C ph = std::polar(R(1), 2 * pi * k / n);
     // S = P^H E P, P: class a -> local node a (a < q), and local node q = e^{it} class 0
-    auto sym = [&](const std::vector<double>& E, double sc, C (&S)[Q][Q]) {
+    auto sym = [&](const auto& E, R sc, C (&S)[Q][Q]) {
       for (int a = 0; a < Q; ++a)
         for (int b = 0; b < Q; ++b) {
-          C s = E[a * p + b];
-          if (a == 0) s += std::conj(ph) * E[Q * p + b];
-          if (b == 0) s += E[a * p + Q] * ph;
-          if (a == 0 && b == 0) s += E[Q * p + Q];
+          C s = R(E[a * p + b]);
+          if (a == 0) s += std::conj(ph) * R(E[Q * p + b]);
+          if (b == 0) s += R(E[a * p + Q]) * ph;
+          if (a == 0 && b == 0) s += R(E[Q * p + Q]);
           S[a][b] = sc * s;
         }
     };
     C K[Q][Q], M[Q][Q], L[Q][Q] = {}, Li[Q][Q] = {};
-    sym(khat, 1.0 / h, K);
+    sym(khat, 1 / h, K);
     sym(mhat, h, M);
     for (int j = 0; j < Q; ++j) {  // Cholesky M = L L^H
       C s = M[j][j];
@@ -523,9 +595,9 @@ void axis_tables_q(int n, std::vector<AxisQ<Q>>* out) {
       }
     }
     for (int j = 0; j < Q; ++j) {  // L^-1 by forward substitution
-      Li[j][j] = 1.0 / L[j][j];
+      Li[j][j] = R(1) / L[j][j];
       for (int i = j + 1; i < Q; ++i) {
-        C s = 0.0;
+        C s = 0;
         for (int t = j; t < i; ++t) s += L[i][t] * Li[t][j];
         Li[i][j] = -s / L[i][i];
       }
@@ -533,50 +605,50 @@ void axis_tables_q(int n, std::vector<AxisQ<Q>>* out) {
     C Cm[Q][Q];  // L^-1 K L^-H
     for (int i = 0; i < Q; ++i)
       for (int j = 0; j < Q; ++j) {
-        C s = 0.0;
+        C s = 0;
         for (int a = 0; a < Q; ++a)
           for (int b = 0; b < Q; ++b) s += Li[i][a] * K[a][b] * std::conj(Li[j][b]);
         Cm[i][j] = s;
       }
     // real symmetric embedding [[Re, -Im], [Im, Re]]: every eigenvalue twice
     const int d = 2 * Q;
-    std::vector<double> R(static_cast<size_t>(d) * d), w, v;
+    std::vector<R> Re(static_cast<size_t>(d) * d), w, v;
     for (int i = 0; i < Q; ++i)
       for (int j = 0; j < Q; ++j) {
-        R[i * d + j] = Cm[i][j].real();
-        R[i * d + Q + j] = -Cm[i][j].imag();
-        R[(Q + i) * d + j] = Cm[i][j].imag();
-        R[(Q + i) * d + Q + j] = Cm[i][j].real();
+        Re[i * d + j] = Cm[i][j].real();
+        Re[i * d + Q + j] = -Cm[i][j].imag();
+        Re[(Q + i) * d + j] = Cm[i][j].imag();
+        Re[(Q + i) * d + Q + j] = Cm[i][j].real();
       }
-    jacobi_eigen(d, R, &w, &v);
+    jacobi_eigen<R>(d, Re, &w, &v);
     // complex eigenvectors z = y_re + i y_im from the real ones, kept when independent of
     // those already taken (Gram-Schmidt), in ascending eigenvalue order
     std::vector<std::vector<C>> Z;
-    std::vector<double> lam;
+    std::vector<R> lam;
     for (int j = 0; j < d && static_cast<int>(Z.size()) < Q; ++j) {
       std::vector<C> z(Q);
       for (int i = 0; i < Q; ++i) z[i] = C(v[i * d + j], v[(Q + i) * d + j]);
       for (const auto& y : Z) {
-        C dot = 0.0;
+        C dot = 0;
         for (int i = 0; i < Q; ++i) dot += std::conj(y[i]) * z[i];
         for (int i = 0; i < Q; ++i) z[i] -= dot * y[i];
       }
-      double nn = 0.0;
+      R nn = 0;
       for (int i = 0; i < Q; ++i) nn += std::norm(z[i]);
-      if (nn < 1e-12) continue;
+      if (nn < R(1e-12)) continue;
       for (int i = 0; i < Q; ++i) z[i] /= std::sqrt(nn);
       Z.push_back(z);
       lam.push_back(w[j]);
     }
     AxisQ<Q>& A = (*out)[k];
     for (int o = 0; o < Q; ++o) {
-      A.lam[o] = o < static_cast<int>(lam.size()) ? lam[o] : 0.0;
+      A.lam[o] = o < static_cast<int>(lam.size()) ? static_cast<double>(lam[o]) : 0.0;
       for (int r = 0; r < Q; ++r) {  // V = L^-H Z: (L^-H)[r][i] = conj(Li[i][r])
-        C s = 0.0;
+        C s = 0;
         if (o < static_cast<int>(Z.size()))
           for (int i = 0; i < Q; ++i) s += std::conj(Li[i][r]) * Z[o][i];
-        A.vr[r][o] = s.real();
-        A.vi[r][o] = s.imag();
+        A.vr[r][o] = static_cast<double>(s.real());
+        A.vi[r][o] = static_cast<double>(s.imag());
       }
     }
     if (k == 0) A.lam[0] = 0.0;  // the constant is exactly in the kernel of K at t = 0
@@ -585,40 +657,14 @@ void axis_tables_q(int n, std::vector<AxisQ<Q>>* out) {
 
 }  // namespace
 
-FftQ4::~FftQ4() {
-  if (fwd_ok) (void)hipfftDestroy(fft_handle(fwd));
-  if (inv_ok) (void)hipfftDestroy(fft_handle(inv));
-  if (spec) (void)hipFree(spec);
-  if (cls) (void)hipFree(cls);
-  if (axis) (void)hipFree(axis);
-}
+FftQ4::~FftQ4() { fft_release_classes(this); }
 
 hipError_t fft_q4_prepare(FftQ4* f, int n) {
   if (f->n == n && f->fwd_ok && f->inv_ok && f->spec) return hipSuccess;
   if (n < 2) return hipErrorInvalidValue;
-  constexpr int NC = 64;
-  const size_t n3 = static_cast<size_t>(n) * n * n;
-  const size_t m = static_cast<size_t>(n) * n * (n / 2 + 1);
-  if (hipMalloc(&f->spec, sizeof(hipfftDoubleComplex) * NC * m) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMalloc(&f->cls, sizeof(double) * NC * n3) != hipSuccess) return hipErrorOutOfMemory;
   std::vector<AxisQ<4>> tab;
   axis_tables_q<4>(n, &tab);
-  if (hipMalloc(&f->axis, sizeof(AxisQ<4>) * n) != hipSuccess) return hipErrorOutOfMemory;
-  if (hipMemcpy(f->axis, tab.data(), sizeof(AxisQ<4>) * n, hipMemcpyHostToDevice) != hipSuccess) return hipErrorUnknown;
-  int dims[3] = {n, n, n};
-  hipfftHandle h = nullptr;
-  if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(n3), nullptr, 1, static_cast<int>(m), HIPFFT_D2Z, NC) !=
-      HIPFFT_SUCCESS)
-    return hipErrorUnknown;
-  f->fwd = h;
-  f->fwd_ok = true;
-  if (hipfftPlanMany(&h, 3, dims, nullptr, 1, static_cast<int>(m), nullptr, 1, static_cast<int>(n3), HIPFFT_Z2D, NC) !=
-      HIPFFT_SUCCESS)
-    return hipErrorUnknown;
-  f->inv = h;
-  f->inv_ok = true;
-  f->n = n;
-  return hipSuccess;
+  return fft_prepare_classes(f, n, 64, tab);
 }
 
 hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s) {

@@ -116,6 +116,20 @@ struct FftQ4 {
 hipError_t fft_q4_prepare(FftQ4* f, int n);
 hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s);
 
+// Spectral FFT Poisson solve on the uniform N^3 grid (16 <= N <= 1024, a power of two):
+// u = F^-1 [F(f) / (4 pi^2 |m|^2)] with the m = 0 coefficient set to 0.  The complex
+// work buffer (N^3 values) and the table of the N roots of unity are made by
+// spectral_prepare and kept until the object is destroyed; f and u may alias.
+struct FftSpectral {
+  int N = 0;
+  void* buf = nullptr;
+  void* tw = nullptr;
+  ~FftSpectral();
+};
+bool spectral_size_ok(int N);
+hipError_t spectral_prepare(FftSpectral* s, int N);
+hipError_t spectral_solve(const FftSpectral& s, const double* f, double* u, hipStream_t st);
+
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 // The launch shape launch_apply takes on a uniform level: kernel 0 = the point kernel
 // (N <= 32), 1 = the streaming column kernel, 2 = the column kernel that loads all the

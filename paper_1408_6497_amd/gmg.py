@@ -28,7 +28,7 @@ EXPORTS = [
     "gmg_net_backward", "gmg_adam_step", "gmg_net_correction", "gmg_net_loss_grad", "gmg_residual",
     "gmg_octree_refine_gaussians", "gmg_octree_refine_sharp_layer", "gmg_octree_balance", "gmg_level_leaves", "gmg_num_elements", "gmg_dof_coords",
     "gmg_net_get_state", "gmg_net_set_state", "gmg_smooth_zero", "gmg_launch_shape",
-    "gmg_dot_noalloc",
+    "gmg_dot_noalloc", "gmg_spectral_create", "gmg_spectral_solve", "gmg_spectral_destroy",
 ]
 
 NET_WEIGHTS = 7776
@@ -130,6 +130,9 @@ def load():
         "gmg_smooth_zero": [P, I32, I32, P, P, I32],
         "gmg_launch_shape": [P, I32, I32, I32, P],
         "gmg_dot_noalloc": [P, I32, I64, P, P, P],
+        "gmg_spectral_create": [I32, P, ctypes.POINTER(P)],
+        "gmg_spectral_solve": [P, P, P],
+        "gmg_spectral_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -518,3 +521,41 @@ def octree_balance(keys, levels):
     l = np.ascontiguousarray(levels, dtype=np.uint8)
     return _leaves_call(lib.gmg_octree_balance, k.ctypes.data_as(ctypes.c_void_p), l.ctypes.data_as(ctypes.c_void_p),
                         k.size)
+
+class SpectralSolver:
+    """The paper's FFT Poisson method on the uniform N^3 grid (gmg_spectral_*): u with
+    -Laplace(u) = f spectrally, zero mean, f and u FP64 GPU tensors of N^3 values."""
+
+    def __init__(self, N, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.N = N
+        h = ctypes.c_void_p()
+        st = self.lib.gmg_spectral_create(N, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise GmgError(st, f"gmg_spectral_create({N}) failed")
+        self.h = h
+
+    def solve(self, f, u):
+        torch = self._torch
+        for t in (f, u):
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.numel() == self.N ** 3):
+                raise ValueError("expected contiguous float64 GPU tensors of N^3 values")
+        st = self.lib.gmg_spectral_solve(self.h, _ptr(f), _ptr(u))
+        if st != 0:
+            raise GmgError(st, "gmg_spectral_solve failed")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gmg_spectral_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
