@@ -14,6 +14,8 @@ Readings:
     complement of the constants: x = (A_0 + 1 1^T / N_0)^-1 (b - mean(b) 1),
     which is the mean-zero solution of A_0 x = b - mean(b) 1.
   * Level l has n_l = n / 2^(L-1-l) elements per direction; level 0 is coarsest.
+    The recursion may go down to a single periodic element (n_0 = 1): the paper
+    stops coarsening when no further coarsening is possible (Section 2.3.1).
 
 Pins (tests/test_oracle_multigrid.py): coarse solve against numpy's
 pseudo-inverse; V-cycle symmetry and positive definiteness on 1-perp; a
@@ -67,8 +69,8 @@ class Hierarchy:
     def __init__(self, q, n, levels, opts=None, form="csr"):
         if opts is None:
             opts = Options()
-        if n < 2 or (n & (n - 1)) != 0:
-            raise ValueError("n must be a power of two >= 2")
+        if n < 1 or (n & (n - 1)) != 0:
+            raise ValueError("n must be a power of two")
         if levels < 1 or (n >> (levels - 1)) < 1:
             raise ValueError("too many levels")
         self.q, self.n, self.L, self.opts = q, n, levels, opts

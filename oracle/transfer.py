@@ -4,12 +4,15 @@ Paper: Section 2.3.4, eqs. (2.1)-(2.2): the coarse space is a subspace of the
 fine space, so the prolongation has entries P(i, j) = phi_j^{k-1}(p_i), the
 coarse shape function j evaluated at fine node p_i; the restriction is R = P^T.
 
-The coarse mesh has n_c elements per direction, the fine mesh n_f = 2 n_c, both
-of order q.  P is built by visiting each coarse element, evaluating the
-tensor-product coarse basis (q+1 LGL nodes per direction) at every fine node in
-its closure, and keeping one entry per (fine node, coarse node) pair: fine nodes
-on coarse-element faces are reached from several coarse elements, and
-continuity makes those evaluations equal (checked when building).
+The coarse mesh has n_c >= 1 elements per direction, the fine mesh n_f = 2 n_c,
+both of order q.  P is built by visiting each coarse element and, in it, each fine
+node of its half-open extent [E, E+1) (so every fine node once), evaluating the
+coarse element's tensor-product basis (q+1 LGL nodes per direction) there, and
+adding the value into the entry of the global coarse node each local node is.
+Continuity makes the half-open choice immaterial.  On a single periodic element
+(n_c = 1) the element's two end nodes are one global node, whose basis function is
+the sum of the two local ones; the sum is what the adding gives (for n_c >= 2 no
+two local nodes of an element share a global node).
 
 Pins (tests/test_oracle_transfer.py): P 1 = 1; P equals the Kronecker cube of
 its 1D version and reproduces polynomials of degree <= q locally; the Galerkin
@@ -37,20 +40,19 @@ def prolongation_1d(q, n_c):
     Nf, Nc = 2 * q * n_c, q * n_c
     xi = lgl_nodes(q)
     phi = lagrange(xi, _child_coords(q))   # (q+1, 2q+1)
-    entries = {}
+    rows, cols, vals = [], [], []
     for E in range(n_c):
-        for b in range(2 * q + 1):
-            i = (2 * q * E + b) % Nf
+        for b in range(2 * q):                 # the half-open extent: each fine node once
             for a in range(q + 1):
-                j = (q * E + a) % Nc
                 v = phi[a, b]
                 if abs(v) < 1e-15:
                     continue
-                if (i, j) in entries:
-                    assert abs(entries[(i, j)] - v) < 1e-13
-                entries[(i, j)] = v
-    ij = np.array(list(entries.keys()), dtype=np.int64).reshape(-1, 2)
-    return sp.coo_matrix((list(entries.values()), (ij[:, 0], ij[:, 1])), shape=(Nf, Nc)).tocsr()
+                rows.append((2 * q * E + b) % Nf)
+                cols.append((q * E + a) % Nc)
+                vals.append(v)
+    P = sp.coo_matrix((vals, (rows, cols)), shape=(Nf, Nc)).tocsr()   # duplicates (n_c = 1) summed
+    P.sum_duplicates()
+    return P
 
 
 def prolongation(q, n_c):
@@ -58,8 +60,8 @@ def prolongation(q, n_c):
     Nf, Nc = 2 * q * n_c, q * n_c
     xi = lgl_nodes(q)
     phi = lagrange(xi, _child_coords(q))   # phi[a, b]: coarse 1D node a at child node b
-    m = 2 * q + 1
-    # fine closure nodes (bx, by, bz) and coarse element nodes (a1, a2, a3)
+    m = 2 * q
+    # fine nodes of the element's half-open extent (bx, by, bz) and coarse element nodes (a1, a2, a3)
     bx, by, bz = [g.ravel() for g in np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")]
     a1, a2, a3 = [g.ravel() for g in np.meshgrid(np.arange(q + 1), np.arange(q + 1), np.arange(q + 1), indexing="ij")]
     val = phi[a1][:, bx] * phi[a2][:, by] * phi[a3][:, bz]          # (coarse local, fine local)
@@ -79,20 +81,10 @@ def prolongation(q, n_c):
                 rows.append(I + Nf * (J + Nf * K))
                 cols.append(cI + Nc * (cJ + Nc * cK))
                 vals.append(v)
-    rows = np.concatenate(rows)
-    cols = np.concatenate(cols)
-    vals = np.concatenate(vals)
-    key = rows * (Nc ** 3) + cols
-    order = np.argsort(key, kind="stable")
-    key, rows, cols, vals = key[order], rows[order], cols[order], vals[order]
-    first = np.ones(len(key), dtype=bool)
-    first[1:] = key[1:] != key[:-1]
-    # every repeated (fine, coarse) pair must carry the same value (continuity)
-    grp = np.cumsum(first) - 1
-    ref = vals[first][grp]
-    assert np.max(np.abs(ref - vals), initial=0.0) < 1e-13
-    return sp.coo_matrix((vals[first], (rows[first], cols[first])),
-                         shape=(Nf ** 3, Nc ** 3)).tocsr()
+    P = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(Nf ** 3, Nc ** 3)).tocsr()      # duplicates (n_c = 1) summed
+    P.sum_duplicates()
+    return P
 
 
 class KroneckerProlongation:
