@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the GMG hot path on one MI355X.
 
-One step = one complete solve of the periodic Q2 Poisson problem on 128^3 elements
-(256^3 DoFs) with a 32-Gaussian source (seed 0) to a relative true FP64 residual of
-1e-8: FP32 Chebyshev-Jacobi V-cycles inside flexible CG, wrapped in FP64 iterative
-refinement.  Inputs (source, buffers, hierarchy) are resident in HBM before the
-timed region.  The plain FP64 solve (CG on FP64 V-cycles) of the same problem is
-timed next to it, and the operator apply is timed alone (GDoF/s).
+One step = one complete solve of the periodic Q2 Poisson problem on 256^3 elements
+(512^3 DoFs) with a Gaussian-random-field source (power spectrum |k|^-alpha,
+alpha ~ U[2, 4]; the held-out evaluation seeds 30000-30004 in turn) to a relative
+true FP64 residual of 1e-8, with the learned smoother: FP32 V-cycles whose smoothing
+phases end with a learned correction (per-cycle fallback to the plain cycle) inside
+FP64 flexible CG.  Inputs (sources, buffers, hierarchy) are resident in HBM before
+the timed region.  The plain FP64 solve (CG on FP64 V-cycles) and the FP32 solve
+without the net run the same sources next to it, the operator apply is timed alone
+(GDoF/s), and the other workloads (the 256^3-DoF Gaussian and sharp Q2/Q4 problems,
+the octree, the sharp layer, the FFT methods) are reported as extras.
 
 Prints one JSON line (stdout).  --gpus > 1 is not supported: this build runs on a
 single GPU.
@@ -102,77 +106,252 @@ def traffic_record():
     return None
 
 
-def cpu_baseline(q=2, n_sample=64, n_full=128, seed=0):
-    """The oracle (numpy/scipy, FP64, Kronecker form) solving the same workload at a
-    smaller size; its solve time is scaled to the full size by the DoF ratio (the
-    method's work is linear in N)."""
+EVAL_SEEDS = (30000, 30001, 30002, 30003, 30004)
+# the learned configuration of the headline: nets on depths 2 and coarser (the two finest
+# levels keep the polynomial, where one net application costs several Chebyshev ones)
+LEARNED_OPTS = dict(use_learned=1, learned_min_depth=2)
+
+
+def load_nets(ctx):
+    """Install every shipped net (weights/q2_depth<d>.gmgw) on its depth; returns the depths."""
+    import glob
+    import re
+    from paper_1408_6497_amd import train as T
+    depths = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1408_6497_amd", "weights", "q2_depth*.gmgw"))):
+        d = int(re.search(r"q2_depth(\d+)\.gmgw$", path).group(1))
+        if d < ctx.levels - 1:
+            ctx.net_set_weights(d, T.load(path)["w"])
+            depths.append(d)
+    return depths
+
+
+def host_info():
+    """CPU model and core counts of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_in_affinity_mask": affinity}
+
+
+def cpu_baseline(n_sample=64, n_full=256, seed=EVAL_SEEDS[0]):
+    """The oracle (numpy/scipy, FP64, Kronecker form, as it stands) on the headline workload.
+
+    Sample: the oracle's whole solve (CG preconditioned by its Chebyshev V-cycle, to 1e-8) of
+    the same kind of source (GRF, evaluation seed) at Q2 n_sample^3 elements, timed; plus one
+    oracle operator apply at the full 512^3-DoF size and one at the sample size, timed.  The
+    value is the sample solve scaled by the ratio of the two applies (the solve's work is
+    a fixed number of applies per iteration and the iteration count does not grow with the
+    mesh; the measured ratio carries the oracle's growing cost per DoF at the full size)."""
     import numpy as np
     from oracle import multigrid as mg, krylov
     from oracle import operator as op
-    from workloads import gaussian_params, gaussian_source
-    x1 = op.dof_coords_1d(q, n_sample)
-    f = gaussian_source(x1, gaussian_params(seed, 32, 0.02, 0.1)).numpy()
+    from workloads import grf
+    q = 2
+    N = q * n_sample
+    f = grf(N, seed)[0].numpy()
     H = mg.Hierarchy(q, n_sample, int(math.log2(n_sample)) - 1, mg.Options(seed=0), form="kron")
     b = mg.rhs(q, n_sample, f, form="kron")
     t0 = time.perf_counter()
     u, info = krylov.pcg(H.finest.A, b, H.vcycle, 1e-8)
     t = time.perf_counter() - t0
-    ratio = (n_full / n_sample) ** 3
-    threads = 1
-    try:
-        import threadpoolctl
-        for p in threadpoolctl.threadpool_info():
-            threads = max(threads, int(p.get("num_threads", 1)))
-    except Exception:
-        pass
+    x = np.random.default_rng(1).standard_normal(N ** 3)
+    t0 = time.perf_counter()
+    H.finest.A @ x
+    t_apply_sample = time.perf_counter() - t0
+    del x, u, H
+    A = op.KroneckerOperator(q, n_full)
+    x = np.random.default_rng(2).standard_normal((q * n_full) ** 3)
+    t0 = time.perf_counter()
+    A @ x
+    t_apply_full = time.perf_counter() - t0
+    del x
+    dof_ratio = (n_full / n_sample) ** 3
+    # the oracle's cost per DoF grows with the size (its sparse products leave the caches), so
+    # the sample is scaled by the measured ratio of its own applies at the two sizes, not by
+    # the DoF count
+    ratio = t_apply_full / t_apply_sample
     return {"value": t * ratio, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle FP64 CG + Chebyshev V-cycle (Kronecker form) on the same source at Q2 "
-                       f"{n_sample}^3 elements ({(q * n_sample) ** 3} DoFs), {info.iters} iterations to 1e-8 in "
-                       f"{t:.2f} s, scaled by the DoF ratio {ratio:.0f}; scipy sparse products are "
-                       f"single-threaded (BLAS pool reports {threads} threads, unused by them)"),
-            "sample_seconds": t, "sample_iters": info.iters}
+            "sample": (f"oracle FP64 CG + Chebyshev(3) V(2,2) cycle (Kronecker 1D-CSR form, scipy sparse products, "
+                       f"single-threaded) on a GRF source (seed {seed}) at Q2 {n_sample}^3 elements "
+                       f"({N ** 3} DoFs): {info.iters} iterations to 1e-8 in {t:.2f} s; one oracle operator apply "
+                       f"takes {t_apply_sample:.3f} s there and {t_apply_full:.2f} s at the full 512^3 DoFs "
+                       f"({dof_ratio:.0f}x the DoFs), and the solve is scaled by that measured ratio "
+                       f"{ratio:.1f} (the iteration count does not grow with the mesh)"),
+            "sample_seconds": t, "sample_iters": info.iters, "apply_sample_s": t_apply_sample,
+            "apply_full_s": t_apply_full, "scale": ratio, "dof_ratio": dof_ratio, "host": host_info()}
 
 
-def learned_workload(seeds=(30000, 30001, 30002, 30003, 30004), n=256):
-    """Q2 on 256^3 elements (512^3 DoFs), Gaussian-random-field sources of the held-out
-    evaluation seeds: plain FP64 CG, the FP32-cycle ablation and the learned FP32 cycle to
-    1e-8; seconds per solve (graph replay).  The learned cycle uses the shipped depth-0 net
-    on depths 2 and coarser (the two finest levels keep the Chebyshev smoother: there one
-    net application costs about 8x the polynomial it replaces), and once more on every
-    depth for comparison."""
+def c4_solves(steps, warmup, n=256, seeds=EVAL_SEEDS):
+    """The headline workload: Q2 on n^3 elements, GRF sources of the evaluation seeds; the
+    learned FP32 cycle (shipped nets, per-cycle fallback), the FP32 cycle without the net and
+    plain FP64 CG, each to 1e-8; step i solves seed i mod len(seeds).  Seconds per solve."""
     import torch
     from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64
-    from paper_1408_6497_amd import train as T
     from workloads import grf
-    w = T.load(os.path.join(ROOT, "paper_1408_6497_amd", "weights", "q2_depth0.gmgw"))["w"]
-    out = {"workload": f"Q2, {n}^3 elements ({(2 * n) ** 3} DoFs), GRF |k|^-alpha sources, seeds "
-                       f"{seeds[0]}..{seeds[-1]}, to 1e-8", "seeds": list(seeds)}
-    for name, kw in (("plain_fp64", dict(vcycle_prec=GMG_FP64)), ("fp32", dict(vcycle_prec=GMG_FP32)),
-                     ("learned_fp32", dict(use_learned=1, learned_min_depth=2)),
-                     ("learned_fp32_every_depth", dict(use_learned=1))):
+    N = 2 * n
+    sources = [grf(N, sd, device="cuda")[0] for sd in seeds]
+    out = {"workload": f"Q2, {n}^3 elements ({N ** 3} DoFs), GRF |k|^-alpha sources, seeds "
+                       f"{seeds[0]}..{seeds[-1]} in turn, to 1e-8", "seeds": list(seeds)}
+    for name, kw in (("learned_fp32", LEARNED_OPTS), ("fp32", dict(vcycle_prec=GMG_FP32)),
+                     ("plain_fp64", dict(vcycle_prec=GMG_FP64))):
         ctx = Context(2, n, 0, seed=0, **kw)
         if name.startswith("learned"):
-            ctx.net_set_weights(0, w)
-        times, iters, fbs, rels = [], [], [], []
-        for i, sd in enumerate(seeds):
-            f, _ = grf(ctx.lattice(), sd, device="cuda")
-            u = torch.empty_like(f)
-            if i == 0:
-                ctx.solve(f, u, 1e-8)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            info = ctx.solve(f, u, 1e-8)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            iters.append(info.inner_iters)
-            fbs.append(info.fallbacks)
-            rels.append(info.rel_residual_f64)
-            del f, u
-        out[name] = {"mean_s": sum(times) / len(times), "iters": iters, "fallbacks": fbs, "max_rel_residual": max(rels)}
-        log(f"[bench] learned workload {name}: {out[name]}")
+            out["net_depths"] = load_nets(ctx)
+        u = torch.empty_like(sources[0])
+        for i in range(max(warmup, 1)):
+            ctx.solve(sources[i % len(seeds)], u, 1e-8)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            infos.append(ctx.solve(sources[i % len(seeds)], u, 1e-8))
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        out[name] = {"s": t, "iters": [x.inner_iters for x in infos[:len(seeds)]],
+                     "fallbacks": [x.fallbacks for x in infos[:len(seeds)]],
+                     "max_rel_residual_f64": max(x.rel_residual_f64 for x in infos)}
+        log(f"[bench] C4 {name}: {t * 1e3:.2f} ms/solve {out[name]}")
         ctx.close()
-        del ctx
+        del ctx, u
         torch.cuda.empty_cache()
+    del sources
+    torch.cuda.empty_cache()
+    return out
+
+
+def c4_roofline(n=256, seed=EVAL_SEEDS[0]):
+    """Per-kernel durations of one learned solve of the headline workload, from the library's
+    HIP events (timing=1: the same kernels and arguments, launched eagerly): the dominant
+    kernel, the FP32 smoother step k_apply_col<float, 2, 1, Cheb> on the levels that keep the
+    polynomial, and the learned corrections."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32
+    from workloads import grf
+    ctx = Context(2, n, 0, seed=0, timing=1, **LEARNED_OPTS)
+    load_nets(ctx)
+    f = grf(2 * n, seed, device="cuda")[0]
+    u = torch.empty_like(f)
+    ctx.solve(f, u, 1e-8)
+    torch.cuda.synchronize()
+    ctx.timing_reset()
+    info = ctx.solve(f, u, 1e-8)
+    launches, sec, algo_bytes, per_level = smoother_roofline(ctx, 2)
+    learned = []
+    for l in range(ctx.levels):
+        c, s_ = ctx.timing(l, Context.KIND_LEARNED, GMG_FP32)
+        if c:
+            learned.append({"level": l, "lattice": ctx.lattice(l), "corrections": c, "avg_us": s_ / c * 1e6})
+    ctx.close()
+    del f, u
+    torch.cuda.empty_cache()
+    return launches, sec, algo_bytes, per_level, learned, info
+
+
+def c1_workload(steps=20):
+    """C1: Q1 on 32^3 elements, 4 levels, f = 12 pi^2 sin sin sin, plain FP64 to 1e-10; the
+    solve launched through the captured HIP graphs and eagerly; the amplitude of the solution
+    against the closed-form discrete one (0.99679344074)."""
+    import numpy as np
+    import torch
+    from paper_1408_6497_amd import Context
+    from workloads import sin_exact, sin_source
+    out = {"workload": "Q1, 32^3 elements, 4 levels, 12 pi^2 sin sin sin, plain FP64 to 1e-10"}
+    for name, kw in (("graph", {}), ("no_graph", dict(no_graphs=1))):
+        ctx = Context(1, 32, 4, seed=0, **kw)
+        x1 = ctx.dof_coords_1d()
+        f = sin_source(x1, device="cuda")
+        u = torch.empty_like(f)
+        ctx.solve(f, u, 1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = ctx.solve(f, u, 1e-10)
+        torch.cuda.synchronize()
+        ue = sin_exact(x1)
+        amp = float(np.dot(u.cpu().numpy(), ue) / np.dot(ue, ue))
+        out[name] = {"s": (time.perf_counter() - t0) / steps, "iters": info.inner_iters,
+                     "rel_residual_f64": info.rel_residual_f64, "amplitude": amp,
+                     "amplitude_err": abs(amp - 0.99679344074) / 0.99679344074}
+        ctx.close()
+    log(f"[bench] C1: {out}")
+    return out
+
+
+def spectral_workload(sizes=(256, 512), steps=5):
+    """The paper's FFT Poisson method (Section 2.1): the spectral solve on the N^3 grid, test
+    case 1 of Section 3 at frequency N/4 (u = sin sin sin, exact on the grid); seconds per solve
+    and the max error."""
+    import torch
+    from paper_1408_6497_amd import SpectralSolver
+    out = {"workload": "spectral FFT Poisson solve (own transforms), f = 12 pi^2 k^2 sss at k = N/4"}
+    for N in sizes:
+        k = N // 4
+        x = torch.arange(N, dtype=torch.float64, device="cuda") / N
+        s = torch.sin(2 * math.pi * k * x)
+        ue = (s[:, None, None] * s[None, :, None] * s[None, None, :]).reshape(-1)
+        f = 12 * math.pi ** 2 * k * k * ue
+        u = torch.empty_like(f)
+        sp = SpectralSolver(N)
+        sp.solve(f, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sp.solve(f, u)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        out[f"N{N}"] = {"s": t, "max_err": float((u - ue).abs().max()), "gbs_at_144B_per_point": 144 * N ** 3 / t * 1e-9}
+        sp.close()
+        del f, u, ue, s
+        torch.cuda.empty_cache()
+    log(f"[bench] spectral: {out}")
+    return out
+
+
+def c2_workload(steps, warmup):
+    """Q2 on 128^3 elements (256^3 DoFs), 32 Gaussians (sigma U[0.02, 0.1], seed 0): FP32 cycles in
+    FP64 flexible CG against plain FP64 CG, to 1e-8, and the FP32 smoother step's bandwidth on
+    its 256^3- and 128^3-node levels (HIP events in an eager repeat)."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64
+    from workloads import gaussian_params, gaussian_source
+    q, n = 2, 128
+    out = {"workload": "Q2, 128^3 elements (256^3 DoFs), 32 Gaussians sigma U[0.02, 0.1], seed 0, to 1e-8"}
+    f = None
+    for name, kw in (("fp32", dict(vcycle_prec=GMG_FP32)), ("plain_fp64", dict(vcycle_prec=GMG_FP64))):
+        ctx = Context(q, n, 0, seed=0, **kw)
+        if f is None:
+            f = gaussian_source(ctx.dof_coords_1d(), gaussian_params(0, 32, 0.02, 0.1), device="cuda")
+            u = torch.empty_like(f)
+        for _ in range(max(warmup, 1)):
+            ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        out[name] = {"s": (time.perf_counter() - t0) / steps, "iters": info.inner_iters,
+                     "rel_residual_f64": info.rel_residual_f64}
+        ctx.close()
+    ctxt = Context(q, n, 0, seed=0, vcycle_prec=GMG_FP32, timing=1)
+    ctxt.solve(f, u, 1e-8)
+    torch.cuda.synchronize()
+    ctxt.timing_reset()
+    ctxt.solve(f, u, 1e-8)
+    launches, sec, algo_bytes, per_level = smoother_roofline(ctxt, q)
+    out["smoother_step"] = {"launches": launches, "avg_us": sec / max(launches, 1) * 1e6,
+                            "gbs": algo_bytes / sec * 1e-9 if sec > 0 else None, "per_level": per_level}
+    ctxt.close()
+    log(f"[bench] c2 workload: {out}")
     return out
 
 
@@ -217,8 +396,11 @@ def octree_workload(steps=5):
     out = {"workload": "Q2 octree, leaf levels 3..9 refined on a gradient bound around 4 Gaussians "
                        "(sigma 1e-3, seed 0), hanging nodes, to 1e-8", "leaves": int(leaves[0].size),
            "tree_build_s": t_tree}
-    for name, kw in (("plain_fp64", dict(vcycle_prec=GMG_FP64)), ("fp32", dict(vcycle_prec=GMG_FP32))):
+    for name, kw in (("plain_fp64", dict(vcycle_prec=GMG_FP64)), ("fp32", dict(vcycle_prec=GMG_FP32)),
+                     ("learned_fp32", LEARNED_OPTS)):
         ctx = Context(2, 0, leaves=leaves, seed=0, **kw)
+        if name.startswith("learned"):
+            load_nets(ctx)
         f = torch.from_numpy(gaussian_source_points(ctx.dof_coords(), p)).cuda()
         u = torch.empty_like(f)
         ctx.solve(f, u, 1e-8)
@@ -228,7 +410,8 @@ def octree_workload(steps=5):
             info = ctx.solve(f, u, 1e-8)
         torch.cuda.synchronize()
         out[name] = {"s": (time.perf_counter() - t0) / steps, "iters": info.inner_iters,
-                     "rel_residual_f64": info.rel_residual_f64, "setup_s": info.t_setup}
+                     "rel_residual_f64": info.rel_residual_f64, "setup_s": info.t_setup,
+                     "fallbacks": info.fallbacks}
         out["dofs"] = ctx.num_dofs()
         out["levels"] = ctx.levels
         ctx.close()
@@ -311,19 +494,19 @@ def fft_workload(n=256, steps=5, q=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-apply-bench", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the learned-smoother (512^3 DoFs), Q4 and octree workloads")
-    ap.add_argument("--profile-workload", choices=("learned", "q4", "octree"), default=None,
+                    help="skip the other workloads (Q2/Q4 on 256^3 DoFs, octree, sharp layer, C1, FFT methods)")
+    ap.add_argument("--profile-workload", choices=("learned", "q4", "octree", "c2", "spectral"), default=None,
                     help="for profilers: run only this workload and print its JSON (no timed bench step)")
     ap.add_argument("--profile-n", type=int, default=256,
                     help="elements per direction of the learned workload under --profile-workload")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc runs: a 256 MiB device copy (counter calibration), then one eager "
-                         "mixed solve of the bench problem; prints nothing on stdout")
+                         "learned solve of the headline problem; prints nothing on stdout")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -331,83 +514,54 @@ def main():
 
     import torch
     from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64
-    from workloads import gaussian_params, gaussian_source
+    from workloads import gaussian_params, gaussian_source, grf
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.profile_workload:
         if args.profile_workload == "learned":
-            res = learned_workload(seeds=(30000, 30001), n=args.profile_n)
+            res = c4_solves(2, 1, n=args.profile_n, seeds=EVAL_SEEDS[:2])
         elif args.profile_workload == "q4":
             res = q4_workload()
+        elif args.profile_workload == "c2":
+            res = c2_workload(3, 1)
+        elif args.profile_workload == "spectral":
+            res = spectral_workload(sizes=(512,), steps=3)
         else:
             res = octree_workload()
         print(json.dumps(res), flush=True)
         return
-    q, n, seed = 2, 128, 0
     if args.traffic_probe:
         a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)          # reads and writes 256 MiB each
         torch.cuda.synchronize()
-        ctxp = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP32, no_graphs=1)
-        f = gaussian_source(ctxp.dof_coords_1d(), gaussian_params(seed, 32, 0.02, 0.1), device="cuda")
+        ctxp = Context(2, 256, 0, seed=0, no_graphs=1, **LEARNED_OPTS)
+        load_nets(ctxp)
+        f = grf(512, EVAL_SEEDS[0], device="cuda")[0]
         u = torch.empty_like(f)
         ctxp.solve(f, u, 1e-8)
         torch.cuda.synchronize()
         log("[bench] traffic probe done")
         return
-    log(f"[bench] setup Q{q} n={n}")
-    ctx32 = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP32)
-    ctx64 = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP64)
-    f = gaussian_source(ctx32.dof_coords_1d(), gaussian_params(seed, 32, 0.02, 0.1), device="cuda")
-    u = torch.empty_like(f)
-    for _ in range(args.warmup):
-        ctx32.solve(f, u, 1e-8)
-        ctx64.solve(f, u, 1e-8)
 
-    # ---- timed region: K solves, FP32 V-cycles inside FP64 flexible CG
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        infos.append(ctx32.solve(f, u, 1e-8))
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / args.steps
-    log(f"[bench] mixed solve {t_mixed * 1e3:.2f} ms/step, iters={infos[-1].inner_iters} "
-        f"rel={infos[-1].rel_residual_f64:.2e}")
+    # ---- timed region: K learned solves of the headline workload (and the same sources
+    # with the FP32 cycle without the net and with plain FP64 CG)
+    log("[bench] headline: Q2 on 256^3 elements, GRF evaluation seeds")
+    c4 = c4_solves(args.steps, args.warmup)
+    t_learned = c4["learned_fp32"]["s"]
 
-    # ---- plain FP64 reference solve, same problem
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info64 = ctx64.solve(f, u, 1e-8)
-    torch.cuda.synchronize()
-    t_fp64 = (time.perf_counter() - t0) / args.steps
-    log(f"[bench] plain FP64 solve {t_fp64 * 1e3:.2f} ms/step, iters={info64.inner_iters}")
-
-    # ---- per-launch durations: the same solve, launched eagerly with HIP events
-    # around every operator-apply launch (identical kernels and arguments)
-    ctxt = Context(q, n, 0, seed=seed, vcycle_prec=GMG_FP32, timing=1)
-    ctxt.solve(f, u, 1e-8)
-    torch.cuda.synchronize()
-    ctxt.timing_reset()
-    info_t = ctxt.solve(f, u, 1e-8)
-    launches, sec, algo_bytes, per_level = smoother_roofline(ctxt, q)
+    # ---- per-launch durations of the dominant kernel inside the same (learned) solve
+    launches, sec, algo_bytes, per_level, learned_apps, info_t = c4_roofline()
     avg_dur = sec / max(launches, 1)
     achieved = algo_bytes / sec * 1e-9 if sec > 0 else 0.0
     log(f"[bench] smoother kernel: {launches} launches, avg {avg_dur * 1e6:.2f} us, {achieved:.0f} GB/s")
 
     apply = {}
     if not args.no_apply_bench:
-        apply["q2_256cubed_fp32"] = apply_rate(ctxt, GMG_FP32)
-        apply["q2_256cubed_fp64"] = apply_rate(ctxt, GMG_FP64)
-        ctxt.close()
-        del ctx64
-        torch.cuda.empty_cache()
         # 512^3 DoFs for every order (Q1 on 512^3, Q2 on 256^3, Q4 on 128^3 elements)
         for qq, nn in ((2, 256), (1, 512), (4, 128)):
-            big = Context(qq, nn, 0, seed=seed, timing=1, lambda_override=1.0)
+            big = Context(qq, nn, 0, seed=0, timing=1, lambda_override=1.0)
             apply[f"q{qq}_512cubed_fp32"] = apply_rate(big, GMG_FP32)
             apply[f"q{qq}_512cubed_fp64"] = apply_rate(big, GMG_FP64)
             big.close()
@@ -417,10 +571,12 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        extra["learned"] = learned_workload()
+        extra["c2_gaussians"] = c2_workload(args.steps, 1)
         extra["q4_sharp"] = q4_workload()
         extra["octree"] = octree_workload()
+        extra["c1"] = c1_workload()
         extra["sharp_layer"] = sharp_layer_workload()
+        extra["spectral_fft"] = spectral_workload()
         extra["fft_q1"] = fft_workload()
         extra["fft_q2"] = fft_workload(n=128, q=2)
         extra["fft_q4"] = fft_workload(n=64, q=4)
@@ -434,41 +590,45 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": t_mixed,
+        "value": t_learned,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_mixed * 1e3,
+        "ms_per_step": t_learned * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "bf16+f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": ("Q2 periodic Poisson, uniform 128^3 elements (256^3 DoFs), 32-Gaussian source seed 0, "
-                         "FP32 Chebyshev(3) V(2,2) cycles preconditioning FP64 flexible CG, to 1e-8"),
-            "order": q, "elements_per_dim": n, "dofs": ctx32.num_dofs(), "levels": ctx32.levels,
-            "smoother": "chebyshev-jacobi", "learned": False,
+            "workload": ("Q2 periodic Poisson, uniform 256^3 elements (512^3 DoFs), Gaussian-random-field sources "
+                         "(|k|^-alpha, alpha ~ U[2,4], evaluation seeds 30000-30004 in turn), learned smoother "
+                         "(BF16 3-layer conv net on depths >= 2, per-cycle fallback) in FP32 Chebyshev(3) V(2,2) "
+                         "cycles preconditioning FP64 flexible CG, to 1e-8"),
+            "order": 2, "elements_per_dim": 256, "dofs": (2 * 256) ** 3, "learned": True,
+            "learned_min_depth": LEARNED_OPTS["learned_min_depth"], "net_depths": c4.get("net_depths"),
         },
         "solve": {
-            "mixed_s": t_mixed, "mixed_iters": infos[-1].inner_iters,
-            "mixed_rel_residual_f64": infos[-1].rel_residual_f64,
-            "plain_fp64_s": t_fp64, "plain_fp64_iters": info64.inner_iters,
-            "plain_fp64_rel_residual": info64.rel_residual_f64,
-            "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
+            "learned_fp32_s": t_learned, "fp32_s": c4["fp32"]["s"], "plain_fp64_s": c4["plain_fp64"]["s"],
+            "speedup_learned_vs_plain_fp64": c4["plain_fp64"]["s"] / t_learned,
+            "speedup_learned_vs_fp32": c4["fp32"]["s"] / t_learned,
+            "speedup_fp32_vs_plain_fp64": c4["plain_fp64"]["s"] / c4["fp32"]["s"],
+            "detail": c4,
         },
         "apply": apply,
         "roofline": {
-            "kernel": "k_apply_col<float, 2, 1, Cheb>: FP32 smoother step on the 256^3 and 128^3 levels",
+            "kernel": ("k_apply_col<float, 2, 1, Cheb>: the FP32 smoother step on the 512^3-, 256^3- and 128^3-node "
+                       "levels of the learned solve"),
             "measured": ("HIP events on the library stream around each run of consecutive launches of this "
-                         "kernel (one smoothing phase) in an eager repeat of the timed solve"),
+                         "kernel (one smoothing phase) in an eager repeat of a timed learned solve (seed 30000)"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (traffic["traffic_bytes_per_launch"] if traffic else None),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00, copy-calibrated)",
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": algo_bytes / max(launches, 1),
             "launches": launches, "avg_launch_us": avg_dur * 1e6, "per_level": per_level,
+            "learned_corrections": learned_apps,
         },
         "cpu_baseline": cpu,
         "workloads": extra,

@@ -33,7 +33,7 @@
  *    call says so.
  *  - A context is not thread-safe; distinct contexts are independent.
  *  - Errors: GMG_E_ARG for an invalid argument (null pointer, level out of
- *    range, order not in {1,2,4}, n not a power of two, ...); GMG_E_HIP when a
+ *    range, order not in {1, ..., 8}, n not a power of two, ...); GMG_E_HIP when a
  *    HIP runtime call fails (the context should then be destroyed);
  *    GMG_E_NOCONV when a solve stops at max_iters (info is filled);
  *    GMG_E_BREAKDOWN for NaN/Inf or a non-positive p^T A p; GMG_E_OOM when a
@@ -64,11 +64,16 @@ typedef enum {
 
 typedef enum { GMG_FP64 = 0, GMG_FP32 = 1 } gmg_prec;
 
-/* Mesh description.  Uniform periodic meshes: n = elements per direction
- * (a power of two, 2 <= n <= 512 (256 for q = 4), and q*n >= 4), order in {1, 2, 4}.
+/* Mesh description.  Uniform periodic meshes: n = elements per direction, a power
+ * of two with q*n >= 4, and order q in {1, ..., 8} (Section 2.3.2 admits up to 16).
+ * Orders 1, 2, 4 run the specialised streaming kernels, 2 <= n <= 512 (256 for q = 4);
+ * orders 3, 5, 6, 7, 8 run generic kernels (three banded passes per operator apply,
+ * one-axis transfer passes), 1 <= n <= 64, and their hierarchies may end on a single
+ * periodic element (n = 1, where coarsening ends, Section 2.3.1).
  * levels = number of multigrid levels (level 0 coarsest, levels-1 finest, n
  * halves per level, Section 2.3.1); 0 selects the deepest hierarchy whose
- * coarsest level has at most 512 DoFs and at least 2 elements per direction.
+ * coarsest level has at most 512 DoFs and at least 2 elements per direction (1 for
+ * the generic orders).
  * The coarsest level is solved with a dense FP64 pseudo-inverse, so an explicit
  * `levels` must leave at most 512 DoFs there (else GMG_E_ARG).
  *
@@ -291,7 +296,10 @@ gmg_status gmg_dot_noalloc(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x
  * learned cycle is kept only if ||r - A z|| / ||r|| is no larger than the plain
  * cycle's last measured value (initialized by two plain cycles on a seeded
  * vector); otherwise the plain FP32 cycle replaces it (info->fallbacks).
- * The lattice must have at least 16 nodes per direction (GMG_E_ARG otherwise).
+ * The lattice must have at least 16 nodes per direction (GMG_E_ARG otherwise).  On an
+ * octree hierarchy the levels whose leaves all have one level are uniform lattices (their
+ * DoFs are numbered in lattice order) and take the net like uniform levels; the adaptive
+ * levels keep the polynomial smoother (a lattice convolution is undefined across leaf sizes).
  * ------------------------------------------------------------------------- */
 
 /* FP32 master weights of one depth (host, 7776 values); resets its Adam state. */

@@ -60,6 +60,21 @@ static_assert(S_SSUM + 32 <= S_RS && S_WS < kNumScal, "scalar slots overlap");
 
 struct Level {
   int n = 0, N = 0;   // uniform: elements and lattice nodes per direction (0 on octree levels)
+  // lattice nodes per direction of a level whose DoFs form a uniform lattice in lattice
+  // order: every uniform level, and an octree level whose leaves all have one level (its
+  // DoF numbering is the lattice order); 0 otherwise.  Such a level has the uniform
+  // tables in `tab` (the learned correction reads its Jacobi diagonal by node class).
+  int latN = 0;
+  // orders without a specialised kernel (q = 3, 5, 6, 7, 8): the generic passes' device
+  // tables, and the node-class tables (q^3 values) in device memory plus a host copy of
+  // the diagonal
+  bool gen = false;
+  GenOp gstiff{}, gmass{};
+  const double* gdiag = nullptr;
+  const double* gdsqrt = nullptr;
+  const double* gdinv_sqrt = nullptr;
+  const double* gwint = nullptr;
+  std::vector<double> gdiag_host;
   int64_t size = 0;
   LevelTables tab{};
   // octree levels: device arrays, and host copies of the leaves and DoF positions
@@ -92,12 +107,16 @@ struct gmg_ctx {
   // [3..6] the learned / plain test sequences of the learned cycle (see precondition)
   // captured launch sequences: 0-2 V-cycles, 3-6 learned cycles under test, 7-8 the
   // cycle plus direction update of FP64 flexible CG around FP32 cycles
-  static constexpr int kGraphKeys = 9;
+  // 9-10: the direction updates after a learned cycle in that same loop
+  static constexpr int kGraphKeys = 11;
   hipGraphExec_t vgraph[kGraphKeys] = {};
   bool graph_failed[kGraphKeys] = {};
   bool suppress_learned = false;
   std::vector<Level> lv;
   TransferTab xfer{};
+  GenXfer gxfer{};             // transfer weights of an order without a specialised kernel
+  bool gen = false;            // the order has no specialised kernels (every level is generic)
+  void* gtmp[2][4] = {};       // the generic apply's four temporaries, per precision
   void* tA[2] = {nullptr, nullptr};
   void* tB[2] = {nullptr, nullptr};
   bool have_prec[2] = {false, false};
@@ -206,6 +225,8 @@ gmg_status ensure_prec(gmg_ctx* c, int pi) {
   STCHK(dalloc(c, &c->kp[pi], nf * es));
   STCHK(dalloc(c, &c->kw[pi], nf * es));
   STCHK(dalloc(c, &c->kc[pi], nf * es));
+  if (c->gen)
+    for (int t = 0; t < 4; ++t) STCHK(dalloc(c, &c->gtmp[pi][t], nf * es));
   c->have_prec[pi] = true;
   return GMG_OK;
 }
@@ -313,7 +334,7 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
                     int d1 = -1) {
   const Level& L = c->lv[l];
   // the uniform kernel moves q consecutive values per vector access
-  const uintptr_t al = static_cast<uintptr_t>(L.oct ? 1 : c->q) * esize(pi);
+  const uintptr_t al = static_cast<uintptr_t>((L.oct || L.gen) ? 1 : c->q) * esize(pi);
   for (const void* ptr : {x, static_cast<const void*>(out), b, xp, static_cast<const void*>(x1)})
     if (ptr && (reinterpret_cast<uintptr_t>(ptr) % al) != 0)
       return fail(c, GMG_E_ARG, "device buffer not aligned to q elements");
@@ -331,7 +352,8 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.x1 = x1;
   a.s0 = s0;
   if (epi == Epi::ApplyDot || epi == Epi::ResidualSums) {
-    if (L.oct || pi != 0 || mass || d0 < 0 || d1 < 0) return fail(c, GMG_E_ARG, "fused apply and dot unsupported here");
+    if (L.oct || L.gen || pi != 0 || mass || d0 < 0 || d1 < 0)
+      return fail(c, GMG_E_ARG, "fused apply and dot unsupported here");
     a.part = c->part;
     a.part_cap = c->part_cap;
     a.sc = c->scal;
@@ -362,6 +384,9 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   if (L.oct) {
     const OctApply oa{x, out, b, xp, c1, c2, epi, c->oye[pi]};
     HIPCHK(c, launch_oct_apply(L.od, pi == 1, mass, oa, c->stream));
+  } else if (L.gen) {
+    if (!c->gtmp[pi][0]) return fail(c, GMG_E_STATE, "generic apply temporaries of this precision not allocated");
+    HIPCHK(c, launch_gen_apply(mass ? L.gmass : L.gstiff, pi == 1, a, c->gtmp[pi], c->stream));
   } else {
     HIPCHK(c, launch_apply(mass ? L.tab.mass : L.tab.stiff, pi == 1, a, c->stream));
   }
@@ -416,6 +441,7 @@ gmg_status project(gmg_ctx* c, int pi, int64_t n, void* v) {
 // out = w D^-1 b on one level
 hipError_t dinv_scale(gmg_ctx* c, const Level& L, bool f32, double w, const void* b, void* out) {
   if (L.oct) return launch_vec_scale(f32, L.size, L.od.dinv64, w, b, out, c->stream);
+  if (L.gen) return launch_gclass_scale(f32, c->q, L.N, L.gstiff.dinv64, w, b, out, c->stream);
   return launch_class_scale(f32, c->q, L.N, L.tab.stiff.dinv, w, b, out, c->stream);
 }
 
@@ -458,7 +484,7 @@ gmg_status smooth(gmg_ctx* c, int l, int pi, const void* b, void* u, int nu, boo
     const int deg = c->opt.cheb_degree;
     // from a zero guess on a uniform level the scaling x_1 = D^-1 b / theta is not a
     // pass of its own: the next step forms x_1 from b as it loads it (Epi::ChebZero)
-    const bool fuse_zero = !L.oct && deg >= 2;
+    const bool fuse_zero = !L.oct && !L.gen && deg >= 2;
     double s0 = 0.0;
     for (int app = 0; app < nu; ++app) {
       double rho = 1.0 / sigma;
@@ -507,6 +533,7 @@ gmg_status restrict_level(gmg_ctx* c, int l, int pi, const void* rf, void* rc) {
   const bool f32 = pi == 1;
   return timed(c, l, K_RESTRICT, pi, [&]() -> gmg_status {
     if (c->lv[l].oct) HIPCHK(c, launch_oct_restrict(c->lv[l].od, c->lv[l - 1].size, f32, rf, rc, c->stream));
+    else if (c->lv[l].gen) HIPCHK(c, launch_gen_restrict(c->gxfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream));
     else
       HIPCHK(c, launch_restrict(c->xfer, f32, rf, c->tA[pi], c->tB[pi], rc, Nc, c->stream, !c->opt.no_fused_transfer));
     return GMG_OK;
@@ -519,6 +546,7 @@ gmg_status prolong_level(gmg_ctx* c, int l, int pi, const void* ec, void* uf) {
   const bool f32 = pi == 1;
   return timed(c, l, K_PROLONG, pi, [&]() -> gmg_status {
     if (c->lv[l].oct) HIPCHK(c, launch_oct_prolong(c->lv[l].od, f32, ec, uf, c->stream));
+    else if (c->lv[l].gen) HIPCHK(c, launch_gen_prolong(c->gxfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream));
     else
       HIPCHK(c, launch_prolong(c->xfer, f32, ec, c->tB[pi], c->tA[pi], uf, Nc, c->stream, !c->opt.no_fused_transfer));
     return GMG_OK;
@@ -544,14 +572,15 @@ bool learned_on_level(const gmg_ctx* c, int l, int pi) {
   const int d = c->L - 1 - l;
   if (c->opt.learned_depths > 0 && d >= c->opt.learned_depths) return false;
   if (d < c->opt.learned_min_depth) return false;
-  if (c->lv[l].oct) return false;  // the lattice convolution needs a uniform level
-  return c->opt.use_learned && !c->suppress_learned && pi == 1 && l > 0 && c->lv[l].N >= 16 &&
+  // the lattice convolution needs a level whose DoFs form a uniform lattice (every uniform
+  // level; of an octree hierarchy, the levels whose leaves all have one level)
+  return c->opt.use_learned && !c->suppress_learned && pi == 1 && l > 0 && c->lv[l].latN >= 16 &&
          net_for_depth(c, d) >= 0;
 }
 
 gmg_status ensure_lcache(gmg_ctx* c, int l) {
   if (c->lcache[l]) return GMG_OK;
-  return dalloc(c, &c->lcache[l], static_cast<size_t>(net_cache_bytes(c->lv[l].N)));
+  return dalloc(c, &c->lcache[l], static_cast<size_t>(net_cache_bytes(c->lv[l].latN)));
 }
 
 // u <- u + s N_d(D^-1 (b - A u) / s) on level l (FP32), s = RMS(D^-1 (b - A u)).
@@ -562,8 +591,8 @@ gmg_status learned_correction(gmg_ctx* c, int l, const void* b, void* u) {
   return timed(c, l, K_LEARNED, 1, [&]() -> gmg_status {
     STCHK(apply_op(c, l, 1, Epi::Residual, u, L.xp[1], b, nullptr, 0, 0));
     HIPCHK(c, launch_net_input(static_cast<const float*>(L.xp[1]), L.tab.stiff.dinv, c->q, c->scal + S_SSUM + l,
-                               c->part, c->part_cap, L.N, c->lcache[l], c->stream));
-    HIPCHK(c, launch_net_forward(c->nets[d], L.N, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
+                               c->part, c->part_cap, L.latN, c->lcache[l], c->stream));
+    HIPCHK(c, launch_net_forward(c->nets[d], L.latN, c->lcache[l], 1, c->scal + S_SSUM + l, static_cast<float*>(u),
                                  c->stream, false));
     return GMG_OK;
   });
@@ -602,7 +631,7 @@ void phase_steps(const gmg_ctx* c, const Level& L, int nu, int* count, double* c
 // The level of 16^3 nodes next to the coarsest runs its whole cycle in two
 // one-workgroup launches around the coarsest solve (uniform levels, plain smoother).
 bool fused_tail(const gmg_ctx* c, int l, int pi, TailSteps* st) {
-  if (l != 1 || c->opt.no_fused_tail || c->lv[l].oct || learned_on_level(c, l, pi)) return false;
+  if (l != 1 || c->opt.no_fused_tail || c->lv[l].oct || c->lv[l].gen || learned_on_level(c, l, pi)) return false;
   const int deg = c->opt.smoother == 1 ? 1 : c->opt.cheb_degree;
   if (c->opt.nu_pre < 0 || c->opt.nu_post < 0 || deg < 1 ||
       static_cast<int64_t>(c->opt.nu_pre + c->opt.nu_post) * deg > kTailMaxSteps)
@@ -770,14 +799,20 @@ bool learned_precond(const gmg_ctx* c, int vpi) {
   return c->opt.use_learned && vpi == 1 && net_for_depth(c, 0) >= 0;
 }
 
-gmg_status precondition(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
-  if (!learned_precond(c, vpi)) return run_vcycle(c, pi, vpi, r, z);
-  const int l = c->L - 1;
-  const int64_t n = c->lv[l].size;
+// The two halves of a learned preconditioner step: enqueue the learned cycle under test
+// (z32 = V_L r, then ||r32 - A z32||^2 and ||r32||^2; reads nothing back), and read its
+// contraction, run the plain cycle instead when it is worse (a fallback), and record the
+// decision.  The mixed-precision flexible CG enqueues the first half behind the read-back
+// of the residual norm and takes the second once the norm says the iteration goes on.
+gmg_status learned_test_enqueue(gmg_ctx* c, int pi, int vpi, const void* r) {
   if (c->rho_plain < 0.0) return fail(c, GMG_E_STATE, "learned cycle used before prepare_learned");
+  const int base = 3 + (pi == vpi ? 2 : 0);
+  return graph_run(c, base, [&] { return test_cycle(c, pi, r, false); });
+}
+
+gmg_status learned_decide(gmg_ctx* c, int pi, int vpi, const void* r) {
   double hs[kNumScal];
   const int base = 3 + (pi == vpi ? 2 : 0);
-  STCHK(graph_run(c, base, [&] { return test_cycle(c, pi, r, false); }));
   STCHK(read_scalars(c, hs, kNumScal));
   const double rho_l = std::sqrt(hs[S_LRES] / hs[S_LRR]);
   const double rho_ref = c->rho_plain;
@@ -789,6 +824,15 @@ gmg_status precondition(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
     c->rho_plain = rho_p = std::sqrt(hs[S_LRES] / hs[S_LRR]);
   }
   c->hist_cyc.insert(c->hist_cyc.end(), {rho_l, rho_ref, rho_p});
+  return GMG_OK;
+}
+
+gmg_status precondition(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
+  if (!learned_precond(c, vpi)) return run_vcycle(c, pi, vpi, r, z);
+  const int l = c->L - 1;
+  const int64_t n = c->lv[l].size;
+  STCHK(learned_test_enqueue(c, pi, vpi, r));
+  STCHK(learned_decide(c, pi, vpi, r));
   if (pi == 0) HIPCHK(c, launch_cast_f2d(n, static_cast<const float*>(c->kz[1]), static_cast<double*>(z), c->stream));
   else if (z != c->kz[1]) HIPCHK(c, launch_copy(true, n, c->kz[1], z, c->stream));
   return GMG_OK;
@@ -808,8 +852,10 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
                                               1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
                                               1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
   // the level's diagonal as a class table (uniform) or a vector (octree)
-  auto scale = [&](const double* tab, const double* vec, double a, const void* in, void* out) {
-    return L.oct ? launch_vec_scale(false, n, vec, a, in, out, s) : launch_class_scale(false, q, L.N, tab, a, in, out, s);
+  auto scale = [&](const double* tab, const double* vec, const double* gtab, double a, const void* in, void* out) {
+    if (L.oct) return launch_vec_scale(false, n, vec, a, in, out, s);
+    if (L.gen) return launch_gclass_scale(false, q, L.N, gtab, a, in, out, s);
+    return launch_class_scale(false, q, L.N, tab, a, in, out, s);
   };
   HIPCHK(c, launch_splitmix_start(c->opt.seed + static_cast<uint64_t>(l), n, static_cast<double*>(v), s));
   // project out the null vector D^1/2 1 of the scaled operator
@@ -817,6 +863,10 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
   if (L.oct) {
     w0w0 = L.w0w0;
     HIPCHK(c, launch_dot(false, n, L.dsqrt64, v, c->part, c->scal + S_TMP, s));
+  } else if (L.gen) {
+    const int64_t per_class = n / (q * q * q);
+    for (int i = 0; i < q * q * q; ++i) w0w0 += L.gdiag_host[i] * static_cast<double>(per_class);
+    HIPCHK(c, launch_gclass_dot(false, q, L.N, L.gdsqrt, v, c->part, c->part_cap, c->scal + S_TMP, s));
   } else {
     const int64_t per_class = n / (q * q * q);
     for (int i = 0; i < q * q * q; ++i) w0w0 += L.tab.diag[i] * static_cast<double>(per_class);
@@ -825,18 +875,19 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
   double hs[kNumScal];
   STCHK(read_scalars(c, hs, kNumScal));
   if (L.oct) HIPCHK(c, launch_axpy(false, n, -hs[S_TMP] / w0w0, L.dsqrt64, v, s));
+  else if (L.gen) HIPCHK(c, launch_gclass_axpy(q, L.N, L.gdsqrt, -hs[S_TMP] / w0w0, static_cast<double*>(v), s));
   else HIPCHK(c, launch_class_axpy(false, q, L.N, L.tab.dsqrt, -hs[S_TMP] / w0w0, v, s));
   HIPCHK(c, launch_dot(false, n, v, v, c->part, c->scal + S_TMP, s));
   STCHK(read_scalars(c, hs, kNumScal));
-  HIPCHK(c, scale(ones, nullptr, 1.0 / std::sqrt(hs[S_TMP]), v, v));
+  HIPCHK(c, scale(ones, nullptr, nullptr, 1.0 / std::sqrt(hs[S_TMP]), v, v));
   HIPCHK(c, launch_fill_zero(false, n, vprev, s));
   const int steps = static_cast<int>(std::min<int64_t>(c->opt.lanczos_steps, n - 1));
   std::vector<double> alpha, beta;
   double bprev = 0.0, amax = 0.0;
   for (int j = 0; j < steps; ++j) {
-    HIPCHK(c, scale(L.tab.dinv_sqrt, L.dinv_sqrt64, 1.0, v, t));
+    HIPCHK(c, scale(L.tab.dinv_sqrt, L.dinv_sqrt64, L.gdinv_sqrt, 1.0, v, t));
     STCHK(apply_op(c, l, 0, Epi::Apply, t, w, nullptr, nullptr, 0, 0));
-    HIPCHK(c, scale(L.tab.dinv_sqrt, L.dinv_sqrt64, 1.0, w, w));
+    HIPCHK(c, scale(L.tab.dinv_sqrt, L.dinv_sqrt64, L.gdinv_sqrt, 1.0, w, w));
     if (bprev != 0.0) HIPCHK(c, launch_axpy(false, n, -bprev, vprev, w, s));
     HIPCHK(c, launch_dot(false, n, w, v, c->part, c->scal + S_TMP, s));
     STCHK(read_scalars(c, hs, kNumScal));
@@ -851,7 +902,7 @@ gmg_status lanczos(gmg_ctx* c, int l, double* lam_out) {
     beta.push_back(bnew);
     // vprev <- v ; v <- w / bnew
     std::swap(v, vprev);
-    HIPCHK(c, scale(ones, nullptr, 1.0 / bnew, w, v));
+    HIPCHK(c, scale(ones, nullptr, nullptr, 1.0 / bnew, w, v));
     bprev = bnew;
   }
   *lam_out = tridiag_max_eig(alpha, beta);
@@ -865,6 +916,8 @@ gmg_status zero_integral(gmg_ctx* c, int l, void* u) {
   const Level& F = c->lv[l];
   const int64_t n = F.size;
   if (F.oct) HIPCHK(c, launch_dot(false, n, F.wint64, u, c->part, c->scal + S_TMP, c->stream));
+  else if (F.gen)
+    HIPCHK(c, launch_gclass_dot(false, c->q, F.N, F.gwint, u, c->part, c->part_cap, c->scal + S_TMP, c->stream));
   else HIPCHK(c, launch_class_dot(false, c->q, F.N, F.tab.wint, u, c->part, c->part_cap, c->scal + S_TMP, c->stream));
   HIPCHK(c, launch_shift(false, n, c->scal, S_TMP, 1.0, u, c->stream));
   return GMG_OK;
@@ -896,11 +949,21 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   // sum(r) and sum(w), reduced with the step's products; the stored residual's
   // exact sum keeps the norm and the next prediction exact), and the direction
   // updates read the cycle's FP32 output directly (no FP64 copy of z)
-  const bool mixed = pi == 0 && vpi == 1 && flexible && r == c->kr[0] && !learned_precond(c, vpi);
+  const bool mixed = pi == 0 && vpi == 1 && flexible && r == c->kr[0];
+  // the learned cycle in that loop: z32 = V_L r32 under its per-cycle test (and the plain
+  // cycle on a fallback) takes the place of the captured plain cycle; the vector work
+  // after it is the same
+  const bool lrn = mixed && learned_precond(c, vpi);
+  bool lrn_pending = false;  // a learned cycle under test is enqueued, not yet decided
+  auto lrn_cycle = [&]() -> gmg_status {
+    if (!lrn_pending) STCHK(learned_test_enqueue(c, 1, 1, c->kr[1]));
+    lrn_pending = false;
+    return learned_decide(c, 1, 1, c->kr[1]);
+  };
   // on levels the column kernel runs, p.w and sum(w) come out of the apply itself, and
   // p.r is taken as (z - mean z).r: p_old.r = 0 by the choice of alpha, so the two agree
   // in exact arithmetic, and z.r joins the direction update's reduction
-  const bool fused_pw = mixed && !c->lv[l].oct && c->lv[l].N > 32;
+  const bool fused_pw = mixed && !c->lv[l].oct && !c->lv[l].gen && c->lv[l].N > 32;
   float* r32 = static_cast<float*>(c->kr[1]);
   const float* z32 = static_cast<const float*>(c->kz[1]);
   *iters = 0;
@@ -922,8 +985,9 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   // argument is fixed for the context)
   auto restart = [&]() -> gmg_status {
     if (mixed) {
-      return graph_run(c, 7, [&]() -> gmg_status {
-        STCHK(vcycle_seq(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+      if (lrn) STCHK(lrn_cycle());
+      return graph_run(c, lrn ? 9 : 7, [&]() -> gmg_status {
+        if (!lrn) STCHK(vcycle_seq(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
         if (fused_pw) {
           HIPCHK(c, launch_sums3_mixed(n, z32, static_cast<const double*>(r), c->part, c->scal, S_ZS, S_ZR, S_YS, s));
           HIPCHK(c, launch_combine(c->scal, S_PR, S_ZR, S_ZS, S_RS, inv_n, s));
@@ -942,8 +1006,9 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   };
   // the mixed solve's next cycle and direction update (z = V r, p = (z - mean z) + beta p)
   auto mixed_direction = [&]() -> gmg_status {
-    return graph_run(c, 8, [&]() -> gmg_status {
-      STCHK(vcycle_seq(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
+    if (lrn) STCHK(lrn_cycle());
+    return graph_run(c, lrn ? 10 : 8, [&]() -> gmg_status {
+      if (!lrn) STCHK(vcycle_seq(c, 1, 1, c->kr[1], c->kz[1]));  // z32 = V r32
       if (fused_pw) {
         HIPCHK(c, launch_sums4_mixed(n, z32, static_cast<const double*>(w), static_cast<const double*>(r), c->part,
                                      c->scal, S_ZS, S_ZW, S_YS, S_ZR, s));
@@ -983,8 +1048,13 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
   const bool speculate = mixed && !c->opt.no_speculation;
   if (speculate) {
     STCHK(scalars_async(c, kNumScal));
-    STCHK(restart());
-    have_dir = true;
+    if (lrn) {  // only the cycle under test; its decision waits for the norm
+      STCHK(learned_test_enqueue(c, 1, 1, c->kr[1]));
+      lrn_pending = true;
+    } else {
+      STCHK(restart());
+      have_dir = true;
+    }
     STCHK(scalars_wait(c, hs, kNumScal));
   } else {
     STCHK(read_scalars(c, hs, kNumScal));
@@ -1009,6 +1079,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       return fail(c, GMG_E_BREAKDOWN, "Krylov breakdown: non-finite residual");
     }
     if (std::sqrt(rr) <= tol_abs) {
+      lrn_pending = false;  // a speculative learned cycle is dropped with its residual
       if (!b_true) break;
       if (fused_pw) {
         // the true residual (into the unused FP64 z buffer) with its sums from the
@@ -1063,7 +1134,14 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
       HIPCHK(c, launch_shift(f32, n, c->scal, S_SUM, inv_n, r, s));
     }
     const bool spec = speculate && std::isfinite(rr) && std::sqrt(rr) > kSpecMargin * tol_abs;
-    if (spec) {
+    if (spec && lrn) {
+      // the learned cycle under test goes behind the read-back; its decision (a second
+      // read-back) and the direction update wait for the norm
+      STCHK(scalars_async(c, kNumScal));
+      STCHK(learned_test_enqueue(c, 1, 1, c->kr[1]));
+      lrn_pending = true;
+      STCHK(scalars_wait(c, hs, kNumScal));
+    } else if (spec) {
       STCHK(scalars_async(c, kNumScal));
       STCHK(mixed_direction());
       STCHK(scalars_wait(c, hs, kNumScal));
@@ -1092,7 +1170,7 @@ gmg_status krylov(gmg_ctx* c, int pi, int vpi, bool flexible, const void* b_true
     // z is projected inside the direction update: p = (z - mean z) + beta p, with
     // (z - mean z).y = z.y - (sum z)(sum y) / n (y = w for FCG, y = r for PCG)
     if (mixed) {
-      if (!spec) STCHK(mixed_direction());
+      if (!spec || lrn) STCHK(mixed_direction());
       continue;
     }
     STCHK(precondition(c, pi, vpi, r, z));
@@ -1275,11 +1353,42 @@ gmg_status upload_octree_level(gmg_ctx* c, Level& L, OctHost& h, const std::vect
   L.dinv_sqrt64 = const_cast<double*>(p);
   STCHK(upload(c, h.wint, &p));
   L.wint64 = const_cast<double*>(p);
+  // leaves all of one level: the DoFs are the uniform lattice of 2^level elements a side
+  bool one_level = !h.sp.leaves.empty();
+  for (const auto& lf : h.sp.leaves) one_level = one_level && lf.level == h.sp.leaves[0].level;
+  if (one_level) {
+    const int ne = 1 << h.sp.leaves[0].level;
+    if (static_cast<int64_t>(c->q * ne) * (c->q * ne) * (c->q * ne) == L.size) {
+      L.latN = c->q * ne;
+      L.tab = make_level_tables(c->q, ne);
+    }
+  }
   if (h.P.rows > 0) {
     STCHK(upload_csr(c, h.P, &d.pptr, &d.pcol, &d.pval64, &d.pval32));
     STCHK(upload_csr(c, oct::transpose(h.P), &d.rptr, &d.rcol, &d.rval64, &d.rval32));
   }
   c->oye_size = std::max<int64_t>(c->oye_size, d.E * d.m);
+  return GMG_OK;
+}
+
+// Device tables of a uniform level of an order without a specialised kernel.
+gmg_status upload_generic_level(gmg_ctx* c, Level& L) {
+  const GenTables T = make_generic_tables(c->q, L.n);
+  L.gen = true;
+  L.latN = 0;  // the learned smoother runs on q <= 4 lattices only
+  for (GenOp* op : {&L.gstiff, &L.gmass}) {
+    const std::vector<double>& rows = op == &L.gstiff ? T.stiff_rows : T.mass_rows;
+    op->q = c->q;
+    STCHK(upload(c, rows, &op->rows64));
+    STCHK(upload(c, to_f32(rows), &op->rows32));
+    STCHK(upload(c, T.dinv, &op->dinv64));
+    STCHK(upload(c, to_f32(T.dinv), &op->dinv32));
+  }
+  STCHK(upload(c, T.diag, &L.gdiag));
+  STCHK(upload(c, T.dsqrt, &L.gdsqrt));
+  STCHK(upload(c, T.dinv_sqrt, &L.gdinv_sqrt));
+  STCHK(upload(c, T.wint, &L.gwint));
+  L.gdiag_host = T.diag;
   return GMG_OK;
 }
 
@@ -1294,7 +1403,10 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   const int q = mesh->order;
   const int n = mesh->n;
   const bool octree = n == 0;
-  if (!(q == 1 || q == 2 || q == 4)) return GMG_E_ARG;
+  // q = 1, 2, 4 run the specialised kernels; 3, 5, 6, 7, 8 the generic ones (uniform meshes)
+  const bool gen = q == 3 || (q >= 5 && q <= kGenMaxQ);
+  if (!(q == 1 || q == 2 || q == 4 || gen)) return GMG_E_ARG;
+  if (gen && n == 0) return GMG_E_ARG;  // octree meshes: orders 1 and 2
   int L = mesh->levels;
   int nc0 = 0;
   int64_t n0 = 0;
@@ -1313,20 +1425,24 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     L = static_cast<int>(oh.size());
     n0 = oh[0].sp.ndof();
   } else {
-    if (n < 2 || (n & (n - 1)) != 0 || q * n < 4 || n > (q == 4 ? 256 : 512)) return GMG_E_ARG;
+    // the generic orders go down to a single periodic element (where coarsening ends,
+    // Section 2.3.1); q = 1, 2, 4 keep at least two elements a side
+    const int nmin = gen ? 1 : 2;
+    const int Nmin = gen ? 3 : 4;  // lattice nodes a side: the shapes of the q = 1, 2, 4 kernels need 4
+    if (n < nmin || (n & (n - 1)) != 0 || q * n < Nmin || n > (gen ? 64 : (q == 4 ? 256 : 512))) return GMG_E_ARG;
     if (L <= 0) {
       L = 1;
-      // deepest hierarchy with coarsest level >= 2 elements and <= 512 DoFs
+      // deepest hierarchy with coarsest level >= nmin elements and <= 512 DoFs
       while (true) {
         const int nc = n >> (L - 1);
         const int64_t dofs = static_cast<int64_t>(q * nc) * (q * nc) * (q * nc);
-        if (dofs <= 512 || nc / 2 < 2 || q * (nc / 2) < 4) break;
+        if (dofs <= 512 || nc / 2 < nmin || q * (nc / 2) < Nmin) break;
         ++L;
       }
     }
     if ((n >> (L - 1)) < 1 || (n >> (L - 1)) << (L - 1) != n) return GMG_E_ARG;
     nc0 = n >> (L - 1);
-    if (q * nc0 < 4 || nc0 < 2) return GMG_E_ARG;
+    if (q * nc0 < Nmin || nc0 < nmin) return GMG_E_ARG;
     n0 = static_cast<int64_t>(q * nc0) * (q * nc0) * (q * nc0);
     if (n0 > 512) return GMG_E_ARG;  // dense FP64 coarsest solve: at most 512 DoFs
   }
@@ -1336,6 +1452,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   c->q = q;
   c->L = L;
   c->octree = octree;
+  c->gen = gen;
   gmg_options o{};
   if (opts) o = *opts;
   if (o.cheb_degree <= 0) o.cheb_degree = 3;
@@ -1403,11 +1520,23 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
       lev.n = n >> (L - 1 - l);
       lev.N = q * lev.n;
       lev.size = static_cast<int64_t>(lev.N) * lev.N * lev.N;
+      if (gen) {
+        if ((st = upload_generic_level(c, lev)) != GMG_OK) return bail(st);
+        continue;
+      }
+      lev.latN = lev.N;
       lev.tab = make_level_tables(q, lev.n);
       prime_apply_shapes(q, lev.N);
       if (l + 1 < L) prime_transfer_shapes(q, lev.N);  // restriction onto this level
     }
-    make_transfer_table(q, &c->xfer);
+    if (gen) {
+      std::vector<double> p, r;
+      make_generic_transfer(q, &p, &r);
+      c->gxfer.q = q;
+      if ((st = upload(c, p, &c->gxfer.p)) != GMG_OK || (st = upload(c, r, &c->gxfer.r)) != GMG_OK) return bail(st);
+    } else {
+      make_transfer_table(q, &c->xfer);
+    }
   }
   if ((st = dalloc(c, reinterpret_cast<void**>(&c->scal), sizeof(double) * kNumScal)) != GMG_OK) return bail(st);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->scal_host), sizeof(double) * kNumScal, hipHostMallocDefault) !=
@@ -1510,6 +1639,7 @@ gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev) {
   const Level& L = ctx->lv[level];
   return scoped(ctx, [&] {
     if (L.oct) HIPCHK(ctx, launch_copy(false, L.size, L.diag64, d_dev, ctx->stream));
+    else if (L.gen) HIPCHK(ctx, launch_gclass_scale(false, ctx->q, L.N, L.gdiag, 1.0, nullptr, d_dev, ctx->stream));
     else HIPCHK(ctx, launch_class_scale(false, ctx->q, L.N, L.tab.diag, 1.0, nullptr, d_dev, ctx->stream));
     return GMG_OK;
   });
@@ -1518,6 +1648,7 @@ gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev) {
 gmg_status gmg_apply(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {
   if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "apply: x and y must not alias");
+  if (ctx->gen) STCHK(ensure_prec(ctx, pidx(prec)));  // the generic passes' temporaries
   return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0); });
 }
 
@@ -1527,6 +1658,7 @@ gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev) {
     return fail(ctx, GMG_E_ARG, "FFT solve: b and u must not alias");
   const Level& F = ctx->lv.back();
   if (F.oct) return fail(ctx, GMG_E_ARG, "FFT solve: uniform meshes only");
+  if (F.gen) return fail(ctx, GMG_E_ARG, "FFT solve: orders 1, 2 and 4 only");
   if (ctx->q == 1) {
     if (!ctx->fft) ctx->fft.reset(new FftQ1());
     return scoped(ctx, [&]() -> gmg_status {
@@ -1554,6 +1686,7 @@ gmg_status gmg_fft_solve(gmg_ctx* ctx, const double* b_dev, double* u_dev) {
 gmg_status gmg_mass(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev) {
   if (!ctx || !x_dev || !y_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
   if (x_dev == y_dev) return fail(ctx, GMG_E_ARG, "mass: x and y must not alias");
+  if (ctx->gen) STCHK(ensure_prec(ctx, pidx(prec)));  // the generic passes' temporaries
   return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Apply, x_dev, y_dev, nullptr, nullptr, 0, 0, true); });
 }
 
@@ -1940,9 +2073,23 @@ gmg_status ensure_net(gmg_ctx* c, int d) {
   return GMG_OK;
 }
 
+// A depth that can hold a net (every level but the coarsest, which has no smoother)...
+gmg_status check_net_depth(const gmg_ctx* c, int d) {
+  if (!c || d < 0 || d >= c->L - 1) return GMG_E_ARG;
+  return GMG_OK;
+}
+
+// ... and one whose level is a lattice of at least 16 nodes a side, where the net runs
 gmg_status check_depth(const gmg_ctx* c, int d) {
-  if (!c || d < 0 || d >= c->L - 1) return GMG_E_ARG;  // the coarsest level has no smoother
-  if (c->lv[c->L - 1 - d].N < 16) return GMG_E_ARG;
+  STCHK(check_net_depth(c, d));
+  if (c->lv[c->L - 1 - d].latN < 16) return GMG_E_ARG;
+  return GMG_OK;
+}
+
+// training (forward with its cache, backward, loss) runs on uniform meshes' levels
+gmg_status check_train_depth(const gmg_ctx* c, int d) {
+  STCHK(check_depth(c, d));
+  if (c->lv[c->L - 1 - d].oct) return GMG_E_ARG;
   return GMG_OK;
 }
 
@@ -1971,17 +2118,17 @@ extern "C" {
 
 gmg_status gmg_net_cache_bytes(const gmg_ctx* ctx, int32_t depth, int64_t* bytes) {
   if (!bytes || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
-  *bytes = net_cache_bytes(ctx->lv[ctx->L - 1 - depth].N);
+  *bytes = net_cache_bytes(ctx->lv[ctx->L - 1 - depth].latN);
   return GMG_OK;
 }
 
 gmg_status gmg_net_set_weights(gmg_ctx* ctx, int32_t depth, const float* w_host, int64_t n) {
-  if (!w_host || n != kNetWeights || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  if (!w_host || n != kNetWeights || check_net_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
   return scoped(ctx, [&] { return set_master(ctx, depth, w_host); });
 }
 
 gmg_status gmg_set_learned(gmg_ctx* ctx, int32_t depth, const uint16_t* w_bf16_host, int64_t n_w) {
-  if (!w_bf16_host || n_w != kNetWeights || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  if (!w_bf16_host || n_w != kNetWeights || check_net_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
   std::vector<float> w(kNetWeights);
   for (int i = 0; i < kNetWeights; ++i) {
     const uint32_t u = static_cast<uint32_t>(w_bf16_host[i]) << 16;
@@ -1991,7 +2138,7 @@ gmg_status gmg_set_learned(gmg_ctx* ctx, int32_t depth, const uint16_t* w_bf16_h
 }
 
 gmg_status gmg_net_get_weights(gmg_ctx* ctx, int32_t depth, float* w_host, int64_t n) {
-  if (!w_host || n != kNetWeights || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
+  if (!w_host || n != kNetWeights || check_net_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
   return scoped(ctx, [&] {
     HIPCHK(ctx, hipMemcpyAsync(w_host, ctx->nets[depth].w, sizeof(float) * kNetWeights, hipMemcpyDeviceToHost,
                                ctx->stream));
@@ -2001,7 +2148,7 @@ gmg_status gmg_net_get_weights(gmg_ctx* ctx, int32_t depth, float* w_host, int64
 }
 
 gmg_status gmg_net_get_state(gmg_ctx* ctx, int32_t depth, float* w_host, float* m_host, float* v_host) {
-  if (!w_host || !m_host || !v_host || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
+  if (!w_host || !m_host || !v_host || check_net_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
   return scoped(ctx, [&] {
     const NetDev& n = ctx->nets[depth];
     const size_t bytes = sizeof(float) * kNetWeights;
@@ -2015,7 +2162,7 @@ gmg_status gmg_net_get_state(gmg_ctx* ctx, int32_t depth, float* w_host, float* 
 
 gmg_status gmg_net_set_state(gmg_ctx* ctx, int32_t depth, const float* w_host, const float* m_host,
                              const float* v_host) {
-  if (!w_host || !m_host || !v_host || check_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
+  if (!w_host || !m_host || !v_host || check_net_depth(ctx, depth) != GMG_OK) return GMG_E_ARG;
   return scoped(ctx, [&] {
     STCHK(set_master(ctx, depth, w_host));
     const NetDev& n = ctx->nets[depth];
@@ -2028,7 +2175,7 @@ gmg_status gmg_net_set_state(gmg_ctx* ctx, int32_t depth, const float* w_host, c
 }
 
 gmg_status gmg_net_forward(gmg_ctx* ctx, int32_t depth, const float* x_dev, float* y_dev, void* cache_dev) {
-  if (!x_dev || !y_dev || !cache_dev || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
+  if (!x_dev || !y_dev || !cache_dev || check_train_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth]) return GMG_E_ARG;
   const int N = ctx->lv[ctx->L - 1 - depth].N;
   return scoped(ctx, [&] {
     HIPCHK(ctx, launch_net_input(x_dev, nullptr, ctx->q, nullptr, ctx->part, ctx->part_cap, N, cache_dev, ctx->stream));
@@ -2039,7 +2186,7 @@ gmg_status gmg_net_forward(gmg_ctx* ctx, int32_t depth, const float* x_dev, floa
 
 gmg_status gmg_net_backward(gmg_ctx* ctx, int32_t depth, const float* gy_dev, const void* cache_dev, float* gw_dev,
                             float* gin_dev) {
-  if (!gy_dev || !cache_dev || !gw_dev || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
+  if (!gy_dev || !cache_dev || !gw_dev || check_train_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
     return GMG_E_ARG;
   const int N = ctx->lv[ctx->L - 1 - depth].N;
   const int64_t nv = static_cast<int64_t>(N) * N * N;
@@ -2059,7 +2206,7 @@ gmg_status gmg_net_backward(gmg_ctx* ctx, int32_t depth, const float* gy_dev, co
 }
 
 gmg_status gmg_adam_step(gmg_ctx* ctx, int32_t depth, const float* gw_dev, float lr, int64_t step) {
-  if (!gw_dev || step < 1 || !(lr > 0.0f) || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
+  if (!gw_dev || step < 1 || !(lr > 0.0f) || check_net_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
     return GMG_E_ARG;
   return scoped(ctx, [&] {
     HIPCHK(ctx, launch_adam(ctx->nets[depth], gw_dev, lr, step, ctx->stream));
@@ -2068,16 +2215,16 @@ gmg_status gmg_adam_step(gmg_ctx* ctx, int32_t depth, const float* gw_dev, float
 }
 
 gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, float* e_dev) {
-  if (!ctx || !r_dev || !e_dev || check_level(ctx, level) != GMG_OK || ctx->lv[level].N < 16) return GMG_E_ARG;
+  if (!ctx || !r_dev || !e_dev || check_level(ctx, level) != GMG_OK || ctx->lv[level].latN < 16) return GMG_E_ARG;
   const int d = net_for_depth(ctx, ctx->L - 1 - level);
   if (d < 0) return fail(ctx, GMG_E_STATE, "no learned weights set");
   return scoped(ctx, [&] {
     STCHK(ensure_lcache(ctx, level));
     const Level& L = ctx->lv[level];
     HIPCHK(ctx, launch_fill_zero(true, L.size, e_dev, ctx->stream));
-    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ctx->scal + S_SSUM + level, ctx->part, ctx->part_cap, L.N,
+    HIPCHK(ctx, launch_net_input(r_dev, L.tab.stiff.dinv, ctx->q, ctx->scal + S_SSUM + level, ctx->part, ctx->part_cap, L.latN,
                                  ctx->lcache[level], ctx->stream));
-    HIPCHK(ctx, launch_net_forward(ctx->nets[d], L.N, ctx->lcache[level], 1, ctx->scal + S_SSUM + level, e_dev,
+    HIPCHK(ctx, launch_net_forward(ctx->nets[d], L.latN, ctx->lcache[level], 1, ctx->scal + S_SSUM + level, e_dev,
                                    ctx->stream, false));
     return GMG_OK;
   });
@@ -2086,6 +2233,7 @@ gmg_status gmg_net_correction(gmg_ctx* ctx, int32_t level, const float* r_dev, f
 gmg_status gmg_residual(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, const void* u_dev,
                         void* r_dev) {
   if (!ctx || !b_dev || !u_dev || !r_dev || u_dev == r_dev || check_level(ctx, level) != GMG_OK) return GMG_E_ARG;
+  if (ctx->gen) STCHK(ensure_prec(ctx, pidx(prec)));  // the generic passes' temporaries
   return scoped(ctx, [&] { return apply_op(ctx, level, pidx(prec), Epi::Residual, u_dev, r_dev, b_dev, nullptr, 0, 0); });
 }
 
@@ -2101,8 +2249,8 @@ gmg_status gmg_launch_shape(const gmg_ctx* ctx, int32_t level, gmg_prec prec, in
   const Level& L = ctx->lv[level];
   const bool f32 = prec == GMG_FP32;
   for (int i = 0; i < 4; ++i) shape_host[i] = 0;
-  if (L.oct) {
-    shape_host[0] = 5;
+  if (L.oct || L.gen) {
+    shape_host[0] = L.oct ? 5 : 6;
     return GMG_OK;
   }
   if (op >= 4) {
@@ -2125,7 +2273,7 @@ gmg_status gmg_launch_shape(const gmg_ctx* ctx, int32_t level, gmg_prec prec, in
 
 gmg_status gmg_net_loss_grad(gmg_ctx* ctx, int32_t depth, int32_t kind, const float* r_dev, const float* e_dev,
                              void* cache_dev, float* gw_dev, float scale, double* loss_host) {
-  if (!r_dev || !cache_dev || !loss_host || check_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
+  if (!r_dev || !cache_dev || !loss_host || check_train_depth(ctx, depth) != GMG_OK || !ctx->net_set[depth])
     return GMG_E_ARG;
   if (kind != 0 && kind != 1) return GMG_E_ARG;
   if (kind == 0 && !e_dev) return GMG_E_ARG;

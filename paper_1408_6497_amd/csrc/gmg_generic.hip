@@ -1,0 +1,329 @@
+// Operator, transfers and diagonal-class arithmetic of uniform periodic levels whose
+// order has no specialised kernel: q = 3, 5, 6, 7, 8 (Section 2.3.2 admits 1 <= q <= 16;
+// Table 10 runs q = 4, 5, 6, 8).  N = q n lattice nodes per direction, n a power of two
+// (n = 1 allowed: a single periodic element), so N is not a power of two in general and
+// every periodic index is taken modulo N.
+//
+// The operator A = Kx (x) My (x) Mz + Mx (x) Ky (x) Mz + Mx (x) My (x) Kz is applied in the
+// tile form, as three banded 1D passes through global memory:
+//   z pass   T1 = Mz x,            T2 = Kz x
+//   y pass   U1 = My T1,           V  = Ky T1 + My T2
+//   x pass   y  = Kx U1 + Mx V,    with the epilogue (residual, smoother step)
+// Row c of a 1D matrix (node class c = i mod q) has 2q+1 taps at offsets -q..q; every
+// node is touched once per pass (14 (q+2) flops per DoF) at the cost of four temporaries.
+// The mass M (x) M (x) M goes through the same passes with Kz = Ky = 0 and the x pass's
+// K row set to M.  Transfers P = P1 (x) P1 (x) P1 and P^T are three one-axis passes
+// each, a thread per output node.  One thread per node throughout: these levels trade
+// the fused streaming kernels of q = 1, 2, 4 for generality.
+#include "gmg_kernels.h"
+
+namespace gmg {
+namespace {
+
+constexpr int kGB = 256;
+
+inline unsigned gen_grid(int64_t n) {
+  int64_t g = (n + kGB - 1) / kGB;
+  if (g > 1 << 30) g = 1 << 30;
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+__device__ __forceinline__ int wrap(int i, int N) {
+  i %= N;
+  return i < 0 ? i + N : i;
+}
+
+// one banded pass along AXIS; T1/T2 (z), U1/V (y) or the output (x)
+// rows: 6 blocks of q (2q+1): z K, z M, y K, y M, x K, x M
+template <typename T, int AXIS, int EPI>
+__global__ void __launch_bounds__(kGB) k_gen_pass(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                   const T* __restrict__ rows, const T* __restrict__ dinv, const int q,
+                                                   const int N, T* __restrict__ out0, T* __restrict__ out1,
+                                                   const T* __restrict__ x, const T* __restrict__ b,
+                                                   const T* xp, const T c1, const T c2) {
+  __shared__ T rk[kGenMaxQ * (2 * kGenMaxQ + 1)], rm[kGenMaxQ * (2 * kGenMaxQ + 1)];
+  const int w = 2 * q + 1;
+  const int blk = q * w;
+  const T* kr = rows + (2 * AXIS) * blk;
+  for (int e = threadIdx.x; e < blk; e += blockDim.x) {
+    rk[e] = kr[e];
+    rm[e] = kr[blk + e];
+  }
+  __syncthreads();
+  const int64_t n3 = static_cast<int64_t>(N) * N * N;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx % N);
+    const int j = static_cast<int>((idx / N) % N);
+    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    const int a = AXIS == 2 ? i : (AXIS == 1 ? j : k);   // coordinate along the pass
+    const int c = a % q;
+    const T* rkc = rk + c * w;
+    const T* rmc = rm + c * w;
+    T s0 = T(0), s1 = T(0);
+    for (int o = -q; o <= q; ++o) {
+      const int aa = wrap(a + o, N);
+      int64_t src;
+      if (AXIS == 0) src = (static_cast<int64_t>(aa) * N + j) * N + i;
+      else if (AXIS == 1) src = (static_cast<int64_t>(k) * N + aa) * N + i;
+      else src = (static_cast<int64_t>(k) * N + j) * N + aa;
+      const T kv = rkc[o + q], mv = rmc[o + q];
+      if (AXIS == 0) {                       // T1 = M x, T2 = K x
+        const T v = in0[src];
+        s0 += mv * v;
+        s1 += kv * v;
+      } else if (AXIS == 1) {                // U1 = M T1, V = K T1 + M T2
+        const T t1 = in0[src], t2 = in1[src];
+        s0 += mv * t1;
+        s1 += kv * t1 + mv * t2;
+      } else {                               // y = K U1 + M V
+        s0 += kv * in0[src] + mv * in1[src];
+      }
+    }
+    if constexpr (AXIS < 2) {
+      out0[idx] = s0;
+      out1[idx] = s1;
+    } else if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+      out0[idx] = s0;
+    } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
+      out0[idx] = b[idx] - s0;
+    } else {  // Epi::Cheb: x + c1 (x - xp) + c2 D^-1 (b - A x); xp read as 0 when null
+      const int cls = (i % q) + q * ((j % q) + q * (k % q));
+      const T xv = x[idx];
+      const T xpv = (xp != nullptr && c1 != T(0)) ? xp[idx] : T(0);
+      out0[idx] = xv + c1 * (xv - xpv) + c2 * dinv[cls] * (b[idx] - s0);
+    }
+  }
+}
+
+template <typename T>
+hipError_t gen_apply_t(const GenOp& op, const ApplyArgs& a, void* t1, void* t2, void* t3, void* t4, hipStream_t s) {
+  const int N = a.N, q = op.q;
+  const int64_t n3 = static_cast<int64_t>(N) * N * N;
+  const T* rows = static_cast<const T*>(sizeof(T) == 4 ? static_cast<const void*>(op.rows32) : op.rows64);
+  const T* dinv = static_cast<const T*>(sizeof(T) == 4 ? static_cast<const void*>(op.dinv32) : op.dinv64);
+  const dim3 g(gen_grid(n3)), bl(kGB);
+  hipLaunchKernelGGL((k_gen_pass<T, 0, 0>), g, bl, 0, s, static_cast<const T*>(a.x), nullptr, rows, dinv, q, N,
+                     static_cast<T*>(t1), static_cast<T*>(t2), nullptr, nullptr, nullptr, T(0), T(0));
+  hipLaunchKernelGGL((k_gen_pass<T, 1, 0>), g, bl, 0, s, static_cast<const T*>(t1), static_cast<const T*>(t2), rows,
+                     dinv, q, N, static_cast<T*>(t3), static_cast<T*>(t4), nullptr, nullptr, nullptr, T(0), T(0));
+  const T* x = static_cast<const T*>(a.x);
+  const T* b = static_cast<const T*>(a.b);
+  T* out = static_cast<T*>(a.out);
+  switch (a.epi) {
+    case Epi::Apply:
+      hipLaunchKernelGGL((k_gen_pass<T, 2, static_cast<int>(Epi::Apply)>), g, bl, 0, s, static_cast<const T*>(t3),
+                         static_cast<const T*>(t4), rows, dinv, q, N, out, nullptr, x, b,
+                         static_cast<const T*>(a.xp), T(0), T(0));
+      break;
+    case Epi::Residual:
+      hipLaunchKernelGGL((k_gen_pass<T, 2, static_cast<int>(Epi::Residual)>), g, bl, 0, s,
+                         static_cast<const T*>(t3), static_cast<const T*>(t4), rows, dinv, q, N, out, nullptr, x, b,
+                         static_cast<const T*>(a.xp), T(0), T(0));
+      break;
+    case Epi::Cheb:
+      hipLaunchKernelGGL((k_gen_pass<T, 2, static_cast<int>(Epi::Cheb)>), g, bl, 0, s, static_cast<const T*>(t3),
+                         static_cast<const T*>(t4), rows, dinv, q, N, out, nullptr, x, b,
+                         static_cast<const T*>(a.xp), static_cast<T>(a.c1), static_cast<T>(a.c2));
+      break;
+    default:
+      return hipErrorInvalidValue;  // the fused variants exist for q = 1, 2, 4 only
+  }
+  return hipGetLastError();
+}
+
+// ---- transfers: P1 and P1^T along one axis, a thread per output node
+// p: 2q x (q+1) (fine node 2qE + b from coarse q E + a), r: q x (4q+1) (coarse node
+// q E + a from fine 2qE - 2q + t); extents: (X, Y, Z) of the output, the input equal
+// except along AXIS
+template <typename T, int AXIS, bool ACC>
+__global__ void __launch_bounds__(kGB) k_gen_prolong(const T* __restrict__ in, T* __restrict__ out,
+                                                      const double* __restrict__ p, const int q, const int X,
+                                                      const int Y, const int Z, const int Nc) {
+  const int64_t total = static_cast<int64_t>(X) * Y * Z;
+  const int ix = AXIS == 0 ? Nc : X, iy = AXIS == 1 ? Nc : Y;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx % X), j = static_cast<int>((idx / X) % Y);
+    const int k = static_cast<int>(idx / (static_cast<int64_t>(X) * Y));
+    const int f = AXIS == 0 ? i : (AXIS == 1 ? j : k);
+    const int E = f / (2 * q), bb = f - 2 * q * E;
+    double s = 0.0;
+    for (int a = 0; a <= q; ++a) {
+      const int cc = (q * E + a) % Nc;
+      int ii = i, jj = j, kk = k;
+      if (AXIS == 0) ii = cc;
+      else if (AXIS == 1) jj = cc;
+      else kk = cc;
+      s = fma(p[bb * (q + 1) + a], static_cast<double>(in[(static_cast<int64_t>(kk) * iy + jj) * ix + ii]), s);
+    }
+    out[idx] = ACC ? static_cast<T>(static_cast<double>(out[idx]) + s) : static_cast<T>(s);
+  }
+}
+
+template <typename T, int AXIS>
+__global__ void __launch_bounds__(kGB) k_gen_restrict(const T* __restrict__ in, T* __restrict__ out,
+                                                       const double* __restrict__ r, const int q, const int X,
+                                                       const int Y, const int Z, const int Nf) {
+  const int64_t total = static_cast<int64_t>(X) * Y * Z;
+  const int ix = AXIS == 0 ? Nf : X, iy = AXIS == 1 ? Nf : Y;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx % X), j = static_cast<int>((idx / X) % Y);
+    const int k = static_cast<int>(idx / (static_cast<int64_t>(X) * Y));
+    const int c = AXIS == 0 ? i : (AXIS == 1 ? j : k);
+    const int E = c / q, a = c - q * E;
+    double s = 0.0;
+    for (int t = 0; t <= 4 * q; ++t) {
+      const double w = r[a * (4 * q + 1) + t];
+      if (w == 0.0) continue;
+      const int ff = wrap(2 * q * E - 2 * q + t, Nf);
+      int ii = i, jj = j, kk = k;
+      if (AXIS == 0) ii = ff;
+      else if (AXIS == 1) jj = ff;
+      else kk = ff;
+      s = fma(w, static_cast<double>(in[(static_cast<int64_t>(kk) * iy + jj) * ix + ii]), s);
+    }
+    out[idx] = static_cast<T>(s);
+  }
+}
+
+template <typename T>
+hipError_t gen_prolong_t(const GenXfer& t, const T* ec, T* t1, T* t2, T* uf, int Nc, hipStream_t s) {
+  const int Nf = 2 * Nc, q = t.q;
+  const dim3 bl(kGB);
+  hipLaunchKernelGGL((k_gen_prolong<T, 0, false>), dim3(gen_grid(static_cast<int64_t>(Nf) * Nc * Nc)), bl, 0, s, ec,
+                     t1, t.p, q, Nf, Nc, Nc, Nc);
+  hipLaunchKernelGGL((k_gen_prolong<T, 1, false>), dim3(gen_grid(static_cast<int64_t>(Nf) * Nf * Nc)), bl, 0, s,
+                     static_cast<const T*>(t1), t2, t.p, q, Nf, Nf, Nc, Nc);
+  hipLaunchKernelGGL((k_gen_prolong<T, 2, true>), dim3(gen_grid(static_cast<int64_t>(Nf) * Nf * Nf)), bl, 0, s,
+                     static_cast<const T*>(t2), uf, t.p, q, Nf, Nf, Nf, Nc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gen_restrict_t(const GenXfer& t, const T* rf, T* t1, T* t2, T* rc, int Nc, hipStream_t s) {
+  const int Nf = 2 * Nc, q = t.q;
+  const dim3 bl(kGB);
+  hipLaunchKernelGGL((k_gen_restrict<T, 0>), dim3(gen_grid(static_cast<int64_t>(Nc) * Nf * Nf)), bl, 0, s, rf, t1,
+                     t.r, q, Nc, Nf, Nf, Nf);
+  hipLaunchKernelGGL((k_gen_restrict<T, 1>), dim3(gen_grid(static_cast<int64_t>(Nc) * Nc * Nf)), bl, 0, s,
+                     static_cast<const T*>(t1), t2, t.r, q, Nc, Nc, Nf, Nf);
+  hipLaunchKernelGGL((k_gen_restrict<T, 2>), dim3(gen_grid(static_cast<int64_t>(Nc) * Nc * Nc)), bl, 0, s,
+                     static_cast<const T*>(t2), rc, t.r, q, Nc, Nc, Nc, Nf);
+  return hipGetLastError();
+}
+
+// ---- node-class arithmetic with the class table in device memory (q^3 values)
+template <typename T>
+__global__ void __launch_bounds__(kGB) k_gclass_scale(const double* __restrict__ tab, const int q, const int N,
+                                                       const double c, const T* in, T* out) {
+  const int64_t n3 = static_cast<int64_t>(N) * N * N;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx % N), j = static_cast<int>((idx / N) % N);
+    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    const double d = tab ? tab[(i % q) + q * ((j % q) + q * (k % q))] : 1.0;
+    const double v = in ? static_cast<double>(in[idx]) : 1.0;
+    out[idx] = static_cast<T>(c * d * v);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kGB) k_gclass_axpy(const double* __restrict__ tab, const int q, const int N,
+                                                      const double c, T* v) {
+  const int64_t n3 = static_cast<int64_t>(N) * N * N;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx % N), j = static_cast<int>((idx / N) % N);
+    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    v[idx] = static_cast<T>(static_cast<double>(v[idx]) + c * tab[(i % q) + q * ((j % q) + q * (k % q))]);
+  }
+}
+
+// per-block partials of sum tab[class(i)] x_i, in a fixed order
+template <typename T>
+__global__ void __launch_bounds__(kGB) k_gclass_dot(const double* __restrict__ tab, const int q, const int N,
+                                                     const T* __restrict__ x, double* part) {
+  __shared__ double red[kGB / 64];
+  const int64_t n3 = static_cast<int64_t>(N) * N * N;
+  double s = 0.0;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx % N), j = static_cast<int>((idx / N) % N);
+    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    s = fma(tab[(i % q) + q * ((j % q) + q * (k % q))], static_cast<double>(x[idx]), s);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kGB / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gen_apply(const GenOp& op, bool fp32, const ApplyArgs& a, void* const tmp[4], hipStream_t s) {
+  if (op.q < 1 || op.q > kGenMaxQ || a.N != op.q * a.n || a.N < 1) return hipErrorInvalidValue;
+  if (fp32) return gen_apply_t<float>(op, a, tmp[0], tmp[1], tmp[2], tmp[3], s);
+  return gen_apply_t<double>(op, a, tmp[0], tmp[1], tmp[2], tmp[3], s);
+}
+
+hipError_t launch_gen_prolong(const GenXfer& t, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
+                              hipStream_t s) {
+  if (t.q < 1 || t.q > kGenMaxQ || Nc < t.q || Nc % t.q != 0) return hipErrorInvalidValue;
+  if (fp32)
+    return gen_prolong_t<float>(t, static_cast<const float*>(ec), static_cast<float*>(t1), static_cast<float*>(t2),
+                                static_cast<float*>(uf), Nc, s);
+  return gen_prolong_t<double>(t, static_cast<const double*>(ec), static_cast<double*>(t1), static_cast<double*>(t2),
+                               static_cast<double*>(uf), Nc, s);
+}
+
+hipError_t launch_gen_restrict(const GenXfer& t, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
+                               hipStream_t s) {
+  if (t.q < 1 || t.q > kGenMaxQ || Nc < t.q || Nc % t.q != 0) return hipErrorInvalidValue;
+  if (fp32)
+    return gen_restrict_t<float>(t, static_cast<const float*>(rf), static_cast<float*>(t1), static_cast<float*>(t2),
+                                 static_cast<float*>(rc), Nc, s);
+  return gen_restrict_t<double>(t, static_cast<const double*>(rf), static_cast<double*>(t1), static_cast<double*>(t2),
+                                static_cast<double*>(rc), Nc, s);
+}
+
+hipError_t launch_gclass_scale(bool fp32, int q, int N, const double* tab_dev, double c, const void* in, void* out,
+                               hipStream_t s) {
+  const unsigned g = gen_grid(static_cast<int64_t>(N) * N * N);
+  if (fp32)
+    hipLaunchKernelGGL(k_gclass_scale<float>, dim3(g), dim3(kGB), 0, s, tab_dev, q, N, c,
+                       static_cast<const float*>(in), static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(k_gclass_scale<double>, dim3(g), dim3(kGB), 0, s, tab_dev, q, N, c,
+                       static_cast<const double*>(in), static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_gclass_axpy(int q, int N, const double* tab_dev, double c, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_gclass_axpy<double>, dim3(gen_grid(static_cast<int64_t>(N) * N * N)), dim3(kGB), 0, s,
+                     tab_dev, q, N, c, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_gclass_dot(bool fp32, int q, int N, const double* tab_dev, const void* x, double* part,
+                             int64_t part_cap, double* dst, hipStream_t s) {
+  int g = static_cast<int>(gen_grid(static_cast<int64_t>(N) * N * N));
+  if (g > kRedBlocks) g = kRedBlocks;
+  if (part_cap < g) return hipErrorInvalidValue;
+  if (fp32)
+    hipLaunchKernelGGL(k_gclass_dot<float>, dim3(g), dim3(kGB), 0, s, tab_dev, q, N, static_cast<const float*>(x),
+                       part);
+  else
+    hipLaunchKernelGGL(k_gclass_dot<double>, dim3(g), dim3(kGB), 0, s, tab_dev, q, N, static_cast<const double*>(x),
+                       part);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_partials(part, g, part_cap, dst, s);
+}
+
+}  // namespace gmg

@@ -116,6 +116,40 @@ struct FftQ4 {
 hipError_t fft_q4_prepare(FftQ4* f, int n);
 hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s);
 
+// Orders without a specialised kernel (q = 3, 5, 6, 7, 8; gmg_generic.hip): the operator as
+// three banded 1D passes through four level-size temporaries, transfers as one-axis passes,
+// and the node-class arithmetic with its class tables in device memory.
+constexpr int kGenMaxQ = 8;
+// rows: 6 blocks of q (2q+1) values (z K, z M, y K, y M, x K, x M; row c = node class,
+// tap o + q for offset o); dinv: 1 / A_ii by node class (q^3)
+struct GenOp {
+  int q = 0;
+  const double* rows64 = nullptr;
+  const float* rows32 = nullptr;
+  const double* dinv64 = nullptr;
+  const float* dinv32 = nullptr;
+};
+// p: 2q x (q+1) weights of P1, r: q x (4q+1) weights of P1^T (device, FP64), laid out as
+// the one-axis tables of TransferTab
+struct GenXfer {
+  int q = 0;
+  const double* p = nullptr;
+  const double* r = nullptr;
+};
+// Epi::Apply, Residual and Cheb (the fused variants are for q = 1, 2, 4); tmp: four
+// temporaries of N^3 values of the kernel precision
+hipError_t launch_gen_apply(const GenOp& op, bool fp32, const ApplyArgs& a, void* const tmp[4], hipStream_t s);
+hipError_t launch_gen_prolong(const GenXfer& t, bool fp32, const void* ec, void* t1, void* t2, void* uf, int Nc,
+                              hipStream_t s);
+hipError_t launch_gen_restrict(const GenXfer& t, bool fp32, const void* rf, void* t1, void* t2, void* rc, int Nc,
+                               hipStream_t s);
+// out = c tab[class] in (in null: 1; tab null: 1); v += c tab[class] (FP64); dst = sum tab[class] x
+hipError_t launch_gclass_scale(bool fp32, int q, int N, const double* tab_dev, double c, const void* in, void* out,
+                               hipStream_t s);
+hipError_t launch_gclass_axpy(int q, int N, const double* tab_dev, double c, double* v, hipStream_t s);
+hipError_t launch_gclass_dot(bool fp32, int q, int N, const double* tab_dev, const void* x, double* part,
+                             int64_t part_cap, double* dst, hipStream_t s);
+
 // Spectral FFT Poisson solve on the uniform N^3 grid (16 <= N <= 1024, a power of two):
 // u = F^-1 [F(f) / (4 pi^2 |m|^2)] with the m = 0 coefficient set to 0.  The complex
 // work buffer (N^3 values) and the table of the N roots of unity are made by

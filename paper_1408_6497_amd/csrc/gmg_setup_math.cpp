@@ -203,6 +203,78 @@ void make_transfer_table(int q, TransferTab* tab) {
     }
 }
 
+// Rows of the assembled periodic 1D matrix, any order: row c (node class), tap o + q.
+static std::vector<double> generic_rows(int q, const std::vector<double>& ehat, double scale) {
+  const int w = 2 * q + 1;
+  std::vector<double> rows(static_cast<size_t>(q) * w, 0.0);
+  for (int b = 0; b <= q; ++b) {
+    rows[(b - q) + q] += ehat[q * (q + 1) + b] * scale;  // vertex: left element (local node q)
+    rows[b + q] += ehat[0 * (q + 1) + b] * scale;        // vertex: right element (local node 0)
+  }
+  for (int c = 1; c < q; ++c)
+    for (int b = 0; b <= q; ++b) rows[c * w + (b - c) + q] = ehat[c * (q + 1) + b] * scale;
+  return rows;
+}
+
+GenTables make_generic_tables(int q, int n) {
+  GenTables T;
+  T.q = q;
+  const double h = 1.0 / n;
+  const int w = 2 * q + 1, blk = q * w;
+  std::vector<double> khat, mhat;
+  reference_matrices(q, &khat, &mhat);
+  const std::vector<double> K = generic_rows(q, khat, 1.0 / h), M = generic_rows(q, mhat, h);
+  const std::vector<double> Z(blk, 0.0);
+  // stiffness: z (K, M), y (K, M), x (K, M); mass: z (0, M), y (0, M), x (M, M)
+  for (const auto* part : {&K, &M, &K, &M, &K, &M}) T.stiff_rows.insert(T.stiff_rows.end(), part->begin(), part->end());
+  for (const auto* part : {&Z, &M, &Z, &M, &M, &M}) T.mass_rows.insert(T.mass_rows.end(), part->begin(), part->end());
+  // diagonal entries: the taps landing on the node itself (offset 0, and +-q on a single
+  // periodic element, where both ends of the element are the node)
+  const int N = q * n;
+  std::vector<double> kd(q, 0.0), md(q, 0.0), msum(q, 0.0);
+  for (int c = 0; c < q; ++c)
+    for (int o = -q; o <= q; ++o) {
+      if (o % N == 0) {
+        kd[c] += K[c * w + o + q];
+        md[c] += M[c * w + o + q];
+      }
+      msum[c] += M[c * w + o + q];
+    }
+  const int nc = q * q * q;
+  T.diag.resize(nc);
+  T.dinv.resize(nc);
+  T.dsqrt.resize(nc);
+  T.dinv_sqrt.resize(nc);
+  T.wint.resize(nc);
+  for (int cz = 0; cz < q; ++cz)
+    for (int cy = 0; cy < q; ++cy)
+      for (int cx = 0; cx < q; ++cx) {
+        const int i = cx + q * (cy + q * cz);
+        const double d = kd[cx] * md[cy] * md[cz] + md[cx] * kd[cy] * md[cz] + md[cx] * md[cy] * kd[cz];
+        T.diag[i] = d;
+        T.dinv[i] = 1.0 / d;
+        T.dinv_sqrt[i] = 1.0 / std::sqrt(d);
+        T.dsqrt[i] = std::sqrt(d);
+        T.wint[i] = msum[cx] * msum[cy] * msum[cz];
+      }
+  return T;
+}
+
+void make_generic_transfer(int q, std::vector<double>* p, std::vector<double>* r) {
+  const std::vector<double> xi = lgl_nodes01(q);
+  p->assign(static_cast<size_t>(2 * q) * (q + 1), 0.0);
+  r->assign(static_cast<size_t>(q) * (4 * q + 1), 0.0);
+  for (int b = 0; b < 2 * q; ++b)
+    for (int a = 0; a <= q; ++a) (*p)[b * (q + 1) + a] = lagrange_at(xi, a, child_coord(xi, q, b));
+  for (int a = 0; a < q; ++a)
+    for (int t = 0; t <= 4 * q; ++t) {
+      double w = 0.0;
+      if (t >= 2 * q) w = lagrange_at(xi, a, child_coord(xi, q, t - 2 * q));
+      else if (a == 0) w = lagrange_at(xi, q, child_coord(xi, q, t));
+      (*r)[a * (4 * q + 1) + t] = (std::fabs(w) < 1e-15) ? 0.0 : w;
+    }
+}
+
 // Dense periodic 1D matrices of order q on n elements (N = q n).
 static void dense_1d(int q, int n, std::vector<double>* K, std::vector<double>* M) {
   const int N = q * n;

@@ -18,6 +18,18 @@ struct LevelTables {
   double wint[kMaxQ * kMaxQ * kMaxQ];      // int phi_i dx (row sums of M) by class
 };
 
+// Tables of a level of an order without a specialised kernel (see GenOp): the banded
+// rows of the stiffness and of the mass passes (6 q (2q+1) values each) and the node-class
+// tables (q^3 values each).
+struct GenTables {
+  int q = 0;
+  std::vector<double> stiff_rows, mass_rows;
+  std::vector<double> diag, dinv, dsqrt, dinv_sqrt, wint;
+};
+GenTables make_generic_tables(int q, int n);
+// P1 (2q x (q+1)) and P1^T (q x (4q+1)) weights, as in TransferTab
+void make_generic_transfer(int q, std::vector<double>* p, std::vector<double>* r);
+
 std::vector<double> lgl_nodes01(int q);
 void gauss01(int m, std::vector<double>* pts, std::vector<double>* wts);
 double lagrange_at(const std::vector<double>& xi, int a, double t);

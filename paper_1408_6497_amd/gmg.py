@@ -300,7 +300,7 @@ class Context:
 
     SHAPE_OPS = {"apply": 0, "residual": 1, "smooth": 2, "smooth_zero": 3, "restrict": 4, "prolong": 5}
     SHAPE_KERNELS = {0: "point", 1: "column", 2: "column_preload", 3: "transfer_fused", 4: "transfer_axis",
-                     5: "octree"}
+                     5: "octree", 6: "generic"}
 
     def launch_shape(self, level, prec, op):
         """(kernel name, G, TZ, blocks) of the launch an operation takes on a level."""
@@ -521,6 +521,7 @@ def octree_balance(keys, levels):
     l = np.ascontiguousarray(levels, dtype=np.uint8)
     return _leaves_call(lib.gmg_octree_balance, k.ctypes.data_as(ctypes.c_void_p), l.ctypes.data_as(ctypes.c_void_p),
                         k.size)
+
 
 class SpectralSolver:
     """The paper's FFT Poisson method on the uniform N^3 grid (gmg_spectral_*): u with

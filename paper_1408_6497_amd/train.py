@@ -26,7 +26,12 @@ Checkpoint file (little endian):
   end on the same bits as an uninterrupted one.
 
   python -m paper_1408_6497_amd.train --n 64 --sources 10000 --out weights.gmgw
+  python -m paper_1408_6497_amd.train --n 64 --depth 2 --sources 10000 --out q2_depth2.gmgw
   python -m paper_1408_6497_amd.train --resume weights.gmgw --out weights.gmgw
+
+The net of depth d (d levels below the finest) is trained on the level at depth d of the
+n-element training hierarchy: the finest level of the mesh with n / 2^d elements, whose
+cycles are that hierarchy's cycles below depth d.  The file records d.
 """
 import argparse
 import json
@@ -194,9 +199,10 @@ def validate(ctx, pm, cache, seeds, kind, with_cheb=False, cycles=1, positions=(
 
 def train(n=64, sources=10000, batch=8, lr=1e-3, val=100, init_seed=12345, out=None, log=print,
           train_seed0=0, val_seed0=20000, cycles=2, positions=("pre", "post"), loss="residual",
-          stop_after=None, resume=None):
-    """Adam on the net of depth 0; stop_after ends the run early (a checkpoint to resume from),
-    resume continues a version-2 checkpoint with its own configuration."""
+          stop_after=None, resume=None, depth=0):
+    """Adam on the net of one depth (trained on the finest level of the n / 2^depth-element mesh);
+    stop_after ends the run early (a checkpoint to resume from), resume continues a version-2
+    checkpoint with its own configuration."""
     import torch
     from paper_1408_6497_amd import Context, GMG_FP64, LOSS_ENERGY, LOSS_RESIDUAL
     ck = None
@@ -208,12 +214,16 @@ def train(n=64, sources=10000, batch=8, lr=1e-3, val=100, init_seed=12345, out=N
         n, sources, batch, lr, val = cfg["n"], cfg["sources"], cfg["batch"], cfg["lr"], cfg["val"]
         init_seed, train_seed0, val_seed0 = cfg["init_seed"], cfg["train_seed0"], cfg["val_seed0"]
         cycles, positions, loss = cfg["cycles"], tuple(cfg["positions"]), cfg["loss"]
+        depth = cfg.get("depth", 0)
     config = {"n": n, "sources": sources, "batch": batch, "lr": lr, "val": val, "init_seed": init_seed,
               "train_seed0": train_seed0, "val_seed0": val_seed0, "cycles": cycles, "positions": list(positions),
-              "loss": loss}
+              "loss": loss, "depth": depth}
+    nd = n >> depth
+    if nd < 8 or nd << depth != n:
+        raise ValueError(f"depth {depth} leaves {n / 2 ** depth} elements of the {n}-element mesh (8 at least)")
     kind = {"energy": LOSS_ENERGY, "residual": LOSS_RESIDUAL}[loss]
-    ctx = Context(2, n, 0, seed=0, vcycle_prec=GMG_FP64)
-    cctx = Context(2, n // 2, 0, seed=0, vcycle_prec=GMG_FP64) if "post" in positions else None
+    ctx = Context(2, nd, 0, seed=0, vcycle_prec=GMG_FP64)
+    cctx = Context(2, nd // 2, 0, seed=0, vcycle_prec=GMG_FP64) if "post" in positions else None
     pm = PairMaker(ctx, cctx)
     if ck:
         ctx.net_set_state(0, ck["w"], ck["m"], ck["v"])
@@ -263,7 +273,7 @@ def train(n=64, sources=10000, batch=8, lr=1e-3, val=100, init_seed=12345, out=N
             log(f"[train] step {step}/{steps} loss {np.mean(hist[-50:]):.4f} ({time.perf_counter() - t0:.1f} s)")
     w, m, v = ctx.net_get_state(0)
     if out:
-        save(out, w, 0, 2, n, last, m, v, {"config": config, "stream": state})
+        save(out, w, depth, 2, nd, last, m, v, {"config": config, "stream": state})
     v1, _ = validate(ctx, pm, cache, vseeds, kind, cycles=cycles, positions=positions)
     log(f"[train] validation after: loss {v1:.4f}")
     return {"w": w, "val_before": v0, "val_after": v1, "val_chebyshev": vcheb, "steps": last - step0,
@@ -283,10 +293,11 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--stop-after", type=int, default=None, help="stop after this many Adam steps (checkpoint)")
     ap.add_argument("--resume", default=None, help="continue a version-2 checkpoint")
+    ap.add_argument("--depth", type=int, default=0, help="the net's depth below the finest level")
     a = ap.parse_args()
     res = train(a.n, a.sources, a.batch, a.lr, a.val, out=a.out, log=lambda *m: print(*m, flush=True),
                 cycles=a.cycles, positions=tuple(a.positions.split(",")), loss=a.loss,
-                stop_after=a.stop_after, resume=a.resume)
+                stop_after=a.stop_after, resume=a.resume, depth=a.depth)
     print(f"[train] done: {res['steps']} steps in {res['seconds']:.1f} s; validation {res['val_before']:.4f} -> "
           f"{res['val_after']:.4f} (Chebyshev {res['val_chebyshev']:.4f})", flush=True)
 

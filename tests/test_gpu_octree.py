@@ -304,3 +304,54 @@ def test_sharp_layer_solve_matches_oracle_and_converges(q):
             assert abs(e - e_oracle) <= 1e-3 * e_oracle
         errs.append(e_oracle)
     assert errs[1] < 0.25 * errs[0]
+
+
+def test_learned_correction_on_the_uniform_levels_of_an_octree_hierarchy():
+    """An octree level whose leaves all have one level is the uniform lattice in lattice order:
+    the learned correction runs there (the lattice convolution is defined) and gives the bits of
+    the uniform context's correction on the same lattice; a learned solve uses it on that level
+    and reaches 1e-8 on the oracle's operator.  Coarsening merges every complete family at once,
+    so a hierarchy has uniform levels above the coarsest only when its tree is uniform: here the
+    level-4 tree (levels of 32^3, 16^3 and 8^3 Q2 nodes).  (The adaptive workload's hierarchy has
+    no uniform level but the coarsest, so its learned solve runs no net.)"""
+    torch = torch_cuda()
+    import os
+    from oracle import octree as ot, octree_fe as ofe, multigrid as mg
+    from paper_1408_6497_amd import Context
+    from paper_1408_6497_amd import train as T
+    from workloads import gaussian_params, gaussian_source_points
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    w = T.load(os.path.join(root, "paper_1408_6497_amd", "weights", "q2_depth0.gmgw"))["w"]
+    from oracle import octree as ot_
+    tree = ot_.sort_leaves(ot_.uniform(4))
+    ctx = Context(2, 0, leaves=_arrays(tree), use_learned=1, learned_min_depth=1, timing=1)
+    ctx.net_set_weights(0, w)
+    sizes = [ctx.num_dofs(l) for l in range(ctx.levels)]
+    l1 = sizes.index(16 ** 3)          # the uniform level-3 mesh
+    assert l1 < ctx.levels - 1
+    uni = Context(2, 8, 0)
+    uni.net_set_weights(0, w)
+    assert np.array_equal(ctx.dof_coords(l1), uni.dof_coords(uni.levels - 1))
+    r = torch.from_numpy(np.random.default_rng(4).standard_normal(16 ** 3)).float().cuda()
+    e_oct, e_uni = torch.empty_like(r), torch.empty_like(r)
+    ctx.net_correction(l1, r, e_oct)
+    uni.net_correction(uni.levels - 1, r, e_uni)
+    torch.cuda.synchronize()
+    assert torch.equal(e_oct, e_uni)
+    S = ofe.OctreeSpace(tree, 2)
+    p = gaussian_params(3, 4, 0.01, 0.05)
+    f = gaussian_source_points(S.coords(), p)
+    b = mg.project(S.M @ f)
+    fd = torch.from_numpy(f).cuda()
+    u = torch.empty_like(fd)
+    ctx.timing_reset()
+    info = ctx.solve(fd, u, 1e-8)
+    torch.cuda.synchronize()
+    used = ctx.timing(l1, Context.KIND_LEARNED, 1)[0]
+    others = sum(ctx.timing(l, Context.KIND_LEARNED, 1)[0] for l in range(ctx.levels) if l != l1)
+    res = b - S.A @ to_host(u)
+    rel = np.linalg.norm(res - res.mean()) / np.linalg.norm(b)
+    print(f"[octree-learned] level sizes {sizes}: iters {info.inner_iters} fallbacks {info.fallbacks} learned "
+          f"corrections on the uniform level {used}, elsewhere {others}; rel {rel:.2e}", flush=True)
+    assert used > 0 and others == 0
+    assert rel <= 1e-8 * 1.001
