@@ -752,8 +752,7 @@ gmg_status test_cycle(gmg_ctx* c, int pi, const void* r, bool plain) {
   STCHK(st);
   void* t = c->lv[l].xp[1];
   STCHK(apply_op(c, l, 1, Epi::Residual, c->kz[1], t, r32, nullptr, 0, 0));
-  HIPCHK(c, launch_dot(true, n, t, t, c->part, c->scal + S_LRES, c->stream));
-  HIPCHK(c, launch_dot(true, n, r32, r32, c->part, c->scal + S_LRR, c->stream));
+  HIPCHK(c, launch_sq2(true, n, t, r32, c->part, c->scal, S_LRES, S_LRR, c->stream));
   return GMG_OK;
 }
 
@@ -2068,6 +2067,10 @@ gmg_status ensure_net(gmg_ctx* c, int d) {
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.v), sizeof(float) * kNetWeights));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w1q), sizeof(float) * 432));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w3q), sizeof(float) * 432));
+  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w3p), sizeof(uint32_t) * 216));
+  STCHK(dalloc(c, &n.w2fl, 16 * 15 * 64));
+  STCHK(dalloc(c, &n.w2bl, 16 * 15 * 64));
+  STCHK(dalloc(c, &n.w1l, 16 * 2 * 64));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w2f), sizeof(uint16_t) * 6912));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w2b), sizeof(uint16_t) * 6912));
   return GMG_OK;

@@ -272,6 +272,9 @@ hipError_t launch_dot_noalloc(int device, bool fp32, int64_t n, const void* x, c
 //   sums3:       sc[dz] = sum z, sc[dzy] = z.y, sc[dy] = sum y
 //   combine:     sc[dst] = sc[a] - sc[b] sc[c] scale (one thread)
 //   xpby_shift:  p = (z - sc[imean] scale) + (sgn sc[inum] / sc[iden]) p
+//   sq2:         sc[dx] = x.x, sc[dy] = y.y
+hipError_t launch_sq2(bool fp32, int64_t n, const void* x, const void* y, double* part, double* sc, int dx, int dy,
+                      hipStream_t s);
 hipError_t launch_dot2(bool fp32, int64_t n, const void* x, const void* y, const void* z, double* part, double* sc,
                        int dxy, int dxz, hipStream_t s);
 hipError_t launch_axpy2_sums(bool fp32, int64_t n, double* sc, int inum, int iden, void* u, const void* p, void* r,
@@ -354,6 +357,12 @@ struct NetDev {
   uint16_t* w2f = nullptr;
   uint16_t* w2b = nullptr;
   float* w3q = nullptr;
+  uint32_t* w3p = nullptr;  // W3 as BF16 channel pairs per tap [27][8]
+  // lane-ordered MFMA operands (16 bytes per entry): layer 2 forward and backward-data (15 x 64
+  // each), layer 1 (2 x 64)
+  void* w2fl = nullptr;
+  void* w2bl = nullptr;
+  void* w1l = nullptr;
 };
 constexpr int kNetWeights = 7776;
 // bytes of the forward cache (BF16 input + two 16-channel BF16 activations)
@@ -363,7 +372,8 @@ int64_t net_partial_floats(int N);
 hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s);
 // cache.x_in = bf16(D^-1 r / s), s = RMS(D^-1 r) written to *ssum as a sum of squares
 // (dinv == null: x_in = bf16(r), ssum unused); part needs N^2 doubles (part_cap of them
-// are allocated; with N^2 + N^2/64 the partials are folded in two passes).
+// are allocated; with N^2 + N^2/64 the partials are folded in two passes).  N a multiple of
+// 4, r and cache 16-byte aligned (else hipErrorInvalidValue).
 hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part,
                             int64_t part_cap, int N, void* cache, hipStream_t s);
 // y = N(x_in) (mode 0) or y += s N(x_in) with s = sqrt(*ssum / N^3) (mode 1).

@@ -14,18 +14,19 @@
 // + (dx+1) reads the voxel at offset (dx, dy, dz), wrapped periodically.
 //
 // Forward pass, two kernels per application:
-//   k_net_l12  one 16x8x4 brick per block: bf16(x) with a two-voxel halo in LDS;
+//   k_net_l12  one 16x8x4 brick per block: bf16(x) with a two-voxel halo in LDS,
+//              expanded into x-triples (the three dx taps of a row in 8 bytes);
 //              layer 1 on the matrix cores over the brick plus a one-voxel halo
-//              (27 taps padded to K = 32); a1 stays in LDS; layer 2 (6912 of the
-//              7776 multiply-adds per voxel) on v_mfma_f32_16x16x16_bf16 with the
-//              16x16 weight block of a tap as A (registers, all 27 taps) and 16
-//              input channels x 16 voxels along x as B (from the LDS tile),
-//              accumulating 16 output channels x 16 voxels over the 27 taps; a2
-//              to HBM (32 B per voxel), a1 only when training keeps it.
-//   k_net_l3t  layer 3 over the same bricks from an LDS tile of a2, two voxels
-//              per thread, with the output update u += s y fused.
-// The backward-data pass of layer 2 is k_net_l2 with the flipped, transposed
-// weights and the ReLU mask of the forward pass.
+//              (9 rows of 3 taps as K = 36 of 64: two v_mfma_f32_16x16x32_bf16 per 16
+//              voxels); a1 stays in LDS; layer 2 (6912 of the 7776 multiply-adds per voxel) on
+//              v_mfma_f32_16x16x32_bf16 with two (dz, dx) offsets of one input row per
+//              B operand (16 voxels along x, 8 channels per lane) and the matching
+//              16 x 32 weight blocks as A (registers), accumulating 16 output channels
+//              x 16 voxels; a2 to HBM (32 B per voxel), a1 only when training keeps it.
+//   k_net_l3t  layer 3 over 16x8x8 bricks from an LDS tile of a2, four voxels per
+//              thread, with the output update u += s y fused.
+// The backward-data pass of layer 2 (k_net_l2bwd) runs the same MFMA loop with the
+// flipped, transposed weights and the ReLU mask of the forward pass.
 #include <algorithm>
 
 #include "gmg_kernels.h"
@@ -33,8 +34,10 @@
 namespace gmg {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kNC = 16;
 constexpr int kTaps = 27;
@@ -50,9 +53,19 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(stati
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // Two FP32 values to packed BF16 (round to nearest even: v_cvt_pk_bf16_f32), a in the low half.
+typedef float float2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  const bf16x2 v = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
-  return __builtin_bit_cast(uint32_t, v);
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v{a, b}, bf16x2));
+}
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// bf16(relu(a)), bf16(relu(b)) packed, a in the low half: rounded first, then every value with
+// the sign bit set (negative or -0) cleared by a 16-bit integer max with 0 (v_pk_max_i16).
+// Rounding to nearest keeps the sign, so this equals rounding the rectified values.
+__device__ __forceinline__ uint32_t pack2_relu(float a, float b) {
+  const short2v v = __builtin_bit_cast(short2v, pack2(a, b));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, short2v{0, 0}));
 }
 
 __device__ __forceinline__ size_t vox(int i, int j, int k, int N) {
@@ -71,25 +84,34 @@ struct ClassTab64 {
 };
 
 // ---------------------------------------------------------------------------- input
-// x_in = bf16(D^-1 r / s) with s = sqrt(ssum / N^3) (or x_in = bf16(x) when dinv is null)
-__global__ void __launch_bounds__(kBlk) k_net_in(const float* __restrict__ r, const ClassTab64 dinv, const int q,
-                                                 const int use_dinv, const double* __restrict__ ssum, const int N,
-                                                 uint16_t* __restrict__ xin) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// x_in = bf16(D^-1 r / s) with s = sqrt(ssum / N^3) (or x_in = bf16(x) when dinv is null);
+// four consecutive voxels of a row per thread (N is a multiple of 4), s formed once per thread.
+constexpr int kInThreads = 64;
+
+__global__ void __launch_bounds__(kInThreads) k_net_in(const float* __restrict__ r, const ClassTab64 dinv,
+                                                       const int q, const int use_dinv,
+                                                       const double* __restrict__ ssum, const int N,
+                                                       uint16_t* __restrict__ xin) {
+  const int i0 = 4 * (blockIdx.x * kInThreads + threadIdx.x);
   const int j = blockIdx.y, k = blockIdx.z;
-  if (i >= N) return;
-  const size_t v = vox(i, j, k, N);
-  float x = r[v];
+  if (i0 >= N) return;
+  const size_t v = vox(i0, j, k, N);
+  const float4 x4 = *reinterpret_cast<const float4*>(r + v);
+  float x[4] = {x4.x, x4.y, x4.z, x4.w};
   if (use_dinv) {
     const double nn = static_cast<double>(N) * N * N;
     const float s = static_cast<float>(sqrt(*ssum / nn));
-    const float d = static_cast<float>(dinv.v[(i % q) + q * ((j % q) + q * (k % q))]);
-    x = (s > 0.0f) ? (d * x) / s : 0.0f;
+    const int base = q * ((j % q) + q * (k % q));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = static_cast<float>(dinv.v[base + (i0 + e) % q]);
+      x[e] = (s > 0.0f) ? (d * x[e]) / s : 0.0f;
+    }
   }
-  xin[v] = f2bf(x);
+  *reinterpret_cast<u32x2*>(xin + v) = u32x2{pack2(x[0], x[1]), pack2(x[2], x[3])};
 }
 
-// sum over voxels of (D^-1 r)^2, one partial per (j, k) row
+// sum over voxels of (D^-1 r)^2, one partial per (j, k) row; four consecutive voxels per thread
 __global__ void __launch_bounds__(kBlk) k_net_sqsum(const float* __restrict__ r, const ClassTab64 dinv, const int q,
                                                     const int N, double* part) {
   __shared__ double red[kBlk / 64];
@@ -97,263 +119,353 @@ __global__ void __launch_bounds__(kBlk) k_net_sqsum(const float* __restrict__ r,
   double s = 0.0;
   const float* row = r + (static_cast<size_t>(k) * N + j) * N;
   const int base = q * ((j % q) + q * (k % q));
-  for (int i = threadIdx.x; i < N; i += kBlk) {
-    const float d = static_cast<float>(dinv.v[base + i % q]);
-    const double t = static_cast<double>(d * row[i]);
-    s = fma(t, t, s);
+  for (int i0 = 4 * threadIdx.x; i0 < N; i0 += 4 * blockDim.x) {
+    const float4 x4 = *reinterpret_cast<const float4*>(row + i0);
+    const float x[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float d = static_cast<float>(dinv.v[base + (i0 + e) % q]);
+      const double t = static_cast<double>(d * x[e]);
+      s = fma(t, t, s);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int w = 0; w < kBlk / 64; ++w) t += red[w];
+    for (int w = 0; w < static_cast<int>(blockDim.x / 64); ++w) t += red[w];
     part[static_cast<size_t>(k) * N + j] = t;
   }
 }
 
 // ---------------------------------------------------------------------------- layer 2 (16 -> 16, MFMA)
+// Bricks of 16x8x4 output voxels; one block of four wavefronts per brick, wavefront tz owning
+// the 8 output rows (16 voxels along x each) of plane tz.  The 16-channel input of the brick
+// plus a one-voxel halo sits in LDS as two half tiles (channels 0-7 and 8-15, 16 bytes per
+// voxel each), so the 16-byte reads of 16 consecutive voxels are free of bank conflicts.
+//
+// The contraction over 27 taps x 16 input channels runs on v_mfma_f32_16x16x32_bf16 (K = 32):
+// the 9 (dz, dx) offsets are taken in pairs (the last with an empty partner), so one B operand
+// holds one input row (16 voxels, 8 channels per lane) at two offsets, and the A operand the
+// matching 16 x 32 weight block for one dy.  Every row loaded from LDS feeds the up to three
+// output rows it is a y-neighbour of: 50 B loads and 120 MFMAs per wavefront.
 constexpr int kBX = 16, kBY = 8, kBZ = 4;
 constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;  // 1080 voxels
+constexpr int kHalf = kHalo + 4;        // half-tile stride in 16-byte entries (bank offset 16)
+constexpr int kPairs = 5;               // ceil(9 / 2) (dz, dx) pairs
 
-// out[v][m] = sum_t sum_k wA[t][m][k] in[v + off(t)][k];  forward: bf16(relu(.)),
-// backward-data (MASK): bf16(. * 1[mask[v][m] > 0]).  N >= 16.
-template <bool MASK>
-__global__ void __launch_bounds__(kBlk) k_net_l2(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wA,
-                                                 const uint16_t* __restrict__ mask, const int N,
-                                                 uint16_t* __restrict__ out) {
-  __shared__ uint2 tile[kHZ * kHY * kHX * 4];  // 4 x (4 bf16) per voxel
+
+__device__ __forceinline__ floatx4 mfma32(const u32x4 a, const u32x4 b, const floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+// (dz, dx) offset of slot f (0, 1) of pair p; the empty partner of the last pair repeats
+// offset 8 (its weights are zero)
+__device__ __forceinline__ int pair_combo(int p, int f) { return min(2 * p + f, 8); }
+
+// A operands of layer 2 for this lane from the lane-ordered copy k_net_pack_lanes writes:
+// entry (p, dy) of lane l is W[t][l & 15][8h .. 8h + 7] for the tap t of pair p, slot g >> 1, dy
+// (g = l >> 4, h = g & 1), zero for the empty slot -- one 16-byte load per operand.
+__device__ __forceinline__ void load_l2_weights(const u32x4* __restrict__ wl, int lane, u32x4 (&wa)[kPairs][3]) {
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) wa[p][dy] = wl[(p * 3 + dy) * 64 + lane];
+}
+
+// acc[ty] (output channels 4g .. 4g+3 of voxel (col, ty, tz)) = sum over taps and input channels.
+// The five B operands of input row r + 1 are loaded while the MFMAs of row r run.
+__device__ __forceinline__ void layer2_wave(const u32x4* __restrict__ tile, const u32x4 (&wa)[kPairs][3], int tz,
+                                            int col, int g, floatx4 (&acc)[kBY]) {
+  const int h = g & 1;
+#pragma unroll
+  for (int ty = 0; ty < kBY; ++ty) acc[ty] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  // per pair: this lane's offset into the tile (slot g >> 1)
+  int off[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    const int c = pair_combo(p, g >> 1);
+    const int dz = c / 3 - 1, dx = c % 3 - 1;
+    off[p] = h * kHalf + ((tz + 1 + dz) * kHY) * kHX + (col + 1 + dx);
+  }
+  u32x4 bq[2][kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) bq[0][p] = tile[off[p]];
+#pragma unroll
+  for (int r = 0; r < kHY; ++r) {
+    if (r + 1 < kHY) {
+#pragma unroll
+      for (int p = 0; p < kPairs; ++p) bq[(r + 1) & 1][p] = tile[off[p] + (r + 1) * kHX];
+    }
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int ty = r - dy;  // the row whose tap dy - 1 reads row r
+        if (ty < 0 || ty >= kBY) continue;
+        acc[ty] = mfma32(wa[p][dy], bq[r & 1][p], acc[ty]);
+      }
+    }
+    __builtin_amdgcn_iglp_opt(0);
+  }
+}
+
+// The 16-channel input of a brick plus a one-voxel halo (kHX x kHY x kHZ voxels, periodic wrap)
+// into the two half tiles, plane by plane: thread t takes the half-voxel entries t and t + 256 of
+// every plane (360 per plane), so the row and column part of each global address is formed once
+// and all loads are issued before the first LDS store.
+__device__ __forceinline__ void fill_halo_tile(const u32x4* __restrict__ in4, int N, int x0, int y0, int z0,
+                                               u32x4* __restrict__ tile) {
+  constexpr int kPlane = kHX * kHY * 2;  // 360 half-voxel entries per plane
+  const int m = N - 1;
+  int src[2], dst[2];
+  bool use[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = threadIdx.x + k * kBlk;
+    use[k] = e < kPlane;
+    const int ee = use[k] ? e : 0;
+    const int h = ee & 1, vx = ee >> 1;
+    const int hx = vx % kHX, hy = vx / kHX;
+    src[k] = ((((y0 - 1 + hy) & m) * N + ((x0 - 1 + hx) & m)) << 1) + h;
+    dst[k] = h * kHalf + hy * kHX + hx;
+  }
+  u32x4 v[kHZ][2];
+#pragma unroll
+  for (int hz = 0; hz < kHZ; ++hz) {
+    const size_t zoff = static_cast<size_t>((z0 - 1 + hz) & m) * N * N * 2;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (use[k]) v[hz][k] = in4[zoff + src[k]];
+  }
+#pragma unroll
+  for (int hz = 0; hz < kHZ; ++hz)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (use[k]) tile[dst[k] + hz * kHX * kHY] = v[hz][k];
+}
+
+// out[v][m] = sum_t sum_k wA[t][m][k] in[v + off(t)][k];  backward-data: bf16(. * 1[mask[v][m] > 0]).
+// N >= 16.
+__global__ void __launch_bounds__(kBlk) k_net_l2bwd(const uint16_t* __restrict__ in, const u32x4* __restrict__ wl,
+                                                    const uint16_t* __restrict__ mask, const int N,
+                                                    uint16_t* __restrict__ out) {
+  __shared__ u32x4 tile[2 * kHalf];
   const int nbx = N / kBX, nby = N / kBY;
   const int b = blockIdx.x;
   const int x0 = (b % nbx) * kBX;
   const int y0 = ((b / nbx) % nby) * kBY;
   const int z0 = (b / (nbx * nby)) * kBZ;
   const int m = N - 1;
-  const uint2* in2 = reinterpret_cast<const uint2*>(in);
-  for (int e = threadIdx.x; e < kHZ * kHY * kHX * 4; e += kBlk) {
-    const int c = e & 3;
-    const int vx = e >> 2;
-    const int hx = vx % kHX, hy = (vx / kHX) % kHY, hz = vx / (kHX * kHY);
-    const size_t g = vox((x0 - 1 + hx) & m, (y0 - 1 + hy) & m, (z0 - 1 + hz) & m, N);
-    tile[e] = in2[g * 4 + c];
-  }
+  const u32x4* in4 = reinterpret_cast<const u32x4*>(in);
+  fill_halo_tile(reinterpret_cast<const u32x4*>(in), N, x0, y0, z0, tile);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int col = lane & 15;   // A row (output channel) / B column (voxel)
-  const int kb = lane >> 4;    // k block: input channels 4 kb .. 4 kb + 3
-  bf16x4 wa[kTaps];
-  const uint2* wA2 = reinterpret_cast<const uint2*>(wA);
-#pragma unroll
-  for (int t = 0; t < kTaps; ++t) {
-    const uint2 u = wA2[(t * kNC + col) * 4 + kb];
-    wa[t] = *reinterpret_cast<const bf16x4*>(&u);
-  }
+  const int col = lane & 15, g = lane >> 4;
+  u32x4 wa[kPairs][3];
+  load_l2_weights(wl, lane, wa);
   __syncthreads();
-  for (int tt = wave; tt < kBY * kBZ; tt += kBlk / 64) {
-    const int ty = tt % kBY, tz = tt / kBY;
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int tz = threadIdx.x >> 6;
+  floatx4 acc[kBY];
+  layer2_wave(tile, wa, tz, col, g, acc);
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-      const int dx = (t % 3) - 1, dy = ((t / 3) % 3) - 1, dz = (t / 9) - 1;
-      const int hidx = ((tz + 1 + dz) * kHY + (ty + 1 + dy)) * kHX + (col + 1 + dx);
-      const uint2 u = tile[hidx * 4 + kb];
-      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&u);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], bv, acc, 0, 0, 0);
-    }
-    // lane holds output channels 4 kb .. 4 kb + 3 of voxel (x0 + col, y0 + ty, z0 + tz)
+  for (int ty = 0; ty < kBY; ++ty) {
     const size_t v = vox(x0 + col, y0 + ty, z0 + tz, N);
-    float o[4];
-    if (MASK) {
-      const uint2 mk = reinterpret_cast<const uint2*>(mask)[v * 4 + kb];
-      const uint16_t mv[4] = {static_cast<uint16_t>(mk.x & 0xFFFF), static_cast<uint16_t>(mk.x >> 16),
-                              static_cast<uint16_t>(mk.y & 0xFFFF), static_cast<uint16_t>(mk.y >> 16)};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = bf2f(mv[r]) > 0.0f ? acc[r] : 0.0f;
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = fmaxf(acc[r], 0.0f);
-    }
-    uint2 pk;
-    pk.x = static_cast<uint32_t>(f2bf(o[0])) | (static_cast<uint32_t>(f2bf(o[1])) << 16);
-    pk.y = static_cast<uint32_t>(f2bf(o[2])) | (static_cast<uint32_t>(f2bf(o[3])) << 16);
-    reinterpret_cast<uint2*>(out)[v * 4 + kb] = pk;
+    const u32x2 mk = reinterpret_cast<const u32x2*>(mask)[v * 4 + g];
+    const float o0 = __uint_as_float(mk.x << 16) > 0.0f ? acc[ty][0] : 0.0f;
+    const float o1 = __uint_as_float(mk.x & 0xFFFF0000u) > 0.0f ? acc[ty][1] : 0.0f;
+    const float o2 = __uint_as_float(mk.y << 16) > 0.0f ? acc[ty][2] : 0.0f;
+    const float o3 = __uint_as_float(mk.y & 0xFFFF0000u) > 0.0f ? acc[ty][3] : 0.0f;
+    reinterpret_cast<u32x2*>(out)[v * 4 + g] = u32x2{pack2(o0, o1), pack2(o2, o3)};
   }
 }
 
 // ---------------------------------------------------------------------------- fused layers 1 + 2
-// One block per 16x8x4 output brick.  bf16(x) of the brick plus a two-voxel halo
-// goes to LDS; layer 1 runs on the matrix cores over the brick plus a one-voxel
-// halo (27 taps as K = 32: two v_mfma_f32_16x16x16_bf16 per 16 voxels, W1 as A,
-// the taps of 16 voxels as B), ReLU and BF16 rounding, into an LDS tile of the
-// same layout layer 2 reads; layer 2 then runs as in k_net_l2.  a1 never goes to
-// HBM unless the caller keeps it (training: the backward pass reads it).
+// One block per 16x8x4 output brick.  bf16(x) of the brick plus a two-voxel halo goes to LDS and
+// is expanded into x-triples: entry (c, row, plane) holds the inputs at columns c - 1, c, c + 1
+// (and a zero), 8 bytes.  Layer 1 runs on the matrix cores over the brick plus a one-voxel halo,
+// 16 voxels per step: the 27 taps are 9 (dz, dy) rows of 3 dx taps, each row one 8-byte read of
+// a triple (4 K slots, the fourth with a zero weight); one v_mfma_f32_16x16x32_bf16 takes rows
+// 0-7 (two per lane group) and a second one row 8.  ReLU and BF16 rounding into the half tiles
+// layer 2 reads; layer 2 as above.  a1 never goes to HBM unless the caller keeps it (training:
+// the backward pass reads it).
 constexpr int kXX = kBX + 4, kXY = kBY + 4, kXZ = kBZ + 4;  // input tile with a two-voxel halo
-constexpr int kHalo = kHX * kHY * kHZ;                      // 1080 voxels of layer 1 output
+constexpr int kTX = kBX + 2;                                 // triple columns (the layer-1 halo width)
+constexpr int kTriples = kTX * kXY * kXZ;                    // 1728 entries of 8 bytes
 
 template <bool KEEP_A1>
-__global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ xin, const float* __restrict__ w1q,
-                                                  const uint16_t* __restrict__ wA, const int N,
+__global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ xin, const u32x4* __restrict__ w1l,
+                                                  const u32x4* __restrict__ wl, const int N,
                                                   uint16_t* __restrict__ a1_out, uint16_t* __restrict__ a2_out) {
-  __shared__ uint16_t xt[kXZ * kXY * kXX];
-  __shared__ uint2 tile[kHalo * 4];
+  __shared__ u32x2 x3[kTriples];
+  __shared__ u32x4 tile[2 * kHalf];
+  static_assert(kXZ * kXY * kXX * sizeof(uint16_t) <= sizeof(tile), "the plain input tile fits in the half tiles");
+  uint16_t* xt = reinterpret_cast<uint16_t*>(tile);  // plain input tile, dead once the triples are built
   const int nbx = N / kBX, nby = N / kBY;
   const int b = blockIdx.x;
   const int x0 = (b % nbx) * kBX;
   const int y0 = ((b / nbx) % nby) * kBY;
   const int z0 = (b / (nbx * nby)) * kBZ;
   const int m = N - 1;
-  for (int e = threadIdx.x; e < kXZ * kXY * kXX; e += kBlk) {
-    const int hx = e % kXX, hy = (e / kXX) % kXY, hz = e / (kXX * kXY);
-    xt[e] = xin[vox((x0 - 2 + hx) & m, (y0 - 2 + hy) & m, (z0 - 2 + hz) & m, N)];
+  {  // plane by plane: thread t < 240 takes column t % 20 of row t / 20 in every plane, so the row
+     // and column part of the global address is formed once; all loads before the first store
+    constexpr int kRowCol = kXY * kXX;  // 240
+    const int t = threadIdx.x < kRowCol ? threadIdx.x : 0;
+    const int hx = t % kXX, hy = t / kXX;
+    const int src = ((y0 - 2 + hy) & m) * N + ((x0 - 2 + hx) & m);
+    uint16_t v[kXZ];
+#pragma unroll
+    for (int hz = 0; hz < kXZ; ++hz)
+      v[hz] = xin[static_cast<size_t>((z0 - 2 + hz) & m) * N * N + src];
+    if (threadIdx.x < kRowCol) {
+#pragma unroll
+      for (int hz = 0; hz < kXZ; ++hz) xt[hz * kRowCol + t] = v[hz];
+    }
   }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = lane & 15;
-  const int kb = lane >> 4;
-  // W1 as the A operand: row = output channel col, k = taps 16 j + 4 kb + r
-  bf16x4 w1a[2];
+  const int g = lane >> 4;
+  // W1 as the A operands (lane-ordered copy, k_net_pack_lanes): row = output channel col; first
+  // MFMA, lane group g: (dz, dy) rows 2g and 2g + 1, taps dx = -1, 0, 1 and a zero each; second
+  // MFMA: row 8 in group 0, zeros elsewhere.  Tap of row rho and dx: 3 rho + dx + 1.
+  const u32x4 w1a = w1l[lane], w1b = w1l[64 + lane];
+  u32x4 wa[kPairs][3];
+  load_l2_weights(wl, lane, wa);
+  // this lane's triple offsets for rows 2g and 2g + 1 ((dz, dy) of row rho: rho / 3 - 1, rho % 3 - 1)
+  const int offa = ((2 * g) / 3 - 1) * kXY * kTX + ((2 * g) % 3 - 1) * kTX;
+  const int offb = ((2 * g + 1) / 3 - 1) * kXY * kTX + ((2 * g + 1) % 3 - 1) * kTX;
+  constexpr int off8 = kXY * kTX + kTX;  // row 8: dz = dy = 1
+  __syncthreads();
+  // triples: entry (c - 1, row, plane) for triple columns c = 1 .. kTX of the input tile; thread
+  // t < 216 takes column t % 18 of row t / 18 in every plane (constant offsets per plane)
+  if (threadIdx.x < kTX * kXY) {
+    const int c = threadIdx.x % kTX, row = threadIdx.x / kTX;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    short h[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int t = 16 * j + 4 * kb + r;
-      h[r] = t < kTaps ? static_cast<short>(f2bf(w1q[t * kNC + col])) : static_cast<short>(0);
+    for (int pl = 0; pl < kXZ; ++pl) {
+      const uint16_t* src = xt + (pl * kXY + row) * kXX + c;
+      x3[(pl * kXY + row) * kTX + c] = u32x2{static_cast<uint32_t>(src[0]) | (static_cast<uint32_t>(src[1]) << 16), src[2]};
     }
-    w1a[j] = bf16x4{h[0], h[1], h[2], h[3]};
-  }
-  bf16x4 wa[kTaps];
-  const uint2* wA2 = reinterpret_cast<const uint2*>(wA);
-#pragma unroll
-  for (int t = 0; t < kTaps; ++t) {
-    const uint2 u = wA2[(t * kNC + col) * 4 + kb];
-    wa[t] = *reinterpret_cast<const bf16x4*>(&u);
   }
   __syncthreads();
-  // per-lane tap offsets in the input tile: taps 16 j + 4 kb + r (taps >= 27 read zero)
-  int toff[8];
-  bool tuse[8];
+  // layer 1 over the 1080 voxels of the brick plus a one-voxel halo, 16 at a time: wavefront w
+  // takes groups w, w + 4, ..., 17 of them (the last partly beyond the 1080).  Voxel e = hx + 18 hy
+  // + 180 hz has its centre triple at e + 234 + 36 hz.
+  constexpr int kGroups = (kHalo + 15) / 16;
+  static_assert(kGroups % (kBlk / 64) == 0, "every wavefront takes the same number of groups");
+  static_assert(kTX == kHX && kTX * (kXY - kHY) == 36 && kXY * kTX + kTX == 234, "triple index of a halo voxel");
+  int e = 16 * wave + col;
+  int hz = e / (kHX * kHY);
+  int rem = e - hz * (kHX * kHY);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int t = 16 * (i >> 2) + 4 * kb + (i & 3);
-    tuse[i] = t < kTaps;
-    const int dx = (t % 3) - 1, dy = ((t / 3) % 3) - 1, dz = (t / 9) - 1;
-    toff[i] = tuse[i] ? (dz * kXY + dy) * kXX + dx : 0;
-  }
-  // layer 1 over the 1080 voxels of the brick plus a one-voxel halo, 16 at a time
-  for (int g = wave; g < (kHalo + 15) / 16; g += kBlk / 64) {
-    const int e = 16 * g + col;
+  for (int it = 0; it < kGroups / (kBlk / 64); ++it) {
     const bool live = e < kHalo;
-    const int ec = live ? e : kHalo - 1;
-    const int hz = ec / (kHX * kHY);
-    const int rem = ec - hz * (kHX * kHY);
-    const int hy = rem / kHX;
-    const int hx = rem - hy * kHX;
-    const int base = ((hz + 1) * kXY + (hy + 1)) * kXX + (hx + 1);
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      short h[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h[r] = tuse[4 * j + r] ? static_cast<short>(xt[base + toff[4 * j + r]]) : short(0);
-      const bf16x4 bv{h[0], h[1], h[2], h[3]};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1a[j], bv, acc, 0, 0, 0);
+    const int c3 = live ? e + off8 + 36 * hz : off8;  // centre triple of voxel e
+    const u32x2 ta = x3[c3 + offa], tb = x3[c3 + offb], t8 = x3[c3 + off8];
+    floatx4 acc = mfma32(w1a, u32x4{ta.x, ta.y, tb.x, tb.y}, floatx4{0.0f, 0.0f, 0.0f, 0.0f});
+    acc = mfma32(w1b, u32x4{t8.x, t8.y, 0u, 0u}, acc);
+    // lane holds output channels 4 g .. 4 g + 3 of voxel e: half g >> 1, bytes 8 (g & 1) ..
+    const u32x2 pk{pack2_relu(acc[0], acc[1]), pack2_relu(acc[2], acc[3])};
+    // lanes past the 1080 voxels store into the half tiles' padding (no branch in the loop)
+    reinterpret_cast<u32x2*>(tile + (g >> 1) * kHalf + (live ? e : kHalo + (e & 3)))[g & 1] = pk;
+    if (KEEP_A1 && live) {
+      const int hy = rem / kHX, hx = rem - (rem / kHX) * kHX;
+      if (hx >= 1 && hx <= kBX && hy >= 1 && hy <= kBY && hz >= 1 && hz <= kBZ)
+        reinterpret_cast<u32x2*>(a1_out)[vox(x0 + hx - 1, y0 + hy - 1, z0 + hz - 1, N) * 4 + g] = pk;
     }
-    // lane holds output channels 4 kb .. 4 kb + 3 of voxel e
-    uint2 pk;
-    pk.x = pack2(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f));
-    pk.y = pack2(fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
-    if (live) {
-      tile[e * 4 + kb] = pk;
-      if (KEEP_A1 && hx >= 1 && hx <= kBX && hy >= 1 && hy <= kBY && hz >= 1 && hz <= kBZ)
-        reinterpret_cast<uint2*>(a1_out)[vox(x0 + hx - 1, y0 + hy - 1, z0 + hz - 1, N) * 4 + kb] = pk;
+    e += 64;
+    rem += 64;
+    if (rem >= kHX * kHY) {
+      rem -= kHX * kHY;
+      ++hz;
     }
+    __builtin_amdgcn_iglp_opt(0);
   }
   __syncthreads();
-  // layer 2: wave tz owns the 8 output rows of plane tz (16 channels x 16 voxels
-  // each).  Every a1 row loaded from LDS feeds the up to three output rows it is
-  // a y-neighbour of, so the tile is read 90 times per wave instead of 216.
   static_assert(kBlk / 64 == kBZ, "one wave per plane of the brick");
   const int tz = wave;
   floatx4 acc[kBY];
-#pragma unroll
-  for (int ty = 0; ty < kBY; ++ty) acc[ty] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx)
-#pragma unroll
-      for (int r = 0; r < kHY; ++r) {
-        const uint2 u = tile[(((tz + 1 + dz) * kHY + r) * kHX + (col + 1 + dx)) * 4 + kb];
-        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&u);
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-          const int ty = r - 1 - dy;
-          if (ty < 0 || ty >= kBY) continue;
-          const int t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-          acc[ty] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], bv, acc[ty], 0, 0, 0);
-        }
-      }
+  layer2_wave(tile, wa, tz, col, g, acc);
 #pragma unroll
   for (int ty = 0; ty < kBY; ++ty) {
     const size_t v = vox(x0 + col, y0 + ty, z0 + tz, N);
-    uint2 pk;
-    pk.x = pack2(fmaxf(acc[ty][0], 0.0f), fmaxf(acc[ty][1], 0.0f));
-    pk.y = pack2(fmaxf(acc[ty][2], 0.0f), fmaxf(acc[ty][3], 0.0f));
-    reinterpret_cast<uint2*>(a2_out)[v * 4 + kb] = pk;
+    reinterpret_cast<u32x2*>(a2_out)[v * 4 + g] =
+        u32x2{pack2_relu(acc[ty][0], acc[ty][1]), pack2_relu(acc[ty][2], acc[ty][3])};
   }
 }
 
 // ---------------------------------------------------------------------------- layer 3, LDS-tiled
-// y = W3 * a2 over one 16x8x4 brick: a2 of the brick plus a one-voxel halo in LDS,
-// each thread two neighbouring voxels along x (the 4 x-columns they need are read
-// once for both).  Channel pairs go through v_dot2c_f32_bf16 (two BF16 products
-// added to the FP32 accumulator) straight from the packed activations; the sum
-// runs over taps t = 0..26, then channel pairs.  Tile rows are padded by 16 bytes
-// so the 128-bit reads of neighbouring rows fall on different LDS banks.
-constexpr int kRowU2 = kHX * 4 + 2;  // uint2 per padded tile row
+// y = W3 * a2 over bricks of 16x8x8 voxels: a2 of the brick plus a one-voxel halo in LDS (rows of
+// 18 voxels x 32 bytes, padded to 592 bytes), each thread four neighbouring voxels along x, so
+// the 6 x-columns they need are read once for all four.  Channel pairs go through
+// v_dot2_f32_bf16 (two BF16 products added to the FP32 accumulator) straight from the packed
+// activations, with the packed weights read through the scalar cache; per voxel the sum runs
+// over taps t = 0..26, then channel pairs.  Lanes are ordered row-fastest: the 8 rows of one
+// 16-byte read phase fall on disjoint banks with the 592-byte row stride.
+constexpr int k3X = 16, k3Y = 8, k3Z = 8;
+constexpr int k3HX = k3X + 2, k3HY = k3Y + 2, k3HZ = k3Z + 2;
+constexpr int k3Row = k3HX * 2 + 1;  // 16-byte entries per padded tile row (37 = 592 bytes)
 
 __device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
   return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
 }
 
-__global__ void __launch_bounds__(kBlk) k_net_l3t(const uint16_t* __restrict__ a2, const float* __restrict__ w3q,
+__global__ void __launch_bounds__(kBlk) k_net_l3t(const uint16_t* __restrict__ a2, const uint32_t* __restrict__ w3p,
                                                   const int N, const int mode, const double* __restrict__ ssum,
                                                   float* __restrict__ y) {
-  __shared__ __align__(16) uint2 tile[kHZ * kHY * kRowU2];
-  __shared__ uint32_t w[kTaps * kNC / 2];  // [t][channel pair], BF16 pairs
-  const int nbx = N / kBX, nby = N / kBY;
+  __shared__ u32x4 tile[k3HZ * k3HY * k3Row];
+  const int nbx = N / k3X, nby = N / k3Y;
   const int b = blockIdx.x;
-  const int x0 = (b % nbx) * kBX;
-  const int y0 = ((b / nbx) % nby) * kBY;
-  const int z0 = (b / (nbx * nby)) * kBZ;
+  const int x0 = (b % nbx) * k3X;
+  const int y0 = ((b / nbx) % nby) * k3Y;
+  const int z0 = (b / (nbx * nby)) * k3Z;
   const int m = N - 1;
-  const uint2* in2 = reinterpret_cast<const uint2*>(a2);
-  for (int e = threadIdx.x; e < kHalo * 4; e += kBlk) {
-    const int c = e & 3;
-    const int vx = e >> 2;
-    const int hx = vx % kHX, hy = (vx / kHX) % kHY, hz = vx / (kHX * kHY);
-    tile[(hz * kHY + hy) * kRowU2 + hx * 4 + c] =
-        in2[vox((x0 - 1 + hx) & m, (y0 - 1 + hy) & m, (z0 - 1 + hz) & m, N) * 4 + c];
+  const u32x4* in4 = reinterpret_cast<const u32x4*>(a2);
+  {  // plane by plane (360 half-voxel entries each): thread t takes entries t and t + 256 of every
+     // plane, the row and column part of each address formed once, all loads before the stores
+    constexpr int kPlane = k3HX * k3HY * 2;
+    int src[2], dst[2];
+    bool use[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = threadIdx.x + k * kBlk;
+      use[k] = e < kPlane;
+      const int ee = use[k] ? e : 0;
+      const int c = ee & 1, vx = ee >> 1;
+      const int hx = vx % k3HX, hy = vx / k3HX;
+      src[k] = ((((y0 - 1 + hy) & m) * N + ((x0 - 1 + hx) & m)) << 1) + c;
+      dst[k] = hy * k3Row + hx * 2 + c;
+    }
+    u32x4 v[k3HZ][2];
+#pragma unroll
+    for (int hz = 0; hz < k3HZ; ++hz) {
+      const size_t zoff = static_cast<size_t>((z0 - 1 + hz) & m) * N * N * 2;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (use[k]) v[hz][k] = in4[zoff + src[k]];
+    }
+#pragma unroll
+    for (int hz = 0; hz < k3HZ; ++hz)
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (use[k]) tile[hz * k3HY * k3Row + dst[k]] = v[hz][k];
   }
-  for (int e = threadIdx.x; e < kTaps * kNC / 2; e += kBlk)
-    w[e] = static_cast<uint32_t>(f2bf(w3q[2 * e])) | (static_cast<uint32_t>(f2bf(w3q[2 * e + 1])) << 16);
   __syncthreads();
-  const int xp = threadIdx.x & 7;          // voxel pair along x
-  const int ty = (threadIdx.x >> 3) & 7;
-  const int tz = threadIdx.x >> 6;
-  const int hx0 = 2 * xp;                   // halo column of x - 1 for the first voxel
-  float acc0 = 0.0f, acc1 = 0.0f;
+  const int ty = threadIdx.x & 7;          // row fastest
+  const int xq = (threadIdx.x >> 3) & 3;   // voxel quad along x
+  const int tz = threadIdx.x >> 5;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz)
+  for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int rowb = ((tz + 1 + dz) * kHY + (ty + 1 + dy)) * kRowU2;
-      uint32_t a[4][kNC / 2];
+    for (int dy = 0; dy < 3; ++dy) {
+      const u32x4* row = tile + ((tz + dz) * k3HY + (ty + dy)) * k3Row + 8 * xq;
+      uint32_t a[6][kNC / 2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint4* q = reinterpret_cast<const uint4*>(tile + rowb + (hx0 + k) * 4);
-        const uint4 u0 = q[0], u1 = q[1];
+      for (int k = 0; k < 6; ++k) {
+        const u32x4 u0 = row[2 * k], u1 = row[2 * k + 1];
         a[k][0] = u0.x;
         a[k][1] = u0.y;
         a[k][2] = u0.z;
@@ -363,26 +475,30 @@ __global__ void __launch_bounds__(kBlk) k_net_l3t(const uint16_t* __restrict__ a
         a[k][6] = u1.z;
         a[k][7] = u1.w;
       }
-      const int tb = (dz + 1) * 9 + (dy + 1) * 3;
+      const int tb = dz * 9 + dy * 3;
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const uint32_t* wt = w + (tb + dx) * (kNC / 2);
+        const uint32_t* wt = w3p + (tb + dx) * (kNC / 2);
 #pragma unroll
         for (int c = 0; c < kNC / 2; ++c) {
-          acc0 = dot2(a[dx][c], wt[c], acc0);
-          acc1 = dot2(a[dx + 1][c], wt[c], acc1);
+          const uint32_t w = wt[c];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = dot2(a[v + dx][c], w, acc[v]);
         }
       }
     }
-  const size_t v = vox(x0 + 2 * xp, y0 + ty, z0 + tz, N);
+  float* dst = y + vox(x0 + 4 * xq, y0 + ty, z0 + tz, N);
   if (mode == 0) {
-    y[v] = acc0;
-    y[v + 1] = acc1;
+    *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
   } else {
     const double nn = static_cast<double>(N) * N * N;
     const float sc = static_cast<float>(sqrt(*ssum / nn));
-    y[v] += sc * acc0;
-    y[v + 1] += sc * acc1;
+    float4 o = *reinterpret_cast<const float4*>(dst);
+    o.x += sc * acc[0];
+    o.y += sc * acc[1];
+    o.z += sc * acc[2];
+    o.w += sc * acc[3];
+    *reinterpret_cast<float4*>(dst) = o;
   }
 }
 
@@ -500,10 +616,10 @@ __global__ void __launch_bounds__(kBlk) k_net_wgrad13(const float* __restrict__ 
   if (threadIdx.x < kNC) part[(static_cast<size_t>(blockIdx.x) * kTaps + t) * kNC + threadIdx.x] = red[0][threadIdx.x];
 }
 
-// Layer-2 weight gradient on the matrix cores: for each tap,
-// D[o][i] += sum over 16-voxel groups of G^T (16 o x 16 voxels) X_t (16 voxels x 16 i),
-// G = g2, X_t = a1 shifted by the tap.  Each wavefront sums kW2Vox voxels and
-// writes one partial of 27 x 256 values.
+// Layer-2 weight gradient on the matrix cores (v_mfma_f32_16x16x32_bf16): for each tap,
+// D[o][i] += sum over 32-voxel groups of G^T (16 o x 32 voxels) X_t (32 voxels x 16 i),
+// G = g2, X_t = a1 shifted by the tap.  Each wavefront sums kW2Vox voxels and writes one
+// partial of 27 x 256 values.
 constexpr int kW2Vox = 2048;
 
 __global__ void __launch_bounds__(kBlk) k_net_wgrad2(const uint16_t* __restrict__ g2, const uint16_t* __restrict__ a1,
@@ -512,36 +628,39 @@ __global__ void __launch_bounds__(kBlk) k_net_wgrad2(const uint16_t* __restrict_
   const int wv = blockIdx.x * (kBlk / 64) + (threadIdx.x >> 6);
   const size_t nv = static_cast<size_t>(N) * N * N;
   const size_t v0 = static_cast<size_t>(wv) * kW2Vox;
-  const int col = lane & 15, kb = lane >> 4;
+  const int col = lane & 15, g = lane >> 4;
   floatx4 acc[kTaps];
 #pragma unroll
   for (int t = 0; t < kTaps; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (size_t g = v0; g < v0 + kW2Vox && g < nv; g += 16) {
-    // group of 16 consecutive voxels along x (N is a multiple of 16)
-    const int i0 = static_cast<int>(g % N);
-    const int j = static_cast<int>((g / N) % N);
-    const int k = static_cast<int>(g / (static_cast<size_t>(N) * N));
-    // A[m = o = col][kk = voxel 4 kb + r] = g2[g + 4 kb + r][col]
-    short av[4];
+  for (size_t g0 = v0; g0 < v0 + kW2Vox && g0 < nv; g0 += 32) {
+    // this lane's voxels g0 + 8 g + e, e = 0 .. 7 (N^3 is a multiple of 32)
+    int vi[8], vj[8], vk[8];
+    uint32_t av[8];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) av[r] = static_cast<short>(g2[(g + 4 * kb + r) * kNC + col]);
-    const bf16x4 a = {av[0], av[1], av[2], av[3]};
+    for (int e = 0; e < 8; ++e) {
+      const size_t v = g0 + 8 * g + e;
+      vi[e] = static_cast<int>(v % N);
+      vj[e] = static_cast<int>((v / N) % N);
+      vk[e] = static_cast<int>(v / (static_cast<size_t>(N) * N));
+      av[e] = g2[v * kNC + col];  // A[m = o = col][k = voxel]
+    }
+    const u32x4 a{av[0] | (av[1] << 16), av[2] | (av[3] << 16), av[4] | (av[5] << 16), av[6] | (av[7] << 16)};
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) {
-      // B[kk = voxel 4 kb + r][n = i = col] = a1[(voxel + off(t))][col]
-      short bv[4];
+      // B[k = voxel][n = i = col] = a1[voxel + off(t)][col]
+      uint32_t bv[8];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bv[r] = static_cast<short>(a1[nbr(i0 + 4 * kb + r, j, k, t, 1, N) * kNC + col]);
-      const bf16x4 b = {bv[0], bv[1], bv[2], bv[3]};
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) bv[e] = a1[nbr(vi[e], vj[e], vk[e], t, 1, N) * kNC + col];
+      const u32x4 b{bv[0] | (bv[1] << 16), bv[2] | (bv[3] << 16), bv[4] | (bv[5] << 16), bv[6] | (bv[7] << 16)};
+      acc[t] = mfma32(a, b, acc[t]);
     }
   }
-  // D[o = 4 kb + r][i = col]
+  // D[o = 4 g + r][i = col]
   float* dst = part + static_cast<size_t>(wv) * kTaps * kNC * kNC;
 #pragma unroll
   for (int t = 0; t < kTaps; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[(t * kNC + 4 * kb + r) * kNC + col] = acc[t][r];
+    for (int r = 0; r < 4; ++r) dst[(t * kNC + 4 * g + r) * kNC + col] = acc[t][r];
 }
 
 // gw[base + (o * nin + i) * 27 + t] += sum_p part[p][t][o][i]   (fixed order)
@@ -563,8 +682,13 @@ __global__ void __launch_bounds__(kBlk) k_net_reduce(const float* __restrict__ p
 // (backward-data A operand).
 __global__ void __launch_bounds__(kBlk) k_net_pack(const float* __restrict__ w, float* __restrict__ w1q,
                                                    uint16_t* __restrict__ w2f, uint16_t* __restrict__ w2b,
-                                                   float* __restrict__ w3q) {
+                                                   float* __restrict__ w3q, uint32_t* __restrict__ w3p) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < kTaps * kNC / 2) {  // w3p[t][channel pair]: BF16 pairs of W3[2c][t], W3[2c + 1][t]
+    const int t = e / (kNC / 2), c = e % (kNC / 2);
+    w3p[e] = static_cast<uint32_t>(f2bf(w[432 + 6912 + (2 * c) * kTaps + t])) |
+             (static_cast<uint32_t>(f2bf(w[432 + 6912 + (2 * c + 1) * kTaps + t])) << 16);
+  }
   if (e < 432) {
     const int co = e / kTaps, t = e % kTaps;
     w1q[t * kNC + co] = bf2f(f2bf(w[e]));
@@ -578,6 +702,43 @@ __global__ void __launch_bounds__(kBlk) k_net_pack(const float* __restrict__ w, 
     const int f = e - 432 - 6912;
     const int ci = f / kTaps, t = f % kTaps;
     w3q[t * kNC + ci] = bf2f(f2bf(w[e]));
+  }
+}
+
+// Lane-ordered copies of the MFMA A operands, one 16-byte entry per (operand, lane), so a lane
+// loads each operand with one load at a fixed offset:
+//   w2fl / w2bl  entry (p * 3 + dy) * 64 + l: w2f / w2b[t][l & 15][8h .. 8h + 7] for the tap t of
+//                (dz, dx) pair p, slot (l >> 4) >> 1, and dy (h = (l >> 4) & 1), zero for the empty
+//                slot of the last pair (see load_l2_weights);
+//   w1l          entry l: W1 taps of (dz, dy) rows 2g and 2g + 1 (dx = -1, 0, 1, then a zero, each)
+//                for output channel l & 15, g = l >> 4; entry 64 + l: row 8 in group 0, else zero.
+__global__ void __launch_bounds__(kBlk) k_net_pack_lanes(const uint16_t* __restrict__ w2f,
+                                                         const uint16_t* __restrict__ w2b,
+                                                         const float* __restrict__ w1q, u32x4* __restrict__ w2fl,
+                                                         u32x4* __restrict__ w2bl, u32x4* __restrict__ w1l) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < kPairs * 3 * 64) {
+    const int l = e % 64, pd = e / 64, p = pd / 3, dy = pd % 3;
+    const int col = l & 15, g = l >> 4, h = g & 1, c = 2 * p + (g >> 1);
+    u32x4 f{0u, 0u, 0u, 0u}, bk{0u, 0u, 0u, 0u};
+    if (c < 9) {
+      const int t = (c / 3) * 9 + dy * 3 + (c % 3);
+      f = *reinterpret_cast<const u32x4*>(w2f + (t * kNC + col) * kNC + 8 * h);
+      bk = *reinterpret_cast<const u32x4*>(w2b + (t * kNC + col) * kNC + 8 * h);
+    }
+    w2fl[e] = f;
+    w2bl[e] = bk;
+  } else if (e < kPairs * 3 * 64 + 128) {
+    const int f = e - kPairs * 3 * 64;
+    const int l = f % 64, col = l & 15, g = l >> 4;
+    auto wt = [&](int t) { return w1q[t * kNC + col]; };
+    if (f < 64) {
+      const int ra = 2 * g, rb = 2 * g + 1;
+      w1l[f] = u32x4{pack2(wt(3 * ra), wt(3 * ra + 1)), pack2(wt(3 * ra + 2), 0.0f), pack2(wt(3 * rb), wt(3 * rb + 1)),
+                     pack2(wt(3 * rb + 2), 0.0f)};
+    } else {
+      w1l[f] = g == 0 ? u32x4{pack2(wt(24), wt(25)), pack2(wt(26), 0.0f), 0u, 0u} : u32x4{0u, 0u, 0u, 0u};
+    }
   }
 }
 
@@ -618,6 +779,7 @@ __global__ void __launch_bounds__(kBlk) k_loss_gy(const float* __restrict__ d, c
 }
 
 inline dim3 vgrid(int N) { return dim3((N + kBlk - 1) / kBlk, N, N); }
+inline dim3 in_grid(int N) { return dim3((N / 4 + kInThreads - 1) / kInThreads, N, N); }
 
 ClassTab64 ctab(const double* t, int q) {
   ClassTab64 c{};
@@ -642,22 +804,30 @@ int64_t net_partial_floats(int N) {
 }
 
 hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_net_pack, dim3((7776 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, w, d.w1q, d.w2f, d.w2b, d.w3q);
+  hipLaunchKernelGGL(k_net_pack, dim3((7776 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, w, d.w1q, d.w2f, d.w2b, d.w3q,
+                     d.w3p);
+  hipLaunchKernelGGL(k_net_pack_lanes, dim3((kPairs * 3 * 64 + 128 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, d.w2f,
+                     d.w2b, d.w1q, reinterpret_cast<u32x4*>(d.w2fl), reinterpret_cast<u32x4*>(d.w2bl),
+                     reinterpret_cast<u32x4*>(d.w1l));
   return hipGetLastError();
 }
 
 hipError_t launch_net_input(const float* r, const double* dinv, int q, const double* ssum, double* part,
                             int64_t part_cap, int N, void* cache, hipStream_t s) {
   uint16_t* xin = static_cast<uint16_t*>(cache);
+  // rows are read four values at a time
+  if (N % 4 != 0 || reinterpret_cast<uintptr_t>(r) % 16 != 0 || reinterpret_cast<uintptr_t>(cache) % 16 != 0)
+    return hipErrorInvalidValue;
   if (dinv) {
     const ClassTab64 c = ctab(dinv, q);
-    hipLaunchKernelGGL(k_net_sqsum, dim3(1, N, N), dim3(kBlk), 0, s, r, c, q, N, part);
+    const int sq_threads = std::min(kBlk, std::max(64, (N / 4 + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_net_sqsum, dim3(1, N, N), dim3(sq_threads), 0, s, r, c, q, N, part);
     const hipError_t e = launch_sum_partials(part, static_cast<int64_t>(N) * N, part_cap, const_cast<double*>(ssum), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_net_in, vgrid(N), dim3(kBlk), 0, s, r, c, q, 1, ssum, N, xin);
+    hipLaunchKernelGGL(k_net_in, in_grid(N), dim3(kInThreads), 0, s, r, c, q, 1, ssum, N, xin);
   } else {
     const ClassTab64 c{};
-    hipLaunchKernelGGL(k_net_in, vgrid(N), dim3(kBlk), 0, s, r, c, q, 0, ssum, N, xin);
+    hipLaunchKernelGGL(k_net_in, in_grid(N), dim3(kInThreads), 0, s, r, c, q, 0, ssum, N, xin);
   }
   return hipGetLastError();
 }
@@ -671,10 +841,13 @@ hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, con
   uint16_t* a2 = a1 + nv * kNC;
   const int nb = (N / kBX) * (N / kBY) * (N / kBZ);
   if (keep_a1)
-    hipLaunchKernelGGL(k_net_l12<true>, dim3(nb), dim3(kBlk), 0, s, xin, d.w1q, d.w2f, N, a1, a2);
+    hipLaunchKernelGGL(k_net_l12<true>, dim3(nb), dim3(kBlk), 0, s, xin, reinterpret_cast<const u32x4*>(d.w1l),
+                       reinterpret_cast<const u32x4*>(d.w2fl), N, a1, a2);
   else
-    hipLaunchKernelGGL(k_net_l12<false>, dim3(nb), dim3(kBlk), 0, s, xin, d.w1q, d.w2f, N, nullptr, a2);
-  hipLaunchKernelGGL(k_net_l3t, dim3(nb), dim3(kBlk), 0, s, a2, d.w3q, N, mode, ssum, y);
+    hipLaunchKernelGGL(k_net_l12<false>, dim3(nb), dim3(kBlk), 0, s, xin, reinterpret_cast<const u32x4*>(d.w1l),
+                       reinterpret_cast<const u32x4*>(d.w2fl), N, nullptr, a2);
+  const int nb3 = (N / k3X) * (N / k3Y) * (N / k3Z);
+  hipLaunchKernelGGL(k_net_l3t, dim3(nb3), dim3(kBlk), 0, s, a2, d.w3p, N, mode, ssum, y);
   return hipGetLastError();
 }
 
@@ -689,7 +862,8 @@ hipError_t launch_net_backward(const NetDev& d, int N, const void* cache, const 
   uint16_t* g1 = g2 + nv * kNC;
   hipLaunchKernelGGL(k_net_l3_bwd, vgrid(N), dim3(kBlk), 0, s, gy, a2, d.w3q, N, g2);
   const int nb = (N / kBX) * (N / kBY) * (N / kBZ);
-  hipLaunchKernelGGL(k_net_l2<true>, dim3(nb), dim3(kBlk), 0, s, g2, d.w2b, a1, N, g1);
+  hipLaunchKernelGGL(k_net_l2bwd, dim3(nb), dim3(kBlk), 0, s, g2, reinterpret_cast<const u32x4*>(d.w2bl), a1, N,
+                     g1);
   // layer 3 weights
   const int nch = static_cast<int>((nv + kWgChunk - 1) / kWgChunk);
   hipLaunchKernelGGL(k_net_wgrad13<3>, dim3(nch, kTaps), dim3(kBlk), 0, s, gy, a2, nullptr, nullptr, N, part);

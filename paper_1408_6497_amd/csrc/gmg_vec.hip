@@ -68,13 +68,26 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;  // valid in thread 0
 }
 
+// Each thread visits i, i + S, i + 2 S, ... (S = threads in the grid) in that order and
+// sums in that order; the loads of four visits are issued before their products, so
+// more bytes are in flight per thread than in the one-visit loop (same sums, bit for bit).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dot(const int64_t n, const T* __restrict__ x, const T* __restrict__ y,
                                                  double* part) {
   double s = 0.0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    s = fma(static_cast<double>(x[i]), static_cast<double>(y ? y[i] : T(1)), s);
+  const int64_t S = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {
+    T xv[4], yv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = x[i + k * S];
+      yv[k] = y ? y[i + k * S] : T(1);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s = fma(static_cast<double>(xv[k]), static_cast<double>(yv[k]), s);
+  }
+  for (; i < n; i += S) s = fma(static_cast<double>(x[i]), static_cast<double>(y ? y[i] : T(1)), s);
   s = block_sum(s);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -127,6 +140,37 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
 }
 
 // Fused reductions of the Krylov loop.  Each block writes its partials to
+// (x.x, y.y) in one pass, visiting as k_dot does
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sq2(const int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                                                 double* part) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  const int64_t S = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {
+    T xv[4], yv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = x[i + k * S];
+      yv[k] = y[i + k * S];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a = fma(static_cast<double>(xv[k]), static_cast<double>(xv[k]), a);
+      b = fma(static_cast<double>(yv[k]), static_cast<double>(yv[k]), b);
+    }
+  }
+  for (; i < n; i += S) {
+    a = fma(static_cast<double>(x[i]), static_cast<double>(x[i]), a);
+    b = fma(static_cast<double>(y[i]), static_cast<double>(y[i]), b);
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+  }
+}
+
 // part[k * nblocks + block] (k = 0, 1, 2); k_finish_multi folds them in a fixed order.
 // (x.y, x.z)
 template <typename T>
@@ -182,8 +226,29 @@ __global__ void __launch_bounds__(kBlock) k_axpy2_cast(const int64_t n, const do
   const double al = sc[inum] / sc[iden];
   const double m = (sc[irs] - al * sc[iws]) * scale;
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  // visits in k_dot's order, the loads of four visits issued together
+  const int64_t S = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {
+    double uv[4], pv[4], rv[4], wv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uv[k] = u[i + k * S];
+      pv[k] = p[i + k * S];
+      rv[k] = r[i + k * S];
+      wv[k] = w[i + k * S];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u[i + k * S] = fma(al, pv[k], uv[k]);
+      const double v = fma(-al, wv[k], rv[k]) - m;
+      r[i + k * S] = v;
+      r32[i + k * S] = static_cast<float>(v);
+      a += v;
+      b = fma(v, v, b);
+    }
+  }
+  for (; i < n; i += S) {
     u[i] = fma(al, p[i], u[i]);
     const double v = fma(-al, w[i], r[i]) - m;
     r[i] = v;
@@ -323,9 +388,20 @@ __global__ void __launch_bounds__(kBlock) k_xpby_shift_mixed(const int64_t n, co
                                                              double* p) {
   const double be = sgn * sc[inum] / sc[iden];
   const double m = sc[imean] * scale;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    p[i] = fma(be, p[i], static_cast<double>(z[i]) - m);
+  const int64_t S = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (; i + 3 * S < n; i += 4 * S) {
+    double pv[4];
+    float zv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pv[k] = p[i + k * S];
+      zv[k] = z[i + k * S];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[i + k * S] = fma(be, pv[k], static_cast<double>(zv[k]) - m);
+  }
+  for (; i < n; i += S) p[i] = fma(be, p[i], static_cast<double>(z[i]) - m);
 }
 
 // r -= sc[i0] scale, r32 = float(r), and the partial sums of squares and of the
@@ -592,6 +668,19 @@ hipError_t launch_dot_noalloc(int device, bool fp32, int64_t n, const void* x, c
   // needs clearing between calls; its block count must fit the scratch
   if (red_grid(n) > kNoallocPartials) return hipErrorInvalidValue;
   return launch_dot(fp32, n, x, y, static_cast<double*>(p), dst, s);
+}
+
+hipError_t launch_sq2(bool fp32, int64_t n, const void* x, const void* y, double* part, double* sc, int dx, int dy,
+                      hipStream_t s) {
+  const int g = red_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_sq2<float>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const float*>(x),
+                       static_cast<const float*>(y), part);
+  else
+    hipLaunchKernelGGL(k_sq2<double>, dim3(g), dim3(kBlock), 0, s, n, static_cast<const double*>(x),
+                       static_cast<const double*>(y), part);
+  hipLaunchKernelGGL(k_finish_multi, dim3(2), dim3(kBlock), 0, s, part, g, sc, dx, dy, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_dot2(bool fp32, int64_t n, const void* x, const void* y, const void* z, double* part, double* sc,

@@ -56,6 +56,48 @@ def test_net_forward_backward_parity(q, n):
     assert err_in <= 1e-3
 
 
+@pytest.mark.parametrize("n", [64, 256])
+def test_net_forward_sampled_at_production_lattices(n):
+    """The forward kernels at the lattices the solves and the bench run them on (128^3 voxels:
+    the depth-2 level of the headline problem; 512^3: its finest level, where the bench times one
+    application), in the same launch configuration, on 96 sampled voxels: a voxel's output
+    depends on the 7^3 input neighbourhood around it only, so the oracle's forward pass on that
+    7^3 patch (its periodic wrap never reaches the centre's dependencies) gives the exact
+    reference value at the patch centre."""
+    torch = torch_cuda()
+    from oracle import learned
+    ctx = _ctx(2, n)
+    N = 2 * n
+    assert ctx.lattice(ctx.levels - 1) == N
+    w = _weights(11)
+    ctx.net_set_weights(0, w)
+    g = torch.Generator(device="cuda").manual_seed(12)
+    xd = torch.randn(N ** 3, device="cuda", dtype=torch.float32, generator=g)
+    yd = torch.empty_like(xd)
+    cache = ctx.net_cache(0)
+    print(f"[net sampled] N={N}", flush=True)
+    ctx.net_forward(0, xd, yd, cache)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(13)
+    # samples on brick edges and corners as well as inside (bricks are 16 x 8 x 4 and 16 x 8 x 8)
+    pts = [(0, 0, 0), (N - 1, N - 1, N - 1), (15, 7, 3), (16, 8, 4), (N - 1, 0, 7)]
+    pts += [tuple(int(v) for v in rng.integers(0, N, 3)) for _ in range(91)]
+    ys, refs = [], []
+    ar = np.arange(-3, 4)
+    for (i, j, k) in pts:
+        iz, iy, ix = (k + ar) % N, (j + ar) % N, (i + ar) % N
+        idx = (iz[:, None, None] * N + iy[None, :, None]) * N + ix[None, None, :]
+        patch = to_host(xd[torch.from_numpy(idx.ravel()).cuda()]).reshape(7, 7, 7)
+        y_ref, _ = learned.forward(w, patch)
+        refs.append(y_ref[3, 3, 3])
+        ys.append(float(yd[(k * N + j) * N + i]))
+    err = rel_l2(np.array(ys), np.array(refs))
+    print(f"[net sampled] N={N}: rel l2 over {len(pts)} voxels {err:.2e}", flush=True)
+    assert err <= 1e-2
+    del cache, xd, yd
+    ctx.close()
+
+
 def test_net_correction_parity_and_jacobi_special_case():
     torch = torch_cuda()
     from oracle import learned, operator as op
