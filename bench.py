@@ -35,25 +35,29 @@ def log(*a):
 
 
 def apply_rate(ctx, prec, reps=20):
-    """Average duration of the finest-level apply kernel, from the library's own
-    HIP events around each launch (context built with timing=1)."""
+    """Average duration of the finest-level apply kernel: `reps` back-to-back launches between
+    two HIP events recorded on the context's stream (torch's current stream, which the context
+    was built on), so no event sits between two launches."""
     import torch
-    from paper_1408_6497_amd import GMG_FP32, Context
+    from paper_1408_6497_amd import GMG_FP32
     n = ctx.num_dofs()
     dt = torch.float32 if prec == GMG_FP32 else torch.float64
     g = torch.Generator(device="cuda").manual_seed(1)
     x = torch.randn(n, device="cuda", dtype=dt, generator=g)
     y = torch.empty_like(x)
+    assert ctx.stream == torch.cuda.current_stream()
     for _ in range(3):
         ctx.apply(-1, x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ctx.timing_reset()
+    e0.record()
     for _ in range(reps):
         ctx.apply(-1, x, y)
-    cnt, secs = ctx.timing(-1, Context.KIND_APPLY, prec)
-    sec = secs / cnt
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
     bytes_per = 2 * n * x.element_size()
-    return {"dofs": n, "launches": cnt, "sec": sec, "gdofs": n / sec * 1e-9, "gbs": bytes_per / sec * 1e-9,
+    return {"dofs": n, "launches": reps, "sec": sec, "gdofs": n / sec * 1e-9, "gbs": bytes_per / sec * 1e-9,
             "hbm_frac": bytes_per / sec * 1e-9 / HBM_PEAK_GBS}
 
 
@@ -91,7 +95,7 @@ def traffic_record():
     FETCH_SIZE / WRITE_SIZE summary; None if the kernel source changed since the
     counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_apply_col_f32_q2_256cubed_traffic.md")
+    path = os.path.join(ROOT, "profiles", "k_apply_col_f32_q2_c4_learned_traffic.md")
     src = os.path.join(ROOT, "paper_1408_6497_amd", "csrc", "gmg_apply.hip")
     try:
         rec = None
@@ -415,7 +419,7 @@ def octree_workload(steps=5):
         out["dofs"] = ctx.num_dofs()
         out["levels"] = ctx.levels
         ctx.close()
-    ctxt = Context(2, 0, leaves=leaves, seed=0, timing=1)
+    ctxt = Context(2, 0, leaves=leaves, seed=0)
     for prec in (GMG_FP32, GMG_FP64):
         r = apply_rate(ctxt, prec)
         out["apply_" + ("fp32" if prec == GMG_FP32 else "fp64")] = {"us": r["sec"] * 1e6, "gdofs": r["gdofs"]}
@@ -491,6 +495,75 @@ def fft_workload(n=256, steps=5, q=1):
     return out
 
 
+NET_FLOPS_PER_VOXEL = 2 * (432 + 6912 + 432)  # multiply-adds of layers 1, 2 and 3 per voxel, x 2
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+
+
+def net_rate(n=256, reps=10):
+    """One learned correction (the FP32 residual scaled by D^-1 and its RMS, the 3-layer BF16 net,
+    u += s y) on the finest level of Q2 on n^3 elements ((2n)^3-voxel lattice), the shipped
+    depth-0 net: `reps` back-to-back corrections between two HIP events on the context's stream."""
+    import torch
+    from paper_1408_6497_amd import Context
+    from paper_1408_6497_amd import train as T
+    ctx = Context(2, n, 0, seed=0, lambda_override=1.0)
+    ctx.net_set_weights(0, T.load(os.path.join(ROOT, "paper_1408_6497_amd", "weights", "q2_depth0.gmgw"))["w"])
+    top = ctx.levels - 1
+    nv = ctx.num_dofs(top)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    r = torch.randn(nv, device="cuda", dtype=torch.float32, generator=g)
+    e = torch.empty_like(r)
+    assert ctx.stream == torch.cuda.current_stream()
+    for _ in range(2):
+        ctx.net_correction(top, r, e)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.net_correction(top, r, e)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    ctx.close()
+    del r, e
+    torch.cuda.empty_cache()
+    tf = NET_FLOPS_PER_VOXEL * nv / sec * 1e-12
+    return {"lattice": 2 * n, "voxels": nv, "us": sec * 1e6, "tflops": tf, "frac_bf16_peak": tf / BF16_PEAK_TFLOPS}
+
+
+def apply512_probe(reps=5):
+    """For rocprofv3 counter runs: a 256 MiB device copy three times (the counters' calibration),
+    then `reps` applies, restrictions onto the next level and prolongations from it, FP32 and FP64,
+    of Q1 on 512^3 elements and Q2 on 256^3 elements (512^3 DoFs)."""
+    import torch
+    from paper_1408_6497_amd import Context
+    a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    del a, b
+    out = {}
+    for q, n in ((1, 512), (2, 256)):
+        ctx = Context(q, n, 0, seed=0, lambda_override=1.0)
+        for dt in (torch.float32, torch.float64):
+            g = torch.Generator(device="cuda").manual_seed(3)
+            x = torch.randn(ctx.num_dofs(), device="cuda", dtype=dt, generator=g)
+            y = torch.empty_like(x)
+            xc = torch.randn(ctx.num_dofs(ctx.levels - 2), device="cuda", dtype=dt, generator=g)
+            for _ in range(reps):
+                ctx.apply(-1, x, y)
+            for _ in range(reps):
+                ctx.restrict(-1, x, xc)
+            for _ in range(reps):
+                ctx.prolong(-1, xc, y)
+            torch.cuda.synchronize()
+            out[f"q{q}_{str(dt).split('.')[-1]}"] = {"dofs": ctx.num_dofs(), "coarse_dofs": ctx.num_dofs(ctx.levels - 2)}
+            del x, y, xc
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,8 +573,13 @@ def main():
     ap.add_argument("--no-apply-bench", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (Q2/Q4 on 256^3 DoFs, octree, sharp layer, C1, FFT methods)")
-    ap.add_argument("--profile-workload", choices=("learned", "q4", "octree", "c2", "spectral"), default=None,
-                    help="for profilers: run only this workload and print its JSON (no timed bench step)")
+    ap.add_argument("--profile-workload", choices=("learned", "q4", "octree", "c2", "spectral", "c4roofline",
+                                                   "apply512", "net512"), default=None,
+                    help="for profilers: run only this workload and print its JSON (no timed bench step); "
+                         "c4roofline is the bench's own per-launch measurement of the learned solve, apply512 "
+                         "a 256 MiB copy (counter calibration) then five Q1 and Q2 applies, restrictions and "
+                         "prolongations of each precision on 512^3 DoFs, net512 five learned corrections on the 512^3 and "
+                         "256^3 lattices")
     ap.add_argument("--profile-n", type=int, default=256,
                     help="elements per direction of the learned workload under --profile-workload")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -526,6 +604,14 @@ def main():
             res = c2_workload(3, 1)
         elif args.profile_workload == "spectral":
             res = spectral_workload(sizes=(512,), steps=3)
+        elif args.profile_workload == "c4roofline":
+            launches, sec, algo_bytes, per_level, learned_apps, info_t = c4_roofline()
+            res = {"launches": launches, "avg_launch_us": sec / max(launches, 1) * 1e6,
+                   "achieved_gbs": algo_bytes / sec * 1e-9, "per_level": per_level}
+        elif args.profile_workload == "apply512":
+            res = apply512_probe()
+        elif args.profile_workload == "net512":
+            res = {"net_512": net_rate(256, reps=5), "net_256": net_rate(128, reps=5)}
         else:
             res = octree_workload()
         print(json.dumps(res), flush=True)
@@ -561,7 +647,7 @@ def main():
     if not args.no_apply_bench:
         # 512^3 DoFs for every order (Q1 on 512^3, Q2 on 256^3, Q4 on 128^3 elements)
         for qq, nn in ((2, 256), (1, 512), (4, 128)):
-            big = Context(qq, nn, 0, seed=0, timing=1, lambda_override=1.0)
+            big = Context(qq, nn, 0, seed=0, lambda_override=1.0)
             apply[f"q{qq}_512cubed_fp32"] = apply_rate(big, GMG_FP32)
             apply[f"q{qq}_512cubed_fp64"] = apply_rate(big, GMG_FP64)
             big.close()
@@ -571,6 +657,8 @@ def main():
 
     extra = {}
     if not args.no_extra:
+        extra["learned_net"] = {"per_application_512cubed": net_rate(256), "per_application_256cubed": net_rate(128),
+                                "flops_per_voxel": NET_FLOPS_PER_VOXEL, "peak_tflops": BF16_PEAK_TFLOPS}
         extra["c2_gaussians"] = c2_workload(args.steps, 1)
         extra["q4_sharp"] = q4_workload()
         extra["octree"] = octree_workload()
