@@ -14,10 +14,11 @@
 //     wavefront reads 64 q consecutive values per row) and RY rows of the 4
 //     rows 4 ty .. 4 ty + 3 of the tile.  RY = 4 (one workgroup per tile),
 //     except FP64 q = 4 and the FP64 q = 2 smoother steps, whose accumulators
-//     do not fit the register file four rows deep: there RY = 2 and two
-//     workgroups share a tile, one taking rows 0, 1 and the other rows 2, 3 of
-//     each group of four (the row class is uniform over the workgroup, so it
-//     stays compile-time);
+//     do not fit the register file four rows deep, and the FP32 q = 2 residuals
+//     and smoother steps, which need the occupancy of the smaller register
+//     count: there RY = 2 and two workgroups share a tile, one taking rows 0, 1
+//     and the other rows 2, 3 of each group of four (the row class is uniform
+//     over the workgroup, so it stays compile-time);
 //   * each thread loads its own column strip of RY + 2q rows (the y halo wraps
 //     periodically) straight into registers and does the y pass there
 //     (P = My x, S = Ky x); only P and S go through LDS, double-buffered, for
@@ -27,6 +28,8 @@
 //     q+1 accumulators per point (element form), so only the element layer
 //     below the chunk is recomputed;
 //   * the next plane's loads are issued before the current plane is computed;
+//   * the smoother step and the apply with its dot keep the centre rows of the
+//     planes of the current element layer for the epilogue's x;
 //   * node classes (i mod q) are compile-time in y and z and per thread in x,
 //     so structurally zero taps are never issued;
 //   * blocks are remapped so each XCD (blockIdx mod 8) sweeps a contiguous
@@ -103,17 +106,17 @@ __device__ __forceinline__ void store_nt(T* p, const VecQ<T, Q>& v) {
   }
 }
 
-// Fused epilogue on one q-wide output vector.
+// Fused epilogue on one q-wide output vector.  xc: the input values at idx when the caller
+// still holds them in registers, else null and they are read again from memory.
 template <typename T, int Q, int EPI>
 __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, const int cy, const int cz,
                                      const T (&ax)[Q], const T* __restrict__ x, T* out, const T* bvec,
-                                     const T* xp, const T c1, const T c2, T* x1o, double (&dacc)[2]) {
+                                     const T* xp, const T c1, const T c2, T* x1o, double (&dacc)[2],
+                                     const VecQ<T, Q>* xc = nullptr) {
   using V = VecQ<T, Q>;
   V res;
   if constexpr (EPI == kEpiDot) {
-    // x . A x and sum(A x) of this thread's outputs; x was loaded a few planes ago
-    // and is read again from the cache
-    const V xv = *reinterpret_cast<const V*>(x + idx);
+    const V xv = xc ? *xc : *reinterpret_cast<const V*>(x + idx);
 #pragma unroll
     for (int c = 0; c < Q; ++c) {
       res.v[c] = ax[c];
@@ -155,7 +158,7 @@ __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, con
     for (int c = 0; c < Q; ++c) res.v[c] = bv.v[c] - ax[c];
   } else {
     const V bv = *reinterpret_cast<const V*>(bvec + idx);
-    const V xv = *reinterpret_cast<const V*>(x + idx);
+    const V xv = xc ? *xc : *reinterpret_cast<const V*>(x + idx);
     V pv;
     if (c1 != T(0)) {
       if (xp != nullptr) {
@@ -186,10 +189,18 @@ constexpr int col_bound() {
 // steps (whose epilogue holds three more vectors) and reducing epilogues take two,
 // or their element-layer accumulators would spill; the rest take four (measured on
 // 256^3 DoFs: FP64 q = 2 smoother step 140 -> 117 us with two rows, the apply with
-// its two sums 70 -> 49 us, the plain FP64 apply slower with two).
+// its two sums 70 -> 49 us, the plain FP64 apply slower with two).  FP32 q = 2
+// residuals and smoother steps take two as well: 110 instead of 174-190 VGPRs, four
+// wavefronts per SIMD instead of two, which their extra input streams need to keep
+// memory busy (512^3 DoFs: smoother step 550 -> 444 us, residual 434 -> 371 us; the
+// plain apply is faster with four, 243 against 274 us).
 template <typename T, int Q, int EPI>
 constexpr int col_rows() {
-  if (sizeof(T) != 8) return 4;
+  if (sizeof(T) != 8)
+    return (Q == 2 && (EPI == static_cast<int>(Epi::Residual) || EPI == static_cast<int>(Epi::Cheb) ||
+                       EPI == static_cast<int>(Epi::ChebZero)))
+               ? 2
+               : 4;
   if (Q == 4) return 2;
   if (Q == 2 && (EPI == static_cast<int>(Epi::Cheb) || EPI == static_cast<int>(Epi::ChebZero) ||
                  EPI == static_cast<int>(Epi::ApplyDot) || EPI == static_cast<int>(Epi::ResidualSums)))
@@ -244,6 +255,17 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
   const int txr = (tx + 1) & (NX - 1);
   T g[RY][Q], h[RY][Q];
   int parity = 0;
+  // epilogues that need x at the output point keep the RY centre rows of the planes of the
+  // current element layer (slot b: plane E q + b) instead of reading them again from memory
+  // (512^3 DoFs, FP32 q = 2 smoother step: 444 -> 421 us)
+  constexpr bool kKeep = Q <= 2 && (EPI == static_cast<int>(Epi::Cheb) || EPI == kEpiDot);
+  V xcen[kKeep ? Q + 1 : 1][RY];
+  auto keep = [&](const V (&xv)[NR], int slot) {
+    if constexpr (kKeep) {
+#pragma unroll
+      for (int i = 0; i < RY; ++i) xcen[slot][i] = xv[Q + i];
+    }
+  };
 
   // y pass in registers: P = My x and S = Ky x of the RY output rows into LDS
   auto ypass = [&](const V (&xv)[NR], T* ps, T* ss) {
@@ -316,7 +338,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     parity ^= 1;
   };
 
-  auto compute_gh = [&](int p, bool prefetch) {
+  auto compute_gh = [&](int p, bool prefetch, int slot) {
     T* ps = lds + parity * buf_stride;
     T* ss = ps + TY * N;
     if constexpr (kLatePrefetch) {
@@ -324,6 +346,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
       // of registers instead of two (q = 4 would spill), the loads still overlap the
       // x and z passes
       ypass(pre, ps, ss);
+      keep(pre, slot);
       if (prefetch) load_plane(p + 1);
     } else {
       V xv[NR];
@@ -331,6 +354,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
       for (int r = 0; r < NR; ++r) xv[r] = pre[r];
       if (prefetch) load_plane(p + 1);
       ypass(xv, ps, ss);
+      keep(xv, slot);
     }
     __syncthreads();
     xpass();
@@ -379,7 +403,8 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
 #pragma unroll
             for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
             const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
-            emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc);
+            emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc,
+                            kKeep ? &allp[Q + a][Q + i] : nullptr);
           }
         }
       } else {
@@ -400,7 +425,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
   const int zlast = (E0 + TZ) * Q;
 
   load_plane((E0 - 1) * Q);
-  compute_gh((E0 - 1) * Q, true);
+  compute_gh((E0 - 1) * Q, true, 0);
 #pragma unroll
   for (int i = 0; i < RY; ++i)
 #pragma unroll
@@ -412,7 +437,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
 #pragma unroll
     for (int b = 1; b <= Q; ++b) {
       const int p = E * Q + b;
-      compute_gh(p, p < zlast);
+      compute_gh(p, p < zlast, b);
 #pragma unroll
       for (int i = 0; i < RY; ++i)
 #pragma unroll
@@ -431,9 +456,14 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
 #pragma unroll
           for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
           const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
-          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc);
+          emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc,
+                          kKeep ? &xcen[a][i] : nullptr);
         }
       }
+    }
+    if constexpr (kKeep) {  // plane (E + 1) q is slot 0 of the next layer
+#pragma unroll
+      for (int i = 0; i < RY; ++i) xcen[0][i] = xcen[Q][i];
     }
     // carry the shared vertex plane into the next element layer
 #pragma unroll

@@ -57,7 +57,9 @@ def test_apply_mass_diagonal_parity(q, n):
 def test_transfer_parity(q, n_c):
     torch = torch_cuda()
     from oracle import transfer
-    ctx = _ctx(q, 2 * n_c, 0)   # the finest transfer of the default hierarchy
+    # the finest transfer of the default hierarchy; a fine level small enough to be the
+    # coarsest on its own (q = 3, 2 elements: 216 DoFs) is given its two levels explicitly
+    ctx = _ctx(q, 2 * n_c, 2 if (2 * q * n_c) ** 3 <= 512 else 0)
     top = ctx.levels - 1
     assert ctx.num_dofs(top - 1) == (q * n_c) ** 3
     P = transfer.prolongation(q, n_c)
