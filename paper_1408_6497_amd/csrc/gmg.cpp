@@ -2067,10 +2067,10 @@ gmg_status ensure_net(gmg_ctx* c, int d) {
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.v), sizeof(float) * kNetWeights));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w1q), sizeof(float) * 432));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w3q), sizeof(float) * 432));
-  STCHK(dalloc(c, reinterpret_cast<void**>(&n.w3p), sizeof(uint32_t) * 216));
   STCHK(dalloc(c, &n.w2fl, 16 * 15 * 64));
   STCHK(dalloc(c, &n.w2bl, 16 * 15 * 64));
   STCHK(dalloc(c, &n.w1l, 16 * 2 * 64));
+  STCHK(dalloc(c, &n.w3l, 16 * 2 * 64));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w2f), sizeof(uint16_t) * 6912));
   STCHK(dalloc(c, reinterpret_cast<void**>(&n.w2b), sizeof(uint16_t) * 6912));
   return GMG_OK;

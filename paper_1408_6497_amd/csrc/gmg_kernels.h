@@ -357,12 +357,12 @@ struct NetDev {
   uint16_t* w2f = nullptr;
   uint16_t* w2b = nullptr;
   float* w3q = nullptr;
-  uint32_t* w3p = nullptr;  // W3 as BF16 channel pairs per tap [27][8]
   // lane-ordered MFMA operands (16 bytes per entry): layer 2 forward and backward-data (15 x 64
-  // each), layer 1 (2 x 64)
+  // each), layer 1 (2 x 64), layer 3 (2 x 64)
   void* w2fl = nullptr;
   void* w2bl = nullptr;
   void* w1l = nullptr;
+  void* w3l = nullptr;  // layer 3 (2 x 64)
 };
 constexpr int kNetWeights = 7776;
 // bytes of the forward cache (BF16 input + two 16-channel BF16 activations)

@@ -23,8 +23,9 @@
 //              B operand (16 voxels along x, 8 channels per lane) and the matching
 //              16 x 32 weight blocks as A (registers), accumulating 16 output channels
 //              x 16 voxels; a2 to HBM (32 B per voxel), a1 only when training keeps it.
-//   k_net_l3t  layer 3 over 16x8x8 bricks from an LDS tile of a2, four voxels per
-//              thread, with the output update u += s y fused.
+//   k_net_l3m  layer 3 over the same bricks: per row of the brick plus a halo the nine
+//              (dz, dy) partial sums over dx and channels on the MFMA (fixed A), then
+//              nine LDS reads per output, with the output update u += s y fused.
 // The backward-data pass of layer 2 (k_net_l2bwd) runs the same MFMA loop with the
 // flipped, transposed weights and the ReLU mask of the forward pass.
 #include <algorithm>
@@ -162,6 +163,20 @@ __device__ __forceinline__ floatx4 mfma32(const u32x4 a, const u32x4 b, const fl
                                                  0, 0);
 }
 
+// Brick of this block.  Blocks go to the XCDs round-robin (blockIdx mod 8), so block b is taken
+// as the (b / 8)-th brick of XCD b mod 8, and each XCD owns a contiguous range of bricks in an
+// order with z fastest, then x, then y: the bricks a XCD has in flight at once are mostly z
+// neighbours and share their halo planes in that XCD's L2.  The brick count (N / 16)(N / 8)(N / 4)
+// is a multiple of 8 for N >= 16.
+__device__ __forceinline__ void brick_of(int N, int& x0, int& y0, int& z0) {
+  const int nbx = N / kBX, nbz = N / kBZ;
+  const int per_xcd = (nbx * (N / kBY) * nbz) >> 3;
+  const int l = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  z0 = (l % nbz) * kBZ;
+  x0 = ((l / nbz) % nbx) * kBX;
+  y0 = (l / (nbz * nbx)) * kBY;
+}
+
 // (dz, dx) offset of slot f (0, 1) of pair p; the empty partner of the last pair repeats
 // offset 8 (its weights are zero)
 __device__ __forceinline__ int pair_combo(int p, int f) { return min(2 * p + f, 8); }
@@ -254,11 +269,8 @@ __global__ void __launch_bounds__(kBlk) k_net_l2bwd(const uint16_t* __restrict__
                                                     const uint16_t* __restrict__ mask, const int N,
                                                     uint16_t* __restrict__ out) {
   __shared__ u32x4 tile[2 * kHalf];
-  const int nbx = N / kBX, nby = N / kBY;
-  const int b = blockIdx.x;
-  const int x0 = (b % nbx) * kBX;
-  const int y0 = ((b / nbx) % nby) * kBY;
-  const int z0 = (b / (nbx * nby)) * kBZ;
+  int x0, y0, z0;
+  brick_of(N, x0, y0, z0);
   const int m = N - 1;
   const u32x4* in4 = reinterpret_cast<const u32x4*>(in);
   fill_halo_tile(reinterpret_cast<const u32x4*>(in), N, x0, y0, z0, tile);
@@ -303,11 +315,8 @@ __global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ x
   __shared__ u32x4 tile[2 * kHalf];
   static_assert(kXZ * kXY * kXX * sizeof(uint16_t) <= sizeof(tile), "the plain input tile fits in the half tiles");
   uint16_t* xt = reinterpret_cast<uint16_t*>(tile);  // plain input tile, dead once the triples are built
-  const int nbx = N / kBX, nby = N / kBY;
-  const int b = blockIdx.x;
-  const int x0 = (b % nbx) * kBX;
-  const int y0 = ((b / nbx) % nby) * kBY;
-  const int z0 = (b / (nbx * nby)) * kBZ;
+  int x0, y0, z0;
+  brick_of(N, x0, y0, z0);
   const int m = N - 1;
   {  // plane by plane: thread t < 240 takes column t % 20 of row t / 20 in every plane, so the row
      // and column part of the global address is formed once; all loads before the first store
@@ -388,117 +397,95 @@ __global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ x
   const int tz = wave;
   floatx4 acc[kBY];
   layer2_wave(tile, wa, tz, col, g, acc);
+  u32x2* dst = reinterpret_cast<u32x2*>(a2_out) + vox(x0 + col, y0, z0 + tz, N) * 4 + g;
 #pragma unroll
-  for (int ty = 0; ty < kBY; ++ty) {
-    const size_t v = vox(x0 + col, y0 + ty, z0 + tz, N);
-    reinterpret_cast<u32x2*>(a2_out)[v * 4 + g] =
+  for (int ty = 0; ty < kBY; ++ty)
+    dst[static_cast<size_t>(ty) * N * 4] =
         u32x2{pack2_relu(acc[ty][0], acc[ty][1]), pack2_relu(acc[ty][2], acc[ty][3])};
-  }
 }
 
-// ---------------------------------------------------------------------------- layer 3, LDS-tiled
-// y = W3 * a2 over bricks of 16x8x8 voxels: a2 of the brick plus a one-voxel halo in LDS (rows of
-// 18 voxels x 32 bytes, padded to 592 bytes), each thread four neighbouring voxels along x, so
-// the 6 x-columns they need are read once for all four.  Channel pairs go through
-// v_dot2_f32_bf16 (two BF16 products added to the FP32 accumulator) straight from the packed
-// activations, with the packed weights read through the scalar cache; per voxel the sum runs
-// over taps t = 0..26, then channel pairs.  Lanes are ordered row-fastest: the 8 rows of one
-// 16-byte read phase fall on disjoint banks with the 592-byte row stride.
-constexpr int k3X = 16, k3Y = 8, k3Z = 8;
-constexpr int k3HX = k3X + 2, k3HY = k3Y + 2, k3HZ = k3Z + 2;
-constexpr int k3Row = k3HX * 2 + 1;  // 16-byte entries per padded tile row (37 = 592 bytes)
+// ---------------------------------------------------------------------------- layer 3 (16 -> 1, MFMA)
+// y = W3 * a2 over the 16x8x4 bricks of k_net_l12, in two stages:
+//   1. for every row (hy, hz) of the brick plus a one-voxel halo (60 rows of 16 voxels) the
+//      9 partial sums P[(dz, dy)](v) = sum_dx sum_c W3[(dz, dy, dx)][c] a2[v + dx][c] come out of
+//      two v_mfma_f32_16x16x32_bf16 with a fixed A: row m = 4 (dz + 1) + (dy + 1) of A holds the
+//      weights of (dz, dy) (rows 3, 7, 11 and 12-15 zero), K = (two dx offsets, 16 channels)
+//      and (dx = +1, zero); the B operands are the a2 row at dx = -1, 0 and +1 from the half
+//      tiles, as in layer 2;
+//   2. after a barrier the partial sums go to LDS (over the a2 tile, 12 bytes per (row, dz,
+//      voxel)) and y(v) = sum over (dz, dy) of P[(dz, dy)] at row (y + dy, z + dz): nine LDS
+//      reads per output, summed in a fixed order.
+// Per 512 outputs: 120 MFMAs and 34.6 KB of LDS for the tile (four blocks per CU), where the
+// dot-product form needed 216 v_dot2 per output.
+constexpr int kL3Rows = kHY * kHZ;                 // 60 input rows
+constexpr int kL3RowsPerWave = kL3Rows / (kBlk / 64);  // 15
+static_assert(kL3Rows % (kBlk / 64) == 0, "every wavefront takes the same number of rows");
+static_assert(kL3Rows * 3 * kBX * 3 * 4 <= 2 * kHalf * 16, "the partial sums fit over the a2 tile");
 
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
-  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
-}
-
-__global__ void __launch_bounds__(kBlk) k_net_l3t(const uint16_t* __restrict__ a2, const uint32_t* __restrict__ w3p,
+__global__ void __launch_bounds__(kBlk) k_net_l3m(const uint16_t* __restrict__ a2, const u32x4* __restrict__ w3l,
                                                   const int N, const int mode, const double* __restrict__ ssum,
                                                   float* __restrict__ y) {
-  __shared__ u32x4 tile[k3HZ * k3HY * k3Row];
-  const int nbx = N / k3X, nby = N / k3Y;
-  const int b = blockIdx.x;
-  const int x0 = (b % nbx) * k3X;
-  const int y0 = ((b / nbx) % nby) * k3Y;
-  const int z0 = (b / (nbx * nby)) * k3Z;
-  const int m = N - 1;
-  const u32x4* in4 = reinterpret_cast<const u32x4*>(a2);
-  {  // plane by plane (360 half-voxel entries each): thread t takes entries t and t + 256 of every
-     // plane, the row and column part of each address formed once, all loads before the stores
-    constexpr int kPlane = k3HX * k3HY * 2;
-    int src[2], dst[2];
-    bool use[2];
+  __shared__ u32x4 tile[2 * kHalf];
+  int x0, y0, z0;
+  brick_of(N, x0, y0, z0);
+  fill_halo_tile(reinterpret_cast<const u32x4*>(a2), N, x0, y0, z0, tile);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15, g = lane >> 4;
+  const u32x4 wA1 = w3l[lane], wA2 = w3l[64 + lane];
+  __syncthreads();
+  // stage 1: rows j = wave + 4 k of the 60; slot g >> 1 of the first B is dx = -1 or 0, both
+  // slots of the second dx = +1 (its second slot meets zero weights)
+  const u32x4* t1 = tile + (g & 1) * kHalf + col + (g >> 1);
+  const u32x4* t2 = tile + (g & 1) * kHalf + col + 2;
+  floatx4 p[kL3RowsPerWave];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int e = threadIdx.x + k * kBlk;
-      use[k] = e < kPlane;
-      const int ee = use[k] ? e : 0;
-      const int c = ee & 1, vx = ee >> 1;
-      const int hx = vx % k3HX, hy = vx / k3HX;
-      src[k] = ((((y0 - 1 + hy) & m) * N + ((x0 - 1 + hx) & m)) << 1) + c;
-      dst[k] = hy * k3Row + hx * 2 + c;
+  for (int k = 0; k < kL3RowsPerWave; ++k) {
+    const int j = wave + 4 * k;  // row hy + kHY hz of the halo'd brick
+    p[k] = mfma32(wA1, t1[j * kHX], floatx4{0.0f, 0.0f, 0.0f, 0.0f});
+    p[k] = mfma32(wA2, t2[j * kHX], p[k]);
+  }
+  __builtin_amdgcn_iglp_opt(0);
+  __syncthreads();
+  // lane (col, g < 3) holds P[(dz = g - 1, dy = -1, 0, 1)] of voxel col of its rows
+  float* pl = reinterpret_cast<float*>(tile);  // [row][dz][x][dy]
+  if (g < 3) {
+#pragma unroll
+    for (int k = 0; k < kL3RowsPerWave; ++k) {
+      const int j = wave + 4 * k;
+      float* d = pl + ((j * 3 + g) * kBX + col) * 3;
+      d[0] = p[k][0];
+      d[1] = p[k][1];
+      d[2] = p[k][2];
     }
-    u32x4 v[k3HZ][2];
-#pragma unroll
-    for (int hz = 0; hz < k3HZ; ++hz) {
-      const size_t zoff = static_cast<size_t>((z0 - 1 + hz) & m) * N * N * 2;
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-        if (use[k]) v[hz][k] = in4[zoff + src[k]];
-    }
-#pragma unroll
-    for (int hz = 0; hz < k3HZ; ++hz)
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-        if (use[k]) tile[hz * k3HY * k3Row + dst[k]] = v[hz][k];
   }
   __syncthreads();
-  const int ty = threadIdx.x & 7;          // row fastest
-  const int xq = (threadIdx.x >> 3) & 3;   // voxel quad along x
-  const int tz = threadIdx.x >> 5;
-  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // stage 2: thread (x, ty, tz pair) sums its two outputs over (dz, dy)
+  const int x = threadIdx.x & 15, ty = (threadIdx.x >> 4) & 7, tz0 = 2 * (threadIdx.x >> 7);
+  float acc[2];
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
+  for (int o = 0; o < 2; ++o) {
+    const int tz = tz0 + o;
+    float s = 0.0f;
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-      const u32x4* row = tile + ((tz + dz) * k3HY + (ty + dy)) * k3Row + 8 * xq;
-      uint32_t a[6][kNC / 2];
+    for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const u32x4 u0 = row[2 * k], u1 = row[2 * k + 1];
-        a[k][0] = u0.x;
-        a[k][1] = u0.y;
-        a[k][2] = u0.z;
-        a[k][3] = u0.w;
-        a[k][4] = u1.x;
-        a[k][5] = u1.y;
-        a[k][6] = u1.z;
-        a[k][7] = u1.w;
+      for (int dy = 0; dy < 3; ++dy) {
+        const int j = (tz + dz) * kHY + (ty + dy);  // input row (ty + 1 + dy - 1, tz + 1 + dz - 1)
+        s += pl[((j * 3 + dz) * kBX + x) * 3 + dy];
       }
-      const int tb = dz * 9 + dy * 3;
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const uint32_t* wt = w3p + (tb + dx) * (kNC / 2);
-#pragma unroll
-        for (int c = 0; c < kNC / 2; ++c) {
-          const uint32_t w = wt[c];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[v] = dot2(a[v + dx][c], w, acc[v]);
-        }
-      }
-    }
-  float* dst = y + vox(x0 + 4 * xq, y0 + ty, z0 + tz, N);
-  if (mode == 0) {
-    *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-  } else {
+    acc[o] = s;
+  }
+  float sc = 1.0f;
+  if (mode != 0) {
     const double nn = static_cast<double>(N) * N * N;
-    const float sc = static_cast<float>(sqrt(*ssum / nn));
-    float4 o = *reinterpret_cast<const float4*>(dst);
-    o.x += sc * acc[0];
-    o.y += sc * acc[1];
-    o.z += sc * acc[2];
-    o.w += sc * acc[3];
-    *reinterpret_cast<float4*>(dst) = o;
+    sc = static_cast<float>(sqrt(*ssum / nn));
+  }
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    float* dst = y + vox(x0 + x, y0 + ty, z0 + tz0 + o, N);
+    if (mode == 0) *dst = acc[o];
+    else *dst += sc * acc[o];
   }
 }
 
@@ -682,13 +669,8 @@ __global__ void __launch_bounds__(kBlk) k_net_reduce(const float* __restrict__ p
 // (backward-data A operand).
 __global__ void __launch_bounds__(kBlk) k_net_pack(const float* __restrict__ w, float* __restrict__ w1q,
                                                    uint16_t* __restrict__ w2f, uint16_t* __restrict__ w2b,
-                                                   float* __restrict__ w3q, uint32_t* __restrict__ w3p) {
+                                                   float* __restrict__ w3q) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < kTaps * kNC / 2) {  // w3p[t][channel pair]: BF16 pairs of W3[2c][t], W3[2c + 1][t]
-    const int t = e / (kNC / 2), c = e % (kNC / 2);
-    w3p[e] = static_cast<uint32_t>(f2bf(w[432 + 6912 + (2 * c) * kTaps + t])) |
-             (static_cast<uint32_t>(f2bf(w[432 + 6912 + (2 * c + 1) * kTaps + t])) << 16);
-  }
   if (e < 432) {
     const int co = e / kTaps, t = e % kTaps;
     w1q[t * kNC + co] = bf2f(f2bf(w[e]));
@@ -714,8 +696,10 @@ __global__ void __launch_bounds__(kBlk) k_net_pack(const float* __restrict__ w, 
 //                for output channel l & 15, g = l >> 4; entry 64 + l: row 8 in group 0, else zero.
 __global__ void __launch_bounds__(kBlk) k_net_pack_lanes(const uint16_t* __restrict__ w2f,
                                                          const uint16_t* __restrict__ w2b,
-                                                         const float* __restrict__ w1q, u32x4* __restrict__ w2fl,
-                                                         u32x4* __restrict__ w2bl, u32x4* __restrict__ w1l) {
+                                                         const float* __restrict__ w1q,
+                                                         const float* __restrict__ w3q, u32x4* __restrict__ w2fl,
+                                                         u32x4* __restrict__ w2bl, u32x4* __restrict__ w1l,
+                                                         u32x4* __restrict__ w3l) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < kPairs * 3 * 64) {
     const int l = e % 64, pd = e / 64, p = pd / 3, dy = pd % 3;
@@ -739,6 +723,20 @@ __global__ void __launch_bounds__(kBlk) k_net_pack_lanes(const uint16_t* __restr
     } else {
       w1l[f] = g == 0 ? u32x4{pack2(wt(24), wt(25)), pack2(wt(26), 0.0f), 0u, 0u} : u32x4{0u, 0u, 0u, 0u};
     }
+  } else if (e < kPairs * 3 * 64 + 256) {
+    // layer 3 (k_net_l3m): entry l: row m = l & 15 = 4 (dz + 1) + (dy + 1), k group g = l >> 4,
+    // channels 8 (g & 1) .. +7 of dx = (g >> 1) - 1; entry 64 + l: dx = +1 in slot 0, zero in slot 1
+    const int f = e - kPairs * 3 * 64 - 128;
+    const int l = f % 64, m = l & 15, g = l >> 4, h = g & 1, slot = g >> 1;
+    const int dz = m / 4 - 1, dy = m % 4 - 1;
+    const int dx = f < 64 ? slot - 1 : (slot == 0 ? 1 : 2);
+    float w[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (dz <= 1 && dy <= 1 && dx <= 1) {
+      const int t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w[j] = w3q[t * kNC + 8 * h + j];
+    }
+    w3l[f] = u32x4{pack2(w[0], w[1]), pack2(w[2], w[3]), pack2(w[4], w[5]), pack2(w[6], w[7])};
   }
 }
 
@@ -804,11 +802,10 @@ int64_t net_partial_floats(int N) {
 }
 
 hipError_t launch_net_pack(const float* w, NetDev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_net_pack, dim3((7776 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, w, d.w1q, d.w2f, d.w2b, d.w3q,
-                     d.w3p);
-  hipLaunchKernelGGL(k_net_pack_lanes, dim3((kPairs * 3 * 64 + 128 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, d.w2f,
-                     d.w2b, d.w1q, reinterpret_cast<u32x4*>(d.w2fl), reinterpret_cast<u32x4*>(d.w2bl),
-                     reinterpret_cast<u32x4*>(d.w1l));
+  hipLaunchKernelGGL(k_net_pack, dim3((7776 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, w, d.w1q, d.w2f, d.w2b, d.w3q);
+  hipLaunchKernelGGL(k_net_pack_lanes, dim3((kPairs * 3 * 64 + 256 + kBlk - 1) / kBlk), dim3(kBlk), 0, s, d.w2f,
+                     d.w2b, d.w1q, d.w3q, reinterpret_cast<u32x4*>(d.w2fl), reinterpret_cast<u32x4*>(d.w2bl),
+                     reinterpret_cast<u32x4*>(d.w1l), reinterpret_cast<u32x4*>(d.w3l));
   return hipGetLastError();
 }
 
@@ -846,8 +843,8 @@ hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, con
   else
     hipLaunchKernelGGL(k_net_l12<false>, dim3(nb), dim3(kBlk), 0, s, xin, reinterpret_cast<const u32x4*>(d.w1l),
                        reinterpret_cast<const u32x4*>(d.w2fl), N, nullptr, a2);
-  const int nb3 = (N / k3X) * (N / k3Y) * (N / k3Z);
-  hipLaunchKernelGGL(k_net_l3t, dim3(nb3), dim3(kBlk), 0, s, a2, d.w3p, N, mode, ssum, y);
+  hipLaunchKernelGGL(k_net_l3m, dim3(nb), dim3(kBlk), 0, s, a2, reinterpret_cast<const u32x4*>(d.w3l), N, mode,
+                     ssum, y);
   return hipGetLastError();
 }
 
