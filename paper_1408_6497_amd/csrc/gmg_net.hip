@@ -23,9 +23,10 @@
 //              B operand (16 voxels along x, 8 channels per lane) and the matching
 //              16 x 32 weight blocks as A (registers), accumulating 16 output channels
 //              x 16 voxels; a2 to HBM (32 B per voxel), a1 only when training keeps it.
-//   k_net_l3m  layer 3 over the same bricks: per row of the brick plus a halo the nine
-//              (dz, dy) partial sums over dx and channels on the MFMA (fixed A), then
-//              nine LDS reads per output, with the output update u += s y fused.
+//   k_net_l3s  layer 3 streamed along z over 16x16 output columns (lattices of 128 nodes
+//              and more; k_net_l3m on the bricks below that): per row of each a2 plane the
+//              nine (dz, dy) partial sums over dx and channels on the MFMA (fixed A), then
+//              three rolling output planes, with u += s y fused.
 // The backward-data pass of layer 2 (k_net_l2bwd) runs the same MFMA loop with the
 // flipped, transposed weights and the ReLU mask of the forward pass.
 #include <algorithm>
@@ -405,7 +406,125 @@ __global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ x
 }
 
 // ---------------------------------------------------------------------------- layer 3 (16 -> 1, MFMA)
-// y = W3 * a2 over the 16x8x4 bricks of k_net_l12, in two stages:
+// y = W3 * a2, streamed along z: a block owns a 16x16 column of outputs and a segment of its
+// planes, and walks the input planes once (segment plus one plane each side):
+//   1. the plane of a2 with a one-voxel x and y halo (18x18 voxels) goes to LDS as two half
+//      tiles; for each of its 18 rows the nine partial sums P[(dz, dy)](v) = sum_dx sum_c
+//      W3[(dz, dy, dx)][c] a2[v + dx][c] come out of two v_mfma_f32_16x16x32_bf16 with a fixed
+//      A: row m = 4 (dz + 1) + (dy + 1) holds the weights of (dz, dy) (rows 3, 7, 11 and 12-15
+//      zero), K = (two dx offsets, 16 channels), then (dx = +1, zero); the B operands are the
+//      row at dx = -1, 0 and +1;
+//   2. the partial sums go to LDS (12 bytes per (row, dz, voxel)); thread (x, y) adds the three
+//      dy values of each dz to the output plane that dz reaches (z - dz): plane p feeds outputs
+//      p + 1, p and p - 1, kept in three rolling registers, and output p - 1 is complete and
+//      stored (y = sum or y += s sum) after plane p.
+// Each input plane is read once per column (a2 traffic 1.27x for the x and y halo, plus two planes
+// per segment), where bricks with a z halo read it 2.1x; the next plane's loads are in flight
+// while the current one is computed.
+constexpr int kSX = 16, kSY = 16;               // output cross-section of a column
+constexpr int kSHX = kSX + 2, kSHY = kSY + 2;   // with the halo
+constexpr int kSHalf = kSHX * kSHY + 8;         // half-tile stride in 16-byte entries
+constexpr int kSPlane = kSHX * kSHY * 2;        // 648 half-voxel entries per plane
+constexpr int kSLoads = (kSPlane + kBlk - 1) / kBlk;  // 3 per thread
+constexpr int kSRowsPerWave = (kSHY + 3) / 4;   // 5 (waves 2 and 3 take 4)
+static_assert(kSX * kSY == kBlk, "one output per thread and plane");
+
+__global__ void __launch_bounds__(kBlk) k_net_l3s(const uint16_t* __restrict__ a2, const u32x4* __restrict__ w3l,
+                                                  const int N, const int nseg, const int mode,
+                                                  const double* __restrict__ ssum, float* __restrict__ y) {
+  __shared__ u32x4 abuf[2 * kSHalf];
+  __shared__ float pbuf[kSHY * 3 * kSX * 3];  // [row][dz][x][dy]
+  const int ncx = N / kSX, ncy = N / kSY;
+  const int c = blockIdx.x % (ncx * ncy), seg = blockIdx.x / (ncx * ncy);
+  const int x0 = (c % ncx) * kSX, y0 = (c / ncx) * kSY;
+  const int L = N / nseg, zs = seg * L, ze = zs + L;
+  const int m = N - 1;
+  const u32x4* in4 = reinterpret_cast<const u32x4*>(a2);
+  // this thread's half-voxel entries of every plane: row/column part of the address, LDS slot
+  int src[kSLoads], dst[kSLoads];
+  bool use[kSLoads];
+#pragma unroll
+  for (int k = 0; k < kSLoads; ++k) {
+    const int e = threadIdx.x + k * kBlk;
+    use[k] = e < kSPlane;
+    const int ee = use[k] ? e : 0;
+    const int h = ee & 1, vx = ee >> 1;
+    const int hx = vx % kSHX, hy = vx / kSHX;
+    src[k] = ((((y0 - 1 + hy) & m) * N + ((x0 - 1 + hx) & m)) << 1) + h;
+    dst[k] = h * kSHalf + vx;
+  }
+  auto load_plane = [&](int p, u32x4 (&v)[kSLoads]) {
+    const size_t zoff = static_cast<size_t>(p & m) * N * N * 2;
+#pragma unroll
+    for (int k = 0; k < kSLoads; ++k)
+      if (use[k]) v[k] = in4[zoff + src[k]];
+  };
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15, g = lane >> 4;
+  const u32x4 wA1 = w3l[lane], wA2 = w3l[64 + lane];
+  const u32x4* t1 = abuf + (g & 1) * kSHalf + col + (g >> 1);
+  const u32x4* t2 = abuf + (g & 1) * kSHalf + col + 2;
+  const int ox = threadIdx.x & 15, oy = threadIdx.x >> 4;  // this thread's output column
+  float sc = 1.0f;
+  if (mode != 0) sc = static_cast<float>(sqrt(*ssum / (static_cast<double>(N) * N * N)));
+  float a_prev = 0.0f, a_cur = 0.0f, a_next = 0.0f;  // outputs p - 1, p, p + 1
+  u32x4 pre[kSLoads];
+  load_plane(zs - 1, pre);
+  for (int p = zs - 1; p <= ze; ++p) {
+#pragma unroll
+    for (int k = 0; k < kSLoads; ++k)
+      if (use[k]) abuf[dst[k]] = pre[k];
+    __syncthreads();
+    if (p < ze) load_plane(p + 1, pre);
+    floatx4 pr[kSRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kSRowsPerWave; ++k) {
+      const int hy = wave + 4 * k;
+      if (hy < kSHY) {
+        pr[k] = mfma32(wA1, t1[hy * kSHX], floatx4{0.0f, 0.0f, 0.0f, 0.0f});
+        pr[k] = mfma32(wA2, t2[hy * kSHX], pr[k]);
+      }
+    }
+    if (g < 3) {
+#pragma unroll
+      for (int k = 0; k < kSRowsPerWave; ++k) {
+        const int hy = wave + 4 * k;
+        if (hy < kSHY) {
+          float* d = pbuf + ((hy * 3 + g) * kSX + col) * 3;
+          d[0] = pr[k][0];
+          d[1] = pr[k][1];
+          d[2] = pr[k][2];
+        }
+      }
+    }
+    __syncthreads();
+    // dz index d reaches output p + 1 - d
+    float sd[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float t = 0.0f;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) t += pbuf[(((oy + dy) * 3 + d) * kSX + ox) * 3 + dy];
+      sd[d] = t;
+    }
+    a_next += sd[0];
+    a_cur += sd[1];
+    a_prev += sd[2];
+    const int o = p - 1;  // complete now
+    if (o >= zs && o < ze) {
+      float* dsty = y + vox(x0 + ox, y0 + oy, o, N);
+      if (mode == 0) *dsty = a_prev;
+      else *dsty += sc * a_prev;
+    }
+    a_prev = a_cur;
+    a_cur = a_next;
+    a_next = 0.0f;
+  }
+}
+
+// Layer 3 on the bricks of k_net_l12 (lattices below 128 nodes, where a z stream of a few planes
+// per column would be latency-bound), in two stages:
 //   1. for every row (hy, hz) of the brick plus a one-voxel halo (60 rows of 16 voxels) the
 //      9 partial sums P[(dz, dy)](v) = sum_dx sum_c W3[(dz, dy, dx)][c] a2[v + dx][c] come out of
 //      two v_mfma_f32_16x16x32_bf16 with a fixed A: row m = 4 (dz + 1) + (dy + 1) of A holds the
@@ -415,8 +534,7 @@ __global__ void __launch_bounds__(kBlk) k_net_l12(const uint16_t* __restrict__ x
 //   2. after a barrier the partial sums go to LDS (over the a2 tile, 12 bytes per (row, dz,
 //      voxel)) and y(v) = sum over (dz, dy) of P[(dz, dy)] at row (y + dy, z + dz): nine LDS
 //      reads per output, summed in a fixed order.
-// Per 512 outputs: 120 MFMAs and 34.6 KB of LDS for the tile (four blocks per CU), where the
-// dot-product form needed 216 v_dot2 per output.
+// Per 512 outputs: 120 MFMAs and 34.6 KB of LDS for the tile (four blocks per CU).
 constexpr int kL3Rows = kHY * kHZ;                 // 60 input rows
 constexpr int kL3RowsPerWave = kL3Rows / (kBlk / 64);  // 15
 static_assert(kL3Rows % (kBlk / 64) == 0, "every wavefront takes the same number of rows");
@@ -487,6 +605,14 @@ __global__ void __launch_bounds__(kBlk) k_net_l3m(const uint16_t* __restrict__ a
     if (mode == 0) *dst = acc[o];
     else *dst += sc * acc[o];
   }
+}
+
+// planes per segment of k_net_l3s: segments of at least 16 planes, enough blocks to fill the device
+inline int l3s_segments(int N) {
+  const int cols = (N / kSX) * (N / kSY);
+  int nseg = 1;
+  while (cols * nseg < 4096 && N / (2 * nseg) >= 16) nseg *= 2;
+  return nseg;
 }
 
 // 16 BF16 channels of one voxel (32 bytes) to FP32
@@ -724,7 +850,7 @@ __global__ void __launch_bounds__(kBlk) k_net_pack_lanes(const uint16_t* __restr
       w1l[f] = g == 0 ? u32x4{pack2(wt(24), wt(25)), pack2(wt(26), 0.0f), 0u, 0u} : u32x4{0u, 0u, 0u, 0u};
     }
   } else if (e < kPairs * 3 * 64 + 256) {
-    // layer 3 (k_net_l3m): entry l: row m = l & 15 = 4 (dz + 1) + (dy + 1), k group g = l >> 4,
+    // layer 3 (k_net_l3s, k_net_l3m): entry l: row m = l & 15 = 4 (dz + 1) + (dy + 1), k group g = l >> 4,
     // channels 8 (g & 1) .. +7 of dx = (g >> 1) - 1; entry 64 + l: dx = +1 in slot 0, zero in slot 1
     const int f = e - kPairs * 3 * 64 - 128;
     const int l = f % 64, m = l & 15, g = l >> 4, h = g & 1, slot = g >> 1;
@@ -843,8 +969,14 @@ hipError_t launch_net_forward(const NetDev& d, int N, void* cache, int mode, con
   else
     hipLaunchKernelGGL(k_net_l12<false>, dim3(nb), dim3(kBlk), 0, s, xin, reinterpret_cast<const u32x4*>(d.w1l),
                        reinterpret_cast<const u32x4*>(d.w2fl), N, nullptr, a2);
-  hipLaunchKernelGGL(k_net_l3m, dim3(nb), dim3(kBlk), 0, s, a2, reinterpret_cast<const u32x4*>(d.w3l), N, mode,
-                     ssum, y);
+  if (N >= 128) {  // streamed along z (at 512^3 voxels 1.33 against 1.71 ms)
+    const int nseg = l3s_segments(N);
+    hipLaunchKernelGGL(k_net_l3s, dim3((N / kSX) * (N / kSY) * nseg), dim3(kBlk), 0, s, a2,
+                       reinterpret_cast<const u32x4*>(d.w3l), N, nseg, mode, ssum, y);
+  } else {  // one pass over bricks (on 16^3 to 64^3 voxels 35-49 against 52-65 us a correction)
+    hipLaunchKernelGGL(k_net_l3m, dim3(nb), dim3(kBlk), 0, s, a2, reinterpret_cast<const u32x4*>(d.w3l), N, mode,
+                       ssum, y);
+  }
   return hipGetLastError();
 }
 
