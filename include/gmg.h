@@ -137,6 +137,10 @@ typedef struct {
   int32_t no_fused_transfer; /* != 0: restrict and prolong on uniform levels with three
                                one-axis passes instead of the one-pass kernels (the same
                                bits; testing aid)                                        */
+  int32_t no_fused_test_norms; /* != 0: the test of a learned cycle stores the residual and
+                               reduces the two norms in a pass of its own instead of in the
+                               residual's epilogue (the same norms up to summation order;
+                               testing aid)                                              */
 } gmg_options;
 
 typedef struct {

@@ -351,8 +351,8 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.epi = epi;
   a.x1 = x1;
   a.s0 = s0;
-  if (epi == Epi::ApplyDot || epi == Epi::ResidualSums) {
-    if (L.oct || L.gen || pi != 0 || mass || d0 < 0 || d1 < 0)
+  if (epi == Epi::ApplyDot || epi == Epi::ResidualSums || epi == Epi::ResidualNorms) {
+    if (L.oct || L.gen || (pi != 0 && epi != Epi::ResidualNorms) || mass || d0 < 0 || d1 < 0 || L.N <= 32)
       return fail(c, GMG_E_ARG, "fused apply and dot unsupported here");
     a.part = c->part;
     a.part_cap = c->part_cap;
@@ -397,7 +397,7 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
     HIPCHK(c, hipEventRecord(eb, c->stream));
     int kind = K_APPLY;
     if (mass) kind = K_MASS;
-    else if (epi == Epi::Residual) kind = K_RESIDUAL;
+    else if (epi == Epi::Residual || epi == Epi::ResidualNorms) kind = K_RESIDUAL;
     else if (epi == Epi::Cheb) kind = (xp != nullptr && c1 != 0.0) ? K_SMOOTH : K_SMOOTH0;
     else if (epi == Epi::ChebZero) kind = K_SMOOTHZ;
     c->pending.push_back({ea, eb, l, kind, pi});
@@ -740,8 +740,10 @@ gmg_status run_vcycle(gmg_ctx* c, int pi, int vpi, const void* r, void* z) {
 
 // One FP32 cycle under test: z32 = V r32 (learned or plain), then
 // ||r32 - A z32||^2 -> S_LRES and ||r32||^2 -> S_LRR.  r is the Krylov residual
-// (FP64 when pi = 0: cast down first).
-gmg_status test_cycle(gmg_ctx* c, int pi, const void* r, bool plain) {
+// (FP64 when pi = 0: cast down first).  With keep_residual the residual r32 - A z32
+// is left in the finest level's xp[1]; otherwise, on uniform levels of more than 32
+// nodes, both norms come out of the residual's epilogue and it is not stored.
+gmg_status test_cycle(gmg_ctx* c, int pi, const void* r, bool plain, bool keep_residual = false) {
   const int l = c->L - 1;
   const int64_t n = c->lv[l].size;
   void* r32 = c->kr[1];
@@ -750,7 +752,13 @@ gmg_status test_cycle(gmg_ctx* c, int pi, const void* r, bool plain) {
   const gmg_status st = vcycle_level(c, l, 1, r32, c->kz[1]);
   c->suppress_learned = false;
   STCHK(st);
-  void* t = c->lv[l].xp[1];
+  const Level& L = c->lv[l];
+  if (!keep_residual && !c->opt.no_fused_test_norms && !L.oct && !L.gen && L.N > 32) {
+    // both norms in the residual's epilogue, the residual itself not stored
+    return apply_op(c, l, 1, Epi::ResidualNorms, c->kz[1], nullptr, r32, nullptr, 0, 0, false, nullptr, 0.0, S_LRES,
+                    S_LRR);
+  }
+  void* t = L.xp[1];
   STCHK(apply_op(c, l, 1, Epi::Residual, c->kz[1], t, r32, nullptr, 0, 0));
   HIPCHK(c, launch_sq2(true, n, t, r32, c->part, c->scal, S_LRES, S_LRR, c->stream));
   return GMG_OK;
@@ -766,7 +774,7 @@ gmg_status init_rho_plain(gmg_ctx* c) {
   STCHK(project(c, 0, n, c->kc[0]));
   double rho = 0.0;
   for (int k = 0; k < 2; ++k) {
-    STCHK(test_cycle(c, 0, c->kc[0], true));
+    STCHK(test_cycle(c, 0, c->kc[0], true, true));
     STCHK(read_scalars(c, hs, kNumScal));
     rho = std::sqrt(hs[S_LRES] / hs[S_LRR]);
     // next input: the residual of this cycle, widened to FP64

@@ -74,8 +74,9 @@ struct KTab {
 constexpr int kEpiZero = static_cast<int>(Epi::ChebZero);
 constexpr int kEpiDot = static_cast<int>(Epi::ApplyDot);
 constexpr int kEpiResSums = static_cast<int>(Epi::ResidualSums);
+constexpr int kEpiResNorms = static_cast<int>(Epi::ResidualNorms);
 // epilogues that reduce two sums per block into a partials buffer
-constexpr bool reduces(int epi) { return epi == kEpiDot || epi == kEpiResSums; }
+constexpr bool reduces(int epi) { return epi == kEpiDot || epi == kEpiResSums || epi == kEpiResNorms; }
 
 // x_1 = s0 D^-1 b at one node of class cls
 template <typename T, int Q>
@@ -152,6 +153,16 @@ __device__ __forceinline__ void emit(const KTab<T, Q>& tb, const size_t idx, con
       dacc[0] = fma(static_cast<double>(res.v[c]), static_cast<double>(res.v[c]), dacc[0]);
       dacc[1] += static_cast<double>(res.v[c]);
     }
+  } else if constexpr (EPI == kEpiResNorms) {
+    // |b - A x|^2 and |b|^2 of this thread's outputs (the test of a learned cycle); no store
+    const V bv = *reinterpret_cast<const V*>(bvec + idx);
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      const T r = bv.v[c] - ax[c];
+      dacc[0] = fma(static_cast<double>(r), static_cast<double>(r), dacc[0]);
+      dacc[1] = fma(static_cast<double>(bv.v[c]), static_cast<double>(bv.v[c]), dacc[1]);
+    }
+    return;
   } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
     const V bv = *reinterpret_cast<const V*>(bvec + idx);
 #pragma unroll
@@ -198,12 +209,13 @@ template <typename T, int Q, int EPI>
 constexpr int col_rows() {
   if (sizeof(T) != 8)
     return (Q == 2 && (EPI == static_cast<int>(Epi::Residual) || EPI == static_cast<int>(Epi::Cheb) ||
-                       EPI == static_cast<int>(Epi::ChebZero)))
+                       EPI == static_cast<int>(Epi::ChebZero) || EPI == kEpiResNorms))
                ? 2
                : 4;
   if (Q == 4) return 2;
   if (Q == 2 && (EPI == static_cast<int>(Epi::Cheb) || EPI == static_cast<int>(Epi::ChebZero) ||
-                 EPI == static_cast<int>(Epi::ApplyDot) || EPI == static_cast<int>(Epi::ResidualSums)))
+                 EPI == static_cast<int>(Epi::ApplyDot) || EPI == static_cast<int>(Epi::ResidualSums) ||
+                 EPI == kEpiResNorms))
     return 2;
   return 4;
 }
@@ -825,6 +837,7 @@ ApplyShape shape_tq(Epi epi, int N, int n) {
     case Epi::ResidualSums:
       if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiResSums>(N, n);
       break;
+    case Epi::ResidualNorms: return shape_te<T, Q, kEpiResNorms>(N, n);
   }
   return ApplyShape{-1, 0, 0, 0};
 }
@@ -835,6 +848,7 @@ void prime_tq(int N) {
   prime_te<T, Q, 1>(N);
   prime_te<T, Q, 2>(N);
   prime_te<T, Q, kEpiZero>(N);
+  prime_te<T, Q, kEpiResNorms>(N);
   if constexpr (sizeof(T) == 8) {
     prime_te<T, Q, kEpiDot>(N);
     prime_te<T, Q, kEpiResSums>(N);
@@ -856,6 +870,7 @@ hipError_t launch_tq(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
     case Epi::ResidualSums:
       if constexpr (sizeof(T) == 8) return launch_te<T, Q, kEpiResSums>(tab, a, s);
       return hipErrorInvalidValue;
+    case Epi::ResidualNorms: return launch_te<T, Q, kEpiResNorms>(tab, a, s);
   }
   return hipErrorInvalidValue;
 }

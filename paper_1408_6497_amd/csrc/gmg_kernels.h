@@ -44,7 +44,7 @@ struct TransferTab {
   double r[kMaxQ][4 * kMaxQ + 1];
 };
 
-enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3, ApplyDot = 4, ResidualSums = 5 };
+enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3, ApplyDot = 4, ResidualSums = 5, ResidualNorms = 6 };
 
 // out = A x                          (Epi::Apply)
 // out = A x, sc[d0] = x . A x and sc[d1] = sum(A x)   (Epi::ApplyDot: FP64, uniform levels
@@ -53,6 +53,8 @@ enum class Epi : int { Apply = 0, Residual = 1, Cheb = 2, ChebZero = 3, ApplyDot
 // out = b - A x, sc[d0] = out . out and sc[d1] = sum(out)   (Epi::ResidualSums: the same
 //                                      conditions as Epi::ApplyDot)
 // out = b - A x                      (Epi::Residual)
+// sc[d0] = |b - A x|^2 and sc[d1] = |b|^2, nothing stored (Epi::ResidualNorms: FP32 or FP64,
+//                                      uniform levels of N >= 64 nodes; partials as ApplyDot)
 // out = x + c1 (x - xp) + c2 D^-1 (b - A x)   (Epi::Cheb; xp unused when c1 == 0,
 //                                      read as zero when null; out may alias xp, never x)
 // the first two Chebyshev steps from x_0 = 0 in one pass (Epi::ChebZero, uniform

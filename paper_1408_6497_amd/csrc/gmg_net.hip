@@ -272,8 +272,6 @@ __global__ void __launch_bounds__(kBlk) k_net_l2bwd(const uint16_t* __restrict__
   __shared__ u32x4 tile[2 * kHalf];
   int x0, y0, z0;
   brick_of(N, x0, y0, z0);
-  const int m = N - 1;
-  const u32x4* in4 = reinterpret_cast<const u32x4*>(in);
   fill_halo_tile(reinterpret_cast<const u32x4*>(in), N, x0, y0, z0, tile);
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, g = lane >> 4;

@@ -52,7 +52,7 @@ class GmgOptions(ctypes.Structure):
         ("ir_mode", ctypes.c_int32), ("use_learned", ctypes.c_int32),
         ("learned_depths", ctypes.c_int32), ("no_fused_tail", ctypes.c_int32),
         ("learned_min_depth", ctypes.c_int32), ("no_speculation", ctypes.c_int32),
-        ("no_fused_transfer", ctypes.c_int32),
+        ("no_fused_transfer", ctypes.c_int32), ("no_fused_test_norms", ctypes.c_int32),
     ]
 
 

@@ -288,6 +288,41 @@ def test_trained_net_gain_on_held_out_sources():
     assert out["learned"][2] <= 1e-8 and out["learned"][0] <= out["plain"][0]
 
 
+def test_learned_test_norms_fused_into_the_residual():
+    """The per-cycle test of a learned cycle takes ||r32 - A z32||^2 and ||r32||^2 in the FP32
+    residual's epilogue on uniform levels of more than 32 nodes (the residual itself is not
+    stored); with no_fused_test_norms it stores the residual and reduces both norms in a pass of
+    its own.  At 32^3 Q2 elements the top level (64 nodes a side) takes the fused form.  The two
+    forms compute the residual by the same FP32 expression and differ in the order of the FP64
+    sums (and at most in one FP32 rounding per entry where the compiler contracts differently),
+    so the contractions agree to 1e-7 relative, the keep-or-fall-back decisions are the same,
+    and so is every cycle's output and the solution."""
+    torch = torch_cuda()
+    import os
+    from paper_1408_6497_amd import Context
+    from paper_1408_6497_amd import train as T
+    from workloads import grf
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    w = T.load(os.path.join(here, "paper_1408_6497_amd", "weights", "q2_depth0.gmgw"))["w"]
+    out = {}
+    for fused in (True, False):
+        c = Context(2, 32, 0, seed=0, use_learned=1, no_fused_test_norms=0 if fused else 1)
+        c.net_set_weights(0, w)
+        f, _ = grf(c.lattice(), 30001, device="cuda")
+        u = torch.empty_like(f)
+        info = c.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        out[fused] = (info.inner_iters, info.fallbacks, c.history(1), to_host(u))
+        c.close()
+    (i1, f1, h1, u1), (i0, f0, h0, u0) = out[True], out[False]
+    print(f"[test norms] iterations {i1} / {i0}, fallbacks {f1} / {f0}, rho {h1[:, 0]}", flush=True)
+    assert (i1, f1) == (i0, f0) and h1.shape == h0.shape
+    fin = np.isfinite(h0)
+    assert np.array_equal(fin, np.isfinite(h1))
+    assert np.allclose(h1[fin], h0[fin], rtol=1e-7, atol=0.0)
+    assert rel_l2(u1, u0) <= 1e-12
+
+
 @pytest.mark.parametrize("depth", [2, 3, 4, 5])
 def test_per_depth_nets_beat_chebyshev_on_their_levels(depth):
     """The shipped net of each depth of the headline hierarchy (Q2 on 256^3 elements; depth d is
