@@ -564,6 +564,43 @@ def apply512_probe(reps=5):
     return out
 
 
+def q4apply512_probe(reps=5):
+    """For rocprofv3 counter runs: a 256 MiB device copy three times (the counters' calibration),
+    then on Q4 with 128^3 elements (512^3 DoFs) `reps` applies, residuals, smoother applications
+    from a guess (three Chebyshev steps each) and from zero (the fused first two steps and one
+    more): FP32 in the vector form and in the matrix-core form (option q4_mfma), then FP64."""
+    import torch
+    from paper_1408_6497_amd import Context
+    a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    del a, b
+    out = {}
+    for name, dt, mf in (("fp32_vector", torch.float32, 0), ("fp32_mfma", torch.float32, 1),
+                         ("fp64_vector", torch.float64, 0)):
+        ctx = Context(4, 128, 0, seed=0, lambda_override=2.199326, q4_mfma=mf)
+        g = torch.Generator(device="cuda").manual_seed(3)
+        x = torch.randn(ctx.num_dofs(), device="cuda", dtype=dt, generator=g)
+        rhs = torch.randn(ctx.num_dofs(), device="cuda", dtype=dt, generator=g)
+        y = torch.empty_like(x)
+        for _ in range(reps):
+            ctx.apply(-1, x, y)
+        for _ in range(reps):
+            ctx.residual(-1, rhs, x, y)
+        for _ in range(reps):
+            ctx.smooth(-1, rhs, x, 1)
+        for _ in range(reps):
+            ctx.smooth_zero(-1, rhs, y, 1)
+        torch.cuda.synchronize()
+        out[name] = {"dofs": ctx.num_dofs(),
+                     "shape_smooth": ctx.launch_shape(-1, 1 if dt == torch.float32 else 0, "smooth")}
+        del x, rhs, y
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -574,12 +611,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (Q2/Q4 on 256^3 DoFs, octree, sharp layer, C1, FFT methods)")
     ap.add_argument("--profile-workload", choices=("learned", "q4", "octree", "c2", "spectral", "c4roofline",
-                                                   "apply512", "net512"), default=None,
+                                                   "apply512", "net512", "q4apply512"), default=None,
                     help="for profilers: run only this workload and print its JSON (no timed bench step); "
                          "c4roofline is the bench's own per-launch measurement of the learned solve, apply512 "
                          "a 256 MiB copy (counter calibration) then five Q1 and Q2 applies, restrictions and "
                          "prolongations of each precision on 512^3 DoFs, net512 five learned corrections on the 512^3 and "
-                         "256^3 lattices")
+                         "256^3 lattices, q4apply512 the same copy then five Q4 applies, residuals and smoother "
+                         "applications on 512^3 DoFs in each form (FP32 vector, FP32 matrix cores, FP64)")
     ap.add_argument("--profile-n", type=int, default=256,
                     help="elements per direction of the learned workload under --profile-workload")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -610,6 +648,8 @@ def main():
                    "achieved_gbs": algo_bytes / sec * 1e-9, "per_level": per_level}
         elif args.profile_workload == "apply512":
             res = apply512_probe()
+        elif args.profile_workload == "q4apply512":
+            res = q4apply512_probe()
         elif args.profile_workload == "net512":
             res = {"net_512": net_rate(256, reps=5), "net_256": net_rate(128, reps=5)}
         else:

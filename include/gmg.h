@@ -141,6 +141,13 @@ typedef struct {
                                reduces the two norms in a pass of its own instead of in the
                                residual's epilogue (the same norms up to summation order;
                                testing aid)                                              */
+  int32_t q4_mfma;          /* != 0: the FP32 q = 4 applies, residuals and smoother steps on
+                               uniform levels of N >= 64 nodes take the x and z passes of
+                               the sum factorization (Section 4: 1D contractions of the
+                               element-local values) on the matrix cores (4x4x1 FP32
+                               MFMA) instead of the vector unit; the same operator to FP32
+                               rounding.  Off by default: measured slower here (the vector
+                               form is not bound by its arithmetic)                       */
 } gmg_options;
 
 typedef struct {
@@ -216,7 +223,8 @@ gmg_status gmg_smooth_zero(gmg_ctx* ctx, int32_t level, gmg_prec prec, const voi
  *   [0] kernel: 0 point kernel (one thread per element column, levels of N <= 32
  *       nodes), 1 streaming column kernel, 2 column kernel that loads all planes of its
  *       one-layer z chunk at once, 3 one-pass (fused) transfer, 4 three one-axis
- *       transfer passes, 5 octree kernels;
+ *       transfer passes, 5 octree kernels, 6 generic-order kernels, 7 streaming
+ *       column kernel with its x and z passes on the matrix cores (option q4_mfma);
  *   [1] G (a tile is 4G lattice rows), [2] TZ (element layers per block; 0 for the
  *   point kernel), [3] blocks per launch (0 for transfers and octree levels).
  * GMG_E_ARG for an invalid level or op (restriction and prolongation need level >= 1). */

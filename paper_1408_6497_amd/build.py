@@ -22,8 +22,10 @@ HIPCC_FLAGS = [
 
 # per-source additions: the learned-net kernels keep their MFMA results in ordinary VGPRs, so
 # the epilogues (ReLU, BF16 packing, stores) read them without v_accvgpr_read (about 100 fewer
-# VALU instructions per wavefront of k_net_l12, no accumulation registers)
-SOURCE_FLAGS = {"gmg_net.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# VALU instructions per wavefront of k_net_l12, no accumulation registers); so does the
+# matrix-core form of the q = 4 column kernel, whose accumulators feed vector FMAs and stores
+SOURCE_FLAGS = {"gmg_net.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+                "gmg_apply.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():

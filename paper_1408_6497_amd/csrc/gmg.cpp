@@ -351,6 +351,7 @@ gmg_status apply_op(gmg_ctx* c, int l, int pi, Epi epi, const void* x, void* out
   a.epi = epi;
   a.x1 = x1;
   a.s0 = s0;
+  a.mfma = c->opt.q4_mfma != 0;
   if (epi == Epi::ApplyDot || epi == Epi::ResidualSums || epi == Epi::ResidualNorms) {
     if (L.oct || L.gen || (pi != 0 && epi != Epi::ResidualNorms) || mass || d0 < 0 || d1 < 0 || L.N <= 32)
       return fail(c, GMG_E_ARG, "fused apply and dot unsupported here");
@@ -2273,9 +2274,9 @@ gmg_status gmg_launch_shape(const gmg_ctx* ctx, int32_t level, gmg_prec prec, in
     return GMG_OK;
   }
   static const Epi epis[4] = {Epi::Apply, Epi::Residual, Epi::Cheb, Epi::ChebZero};
-  const ApplyShape sh = apply_shape(ctx->q, f32, epis[op], L.N, L.n);
+  const ApplyShape sh = apply_shape(ctx->q, f32, epis[op], L.N, L.n, ctx->opt.q4_mfma != 0);
   if (sh.kernel < 0) return GMG_E_ARG;
-  shape_host[0] = sh.kernel;
+  shape_host[0] = sh.kernel == 3 ? 7 : sh.kernel;
   shape_host[1] = sh.G;
   shape_host[2] = sh.TZ;
   shape_host[3] = sh.nblocks;

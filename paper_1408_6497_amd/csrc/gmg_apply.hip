@@ -40,6 +40,15 @@
 //   registers; the whole level sits in cache.  For q >= 2 the 2q+1 z rows of
 //   the neighbourhood go to 2q+1 wavefronts and their partial sums meet in LDS.
 //
+// FP32 q = 4 on the matrix cores: the x and z passes of the column kernel are
+//   v_mfma_f32_4x4x1_16b_f32 outer products.  Lane l's four result registers
+//   hold sum_k A(lane 4 (l / 4) + v) B(lane l), v = 0 .. 3: each lane gives one
+//   value of its own element column as B and the lanes of its group of four give
+//   the weights of node class v as A, so one instruction adds one tap (x pass) or
+//   one plane of the element layer (z pass) to all four classes or output planes
+//   of every lane.  Only the vertex's taps into the left element (x) and the
+//   shared top plane (z) stay on the vector unit.
+//
 // Epilogues fuse the residual (b - A x) and the Chebyshev-Jacobi step
 // x + c1 (x - x_prev) + c2 D^-1 (b - A x) into the same pass.  From a zero
 // guess the first two steps are one pass: the input values are b scaled by
@@ -53,6 +62,24 @@
 
 namespace gmg {
 namespace {
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// Instances with a matrix-core form of the column kernel (ApplyArgs::mfma).
+template <typename T, int Q>
+constexpr bool col_mfma_ok() {
+  return sizeof(T) == 4 && Q == 4;
+}
+
+// one tap: d[v] += A(lane 4 (l / 4) + v) * B(lane l)
+__device__ __forceinline__ mf4 mfma4(float a, float b, mf4 d) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, d, 0, 0, 0);
+}
+
+// the value of four by node class c = 0 .. 3
+__device__ __forceinline__ float by_class(int c, float v0, float v1, float v2, float v3) {
+  return c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : v3;
+}
 
 template <typename T, int Q>
 struct alignas(sizeof(T) * Q) VecQ {
@@ -204,11 +231,13 @@ constexpr int col_bound() {
 // residuals and smoother steps take two as well: 110 instead of 174-190 VGPRs, four
 // wavefronts per SIMD instead of two, which their extra input streams need to keep
 // memory busy (512^3 DoFs: smoother step 550 -> 444 us, residual 434 -> 371 us; the
-// plain apply is faster with four, 243 against 274 us).
+// plain apply is faster with four, 243 against 274 us).  So do the FP32 q = 4 ones:
+// two wavefronts per SIMD instead of one (512^3 DoFs: smoother step 732 -> 495 us,
+// residual 520 -> 378 us; the plain apply 309 us with four rows, 323 with two).
 template <typename T, int Q, int EPI>
 constexpr int col_rows() {
   if (sizeof(T) != 8)
-    return (Q == 2 && (EPI == static_cast<int>(Epi::Residual) || EPI == static_cast<int>(Epi::Cheb) ||
+    return ((Q == 2 || Q == 4) && (EPI == static_cast<int>(Epi::Residual) || EPI == static_cast<int>(Epi::Cheb) ||
                        EPI == static_cast<int>(Epi::ChebZero) || EPI == kEpiResNorms))
                ? 2
                : 4;
@@ -223,7 +252,7 @@ constexpr int col_rows() {
 // --------------------------------------------------------------------------
 // Streaming column kernel.
 // Body of the column kernel for workgroups whose threads start at row class CY0.
-template <typename T, int Q, int G, int EPI, int RY, int CY0, bool PRE>
+template <typename T, int Q, int G, int EPI, int RY, int CY0, bool PRE, bool MFK>
 __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, Q>& tb, const int N, const int TZ,
                                          const int Y0, const int E0, T* out, const T* bvec, const T* xp,
                                          const T c1, const T c2, T* x1o, double (&dacc)[2]) {
@@ -306,10 +335,67 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     }
   };
 
+  // matrix-core form (FP32 q = 4): per-lane A operands, row (tx & 3) of each weight
+  // table.  x pass: window tap Q + j of node class c is table column Q + j - c; z pass:
+  // output plane c from plane j of the element layer.
+  constexpr bool MF = MFK && col_mfma_ok<T, Q>();
+  constexpr int NMF = MF ? Q + 1 : 1;
+  float xkA[NMF], xmA[NMF], zkA[NMF], zmA[NMF];
+  if constexpr (MF) {
+    const int cl = tx & 3;
+#pragma unroll
+    for (int j = 0; j <= Q; ++j) {
+      xkA[j] = by_class(cl, tb.kr[0][Q + j], tb.kr[1][Q + j - 1], tb.kr[2][Q + j - 2], tb.kr[3][Q + j - 3]);
+      xmA[j] = by_class(cl, tb.mr[0][Q + j], tb.mr[1][Q + j - 1], tb.mr[2][Q + j - 2], tb.mr[3][Q + j - 3]);
+      zkA[j] = by_class(cl, tb.zk[0][j], tb.zk[1][j], tb.zk[2][j], tb.zk[3][j]);
+      zmA[j] = by_class(cl, tb.zm[0][j], tb.zm[1][j], tb.zm[2][j], tb.zm[3][j]);
+    }
+  }
+
   // x pass across element columns, after the y pass of this plane went to LDS
   auto xpass = [&]() {
     T* ps = lds + parity * buf_stride;
     T* ss = ps + TY * N;
+    if constexpr (MF) {
+#pragma unroll
+      for (int i = 0; i < RY; ++i) {
+        const int row = (ty * RY + i) * N;
+        const V a = *reinterpret_cast<const V*>(ps + row + Q * txl);
+        const V b = *reinterpret_cast<const V*>(ps + row + Q * tx);
+        const T c = ps[row + Q * txr];
+        const V d = *reinterpret_cast<const V*>(ss + row + Q * txl);
+        const V e = *reinterpret_cast<const V*>(ss + row + Q * tx);
+        const T f = ss[row + Q * txr];
+        // own element column and the right vertex: every class has these taps
+        mf4 gv = {0.f, 0.f, 0.f, 0.f}, hv = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          gv = mfma4(xkA[j], b.v[j], gv);
+          gv = mfma4(xmA[j], e.v[j], gv);
+          hv = mfma4(xmA[j], b.v[j], hv);
+        }
+        gv = mfma4(xkA[Q], c, gv);
+        gv = mfma4(xmA[Q], f, gv);
+        hv = mfma4(xmA[Q], c, hv);
+        // the vertex (class 0) also reaches into the left element column (offsets -q .. -1)
+        T g0 = gv[0], h0 = hv[0];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          g0 = fma(tb.kr[0][k], a.v[k], g0);
+          g0 = fma(tb.mr[0][k], d.v[k], g0);
+          h0 = fma(tb.mr[0][k], a.v[k], h0);
+        }
+        g[i][0] = g0;
+        h[i][0] = h0;
+#pragma unroll
+        for (int cc = 1; cc < Q; ++cc) {
+          g[i][cc] = gv[cc];
+          h[i][cc] = hv[cc];
+        }
+      }
+      parity ^= 1;
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       const int row = (ty * RY + i) * N;
@@ -356,10 +442,14 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     if constexpr (kLatePrefetch) {
       // the next plane's loads go out once the y pass has consumed this one: one strip
       // of registers instead of two (q = 4 would spill), the loads still overlap the
-      // x and z passes
+      // x and z passes.  They go out unconditionally (past the chunk's last plane they
+      // read a plane of the next chunk, in bounds through the periodic wrap, and unused):
+      // behind a branch the compiler moved the next y pass into it and waited on each
+      // load at once (512^3 DoFs, FP32 apply 335 -> 309 us, FP64 smoother step 1086 ->
+      // 907 us)
       ypass(pre, ps, ss);
       keep(pre, slot);
-      if (prefetch) load_plane(p + 1);
+      load_plane(p + 1);
     } else {
       V xv[NR];
 #pragma unroll
@@ -372,7 +462,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     xpass();
   };
 
-  T acc[RY][Q][Q + 1];
+  T acc[MF ? 1 : RY][Q][Q + 1];
   if constexpr (PRE) {
     // a one-layer chunk (TZ = 1): the 2q+1 planes (E0-1) q .. (E0+1) q are loaded at
     // once, so the block waits for memory once instead of once per plane
@@ -436,27 +526,57 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
   }
   const int zlast = (E0 + TZ) * Q;
 
+  // z pass in element form: plane 0 of an element layer starts its accumulators (and,
+  // with carry, adds the shared vertex plane the layer below left in slot q), each
+  // further plane b adds its two terms
+  mf4 acc4[MF ? RY : 1][Q];
+  T top[MF ? RY : 1][Q];
+  auto z_first = [&](bool carry) {
+#pragma unroll
+    for (int i = 0; i < RY; ++i)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        if constexpr (MF) {
+          mf4 t = mfma4(zmA[0], g[i][c], mf4{0.f, 0.f, 0.f, 0.f});
+          t = mfma4(zkA[0], h[i][c], t);
+          if (carry) t[0] += top[i][c];
+          acc4[i][c] = t;
+          top[i][c] = tb.zm[Q][0] * g[i][c] + tb.zk[Q][0] * h[i][c];
+        } else {
+          const T top0 = acc[i][c][Q];
+          acc[i][c][0] = carry ? top0 + tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c]
+                               : tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c];
+#pragma unroll
+          for (int a = 1; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
+        }
+      }
+  };
+  auto z_plane = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < RY; ++i)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        if constexpr (MF) {
+          acc4[i][c] = mfma4(zmA[b], g[i][c], mfma4(zkA[b], h[i][c], acc4[i][c]));
+          top[i][c] = fma(tb.zm[Q][b], g[i][c], fma(tb.zk[Q][b], h[i][c], top[i][c]));
+        } else {
+#pragma unroll
+          for (int a = 0; a <= Q; ++a)
+            acc[i][c][a] = fma(tb.zm[a][b], g[i][c], fma(tb.zk[a][b], h[i][c], acc[i][c][a]));
+        }
+      }
+  };
+
   load_plane((E0 - 1) * Q);
   compute_gh((E0 - 1) * Q, true, 0);
-#pragma unroll
-  for (int i = 0; i < RY; ++i)
-#pragma unroll
-    for (int c = 0; c < Q; ++c)
-#pragma unroll
-      for (int a = 0; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
+  z_first(false);
 
   for (int E = E0 - 1; E < E0 + TZ; ++E) {
 #pragma unroll
     for (int b = 1; b <= Q; ++b) {
       const int p = E * Q + b;
       compute_gh(p, p < zlast, b);
-#pragma unroll
-      for (int i = 0; i < RY; ++i)
-#pragma unroll
-        for (int c = 0; c < Q; ++c)
-#pragma unroll
-          for (int a = 0; a <= Q; ++a)
-            acc[i][c][a] = fma(tb.zm[a][b], g[i][c], fma(tb.zk[a][b], h[i][c], acc[i][c][a]));
+      z_plane(b);
     }
     if (E >= E0) {
 #pragma unroll
@@ -466,7 +586,10 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
         for (int i = 0; i < RY; ++i) {
           T ax[Q];
 #pragma unroll
-          for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
+          for (int c = 0; c < Q; ++c) {
+            if constexpr (MF) ax[c] = acc4[i][c][a];
+            else ax[c] = acc[i][c][a];
+          }
           const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
           emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc,
                           kKeep ? &xcen[a][i] : nullptr);
@@ -478,20 +601,21 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
       for (int i = 0; i < RY; ++i) xcen[0][i] = xcen[Q][i];
     }
     // carry the shared vertex plane into the next element layer
-#pragma unroll
-    for (int i = 0; i < RY; ++i)
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        const T top = acc[i][c][Q];
-        acc[i][c][0] = top + tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c];
-#pragma unroll
-        for (int a = 1; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
-      }
+    z_first(true);
   }
 }
 
-template <typename T, int Q, int G, int EPI, bool PRE = false>
-__global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
+// Wavefronts per SIMD the compiler is held to: two for the two-row FP32 q = 4 instances
+// (left alone, the zero-guess smoother step took 266 registers and so one wavefront; held
+// to two it needs 240 and spills nothing), the compiler's own choice elsewhere.
+template <typename T, int Q, int EPI>
+constexpr int col_min_waves() {
+  return (sizeof(T) == 4 && Q == 4 && col_rows<T, Q, EPI>() == 2) ? 2 : 1;
+}
+
+template <typename T, int Q, int G, int EPI, bool PRE = false, bool MF = false>
+__global__ void __launch_bounds__(col_bound<Q>()) __attribute__((amdgpu_waves_per_eu(col_min_waves<T, Q, EPI>())))
+k_apply_col(const T* __restrict__ x, const KTab<T, Q> tb,
                                                               const int N, const int TZ, const int ntiles_y,
                                                               T* out, const T* bvec, const T* xp, const T c1,
                                                               const T c2, T* x1o, double* part) {
@@ -505,10 +629,10 @@ __global__ void __launch_bounds__(col_bound<Q>()) k_apply_col(const T* __restric
   const int E0 = (tile / ntiles_y) * TZ;
   double dacc[2] = {0.0, 0.0};
   if constexpr (SPLIT == 1) {
-    col_body<T, Q, G, EPI, RY, 0, PRE>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    col_body<T, Q, G, EPI, RY, 0, PRE, MF>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
   } else {
-    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0, PRE>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
-    else col_body<T, Q, G, EPI, RY, 2, PRE>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    if (b % SPLIT == 0) col_body<T, Q, G, EPI, RY, 0, PRE, MF>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
+    else col_body<T, Q, G, EPI, RY, 2, PRE, MF>(x, tb, N, TZ, Y0, E0, out, bvec, xp, c1, c2, x1o, dacc);
   }
   if constexpr (reduces(EPI)) {
     // block partials in a fixed order: wavefront shuffles, then the wavefronts in turn
@@ -674,7 +798,7 @@ inline ColShape col_shape(int N, int Q, size_t elem, int RY) {
 // CU from the occupancy API (registers, LDS, block size) times the CU count.
 // Cached per device and LDS size; the context primes it at setup, so no query
 // runs while a launch sequence is being captured into a graph.
-template <typename T, int Q, int G, int EPI>
+template <typename T, int Q, int G, int EPI, bool MF = false>
 int resident_blocks(int threads, size_t lds) {
   static std::mutex mu;
   static std::map<std::pair<int, size_t>, int> cache;
@@ -685,7 +809,7 @@ int resident_blocks(int threads, size_t lds) {
   const auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int per_cu = 0, cus = 0;
-  const void* fn = reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>);
+  const void* fn = reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI, false, MF>);
   if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
       per_cu < 1)
@@ -718,18 +842,21 @@ constexpr bool pre_ok() {
   return sizeof(T) == 4 && Q <= 2 && !reduces(EPI);
 }
 
-template <typename T, int Q, int G, int EPI>
+template <typename T, int Q, int G, int EPI, bool MF = false>
 hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hipStream_t s) {
+  if constexpr (col_mfma_ok<T, Q>() && !MF) {
+    if (a.mfma) return launch_col<T, Q, G, EPI, true>(kt, a, sh, s);
+  }
   const int threads = (a.N / Q) * G;
   const int64_t tiles = static_cast<int64_t>(sh.ntiles_y) * sh.split;
-  sh.TZ = pick_tz(a.n, tiles, resident_blocks<T, Q, G, EPI>(threads, sh.lds));
+  sh.TZ = pick_tz(a.n, tiles, resident_blocks<T, Q, G, EPI, MF>(threads, sh.lds));
   sh.nblocks = static_cast<int>(tiles * (a.n / sh.TZ));
   if constexpr (reduces(EPI)) {
     if (a.part == nullptr || a.sc == nullptr || 2 * static_cast<int64_t>(sh.nblocks) > a.part_cap)
       return hipErrorInvalidValue;
   }
   if (sh.lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_col<T, Q, G, EPI, false, MF>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sh.lds));
     if (e != hipSuccess) return e;
   }
@@ -742,7 +869,7 @@ hipError_t launch_col(const KTab<T, Q>& kt, const ApplyArgs& a, ColShape sh, hip
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
+  hipLaunchKernelGGL((k_apply_col<T, Q, G, EPI, false, MF>), dim3(sh.nblocks), dim3(a.N / Q, G), sh.lds, s,
                      static_cast<const T*>(a.x), kt, a.N, sh.TZ, sh.ntiles_y, static_cast<T*>(a.out),
                      static_cast<const T*>(a.b), static_cast<const T*>(a.xp), static_cast<T>(a.c1),
                      static_cast<T>(a.c2), static_cast<T*>(a.x1), a.part);
@@ -783,21 +910,28 @@ hipError_t launch_te(const OpTab& tab, const ApplyArgs& a, hipStream_t s) {
   return hipErrorInvalidConfiguration;
 }
 
+template <typename T, int Q, int EPI, bool MF>
+int resident_any(int G, int threads, size_t lds) {
+  switch (G) {
+    case 1: return resident_blocks<T, Q, 1, EPI, MF>(threads, lds);
+    case 2: return resident_blocks<T, Q, 2, EPI, MF>(threads, lds);
+    case 4: return resident_blocks<T, Q, 4, EPI, MF>(threads, lds);
+  }
+  return 1;
+}
+
 template <typename T, int Q, int EPI>
 void prime_te(int N) {
   if (N <= 32) return;
   const ColShape sh = col_shape(N, Q, sizeof(T), col_rows<T, Q, EPI>());
   const int threads = (N / Q) * sh.G;
-  switch (sh.G) {
-    case 1: resident_blocks<T, Q, 1, EPI>(threads, sh.lds); break;
-    case 2: resident_blocks<T, Q, 2, EPI>(threads, sh.lds); break;
-    case 4: resident_blocks<T, Q, 4, EPI>(threads, sh.lds); break;
-  }
+  resident_any<T, Q, EPI, false>(sh.G, threads, sh.lds);
+  if constexpr (col_mfma_ok<T, Q>()) resident_any<T, Q, EPI, true>(sh.G, threads, sh.lds);
 }
 
 // The shape launch_te takes for one instance (a query for tests and tracing).
 template <typename T, int Q, int EPI>
-ApplyShape shape_te(int N, int n) {
+ApplyShape shape_te(int N, int n, bool mfma) {
   ApplyShape out{};
   if (N <= 32) {
     out.kernel = 0;
@@ -810,34 +944,32 @@ ApplyShape shape_te(int N, int n) {
   }
   ColShape sh = col_shape(N, Q, sizeof(T), col_rows<T, Q, EPI>());
   const int threads = (N / Q) * sh.G;
-  int resident = 1;
-  switch (sh.G) {
-    case 1: resident = resident_blocks<T, Q, 1, EPI>(threads, sh.lds); break;
-    case 2: resident = resident_blocks<T, Q, 2, EPI>(threads, sh.lds); break;
-    case 4: resident = resident_blocks<T, Q, 4, EPI>(threads, sh.lds); break;
-  }
+  bool mf = false;
+  if constexpr (col_mfma_ok<T, Q>()) mf = mfma;
+  const int resident = mf ? resident_any<T, Q, EPI, col_mfma_ok<T, Q>()>(sh.G, threads, sh.lds)
+                          : resident_any<T, Q, EPI, false>(sh.G, threads, sh.lds);
   const int64_t tiles = static_cast<int64_t>(sh.ntiles_y) * sh.split;
   out.TZ = pick_tz(n, tiles, resident);
   out.G = sh.G;
   out.nblocks = static_cast<int>(tiles * (n / out.TZ));
-  out.kernel = (pre_ok<T, Q, EPI>() && out.TZ == 1) ? 2 : 1;
+  out.kernel = (pre_ok<T, Q, EPI>() && out.TZ == 1) ? 2 : mf ? 3 : 1;
   return out;
 }
 
 template <typename T, int Q>
-ApplyShape shape_tq(Epi epi, int N, int n) {
+ApplyShape shape_tq(Epi epi, int N, int n, bool mfma) {
   switch (epi) {
-    case Epi::Apply: return shape_te<T, Q, 0>(N, n);
-    case Epi::Residual: return shape_te<T, Q, 1>(N, n);
-    case Epi::Cheb: return shape_te<T, Q, 2>(N, n);
-    case Epi::ChebZero: return shape_te<T, Q, kEpiZero>(N, n);
+    case Epi::Apply: return shape_te<T, Q, 0>(N, n, mfma);
+    case Epi::Residual: return shape_te<T, Q, 1>(N, n, mfma);
+    case Epi::Cheb: return shape_te<T, Q, 2>(N, n, mfma);
+    case Epi::ChebZero: return shape_te<T, Q, kEpiZero>(N, n, mfma);
     case Epi::ApplyDot:
-      if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiDot>(N, n);
+      if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiDot>(N, n, mfma);
       break;
     case Epi::ResidualSums:
-      if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiResSums>(N, n);
+      if constexpr (sizeof(T) == 8) return shape_te<T, Q, kEpiResSums>(N, n, mfma);
       break;
-    case Epi::ResidualNorms: return shape_te<T, Q, kEpiResNorms>(N, n);
+    case Epi::ResidualNorms: return shape_te<T, Q, kEpiResNorms>(N, n, mfma);
   }
   return ApplyShape{-1, 0, 0, 0};
 }
@@ -887,12 +1019,12 @@ void prime_apply_shapes(int q, int N) {
   }
 }
 
-ApplyShape apply_shape(int q, bool fp32, Epi epi, int N, int n) {
+ApplyShape apply_shape(int q, bool fp32, Epi epi, int N, int n, bool mfma) {
   if (N != q * n || N < 4 || (N & (N - 1)) != 0 || n > apply_max_elements_x(q)) return ApplyShape{-1, 0, 0, 0};
   switch (q) {
-    case 1: return fp32 ? shape_tq<float, 1>(epi, N, n) : shape_tq<double, 1>(epi, N, n);
-    case 2: return fp32 ? shape_tq<float, 2>(epi, N, n) : shape_tq<double, 2>(epi, N, n);
-    case 4: return fp32 ? shape_tq<float, 4>(epi, N, n) : shape_tq<double, 4>(epi, N, n);
+    case 1: return fp32 ? shape_tq<float, 1>(epi, N, n, mfma) : shape_tq<double, 1>(epi, N, n, mfma);
+    case 2: return fp32 ? shape_tq<float, 2>(epi, N, n, mfma) : shape_tq<double, 2>(epi, N, n, mfma);
+    case 4: return fp32 ? shape_tq<float, 4>(epi, N, n, mfma) : shape_tq<double, 4>(epi, N, n, mfma);
   }
   return ApplyShape{-1, 0, 0, 0};
 }

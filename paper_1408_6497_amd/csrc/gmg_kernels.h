@@ -76,6 +76,7 @@ struct ApplyArgs {
   int64_t part_cap;
   double* sc;
   int d0, d1;
+  bool mfma = false;  // FP32 q = 4 column kernel: x and z passes on the matrix cores
 };
 
 // Exact FFT solve of the uniform periodic Q1 system on N^3 nodes (FP64): plans and the
@@ -169,13 +170,14 @@ hipError_t spectral_solve(const FftSpectral& s, const double* f, double* u, hipS
 hipError_t launch_apply(const OpTab& tab, bool fp32, const ApplyArgs& a, hipStream_t s);
 // The launch shape launch_apply takes on a uniform level: kernel 0 = the point kernel
 // (N <= 32), 1 = the streaming column kernel, 2 = the column kernel that loads all the
-// planes of its one-layer z chunk at once; G (4G rows per tile), TZ (element layers per
-// block, 0 for the point kernel) and the block count.  kernel = -1 for an unsupported
-// combination.
+// planes of its one-layer z chunk at once, 3 the streaming column kernel with its x and z
+// passes on the matrix cores (mfma: FP32 q = 4 only); G (4G rows per tile), TZ (element
+// layers per block, 0 for the point kernel) and the block count.  kernel = -1 for an
+// unsupported combination.
 struct ApplyShape {
   int kernel, G, TZ, nblocks;
 };
-ApplyShape apply_shape(int q, bool fp32, Epi epi, int N, int n);
+ApplyShape apply_shape(int q, bool fp32, Epi epi, int N, int n, bool mfma = false);
 // Query (once per device) the occupancy that the launch shape of every apply
 // kernel instance for a level of N nodes a side depends on; call before any
 // launch sequence is captured into a graph.

@@ -165,8 +165,8 @@ hipError_t apply_t(const OctLevelDev& L, bool mass, const OctApply& a, hipStream
       hipLaunchKernelGGL((k_oct_dof<T, 2, kDofLanes>), g, dim3(kB), 0, s, L.n, L.tptr, L.trow, tval, ye, x, b, xp,
                          dinv, c1, c2, out);
       break;
-    case Epi::ChebZero:
-      return hipErrorInvalidValue;  // uniform levels only
+    default:
+      return hipErrorInvalidValue;  // the zero-guess step and the reducing epilogues: uniform levels only
   }
   return hipGetLastError();
 }

@@ -53,6 +53,7 @@ class GmgOptions(ctypes.Structure):
         ("learned_depths", ctypes.c_int32), ("no_fused_tail", ctypes.c_int32),
         ("learned_min_depth", ctypes.c_int32), ("no_speculation", ctypes.c_int32),
         ("no_fused_transfer", ctypes.c_int32), ("no_fused_test_norms", ctypes.c_int32),
+        ("q4_mfma", ctypes.c_int32),
     ]
 
 
@@ -300,7 +301,7 @@ class Context:
 
     SHAPE_OPS = {"apply": 0, "residual": 1, "smooth": 2, "smooth_zero": 3, "restrict": 4, "prolong": 5}
     SHAPE_KERNELS = {0: "point", 1: "column", 2: "column_preload", 3: "transfer_fused", 4: "transfer_axis",
-                     5: "octree", 6: "generic"}
+                     5: "octree", 6: "generic", 7: "column_mfma"}
 
     def launch_shape(self, level, prec, op):
         """(kernel name, G, TZ, blocks) of the launch an operation takes on a level."""
