@@ -462,7 +462,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     xpass();
   };
 
-  T acc[MF ? 1 : RY][Q][Q + 1];
+  T acc[RY][Q][Q + 1];
   if constexpr (PRE) {
     // a one-layer chunk (TZ = 1): the 2q+1 planes (E0-1) q .. (E0+1) q are loaded at
     // once, so the block waits for memory once instead of once per plane
@@ -525,58 +525,81 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     return;
   }
   const int zlast = (E0 + TZ) * Q;
-
-  // z pass in element form: plane 0 of an element layer starts its accumulators (and,
-  // with carry, adds the shared vertex plane the layer below left in slot q), each
-  // further plane b adds its two terms
-  mf4 acc4[MF ? RY : 1][Q];
-  T top[MF ? RY : 1][Q];
-  auto z_first = [&](bool carry) {
+  if constexpr (MF) {
+    // z pass in element form on the matrix cores: four of the q + 1 accumulators of a
+    // point in one mf4 (output planes 0 .. 3 of the element layer), the shared top plane
+    // (slot q) on the vector unit.  Plane 0 of a layer starts them (with carry adding the
+    // top plane the layer below left), each further plane b adds its two terms.
+    mf4 acc4[RY][Q];
+    T top[RY][Q];
+    auto z_first = [&](bool carry) {
 #pragma unroll
-    for (int i = 0; i < RY; ++i)
+      for (int i = 0; i < RY; ++i)
 #pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        if constexpr (MF) {
+        for (int c = 0; c < Q; ++c) {
           mf4 t = mfma4(zmA[0], g[i][c], mf4{0.f, 0.f, 0.f, 0.f});
           t = mfma4(zkA[0], h[i][c], t);
           if (carry) t[0] += top[i][c];
           acc4[i][c] = t;
           top[i][c] = tb.zm[Q][0] * g[i][c] + tb.zk[Q][0] * h[i][c];
-        } else {
-          const T top0 = acc[i][c][Q];
-          acc[i][c][0] = carry ? top0 + tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c]
-                               : tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c];
+        }
+    };
+    load_plane((E0 - 1) * Q);
+    compute_gh((E0 - 1) * Q, true, 0);
+    z_first(false);
+    for (int E = E0 - 1; E < E0 + TZ; ++E) {
 #pragma unroll
-          for (int a = 1; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
+      for (int b = 1; b <= Q; ++b) {
+        const int p = E * Q + b;
+        compute_gh(p, p < zlast, b);
+#pragma unroll
+        for (int i = 0; i < RY; ++i)
+#pragma unroll
+          for (int c = 0; c < Q; ++c) {
+            acc4[i][c] = mfma4(zmA[b], g[i][c], mfma4(zkA[b], h[i][c], acc4[i][c]));
+            top[i][c] = fma(tb.zm[Q][b], g[i][c], fma(tb.zk[Q][b], h[i][c], top[i][c]));
+          }
+      }
+      if (E >= E0) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+          const size_t zoff = static_cast<size_t>(E * Q + a) * NN;
+#pragma unroll
+          for (int i = 0; i < RY; ++i) {
+            T ax[Q];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) ax[c] = acc4[i][c][a];
+            const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
+            emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc, nullptr);
+          }
         }
       }
-  };
-  auto z_plane = [&](int b) {
-#pragma unroll
-    for (int i = 0; i < RY; ++i)
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        if constexpr (MF) {
-          acc4[i][c] = mfma4(zmA[b], g[i][c], mfma4(zkA[b], h[i][c], acc4[i][c]));
-          top[i][c] = fma(tb.zm[Q][b], g[i][c], fma(tb.zk[Q][b], h[i][c], top[i][c]));
-        } else {
-#pragma unroll
-          for (int a = 0; a <= Q; ++a)
-            acc[i][c][a] = fma(tb.zm[a][b], g[i][c], fma(tb.zk[a][b], h[i][c], acc[i][c][a]));
-        }
-      }
-  };
+      z_first(true);  // carry the shared vertex plane into the next element layer
+    }
+    return;
+  }
 
   load_plane((E0 - 1) * Q);
   compute_gh((E0 - 1) * Q, true, 0);
-  z_first(false);
+#pragma unroll
+  for (int i = 0; i < RY; ++i)
+#pragma unroll
+    for (int c = 0; c < Q; ++c)
+#pragma unroll
+      for (int a = 0; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
 
   for (int E = E0 - 1; E < E0 + TZ; ++E) {
 #pragma unroll
     for (int b = 1; b <= Q; ++b) {
       const int p = E * Q + b;
       compute_gh(p, p < zlast, b);
-      z_plane(b);
+#pragma unroll
+      for (int i = 0; i < RY; ++i)
+#pragma unroll
+        for (int c = 0; c < Q; ++c)
+#pragma unroll
+          for (int a = 0; a <= Q; ++a)
+            acc[i][c][a] = fma(tb.zm[a][b], g[i][c], fma(tb.zk[a][b], h[i][c], acc[i][c][a]));
     }
     if (E >= E0) {
 #pragma unroll
@@ -586,10 +609,7 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
         for (int i = 0; i < RY; ++i) {
           T ax[Q];
 #pragma unroll
-          for (int c = 0; c < Q; ++c) {
-            if constexpr (MF) ax[c] = acc4[i][c][a];
-            else ax[c] = acc[i][c][a];
-          }
+          for (int c = 0; c < Q; ++c) ax[c] = acc[i][c][a];
           const size_t idx = zoff + static_cast<size_t>(yrow0 + i) * N + Q * tx;
           emit<T, Q, EPI>(tb, idx, (CY0 + i) % Q, a, ax, x, out, bvec, xp, c1, c2, x1o, dacc,
                           kKeep ? &xcen[a][i] : nullptr);
@@ -601,7 +621,15 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
       for (int i = 0; i < RY; ++i) xcen[0][i] = xcen[Q][i];
     }
     // carry the shared vertex plane into the next element layer
-    z_first(true);
+#pragma unroll
+    for (int i = 0; i < RY; ++i)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const T top = acc[i][c][Q];
+        acc[i][c][0] = top + tb.zm[0][0] * g[i][c] + tb.zk[0][0] * h[i][c];
+#pragma unroll
+        for (int a = 1; a <= Q; ++a) acc[i][c][a] = tb.zm[a][0] * g[i][c] + tb.zk[a][0] * h[i][c];
+      }
   }
 }
 
