@@ -187,7 +187,10 @@ gmg_status gmg_diagonal(gmg_ctx* ctx, int32_t level, double* d_dev);
 /* y = A_level x: matrix-free, sum-factorized stiffness apply (Section 2.3.2). */
 gmg_status gmg_apply(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev);
 
-/* y = M_level x with the consistent mass matrix (used for the load vector). */
+/* y = M_level x with the consistent mass matrix of the continuous Galerkin LGL
+ * discretization (Sections 2.3 and 2.3.2): the same sum-factorized kernel with the 1D
+ * mass rows in every direction.  It forms the load vector of the discrete system
+ * A_h u_h = f_h from nodal source values (gmg_rhs). */
 gmg_status gmg_mass(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* x_dev, void* y_dev);
 
 /* u <- S^nu (u; b): nu applications of the level smoother to A u = b, in place
@@ -207,7 +210,8 @@ gmg_status gmg_coarse_solve(gmg_ctx* ctx, gmg_prec prec, const void* b_dev, void
 /* z = V r: one V-cycle (Algorithm 2.1) on the finest level, zero initial guess. */
 gmg_status gmg_vcycle(gmg_ctx* ctx, gmg_prec prec, const void* r_dev, void* z_dev);
 
-/* r = b - A_level u (vectors of type prec). */
+/* r = b - A_level u (vectors of type prec): the residual step of Algorithm 2.1 on one
+ * level, in the same fused kernel as the apply. */
 gmg_status gmg_residual(gmg_ctx* ctx, int32_t level, gmg_prec prec, const void* b_dev, const void* u_dev, void* r_dev);
 
 /* u = S^nu (0; b): nu applications of the level smoother from a zero initial guess,
@@ -230,7 +234,11 @@ gmg_status gmg_smooth_zero(gmg_ctx* ctx, int32_t level, gmg_prec prec, const voi
  * GMG_E_ARG for an invalid level or op (restriction and prolongation need level >= 1). */
 gmg_status gmg_launch_shape(const gmg_ctx* ctx, int32_t level, gmg_prec prec, int32_t op, int32_t* shape_host);
 
-/* b = M f - mean(M f): load vector of nodal source values f on the finest level. */
+/* b = M f - mean(M f): load vector of nodal source values f on the finest level, the
+ * right-hand side f_h of the Galerkin system A_h u_h = f_h (Section 2.3) for a source
+ * interpolated in the LGL nodal basis (Section 2.3.2).  The mean is removed because on
+ * the periodic unit cube (Section 1, limitations) the system is solvable only for a
+ * right-hand side orthogonal to the constants. */
 gmg_status gmg_rhs(gmg_ctx* ctx, const double* f_dev, double* b_dev);
 
 /* Solve A u = b(f) to ||b - A u||_2 <= rtol ||b||_2 (true FP64 residual); u is
@@ -273,7 +281,9 @@ gmg_status gmg_spectral_create(int32_t N, void* hip_stream, gmg_spectral** out);
 gmg_status gmg_spectral_solve(gmg_spectral* sp, const double* f_dev, double* u_dev);
 gmg_status gmg_spectral_destroy(gmg_spectral* sp);
 
-/* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n). */
+/* *out_host = sum_i x_i y_i accumulated in FP64 (x, y of type prec, length n): the inner
+ * products of the conjugate gradient iteration that the V-cycle preconditions (Section
+ * 2.3), in a fixed summation order (block partials, then one pass over them). */
 gmg_status gmg_dot(gmg_ctx* ctx, gmg_prec prec, int64_t n, const void* x_dev, const void* y_dev, double* out_host);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
