@@ -386,6 +386,39 @@ def q4_workload(steps=5):
     return out
 
 
+def orders_workload(steps=3):
+    """The orders on the generic kernels (q = 3 and 5-16: Tables 7 and 10, Section 3's GMG-16) near
+    256^3 DoFs each: the finest-level apply in both precisions (algorithmic bytes: x read, y
+    written) and FP32 cycles in FP64 flexible CG on 32 Gaussians (sigma U[0.02, 0.1], seed 0) to
+    1e-8."""
+    import torch
+    from paper_1408_6497_amd import Context, GMG_FP32, GMG_FP64
+    from workloads import gaussian_params, gaussian_source
+    params = gaussian_params(0, 32, 0.02, 0.1)
+    out = {"workload": "orders 3, 5, 6, 8, 14, 16 near 256^3 DoFs: apply rates, FP32 cycles in FP64 flexible CG "
+                       "on 32 Gaussians (sigma U[0.02, 0.1], seed 0) to 1e-8"}
+    for q, n in ((3, 64), (5, 32), (6, 32), (8, 32), (14, 16), (16, 16)):
+        ctx = Context(q, n, 0, seed=0, vcycle_prec=GMG_FP32)
+        rec = {"dofs": ctx.num_dofs(), "levels": ctx.levels,
+               "apply_fp32": apply_rate(ctx, GMG_FP32, reps=10), "apply_fp64": apply_rate(ctx, GMG_FP64, reps=10)}
+        f = gaussian_source(ctx.dof_coords_1d(), params, device="cuda")
+        u = torch.empty_like(f)
+        ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = ctx.solve(f, u, 1e-8)
+        torch.cuda.synchronize()
+        rec["fp32_cycles"] = {"s": (time.perf_counter() - t0) / steps, "iters": info.inner_iters,
+                              "rel_residual_f64": info.rel_residual_f64}
+        out[f"q{q}_n{n}"] = rec
+        ctx.close()
+        del f, u
+        torch.cuda.empty_cache()
+    log(f"[bench] orders workload: {out}")
+    return out
+
+
 def octree_workload(steps=5):
     """The adaptive workload: Q2 on the octree refined from level 3 to 9 around 4 Gaussians
     (sigma 1e-3, seed 0); plain FP64 CG vs FP32 cycles in FP64 flexible CG, to 1e-8, plus the
@@ -611,13 +644,14 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (Q2/Q4 on 256^3 DoFs, octree, sharp layer, C1, FFT methods)")
     ap.add_argument("--profile-workload", choices=("learned", "q4", "octree", "c2", "spectral", "c4roofline",
-                                                   "apply512", "net512", "q4apply512"), default=None,
+                                                   "apply512", "net512", "q4apply512", "orders"), default=None,
                     help="for profilers: run only this workload and print its JSON (no timed bench step); "
                          "c4roofline is the bench's own per-launch measurement of the learned solve, apply512 "
                          "a 256 MiB copy (counter calibration) then five Q1 and Q2 applies, restrictions and "
                          "prolongations of each precision on 512^3 DoFs, net512 five learned corrections on the 512^3 and "
                          "256^3 lattices, q4apply512 the same copy then five Q4 applies, residuals and smoother "
-                         "applications on 512^3 DoFs in each form (FP32 vector, FP32 matrix cores, FP64)")
+                         "applications on 512^3 DoFs in each form (FP32 vector, FP32 matrix cores, FP64), orders the "
+                         "generic-kernel orders near 256^3 DoFs (apply rates and FP32-cycle solves)")
     ap.add_argument("--profile-n", type=int, default=256,
                     help="elements per direction of the learned workload under --profile-workload")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -650,6 +684,8 @@ def main():
             res = apply512_probe()
         elif args.profile_workload == "q4apply512":
             res = q4apply512_probe()
+        elif args.profile_workload == "orders":
+            res = orders_workload()
         elif args.profile_workload == "net512":
             res = {"net_512": net_rate(256, reps=5), "net_256": net_rate(128, reps=5)}
         else:
@@ -701,6 +737,7 @@ def main():
                                 "flops_per_voxel": NET_FLOPS_PER_VOXEL, "peak_tflops": BF16_PEAK_TFLOPS}
         extra["c2_gaussians"] = c2_workload(args.steps, 1)
         extra["q4_sharp"] = q4_workload()
+        extra["orders"] = orders_workload()
         extra["octree"] = octree_workload()
         extra["c1"] = c1_workload()
         extra["sharp_layer"] = sharp_layer_workload()

@@ -1411,7 +1411,7 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
   const int q = mesh->order;
   const int n = mesh->n;
   const bool octree = n == 0;
-  // q = 1, 2, 4 run the specialised kernels; 3, 5, 6, 7, 8 the generic ones (uniform meshes)
+  // q = 1, 2, 4 run the specialised kernels; 3 and 5 .. 16 the generic ones (uniform meshes)
   const bool gen = q == 3 || (q >= 5 && q <= kGenMaxQ);
   if (!(q == 1 || q == 2 || q == 4 || gen)) return GMG_E_ARG;
   if (gen && n == 0) return GMG_E_ARG;  // octree meshes: orders 1 and 2
@@ -1452,7 +1452,9 @@ gmg_status gmg_setup(const gmg_mesh* mesh, const gmg_options* opts, void* hip_st
     nc0 = n >> (L - 1);
     if (q * nc0 < Nmin || nc0 < nmin) return GMG_E_ARG;
     n0 = static_cast<int64_t>(q * nc0) * (q * nc0) * (q * nc0);
-    if (n0 > 512) return GMG_E_ARG;  // dense FP64 coarsest solve: at most 512 DoFs
+    // dense FP64 coarsest solve: at most 512 DoFs, or one periodic element of order up to
+    // 16 (at most 4096 DoFs, its pseudo-inverse formed from the 1D eigenpairs)
+    if (n0 > (nc0 == 1 ? 4096 : 512)) return GMG_E_ARG;
   }
 
   gmg_ctx* c = new (std::nothrow) gmg_ctx();

@@ -1,6 +1,6 @@
 // Operator, transfers and diagonal-class arithmetic of uniform periodic levels whose
-// order has no specialised kernel: q = 3, 5, 6, 7, 8 (Section 2.3.2 admits 1 <= q <= 16;
-// Table 10 runs q = 4, 5, 6, 8).  N = q n lattice nodes per direction, n a power of two
+// order has no specialised kernel: q = 3 and 5 .. 16 (Section 2.3.2 admits 1 <= q <= 16;
+// Table 10 runs q = 4, 5, 6, 8, Table 7 q = 14 and 16).  N = q n lattice nodes per direction, n a power of two
 // (n = 1 allowed: a single periodic element), so N is not a power of two in general and
 // every periodic index is taken modulo N.
 //

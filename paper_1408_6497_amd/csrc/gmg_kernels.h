@@ -119,10 +119,10 @@ struct FftQ4 {
 hipError_t fft_q4_prepare(FftQ4* f, int n);
 hipError_t fft_q4_solve(FftQ4* f, const double* b, double* u, hipStream_t s);
 
-// Orders without a specialised kernel (q = 3, 5, 6, 7, 8; gmg_generic.hip): the operator as
+// Orders without a specialised kernel (q = 3 and 5 .. 16; gmg_generic.hip): the operator as
 // three banded 1D passes through four level-size temporaries, transfers as one-axis passes,
 // and the node-class arithmetic with its class tables in device memory.
-constexpr int kGenMaxQ = 8;
+constexpr int kGenMaxQ = 16;
 // rows: 6 blocks of q (2q+1) values (z K, z M, y K, y M, x K, x M; row c = node class,
 // tap o + q for offset o); dinv: 1 / A_ii by node class (q^3)
 struct GenOp {

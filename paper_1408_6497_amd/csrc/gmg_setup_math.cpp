@@ -292,9 +292,157 @@ static void dense_1d(int q, int n, std::vector<double>* K, std::vector<double>* 
       }
 }
 
+// Generalized symmetric eigenpairs of the 1D pair (K, M), M positive definite:
+// V^T M V = I and V^T K V = diag(lam), V column-wise (V[i N + a] = component i of
+// eigenvector a).  M = L L^T (Cholesky), C = L^-1 K L^-T diagonalised by cyclic Jacobi
+// rotations, V = L^-T U.  N is one element's worth of nodes here (q <= 16).
+static void generalized_eigen_1d(int N, const std::vector<double>& K, const std::vector<double>& M,
+                                 std::vector<double>* V, std::vector<double>* lam) {
+  std::vector<double> L(static_cast<size_t>(N) * N, 0.0);
+  for (int j = 0; j < N; ++j) {
+    double d = M[j * N + j];
+    for (int k = 0; k < j; ++k) d -= L[j * N + k] * L[j * N + k];
+    if (!(d > 0.0)) throw std::runtime_error("1D mass matrix is not positive definite");
+    L[j * N + j] = std::sqrt(d);
+    for (int i = j + 1; i < N; ++i) {
+      double t = M[i * N + j];
+      for (int k = 0; k < j; ++k) t -= L[i * N + k] * L[j * N + k];
+      L[i * N + j] = t / L[j * N + j];
+    }
+  }
+  // X = L^-1 K (forward substitution per column), C = L^-1 X^T = L^-1 K L^-T
+  auto lower_solve = [&](const std::vector<double>& B, std::vector<double>* X) {
+    X->assign(static_cast<size_t>(N) * N, 0.0);
+    for (int c = 0; c < N; ++c)
+      for (int i = 0; i < N; ++i) {
+        double t = B[i * N + c];
+        for (int k = 0; k < i; ++k) t -= L[i * N + k] * (*X)[k * N + c];
+        (*X)[i * N + c] = t / L[i * N + i];
+      }
+  };
+  std::vector<double> X, Xt(static_cast<size_t>(N) * N), C;
+  lower_solve(K, &X);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Xt[i * N + j] = X[j * N + i];
+  lower_solve(Xt, &C);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < i; ++j) C[i * N + j] = C[j * N + i] = 0.5 * (C[i * N + j] + C[j * N + i]);
+  std::vector<double> U(static_cast<size_t>(N) * N, 0.0);
+  for (int i = 0; i < N; ++i) U[i * N + i] = 1.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        tot += C[i * N + j] * C[i * N + j];
+        if (i != j) off += C[i * N + j] * C[i * N + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < N - 1; ++p)
+      for (int r = p + 1; r < N; ++r) {
+        const double apr = C[p * N + r];
+        if (apr == 0.0) continue;
+        // the rotation that zeroes C[p][r]: tan(2 theta) = 2 apr / (arr - app)
+        const double theta = 0.5 * std::atan2(2.0 * apr, C[r * N + r] - C[p * N + p]);
+        const double cs = std::cos(theta), sn = std::sin(theta);
+        for (int k = 0; k < N; ++k) {  // columns p, r
+          const double ckp = C[k * N + p], ckr = C[k * N + r];
+          C[k * N + p] = cs * ckp - sn * ckr;
+          C[k * N + r] = sn * ckp + cs * ckr;
+        }
+        for (int k = 0; k < N; ++k) {  // rows p, r
+          const double cpk = C[p * N + k], crk = C[r * N + k];
+          C[p * N + k] = cs * cpk - sn * crk;
+          C[r * N + k] = sn * cpk + cs * crk;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double ukp = U[k * N + p], ukr = U[k * N + r];
+          U[k * N + p] = cs * ukp - sn * ukr;
+          U[k * N + r] = sn * ukp + cs * ukr;
+        }
+      }
+  }
+  lam->assign(N, 0.0);
+  for (int a = 0; a < N; ++a) (*lam)[a] = C[a * N + a];
+  // V = L^-T U (back substitution per column)
+  V->assign(static_cast<size_t>(N) * N, 0.0);
+  for (int c = 0; c < N; ++c)
+    for (int i = N - 1; i >= 0; --i) {
+      double t = U[i * N + c];
+      for (int k = i + 1; k < N; ++k) t -= L[k * N + i] * (*V)[k * N + c];
+      (*V)[i * N + c] = t / L[i * N + i];
+    }
+}
+
+// (A_0 + 1 1^T / n0)^-1 from the eigenpairs of the 1D pair instead of a dense
+// factorisation (n0 up to 4096: one periodic element of order 16).  With W = V (x) V (x) V,
+// W^T A_0 W = D = lam (+) lam (+) lam, so for r orthogonal to the constants
+// e = W D^+ W^T r solves A_0 e = r (D^+ drops the one zero eigenvalue, the constants);
+// removing its mean gives A_0^+ r, and the matrix is A_0^+ + 1 1^T / n0.  Column c:
+// W^T (e_c - 1/n0) is the outer product of three rows of V less W^T 1 / n0, then three
+// 1D mode products with V.
+static std::vector<double> kron_pseudo_inverse(int q, int n) {
+  const int N = q * n;
+  const int n0 = N * N * N;
+  std::vector<double> K, M, V, lam;
+  dense_1d(q, n, &K, &M);
+  generalized_eigen_1d(N, K, M, &V, &lam);
+  int a0 = 0;
+  for (int a = 1; a < N; ++a)
+    if (std::abs(lam[a]) < std::abs(lam[a0])) a0 = a;
+  std::vector<double> dplus(n0), u(N, 0.0);
+  for (int c = 0; c < N; ++c)
+    for (int b = 0; b < N; ++b)
+      for (int a = 0; a < N; ++a) {
+        const double d = lam[a] + lam[b] + lam[c];
+        dplus[a + N * (b + N * c)] = (a == a0 && b == a0 && c == a0) ? 0.0 : 1.0 / d;
+      }
+  for (int a = 0; a < N; ++a)
+    for (int i = 0; i < N; ++i) u[a] += V[i * N + a];
+  std::vector<double> inv(static_cast<size_t>(n0) * n0);
+  std::vector<double> t(n0), w(n0);
+  const double inv_n0 = 1.0 / n0;
+  for (int col = 0; col < n0; ++col) {
+    const int i = col % N, j = (col / N) % N, k = col / (N * N);
+    for (int c = 0; c < N; ++c)
+      for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a) {
+          const int idx = a + N * (b + N * c);
+          t[idx] = (V[i * N + a] * V[j * N + b] * V[k * N + c] - inv_n0 * u[a] * u[b] * u[c]) * dplus[idx];
+        }
+    // y = W t: a mode product along each axis
+    for (int c = 0; c < N; ++c)
+      for (int b = 0; b < N; ++b)
+        for (int x = 0; x < N; ++x) {
+          double s = 0.0;
+          for (int a = 0; a < N; ++a) s += V[x * N + a] * t[a + N * (b + N * c)];
+          w[x + N * (b + N * c)] = s;
+        }
+    for (int c = 0; c < N; ++c)
+      for (int y = 0; y < N; ++y)
+        for (int x = 0; x < N; ++x) {
+          double s = 0.0;
+          for (int b = 0; b < N; ++b) s += V[y * N + b] * w[x + N * (b + N * c)];
+          t[x + N * (y + N * c)] = s;
+        }
+    double mean = 0.0;
+    for (int z = 0; z < N; ++z)
+      for (int y = 0; y < N; ++y)
+        for (int x = 0; x < N; ++x) {
+          double s = 0.0;
+          for (int c = 0; c < N; ++c) s += V[z * N + c] * t[x + N * (y + N * c)];
+          w[x + N * (y + N * z)] = s;
+          mean += s;
+        }
+    mean *= inv_n0;
+    for (int r = 0; r < n0; ++r) inv[static_cast<size_t>(r) * n0 + col] = w[r] - mean + inv_n0;
+  }
+  return inv;
+}
+
 std::vector<double> coarse_pseudo_inverse(int q, int n) {
   const int N = q * n;
   const int n0 = N * N * N;
+  if (n0 > 512) return kron_pseudo_inverse(q, n);
   std::vector<double> K, M;
   dense_1d(q, n, &K, &M);
   // A_0 = K (x) M (x) M + M (x) K (x) M + M (x) M (x) K

@@ -37,7 +37,8 @@ double lagrange_deriv_at(const std::vector<double>& xi, int a, double t);
 void reference_matrices(int q, std::vector<double>* khat, std::vector<double>* mhat);
 LevelTables make_level_tables(int q, int n);
 void make_transfer_table(int q, TransferTab* tab);
-// (A_0 + 1 1^T / N0)^-1 of the coarsest level, dense, symmetric, row-major.
+// (A_0 + 1 1^T / N0)^-1 of the coarsest level, dense, symmetric, row-major: by a dense
+// factorisation up to 512 DoFs, from the eigenpairs of the 1D matrices above (up to 4096).
 std::vector<double> coarse_pseudo_inverse(int q, int n);
 // (A + 1 1^T / n0)^-1 of any dense symmetric n0 x n0 matrix A with null space 1 (row-major).
 std::vector<double> dense_pseudo_inverse(std::vector<double> A, int n0);

@@ -569,14 +569,14 @@ __global__ void __launch_bounds__(kBlock) k_copy(const int64_t n, const T* __res
 // ---------------------------------------------------------------- coarsest solve
 // x = Ainv (b - mean(b)) with Ainv symmetric (row i read contiguously): each
 // block has 4 wavefronts, one row each; every block recomputes the mean of b
-// (n0 <= 512 values) so no second launch is needed.
-constexpr int kCoarseMax = 512;
+// (n0 <= 4096 values, held in dynamic LDS of 8 n0 bytes) so no second launch is needed.
+constexpr int kCoarseMax = 4096;
 constexpr int kCoarseRows = 4;
 
 template <typename T>
 __global__ void __launch_bounds__(64 * kCoarseRows) k_coarse(const int n0, const double* __restrict__ ainv,
                                                               const T* __restrict__ b, T* __restrict__ x) {
-  __shared__ double bs[kCoarseMax];
+  extern __shared__ double bs[];
   __shared__ double red[kCoarseRows];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double s = 0.0;
@@ -932,11 +932,12 @@ hipError_t launch_copy(bool fp32, int64_t n, const void* in, void* out, hipStrea
 hipError_t launch_coarse(bool fp32, int n0, const double* ainv, const void* b, void* x, hipStream_t s) {
   if (n0 < 1 || n0 > kCoarseMax) return hipErrorInvalidValue;
   const dim3 grid((n0 + kCoarseRows - 1) / kCoarseRows);
+  const size_t lds = sizeof(double) * static_cast<size_t>(n0);
   if (fp32)
-    hipLaunchKernelGGL(k_coarse<float>, grid, dim3(64 * kCoarseRows), 0, s, n0, ainv, static_cast<const float*>(b),
-                       static_cast<float*>(x));
+    hipLaunchKernelGGL(k_coarse<float>, grid, dim3(64 * kCoarseRows), lds, s, n0, ainv,
+                       static_cast<const float*>(b), static_cast<float*>(x));
   else
-    hipLaunchKernelGGL(k_coarse<double>, grid, dim3(64 * kCoarseRows), 0, s, n0, ainv,
+    hipLaunchKernelGGL(k_coarse<double>, grid, dim3(64 * kCoarseRows), lds, s, n0, ainv,
                        static_cast<const double*>(b), static_cast<double*>(x));
   return hipGetLastError();
 }

@@ -44,16 +44,17 @@ def test_invalid_arguments_rejected_before_device_work():
     lib = _lib()
     h = ctypes.c_void_p()
     opts = gmg.GmgOptions()
-    # order 9 (beyond the generic kernels), n not a power of two, one element for q = 2, too
+    # order 17 (beyond Section 2.3.2's 16), n not a power of two, one element for q = 2, too
     # few nodes, order 0, a generic order on a mesh above its size limit, a generic order
     # on an octree mesh
-    for order, n in ((9, 8), (2, 6), (2, 1), (1, 2), (0, 8), (5, 128), (3, 0)):
+    for order, n in ((17, 8), (2, 6), (2, 1), (1, 2), (0, 8), (5, 128), (3, 0), (16, 0)):
         mesh = gmg.GmgMesh(order=order, n=n, levels=0, reserved=0)
         st = lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h))
         assert st == 1, (order, n, st)
     assert lib.gmg_setup(None, None, None, ctypes.byref(h)) == 1
-    # too many levels for the mesh; too few (coarsest level above 512 DoFs)
-    for order, n, levels in ((2, 8, 5), (2, 8, 1), (5, 4, 4), (5, 4, 2)):
+    # too many levels for the mesh; too few (coarsest level above 512 DoFs, or above one
+    # element where that element alone has more)
+    for order, n, levels in ((2, 8, 5), (2, 8, 1), (5, 4, 4), (5, 4, 2), (16, 2, 1), (9, 4, 2)):
         mesh = gmg.GmgMesh(order=order, n=n, levels=levels, reserved=0)
         assert lib.gmg_setup(ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(h)) == 1, (order, n, levels)
     assert lib.gmg_status_string(5) == b"not converged"

@@ -1,12 +1,13 @@
-"""The paper's other orders on the GPU (q = 3, 5, 6, 8; Section 2.3.2 admits 1 <= q <= 16, Table 10
-runs q = 4, 5, 6, 8) against the FP64 oracle, element by element, through the C ABI.
+"""The paper's other orders on the GPU (q = 3, 5, 6, 8, 14, 16; Section 2.3.2 admits 1 <= q <= 16,
+Table 10 runs q = 4, 5, 6, 8, Table 7 q = 14) against the FP64 oracle, element by element, through
+the C ABI.
 
 These orders run the generic kernels (three banded passes for the operator, one-axis transfer
 passes, class tables in device memory) and their hierarchies coarsen down to a single periodic
 element (Section 2.3.1).  Bars as for q = 1, 2, 4: apply 1e-12 (FP64) / 2e-5 (FP32) relative l2,
 smoother and V-cycle 1e-11 / 1e-4, transfers 1e-14 / 1e-6, solves by the oracle's own residual.
 The paper's Jacobi V(2,1) cycle in CG to 1e-13 is run for its iteration counts (Section 3 reports
-6, 8 and 20 for q = 1, 4, 8), which are printed as a plausibility check, not pinned.
+6, 8, 20 and 28 for q = 1, 4, 8, 16), which are printed as a plausibility check, not pinned.
 """
 import numpy as np
 import pytest
@@ -105,7 +106,79 @@ def test_lambda_smoother_vcycle_parity(q, n):
         assert es <= ts and ev <= tv
 
 
-@pytest.mark.parametrize("q,n", [(5, 8), (8, 4)])
+@pytest.mark.parametrize("q,n", [(14, 1), (16, 1), (16, 2)])
+def test_high_orders_apply_coarse_solve_vcycle(q, n):
+    """Orders 14 and 16 (Table 7's GMG-14, Section 3's GMG-16) on the generic kernels: the apply
+    in FP64 and FP32; the coarsest solve on the one periodic element their hierarchies end with
+    (2744 or 4096 DoFs; its pseudo-inverse is formed from the eigenpairs of the 1D matrices
+    instead of a dense factorisation); for two elements a side the transfers, the Lanczos
+    estimates, the smoother and the V-cycle.  Against the oracle's Kronecker operator and
+    prolongation and its dense coarsest inverse.  Bars: apply 1e-12 / 2e-5, transfers 1e-14 /
+    1e-6; coarsest solve, smoother and V-cycle 1e-9 in FP64 (the coarsest operator's condition
+    number grows like q^4) and 1e-4 in FP32."""
+    torch = torch_cuda()
+    from oracle import multigrid as mg, operator as op
+    ctx = _ctx(q, n, 0, seed=3)
+    assert ctx.levels == (1 if n == 1 else 2) and ctx.num_dofs(0) == q ** 3
+    top = ctx.levels - 1
+    assert ctx.launch_shape(top, 0, "apply")[0] == "generic"
+    A = op.operator(q, n, "kron")
+    size = (q * n) ** 3
+    x = mean_free_normal(size, 100 + q + n)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+        xd = to_dev(x, dt)
+        yd = torch.empty_like(xd)
+        ctx.apply(top, xd, yd)
+        torch.cuda.synchronize()
+        ea = rel_l2(to_host(yd), A @ to_host(xd))
+        print(f"[high orders] q={q} n={n} {dt}: apply {ea:.2e}", flush=True)
+        assert ea <= tol
+    H = mg.Hierarchy(q, n, ctx.levels, mg.Options(seed=3), form="kron")
+    bc = mean_free_normal(q ** 3, 200 + q)
+    for dt, tol in ((torch.float64, 1e-9), (torch.float32, 1e-4)):
+        bd = to_dev(bc, dt)
+        xd = torch.empty_like(bd)
+        ctx.coarse_solve(bd, xd)
+        torch.cuda.synchronize()
+        ec = rel_l2(to_host(xd), H.coarse_solve(to_host(bd)))
+        print(f"[high orders] q={q} n={n} {dt}: coarsest solve {ec:.2e}", flush=True)
+        assert ec <= tol
+    if n == 1:
+        return
+    from oracle import transfer
+    Pk = transfer.KroneckerProlongation(q, n // 2)
+    for dt, tol in ((torch.float64, 1e-14), (torch.float32, 1e-6)):
+        rf = to_dev(np.random.default_rng(5).standard_normal(size), dt)
+        rc = torch.empty(q ** 3, dtype=dt, device="cuda")
+        ec = to_dev(np.random.default_rng(6).standard_normal(q ** 3), dt)
+        uf = to_dev(np.random.default_rng(7).standard_normal(size), dt)
+        uf0 = to_host(uf)
+        ctx.restrict(top, rf, rc)
+        ctx.prolong(top, ec, uf)
+        torch.cuda.synchronize()
+        er = rel_l2(to_host(rc), Pk.restrict(to_host(rf)))
+        ep = rel_l2(to_host(uf), uf0 + Pk.prolong(to_host(ec)))
+        print(f"[high orders] q={q} n={n} {dt}: restrict {er:.2e} prolong {ep:.2e}", flush=True)
+        assert er <= tol and ep <= tol
+    for l in range(ctx.levels):
+        assert abs(ctx.lam(l) - H.levels[l].lam) <= 1e-10 * H.levels[l].lam, (l, ctx.lam(l), H.levels[l].lam)
+    lev = H.finest
+    for dt, tol in ((torch.float64, 1e-9), (torch.float32, 1e-4)):
+        b = to_dev(mean_free_normal(lev.size, 21), dt)
+        u = to_dev(np.random.default_rng(22).standard_normal(lev.size), dt)
+        u0 = to_host(u)
+        ctx.smooth(-1, b, u, 2)
+        r = to_dev(mean_free_normal(lev.size, 31), dt)
+        z = torch.empty_like(r)
+        ctx.vcycle(r, z)
+        torch.cuda.synchronize()
+        es = rel_l2(to_host(u), H.smooth(lev, to_host(b), u0, 2))
+        ev = rel_l2(to_host(z), H.vcycle(to_host(r)))
+        print(f"[high orders] q={q} n={n} {dt}: smoother {es:.2e} vcycle {ev:.2e}", flush=True)
+        assert es <= tol and ev <= tol
+
+
+@pytest.mark.parametrize("q,n", [(5, 8), (8, 4), (16, 2)])
 def test_solves_reach_tolerance_on_the_oracle_operator(q, n):
     """Plain FP64 CG and FP32 cycles in FP64 flexible CG, to 1e-8, the 32-Gaussian source."""
     torch = torch_cuda()
@@ -126,11 +199,11 @@ def test_solves_reach_tolerance_on_the_oracle_operator(q, n):
         assert rel <= 1e-8 * 1.001
 
 
-@pytest.mark.parametrize("q,n", [(1, 32), (4, 8), (5, 8), (6, 4), (8, 4)])
+@pytest.mark.parametrize("q,n", [(1, 32), (4, 8), (5, 8), (6, 4), (8, 4), (14, 2), (16, 2)])
 def test_paper_jacobi_v21_cg_iteration_counts(q, n):
     """The paper's cycle (damped Jacobi, omega = 2/3, two pre- and one post-smoothing sweep) as the
     preconditioner of flexible CG, to 1e-13 relative residual on a random load; the counts are
-    reported next to Section 3's (6, 8, 20 for q = 1, 4, 8 on its scaling runs)."""
+    reported next to Section 3's (6, 8, 20, 28 for q = 1, 4, 8, 16 on its scaling runs)."""
     torch = torch_cuda()
     from oracle import operator as op
     ctx = _ctx(q, n, 0, seed=0, smoother=1, jacobi_omega=2.0 / 3.0, nu_pre=2, nu_post=1, krylov=1, max_iters=200)
@@ -141,7 +214,16 @@ def test_paper_jacobi_v21_cg_iteration_counts(q, n):
     torch.cuda.synchronize()
     r = b - op.KroneckerOperator(q, n) @ to_host(u)
     rel = float(np.linalg.norm(r - r.mean()) / np.linalg.norm(b))
-    paper = {1: 6, 4: 8, 8: 20}.get(q)
+    # the library stops on its own FP64 residual; the oracle's FP64 evaluation of b - A u on
+    # the same u differs from it by the rounding of the two evaluations (it grows with the
+    # order: 6e-16 of |b| at q = 1, 3e-14 at q = 14), which the bar allows on top of the 1e-13
+    # as long as it stays below the tolerance itself
+    rd = torch.empty_like(bd)
+    ctx.residual(ctx.levels - 1, bd, u, rd)
+    torch.cuda.synchronize()
+    gap = float(np.linalg.norm(to_host(rd) - r) / np.linalg.norm(b))
+    paper = {1: 6, 4: 8, 8: 20, 16: 28}.get(q)
     print(f"[orders jacobi V(2,1)] q={q} n={n} levels {ctx.levels}: {info.inner_iters} iterations to "
-          f"{rel:.1e} (paper: {paper})", flush=True)
-    assert rel <= 1.01e-13
+          f"{rel:.2e} (the two residual evaluations differ by {gap:.1e}; paper: {paper})", flush=True)
+    assert gap <= 1e-13
+    assert rel <= 1.01e-13 + gap

@@ -42,7 +42,7 @@ def test_lgl_interior_nodes_are_roots_of_the_legendre_derivative(q):
     assert np.all(np.diff(basis.lgl_nodes(q)) > 0)
 
 
-@pytest.mark.parametrize("q", ORDERS)
+@pytest.mark.parametrize("q", ORDERS + [14, 16])
 def test_element_matrices_integrate_monomials_exactly(q):
     Khat, Mhat = basis.element_matrices_1d(q)
     xi = basis.lgl_nodes(q)
@@ -116,6 +116,29 @@ def test_prolongation_galerkin_and_constants(q, n_c):
     Ac = op.assemble(q, n_c).toarray()
     G = (P.T @ Af @ P)
     assert np.max(np.abs(G - Ac)) < 1e-13 * np.max(np.abs(Ac)) * q
+
+
+@pytest.mark.parametrize("q", [14, 16])
+def test_high_orders_1d_factors(q):
+    """Orders 14 and 16 (Table 7's GMG-14, Section 3's GMG-16) through the 1D factors that the
+    operator and the prolongation are Kronecker products of: K symmetric with the constants as
+    its null space and positive elsewhere, M symmetric positive definite with total mass 1 (the
+    unit interval), P1 reproducing the constants and satisfying P1^T K_f P1 = K_c and
+    P1^T M_f P1 = M_c from one coarse element (every 3D identity is a product of these)."""
+    for n in (1, 2):
+        K1, M1 = (m.toarray() for m in op.assemble_1d(q, n))
+        N = q * n
+        assert np.max(np.abs(K1 - K1.T)) <= 1e-13 * np.max(np.abs(K1))
+        assert np.max(np.abs(K1 @ np.ones(N))) <= 1e-12 * np.max(np.abs(K1))
+        ev = np.linalg.eigvalsh(K1)
+        assert abs(ev[0]) <= 1e-10 * ev[-1] and ev[1] > 1e-6 * ev[-1]
+        assert np.min(np.linalg.eigvalsh(M1)) > 0 and abs(M1.sum() - 1.0) < 1e-13
+    P1 = transfer.prolongation_1d(q, 1).toarray()
+    assert np.max(np.abs(P1 @ np.ones(q) - 1.0)) < 1e-12
+    Kf, Mf = (m.toarray() for m in op.assemble_1d(q, 2))
+    Kc, Mc = (m.toarray() for m in op.assemble_1d(q, 1))
+    assert np.max(np.abs(P1.T @ Kf @ P1 - Kc)) < 1e-11 * np.max(np.abs(Kc))
+    assert np.max(np.abs(P1.T @ Mf @ P1 - Mc)) < 1e-13
 
 
 def test_single_element_prolongation_sums_the_identified_end_nodes():
