@@ -277,20 +277,25 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
   for (int r = 0; r < NR; ++r) roff[r] = ((yrow0 - Q + r) & Nm) * N + Q * tx;
 
   V pre[NR];
-  auto load_to = [&](V(&dst)[NR], int p) {
+  // cz: the plane's z class (p mod q), passed so that it stays a compile-time value where
+  // the plane is chosen at run time
+  auto load_cls = [&](V(&dst)[NR], int p, int cz) {
     const T* base = x + static_cast<size_t>(p & Nm) * NN;
 #pragma unroll
     for (int r = 0; r < NR; ++r) dst[r] = *reinterpret_cast<const V*>(base + roff[r]);
     if constexpr (EPI == kEpiZero) {
-      // strip row r has y class (CY0 + r) mod q, the plane z class p mod q
-      const int cz = p & (Q - 1);
+      // strip row r has y class (CY0 + r) mod q, the plane z class cz
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int c = 0; c < Q; ++c) dst[r].v[c] = x1_of(tb, c + Q * ((CY0 + r) % Q + Q * cz), dst[r].v[c]);
     }
   };
+  auto load_to = [&](V(&dst)[NR], int p) { load_cls(dst, p, p & (Q - 1)); };
   auto load_plane = [&](int p) { load_to(pre, p); };
+  // the next plane, or past the chunk's end plane p + 1 - q (same z class, loaded q - 1
+  // planes ago, still in cache; its values are not used)
+  auto prefetch_next = [&](int p, bool prefetch) { load_cls(pre, prefetch ? p + 1 : p + 1 - Q, (p + 1) & (Q - 1)); };
 
   const int txl = (tx - 1) & (NX - 1);
   const int txr = (tx + 1) & (NX - 1);
@@ -436,25 +441,32 @@ __device__ __forceinline__ void col_body(const T* __restrict__ x, const KTab<T, 
     parity ^= 1;
   };
 
+  // The next plane's loads go out on every plane, with no branch around them (past the
+  // chunk's last plane q <= 2 reads plane p + 1 - q again, in cache, and q = 4 the next
+  // chunk's first plane; the values are not used): behind a branch the compiler waited on
+  // the loads right after issuing them -- q = 4 moved the next y pass into the branch,
+  // q <= 2 copied the loaded rows into the strip registers at the join -- so no load
+  // overlapped the compute (512^3 DoFs: q = 4 FP32 apply 335 -> 309 us, FP64 smoother step
+  // 1086 -> 907 us; q = 2 FP32 smoother step 3.5 % and residual 5 % faster, the C4 FP32
+  // solve 39.3 -> 38.4 ms).
   auto compute_gh = [&](int p, bool prefetch, int slot) {
     T* ps = lds + parity * buf_stride;
     T* ss = ps + TY * N;
     if constexpr (kLatePrefetch) {
       // the next plane's loads go out once the y pass has consumed this one: one strip
       // of registers instead of two (q = 4 would spill), the loads still overlap the
-      // x and z passes.  They go out unconditionally (past the chunk's last plane they
-      // read a plane of the next chunk, in bounds through the periodic wrap, and unused):
-      // behind a branch the compiler moved the next y pass into it and waited on each
-      // load at once (512^3 DoFs, FP32 apply 335 -> 309 us, FP64 smoother step 1086 ->
-      // 907 us)
+      // x and z passes
       ypass(pre, ps, ss);
       keep(pre, slot);
+      // q = 4 takes the next plane even past the chunk's end (a plane of the next chunk, in
+      // bounds through the periodic wrap): the chosen address costs the zero-start step a
+      // spill at its 256-register limit
       load_plane(p + 1);
     } else {
       V xv[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) xv[r] = pre[r];
-      if (prefetch) load_plane(p + 1);
+      prefetch_next(p, prefetch);
       ypass(xv, ps, ss);
       keep(xv, slot);
     }
