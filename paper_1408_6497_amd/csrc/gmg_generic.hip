@@ -12,15 +12,24 @@
 // Row c of a 1D matrix (node class c = i mod q) has 2q+1 taps at offsets -q..q; every
 // node is touched once per pass (14 (q+2) flops per DoF) at the cost of four temporaries.
 // The mass M (x) M (x) M goes through the same passes with Kz = Ky = 0 and the x pass's
-// K row set to M.  Transfers P = P1 (x) P1 (x) P1 and P^T are three one-axis passes
-// each, a thread per output node.  One thread per node throughout: these levels trade
-// the fused streaming kernels of q = 1, 2, 4 for generality.
+// K row set to M.  Each pass is compiled per order: a thread takes one element segment of
+// a lattice line (its q nodes), loads the 2q+1 values its rows reach once and writes q
+// outputs (the z and y passes always; the x pass as set by gen_x_per_element, else a
+// thread per node).  Transfers P = P1 (x) P1 (x) P1 and P^T are three one-axis passes
+// each, a thread per output node.  These levels trade the fused streaming kernels of
+// q = 1, 2, 4 for generality.
 #include "gmg_kernels.h"
 
 namespace gmg {
 namespace {
 
 constexpr int kGB = 256;
+// The x pass in the per-element form (else a thread per node): always for the apply and the
+// residual, for the smoother step up to q = 7.  Measured near 256^3 DoFs: the FP32 apply 1.2-1.3x
+// faster at every order; FP32-cycle solves 9-14 % faster for q = 3, 5, 6, but 4-8 % slower for
+// q = 8 and 16, where the smoother step's three extra streams at that stride cost more than
+// the taps save.
+inline bool gen_x_per_element(int q, Epi epi) { return epi != Epi::Cheb || q <= 7; }
 
 inline unsigned gen_grid(int64_t n) {
   int64_t g = (n + kGB - 1) / kGB;
@@ -28,9 +37,22 @@ inline unsigned gen_grid(int64_t n) {
   return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
+// i mod N for -N <= i < 2N (every shifted index below: a node index plus a tap offset of
+// at most one element's span, and a level is at least one element wide), by two selects
+// instead of an integer division per tap
 __device__ __forceinline__ int wrap(int i, int N) {
-  i %= N;
-  return i < 0 ? i + N : i;
+  i += i < 0 ? N : 0;
+  return i >= N ? i - N : i;
+}
+
+// (i, j, k) of a flat index with x fastest; every extent here has at most 1024^3 < 2^31
+// nodes, so 32-bit divisions suffice
+__device__ __forceinline__ void split3(int64_t idx, int X, int Y, int& i, int& j, int& k) {
+  const uint32_t u = static_cast<uint32_t>(idx);
+  const uint32_t jk = u / static_cast<uint32_t>(X);
+  i = static_cast<int>(u - jk * static_cast<uint32_t>(X));
+  k = static_cast<int>(jk / static_cast<uint32_t>(Y));
+  j = static_cast<int>(jk - static_cast<uint32_t>(k) * static_cast<uint32_t>(Y));
 }
 
 // one banded pass along AXIS; T1/T2 (z), U1/V (y) or the output (x)
@@ -53,9 +75,8 @@ __global__ void __launch_bounds__(kGB) k_gen_pass(const T* __restrict__ in0, con
   const int64_t n3 = static_cast<int64_t>(N) * N * N;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(idx % N);
-    const int j = static_cast<int>((idx / N) % N);
-    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    int i, j, k;
+    split3(idx, N, N, i, j, k);
     const int a = AXIS == 2 ? i : (AXIS == 1 ? j : k);   // coordinate along the pass
     const int c = a % q;
     const T* rkc = rk + c * w;
@@ -96,6 +117,186 @@ __global__ void __launch_bounds__(kGB) k_gen_pass(const T* __restrict__ in0, con
   }
 }
 
+// The z and y passes for order Q: a thread takes one element segment of a lattice line along
+// the pass (its Q nodes), loads the 2Q+1 values its rows reach once (the segment, its right
+// vertex and, for the vertex row, the left element) and writes its Q outputs, skipping the
+// structurally zero taps; consecutive threads take consecutive x, so every load is coalesced.
+// The weights are uniform (scalar loads).  AXIS 0: T1 = M x, T2 = K x; AXIS 1: U1 = M T1,
+// V = K T1 + M T2.
+template <typename T, int Q, int AXIS>
+__global__ void __launch_bounds__(kGB) k_gen_pass_zy(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                      const T* __restrict__ rows, const int N,
+                                                      T* __restrict__ out0, T* __restrict__ out1) {
+  static_assert(AXIS == 0 || AXIS == 1, "z and y passes");
+  constexpr int W = 2 * Q + 1;
+  const T* __restrict__ kr = rows + (2 * AXIS) * (Q * W);
+  const T* __restrict__ mr = kr + Q * W;
+  const int nE = N / Q;
+  const int64_t total = static_cast<int64_t>(nE) * N * N;
+  const int64_t step = AXIS == 0 ? static_cast<int64_t>(N) * N : N;  // along the line
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int i, m, e;  // x; the other coordinate across the line (y for AXIS 0, z for AXIS 1); element
+    if constexpr (AXIS == 0) split3(t, N, N, i, m, e);
+    else split3(t, N, nE, i, e, m);
+    const int64_t base = AXIS == 0 ? static_cast<int64_t>(m) * N + i : static_cast<int64_t>(m) * N * N + i;
+    T w0[W], w1[AXIS == 1 ? W : 1];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const int64_t at = base + static_cast<int64_t>(wrap(e * Q - Q + u, N)) * step;
+      w0[u] = in0[at];
+      if constexpr (AXIS == 1) w1[u] = in1[at];
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int o = -Q; o <= Q; ++o) {
+        if (c != 0 && (o < -c || o > Q - c)) continue;  // structural zero of row c
+        const T kv = kr[c * W + o + Q], mv = mr[c * W + o + Q];
+        const T v0 = w0[c + o + Q];
+        s0 = fma(mv, v0, s0);
+        if constexpr (AXIS == 0) {
+          s1 = fma(kv, v0, s1);
+        } else {
+          s1 = fma(kv, v0, s1);
+          s1 = fma(mv, w1[c + o + Q], s1);
+        }
+      }
+      const int64_t at = base + static_cast<int64_t>(e * Q + c) * step;
+      out0[at] = s0;
+      out1[at] = s1;
+    }
+  }
+}
+
+// The x pass for order Q with its epilogue, in the same form: a thread takes one element
+// segment of an x row (loads at a stride of Q values across the wavefront, each thread's
+// window contiguous), y = Kx U1 + Mx V, then the apply, residual or smoother-step epilogue.
+template <typename T, int Q, int EPI>
+__global__ void __launch_bounds__(kGB) k_gen_pass_x(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                     const T* __restrict__ rows, const T* __restrict__ dinv,
+                                                     const int N, T* __restrict__ out, const T* __restrict__ x,
+                                                     const T* __restrict__ b, const T* xp, const T c1, const T c2) {
+  constexpr int W = 2 * Q + 1;
+  const T* __restrict__ kr = rows + 4 * (Q * W);
+  const T* __restrict__ mr = kr + Q * W;
+  const int nE = N / Q;
+  const int64_t total = static_cast<int64_t>(nE) * N * N;
+  const bool use_xp = xp != nullptr && c1 != T(0);
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int e, j, k;
+    split3(t, nE, N, e, j, k);
+    const int64_t row = (static_cast<int64_t>(k) * N + j) * N;
+    T u0[W], v0[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const int64_t at = row + wrap(e * Q - Q + u, N);
+      u0[u] = in0[at];
+      v0[u] = in1[at];
+    }
+    const int cyz = Q * ((j % Q) + Q * (k % Q));
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      T s0 = T(0);
+#pragma unroll
+      for (int o = -Q; o <= Q; ++o) {
+        if (c != 0 && (o < -c || o > Q - c)) continue;  // structural zero of row c
+        s0 = fma(kr[c * W + o + Q], u0[c + o + Q], s0);
+        s0 = fma(mr[c * W + o + Q], v0[c + o + Q], s0);
+      }
+      const int64_t at = row + e * Q + c;
+      if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+        out[at] = s0;
+      } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
+        out[at] = b[at] - s0;
+      } else {  // Epi::Cheb, x_prev read as 0 when absent
+        const T xv = x[at];
+        const T xpv = use_xp ? xp[at] : T(0);
+        out[at] = xv + c1 * (xv - xpv) + c2 * dinv[c + cyz] * (b[at] - s0);
+      }
+    }
+  }
+}
+
+template <typename T, int Q>
+hipError_t gen_x_q(const T* t3, const T* t4, const T* rows, const T* dinv, const ApplyArgs& a, hipStream_t s) {
+  const int N = a.N;
+  const dim3 g(gen_grid(static_cast<int64_t>(N / Q) * N * N)), bl(kGB);
+  const T* x = static_cast<const T*>(a.x);
+  const T* b = static_cast<const T*>(a.b);
+  const T* xp = static_cast<const T*>(a.xp);
+  T* out = static_cast<T*>(a.out);
+  switch (a.epi) {
+    case Epi::Apply:
+      hipLaunchKernelGGL((k_gen_pass_x<T, Q, static_cast<int>(Epi::Apply)>), g, bl, 0, s, t3, t4, rows, dinv, N, out,
+                         x, b, xp, T(0), T(0));
+      break;
+    case Epi::Residual:
+      hipLaunchKernelGGL((k_gen_pass_x<T, Q, static_cast<int>(Epi::Residual)>), g, bl, 0, s, t3, t4, rows, dinv, N,
+                         out, x, b, xp, T(0), T(0));
+      break;
+    case Epi::Cheb:
+      hipLaunchKernelGGL((k_gen_pass_x<T, Q, static_cast<int>(Epi::Cheb)>), g, bl, 0, s, t3, t4, rows, dinv, N, out,
+                         x, b, xp, static_cast<T>(a.c1), static_cast<T>(a.c2));
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+bool gen_x(int q, const T* t3, const T* t4, const T* rows, const T* dinv, const ApplyArgs& a, hipStream_t s,
+           hipError_t* err) {
+  switch (q) {
+    case 3: *err = gen_x_q<T, 3>(t3, t4, rows, dinv, a, s); return true;
+    case 5: *err = gen_x_q<T, 5>(t3, t4, rows, dinv, a, s); return true;
+    case 6: *err = gen_x_q<T, 6>(t3, t4, rows, dinv, a, s); return true;
+    case 7: *err = gen_x_q<T, 7>(t3, t4, rows, dinv, a, s); return true;
+    case 8: *err = gen_x_q<T, 8>(t3, t4, rows, dinv, a, s); return true;
+    case 9: *err = gen_x_q<T, 9>(t3, t4, rows, dinv, a, s); return true;
+    case 10: *err = gen_x_q<T, 10>(t3, t4, rows, dinv, a, s); return true;
+    case 11: *err = gen_x_q<T, 11>(t3, t4, rows, dinv, a, s); return true;
+    case 12: *err = gen_x_q<T, 12>(t3, t4, rows, dinv, a, s); return true;
+    case 13: *err = gen_x_q<T, 13>(t3, t4, rows, dinv, a, s); return true;
+    case 14: *err = gen_x_q<T, 14>(t3, t4, rows, dinv, a, s); return true;
+    case 15: *err = gen_x_q<T, 15>(t3, t4, rows, dinv, a, s); return true;
+    case 16: *err = gen_x_q<T, 16>(t3, t4, rows, dinv, a, s); return true;
+  }
+  return false;
+}
+
+template <typename T, int Q>
+void gen_zy_q(const T* x, const T* rows, int N, T* t1, T* t2, T* t3, T* t4, hipStream_t s) {
+  const dim3 g(gen_grid(static_cast<int64_t>(N / Q) * N * N)), bl(kGB);
+  hipLaunchKernelGGL((k_gen_pass_zy<T, Q, 0>), g, bl, 0, s, x, nullptr, rows, N, t1, t2);
+  hipLaunchKernelGGL((k_gen_pass_zy<T, Q, 1>), g, bl, 0, s, static_cast<const T*>(t1), static_cast<const T*>(t2),
+                     rows, N, t3, t4);
+}
+
+// z and y passes by order (false for an order without a generic instance)
+template <typename T>
+bool gen_zy(int q, const T* x, const T* rows, int N, T* t1, T* t2, T* t3, T* t4, hipStream_t s) {
+  switch (q) {
+    case 3: gen_zy_q<T, 3>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 5: gen_zy_q<T, 5>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 6: gen_zy_q<T, 6>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 7: gen_zy_q<T, 7>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 8: gen_zy_q<T, 8>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 9: gen_zy_q<T, 9>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 10: gen_zy_q<T, 10>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 11: gen_zy_q<T, 11>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 12: gen_zy_q<T, 12>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 13: gen_zy_q<T, 13>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 14: gen_zy_q<T, 14>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 15: gen_zy_q<T, 15>(x, rows, N, t1, t2, t3, t4, s); return true;
+    case 16: gen_zy_q<T, 16>(x, rows, N, t1, t2, t3, t4, s); return true;
+  }
+  return false;
+}
+
 template <typename T>
 hipError_t gen_apply_t(const GenOp& op, const ApplyArgs& a, void* t1, void* t2, void* t3, void* t4, hipStream_t s) {
   const int N = a.N, q = op.q;
@@ -103,10 +304,18 @@ hipError_t gen_apply_t(const GenOp& op, const ApplyArgs& a, void* t1, void* t2, 
   const T* rows = static_cast<const T*>(sizeof(T) == 4 ? static_cast<const void*>(op.rows32) : op.rows64);
   const T* dinv = static_cast<const T*>(sizeof(T) == 4 ? static_cast<const void*>(op.dinv32) : op.dinv64);
   const dim3 g(gen_grid(n3)), bl(kGB);
-  hipLaunchKernelGGL((k_gen_pass<T, 0, 0>), g, bl, 0, s, static_cast<const T*>(a.x), nullptr, rows, dinv, q, N,
-                     static_cast<T*>(t1), static_cast<T*>(t2), nullptr, nullptr, nullptr, T(0), T(0));
-  hipLaunchKernelGGL((k_gen_pass<T, 1, 0>), g, bl, 0, s, static_cast<const T*>(t1), static_cast<const T*>(t2), rows,
-                     dinv, q, N, static_cast<T*>(t3), static_cast<T*>(t4), nullptr, nullptr, nullptr, T(0), T(0));
+  if (!gen_zy<T>(q, static_cast<const T*>(a.x), rows, N, static_cast<T*>(t1), static_cast<T*>(t2),
+                 static_cast<T*>(t3), static_cast<T*>(t4), s)) {
+    hipLaunchKernelGGL((k_gen_pass<T, 0, 0>), g, bl, 0, s, static_cast<const T*>(a.x), nullptr, rows, dinv, q, N,
+                       static_cast<T*>(t1), static_cast<T*>(t2), nullptr, nullptr, nullptr, T(0), T(0));
+    hipLaunchKernelGGL((k_gen_pass<T, 1, 0>), g, bl, 0, s, static_cast<const T*>(t1), static_cast<const T*>(t2),
+                       rows, dinv, q, N, static_cast<T*>(t3), static_cast<T*>(t4), nullptr, nullptr, nullptr, T(0),
+                       T(0));
+  }
+  if (gen_x_per_element(q, a.epi)) {
+    hipError_t e = hipSuccess;
+    if (gen_x<T>(q, static_cast<const T*>(t3), static_cast<const T*>(t4), rows, dinv, a, s, &e)) return e;
+  }
   const T* x = static_cast<const T*>(a.x);
   const T* b = static_cast<const T*>(a.b);
   T* out = static_cast<T*>(a.out);
@@ -144,13 +353,13 @@ __global__ void __launch_bounds__(kGB) k_gen_prolong(const T* __restrict__ in, T
   const int ix = AXIS == 0 ? Nc : X, iy = AXIS == 1 ? Nc : Y;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(idx % X), j = static_cast<int>((idx / X) % Y);
-    const int k = static_cast<int>(idx / (static_cast<int64_t>(X) * Y));
+    int i, j, k;
+    split3(idx, X, Y, i, j, k);
     const int f = AXIS == 0 ? i : (AXIS == 1 ? j : k);
     const int E = f / (2 * q), bb = f - 2 * q * E;
     double s = 0.0;
     for (int a = 0; a <= q; ++a) {
-      const int cc = (q * E + a) % Nc;
+      const int cc = wrap(q * E + a, Nc);
       int ii = i, jj = j, kk = k;
       if (AXIS == 0) ii = cc;
       else if (AXIS == 1) jj = cc;
@@ -169,8 +378,8 @@ __global__ void __launch_bounds__(kGB) k_gen_restrict(const T* __restrict__ in, 
   const int ix = AXIS == 0 ? Nf : X, iy = AXIS == 1 ? Nf : Y;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(idx % X), j = static_cast<int>((idx / X) % Y);
-    const int k = static_cast<int>(idx / (static_cast<int64_t>(X) * Y));
+    int i, j, k;
+    split3(idx, X, Y, i, j, k);
     const int c = AXIS == 0 ? i : (AXIS == 1 ? j : k);
     const int E = c / q, a = c - q * E;
     double s = 0.0;
@@ -221,8 +430,8 @@ __global__ void __launch_bounds__(kGB) k_gclass_scale(const double* __restrict__
   const int64_t n3 = static_cast<int64_t>(N) * N * N;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(idx % N), j = static_cast<int>((idx / N) % N);
-    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    int i, j, k;
+    split3(idx, N, N, i, j, k);
     const double d = tab ? tab[(i % q) + q * ((j % q) + q * (k % q))] : 1.0;
     const double v = in ? static_cast<double>(in[idx]) : 1.0;
     out[idx] = static_cast<T>(c * d * v);
@@ -235,8 +444,8 @@ __global__ void __launch_bounds__(kGB) k_gclass_axpy(const double* __restrict__ 
   const int64_t n3 = static_cast<int64_t>(N) * N * N;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(idx % N), j = static_cast<int>((idx / N) % N);
-    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    int i, j, k;
+    split3(idx, N, N, i, j, k);
     v[idx] = static_cast<T>(static_cast<double>(v[idx]) + c * tab[(i % q) + q * ((j % q) + q * (k % q))]);
   }
 }
@@ -250,8 +459,8 @@ __global__ void __launch_bounds__(kGB) k_gclass_dot(const double* __restrict__ t
   double s = 0.0;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n3;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(idx % N), j = static_cast<int>((idx / N) % N);
-    const int k = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    int i, j, k;
+    split3(idx, N, N, i, j, k);
     s = fma(tab[(i % q) + q * ((j % q) + q * (k % q))], static_cast<double>(x[idx]), s);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
