@@ -14,8 +14,8 @@
 // The mass M (x) M (x) M goes through the same passes with Kz = Ky = 0 and the x pass's
 // K row set to M.  Each pass is compiled per order: a thread takes one element segment of
 // a lattice line (its q nodes), loads the 2q+1 values its rows reach once and writes q
-// outputs (the z and y passes always; the x pass as set by gen_x_per_element, else a
-// thread per node).  Transfers P = P1 (x) P1 (x) P1 and P^T are three one-axis passes
+// outputs (the z and y passes always; the x pass as set by gen_x_lds and gen_x_per_element,
+// else a thread per node).  Transfers P = P1 (x) P1 (x) P1 and P^T are three one-axis passes
 // each, a thread per output node.  These levels trade the fused streaming kernels of
 // q = 1, 2, 4 for generality.
 #include "gmg_kernels.h"
@@ -24,11 +24,14 @@ namespace gmg {
 namespace {
 
 constexpr int kGB = 256;
-// The x pass in the per-element form (else a thread per node): always for the apply and the
-// residual, for the smoother step up to q = 7.  Measured near 256^3 DoFs: the FP32 apply 1.2-1.3x
-// faster at every order; FP32-cycle solves 9-14 % faster for q = 3, 5, 6, but 4-8 % slower for
-// q = 8 and 16, where the smoother step's three extra streams at that stride cost more than
-// the taps save.
+// The x pass: staged through LDS (k_gen_pass_xl) when N / q divides its block, except for the
+// smoother step at q <= 5; else in the per-element register form (k_gen_pass_x) for the apply
+// and the residual, and for the smoother step up to q = 7; else a thread per node
+// (k_gen_pass).  Measured near 256^3 DoFs against the register and per-node forms: the LDS
+// form takes the FP32 apply 21-25 % and the FP64 apply 13-29 % faster at q = 8, 14, 16 and
+// FP32-cycle solves 6 % (q = 6) to 23 % (q = 16) faster; at q = 3, 5 the applies are even and
+// the solves about 1 % slower with it, hence the register form's smoother step there.
+inline bool gen_x_lds(int q, Epi epi) { return epi != Epi::Cheb || q >= 6; }
 inline bool gen_x_per_element(int q, Epi epi) { return epi != Epi::Cheb || q <= 7; }
 
 inline unsigned gen_grid(int64_t n) {
@@ -220,8 +223,144 @@ __global__ void __launch_bounds__(kGB) k_gen_pass_x(const T* __restrict__ in0, c
   }
 }
 
+// The x pass for order Q staged through LDS: a block loads kXlSegs / (N / Q) whole x rows of
+// U1 and V with coalesced loads (element e of a row at slot e S, S = Q or Q + 1 whichever is
+// odd, so that a wavefront reading one window position of consecutive elements hits distinct
+// banks), each thread takes one element segment and keeps its Q sums in registers, writes them
+// over U1 once every window is read, and the epilogue then runs a thread per node with
+// coalesced reads of x, b and x_prev.  N / Q must divide kXlSegs.
+constexpr int kXlSegs = 256;
+
+template <int Q>
+constexpr int xl_stride() {
+  return (Q & 1) ? Q : Q + 1;
+}
+
+template <typename T, int Q, int EPI>
+__global__ void __launch_bounds__(kXlSegs) k_gen_pass_xl(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                          const T* __restrict__ rows, const T* __restrict__ dinv,
+                                                          const int N, T* __restrict__ out,
+                                                          const T* __restrict__ x, const T* __restrict__ b,
+                                                          const T* xp, const T c1, const T c2) {
+  constexpr int W = 2 * Q + 1;
+  constexpr int S = xl_stride<Q>();
+  const T* __restrict__ kr = rows + 4 * (Q * W);
+  const T* __restrict__ mr = kr + Q * W;
+  const int nE = N / Q;
+  const int R = kXlSegs / nE;      // x rows per block
+  const int rowlen = nE * S;       // LDS values per row and array
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* su = reinterpret_cast<T*>(smem_raw);  // [R][rowlen] U1, then the sums
+  T* sv = su + R * rowlen;                  // V
+  const int64_t nrows = static_cast<int64_t>(N) * N;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
+  const int rows_here = static_cast<int>(nrows - row0 < R ? nrows - row0 : R);
+  const int tid = threadIdx.x;
+  const int64_t base = row0 * N;
+  for (int v = tid; v < rows_here * N; v += kXlSegs) {
+    const int r = v / N, a = v - r * N;
+    const int slot = r * rowlen + (a / Q) * S + (a % Q);
+    su[slot] = in0[base + v];
+    sv[slot] = in1[base + v];
+  }
+  __syncthreads();
+  const int r = tid / nE, e = tid - r * nE;
+  const bool live = r < rows_here;
+  T s0[Q];
+  if (live) {
+    const int el = e == 0 ? nE - 1 : e - 1, er = e == nE - 1 ? 0 : e + 1;
+    const T* ru = su + r * rowlen;
+    const T* rv = sv + r * rowlen;
+    T u0[W], v0[W];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      u0[c] = ru[el * S + c];
+      v0[c] = rv[el * S + c];
+      u0[Q + c] = ru[e * S + c];
+      v0[Q + c] = rv[e * S + c];
+    }
+    u0[2 * Q] = ru[er * S];
+    v0[2 * Q] = rv[er * S];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int o = -Q; o <= Q; ++o) {
+        if (c != 0 && (o < -c || o > Q - c)) continue;  // structural zero of row c
+        acc = fma(kr[c * W + o + Q], u0[c + o + Q], acc);
+        acc = fma(mr[c * W + o + Q], v0[c + o + Q], acc);
+      }
+      s0[c] = acc;
+    }
+  }
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < Q; ++c) su[r * rowlen + e * S + c] = s0[c];
+  }
+  __syncthreads();
+  const bool use_xp = xp != nullptr && c1 != T(0);
+  for (int v = tid; v < rows_here * N; v += kXlSegs) {
+    const int rr = v / N, a = v - rr * N;
+    const int64_t at = base + v;
+    const T y = su[rr * rowlen + (a / Q) * S + (a % Q)];
+    if constexpr (EPI == static_cast<int>(Epi::Apply)) {
+      out[at] = y;
+    } else if constexpr (EPI == static_cast<int>(Epi::Residual)) {
+      out[at] = b[at] - y;
+    } else {  // Epi::Cheb, x_prev read as 0 when absent
+      const int64_t row = row0 + rr;
+      const int j = static_cast<int>(row % N), k = static_cast<int>(row / N);
+      const T xv = x[at];
+      const T xpv = use_xp ? xp[at] : T(0);
+      out[at] = xv + c1 * (xv - xpv) + c2 * dinv[(a % Q) + Q * ((j % Q) + Q * (k % Q))] * (b[at] - y);
+    }
+  }
+}
+
+// false when N / Q does not divide kXlSegs (the caller takes the register form)
+template <typename T, int Q, int EPI>
+bool gen_xl_launch(const T* t3, const T* t4, const T* rows, const T* dinv, const ApplyArgs& a, hipStream_t s,
+                   hipError_t* err) {
+  const int N = a.N;
+  const int nE = N / Q;
+  if (nE > kXlSegs || kXlSegs % nE != 0) return false;
+  const int R = kXlSegs / nE;
+  const size_t lds = sizeof(T) * 2 * static_cast<size_t>(R) * nE * xl_stride<Q>();
+  if (lds > 65536) {
+    const void* fn = reinterpret_cast<const void*>(&k_gen_pass_xl<T, Q, EPI>);
+    *err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (*err != hipSuccess) return true;
+  }
+  const int64_t nrows = static_cast<int64_t>(N) * N;
+  const dim3 g(static_cast<unsigned>((nrows + R - 1) / R)), bl(kXlSegs);
+  hipLaunchKernelGGL((k_gen_pass_xl<T, Q, EPI>), g, bl, lds, s, t3, t4, rows, dinv, N, static_cast<T*>(a.out),
+                     static_cast<const T*>(a.x), static_cast<const T*>(a.b), static_cast<const T*>(a.xp),
+                     static_cast<T>(a.c1), static_cast<T>(a.c2));
+  *err = hipGetLastError();
+  return true;
+}
+
+// the x pass of order Q in the LDS or the per-element form; false when neither applies
 template <typename T, int Q>
-hipError_t gen_x_q(const T* t3, const T* t4, const T* rows, const T* dinv, const ApplyArgs& a, hipStream_t s) {
+bool gen_x_q(const T* t3, const T* t4, const T* rows, const T* dinv, const ApplyArgs& a, hipStream_t s,
+             hipError_t* err) {
+  if (gen_x_lds(Q, a.epi)) {
+    switch (a.epi) {
+      case Epi::Apply:
+        if (gen_xl_launch<T, Q, static_cast<int>(Epi::Apply)>(t3, t4, rows, dinv, a, s, err)) return true;
+        break;
+      case Epi::Residual:
+        if (gen_xl_launch<T, Q, static_cast<int>(Epi::Residual)>(t3, t4, rows, dinv, a, s, err)) return true;
+        break;
+      case Epi::Cheb:
+        if (gen_xl_launch<T, Q, static_cast<int>(Epi::Cheb)>(t3, t4, rows, dinv, a, s, err)) return true;
+        break;
+      default:
+        break;
+    }
+  }
+  if (!gen_x_per_element(Q, a.epi)) return false;
   const int N = a.N;
   const dim3 g(gen_grid(static_cast<int64_t>(N / Q) * N * N)), bl(kGB);
   const T* x = static_cast<const T*>(a.x);
@@ -242,28 +381,31 @@ hipError_t gen_x_q(const T* t3, const T* t4, const T* rows, const T* dinv, const
                          x, b, xp, static_cast<T>(a.c1), static_cast<T>(a.c2));
       break;
     default:
-      return hipErrorInvalidValue;
+      *err = hipErrorInvalidValue;
+      return true;
   }
-  return hipGetLastError();
+  *err = hipGetLastError();
+  return true;
 }
 
+// false for an order without a generic instance or a pass left to the per-node form
 template <typename T>
 bool gen_x(int q, const T* t3, const T* t4, const T* rows, const T* dinv, const ApplyArgs& a, hipStream_t s,
            hipError_t* err) {
   switch (q) {
-    case 3: *err = gen_x_q<T, 3>(t3, t4, rows, dinv, a, s); return true;
-    case 5: *err = gen_x_q<T, 5>(t3, t4, rows, dinv, a, s); return true;
-    case 6: *err = gen_x_q<T, 6>(t3, t4, rows, dinv, a, s); return true;
-    case 7: *err = gen_x_q<T, 7>(t3, t4, rows, dinv, a, s); return true;
-    case 8: *err = gen_x_q<T, 8>(t3, t4, rows, dinv, a, s); return true;
-    case 9: *err = gen_x_q<T, 9>(t3, t4, rows, dinv, a, s); return true;
-    case 10: *err = gen_x_q<T, 10>(t3, t4, rows, dinv, a, s); return true;
-    case 11: *err = gen_x_q<T, 11>(t3, t4, rows, dinv, a, s); return true;
-    case 12: *err = gen_x_q<T, 12>(t3, t4, rows, dinv, a, s); return true;
-    case 13: *err = gen_x_q<T, 13>(t3, t4, rows, dinv, a, s); return true;
-    case 14: *err = gen_x_q<T, 14>(t3, t4, rows, dinv, a, s); return true;
-    case 15: *err = gen_x_q<T, 15>(t3, t4, rows, dinv, a, s); return true;
-    case 16: *err = gen_x_q<T, 16>(t3, t4, rows, dinv, a, s); return true;
+    case 3: return gen_x_q<T, 3>(t3, t4, rows, dinv, a, s, err);
+    case 5: return gen_x_q<T, 5>(t3, t4, rows, dinv, a, s, err);
+    case 6: return gen_x_q<T, 6>(t3, t4, rows, dinv, a, s, err);
+    case 7: return gen_x_q<T, 7>(t3, t4, rows, dinv, a, s, err);
+    case 8: return gen_x_q<T, 8>(t3, t4, rows, dinv, a, s, err);
+    case 9: return gen_x_q<T, 9>(t3, t4, rows, dinv, a, s, err);
+    case 10: return gen_x_q<T, 10>(t3, t4, rows, dinv, a, s, err);
+    case 11: return gen_x_q<T, 11>(t3, t4, rows, dinv, a, s, err);
+    case 12: return gen_x_q<T, 12>(t3, t4, rows, dinv, a, s, err);
+    case 13: return gen_x_q<T, 13>(t3, t4, rows, dinv, a, s, err);
+    case 14: return gen_x_q<T, 14>(t3, t4, rows, dinv, a, s, err);
+    case 15: return gen_x_q<T, 15>(t3, t4, rows, dinv, a, s, err);
+    case 16: return gen_x_q<T, 16>(t3, t4, rows, dinv, a, s, err);
   }
   return false;
 }
@@ -312,7 +454,7 @@ hipError_t gen_apply_t(const GenOp& op, const ApplyArgs& a, void* t1, void* t2, 
                        rows, dinv, q, N, static_cast<T*>(t3), static_cast<T*>(t4), nullptr, nullptr, nullptr, T(0),
                        T(0));
   }
-  if (gen_x_per_element(q, a.epi)) {
+  {
     hipError_t e = hipSuccess;
     if (gen_x<T>(q, static_cast<const T*>(t3), static_cast<const T*>(t4), rows, dinv, a, s, &e)) return e;
   }
