@@ -126,49 +126,76 @@ __global__ void __launch_bounds__(kGB) k_gen_pass(const T* __restrict__ in0, con
 // structurally zero taps; consecutive threads take consecutive x, so every load is coalesced.
 // The weights are uniform (scalar loads).  AXIS 0: T1 = M x, T2 = K x; AXIS 1: U1 = M T1,
 // V = K T1 + M T2.
-template <typename T, int Q, int AXIS>
+// The z or y pass for order Q: a thread takes C (1 or 2) consecutive element segments of one
+// lattice line (lanes along x, so every load and store is coalesced), loads the 2q+1-value
+// window of the first and, for the next, only its q new values (the q+1 it shares with the
+// previous window stay in registers), and writes q outputs per element.
+template <typename T, int Q, int AXIS, int C>
 __global__ void __launch_bounds__(kGB) k_gen_pass_zy(const T* __restrict__ in0, const T* __restrict__ in1,
                                                       const T* __restrict__ rows, const int N,
                                                       T* __restrict__ out0, T* __restrict__ out1) {
   static_assert(AXIS == 0 || AXIS == 1, "z and y passes");
   constexpr int W = 2 * Q + 1;
+  constexpr bool kTwo = AXIS == 1;
   const T* __restrict__ kr = rows + (2 * AXIS) * (Q * W);
   const T* __restrict__ mr = kr + Q * W;
-  const int nE = N / Q;
-  const int64_t total = static_cast<int64_t>(nE) * N * N;
+  const int nC = N / Q / C;
+  const int64_t total = static_cast<int64_t>(nC) * N * N;
   const int64_t step = AXIS == 0 ? static_cast<int64_t>(N) * N : N;  // along the line
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
        t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    int i, m, e;  // x; the other coordinate across the line (y for AXIS 0, z for AXIS 1); element
-    if constexpr (AXIS == 0) split3(t, N, N, i, m, e);
-    else split3(t, N, nE, i, e, m);
+    int i, m, ch;  // x; the other coordinate across the line (y for AXIS 0, z for AXIS 1); chunk
+    if constexpr (AXIS == 0) split3(t, N, N, i, m, ch);
+    else split3(t, N, nC, i, ch, m);
     const int64_t base = AXIS == 0 ? static_cast<int64_t>(m) * N + i : static_cast<int64_t>(m) * N * N + i;
-    T w0[W], w1[AXIS == 1 ? W : 1];
+    const int e0 = ch * C;
+    T w0[W], w1[kTwo ? W : 1];
 #pragma unroll
     for (int u = 0; u < W; ++u) {
-      const int64_t at = base + static_cast<int64_t>(wrap(e * Q - Q + u, N)) * step;
+      const int64_t at = base + static_cast<int64_t>(wrap(e0 * Q - Q + u, N)) * step;
       w0[u] = in0[at];
-      if constexpr (AXIS == 1) w1[u] = in1[at];
+      if constexpr (kTwo) w1[u] = in1[at];
     }
 #pragma unroll
-    for (int c = 0; c < Q; ++c) {
-      T s0 = T(0), s1 = T(0);
+    for (int k = 0; k < C; ++k) {
+      const int e = e0 + k;
+      T n0[Q], n1[kTwo ? Q : 1];
+      if (k + 1 < C) {  // the next element's new values, in flight while this one computes
 #pragma unroll
-      for (int o = -Q; o <= Q; ++o) {
-        if (c != 0 && (o < -c || o > Q - c)) continue;  // structural zero of row c
-        const T kv = kr[c * W + o + Q], mv = mr[c * W + o + Q];
-        const T v0 = w0[c + o + Q];
-        s0 = fma(mv, v0, s0);
-        if constexpr (AXIS == 0) {
-          s1 = fma(kv, v0, s1);
-        } else {
-          s1 = fma(kv, v0, s1);
-          s1 = fma(mv, w1[c + o + Q], s1);
+        for (int u = 0; u < Q; ++u) {
+          const int64_t at = base + static_cast<int64_t>(wrap(e * Q + Q + 1 + u, N)) * step;
+          n0[u] = in0[at];
+          if constexpr (kTwo) n1[u] = in1[at];
         }
       }
-      const int64_t at = base + static_cast<int64_t>(e * Q + c) * step;
-      out0[at] = s0;
-      out1[at] = s1;
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int o = -Q; o <= Q; ++o) {
+          if (c != 0 && (o < -c || o > Q - c)) continue;  // structural zero of row c
+          const T kv = kr[c * W + o + Q], mv = mr[c * W + o + Q];
+          const T v0 = w0[c + o + Q];
+          s0 = fma(mv, v0, s0);
+          s1 = fma(kv, v0, s1);
+          if constexpr (kTwo) s1 = fma(mv, w1[c + o + Q], s1);
+        }
+        const int64_t at = base + static_cast<int64_t>(e * Q + c) * step;
+        out0[at] = s0;
+        out1[at] = s1;
+      }
+      if (k + 1 < C) {
+#pragma unroll
+        for (int u = 0; u <= Q; ++u) {
+          w0[u] = w0[u + Q];
+          if constexpr (kTwo) w1[u] = w1[u + Q];
+        }
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+          w0[Q + 1 + u] = n0[u];
+          if constexpr (kTwo) w1[Q + 1 + u] = n1[u];
+        }
+      }
     }
   }
 }
@@ -410,12 +437,38 @@ bool gen_x(int q, const T* t3, const T* t4, const T* rows, const T* dinv, const 
   return false;
 }
 
+template <typename T, int Q, int C>
+void gen_zy_qc(const T* x, const T* rows, int N, T* t1, T* t2, T* t3, T* t4, hipStream_t s) {
+  const dim3 g(gen_grid(static_cast<int64_t>(N / Q / C) * N * N)), bl(kGB);
+  hipLaunchKernelGGL((k_gen_pass_zy<T, Q, 0, C>), g, bl, 0, s, x, nullptr, rows, N, t1, t2);
+  hipLaunchKernelGGL((k_gen_pass_zy<T, Q, 1, C>), g, bl, 0, s, static_cast<const T*>(t1), static_cast<const T*>(t2),
+                     rows, N, t3, t4);
+}
+
+// Two elements per thread pay where that instance keeps at least the occupancy of the one-element
+// instance in both passes (the register count decides; measured near 256^3 DoFs: FP32 q = 8 apply
+// 230 -> 175 us, solve 35.8 -> 31.7 ms), and cost up to 7 % of a solve where it lowers it (fewer
+// waves to hide the strided loads, and half the threads on the coarse levels).
+template <typename T, int Q>
+bool zy_two_pays() {
+  static const bool pays = [] {
+    auto occ = [](const void* f) {
+      int n = 0;
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kGB, 0) == hipSuccess ? n : -1;
+    };
+    const int z1 = occ(reinterpret_cast<const void*>(&k_gen_pass_zy<T, Q, 0, 1>));
+    const int y1 = occ(reinterpret_cast<const void*>(&k_gen_pass_zy<T, Q, 1, 1>));
+    const int z2 = occ(reinterpret_cast<const void*>(&k_gen_pass_zy<T, Q, 0, 2>));
+    const int y2 = occ(reinterpret_cast<const void*>(&k_gen_pass_zy<T, Q, 1, 2>));
+    return z1 > 0 && y1 > 0 && z2 >= z1 && y2 >= y1;
+  }();
+  return pays;
+}
+
 template <typename T, int Q>
 void gen_zy_q(const T* x, const T* rows, int N, T* t1, T* t2, T* t3, T* t4, hipStream_t s) {
-  const dim3 g(gen_grid(static_cast<int64_t>(N / Q) * N * N)), bl(kGB);
-  hipLaunchKernelGGL((k_gen_pass_zy<T, Q, 0>), g, bl, 0, s, x, nullptr, rows, N, t1, t2);
-  hipLaunchKernelGGL((k_gen_pass_zy<T, Q, 1>), g, bl, 0, s, static_cast<const T*>(t1), static_cast<const T*>(t2),
-                     rows, N, t3, t4);
+  if ((N / Q) % 2 == 0 && zy_two_pays<T, Q>()) gen_zy_qc<T, Q, 2>(x, rows, N, t1, t2, t3, t4, s);
+  else gen_zy_qc<T, Q, 1>(x, rows, N, t1, t2, t3, t4, s);
 }
 
 // z and y passes by order (false for an order without a generic instance)
