@@ -16,8 +16,8 @@
 // a lattice line (its q nodes), loads the 2q+1 values its rows reach once and writes q
 // outputs (the z and y passes always; the x pass as set by gen_x_lds and gen_x_per_element,
 // else a thread per node).  Transfers P = P1 (x) P1 (x) P1 and P^T are three one-axis passes
-// each, a thread per output node.  These levels trade the fused streaming kernels of
-// q = 1, 2, 4 for generality.
+// each, a thread per coarse element of a line (a thread per output node for an order without
+// an instance).  These levels trade the fused streaming kernels of q = 1, 2, 4 for generality.
 #include "gmg_kernels.h"
 
 namespace gmg {
@@ -592,8 +592,134 @@ __global__ void __launch_bounds__(kGB) k_gen_restrict(const T* __restrict__ in, 
   }
 }
 
+// The transfers of order Q along one axis, a thread per coarse element of a lattice line (lanes
+// along x for the y and z axes, so their loads and stores are coalesced): the prolongation loads
+// the element's q+1 coarse values once and writes its 2q fine nodes, the restriction loads the
+// 4q+1 fine values the element's rows reach once and writes its q coarse nodes.  Same weights,
+// FP64 accumulation and tap order as the thread-per-node kernels above.  X, Y, Z: extents of the
+// output; the input's extent along AXIS is Nc (prolongation) or Nf (restriction).
+template <int AXIS>
+__device__ inline void xfer_line(int64_t t, int nE, int X, int Y, int& i, int& j, int& k, int& E) {
+  if constexpr (AXIS == 0) { split3(t, nE, Y, E, j, k); i = 0; }
+  else if constexpr (AXIS == 1) { split3(t, X, nE, i, E, k); j = 0; }
+  else { split3(t, X, Y, i, j, E); k = 0; }
+}
+
+template <typename T, int Q, int AXIS, bool ACC>
+__global__ void __launch_bounds__(kGB) k_gen_prolong_e(const T* __restrict__ in, T* __restrict__ out,
+                                                        const double* __restrict__ p, const int X, const int Y,
+                                                        const int Z, const int Nc) {
+  const int nE = Nc / Q;
+  const int ix = AXIS == 0 ? Nc : X, iy = AXIS == 1 ? Nc : Y;
+  const int64_t total = static_cast<int64_t>(nE) * (AXIS == 0 ? 1 : X) * (AXIS == 1 ? 1 : Y) * (AXIS == 2 ? 1 : Z);
+  const int64_t sin = AXIS == 0 ? 1 : (AXIS == 1 ? ix : static_cast<int64_t>(ix) * iy);
+  const int64_t sout = AXIS == 0 ? 1 : (AXIS == 1 ? X : static_cast<int64_t>(X) * Y);
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int i, j, k, E;
+    xfer_line<AXIS>(t, nE, X, Y, i, j, k, E);
+    const int64_t bin = (static_cast<int64_t>(k) * iy + j) * ix + i;
+    const int64_t bout = (static_cast<int64_t>(k) * Y + j) * X + i;
+    double v[Q + 1];
+#pragma unroll
+    for (int a = 0; a <= Q; ++a) v[a] = static_cast<double>(in[bin + wrap(Q * E + a, Nc) * sin]);
+#pragma unroll
+    for (int bb = 0; bb < 2 * Q; ++bb) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a <= Q; ++a) s = fma(p[bb * (Q + 1) + a], v[a], s);
+      const int64_t at = bout + static_cast<int64_t>(2 * Q * E + bb) * sout;
+      out[at] = ACC ? static_cast<T>(static_cast<double>(out[at]) + s) : static_cast<T>(s);
+    }
+  }
+}
+
+template <typename T, int Q, int AXIS>
+__global__ void __launch_bounds__(kGB) k_gen_restrict_e(const T* __restrict__ in, T* __restrict__ out,
+                                                         const double* __restrict__ r, const int X, const int Y,
+                                                         const int Z, const int Nf) {
+  constexpr int W = 4 * Q + 1;
+  const int Nc = Nf / 2, nE = Nc / Q;
+  const int ix = AXIS == 0 ? Nf : X, iy = AXIS == 1 ? Nf : Y;
+  const int64_t total = static_cast<int64_t>(nE) * (AXIS == 0 ? 1 : X) * (AXIS == 1 ? 1 : Y) * (AXIS == 2 ? 1 : Z);
+  const int64_t sin = AXIS == 0 ? 1 : (AXIS == 1 ? ix : static_cast<int64_t>(ix) * iy);
+  const int64_t sout = AXIS == 0 ? 1 : (AXIS == 1 ? X : static_cast<int64_t>(X) * Y);
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int i, j, k, E;
+    xfer_line<AXIS>(t, nE, X, Y, i, j, k, E);
+    const int64_t bin = (static_cast<int64_t>(k) * iy + j) * ix + i;
+    const int64_t bout = (static_cast<int64_t>(k) * Y + j) * X + i;
+    T w[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) w[u] = in[bin + wrap(2 * Q * E - 2 * Q + u, Nf) * sin];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = a == 0 ? 0 : 2 * Q; u < W; ++u) {  // an interior node's rows stop at its element
+        const double wt = r[a * W + u];
+        if (wt != 0.0) s = fma(wt, static_cast<double>(w[u]), s);
+      }
+      out[bout + static_cast<int64_t>(Q * E + a) * sout] = static_cast<T>(s);
+    }
+  }
+}
+
+template <typename T, int Q>
+void gen_prolong_q(const double* p, const T* ec, T* t1, T* t2, T* uf, int Nc, hipStream_t s) {
+  const int Nf = 2 * Nc, nE = Nc / Q;
+  const dim3 bl(kGB);
+  hipLaunchKernelGGL((k_gen_prolong_e<T, Q, 0, false>), dim3(gen_grid(static_cast<int64_t>(nE) * Nc * Nc)), bl, 0,
+                     s, ec, t1, p, Nf, Nc, Nc, Nc);
+  hipLaunchKernelGGL((k_gen_prolong_e<T, Q, 1, false>), dim3(gen_grid(static_cast<int64_t>(nE) * Nf * Nc)), bl, 0,
+                     s, static_cast<const T*>(t1), t2, p, Nf, Nf, Nc, Nc);
+  hipLaunchKernelGGL((k_gen_prolong_e<T, Q, 2, true>), dim3(gen_grid(static_cast<int64_t>(nE) * Nf * Nf)), bl, 0,
+                     s, static_cast<const T*>(t2), uf, p, Nf, Nf, Nf, Nc);
+}
+
+template <typename T, int Q>
+void gen_restrict_q(const double* r, const T* rf, T* t1, T* t2, T* rc, int Nc, hipStream_t s) {
+  const int Nf = 2 * Nc, nE = Nc / Q;
+  const dim3 bl(kGB);
+  hipLaunchKernelGGL((k_gen_restrict_e<T, Q, 0>), dim3(gen_grid(static_cast<int64_t>(nE) * Nf * Nf)), bl, 0, s,
+                     rf, t1, r, Nc, Nf, Nf, Nf);
+  hipLaunchKernelGGL((k_gen_restrict_e<T, Q, 1>), dim3(gen_grid(static_cast<int64_t>(nE) * Nc * Nf)), bl, 0, s,
+                     static_cast<const T*>(t1), t2, r, Nc, Nc, Nf, Nf);
+  hipLaunchKernelGGL((k_gen_restrict_e<T, Q, 2>), dim3(gen_grid(static_cast<int64_t>(nE) * Nc * Nc)), bl, 0, s,
+                     static_cast<const T*>(t2), rc, r, Nc, Nc, Nc, Nf);
+}
+
+// the per-element transfers by order (false for an order without an instance)
+template <typename T>
+bool gen_xfer_e(bool prolong, int q, const double* w, const T* in, T* t1, T* t2, T* out, int Nc, hipStream_t s) {
+#define GMG_XFER_CASE(QQ)                                                  \
+  case QQ:                                                                 \
+    if (prolong) gen_prolong_q<T, QQ>(w, in, t1, t2, out, Nc, s);          \
+    else gen_restrict_q<T, QQ>(w, in, t1, t2, out, Nc, s);                 \
+    return true;
+  switch (q) {
+    GMG_XFER_CASE(3)
+    GMG_XFER_CASE(5)
+    GMG_XFER_CASE(6)
+    GMG_XFER_CASE(7)
+    GMG_XFER_CASE(8)
+    GMG_XFER_CASE(9)
+    GMG_XFER_CASE(10)
+    GMG_XFER_CASE(11)
+    GMG_XFER_CASE(12)
+    GMG_XFER_CASE(13)
+    GMG_XFER_CASE(14)
+    GMG_XFER_CASE(15)
+    GMG_XFER_CASE(16)
+  }
+#undef GMG_XFER_CASE
+  return false;
+}
+
 template <typename T>
 hipError_t gen_prolong_t(const GenXfer& t, const T* ec, T* t1, T* t2, T* uf, int Nc, hipStream_t s) {
+  if (gen_xfer_e<T>(true, t.q, t.p, ec, t1, t2, uf, Nc, s)) return hipGetLastError();
   const int Nf = 2 * Nc, q = t.q;
   const dim3 bl(kGB);
   hipLaunchKernelGGL((k_gen_prolong<T, 0, false>), dim3(gen_grid(static_cast<int64_t>(Nf) * Nc * Nc)), bl, 0, s, ec,
@@ -607,6 +733,7 @@ hipError_t gen_prolong_t(const GenXfer& t, const T* ec, T* t1, T* t2, T* uf, int
 
 template <typename T>
 hipError_t gen_restrict_t(const GenXfer& t, const T* rf, T* t1, T* t2, T* rc, int Nc, hipStream_t s) {
+  if (gen_xfer_e<T>(false, t.q, t.r, rf, t1, t2, rc, Nc, s)) return hipGetLastError();
   const int Nf = 2 * Nc, q = t.q;
   const dim3 bl(kGB);
   hipLaunchKernelGGL((k_gen_restrict<T, 0>), dim3(gen_grid(static_cast<int64_t>(Nc) * Nf * Nf)), bl, 0, s, rf, t1,
