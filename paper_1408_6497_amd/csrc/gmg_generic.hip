@@ -200,6 +200,68 @@ __global__ void __launch_bounds__(kGB) k_gen_pass_zy(const T* __restrict__ in0, 
   }
 }
 
+// The z or y pass for order Q staged through LDS: a block takes kZlLanes consecutive x lanes of
+// one plane across the line (y for the z pass, z for the y pass) and ZT consecutive elements
+// along it, loads the (ZT + 1) q + 1 lattice rows their windows span once (coalesced along x),
+// and each thread computes one element segment of one lane from its 2q+1-row window in LDS.
+constexpr int kZlLanes = 64;
+
+template <typename T, int Q, int AXIS, int ZT>
+__global__ void __launch_bounds__(kZlLanes * ZT) k_gen_pass_zyl(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                                const T* __restrict__ rows, const int N,
+                                                                T* __restrict__ out0, T* __restrict__ out1) {
+  static_assert(AXIS == 0 || AXIS == 1, "z and y passes");
+  constexpr int W = 2 * Q + 1;
+  constexpr int R = (ZT + 1) * Q + 1;  // lattice rows of one block
+  constexpr bool kTwo = AXIS == 1;
+  __shared__ T s0[R * kZlLanes];
+  __shared__ T s1[kTwo ? R * kZlLanes : 1];
+  const T* __restrict__ kr = rows + (2 * AXIS) * (Q * W);
+  const T* __restrict__ mr = kr + Q * W;
+  const int tiles = (N + kZlLanes - 1) / kZlLanes;
+  const int b = blockIdx.x;
+  const int tile = b % tiles, rest = b / tiles;
+  const int m = rest % N, chunk = rest / N;
+  const int e0 = chunk * ZT;
+  const int lane = threadIdx.x % kZlLanes, slot = threadIdx.x / kZlLanes;
+  const int i = tile * kZlLanes + lane;
+  const bool live = i < N;
+  const int64_t step = AXIS == 0 ? static_cast<int64_t>(N) * N : N;  // along the line
+  const int64_t base = (AXIS == 0 ? static_cast<int64_t>(m) * N : static_cast<int64_t>(m) * N * N) + i;
+  if (live) {
+    for (int r = slot; r < R; r += ZT) {
+      const int64_t at = base + static_cast<int64_t>(wrap(e0 * Q - Q + r, N)) * step;
+      s0[r * kZlLanes + lane] = in0[at];
+      if constexpr (kTwo) s1[r * kZlLanes + lane] = in1[at];
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  T w0[W], w1[kTwo ? W : 1];
+#pragma unroll
+  for (int u = 0; u < W; ++u) {
+    w0[u] = s0[(slot * Q + u) * kZlLanes + lane];
+    if constexpr (kTwo) w1[u] = s1[(slot * Q + u) * kZlLanes + lane];
+  }
+  const int e = e0 + slot;
+#pragma unroll
+  for (int c = 0; c < Q; ++c) {
+    T a0 = T(0), a1 = T(0);
+#pragma unroll
+    for (int o = -Q; o <= Q; ++o) {
+      if (c != 0 && (o < -c || o > Q - c)) continue;  // structural zero of row c
+      const T kv = kr[c * W + o + Q], mv = mr[c * W + o + Q];
+      const T v0 = w0[c + o + Q];
+      a0 = fma(mv, v0, a0);
+      a1 = fma(kv, v0, a1);
+      if constexpr (kTwo) a1 = fma(mv, w1[c + o + Q], a1);
+    }
+    const int64_t at = base + static_cast<int64_t>(e * Q + c) * step;
+    out0[at] = a0;
+    out1[at] = a1;
+  }
+}
+
 // The x pass for order Q with its epilogue, in the same form: a thread takes one element
 // segment of an x row (loads at a stride of Q values across the wavefront, each thread's
 // window contiguous), y = Kx U1 + Mx V, then the apply, residual or smoother-step epilogue.
@@ -465,10 +527,35 @@ bool zy_two_pays() {
   return pays;
 }
 
+template <typename T, int Q, int ZT>
+void gen_zy_ql(const T* x, const T* rows, int N, T* t1, T* t2, T* t3, T* t4, hipStream_t s) {
+  const int tiles = (N + kZlLanes - 1) / kZlLanes;
+  const dim3 g(static_cast<unsigned>(tiles * N * (N / Q / ZT))), bl(kZlLanes * ZT);
+  hipLaunchKernelGGL((k_gen_pass_zyl<T, Q, 0, ZT>), g, bl, 0, s, x, nullptr, rows, N, t1, t2);
+  hipLaunchKernelGGL((k_gen_pass_zyl<T, Q, 1, ZT>), g, bl, 0, s, static_cast<const T*>(t1),
+                     static_cast<const T*>(t2), rows, N, t3, t4);
+}
+
+// The z and y passes: two element segments per thread where that pays (above), else staged
+// through LDS on levels of at least 128 nodes a side (FP64: up to q = 10, where a block's LDS
+// stays within 32 KB), else one segment per thread.  Measured near 256^3 DoFs against the
+// one-segment form, the LDS form takes FP32-cycle solves 9 % (q = 14) and 4 % (q = 16) faster;
+// on narrower levels a 64-lane tile runs partly empty and it lost up to 9 % of a solve (q = 5),
+// and in FP64 at q = 14, 16 (1.5 waves per SIMD at 50 KB per block) the apply lost 12-17 %.
 template <typename T, int Q>
 void gen_zy_q(const T* x, const T* rows, int N, T* t1, T* t2, T* t3, T* t4, hipStream_t s) {
-  if ((N / Q) % 2 == 0 && zy_two_pays<T, Q>()) gen_zy_qc<T, Q, 2>(x, rows, N, t1, t2, t3, t4, s);
-  else gen_zy_qc<T, Q, 1>(x, rows, N, t1, t2, t3, t4, s);
+  constexpr int ZT = sizeof(T) == 4 ? 4 : 2;
+  if ((N / Q) % 2 == 0 && zy_two_pays<T, Q>()) {
+    gen_zy_qc<T, Q, 2>(x, rows, N, t1, t2, t3, t4, s);
+    return;
+  }
+  if constexpr (sizeof(T) == 4 || Q <= 10) {
+    if (N >= 128 && (N / Q) % ZT == 0) {
+      gen_zy_ql<T, Q, ZT>(x, rows, N, t1, t2, t3, t4, s);
+      return;
+    }
+  }
+  gen_zy_qc<T, Q, 1>(x, rows, N, t1, t2, t3, t4, s);
 }
 
 // z and y passes by order (false for an order without a generic instance)

@@ -23,7 +23,9 @@ def _ctx(q, n, levels=0, **kw):
     return Context(q, n, levels, **kw)
 
 
-APPLY_CASES = [(3, 1), (3, 2), (3, 8), (5, 1), (5, 2), (5, 4), (6, 2), (8, 1), (8, 2)]
+# the last three are levels at least 128 nodes wide, where the z and y passes may be staged
+# through LDS in 64-lane tiles (N = 160: a ragged last tile) or take two element segments a thread
+APPLY_CASES = [(3, 1), (3, 2), (3, 8), (5, 1), (5, 2), (5, 4), (6, 2), (8, 1), (8, 2), (5, 32), (8, 16), (16, 8)]
 
 
 @pytest.mark.parametrize("q,n", APPLY_CASES)
@@ -51,7 +53,11 @@ def test_apply_mass_diagonal_parity(q, n):
     d = torch.empty(size, dtype=torch.float64, device="cuda")
     ctx.diagonal(top, d)
     torch.cuda.synchronize()
-    assert rel_l2(to_host(d), A.diagonal()) <= 1e-14
+    # a sum of products of 1D element-matrix entries, which the two sides build independently; at
+    # q = 16 those agree to a few 1e-14 (as the FP64 apply does), at q <= 8 to a few ulps
+    ed = rel_l2(to_host(d), A.diagonal())
+    print(f"  diagonal {ed:.2e}", flush=True)
+    assert ed <= (1e-14 if q <= 8 else 1e-13)
 
 
 @pytest.mark.parametrize("q,n_c", [(3, 1), (3, 4), (5, 1), (5, 2), (6, 1), (8, 1)])
