@@ -346,9 +346,18 @@ __global__ void __launch_bounds__(kXlSegs) k_gen_pass_xl(const T* __restrict__ i
   const int rows_here = static_cast<int>(nrows - row0 < R ? nrows - row0 : R);
   const int tid = threadIdx.x;
   const int64_t base = row0 * N;
+  // node a of row r sits at slot r rowlen + (a / Q) S + a % Q, which is (v / Q) S + v % Q for
+  // v = r N + a (N = nE Q, rowlen = nE S): the apply and the residual take that form (measured
+  // faster), the smoother step the row split (measured faster there)
+  constexpr bool kFlat = EPI != static_cast<int>(Epi::Cheb);
   for (int v = tid; v < rows_here * N; v += kXlSegs) {
-    const int r = v / N, a = v - r * N;
-    const int slot = r * rowlen + (a / Q) * S + (a % Q);
+    int slot;
+    if constexpr (kFlat) {
+      slot = (v / Q) * S + (v % Q);
+    } else {
+      const int r = v / N, a = v - r * N;
+      slot = r * rowlen + (a / Q) * S + (a % Q);
+    }
     su[slot] = in0[base + v];
     sv[slot] = in1[base + v];
   }
@@ -390,7 +399,7 @@ __global__ void __launch_bounds__(kXlSegs) k_gen_pass_xl(const T* __restrict__ i
   __syncthreads();
   const bool use_xp = xp != nullptr && c1 != T(0);
   for (int v = tid; v < rows_here * N; v += kXlSegs) {
-    const int rr = v / N, a = v - rr * N;
+    const int rr = kFlat ? 0 : v / N, a = kFlat ? v : v - rr * N;
     const int64_t at = base + v;
     const T y = su[rr * rowlen + (a / Q) * S + (a % Q)];
     if constexpr (EPI == static_cast<int>(Epi::Apply)) {
